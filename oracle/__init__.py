@@ -1,0 +1,292 @@
+"""FP64 CPU oracle of the batched rMD / SCPS hot path -- TEST INFRASTRUCTURE.
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  It shares no code with the HIP library; both consume
+the seeded inputs of ``paper_1705_02180_amd.inputs`` and nothing else.
+
+Every function here marshals numpy arrays into ``liboracle.so`` (plain C,
+double precision, straightforward loops; see ``scps_oracle.c`` for the paper
+passages each routine follows).  The library is compiled on first use if it
+is missing.
+
+Parity status: every routine is pinned by the ``-m "not gpu"`` tests against
+closed forms, invariants, finite differences, published Philox known-answer
+values, library routines or exact stationary statistics, except the long-run
+folding behaviour of the synthetic chains (parity unpinned: the paper prints
+no numbers for them).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import build as _build
+
+CV_STRIDE = 8
+CV_Z, CV_ZM, CV_EB, CV_S, CV_W, CV_SM, CV_WM = range(7)
+
+_lib = None
+
+
+class OrcParams(C.Structure):
+    _fields_ = [
+        ("integrator", C.c_int32), ("bias_mode", C.c_int32),
+        ("dt", C.c_double), ("gamma", C.c_double), ("kT", C.c_double),
+        ("k_bond", C.c_double), ("r_bond", C.c_double),
+        ("lj_eps", C.c_double), ("lj_sigma", C.c_double),
+        ("dh_prefactor", C.c_double), ("dh_kappa", C.c_double),
+        ("nb_excl", C.c_int32), ("min_seq_sep", C.c_int32),
+        ("r0", C.c_double), ("r_cut", C.c_double),
+        ("k_R", C.c_double),
+        ("lam", C.c_double), ("k_s", C.c_double), ("k_w", C.c_double),
+        ("seed", C.c_uint64),
+    ]
+
+
+class OrcSystem(C.Structure):
+    _fields_ = [
+        ("n", C.c_int), ("nc", C.c_int),
+        ("cidx", C.POINTER(C.c_int32)),
+        ("mass", C.POINTER(C.c_float)), ("charge", C.POINTER(C.c_float)),
+        ("native", C.POINTER(C.c_double)),
+        ("K", C.c_int),
+        ("stack", C.POINTER(C.c_double)),
+        ("Z0", C.c_double),
+    ]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB) or os.path.getmtime(_build.LIB) < os.path.getmtime(_build.SRC):
+            _build.build()
+        L = C.CDLL(_build.LIB)
+        d, i32, i64, u64, vp = C.c_double, C.c_int32, C.c_int64, C.c_uint64, C.c_void_p
+        L.orc_contact.restype = d
+        L.orc_contact.argtypes = [d, d, d, vp]
+        L.orc_contact_array.argtypes = [i64, vp, d, d, vp, vp]
+        L.orc_contact_map.argtypes = [C.c_int, vp, C.c_int, vp, d, d, vp]
+        L.orc_z_grad.restype = d
+        L.orc_z_grad.argtypes = [C.c_int, vp, C.c_int, vp, vp, d, d, C.c_int, vp]
+        L.orc_phys_forces.restype = d
+        L.orc_phys_forces.argtypes = [C.c_int, vp, vp, C.POINTER(OrcParams), vp]
+        L.orc_philox4x32_10.argtypes = [vp, vp, vp]
+        L.orc_philox_array.argtypes = [i64, vp, vp, vp]
+        L.orc_uniform.restype = d
+        L.orc_uniform.argtypes = [C.c_uint32]
+        L.orc_normals.argtypes = [u64, C.c_uint32, C.c_uint32, u64, vp]
+        L.orc_normals_array.argtypes = [i64, u64, vp, vp, vp, vp]
+        L.orc_tube.argtypes = [C.c_int, vp, C.c_int, vp, C.c_int, vp, d, d, d, d, C.c_int,
+                               vp, vp, vp, vp, vp]
+        L.orc_total_force.argtypes = [C.POINTER(OrcParams), C.POINTER(OrcSystem), vp, vp, vp, vp]
+        L.orc_steps.argtypes = [C.POINTER(OrcParams), C.POINTER(OrcSystem), C.c_uint32, vp, vp, vp,
+                                i64, u64, C.c_int, vp, i64]
+        L.orc_run_batch.restype = C.c_int
+        L.orc_run_batch.argtypes = [C.POINTER(OrcParams), vp, C.c_int, vp, vp, vp, vp, vp,
+                                    i64, u64, C.c_int]
+        L.orc_update_reference.restype = C.c_int
+        L.orc_update_reference.argtypes = [C.c_int, C.c_int, vp, d, d, C.c_int, C.c_int, vp, vp, vp]
+        _lib = L
+    return _lib
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def make_params(d: dict) -> OrcParams:
+    return OrcParams(
+        integrator=int(d["integrator"]), bias_mode=int(d["bias_mode"]),
+        dt=d["dt"], gamma=d["gamma"], kT=d["kT"], k_bond=d["k_bond"], r_bond=d["r_bond"],
+        lj_eps=d["lj_eps"], lj_sigma=d["lj_sigma"], dh_prefactor=d["dh_prefactor"],
+        dh_kappa=d["dh_kappa"], nb_excl=int(d["nb_excl"]), min_seq_sep=int(d["min_seq_sep"]),
+        r0=d["r0_contact"], r_cut=d["r_cut_contact"], k_R=d["k_R"], lam=d["lam"],
+        k_s=d["k_s"], k_w=d["k_w"], seed=int(d["seed"]))
+
+
+# ---------------------------------------------------------------------------
+# elementary pieces
+# ---------------------------------------------------------------------------
+def contact(r2, r0: float = 7.5, r_cut: float = 0.0):
+    """C and dC/d(r^2) of eq (Cij) for an array of squared distances."""
+    r2 = _f64(np.atleast_1d(r2))
+    Cv = np.empty_like(r2)
+    dC = np.empty_like(r2)
+    lib().orc_contact_array(r2.size, _p(r2), r0, r_cut, _p(Cv), _p(dC))
+    return Cv, dC
+
+
+def contact_map(x, cidx, r0: float = 7.5, r_cut: float = 0.0) -> np.ndarray:
+    x = _f64(x)
+    n = x.shape[-1]
+    cidx = np.ascontiguousarray(cidx, dtype=np.int32)
+    nc = len(cidx)
+    out = np.empty(nc * (nc - 1) // 2)
+    lib().orc_contact_map(n, _p(x), nc, _p(cidx), r0, r_cut, _p(out))
+    return out
+
+
+def z_grad(x, cidx, ref, r0: float = 7.5, r_cut: float = 0.0, min_sep: int = 0, grad: bool = True):
+    x = _f64(x)
+    n = x.shape[-1]
+    cidx = np.ascontiguousarray(cidx, dtype=np.int32)
+    ref = _f64(ref)
+    g = np.empty((3, n)) if grad else None
+    z = lib().orc_z_grad(n, _p(x), len(cidx), _p(cidx), _p(ref), r0, r_cut, min_sep, _p(g))
+    return (z, g) if grad else z
+
+
+def phys_forces(x, charge, params: dict):
+    x = _f64(x)
+    n = x.shape[-1]
+    q = np.ascontiguousarray(charge, dtype=np.float32)
+    F = np.empty((3, n))
+    p = make_params(params)
+    U = lib().orc_phys_forces(n, _p(x), _p(q), C.byref(p), _p(F))
+    return F, U
+
+
+def philox(ctr: Sequence[int], key: Sequence[int]) -> np.ndarray:
+    c = np.ascontiguousarray(np.asarray(ctr, dtype=np.uint32).reshape(-1, 4))
+    k = np.ascontiguousarray(np.broadcast_to(np.asarray(key, dtype=np.uint32).reshape(-1, 2), (len(c), 2)))
+    out = np.empty_like(c)
+    lib().orc_philox_array(len(c), _p(c), _p(k), _p(out))
+    return out
+
+
+def uniform(w: int) -> float:
+    return lib().orc_uniform(int(w))
+
+
+def normals(seed: int, atom, replica, step) -> np.ndarray:
+    atom = np.ascontiguousarray(np.atleast_1d(atom), dtype=np.uint32)
+    m = len(atom)
+    rep = np.ascontiguousarray(np.broadcast_to(np.asarray(replica, dtype=np.uint32), (m,)))
+    st = np.ascontiguousarray(np.broadcast_to(np.asarray(step, dtype=np.uint64), (m,)))
+    out = np.empty((m, 3))
+    lib().orc_normals_array(m, int(seed), _p(atom), _p(rep), _p(st), _p(out))
+    return out
+
+
+def tube(x, cidx, stack, Z0, lam, r0: float = 7.5, r_cut: float = 0.0, min_sep: int = 0,
+         grads: bool = True):
+    """s, w (and their gradients, and d_k) of the mean-field tube variables."""
+    x = _f64(x)
+    n = x.shape[-1]
+    cidx = np.ascontiguousarray(cidx, dtype=np.int32)
+    stack = _f64(stack)
+    K = stack.shape[0]
+    s = C.c_double()
+    w = C.c_double()
+    gs = np.empty((3, n)) if grads else None
+    gw = np.empty((3, n)) if grads else None
+    dk = np.empty(K)
+    lib().orc_tube(n, _p(x), len(cidx), _p(cidx), K, _p(stack), Z0, lam, r0, r_cut, min_sep,
+                   C.byref(s), C.byref(w), _p(gs), _p(gw), _p(dk))
+    return s.value, w.value, gs, gw, dk
+
+
+# ---------------------------------------------------------------------------
+# systems, forces, stepping
+# ---------------------------------------------------------------------------
+class System:
+    """One chain as the oracle sees it (arrays kept alive on the object)."""
+
+    def __init__(self, n, cidx, mass, charge, params: dict, native_xyz=None,
+                 native_map=None, stack=None, Z0: Optional[float] = None):
+        self.n = int(n)
+        self.cidx = np.ascontiguousarray(cidx, dtype=np.int32)
+        self.mass = np.ascontiguousarray(mass, dtype=np.float32)
+        self.charge = np.ascontiguousarray(charge, dtype=np.float32)
+        r0, rc = params["r0_contact"], params["r_cut_contact"]
+        if native_map is None:
+            native_map = contact_map(native_xyz, self.cidx, r0, rc)
+        self.native = _f64(native_map)
+        self.Z0 = float(np.sum(self.native ** 2)) if Z0 is None else float(Z0)
+        self.stack = None if stack is None else _f64(stack)
+        self.K = 0 if stack is None else int(self.stack.shape[0])
+
+    @classmethod
+    def from_inputs(cls, sysin, params: dict):
+        return cls(sysin.n, sysin.contact_idx, sysin.mass, sysin.charge, params,
+                   native_xyz=sysin.native)
+
+    def cstruct(self) -> OrcSystem:
+        f32 = C.POINTER(C.c_float)
+        f64 = C.POINTER(C.c_double)
+        return OrcSystem(
+            n=self.n, nc=len(self.cidx),
+            cidx=self.cidx.ctypes.data_as(C.POINTER(C.c_int32)),
+            mass=self.mass.ctypes.data_as(f32), charge=self.charge.ctypes.data_as(f32),
+            native=self.native.ctypes.data_as(f64), K=self.K,
+            stack=(self.stack.ctypes.data_as(f64) if self.stack is not None else None),
+            Z0=self.Z0)
+
+
+def total_force(params: dict, system: System, x, cv):
+    """(F_total, F_bias, cv_after) at X; cv's running minima are updated."""
+    x = _f64(x)
+    cv = _f64(cv).copy()
+    n = system.n
+    F = np.empty((3, n))
+    Fb = np.empty((3, n))
+    p = make_params(params)
+    s = system.cstruct()
+    lib().orc_total_force(C.byref(p), C.byref(s), _p(x), _p(cv), _p(F), _p(Fb))
+    return F, Fb, cv
+
+
+def steps(params: dict, system: System, replica_id: int, x, v, cv, n_steps: int,
+          step0: int = 0, record_every: int = 0):
+    """n_steps Langevin steps of one replica; returns (x, v, cv, frames)."""
+    x = _f64(x).copy()
+    v = None if v is None else _f64(v).copy()
+    cv = _f64(cv).copy()
+    n = system.n
+    frames = None
+    if record_every > 0:
+        frames = np.zeros((n_steps // record_every + 1, 3, n))
+    p = make_params(params)
+    s = system.cstruct()
+    lib().orc_steps(C.byref(p), C.byref(s), replica_id, _p(x), _p(v), _p(cv), int(n_steps),
+                    int(step0), int(record_every), _p(frames), 3 * n)
+    return x, v, cv, frames
+
+
+def run_batch(params: dict, systems: Sequence[System], replica_system, x, v, cv,
+              n_steps: int, step0: int = 0, n_threads: int = 0):
+    """All replicas of a batch in flat layout (replica r as [3][N_r]); returns
+    (x, v, cv, threads_used)."""
+    rs = np.ascontiguousarray(replica_system, dtype=np.int32)
+    sizes = np.array([systems[s].n for s in rs], dtype=np.int64)
+    off = np.zeros(len(rs) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(sizes)
+    x = _f64(x).copy()
+    v = None if v is None else _f64(v).copy()
+    cv = _f64(cv).copy()
+    structs = (OrcSystem * len(systems))(*[s.cstruct() for s in systems])
+    p = make_params(params)
+    used = lib().orc_run_batch(C.byref(p), C.cast(structs, C.c_void_p), len(rs), _p(rs), _p(off),
+                               _p(x), _p(v), _p(cv), int(n_steps), int(step0), int(n_threads))
+    return x, v, cv, used
+
+
+def update_reference(n, cidx, frames, success, r0: float = 7.5, r_cut: float = 0.0):
+    """eq (avCij): mean contact map per frame over successful paths.
+    frames: [n_frames][n_paths][3][n].  Returns ([n_frames][P], n_success)."""
+    frames = _f64(frames)
+    nf, npth = frames.shape[0], frames.shape[1]
+    cidx = np.ascontiguousarray(cidx, dtype=np.int32)
+    nc = len(cidx)
+    succ = np.ascontiguousarray(success, dtype=np.uint8)
+    out = np.zeros((nf, nc * (nc - 1) // 2))
+    ns = lib().orc_update_reference(int(n), nc, _p(cidx), r0, r_cut, nf, npth, _p(frames),
+                                    _p(succ), _p(out))
+    return out, ns

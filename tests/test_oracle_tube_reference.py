@@ -1,0 +1,163 @@
+"""Pins of the oracle's path-ensemble mean map, eq (avCij), and of the
+mean-field tube variables s_lambda, w_lambda with their ratchet forces.
+
+Expected values: the appendix identity (as lambda grows, s -> 1 - l/M and
+w -> 0 when X is the l-th frame of the reference path), the uniform-weight
+case (identical frames give s = 1/2 exactly and w = d - log(K)/lambda),
+finite differences, numpy means of independently computed maps, and the
+subset/linearity properties of an arithmetic mean.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1705_02180_amd import inputs as I
+
+R0 = 7.5
+
+
+def _path(n=40, K=9, seed=3):
+    """A short oracle trajectory (frames) from an extended start."""
+    w = I.config1()
+    p = dict(w.params)
+    native = I.compact_native(n, seed)
+    s = O.System(n, np.arange(n), np.ones(n), np.zeros(n), p, native_xyz=native)
+    x = I.straight_start(n, seed + 1)
+    cv = np.zeros(8); cv[1] = np.inf
+    _, _, _, frames = O.steps(p, s, 0, x, None, cv, 40 * (K - 1), record_every=40)
+    return native, frames, s
+
+
+def test_appendix_limit_large_lambda():
+    native, frames, s = _path()
+    K = frames.shape[0]
+    cidx = s.cidx
+    stack = np.array([O.contact_map(f, cidx) for f in frames])
+    Z0 = float(np.sum(O.contact_map(native, cidx) ** 2))
+    M = K - 1
+    for l in (0, 3, M):
+        _, _, _, _, dk = O.tube(frames[l], cidx, stack, Z0, 1.0, grads=False)
+        assert dk[l] == 0.0
+        dmin = np.min(np.delete(dk, l))
+        assert dmin > 0
+        # every other frame is suppressed by at least exp(-lambda dmin)
+        for lam_dmin in (2.0, 8.0, 40.0):
+            lam = lam_dmin / dmin
+            sv, wv, _, _, _ = O.tube(frames[l], cidx, stack, Z0, lam, grads=False)
+            bound = K * np.exp(-lam_dmin)
+            assert abs(sv - (1.0 - l / M)) <= bound + 1e-15
+            assert 0.0 >= wv >= -bound / lam - 1e-15
+        assert abs(sv - (1.0 - l / M)) < 1e-15
+
+
+def test_identical_frames_give_uniform_weights():
+    native, frames, s = _path(30, 5, 8)
+    cidx = s.cidx
+    one = O.contact_map(frames[2], cidx)
+    K = 7
+    stack = np.tile(one, (K, 1))
+    Z0 = 3.7
+    lam = 13.5
+    x = frames[4]
+    sv, wv, gs, gw, dk = O.tube(x, cidx, stack, Z0, lam)
+    d = np.sum((O.contact_map(x, cidx) - one) ** 2) / Z0
+    assert np.allclose(dk, d, rtol=1e-14)
+    assert abs(sv - 0.5) < 1e-14
+    assert abs(wv - (d - np.log(K) / lam)) < 1e-12
+    # grad s = 0 and grad w = grad d = (1/Z0) grad z against the single frame
+    _, gz = O.z_grad(x, cidx, one)
+    assert np.abs(gs).max() < 1e-14 * max(1.0, np.abs(gw).max())
+    np.testing.assert_allclose(gw, gz / Z0, rtol=1e-11, atol=1e-15)
+
+
+def test_tube_gradients_central_differences():
+    native, frames, s = _path(24, 6, 5)
+    cidx = s.cidx
+    stack = np.array([O.contact_map(f, cidx) for f in frames])
+    Z0 = float(np.sum(O.contact_map(native, cidx) ** 2))
+    lam = 40.0
+    x = 0.5 * (frames[2] + frames[3])
+    sv, wv, gs, gw, _ = O.tube(x, cidx, stack, Z0, lam)
+    h = 1e-5
+    for i in (0, 7, 23):
+        for c in range(3):
+            xp = x.copy(); xp[c, i] += h
+            xm = x.copy(); xm[c, i] -= h
+            sp, wp, *_ = O.tube(xp, cidx, stack, Z0, lam, grads=False)
+            sm, wm, *_ = O.tube(xm, cidx, stack, Z0, lam, grads=False)
+            assert abs((sp - sm) / (2 * h) - gs[c, i]) < 1e-6 * max(1e-3, np.abs(gs).max())
+            assert abs((wp - wm) / (2 * h) - gw[c, i]) < 1e-6 * max(1e-3, np.abs(gw).max())
+
+
+def test_scps_bias_force_is_minus_gradient_of_ratchet_energies():
+    native, frames, s = _path(24, 6, 5)
+    cidx = s.cidx
+    stack = np.array([O.contact_map(f, cidx) for f in frames])
+    p = dict(I.config1().params)
+    p.update(bias_mode=1, lam=25.0, k_s=2.5, k_w=0.8)
+    so = O.System(s.n, cidx, np.ones(s.n), np.zeros(s.n), p, native_xyz=native, stack=stack)
+    x = 0.5 * (frames[2] + frames[4])
+    sv, wv, *_ = O.tube(x, cidx, stack, so.Z0, 25.0, grads=False)
+    sm, wm = sv - 0.05, wv - 0.01
+    cv = np.zeros(8); cv[5] = sm; cv[6] = wm
+    _, Fb, cv2 = O.total_force(p, so, x, cv)
+    assert cv2[3] == sv and cv2[4] == wv and cv2[5] == sm and cv2[6] == wm
+
+    def E(xx):
+        a, b, *_ = O.tube(xx, cidx, stack, so.Z0, 25.0, grads=False)
+        return 0.5 * 2.5 * max(a - sm, 0) ** 2 + 0.5 * 0.8 * max(b - wm, 0) ** 2
+
+    assert abs(cv2[2] - E(x)) < 1e-12
+    h = 1e-5
+    for i in (1, 12, 20):
+        for c in range(3):
+            xp = x.copy(); xp[c, i] += h
+            xm = x.copy(); xm[c, i] -= h
+            assert abs(-(E(xp) - E(xm)) / (2 * h) - Fb[c, i]) < 1e-6 * np.abs(Fb).max()
+
+
+# ---------------------------------------------------------------------------
+# eq (avCij): mean contact map over successful paths
+# ---------------------------------------------------------------------------
+def _ensemble(n=25, n_frames=4, n_paths=6, seed=2):
+    rng = np.random.default_rng(seed)
+    base = I.random_coil(n, seed)
+    fr = base[None, None] + rng.normal(0, 1.5, size=(n_frames, n_paths, 3, n))
+    return fr
+
+
+def test_reference_equals_numpy_mean_over_masked_paths():
+    fr = _ensemble()
+    cidx = np.array([0, 1, 4, 5, 9, 10, 16, 17, 23, 24], dtype=np.int32)
+    succ = np.array([1, 0, 1, 1, 0, 1], dtype=np.uint8)
+    out, ns = O.update_reference(25, cidx, fr, succ)
+    assert ns == 4
+    for k in range(fr.shape[0]):
+        maps = [O.contact_map(fr[k, q], cidx) for q in range(fr.shape[1]) if succ[q]]
+        np.testing.assert_allclose(out[k], np.mean(maps, axis=0), rtol=1e-14)
+
+
+def test_reference_of_identical_paths_is_their_map():
+    fr = _ensemble(n_paths=1)
+    fr = np.repeat(fr, 5, axis=1)
+    cidx = np.arange(25, dtype=np.int32)
+    out, ns = O.update_reference(25, cidx, fr, np.ones(5, dtype=np.uint8))
+    for k in range(fr.shape[0]):
+        np.testing.assert_allclose(out[k], O.contact_map(fr[k, 0], cidx), rtol=1e-14)
+
+
+def test_reference_is_linear_in_the_path_set():
+    fr = _ensemble()
+    cidx = np.arange(25, dtype=np.int32)
+    a = np.array([1, 1, 0, 0, 0, 0], dtype=np.uint8)
+    b = np.array([0, 0, 1, 1, 1, 1], dtype=np.uint8)
+    ra, _ = O.update_reference(25, cidx, fr, a)
+    rb, _ = O.update_reference(25, cidx, fr, b)
+    rab, _ = O.update_reference(25, cidx, fr, a | b)
+    np.testing.assert_allclose(rab, (2 * ra + 4 * rb) / 6, rtol=1e-13)
+
+
+def test_reference_with_no_success_reports_zero():
+    fr = _ensemble()
+    out, ns = O.update_reference(25, np.arange(25), fr, np.zeros(6, dtype=np.uint8))
+    assert ns == 0 and np.all(out == 0.0)
