@@ -1,0 +1,214 @@
+/*
+ * scps.h -- C ABI of the MI355X batched rMD / SCPS stepping library.
+ *
+ * The library advances many independent replicas of chain molecules under
+ * Langevin dynamics, eq (Lang) of Orioli, a Beccara, Faccioli, "Self
+ * Consistent Path Sampling" (arXiv:1705.02180), biased either by the
+ * ratchet-and-pawl force on the contact-map coordinate z (rMD, eqs (FrMD),
+ * (zrMD), (Cij)) or by the ratchets on the mean-field tube variables
+ * s_lambda, w_lambda (SCPS, eqs (asXa), (awXa), (Fw), (Fs)), and
+ * re-estimates the path-ensemble mean contact map, eq (avCij), from the
+ * paths it generates.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every call returns scps_status.  On failure scps_last_error() returns a
+ *   thread-local message.  INVALID_ARG, SHAPE and STATE leave the context
+ *   usable.  HIP and NONFINITE poison it: afterwards only scps_sync() and
+ *   scps_destroy() are accepted.  No C++ exception crosses the ABI.
+ * - "device" pointers are HIP device allocations (e.g. torch tensors'
+ *   data_ptr() on the same GPU); "host" pointers are ordinary memory and are
+ *   read or written before the call returns.  The library never frees a
+ *   caller's buffer.
+ * - Device work is queued on the context's HIP stream and is asynchronous
+ *   with respect to the host unless stated otherwise.  The caller keeps
+ *   device buffers alive until that work has completed (torch tensors used
+ *   on the same stream satisfy this).
+ * - The library cannot check the extent of a caller's buffer; the sizes
+ *   stated below are the caller's contract.
+ * - A context is not re-entrant: one thread, one stream at a time.
+ *
+ * Data layouts
+ * ------------
+ * - Particles of system s are numbered 0..N_s-1 along the chain.  Bonds join
+ *   i and i+1.  Replica r runs system replica_system[r]; off_r is the sum of
+ *   N over replicas 0..r-1 and Σ N is the sum over all replicas.
+ * - Coordinates x, velocities v: float32, flat, replica r occupies
+ *   [3*off_r, 3*off_r + 3*N_r) as [3][N_r] (all x, then all y, then all z).
+ * - cvstate: float64 [R][SCPS_CV_STRIDE], see the SCPS_CV_* slots.  The
+ *   running minima z_m, s_m, w_m start at +INFINITY; the first force
+ *   evaluation then sets them to the current value (z_m(0) = z(X(0)), as in
+ *   the rMD section of the paper).
+ * - Contact maps are packed upper triangles over a system's contact set:
+ *   for contact positions a<b (indices into contact_idx) the entry sits at
+ *   a*n_c - a*(a+1)/2 + (b-a-1); P = n_c*(n_c-1)/2 entries per map.
+ */
+#ifndef SCPS_H
+#define SCPS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SCPS_OK = 0,
+    SCPS_ERR_INVALID_ARG = -1, /* a NULL or out-of-range argument */
+    SCPS_ERR_SHAPE = -2,       /* sizes that do not fit together */
+    SCPS_ERR_OOM = -3,         /* device or host allocation failed */
+    SCPS_ERR_HIP = -4,         /* a HIP runtime call failed (context poisoned) */
+    SCPS_ERR_STATE = -5,       /* call not valid in the current state */
+    SCPS_ERR_NONFINITE = -6,   /* a replica produced a non-finite coordinate */
+    SCPS_ERR_NO_SUCCESS = -7   /* update_reference_from_paths: no successful path */
+} scps_status;
+
+typedef struct scps_ctx scps_ctx;
+
+#define SCPS_CV_STRIDE 8
+enum {
+    SCPS_CV_Z = 0,   /* z(X) at the last force evaluation (rMD) */
+    SCPS_CV_ZM = 1,  /* running minimum z_m (rMD) */
+    SCPS_CV_EB = 2,  /* bias energy at the last force evaluation */
+    SCPS_CV_S = 3,   /* s_lambda (SCPS) */
+    SCPS_CV_W = 4,   /* w_lambda (SCPS), without the constant w0 */
+    SCPS_CV_SM = 5,  /* running minimum s_m (SCPS) */
+    SCPS_CV_WM = 6   /* running minimum w_m (SCPS) */
+};
+
+enum { SCPS_INTEGRATOR_OVERDAMPED = 0, SCPS_INTEGRATOR_BAOAB = 1 };
+enum { SCPS_BIAS_RMD = 0, SCPS_BIAS_SCPS = 1 };
+enum { SCPS_EXEC_AUTO = 0, SCPS_EXEC_PER_STEP = 1 };
+
+/* Physics and bias parameters (any consistent unit system; the protein-shaped
+ * workloads use A, ps, kJ/mol, e and masses in kJ/mol ps^2/A^2). */
+typedef struct {
+    int32_t integrator;   /* SCPS_INTEGRATOR_*.  Overdamped: x += dt F/(m gamma) + sqrt(2 kT dt/(m gamma)) xi.
+                             BAOAB: v holds the velocity right after the friction/noise substep, so each step is
+                             v += dt F/m; x += dt/2 v; v = c1 v + sqrt((1-c1^2) kT/m) xi; x += dt/2 v, c1 = exp(-gamma dt) */
+    int32_t bias_mode;    /* SCPS_BIAS_RMD: ratchet on z, eq (FrMD).  SCPS_BIAS_SCPS: ratchets on s, w, eqs (Fw),(Fs) */
+    int32_t exec_mode;    /* SCPS_EXEC_AUTO: one persistent launch per call where a replica fits one workgroup;
+                             SCPS_EXEC_PER_STEP: a few kernel launches per step (always used for SCPS and large chains) */
+    int32_t nb_excl;      /* nonbonded pairs need |i-j| > nb_excl (>= 1) */
+    int32_t min_seq_sep;  /* contact pairs need |i-j| > min_seq_sep; the paper's all-atom value is 35 */
+    int32_t replica_base; /* replica r uses replica_base + r as its noise counter word, so a context that
+                             holds one replica of a larger batch reproduces that replica's noise */
+    double dt, gamma, kT;
+    double k_bond, r_bond;        /* harmonic bond i,i+1 */
+    double lj_eps, lj_sigma;      /* Lennard-Jones 12-6; lj_eps = 0 disables */
+    double dh_prefactor, dh_kappa;/* Debye-Hueckel k_e/eps_r * q_i q_j exp(-kappa r)/r; prefactor 0 disables */
+    double r0_contact;            /* r0 of eq (Cij) */
+    double r_cut_contact;         /* <= 0: no cutoff; else C = 0 for r > r_cut */
+    double k_R;                   /* rMD ratchet constant */
+    double lambda, k_s, k_w;      /* SCPS tube variables and ratchet constants */
+    uint64_t seed;                /* Philox4x32-10 key */
+} scps_params;
+
+/* Chains.  All arrays are host memory, copied during scps_init_system. */
+typedef struct {
+    int32_t n_systems;
+    const int32_t *n_particles;   /* [n_systems], each in [2, 1<<20] */
+    const int32_t *n_contact;     /* [n_systems], each in [0, N_s] */
+    const int32_t *contact_idx;   /* concatenated per system, strictly ascending particle indices */
+    const float *mass;            /* concatenated per particle, > 0 */
+    const float *charge;          /* concatenated per particle */
+} scps_topology;
+
+/* Create a context for n_replicas replicas; replica r runs system
+ * replica_system[r] (host array).  hip_stream: a hipStream_t, or NULL for the
+ * null stream.  Allocates the context's device buffers.  Reference maps are
+ * unset until scps_set_reference_map.  Errors: INVALID_ARG, SHAPE, OOM, HIP. */
+scps_status scps_init_system(const scps_params *params, const scps_topology *topology,
+                             int32_t n_replicas, const int32_t *replica_system,
+                             void *hip_stream, scps_ctx **out);
+
+/* Set a system's reference maps.
+ *  n_maps == 1: the native map C0 used by z, eq (zrMD), and by the norm of the
+ *    tube distance.  Either maps (host float64 [P]) or, when maps is NULL,
+ *    native_xyz (host float64 [3][N]) from which C0 = C(X_N), eq (Cij), is
+ *    computed on the device in float64.  z0_norm <= 0 sets
+ *    Z0 = sum_p (C0_p)^2, the denominator of the normalised distance
+ *    ||C - C'||^2 of the SCPS section; otherwise Z0 = z0_norm.
+ *  n_maps >= 2: the SCPS frame stack <C(t_k)>, k = 0..n_maps-1, host float64
+ *    [n_maps][P] in maps; native_xyz must be NULL and z0_norm is ignored.
+ * Blocks until the upload is done.  Errors: INVALID_ARG, OOM, HIP. */
+scps_status scps_set_reference_map(scps_ctx *ctx, int32_t system, int32_t n_maps,
+                                   const double *maps, const double *native_xyz,
+                                   double z0_norm);
+
+/* Advance every replica by n_steps Langevin steps (eq (Lang)) with the bias
+ * of params.bias_mode; global step indices step0 .. step0+n_steps-1.
+ * Each step starts with a force evaluation at the current X, which updates
+ * the running minima before the bias is applied (so the bias vanishes
+ * whenever the collective variable reaches a new minimum).  The noise of
+ * particle i of replica r at step t is Philox4x32-10 with key = seed and
+ * counter = (i, replica_base + r, low32(t), high32(t)); each of the four 32-bit words w maps
+ * to the uniform (2*(w>>9)+1)*2^-24 and Box-Muller turns words 0,1 into the
+ * x, y normals and words 2,3 into the z normal.  Results therefore do not
+ * depend on batching or on how the call is split into smaller calls.
+ *   x, v: device float32 (layout above), in/out.  v may be NULL for the
+ *         overdamped integrator and must not be NULL for BAOAB.
+ *   cvstate: device float64 [R][SCPS_CV_STRIDE], in/out.
+ *   record_every > 0: frames (device float32) receives X after local steps
+ *         0, E, 2E, ... <= n_steps, each record being a full copy of the x
+ *         layout, i.e. frames is [n_steps/E + 1][3 Σ N].  record_every == 0:
+ *         frames is ignored.
+ * Non-finite coordinates are flagged per replica on the device and reported
+ * by scps_sync().  Requires the native map of every system (rMD) or the frame
+ * stack and native map (SCPS).  Errors: INVALID_ARG, STATE, HIP. */
+scps_status scps_step_replicas(scps_ctx *ctx, float *x, float *v, double *cvstate,
+                               int64_t n_steps, uint64_t step0, int32_t record_every,
+                               float *frames);
+
+/* z(X) of eq (zrMD) against each replica's native map, and optionally its
+ * gradient.  x: device float32 (layout above).  z: device float64 [R].
+ * grad: device float32 (x layout) or NULL; receives coef_r * dz/dx for
+ * replica r, where coef_r = grad_coef[r] (device float64 [R]) or 1 when
+ * grad_coef is NULL.  C_ij is recomputed per pair; no map of the current
+ * contacts is stored.  Errors: INVALID_ARG, STATE, HIP. */
+scps_status scps_eval_z_and_grad(scps_ctx *ctx, const float *x, double *z, float *grad,
+                                 const double *grad_coef);
+
+/* Ratchet bias energy and its backward coefficient for a batch of z values
+ * (rMD, eq (FrMD)): E_b[r] = 1/2 k_R (z - z_m)^2 theta(z - z_m), and, when
+ * coef is not NULL, coef[r] = gz[r] + gE[r] * k_R (z - z_m) theta(z - z_m), the
+ * factor that multiplies dz/dx in the gradient of gz*z + gE*E_b.  All
+ * pointers are device float64 [R]; gz and gE may be NULL (taken as 0).
+ * Errors: INVALID_ARG, HIP. */
+scps_status scps_ratchet_energy(scps_ctx *ctx, const double *z, const double *z_m,
+                                double *E_b, const double *gz, const double *gE,
+                                double *coef);
+
+/* Path-ensemble mean contact map, eq (avCij): for every recorded frame k,
+ * <C(t_k)>_p = (1/|S|) sum over successful paths p of C(X_p(t_k)), summed in
+ * float64, and install the result as the system's SCPS frame stack
+ * (n_frames maps).  frames: device float32 [n_frames][n_paths][3][N] (the
+ * layout step_replicas records when all replicas run this system).
+ * success: host uint8 [n_paths], nonzero = path used (the paper keeps paths
+ * that reached the native state).  maps_out: host float64 [n_frames][P] or
+ * NULL.  Blocks until done.  Errors: INVALID_ARG, NO_SUCCESS (stack
+ * unchanged), OOM, HIP. */
+scps_status scps_update_reference_from_paths(scps_ctx *ctx, int32_t system, const float *frames,
+                                             int32_t n_paths, int32_t n_frames,
+                                             const uint8_t *success, double *maps_out);
+
+/* Replace the stream later calls queue work on (a hipStream_t or NULL). */
+scps_status scps_set_stream(scps_ctx *ctx, void *hip_stream);
+
+/* Wait for the context's stream and report replicas flagged non-finite:
+ * *n_bad receives their count and, if bad_replicas is not NULL, up to R ids
+ * (host int32 [R]).  Returns NONFINITE if any replica was flagged (and
+ * poisons the context), HIP on a runtime error, OK otherwise. */
+scps_status scps_sync(scps_ctx *ctx, int32_t *bad_replicas, int32_t *n_bad);
+
+/* Free the context and everything it owns; NULL is accepted. */
+void scps_destroy(scps_ctx *ctx);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *scps_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SCPS_H */

@@ -1,0 +1,595 @@
+// Host side of libscps: validation, ownership, work lists and launches.
+// Every entry point of include/scps.h is defined here.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <exception>
+#include <memory>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/scps.h"
+#include "scps_internal.h"
+
+using namespace scps;
+
+namespace {
+
+thread_local std::string g_err;
+
+scps_status fail(scps_status s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+
+struct SysHost {
+    int n = 0, n_pad = 0, nb = 0, nc = 0, ncb = 0, ntile_c = 0;
+    std::vector<int> perm, bond_next;
+    std::vector<float> mass, charge;
+    int *d_perm = nullptr, *d_bond_next = nullptr;
+    float *d_mass = nullptr, *d_charge = nullptr;
+    float *d_ref = nullptr;
+    bool has_native = false;
+    double Z0 = 0.0;
+    float *d_stack = nullptr;
+    int K = 0;
+};
+
+}  // namespace
+
+struct scps_ctx {
+    scps_params prm{};
+    KParams kp{};
+    hipStream_t stream = nullptr;
+    int R = 0;
+    std::vector<SysHost> sys;
+    std::vector<int> rep_sys;
+    std::vector<int64_t> rep_off, rep_poff;
+    int64_t sumN = 0, sumNpad = 0;
+    int n_pad_max = 0;
+    bool poisoned = false;
+    // device
+    SysDesc *d_sysd = nullptr;
+    RepDesc *d_reps = nullptr;
+    int *d_order = nullptr;
+    int *d_flags = nullptr;
+    TileItem *d_items_all = nullptr;
+    int n_items_all = 0;
+    TileItem *d_items_contact = nullptr;
+    int n_items_contact = 0;
+    float4 *d_xs = nullptr, *d_vs = nullptr;
+    double *d_acc = nullptr, *d_zbuf = nullptr, *d_scale = nullptr, *d_negone = nullptr;
+    double *d_dsum = nullptr, *d_csum = nullptr;
+    float *d_coef = nullptr;
+    int kmax = KMAX;
+    std::vector<void *> owned;
+};
+
+namespace {
+
+#define HIP_TRY(ctx, expr)                                                                  \
+    do {                                                                                    \
+        hipError_t _e = (expr);                                                             \
+        if (_e != hipSuccess) {                                                             \
+            if (ctx) (ctx)->poisoned = true;                                                \
+            return fail(SCPS_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(_e));  \
+        }                                                                                   \
+    } while (0)
+
+template <typename T>
+hipError_t dalloc(scps_ctx *c, T **p, size_t count) {
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T));
+    if (e == hipSuccess) c->owned.push_back(q);
+    *p = reinterpret_cast<T *>(q);
+    return e;
+}
+
+void dfree(scps_ctx *c, void *p) {
+    if (!p) return;
+    auto it = std::find(c->owned.begin(), c->owned.end(), p);
+    if (it != c->owned.end()) c->owned.erase(it);
+    (void)hipFree(p);
+}
+
+KParams make_kparams(const scps_params &p) {
+    KParams k{};
+    k.inv_r0sq = (float)(1.0 / (p.r0_contact * p.r0_contact));
+    k.g_scale = (float)(4.0 / (p.r0_contact * p.r0_contact));
+    k.has_cut = p.r_cut_contact > 0.0;
+    k.r_cut2 = (float)(p.r_cut_contact * p.r_cut_contact);
+    k.lj_sig2 = (float)(p.lj_sigma * p.lj_sigma);
+    k.lj_24eps = (float)(24.0 * p.lj_eps);
+    k.has_lj = p.lj_eps != 0.0;
+    k.dh_pref = (float)p.dh_prefactor;
+    k.dh_kappa = (float)p.dh_kappa;
+    k.dh_kl2 = (float)(-p.dh_kappa * 1.4426950408889634);
+    k.has_dh = p.dh_prefactor != 0.0;
+    k.nb_excl = p.nb_excl;
+    k.min_sep = p.min_seq_sep;
+    k.integrator = p.integrator;
+    k.dt = p.dt;
+    k.kT = p.kT;
+    k.gamma = p.gamma;
+    k.c1 = exp(-p.gamma * p.dt);
+    k.k_bond = p.k_bond;
+    k.has_bond = p.k_bond != 0.0;
+    k.r_bond = p.r_bond;
+    k.k_R = p.k_R;
+    k.lambda = p.lambda;
+    k.k_s = p.k_s;
+    k.k_w = p.k_w;
+    k.seed_lo = (uint32_t)p.seed;
+    k.seed_hi = (uint32_t)(p.seed >> 32);
+    k.rep_base = (uint32_t)p.replica_base;
+    return k;
+}
+
+scps_status upload_sysdesc(scps_ctx *c) {
+    std::vector<SysDesc> d(c->sys.size());
+    for (size_t s = 0; s < c->sys.size(); ++s) {
+        const SysHost &h = c->sys[s];
+        SysDesc &o = d[s];
+        o.n = h.n;
+        o.n_pad = h.n_pad;
+        o.nb = h.nb;
+        o.nc = h.nc;
+        o.ncb = h.ncb;
+        o.ntile_c = h.ntile_c;
+        o.K = h.K;
+        o.perm = h.d_perm;
+        o.bond_next = h.d_bond_next;
+        o.mass = h.d_mass;
+        o.charge = h.d_charge;
+        o.ref = h.d_ref;
+        o.stack = h.d_stack;
+        o.Z0 = h.Z0;
+    }
+    HIP_TRY(c, hipMemcpy(c->d_sysd, d.data(), d.size() * sizeof(SysDesc), hipMemcpyHostToDevice));
+    return SCPS_OK;
+}
+
+bool usable(scps_ctx *c, scps_status *st) {
+    if (!c) {
+        *st = fail(SCPS_ERR_INVALID_ARG, "context is NULL");
+        return false;
+    }
+    if (c->poisoned) {
+        *st = fail(SCPS_ERR_STATE, "context is poisoned by an earlier HIP or non-finite error");
+        return false;
+    }
+    return true;
+}
+
+int pick_wg(int nb) {
+    const int ntile = nb * (nb + 1) / 2;
+    if (ntile >= 16) return 1024;
+    if (ntile >= 8) return 512;
+    if (ntile >= 4) return 256;
+    return 64;
+}
+
+scps_status init_impl(const scps_params *params, const scps_topology *topo, int32_t R, const int32_t *rsys,
+                      void *stream, scps_ctx **out) {
+    if (!params || !topo || !rsys || !out) return fail(SCPS_ERR_INVALID_ARG, "NULL argument");
+    *out = nullptr;
+    const scps_params &p = *params;
+    if (p.integrator != SCPS_INTEGRATOR_OVERDAMPED && p.integrator != SCPS_INTEGRATOR_BAOAB)
+        return fail(SCPS_ERR_INVALID_ARG, "integrator must be 0 (overdamped) or 1 (BAOAB)");
+    if (p.bias_mode != SCPS_BIAS_RMD && p.bias_mode != SCPS_BIAS_SCPS)
+        return fail(SCPS_ERR_INVALID_ARG, "bias_mode must be 0 (rMD) or 1 (SCPS)");
+    if (p.exec_mode != SCPS_EXEC_AUTO && p.exec_mode != SCPS_EXEC_PER_STEP)
+        return fail(SCPS_ERR_INVALID_ARG, "exec_mode must be 0 or 1");
+    if (!(p.dt > 0) || !(p.gamma > 0) || !(p.kT >= 0) || !(p.r0_contact > 0))
+        return fail(SCPS_ERR_INVALID_ARG, "dt, gamma, r0_contact must be > 0 and kT >= 0");
+    if (p.nb_excl < 1 || p.min_seq_sep < 0 || p.replica_base < 0)
+        return fail(SCPS_ERR_INVALID_ARG, "nb_excl must be >= 1, min_seq_sep and replica_base >= 0");
+    if (p.bias_mode == SCPS_BIAS_SCPS && !(p.lambda > 0))
+        return fail(SCPS_ERR_INVALID_ARG, "lambda must be > 0 in SCPS mode");
+    if (p.lj_eps != 0.0 && !(p.lj_sigma > 0)) return fail(SCPS_ERR_INVALID_ARG, "lj_sigma must be > 0");
+    if (topo->n_systems < 1 || !topo->n_particles || !topo->n_contact || !topo->mass || !topo->charge)
+        return fail(SCPS_ERR_INVALID_ARG, "topology needs n_systems >= 1 and non-NULL arrays");
+    if (R < 1) return fail(SCPS_ERR_INVALID_ARG, "n_replicas must be >= 1");
+
+    scps_ctx *c = new (std::nothrow) scps_ctx();
+    if (!c) return fail(SCPS_ERR_OOM, "host allocation failed");
+    std::unique_ptr<scps_ctx, void (*)(scps_ctx *)> guard(c, scps_destroy);
+    c->prm = p;
+    c->kp = make_kparams(p);
+    c->stream = (hipStream_t)stream;
+    c->R = R;
+
+    int64_t poff_part = 0, poff_cidx = 0;
+    c->sys.resize(topo->n_systems);
+    for (int s = 0; s < topo->n_systems; ++s) {
+        SysHost &h = c->sys[s];
+        h.n = topo->n_particles[s];
+        h.nc = topo->n_contact[s];
+        if (h.n < 2 || h.n > (1 << 20)) return fail(SCPS_ERR_SHAPE, "n_particles must be in [2, 2^20]");
+        if (h.nc < 0 || h.nc > h.n) return fail(SCPS_ERR_SHAPE, "n_contact must be in [0, n_particles]");
+        if (h.nc > 0 && !topo->contact_idx) return fail(SCPS_ERR_INVALID_ARG, "contact_idx is NULL");
+        h.n_pad = (h.n + TILE - 1) / TILE * TILE;
+        h.nb = h.n_pad / TILE;
+        h.ncb = (h.nc + TILE - 1) / TILE;
+        h.ntile_c = h.ncb * (h.ncb + 1) / 2;
+        const int32_t *ci = topo->contact_idx + poff_cidx;
+        std::vector<char> in_c(h.n, 0);
+        for (int a = 0; a < h.nc; ++a) {
+            if (ci[a] < 0 || ci[a] >= h.n || (a > 0 && ci[a] <= ci[a - 1]))
+                return fail(SCPS_ERR_INVALID_ARG, "contact_idx must be strictly ascending within [0, N)");
+            in_c[ci[a]] = 1;
+        }
+        h.perm.resize(h.n_pad);
+        std::vector<int> inv(h.n);
+        int k = 0;
+        for (int a = 0; a < h.nc; ++a) h.perm[k++] = ci[a];
+        for (int i = 0; i < h.n; ++i)
+            if (!in_c[i]) h.perm[k++] = i;
+        for (int a = h.n; a < h.n_pad; ++a) h.perm[a] = a;  // pads: indices >= n
+        for (int a = 0; a < h.n; ++a) inv[h.perm[a]] = a;
+        h.bond_next.assign(h.n_pad, -1);
+        h.mass.assign(h.n_pad, 1.f);
+        h.charge.assign(h.n_pad, 0.f);
+        for (int a = 0; a < h.n; ++a) {
+            const int o = h.perm[a];
+            if (o + 1 < h.n) h.bond_next[a] = inv[o + 1];
+            const float m = topo->mass[poff_part + o];
+            if (!(m > 0.f)) return fail(SCPS_ERR_INVALID_ARG, "masses must be > 0");
+            h.mass[a] = m;
+            h.charge[a] = topo->charge[poff_part + o];
+        }
+        poff_part += h.n;
+        poff_cidx += h.nc;
+        c->n_pad_max = std::max(c->n_pad_max, h.n_pad);
+    }
+    c->rep_sys.assign(rsys, rsys + R);
+    c->rep_off.resize(R + 1);
+    c->rep_poff.resize(R + 1);
+    c->rep_off[0] = c->rep_poff[0] = 0;
+    for (int r = 0; r < R; ++r) {
+        if (rsys[r] < 0 || rsys[r] >= topo->n_systems)
+            return fail(SCPS_ERR_INVALID_ARG, "replica_system entry out of range");
+        c->rep_off[r + 1] = c->rep_off[r] + c->sys[rsys[r]].n;
+        c->rep_poff[r + 1] = c->rep_poff[r] + c->sys[rsys[r]].n_pad;
+    }
+    c->sumN = c->rep_off[R];
+    c->sumNpad = c->rep_poff[R];
+
+    // device buffers
+    for (auto &h : c->sys) {
+        HIP_TRY(c, dalloc(c, &h.d_perm, h.n_pad));
+        HIP_TRY(c, dalloc(c, &h.d_bond_next, h.n_pad));
+        HIP_TRY(c, dalloc(c, &h.d_mass, h.n_pad));
+        HIP_TRY(c, dalloc(c, &h.d_charge, h.n_pad));
+        HIP_TRY(c, hipMemcpy(h.d_perm, h.perm.data(), h.n_pad * sizeof(int), hipMemcpyHostToDevice));
+        HIP_TRY(c, hipMemcpy(h.d_bond_next, h.bond_next.data(), h.n_pad * sizeof(int), hipMemcpyHostToDevice));
+        HIP_TRY(c, hipMemcpy(h.d_mass, h.mass.data(), h.n_pad * sizeof(float), hipMemcpyHostToDevice));
+        HIP_TRY(c, hipMemcpy(h.d_charge, h.charge.data(), h.n_pad * sizeof(float), hipMemcpyHostToDevice));
+    }
+    HIP_TRY(c, dalloc(c, &c->d_sysd, c->sys.size()));
+    scps_status st = upload_sysdesc(c);
+    if (st != SCPS_OK) return st;
+
+    std::vector<RepDesc> reps(R);
+    for (int r = 0; r < R; ++r) {
+        reps[r].sys = rsys[r];
+        reps[r].off = c->rep_off[r];
+        reps[r].poff = c->rep_poff[r];
+    }
+    HIP_TRY(c, dalloc(c, &c->d_reps, R));
+    HIP_TRY(c, hipMemcpy(c->d_reps, reps.data(), R * sizeof(RepDesc), hipMemcpyHostToDevice));
+
+    // persistent launch order: longest replicas first
+    std::vector<int> order(R);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return c->sys[rsys[a]].n > c->sys[rsys[b]].n; });
+    HIP_TRY(c, dalloc(c, &c->d_order, R));
+    HIP_TRY(c, hipMemcpy(c->d_order, order.data(), R * sizeof(int), hipMemcpyHostToDevice));
+
+    // per-step work lists: every tile pair, and the contact tile pairs
+    std::vector<TileItem> all, con;
+    for (int r = 0; r < R; ++r) {
+        const SysHost &h = c->sys[rsys[r]];
+        for (int I = 0; I < h.nb; ++I)
+            for (int J = I; J < h.nb; ++J) {
+                TileItem t{r, I, J, 0};
+                all.push_back(t);
+                if (I < h.ncb && J < h.ncb) con.push_back(t);
+            }
+    }
+    c->n_items_all = (int)all.size();
+    c->n_items_contact = (int)con.size();
+    HIP_TRY(c, dalloc(c, &c->d_items_all, all.size()));
+    HIP_TRY(c, dalloc(c, &c->d_items_contact, con.size()));
+    if (!all.empty())
+        HIP_TRY(c, hipMemcpy(c->d_items_all, all.data(), all.size() * sizeof(TileItem), hipMemcpyHostToDevice));
+    if (!con.empty())
+        HIP_TRY(c, hipMemcpy(c->d_items_contact, con.data(), con.size() * sizeof(TileItem),
+                             hipMemcpyHostToDevice));
+
+    HIP_TRY(c, dalloc(c, &c->d_flags, R));
+    HIP_TRY(c, hipMemset(c->d_flags, 0, R * sizeof(int)));
+    HIP_TRY(c, dalloc(c, &c->d_xs, c->sumNpad));
+    HIP_TRY(c, dalloc(c, &c->d_vs, c->sumNpad));
+    HIP_TRY(c, dalloc(c, &c->d_acc, 6 * c->sumNpad));
+    HIP_TRY(c, hipMemset(c->d_acc, 0, 6 * c->sumNpad * sizeof(double)));
+    HIP_TRY(c, dalloc(c, &c->d_zbuf, R));
+    HIP_TRY(c, hipMemset(c->d_zbuf, 0, R * sizeof(double)));
+    HIP_TRY(c, dalloc(c, &c->d_scale, R));
+    HIP_TRY(c, dalloc(c, &c->d_negone, R));
+    std::vector<double> neg(R, -1.0);
+    HIP_TRY(c, hipMemcpy(c->d_negone, neg.data(), R * sizeof(double), hipMemcpyHostToDevice));
+    if (p.bias_mode == SCPS_BIAS_SCPS) {
+        HIP_TRY(c, dalloc(c, &c->d_dsum, (size_t)R * c->kmax));
+        HIP_TRY(c, hipMemset(c->d_dsum, 0, (size_t)R * c->kmax * sizeof(double)));
+        HIP_TRY(c, dalloc(c, &c->d_coef, (size_t)R * c->kmax));
+        HIP_TRY(c, dalloc(c, &c->d_csum, R));
+    }
+    *out = guard.release();
+    return SCPS_OK;
+}
+
+scps_status set_ref_impl(scps_ctx *c, int32_t s, int32_t n_maps, const double *maps, const double *xyz,
+                         double z0) {
+    if (s < 0 || s >= (int)c->sys.size()) return fail(SCPS_ERR_INVALID_ARG, "system index out of range");
+    SysHost &h = c->sys[s];
+    const int64_t P = (int64_t)h.nc * (h.nc - 1) / 2;
+    if (n_maps < 1) return fail(SCPS_ERR_INVALID_ARG, "n_maps must be >= 1");
+    if (n_maps == 1) {
+        if (!maps && !xyz) return fail(SCPS_ERR_INVALID_ARG, "need maps or native_xyz");
+        if (!h.d_ref) HIP_TRY(c, dalloc(c, &h.d_ref, (size_t)h.ntile_c * 4096));
+        double *d_packed = nullptr, *d_sum = nullptr;
+        HIP_TRY(c, dalloc(c, &d_packed, (size_t)std::max<int64_t>(P, 1)));
+        HIP_TRY(c, dalloc(c, &d_sum, 1));
+        if (maps) {
+            HIP_TRY(c, hipMemcpy(d_packed, maps, P * sizeof(double), hipMemcpyHostToDevice));
+            HIP_TRY(c, launch_pack_to_tiles(1, h.nc, h.ncb, d_packed, h.d_ref, c->stream));
+        } else {
+            double *d_xyz = nullptr;
+            HIP_TRY(c, dalloc(c, &d_xyz, 3 * (size_t)h.n));
+            HIP_TRY(c, hipMemcpy(d_xyz, xyz, 3 * h.n * sizeof(double), hipMemcpyHostToDevice));
+            HIP_TRY(c, launch_native_map(h.n, h.n_pad, h.nc, h.ncb, h.d_perm, d_xyz, c->prm.r0_contact,
+                                         c->prm.r_cut_contact, h.d_ref, d_packed, c->stream));
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            dfree(c, d_xyz);
+        }
+        double zz = z0;
+        if (!(z0 > 0.0)) {
+            HIP_TRY(c, launch_sum_squares(P, d_packed, d_sum, c->stream));
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            HIP_TRY(c, hipMemcpy(&zz, d_sum, sizeof(double), hipMemcpyDeviceToHost));
+        }
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        dfree(c, d_packed);
+        dfree(c, d_sum);
+        h.Z0 = zz;
+        h.has_native = true;
+    } else {
+        if (!maps || xyz) return fail(SCPS_ERR_INVALID_ARG, "a frame stack needs maps and no native_xyz");
+        if (n_maps > KMAX) return fail(SCPS_ERR_SHAPE, "at most 64 frames in an SCPS stack");
+        if (h.K != n_maps) {
+            dfree(c, h.d_stack);
+            h.d_stack = nullptr;
+            h.K = 0;
+            HIP_TRY(c, dalloc(c, &h.d_stack, (size_t)n_maps * h.ntile_c * 4096));
+        }
+        double *d_packed = nullptr;
+        HIP_TRY(c, dalloc(c, &d_packed, (size_t)std::max<int64_t>(P * n_maps, 1)));
+        HIP_TRY(c, hipMemcpy(d_packed, maps, (size_t)P * n_maps * sizeof(double), hipMemcpyHostToDevice));
+        HIP_TRY(c, launch_pack_to_tiles(n_maps, h.nc, h.ncb, d_packed, h.d_stack, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        dfree(c, d_packed);
+        h.K = n_maps;
+    }
+    return upload_sysdesc(c);
+}
+
+scps_status step_impl(scps_ctx *c, float *x, float *v, double *cv, int64_t n_steps, uint64_t step0,
+                      int32_t record_every, float *frames) {
+    if (!x || !cv) return fail(SCPS_ERR_INVALID_ARG, "x and cvstate must not be NULL");
+    if (n_steps < 0 || record_every < 0) return fail(SCPS_ERR_INVALID_ARG, "n_steps and record_every must be >= 0");
+    if (record_every > 0 && !frames) return fail(SCPS_ERR_INVALID_ARG, "frames is NULL but record_every > 0");
+    if (c->prm.integrator == SCPS_INTEGRATOR_BAOAB && !v)
+        return fail(SCPS_ERR_INVALID_ARG, "BAOAB needs velocities");
+    const bool scps = c->prm.bias_mode == SCPS_BIAS_SCPS;
+    for (int r = 0; r < c->R; ++r) {
+        const SysHost &h = c->sys[c->rep_sys[r]];
+        if (!h.has_native) return fail(SCPS_ERR_STATE, "a system has no native map (scps_set_reference_map)");
+        if (scps && h.K < 2) return fail(SCPS_ERR_STATE, "SCPS mode needs a frame stack of >= 2 maps");
+    }
+    const int64_t frame_stride = 3 * c->sumN;
+    bool persistent = !scps && c->prm.exec_mode == SCPS_EXEC_AUTO;
+    int nbmax = c->n_pad_max / TILE;
+    const int wg = pick_wg(nbmax);
+    if (persistent && c->n_pad_max > persistent_max_npad(wg)) persistent = false;
+    if (persistent) {
+        HIP_TRY(c, launch_persistent_rmd(wg, c->kp, c->d_sysd, c->d_reps, c->d_order, c->R, c->n_pad_max, x, v, cv,
+                                         n_steps, step0, record_every, frames, frame_stride, c->d_flags,
+                                         c->stream));
+        return SCPS_OK;
+    }
+    HIP_TRY(c, launch_gather(c->d_sysd, c->d_reps, c->R, c->n_pad_max, x, v, c->d_xs, v ? c->d_vs : nullptr,
+                             c->stream));
+    for (int64_t m = 0;; ++m) {
+        if (record_every > 0 && m % record_every == 0)
+            HIP_TRY(c, launch_scatter(c->d_sysd, c->d_reps, c->R, c->n_pad_max, c->d_xs, nullptr, nullptr, nullptr,
+                                      frames + (m / record_every) * frame_stride, c->stream));
+        if (m == n_steps) break;
+        if (!scps) {
+            HIP_TRY(c, launch_pairs(0, c->kp, c->d_sysd, c->d_reps, c->d_items_all, c->n_items_all, c->d_xs,
+                                    c->d_acc, c->d_zbuf, nullptr, nullptr, nullptr, c->kmax, c->stream));
+            HIP_TRY(c, launch_finalize_rmd(c->kp, c->R, c->d_zbuf, cv, c->d_scale, c->stream));
+            HIP_TRY(c, launch_integrate(c->kp, c->d_sysd, c->d_reps, c->R, c->n_pad_max, c->d_xs, c->d_vs, c->d_acc,
+                                        c->d_scale, step0 + (uint64_t)m, c->d_flags, c->stream));
+        } else {
+            HIP_TRY(c, launch_pairs(3, c->kp, c->d_sysd, c->d_reps, c->d_items_contact, c->n_items_contact,
+                                    c->d_xs, c->d_acc, c->d_zbuf, c->d_dsum, nullptr, nullptr, c->kmax,
+                                    c->stream));
+            HIP_TRY(c, launch_finalize_scps(c->kp, c->d_sysd, c->d_reps, c->R, c->kmax, c->d_dsum, cv, c->d_coef,
+                                            c->d_csum, c->stream));
+            HIP_TRY(c, launch_pairs(4, c->kp, c->d_sysd, c->d_reps, c->d_items_all, c->n_items_all, c->d_xs,
+                                    c->d_acc, c->d_zbuf, c->d_dsum, c->d_coef, c->d_csum, c->kmax, c->stream));
+            HIP_TRY(c, launch_integrate(c->kp, c->d_sysd, c->d_reps, c->R, c->n_pad_max, c->d_xs, c->d_vs, c->d_acc,
+                                        c->d_negone, step0 + (uint64_t)m, c->d_flags, c->stream));
+        }
+    }
+    HIP_TRY(c, launch_scatter(c->d_sysd, c->d_reps, c->R, c->n_pad_max, c->d_xs, v ? c->d_vs : nullptr, x, v,
+                              nullptr, c->stream));
+    return SCPS_OK;
+}
+
+scps_status eval_impl(scps_ctx *c, const float *x, double *z, float *grad, const double *coef) {
+    if (!x || !z) return fail(SCPS_ERR_INVALID_ARG, "x and z must not be NULL");
+    for (int r = 0; r < c->R; ++r)
+        if (!c->sys[c->rep_sys[r]].has_native)
+            return fail(SCPS_ERR_STATE, "a system has no native map (scps_set_reference_map)");
+    HIP_TRY(c, launch_gather(c->d_sysd, c->d_reps, c->R, c->n_pad_max, x, nullptr, c->d_xs, nullptr, c->stream));
+    HIP_TRY(c, launch_pairs(grad ? 2 : 1, c->kp, c->d_sysd, c->d_reps, c->d_items_contact, c->n_items_contact,
+                            c->d_xs, c->d_acc, c->d_zbuf, nullptr, nullptr, nullptr, c->kmax, c->stream));
+    HIP_TRY(c, launch_eval_out(c->d_sysd, c->d_reps, c->R, c->n_pad_max, c->d_acc, c->d_zbuf, z, grad, coef,
+                               c->stream));
+    return SCPS_OK;
+}
+
+scps_status update_ref_impl(scps_ctx *c, int32_t s, const float *frames, int32_t n_paths, int32_t n_frames,
+                            const uint8_t *success, double *maps_out) {
+    if (s < 0 || s >= (int)c->sys.size()) return fail(SCPS_ERR_INVALID_ARG, "system index out of range");
+    if (!frames || !success) return fail(SCPS_ERR_INVALID_ARG, "frames and success must not be NULL");
+    if (n_paths < 1 || n_frames < 1) return fail(SCPS_ERR_INVALID_ARG, "n_paths and n_frames must be >= 1");
+    if (n_frames > KMAX) return fail(SCPS_ERR_SHAPE, "at most 64 frames in an SCPS stack");
+    SysHost &h = c->sys[s];
+    std::vector<int> succ;
+    for (int q = 0; q < n_paths; ++q)
+        if (success[q]) succ.push_back(q);
+    if (succ.empty()) return fail(SCPS_ERR_NO_SUCCESS, "no successful path; the frame stack is unchanged");
+    const int64_t P = (int64_t)h.nc * (h.nc - 1) / 2;
+    int *d_succ = nullptr;
+    HIP_TRY(c, dalloc(c, &d_succ, succ.size()));
+    HIP_TRY(c, hipMemcpy(d_succ, succ.data(), succ.size() * sizeof(int), hipMemcpyHostToDevice));
+    float *d_new = nullptr;
+    HIP_TRY(c, dalloc(c, &d_new, (size_t)n_frames * h.ntile_c * 4096));
+    double *d_packed = nullptr;
+    if (maps_out) HIP_TRY(c, dalloc(c, &d_packed, (size_t)std::max<int64_t>(P * n_frames, 1)));
+    HIP_TRY(c, launch_update_reference(h.n, h.n_pad, h.nc, h.ncb, h.d_perm, frames, n_paths, n_frames, d_succ,
+                                       (int)succ.size(), c->prm.r0_contact, c->prm.r_cut_contact, d_new, d_packed,
+                                       c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (maps_out)
+        HIP_TRY(c, hipMemcpy(maps_out, d_packed, (size_t)P * n_frames * sizeof(double), hipMemcpyDeviceToHost));
+    dfree(c, d_packed);
+    dfree(c, d_succ);
+    dfree(c, h.d_stack);
+    h.d_stack = d_new;
+    h.K = n_frames;
+    return upload_sysdesc(c);
+}
+
+}  // namespace
+
+extern "C" {
+
+scps_status scps_init_system(const scps_params *params, const scps_topology *topology, int32_t n_replicas,
+                             const int32_t *replica_system, void *hip_stream, scps_ctx **out) {
+    try {
+        return init_impl(params, topology, n_replicas, replica_system, hip_stream, out);
+    } catch (const std::bad_alloc &) {
+        return fail(SCPS_ERR_OOM, "host allocation failed");
+    } catch (const std::exception &e) {
+        return fail(SCPS_ERR_INVALID_ARG, e.what());
+    }
+}
+
+scps_status scps_set_reference_map(scps_ctx *ctx, int32_t system, int32_t n_maps, const double *maps,
+                                   const double *native_xyz, double z0_norm) {
+    scps_status st;
+    if (!usable(ctx, &st)) return st;
+    try {
+        return set_ref_impl(ctx, system, n_maps, maps, native_xyz, z0_norm);
+    } catch (const std::bad_alloc &) {
+        return fail(SCPS_ERR_OOM, "host allocation failed");
+    }
+}
+
+scps_status scps_step_replicas(scps_ctx *ctx, float *x, float *v, double *cvstate, int64_t n_steps, uint64_t step0,
+                               int32_t record_every, float *frames) {
+    scps_status st;
+    if (!usable(ctx, &st)) return st;
+    return step_impl(ctx, x, v, cvstate, n_steps, step0, record_every, frames);
+}
+
+scps_status scps_eval_z_and_grad(scps_ctx *ctx, const float *x, double *z, float *grad, const double *grad_coef) {
+    scps_status st;
+    if (!usable(ctx, &st)) return st;
+    return eval_impl(ctx, x, z, grad, grad_coef);
+}
+
+scps_status scps_ratchet_energy(scps_ctx *ctx, const double *z, const double *z_m, double *E_b, const double *gz,
+                                const double *gE, double *coef) {
+    scps_status st;
+    if (!usable(ctx, &st)) return st;
+    if (!z || !z_m) return fail(SCPS_ERR_INVALID_ARG, "z and z_m must not be NULL");
+    HIP_TRY(ctx, launch_ratchet_energy(ctx->R, ctx->prm.k_R, z, z_m, E_b, gz, gE, coef, ctx->stream));
+    return SCPS_OK;
+}
+
+scps_status scps_update_reference_from_paths(scps_ctx *ctx, int32_t system, const float *frames, int32_t n_paths,
+                                             int32_t n_frames, const uint8_t *success, double *maps_out) {
+    scps_status st;
+    if (!usable(ctx, &st)) return st;
+    try {
+        return update_ref_impl(ctx, system, frames, n_paths, n_frames, success, maps_out);
+    } catch (const std::bad_alloc &) {
+        return fail(SCPS_ERR_OOM, "host allocation failed");
+    }
+}
+
+scps_status scps_set_stream(scps_ctx *ctx, void *hip_stream) {
+    scps_status st;
+    if (!usable(ctx, &st)) return st;
+    ctx->stream = (hipStream_t)hip_stream;
+    return SCPS_OK;
+}
+
+scps_status scps_sync(scps_ctx *ctx, int32_t *bad_replicas, int32_t *n_bad) {
+    if (!ctx) return fail(SCPS_ERR_INVALID_ARG, "context is NULL");
+    if (n_bad) *n_bad = 0;
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+        ctx->poisoned = true;
+        return fail(SCPS_ERR_HIP, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+    }
+    std::vector<int> flags(ctx->R);
+    e = hipMemcpy(flags.data(), ctx->d_flags, ctx->R * sizeof(int), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+        ctx->poisoned = true;
+        return fail(SCPS_ERR_HIP, std::string("hipMemcpy: ") + hipGetErrorString(e));
+    }
+    int nb = 0;
+    for (int r = 0; r < ctx->R; ++r)
+        if (flags[r]) {
+            if (bad_replicas) bad_replicas[nb] = r;
+            ++nb;
+        }
+    if (n_bad) *n_bad = nb;
+    if (nb) {
+        ctx->poisoned = true;
+        return fail(SCPS_ERR_NONFINITE, std::to_string(nb) + " replica(s) produced non-finite coordinates");
+    }
+    return SCPS_OK;
+}
+
+void scps_destroy(scps_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipStreamSynchronize(ctx->stream);
+    for (void *p : ctx->owned) (void)hipFree(p);
+    delete ctx;
+}
+
+const char *scps_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

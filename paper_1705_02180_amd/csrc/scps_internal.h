@@ -1,0 +1,116 @@
+// Internal declarations shared by the kernels and the host side of libscps.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace scps {
+
+constexpr int TILE = 64;          // tile edge = wavefront width
+constexpr int KMAX = 64;          // largest SCPS frame stack handled per pass
+constexpr int CV_STRIDE = 8;
+enum { CV_Z = 0, CV_ZM = 1, CV_EB = 2, CV_S = 3, CV_W = 4, CV_SM = 5, CV_WM = 6 };
+
+// Scalars every kernel needs, passed by value.
+struct KParams {
+    float inv_r0sq;      // 1/r0^2
+    float g_scale;       // 4/r0^2: dz/dx_i = sum_j g_scale (C - R) C'(q) (x_i - x_j)
+    float r_cut2;        // contact cutoff squared (used when has_cut)
+    float lj_sig2;       // sigma^2
+    float lj_24eps;      // 24 epsilon
+    float dh_pref;       // k_e/eps_r
+    float dh_kappa;
+    float dh_kl2;        // -kappa * log2(e)
+    int nb_excl, min_sep;
+    int has_lj, has_dh, has_cut, has_bond;
+    int integrator;
+    double dt, kT, gamma, c1;
+    double k_bond, r_bond;
+    double k_R;
+    double lambda, k_s, k_w;
+    uint32_t seed_lo, seed_hi;
+    uint32_t rep_base;
+};
+
+// One chain, in the library's internal particle order: contact-set particles
+// first (ascending), then the rest (ascending), padded to a multiple of 64.
+struct SysDesc {
+    int n, n_pad, nb;        // particles, padded count, blocks of 64
+    int nc, ncb, ntile_c;    // contact-set size, its blocks, contact tile pairs
+    int K;                   // SCPS frames in the stack
+    int pad0;
+    const int *perm;         // [n_pad] internal -> chain index (pads: n + k)
+    const int *bond_next;    // [n_pad] internal index of chain neighbour i+1, -1 if none
+    const float *mass;       // [n_pad] internal order (pads: 1)
+    const float *charge;     // [n_pad] internal order (pads: 0)
+    const float *ref;        // native map tiles [ntile_c][64*64]
+    const float *stack;      // SCPS frames [K][ntile_c][64*64]
+    double Z0;
+};
+
+struct RepDesc {
+    int sys;
+    int pad0;
+    int64_t off;             // particle offset of the replica in the flat x layout
+    int64_t poff;            // particle offset in the padded internal-order buffers
+};
+
+// A unit of pair work for the per-step kernels: one tile pair of one replica.
+struct TileItem {
+    int rep, I, J, pad0;
+};
+
+// Contact tile pairs (I <= J < ncb) are numbered row by row.
+__host__ __device__ inline int tile_index(int I, int J, int ncb) {
+    return I * ncb - (I * (I - 1)) / 2 + (J - I);
+}
+
+// ---- launch wrappers (defined in scps_kernels.hip) -------------------------
+size_t persistent_lds_bytes(int n_pad, int wg);
+int persistent_max_npad(int wg);
+
+hipError_t launch_persistent_rmd(int wg, const KParams &P, const SysDesc *sysd, const RepDesc *reps,
+                                 const int *order, int R, int n_pad_max, float *x, float *v,
+                                 double *cv, int64_t n_steps, uint64_t step0, int record_every,
+                                 float *frames, int64_t frame_stride, int *flags, hipStream_t st);
+
+hipError_t launch_gather(const SysDesc *sysd, const RepDesc *reps, int R, int n_pad_max,
+                         const float *x, const float *v, float4 *xs, float4 *vs, hipStream_t st);
+hipError_t launch_scatter(const SysDesc *sysd, const RepDesc *reps, int R, int n_pad_max,
+                          const float4 *xs, const float4 *vs, float *x, float *v, float *frames_slot,
+                          hipStream_t st);
+
+// mode: 0 rMD forces (contact z + grad, nonbonded, bonds); 1 z only; 2 z and grad;
+//       3 SCPS pass 1 (distances to every frame); 4 SCPS pass 2 (bias + nonbonded + bonds)
+hipError_t launch_pairs(int mode, const KParams &P, const SysDesc *sysd, const RepDesc *reps,
+                        const TileItem *items, int n_items, const float4 *xs, double *acc,
+                        double *zbuf, double *dsum, const float *coef, const double *csum,
+                        int kmax, hipStream_t st);
+
+hipError_t launch_finalize_rmd(const KParams &P, int R, double *zbuf, double *cv, double *scale,
+                               hipStream_t st);
+hipError_t launch_finalize_scps(const KParams &P, const SysDesc *sysd, const RepDesc *reps, int R,
+                                int kmax, double *dsum, double *cv, float *coef, double *csum,
+                                hipStream_t st);
+hipError_t launch_integrate(const KParams &P, const SysDesc *sysd, const RepDesc *reps, int R,
+                            int n_pad_max, float4 *xs, float4 *vs, double *acc,
+                            const double *scale, uint64_t step, int *flags, hipStream_t st);
+
+hipError_t launch_eval_out(const SysDesc *sysd, const RepDesc *reps, int R, int n_pad_max,
+                           double *acc, double *zbuf, double *z_out, float *grad,
+                           const double *grad_coef, hipStream_t st);
+hipError_t launch_ratchet_energy(int R, double k_R, const double *z, const double *zm, double *Eb,
+                                 const double *gz, const double *gE, double *coef, hipStream_t st);
+
+hipError_t launch_native_map(int n, int n_pad, int nc, int ncb, const int *perm_dev,
+                             const double *xyz_dev, double r0, double r_cut, float *tiles,
+                             double *packed, hipStream_t st);
+hipError_t launch_pack_to_tiles(int n_maps, int nc, int ncb, const double *packed, float *tiles,
+                                hipStream_t st);
+hipError_t launch_sum_squares(int64_t m, const double *v, double *out, hipStream_t st);
+hipError_t launch_update_reference(int n, int n_pad, int nc, int ncb, const int *perm_dev,
+                                   const float *frames, int n_paths, int n_frames,
+                                   const int *succ_idx, int n_succ, double r0, double r_cut,
+                                   float *tiles, double *packed, hipStream_t st);
+
+}  // namespace scps

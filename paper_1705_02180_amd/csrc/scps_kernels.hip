@@ -1,0 +1,1031 @@
+// HIP kernels for gfx950: batched rMD / SCPS Langevin stepping.
+//
+// Pair work is organised in 64x64 tile pairs (I <= J) of a chain's internal
+// particle order.  In a tile pass lane l of a wavefront owns particle
+// i = 64 I + l and, at sub-step k, meets particle j = 64 J + ((l + k) mod 64),
+// read from LDS (persistent kernel) or L1/L2 (per-step kernels).  Every
+// unordered pair is met once: k = 0..63 in an off-diagonal tile, and
+// k = 1..32 in a diagonal tile with only lanes 0..31 active at k = 32.
+// Newton's third law is applied without atomics inside the loop: the j-side
+// partial sums live in registers and move one lane down after every
+// sub-step (DPP wavefront rotate), so that lane l always holds the partial
+// of the particle it meets next.  Pair arithmetic is float32; every tile's
+// partial sums (at most 64 terms) are added into float64 accumulators.
+//
+// Contact function, eq (Cij) of Orioli, a Beccara, Faccioli (arXiv:1705.02180),
+// with q = (r/r0)^2:
+//   C(q)  = (1 + q + q^2) / (1 + q + q^2 + q^3 + q^4)
+//   C'(q) = -q^2 (3 + 6q + 4q^2 + 2q^3) / (1 + q + q^2 + q^3 + q^4)^2
+// (the numerator of the quotient rule expanded, so no cancellation at small q).
+// z = sum over contact pairs of (C - R)^2, eq (zrMD); dz/dx_i = sum_j
+// (4/r0^2) (C - R) C'(q) (x_i - x_j).
+#include <math.h>
+
+#include "scps_internal.h"
+
+namespace scps {
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ float fexp2(float x) { return __builtin_amdgcn_exp2f(x); }
+
+// Lane l receives what lane (l + 1) mod 64 holds (DPP wave_rol:1).
+__device__ __forceinline__ float rot1(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x134, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds, Weyl key schedule.
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint32_t a = c[0], b = c[2];
+        const uint32_t hi0 = __umulhi(0xD2511F53u, a), lo0 = 0xD2511F53u * a;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, b), lo1 = 0xCD9E8D57u * b;
+        c[0] = hi1 ^ c[1] ^ k0;
+        c[1] = lo1;
+        c[2] = hi0 ^ c[3] ^ k1;
+        c[3] = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+__device__ __forceinline__ double unit_open(uint32_t w) {
+    return (2.0 * (double)(w >> 9) + 1.0) * 0x1p-24;
+}
+
+// Three standard normals for (particle, replica, step); Box-Muller in float64.
+__device__ __forceinline__ void normals3(const KParams &P, uint32_t atom, uint32_t rep, uint64_t step,
+                                         double &g0, double &g1, double &g2) {
+    uint32_t c[4] = {atom, rep, (uint32_t)step, (uint32_t)(step >> 32)};
+    philox4x32_10(c, P.seed_lo, P.seed_hi);
+    const double r01 = sqrt(-2.0 * log(unit_open(c[0])));
+    const double r23 = sqrt(-2.0 * log(unit_open(c[2])));
+    double s, co;
+    sincospi(2.0 * unit_open(c[1]), &s, &co);
+    g0 = r01 * co;
+    g1 = r01 * s;
+    sincospi(2.0 * unit_open(c[3]), &s, &co);
+    g2 = r23 * co;
+}
+
+// ---------------------------------------------------------------------------
+// the pair tile pass
+// ---------------------------------------------------------------------------
+enum { PM_RMD = 0, PM_Z = 1, PM_ZG = 2, PM_SCPS1 = 3, PM_SCPS2 = 4 };
+
+template <int MODE> struct ModeTraits {
+    static constexpr bool nb = (MODE == PM_RMD || MODE == PM_SCPS2);
+    static constexpr bool grad = (MODE == PM_RMD || MODE == PM_ZG || MODE == PM_SCPS2);
+    static constexpr bool z = (MODE == PM_RMD || MODE == PM_Z || MODE == PM_ZG);
+};
+
+// Lane-side state of a tile pass.
+struct LaneI {
+    float4 p;     // x, y, z, charge of particle i
+    int o;        // chain index of i
+    bool valid;   // i < n
+    bool contact; // i in the contact set
+};
+
+// Outputs: fi[0..2] nonbonded, fi[3..5] contact gradient (i side);
+// fj likewise for the j particle lane l holds at the end, which is
+// jl_out = (l + kend + 1) mod 64 of block J.  zt: this lane's z partial.
+// SCPS pass 1 uses dk[0..K) instead (squared distances to every frame).
+template <int MODE, bool DIAG, bool CONTACT>
+__device__ __forceinline__ void tile_pass(const KParams &P, const int lane, const LaneI &A,
+                                          const float4 *__restrict__ posj, const int *__restrict__ orgj,
+                                          const int nvj, const int ncj,
+                                          const float *__restrict__ rt, const int64_t kstride,
+                                          const int K, const float *__restrict__ ck, const float csum,
+                                          float fi[6], float fj[6], float &zt, float *dk) {
+    using T = ModeTraits<MODE>;
+    constexpr int kbeg = DIAG ? 1 : 0;
+    constexpr int kend = DIAG ? 32 : 63;
+#pragma unroll 2
+    for (int k = kbeg; k <= kend; ++k) {
+        const int jl = (lane + k) & 63;
+        const float4 pj = posj[jl];
+        const int oj = orgj[jl];
+        const float dx = A.p.x - pj.x;
+        const float dy = A.p.y - pj.y;
+        const float dz = A.p.z - pj.z;
+        const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+        const bool act = (!DIAG || k < 32 || lane < 32) && A.valid && (jl < nvj);
+        const int sep = abs(A.o - oj);
+        if constexpr (T::nb) {
+            const float inv_r = frsq(r2);
+            const float inv_r2 = inv_r * inv_r;
+            float f = 0.f;
+            if (P.has_lj) {
+                const float s2 = P.lj_sig2 * inv_r2;
+                const float s6 = s2 * s2 * s2;
+                f = P.lj_24eps * s6 * fmaf(2.f, s6, -1.f) * inv_r2;
+            }
+            if (P.has_dh) {
+                const float r = r2 * inv_r;
+                const float u = P.dh_pref * A.p.w * pj.w * fexp2(P.dh_kl2 * r) * inv_r;
+                f = fmaf(u * (P.dh_kappa + inv_r), inv_r, f);
+            }
+            f = (act && sep > P.nb_excl) ? f : 0.f;
+            fi[0] = fmaf(f, dx, fi[0]);
+            fi[1] = fmaf(f, dy, fi[1]);
+            fi[2] = fmaf(f, dz, fi[2]);
+            fj[0] = fmaf(-f, dx, fj[0]);
+            fj[1] = fmaf(-f, dy, fj[1]);
+            fj[2] = fmaf(-f, dz, fj[2]);
+        }
+        if constexpr (CONTACT) {
+            const bool con = act && A.contact && (jl < ncj) && sep > P.min_sep;
+            // beyond the optional cutoff the entry C_ij is set to 0 (R_ij still counts)
+            const bool inside = !P.has_cut || (r2 <= P.r_cut2);
+            const float q = r2 * P.inv_r0sq;
+            const float q2 = q * q;
+            const float num = 1.f + q + q2;
+            const float den = fmaf(q2, q + q2, num);
+            const float inv_den = inside ? frcp(den) : 0.f;
+            const float C = num * inv_den;
+            if constexpr (MODE == PM_SCPS1) {
+                const float *rk = rt + k * 64 + lane;
+#pragma unroll
+                for (int kk = 0; kk < KMAX; ++kk) {
+                    if (kk < K) {
+                        const float d = con ? (C - rk[kk * kstride]) : 0.f;
+                        dk[kk] = fmaf(d, d, dk[kk]);
+                    }
+                }
+            } else {
+                float diff;
+                if constexpr (MODE == PM_SCPS2) {
+                    float eff = csum * C;
+                    for (int kk = 0; kk < K; ++kk) eff = fmaf(-ck[kk], rt[kk * kstride + k * 64 + lane], eff);
+                    diff = eff;
+                } else {
+                    diff = C - rt[k * 64 + lane];
+                }
+                diff = con ? diff : 0.f;
+                if constexpr (T::z) zt = fmaf(diff, diff, zt);
+                if constexpr (T::grad) {
+                    const float poly = fmaf(q, fmaf(q, fmaf(q, 2.f, 4.f), 6.f), 3.f);
+                    const float Cp = -(q2 * poly) * (inv_den * inv_den);
+                    const float g = P.g_scale * diff * Cp;
+                    fi[3] = fmaf(g, dx, fi[3]);
+                    fi[4] = fmaf(g, dy, fi[4]);
+                    fi[5] = fmaf(g, dz, fi[5]);
+                    fj[3] = fmaf(-g, dx, fj[3]);
+                    fj[4] = fmaf(-g, dy, fj[4]);
+                    fj[5] = fmaf(-g, dz, fj[5]);
+                }
+            }
+        }
+        if constexpr (T::nb) {
+            fj[0] = rot1(fj[0]);
+            fj[1] = rot1(fj[1]);
+            fj[2] = rot1(fj[2]);
+        }
+        if constexpr (T::grad) {
+            if constexpr (CONTACT) {
+                fj[3] = rot1(fj[3]);
+                fj[4] = rot1(fj[4]);
+                fj[5] = rot1(fj[5]);
+            }
+        }
+    }
+}
+
+template <bool DIAG>
+__device__ __forceinline__ int jflush_lane(int lane) {
+    return (lane + (DIAG ? 33 : 64)) & 63;
+}
+
+// Harmonic bond between internal particle a and its chain successor b, float64.
+__device__ __forceinline__ void bond_force(const KParams &P, float4 pa, float4 pb, double f[3]) {
+    const double dx = (double)pa.x - (double)pb.x;
+    const double dy = (double)pa.y - (double)pb.y;
+    const double dz = (double)pa.z - (double)pb.z;
+    const double r = sqrt(dx * dx + dy * dy + dz * dz);
+    const double s = -P.k_bond * (r - P.r_bond) / r;
+    f[0] = s * dx;
+    f[1] = s * dy;
+    f[2] = s * dz;
+}
+
+// ---------------------------------------------------------------------------
+// persistent rMD kernel: one workgroup runs one replica for all n_steps
+// ---------------------------------------------------------------------------
+size_t persistent_lds_bytes(int n_pad, int wg) {
+    // pos float4, chain index int, acc 6 x double, vel 3 x float, reduction
+    return (size_t)n_pad * (16 + 4 + 48 + 12) + (size_t)(wg / 64) * 8 + 64;
+}
+
+int persistent_max_npad(int wg) {
+    const size_t lds = 160 * 1024;
+    int n = (int)((lds - (size_t)(wg / 64) * 8 - 64) / (16 + 4 + 48 + 12));
+    return (n / 64) * 64;
+}
+
+__device__ __forceinline__ void tile_decode(int t, int nb, int &I, int &J) {
+    int row = 0;
+    while (t >= nb - row) {
+        t -= nb - row;
+        ++row;
+    }
+    I = row;
+    J = row + t;
+}
+
+template <int WG>
+__global__ __launch_bounds__(WG) void k_rmd_persistent(
+    const KParams P, const SysDesc *__restrict__ sysd, const RepDesc *__restrict__ reps,
+    const int *__restrict__ order, float *__restrict__ x, float *__restrict__ v,
+    double *__restrict__ cv, const int64_t n_steps, const uint64_t step0, const int record_every,
+    float *__restrict__ frames, const int64_t frame_stride, int *__restrict__ flags) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int NW = WG / 64;
+    const int r = order[blockIdx.x];
+    const RepDesc rd = reps[r];
+    const SysDesc S = sysd[rd.sys];
+    const int n = S.n, n_pad = S.n_pad, nb = S.nb;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+    float4 *pos = reinterpret_cast<float4 *>(smem);
+    double *acc = reinterpret_cast<double *>(pos + n_pad);           // [6][n_pad]
+    float *vel = reinterpret_cast<float *>(acc + 6 * (size_t)n_pad);  // [3][n_pad]
+    int *org = reinterpret_cast<int *>(vel + 3 * (size_t)n_pad);      // [n_pad]
+    double *red = reinterpret_cast<double *>(org + n_pad + ((n_pad & 1) ? 1 : 0));
+    __shared__ double sh_scale;
+
+    float *xr = x + 3 * rd.off;
+    float *vr = v ? v + 3 * rd.off : nullptr;
+    for (int a = tid; a < n_pad; a += WG) {
+        const int o = S.perm[a];
+        if (a < n) {
+            pos[a] = make_float4(xr[o], xr[n + o], xr[2 * n + o], S.charge[a]);
+            vel[a] = vr ? vr[o] : 0.f;
+            vel[n_pad + a] = vr ? vr[n + o] : 0.f;
+            vel[2 * n_pad + a] = vr ? vr[2 * n + o] : 0.f;
+        } else {
+            pos[a] = make_float4(1.0e4f + 50.f * (float)a, 1.0e4f, 1.0e4f, 0.f);
+            vel[a] = vel[n_pad + a] = vel[2 * n_pad + a] = 0.f;
+        }
+        org[a] = o;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) acc[c * n_pad + a] = 0.0;
+    }
+    double zm = cv[(int64_t)r * CV_STRIDE + CV_ZM];
+    double z_last = cv[(int64_t)r * CV_STRIDE + CV_Z];
+    double eb_last = cv[(int64_t)r * CV_STRIDE + CV_EB];
+    bool bad = false;
+    __syncthreads();
+
+    const int ntile = nb * (nb + 1) / 2;
+    const double c1 = P.c1;
+    for (int64_t m = 0;; ++m) {
+        if (record_every > 0 && frames && (m % record_every) == 0) {
+            float *fr = frames + (m / record_every) * frame_stride + 3 * rd.off;
+            for (int a = tid; a < n; a += WG) {
+                const int o = org[a];
+                const float4 p = pos[a];
+                fr[o] = p.x;
+                fr[n + o] = p.y;
+                fr[2 * n + o] = p.z;
+            }
+        }
+        if (m == n_steps) break;
+
+        // ---- pair phase: nonbonded + contact z and grad z, bonds ----------
+        double zacc = 0.0;
+        for (int t = wave; t < ntile; t += NW) {
+            int I, J;
+            tile_decode(t, nb, I, J);
+            LaneI A;
+            const int i = I * 64 + lane;
+            A.p = pos[i];
+            A.o = org[i];
+            A.valid = i < n;
+            A.contact = i < S.nc;
+            const int nvj = n - J * 64, ncj = S.nc - J * 64;
+            float fi[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            float fj[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            float zt = 0.f;
+            const bool contact_tile = (I < S.ncb) && (J < S.ncb);
+            const float *rt = contact_tile ? S.ref + (int64_t)tile_index(I, J, S.ncb) * 4096 : nullptr;
+            int jo;
+            if (I == J) {
+                if (contact_tile)
+                    tile_pass<PM_RMD, true, true>(P, lane, A, pos + J * 64, org + J * 64, nvj, ncj, rt, 0, 0,
+                                                  nullptr, 0.f, fi, fj, zt, nullptr);
+                else
+                    tile_pass<PM_RMD, true, false>(P, lane, A, pos + J * 64, org + J * 64, nvj, ncj, rt, 0, 0,
+                                                   nullptr, 0.f, fi, fj, zt, nullptr);
+                jo = J * 64 + jflush_lane<true>(lane);
+            } else {
+                if (contact_tile)
+                    tile_pass<PM_RMD, false, true>(P, lane, A, pos + J * 64, org + J * 64, nvj, ncj, rt, 0, 0,
+                                                   nullptr, 0.f, fi, fj, zt, nullptr);
+                else
+                    tile_pass<PM_RMD, false, false>(P, lane, A, pos + J * 64, org + J * 64, nvj, ncj, rt, 0, 0,
+                                                    nullptr, 0.f, fi, fj, zt, nullptr);
+                jo = J * 64 + jflush_lane<false>(lane);
+            }
+            zacc += (double)zt;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                unsafeAtomicAdd(&acc[c * n_pad + i], (double)fi[c]);
+                unsafeAtomicAdd(&acc[c * n_pad + jo], (double)fj[c]);
+            }
+        }
+        for (int a = tid; a < n && P.has_bond; a += WG) {
+            const int b = S.bond_next[a];
+            if (b >= 0) {
+                double f[3];
+                bond_force(P, pos[a], pos[b], f);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    unsafeAtomicAdd(&acc[c * n_pad + a], f[c]);
+                    unsafeAtomicAdd(&acc[c * n_pad + b], -f[c]);
+                }
+            }
+        }
+        zacc = wave_sum(zacc);
+        if (lane == 0) red[wave] = zacc;
+        __syncthreads();
+
+        // ---- ratchet, eq (FrMD): z_m updated before the force is used -----
+        if (tid == 0) {
+            double z = 0.0;
+            for (int w = 0; w < NW; ++w) z += red[w];
+            zm = fmin(zm, z);
+            const double dzr = z - zm;
+            sh_scale = -P.k_R * dzr;
+            z_last = z;
+            eb_last = 0.5 * P.k_R * dzr * dzr;
+        }
+        __syncthreads();
+        const double scale = sh_scale;
+
+        // ---- Langevin update, float64 per particle -------------------------
+        const uint64_t step = step0 + (uint64_t)m;
+        for (int a = tid; a < n; a += WG) {
+            const double inv_m = 1.0 / (double)S.mass[a];
+            double F[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                F[c] = acc[c * n_pad + a] + scale * acc[(c + 3) * n_pad + a];
+                acc[c * n_pad + a] = 0.0;
+                acc[(c + 3) * n_pad + a] = 0.0;
+            }
+            double g[3];
+            normals3(P, (uint32_t)org[a], P.rep_base + (uint32_t)r, step, g[0], g[1], g[2]);
+            const float4 p = pos[a];
+            double X[3] = {(double)p.x, (double)p.y, (double)p.z};
+            if (P.integrator == 0) {
+                const double mob = P.dt * inv_m / P.gamma;
+                const double amp = sqrt(2.0 * P.kT * mob);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) X[c] += mob * F[c] + amp * g[c];
+            } else {
+                const double amp = sqrt((1.0 - c1 * c1) * P.kT * inv_m);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    double u = (double)vel[c * n_pad + a] + P.dt * F[c] * inv_m;
+                    X[c] += 0.5 * P.dt * u;
+                    u = c1 * u + amp * g[c];
+                    X[c] += 0.5 * P.dt * u;
+                    vel[c * n_pad + a] = (float)u;
+                }
+            }
+            const float4 np = make_float4((float)X[0], (float)X[1], (float)X[2], p.w);
+            bad |= !(isfinite(np.x) && isfinite(np.y) && isfinite(np.z));
+            pos[a] = np;
+        }
+        __syncthreads();
+    }
+
+    for (int a = tid; a < n; a += WG) {
+        const int o = org[a];
+        const float4 p = pos[a];
+        xr[o] = p.x;
+        xr[n + o] = p.y;
+        xr[2 * n + o] = p.z;
+        if (vr) {
+            vr[o] = vel[a];
+            vr[n + o] = vel[n_pad + a];
+            vr[2 * n + o] = vel[2 * n_pad + a];
+        }
+    }
+    if (bad) flags[r] = 1;
+    if (tid == 0 && n_steps > 0) {
+        cv[(int64_t)r * CV_STRIDE + CV_Z] = z_last;
+        cv[(int64_t)r * CV_STRIDE + CV_ZM] = zm;
+        cv[(int64_t)r * CV_STRIDE + CV_EB] = eb_last;
+    }
+}
+
+hipError_t launch_persistent_rmd(int wg, const KParams &P, const SysDesc *sysd, const RepDesc *reps,
+                                 const int *order, int R, int n_pad_max, float *x, float *v,
+                                 double *cv, int64_t n_steps, uint64_t step0, int record_every,
+                                 float *frames, int64_t frame_stride, int *flags, hipStream_t st) {
+    const size_t lds = persistent_lds_bytes(n_pad_max, wg);
+    switch (wg) {
+    case 256:
+        hipLaunchKernelGGL(k_rmd_persistent<256>, dim3(R), dim3(256), lds, st, P, sysd, reps, order, x, v,
+                           cv, n_steps, step0, record_every, frames, frame_stride, flags);
+        break;
+    case 512:
+        hipLaunchKernelGGL(k_rmd_persistent<512>, dim3(R), dim3(512), lds, st, P, sysd, reps, order, x, v,
+                           cv, n_steps, step0, record_every, frames, frame_stride, flags);
+        break;
+    case 1024:
+        hipLaunchKernelGGL(k_rmd_persistent<1024>, dim3(R), dim3(1024), lds, st, P, sysd, reps, order, x, v,
+                           cv, n_steps, step0, record_every, frames, frame_stride, flags);
+        break;
+    default:
+        hipLaunchKernelGGL(k_rmd_persistent<64>, dim3(R), dim3(64), lds, st, P, sysd, reps, order, x, v,
+                           cv, n_steps, step0, record_every, frames, frame_stride, flags);
+        break;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// per-step path: gather / pairs / finalize / integrate / scatter
+// ---------------------------------------------------------------------------
+__global__ void k_gather(const SysDesc *__restrict__ sysd, const RepDesc *__restrict__ reps,
+                         const float *__restrict__ x, const float *__restrict__ v, float4 *__restrict__ xs,
+                         float4 *__restrict__ vs) {
+    const int r = blockIdx.y;
+    const RepDesc rd = reps[r];
+    const SysDesc S = sysd[rd.sys];
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= S.n_pad) return;
+    const int n = S.n;
+    const float *xr = x + 3 * rd.off;
+    float4 p, q = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (a < n) {
+        const int o = S.perm[a];
+        p = make_float4(xr[o], xr[n + o], xr[2 * n + o], S.charge[a]);
+        if (v) {
+            const float *vr = v + 3 * rd.off;
+            q = make_float4(vr[o], vr[n + o], vr[2 * n + o], 0.f);
+        }
+    } else {
+        p = make_float4(1.0e4f + 50.f * (float)a, 1.0e4f, 1.0e4f, 0.f);
+    }
+    xs[rd.poff + a] = p;
+    if (vs) vs[rd.poff + a] = q;
+}
+
+hipError_t launch_gather(const SysDesc *sysd, const RepDesc *reps, int R, int n_pad_max, const float *x,
+                         const float *v, float4 *xs, float4 *vs, hipStream_t st) {
+    hipLaunchKernelGGL(k_gather, dim3((n_pad_max + 255) / 256, R), dim3(256), 0, st, sysd, reps, x, v, xs, vs);
+    return hipGetLastError();
+}
+
+__global__ void k_scatter(const SysDesc *__restrict__ sysd, const RepDesc *__restrict__ reps,
+                          const float4 *__restrict__ xs, const float4 *__restrict__ vs, float *__restrict__ x,
+                          float *__restrict__ v, float *__restrict__ frames_slot) {
+    const int r = blockIdx.y;
+    const RepDesc rd = reps[r];
+    const SysDesc S = sysd[rd.sys];
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= S.n) return;
+    const int n = S.n;
+    const int o = S.perm[a];
+    const float4 p = xs[rd.poff + a];
+    if (x) {
+        float *xr = x + 3 * rd.off;
+        xr[o] = p.x;
+        xr[n + o] = p.y;
+        xr[2 * n + o] = p.z;
+    }
+    if (frames_slot) {
+        float *fr = frames_slot + 3 * rd.off;
+        fr[o] = p.x;
+        fr[n + o] = p.y;
+        fr[2 * n + o] = p.z;
+    }
+    if (v && vs) {
+        const float4 q = vs[rd.poff + a];
+        float *vr = v + 3 * rd.off;
+        vr[o] = q.x;
+        vr[n + o] = q.y;
+        vr[2 * n + o] = q.z;
+    }
+}
+
+hipError_t launch_scatter(const SysDesc *sysd, const RepDesc *reps, int R, int n_pad_max, const float4 *xs,
+                          const float4 *vs, float *x, float *v, float *frames_slot, hipStream_t st) {
+    hipLaunchKernelGGL(k_scatter, dim3((n_pad_max + 255) / 256, R), dim3(256), 0, st, sysd, reps, xs, vs, x, v,
+                       frames_slot);
+    return hipGetLastError();
+}
+
+// One wavefront per tile item; four per workgroup.  Partial sums go to the
+// float64 accumulators in global memory with hardware float64 atomics.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_pairs(const KParams P, const SysDesc *__restrict__ sysd,
+                                               const RepDesc *__restrict__ reps,
+                                               const TileItem *__restrict__ items, const int n_items,
+                                               const float4 *__restrict__ xs, double *__restrict__ acc,
+                                               double *__restrict__ zbuf, double *__restrict__ dsum,
+                                               const float *__restrict__ coef, const double *__restrict__ csum,
+                                               const int kmax) {
+    using T = ModeTraits<MODE>;
+    const int lane = threadIdx.x & 63;
+    const int item = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (item >= n_items) return;
+    const TileItem it = items[item];
+    const RepDesc rd = reps[it.rep];
+    const SysDesc S = sysd[rd.sys];
+    const int I = it.I, J = it.J;
+    const int n = S.n, n_pad = S.n_pad;
+    const float4 *xr = xs + rd.poff;
+    LaneI A;
+    const int i = I * 64 + lane;
+    A.p = xr[i];
+    A.o = S.perm[i];
+    A.valid = i < n;
+    A.contact = i < S.nc;
+    const int nvj = n - J * 64, ncj = S.nc - J * 64;
+    float fi[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float fj[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float zt = 0.f;
+    float dk[KMAX];
+    const bool contact_tile = (I < S.ncb) && (J < S.ncb);
+    const int64_t toff = contact_tile ? (int64_t)tile_index(I, J, S.ncb) * 4096 : 0;
+    const float *rt;
+    int64_t kstride = 0;
+    int K = 0;
+    float cs = 0.f;
+    const float *ck = nullptr;
+    if constexpr (MODE == PM_SCPS1 || MODE == PM_SCPS2) {
+        rt = S.stack + toff;
+        kstride = (int64_t)S.ntile_c * 4096;
+        K = S.K;
+        if constexpr (MODE == PM_SCPS1) {
+#pragma unroll
+            for (int kk = 0; kk < KMAX; ++kk) dk[kk] = 0.f;
+        } else {
+            ck = coef + (int64_t)it.rep * kmax;
+            cs = (float)csum[it.rep];
+        }
+    } else {
+        rt = S.ref + toff;
+    }
+    if constexpr (!T::nb) {
+        if (!contact_tile) return;
+    }
+    const float4 *pj = xr + J * 64;
+    const int *oj = S.perm + J * 64;
+    int jo;
+    if (I == J) {
+        if (contact_tile)
+            tile_pass<MODE, true, true>(P, lane, A, pj, oj, nvj, ncj, rt, kstride, K, ck, cs, fi, fj, zt, dk);
+        else
+            tile_pass<MODE, true, false>(P, lane, A, pj, oj, nvj, ncj, rt, kstride, K, ck, cs, fi, fj, zt, dk);
+        jo = J * 64 + jflush_lane<true>(lane);
+    } else {
+        if (contact_tile)
+            tile_pass<MODE, false, true>(P, lane, A, pj, oj, nvj, ncj, rt, kstride, K, ck, cs, fi, fj, zt, dk);
+        else
+            tile_pass<MODE, false, false>(P, lane, A, pj, oj, nvj, ncj, rt, kstride, K, ck, cs, fi, fj, zt, dk);
+        jo = J * 64 + jflush_lane<false>(lane);
+    }
+    double *ar = acc + 6 * rd.poff;
+    if constexpr (T::nb) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            unsafeAtomicAdd(&ar[c * n_pad + i], (double)fi[c]);
+            unsafeAtomicAdd(&ar[c * n_pad + jo], (double)fj[c]);
+        }
+        // bonds of the particles of block I, once per block (diagonal tile)
+        if (I == J && A.valid && P.has_bond) {
+            const int b = S.bond_next[i];
+            if (b >= 0) {
+                double f[3];
+                bond_force(P, A.p, xr[b], f);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    unsafeAtomicAdd(&ar[c * n_pad + i], f[c]);
+                    unsafeAtomicAdd(&ar[c * n_pad + b], -f[c]);
+                }
+            }
+        }
+    }
+    if constexpr (T::grad) {
+        if (contact_tile) {
+#pragma unroll
+            for (int c = 3; c < 6; ++c) {
+                unsafeAtomicAdd(&ar[c * n_pad + i], (double)fi[c]);
+                unsafeAtomicAdd(&ar[c * n_pad + jo], (double)fj[c]);
+            }
+        }
+    }
+    if constexpr (T::z) {
+        const double zw = wave_sum((double)zt);
+        if (lane == 0 && contact_tile) unsafeAtomicAdd(&zbuf[it.rep], zw);
+    }
+    if constexpr (MODE == PM_SCPS1) {
+#pragma unroll
+        for (int kk = 0; kk < KMAX; ++kk) {
+            if (kk < K) {
+                const double s = wave_sum((double)dk[kk]);
+                if (lane == 0) unsafeAtomicAdd(&dsum[(int64_t)it.rep * kmax + kk], s);
+            }
+        }
+    }
+}
+
+hipError_t launch_pairs(int mode, const KParams &P, const SysDesc *sysd, const RepDesc *reps,
+                        const TileItem *items, int n_items, const float4 *xs, double *acc, double *zbuf,
+                        double *dsum, const float *coef, const double *csum, int kmax, hipStream_t st) {
+    if (n_items == 0) return hipSuccess;
+    const dim3 grid((n_items + 3) / 4), block(256);
+    switch (mode) {
+    case PM_RMD:
+        hipLaunchKernelGGL(k_pairs<PM_RMD>, grid, block, 0, st, P, sysd, reps, items, n_items, xs, acc, zbuf,
+                           dsum, coef, csum, kmax);
+        break;
+    case PM_Z:
+        hipLaunchKernelGGL(k_pairs<PM_Z>, grid, block, 0, st, P, sysd, reps, items, n_items, xs, acc, zbuf,
+                           dsum, coef, csum, kmax);
+        break;
+    case PM_ZG:
+        hipLaunchKernelGGL(k_pairs<PM_ZG>, grid, block, 0, st, P, sysd, reps, items, n_items, xs, acc, zbuf,
+                           dsum, coef, csum, kmax);
+        break;
+    case PM_SCPS1:
+        hipLaunchKernelGGL(k_pairs<PM_SCPS1>, grid, block, 0, st, P, sysd, reps, items, n_items, xs, acc, zbuf,
+                           dsum, coef, csum, kmax);
+        break;
+    default:
+        hipLaunchKernelGGL(k_pairs<PM_SCPS2>, grid, block, 0, st, P, sysd, reps, items, n_items, xs, acc, zbuf,
+                           dsum, coef, csum, kmax);
+        break;
+    }
+    return hipGetLastError();
+}
+
+// rMD ratchet per replica, eq (FrMD); zbuf is consumed and cleared.
+__global__ void k_finalize_rmd(const KParams P, const int R, double *__restrict__ zbuf, double *__restrict__ cv,
+                               double *__restrict__ scale) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    const double z = zbuf[r];
+    zbuf[r] = 0.0;
+    double *c = cv + (int64_t)r * CV_STRIDE;
+    const double zm = fmin(c[CV_ZM], z);
+    const double dz = z - zm;
+    c[CV_Z] = z;
+    c[CV_ZM] = zm;
+    c[CV_EB] = 0.5 * P.k_R * dz * dz;
+    scale[r] = -P.k_R * dz;
+}
+
+hipError_t launch_finalize_rmd(const KParams &P, int R, double *zbuf, double *cv, double *scale, hipStream_t st) {
+    hipLaunchKernelGGL(k_finalize_rmd, dim3((R + 255) / 256), dim3(256), 0, st, P, R, zbuf, cv, scale);
+    return hipGetLastError();
+}
+
+// SCPS tube variables per replica (one wavefront each), from the squared
+// distances d_k*Z0 to every frame k = 0..M of the stack:
+//   s = 1 - (1/M) sum_k k p_k,  w = -(1/lambda) log sum_k exp(-lambda d_k),
+//   p_k = softmax(-lambda d_k); ratchets on s and w, eqs (Fw),(Fs).
+// The bias force is -sum_k c_k grad d_k with
+//   c_k = p_k [k_s (s - s_m)(lambda/M)(k - kbar) + k_w (w - w_m)];
+// coef receives c_k / Z0 and csum sum_k c_k / Z0 for the gradient pass.
+__global__ void k_finalize_scps(const KParams P, const SysDesc *__restrict__ sysd, const RepDesc *__restrict__ reps,
+                                const int kmax, double *__restrict__ dsum, double *__restrict__ cv,
+                                float *__restrict__ coef, double *__restrict__ csum) {
+    const int r = blockIdx.x;
+    const int lane = threadIdx.x;
+    const SysDesc S = sysd[reps[r].sys];
+    const int K = S.K, M = K - 1;
+    double *dr = dsum + (int64_t)r * kmax;
+    const double lam = P.lambda;
+    double a = -INFINITY;
+    for (int k = lane; k < K; k += 64) a = fmax(a, -lam * dr[k] / S.Z0);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) a = fmax(a, __shfl_xor(a, o, 64));
+    double s0 = 0.0, s1 = 0.0;
+    for (int k = lane; k < K; k += 64) {
+        const double e = exp(-lam * dr[k] / S.Z0 - a);
+        s0 += e;
+        s1 += (double)k * e;
+    }
+    s0 = wave_sum(s0);
+    s1 = wave_sum(s1);
+    const double kbar = s1 / s0;
+    const double sv = 1.0 - kbar / (double)M;
+    const double wv = -(a + log(s0)) / lam;
+    double *c = cv + (int64_t)r * CV_STRIDE;
+    const double sm = fmin(c[CV_SM], sv);
+    const double wm = fmin(c[CV_WM], wv);
+    const double ds = sv - sm, dw = wv - wm;
+    double tot = 0.0;
+    for (int k = lane; k < K; k += 64) {
+        const double pk = exp(-lam * dr[k] / S.Z0 - a) / s0;
+        const double ckv = pk * (P.k_s * ds * (lam / (double)M) * ((double)k - kbar) + P.k_w * dw);
+        coef[(int64_t)r * kmax + k] = (float)(ckv / S.Z0);
+        tot += ckv;
+    }
+    tot = wave_sum(tot);
+    __syncthreads();
+    for (int k = lane; k < K; k += 64) dr[k] = 0.0;
+    if (lane == 0) {
+        csum[r] = tot / S.Z0;
+        c[CV_S] = sv;
+        c[CV_W] = wv;
+        c[CV_SM] = sm;
+        c[CV_WM] = wm;
+        c[CV_EB] = 0.5 * P.k_s * ds * ds + 0.5 * P.k_w * dw * dw;
+    }
+}
+
+hipError_t launch_finalize_scps(const KParams &P, const SysDesc *sysd, const RepDesc *reps, int R, int kmax,
+                                double *dsum, double *cv, float *coef, double *csum, hipStream_t st) {
+    hipLaunchKernelGGL(k_finalize_scps, dim3(R), dim3(64), 0, st, P, sysd, reps, kmax, dsum, cv, coef, csum);
+    return hipGetLastError();
+}
+
+// Langevin update of every particle; consumes and clears the accumulators.
+// The force is acc[0..2] + scale[r] * acc[3..5].
+__global__ void k_integrate(const KParams P, const SysDesc *__restrict__ sysd, const RepDesc *__restrict__ reps,
+                            float4 *__restrict__ xs, float4 *__restrict__ vs, double *__restrict__ acc,
+                            const double *__restrict__ scale, const uint64_t step, int *__restrict__ flags) {
+    const int r = blockIdx.y;
+    const RepDesc rd = reps[r];
+    const SysDesc S = sysd[rd.sys];
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= S.n) return;
+    const int n_pad = S.n_pad;
+    double *ar = acc + 6 * rd.poff;
+    const double sc = scale[r];
+    double F[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        F[c] = ar[c * n_pad + a] + sc * ar[(c + 3) * n_pad + a];
+        ar[c * n_pad + a] = 0.0;
+        ar[(c + 3) * n_pad + a] = 0.0;
+    }
+    double g[3];
+    normals3(P, (uint32_t)S.perm[a], P.rep_base + (uint32_t)r, step, g[0], g[1], g[2]);
+    const float4 p = xs[rd.poff + a];
+    double X[3] = {(double)p.x, (double)p.y, (double)p.z};
+    const double inv_m = 1.0 / (double)S.mass[a];
+    if (P.integrator == 0) {
+        const double mob = P.dt * inv_m / P.gamma;
+        const double amp = sqrt(2.0 * P.kT * mob);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) X[c] += mob * F[c] + amp * g[c];
+    } else {
+        const float4 q = vs[rd.poff + a];
+        double V[3] = {(double)q.x, (double)q.y, (double)q.z};
+        const double amp = sqrt((1.0 - P.c1 * P.c1) * P.kT * inv_m);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            V[c] += P.dt * F[c] * inv_m;
+            X[c] += 0.5 * P.dt * V[c];
+            V[c] = P.c1 * V[c] + amp * g[c];
+            X[c] += 0.5 * P.dt * V[c];
+        }
+        vs[rd.poff + a] = make_float4((float)V[0], (float)V[1], (float)V[2], 0.f);
+    }
+    const float4 np = make_float4((float)X[0], (float)X[1], (float)X[2], p.w);
+    if (!(isfinite(np.x) && isfinite(np.y) && isfinite(np.z))) flags[r] = 1;
+    xs[rd.poff + a] = np;
+}
+
+hipError_t launch_integrate(const KParams &P, const SysDesc *sysd, const RepDesc *reps, int R, int n_pad_max,
+                            float4 *xs, float4 *vs, double *acc, const double *scale, uint64_t step, int *flags,
+                            hipStream_t st) {
+    hipLaunchKernelGGL(k_integrate, dim3((n_pad_max + 255) / 256, R), dim3(256), 0, st, P, sysd, reps, xs, vs, acc,
+                       scale, step, flags);
+    return hipGetLastError();
+}
+
+// z and coef * grad z out of the accumulators (eval_z_and_grad); clears them.
+__global__ void k_eval_out(const SysDesc *__restrict__ sysd, const RepDesc *__restrict__ reps,
+                           double *__restrict__ acc, double *__restrict__ zbuf, double *__restrict__ z_out,
+                           float *__restrict__ grad, const double *__restrict__ grad_coef) {
+    const int r = blockIdx.y;
+    const RepDesc rd = reps[r];
+    const SysDesc S = sysd[rd.sys];
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a == 0 && blockIdx.x == 0 && z_out) z_out[r] = zbuf[r];
+    if (a >= S.n) return;
+    if (!grad) return;
+    const int n = S.n, n_pad = S.n_pad;
+    double *ar = acc + 6 * rd.poff;
+    const double cf = grad_coef ? grad_coef[r] : 1.0;
+    const int o = S.perm[a];
+    float *gr = grad + 3 * rd.off;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        gr[c * n + o] = (float)(cf * ar[(c + 3) * n_pad + a]);
+        ar[(c + 3) * n_pad + a] = 0.0;
+    }
+}
+
+__global__ void k_clear_z(int R, double *zbuf) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < R) zbuf[r] = 0.0;
+}
+
+hipError_t launch_eval_out(const SysDesc *sysd, const RepDesc *reps, int R, int n_pad_max, double *acc,
+                           double *zbuf, double *z_out, float *grad, const double *grad_coef, hipStream_t st) {
+    hipLaunchKernelGGL(k_eval_out, dim3((n_pad_max + 255) / 256, R), dim3(256), 0, st, sysd, reps, acc, zbuf, z_out,
+                       grad, grad_coef);
+    hipLaunchKernelGGL(k_clear_z, dim3((R + 255) / 256), dim3(256), 0, st, R, zbuf);
+    return hipGetLastError();
+}
+
+__global__ void k_ratchet_energy(int R, double k_R, const double *__restrict__ z, const double *__restrict__ zm,
+                                 double *__restrict__ Eb, const double *__restrict__ gz,
+                                 const double *__restrict__ gE, double *__restrict__ coef) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    const double d = z[r] - zm[r];
+    const double th = d >= 0.0 ? 1.0 : 0.0;  // theta(0) = 1
+    if (Eb) Eb[r] = 0.5 * k_R * d * d * th;
+    if (coef) coef[r] = (gz ? gz[r] : 0.0) + (gE ? gE[r] : 0.0) * k_R * d * th;
+}
+
+hipError_t launch_ratchet_energy(int R, double k_R, const double *z, const double *zm, double *Eb,
+                                 const double *gz, const double *gE, double *coef, hipStream_t st) {
+    hipLaunchKernelGGL(k_ratchet_energy, dim3((R + 255) / 256), dim3(256), 0, st, R, k_R, z, zm, Eb, gz, gE, coef);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// reference maps
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double contact_f64(double r2, double r0, double r_cut) {
+    if (r_cut > 0.0 && r2 > r_cut * r_cut) return 0.0;
+    const double q = r2 / (r0 * r0);
+    const double q2 = q * q;
+    const double num = 1.0 + q + q2;
+    return num / (num + q2 * (q + q2));
+}
+
+__device__ __forceinline__ int64_t packed_index(int nc, int a, int b) {
+    return (int64_t)a * nc - (int64_t)a * (a + 1) / 2 + (b - a - 1);
+}
+
+// One workgroup of 256 threads per contact tile pair; thread (w, l) fills
+// rows k = w, w+4, ... of the diagonal-major layout element [k][l] =
+// R(64I + l, 64J + ((l + k) mod 64)).  Internal contact positions equal the
+// positions in contact_idx, so tiles and packed maps share indices.
+__global__ void k_native_map(int n, int nc, int ncb, const int *__restrict__ perm, const double *__restrict__ xyz,
+                             double r0, double r_cut, float *__restrict__ tiles, double *__restrict__ packed) {
+    int I, J;
+    tile_decode(blockIdx.x, ncb, I, J);
+    const int l = threadIdx.x & 63;
+    const int a = I * 64 + l;
+    float *t = tiles + (int64_t)blockIdx.x * 4096;
+    for (int k = threadIdx.x >> 6; k < 64; k += 4) {
+        const int b = J * 64 + ((l + k) & 63);
+        double C = 0.0;
+        if (a < nc && b < nc && a != b) {
+            const int oa = perm[a], ob = perm[b];
+            const double dx = xyz[oa] - xyz[ob];
+            const double dy = xyz[n + oa] - xyz[n + ob];
+            const double dz = xyz[2 * n + oa] - xyz[2 * n + ob];
+            C = contact_f64(dx * dx + dy * dy + dz * dz, r0, r_cut);
+            if (packed && a < b) packed[packed_index(nc, a, b)] = C;
+        }
+        t[k * 64 + l] = (float)C;
+    }
+}
+
+hipError_t launch_native_map(int n, int n_pad, int nc, int ncb, const int *perm_dev, const double *xyz_dev,
+                             double r0, double r_cut, float *tiles, double *packed, hipStream_t st) {
+    (void)n_pad;
+    const int nt = ncb * (ncb + 1) / 2;
+    if (nt == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_native_map, dim3(nt), dim3(256), 0, st, n, nc, ncb, perm_dev, xyz_dev, r0, r_cut, tiles,
+                       packed);
+    return hipGetLastError();
+}
+
+__global__ void k_pack_to_tiles(int nc, int ncb, int ntile, const double *__restrict__ packed,
+                                float *__restrict__ tiles) {
+    const int tile = blockIdx.x;
+    const int map = blockIdx.y;
+    int I, J;
+    tile_decode(tile, ncb, I, J);
+    const int64_t P = (int64_t)nc * (nc - 1) / 2;
+    const double *pm = packed + (int64_t)map * P;
+    float *t = tiles + ((int64_t)map * ntile + tile) * 4096;
+    const int l = threadIdx.x & 63;
+    const int a = I * 64 + l;
+    for (int k = threadIdx.x >> 6; k < 64; k += 4) {
+        const int b = J * 64 + ((l + k) & 63);
+        float v = 0.f;
+        if (a < nc && b < nc && a != b) v = (float)pm[a < b ? packed_index(nc, a, b) : packed_index(nc, b, a)];
+        t[k * 64 + l] = v;
+    }
+}
+
+hipError_t launch_pack_to_tiles(int n_maps, int nc, int ncb, const double *packed, float *tiles, hipStream_t st) {
+    const int nt = ncb * (ncb + 1) / 2;
+    if (nt == 0 || n_maps == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pack_to_tiles, dim3(nt, n_maps), dim3(256), 0, st, nc, ncb, nt, packed, tiles);
+    return hipGetLastError();
+}
+
+__global__ void k_sum_squares(int64_t m, const double *__restrict__ v, double *__restrict__ out) {
+    __shared__ double part[4];
+    double s = 0.0;
+    for (int64_t e = threadIdx.x; e < m; e += blockDim.x) s += v[e] * v[e];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) *out = part[0] + part[1] + part[2] + part[3];
+}
+
+hipError_t launch_sum_squares(int64_t m, const double *v, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_sum_squares, dim3(1), dim3(256), 0, st, m, v, out);
+    return hipGetLastError();
+}
+
+// eq (avCij): mean over successful paths of C(X_p(t_k)), float64 sums.
+// Grid (contact tile pair, frame); thread (w, l) owns 16 rows k of the
+// diagonal-major tile and loops over the successful paths.
+__global__ __launch_bounds__(256) void k_update_reference(int n, int nc, int ncb, int ntile,
+                                                          const int *__restrict__ perm,
+                                                          const float *__restrict__ frames, int n_paths,
+                                                          const int *__restrict__ succ, int n_succ, double r0,
+                                                          double r_cut, float *__restrict__ tiles,
+                                                          double *__restrict__ packed) {
+    __shared__ float4 blk[2][64];
+    const int tile = blockIdx.x, f = blockIdx.y;
+    int I, J;
+    tile_decode(tile, ncb, I, J);
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int a = I * 64 + l;
+    double sum[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) sum[k] = 0.0;
+    for (int s = 0; s < n_succ; ++s) {
+        const float *X = frames + ((int64_t)f * n_paths + succ[s]) * 3 * (int64_t)n;
+        __syncthreads();
+        if (threadIdx.x < 128) {
+            const int which = threadIdx.x >> 6;
+            const int c = (which ? J : I) * 64 + l;
+            float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (c < nc) {
+                const int o = perm[c];
+                p = make_float4(X[o], X[n + o], X[2 * n + o], 0.f);
+            }
+            blk[which][l] = p;
+        }
+        __syncthreads();
+        const float4 pa = blk[0][l];
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+            const int k = w * 16 + kk;
+            const float4 pb = blk[1][(l + k) & 63];
+            const double dx = (double)pa.x - (double)pb.x;
+            const double dy = (double)pa.y - (double)pb.y;
+            const double dz = (double)pa.z - (double)pb.z;
+            sum[kk] += contact_f64(dx * dx + dy * dy + dz * dz, r0, r_cut);
+        }
+    }
+    float *t = tiles + ((int64_t)f * ntile + tile) * 4096;
+    const int64_t P = (int64_t)nc * (nc - 1) / 2;
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+        const int k = w * 16 + kk;
+        const int b = J * 64 + ((l + k) & 63);
+        double mean = 0.0;
+        if (a < nc && b < nc && a != b) {
+            mean = sum[kk] / (double)n_succ;
+            if (packed && a < b) packed[(int64_t)f * P + packed_index(nc, a, b)] = mean;
+        }
+        t[k * 64 + l] = (float)mean;
+    }
+}
+
+hipError_t launch_update_reference(int n, int n_pad, int nc, int ncb, const int *perm_dev, const float *frames,
+                                   int n_paths, int n_frames, const int *succ_idx, int n_succ, double r0,
+                                   double r_cut, float *tiles, double *packed, hipStream_t st) {
+    (void)n_pad;
+    const int nt = ncb * (ncb + 1) / 2;
+    if (nt == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_update_reference, dim3(nt, n_frames), dim3(256), 0, st, n, nc, ncb, nt, perm_dev, frames,
+                       n_paths, succ_idx, n_succ, r0, r_cut, tiles, packed);
+    return hipGetLastError();
+}
+
+}  // namespace scps

@@ -1,0 +1,306 @@
+"""Python binding of libscps (include/scps.h): argument marshalling only.
+
+Every computation happens in the HIP library.  Device arrays are torch
+tensors on the current GPU; the library queues its work on torch's current
+stream.  Importing this module loads ``libscps.so`` and raises if it has not
+been built -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch  # loads the HIP runtime the library binds to
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libscps.so")
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1705_02180_amd.build` "
+                      "(or __graft_entry__.build())")
+
+CV_STRIDE = 8
+CV_Z, CV_ZM, CV_EB, CV_S, CV_W, CV_SM, CV_WM = range(7)
+STATUS = {0: "OK", -1: "INVALID_ARG", -2: "SHAPE", -3: "OOM", -4: "HIP", -5: "STATE",
+          -6: "NONFINITE", -7: "NO_SUCCESS"}
+
+
+class ScpsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"scps {STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("integrator", C.c_int32), ("bias_mode", C.c_int32), ("exec_mode", C.c_int32),
+        ("nb_excl", C.c_int32), ("min_seq_sep", C.c_int32), ("replica_base", C.c_int32),
+        ("dt", C.c_double), ("gamma", C.c_double), ("kT", C.c_double),
+        ("k_bond", C.c_double), ("r_bond", C.c_double),
+        ("lj_eps", C.c_double), ("lj_sigma", C.c_double),
+        ("dh_prefactor", C.c_double), ("dh_kappa", C.c_double),
+        ("r0_contact", C.c_double), ("r_cut_contact", C.c_double),
+        ("k_R", C.c_double), ("lam", C.c_double), ("k_s", C.c_double), ("k_w", C.c_double),
+        ("seed", C.c_uint64),
+    ]
+
+
+class Topology(C.Structure):
+    _fields_ = [
+        ("n_systems", C.c_int32),
+        ("n_particles", C.POINTER(C.c_int32)), ("n_contact", C.POINTER(C.c_int32)),
+        ("contact_idx", C.POINTER(C.c_int32)),
+        ("mass", C.POINTER(C.c_float)), ("charge", C.POINTER(C.c_float)),
+    ]
+
+
+_lib = C.CDLL(LIB_PATH)
+_vp, _i32, _i64, _u64, _d = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_double
+_lib.scps_init_system.restype = C.c_int
+_lib.scps_init_system.argtypes = [C.POINTER(Params), C.POINTER(Topology), _i32, _vp, _vp, C.POINTER(_vp)]
+_lib.scps_set_reference_map.restype = C.c_int
+_lib.scps_set_reference_map.argtypes = [_vp, _i32, _i32, _vp, _vp, _d]
+_lib.scps_step_replicas.restype = C.c_int
+_lib.scps_step_replicas.argtypes = [_vp, _vp, _vp, _vp, _i64, _u64, _i32, _vp]
+_lib.scps_eval_z_and_grad.restype = C.c_int
+_lib.scps_eval_z_and_grad.argtypes = [_vp, _vp, _vp, _vp, _vp]
+_lib.scps_ratchet_energy.restype = C.c_int
+_lib.scps_ratchet_energy.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.scps_update_reference_from_paths.restype = C.c_int
+_lib.scps_update_reference_from_paths.argtypes = [_vp, _i32, _vp, _i32, _i32, _vp, _vp]
+_lib.scps_set_stream.restype = C.c_int
+_lib.scps_set_stream.argtypes = [_vp, _vp]
+_lib.scps_sync.restype = C.c_int
+_lib.scps_sync.argtypes = [_vp, _vp, _vp]
+_lib.scps_destroy.restype = None
+_lib.scps_destroy.argtypes = [_vp]
+_lib.scps_last_error.restype = C.c_char_p
+_lib.scps_last_error.argtypes = []
+
+EXPORTS = ["scps_init_system", "scps_set_reference_map", "scps_step_replicas", "scps_eval_z_and_grad",
+           "scps_ratchet_energy", "scps_update_reference_from_paths", "scps_set_stream", "scps_sync",
+           "scps_destroy", "scps_last_error"]
+
+
+def _check(status: int):
+    if status != 0:
+        raise ScpsError(status, _lib.scps_last_error().decode())
+
+
+def _stream() -> C.c_void_p:
+    if not torch.cuda.is_available():      # host-side argument checks only
+        return C.c_void_p(None)
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t: Optional[torch.Tensor], dtype, numel: Optional[int] = None, name: str = "tensor"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+    return C.c_void_p(t.data_ptr())
+
+
+def make_params(d: dict, exec_mode: int = 0, replica_base: int = 0) -> Params:
+    return Params(
+        integrator=int(d["integrator"]), bias_mode=int(d["bias_mode"]), exec_mode=int(exec_mode),
+        nb_excl=int(d["nb_excl"]), min_seq_sep=int(d["min_seq_sep"]), replica_base=int(replica_base),
+        dt=d["dt"], gamma=d["gamma"], kT=d["kT"], k_bond=d["k_bond"], r_bond=d["r_bond"],
+        lj_eps=d["lj_eps"], lj_sigma=d["lj_sigma"], dh_prefactor=d["dh_prefactor"],
+        dh_kappa=d["dh_kappa"], r0_contact=d["r0_contact"], r_cut_contact=d["r_cut_contact"],
+        k_R=d["k_R"], lam=d["lam"], k_s=d["k_s"], k_w=d["k_w"], seed=int(d["seed"]))
+
+
+class Context:
+    """Owns one scps_ctx.  Methods mirror the C entry points."""
+
+    def __init__(self, params: dict, n_particles: Sequence[int], contact_idx: Sequence[np.ndarray],
+                 mass: Sequence[np.ndarray], charge: Sequence[np.ndarray], replica_system: Sequence[int],
+                 exec_mode: int = 0, replica_base: int = 0):
+        self.params = dict(params)
+        self.n = np.ascontiguousarray(n_particles, dtype=np.int32)
+        self.nc = np.ascontiguousarray([len(c) for c in contact_idx], dtype=np.int32)
+        self._cidx = np.ascontiguousarray(np.concatenate([np.asarray(c, dtype=np.int32) for c in contact_idx])
+                                          if len(contact_idx) else np.zeros(0, np.int32))
+        self._mass = np.ascontiguousarray(np.concatenate([np.asarray(m, dtype=np.float32) for m in mass]))
+        self._charge = np.ascontiguousarray(np.concatenate([np.asarray(q, dtype=np.float32) for q in charge]))
+        self.replica_system = np.ascontiguousarray(replica_system, dtype=np.int32)
+        self.R = len(self.replica_system)
+        self._p = make_params(self.params, exec_mode, replica_base)
+        topo = Topology(
+            n_systems=len(self.n),
+            n_particles=self.n.ctypes.data_as(C.POINTER(C.c_int32)),
+            n_contact=self.nc.ctypes.data_as(C.POINTER(C.c_int32)),
+            contact_idx=self._cidx.ctypes.data_as(C.POINTER(C.c_int32)),
+            mass=self._mass.ctypes.data_as(C.POINTER(C.c_float)),
+            charge=self._charge.ctypes.data_as(C.POINTER(C.c_float)))
+        h = C.c_void_p()
+        _check(_lib.scps_init_system(C.byref(self._p), C.byref(topo), self.R,
+                                     self.replica_system.ctypes.data_as(C.c_void_p), _stream(), C.byref(h)))
+        self._h = h
+        sizes = self.n[self.replica_system].astype(np.int64)
+        self.offsets = np.zeros(self.R + 1, dtype=np.int64)
+        self.offsets[1:] = np.cumsum(sizes)
+        self.sumN = int(self.offsets[-1])
+
+    @classmethod
+    def from_workload(cls, w, exec_mode: int = 0, params: Optional[dict] = None, replica_system=None,
+                      replica_base: int = 0):
+        rs = w.replica_system if replica_system is None else replica_system
+        return cls(params or w.params, [s.n for s in w.systems], [s.contact_idx for s in w.systems],
+                   [s.mass for s in w.systems], [s.charge for s in w.systems], rs, exec_mode, replica_base)
+
+    # -- lifetime ---------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.scps_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _ctx(self):
+        if not self._h:
+            raise ScpsError(-5, "context is closed")
+        _check(_lib.scps_set_stream(self._h, _stream()))
+        return self._h
+
+    def n_pairs(self, system: int) -> int:
+        nc = int(self.nc[system])
+        return nc * (nc - 1) // 2
+
+    # -- entry points -----------------------------------------------------------
+    def set_reference_map(self, system: int, maps: Optional[np.ndarray] = None,
+                          native_xyz: Optional[np.ndarray] = None, z0_norm: float = 0.0):
+        if maps is not None:
+            maps = np.ascontiguousarray(maps, dtype=np.float64)
+            n_maps = 1 if maps.ndim == 1 else maps.shape[0]
+            if maps.size != n_maps * self.n_pairs(system):
+                raise ValueError("maps must hold n_maps x P packed entries")
+        else:
+            n_maps = 1
+        if native_xyz is not None:
+            native_xyz = np.ascontiguousarray(native_xyz, dtype=np.float64)
+            if native_xyz.size != 3 * int(self.n[system]):
+                raise ValueError("native_xyz must be [3][N]")
+        _check(_lib.scps_set_reference_map(
+            self._ctx(), int(system), int(n_maps),
+            None if maps is None else maps.ctypes.data_as(C.c_void_p),
+            None if native_xyz is None else native_xyz.ctypes.data_as(C.c_void_p), float(z0_norm)))
+
+    def step_replicas(self, x: torch.Tensor, v: Optional[torch.Tensor], cvstate: torch.Tensor,
+                      n_steps: int, step0: int = 0, record_every: int = 0,
+                      frames: Optional[torch.Tensor] = None):
+        n3 = 3 * self.sumN
+        px = _dev(x, torch.float32, n3, "x")
+        pv = _dev(v, torch.float32, n3, "v")
+        pc = _dev(cvstate, torch.float64, self.R * CV_STRIDE, "cvstate")
+        pf = None
+        if record_every > 0:
+            pf = _dev(frames, torch.float32, (n_steps // record_every + 1) * n3, "frames")
+        _check(_lib.scps_step_replicas(self._ctx(), px, pv, pc, int(n_steps), int(step0),
+                                       int(record_every), pf))
+
+    def eval_z_and_grad(self, x: torch.Tensor, z: torch.Tensor, grad: Optional[torch.Tensor] = None,
+                        grad_coef: Optional[torch.Tensor] = None):
+        n3 = 3 * self.sumN
+        _check(_lib.scps_eval_z_and_grad(self._ctx(), _dev(x, torch.float32, n3, "x"),
+                                         _dev(z, torch.float64, self.R, "z"),
+                                         _dev(grad, torch.float32, n3, "grad"),
+                                         _dev(grad_coef, torch.float64, self.R, "grad_coef")))
+
+    def ratchet_energy(self, z: torch.Tensor, z_m: torch.Tensor, E_b: Optional[torch.Tensor] = None,
+                       gz: Optional[torch.Tensor] = None, gE: Optional[torch.Tensor] = None,
+                       coef: Optional[torch.Tensor] = None):
+        R = self.R
+        _check(_lib.scps_ratchet_energy(self._ctx(), _dev(z, torch.float64, R, "z"),
+                                        _dev(z_m, torch.float64, R, "z_m"), _dev(E_b, torch.float64, R, "E_b"),
+                                        _dev(gz, torch.float64, R, "gz"), _dev(gE, torch.float64, R, "gE"),
+                                        _dev(coef, torch.float64, R, "coef")))
+
+    def update_reference_from_paths(self, system: int, frames: torch.Tensor, n_paths: int, n_frames: int,
+                                    success: Sequence[int], want_maps: bool = False):
+        n = int(self.n[system])
+        pf = _dev(frames, torch.float32, n_frames * n_paths * 3 * n, "frames")
+        succ = np.ascontiguousarray(np.asarray(success, dtype=np.uint8))
+        if succ.size != n_paths:
+            raise ValueError("success must have n_paths entries")
+        out = np.zeros((n_frames, self.n_pairs(system))) if want_maps else None
+        _check(_lib.scps_update_reference_from_paths(
+            self._ctx(), int(system), pf, int(n_paths), int(n_frames), succ.ctypes.data_as(C.c_void_p),
+            None if out is None else out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def sync(self):
+        bad = np.zeros(self.R, dtype=np.int32)
+        nb = C.c_int32(0)
+        st = _lib.scps_sync(self._h, bad.ctypes.data_as(C.c_void_p), C.byref(nb))
+        if st == -6:
+            raise ScpsError(st, f"{_lib.scps_last_error().decode()}: replicas {bad[:nb.value].tolist()}")
+        _check(st)
+
+
+# module-level names matching the C entry points
+def init_system(params: dict, n_particles, contact_idx, mass, charge, replica_system, exec_mode: int = 0):
+    return Context(params, n_particles, contact_idx, mass, charge, replica_system, exec_mode)
+
+
+def set_reference_map(ctx: Context, system: int, maps=None, native_xyz=None, z0_norm: float = 0.0):
+    return ctx.set_reference_map(system, maps, native_xyz, z0_norm)
+
+
+def step_replicas(ctx: Context, x, v, cvstate, n_steps, step0=0, record_every=0, frames=None):
+    return ctx.step_replicas(x, v, cvstate, n_steps, step0, record_every, frames)
+
+
+def eval_z_and_grad(ctx: Context, x, z, grad=None, grad_coef=None):
+    return ctx.eval_z_and_grad(x, z, grad, grad_coef)
+
+
+def update_reference_from_paths(ctx: Context, system, frames, n_paths, n_frames, success, want_maps=False):
+    return ctx.update_reference_from_paths(system, frames, n_paths, n_frames, success, want_maps)
+
+
+class ZBias(torch.autograd.Function):
+    """z(X) and the rMD bias energy E_b = 1/2 k_R (z - z_m)^2 theta(z - z_m) as a
+    differentiable function of the coordinates.  forward evaluates z only;
+    backward recomputes every C_ij in the pair-gradient kernel (no stored map)
+    and returns (g_z + g_E k_R (z - z_m) theta) dz/dx."""
+
+    @staticmethod
+    def forward(ctx_, x: torch.Tensor, z_m: torch.Tensor, lib_ctx: Context):
+        z = torch.empty(lib_ctx.R, dtype=torch.float64, device=x.device)
+        lib_ctx.eval_z_and_grad(x, z)
+        Eb = torch.empty_like(z)
+        lib_ctx.ratchet_energy(z, z_m, Eb)
+        ctx_.save_for_backward(x, z, z_m)
+        ctx_.lib_ctx = lib_ctx
+        return z, Eb
+
+    @staticmethod
+    def backward(ctx_, gz: torch.Tensor, gE: torch.Tensor):
+        x, z, z_m = ctx_.saved_tensors
+        lib = ctx_.lib_ctx
+        coef = torch.empty_like(z)
+        gz = None if gz is None else gz.contiguous().to(torch.float64)
+        gE = None if gE is None else gE.contiguous().to(torch.float64)
+        lib.ratchet_energy(z, z_m, None, gz, gE, coef)
+        grad = torch.empty_like(x)
+        ztmp = torch.empty_like(z)
+        lib.eval_z_and_grad(x, ztmp, grad, coef)
+        return grad, None, None
+
+
+def zbias(x: torch.Tensor, z_m: torch.Tensor, lib_ctx: Context):
+    return ZBias.apply(x, z_m, lib_ctx)

@@ -1,0 +1,499 @@
+"""GPU parity: the HIP library, called through its C ABI, against the FP64
+CPU oracle on the same seeded inputs.
+
+Tolerances (pair arithmetic in float32, sums in float64):
+  z:      |z_gpu - z_ref| <= 1e-5 * max(z_ref, 1e-3 * Z0)
+  forces: max_i |F_gpu,i - F_ref,i| <= 1e-5 * max_i |F_ref,i| per replica
+          (normwise: a per-component relative error is meaningless near 0)
+Forces are read back from one BAOAB step at kT = 0 from rest, where the new
+velocity is exactly c1 dt F / m (float32 storage adds at most 6e-8).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1705_02180_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_1705_02180_amd import scps
+    return scps
+
+
+def dev(a, dtype="f32"):
+    import torch
+    t = {"f32": torch.float32, "f64": torch.float64}[dtype]
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=t, device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def context(S, w, params=None, exec_mode=0, replica_system=None, replica_base=0):
+    ctx = S.Context.from_workload(w, exec_mode=exec_mode, params=params, replica_system=replica_system,
+                                  replica_base=replica_base)
+    for s, sy in enumerate(w.systems):
+        ctx.set_reference_map(s, native_xyz=sy.native)
+    return ctx
+
+
+def normwise(a, b):
+    """max_i |a_i - b_i| / max_i |b_i| over particles (3-vectors)."""
+    d = np.linalg.norm((a - b).reshape(3, -1), axis=0).max()
+    return d / max(np.linalg.norm(b.reshape(3, -1), axis=0).max(), 1e-300)
+
+
+def single_system_workload(n, contact_idx, params, n_rep, seed=11, charges=True):
+    rng = np.random.default_rng(seed)
+    sy = I.System(n=n, contact_idx=np.asarray(contact_idx, dtype=np.int32),
+                  mass=np.full(n, 12.011 * I.AMU, dtype=np.float32),
+                  charge=(rng.normal(0, 0.3, n) if charges else np.zeros(n)).astype(np.float32),
+                  native=I.compact_native(n, seed), start=I.persistent_start(n, seed + 1))
+    return I.Workload(f"chain{n}", dict(params), [sy], np.zeros(n_rep, dtype=np.int32), 1)
+
+
+def states(sy, n_rep, seed):
+    """Different conformations per replica: random coils, a perturbed native, the start."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for r in range(n_rep):
+        if r % 3 == 0:
+            x = I.random_coil(sy.n, seed + 100 + r)
+        elif r % 3 == 1:
+            x = sy.native + rng.normal(0, 0.4, size=sy.native.shape)
+        else:
+            x = sy.start + rng.normal(0, 0.2, size=sy.start.shape)
+        out.append(x.astype(np.float32))
+    return np.stack(out)
+
+
+# ---------------------------------------------------------------------------
+# z and grad z
+# ---------------------------------------------------------------------------
+EVAL_CASES = [
+    ("fip35_shaped_560", 560, "heavy", {}),
+    ("ragged_100_all", 100, "all", {}),
+    ("ragged_257_every3", 257, "every3", {}),
+    ("seqsep35_300", 300, "all", {"min_seq_sep": 35}),
+    ("cutoff12_200", 200, "all", {"r_cut_contact": 12.0}),
+    ("tiny_2", 2, "all", {}),
+    ("no_contacts_70", 70, "none", {}),
+]
+
+
+def _cidx(n, kind):
+    if kind == "all":
+        return np.arange(n)
+    if kind == "heavy":
+        return np.nonzero(np.arange(n) % 16 < 8)[0]
+    if kind == "every3":
+        return np.arange(0, n, 3)
+    return np.zeros(0, dtype=np.int32)
+
+
+@pytest.mark.parametrize("name,n,kind,over", EVAL_CASES, ids=[c[0] for c in EVAL_CASES])
+def test_eval_z_and_grad_matches_oracle(S, name, n, kind, over):
+    import torch
+    p = dict(I._base_params())
+    p.update(over)
+    w = single_system_workload(n, _cidx(n, kind), p, 4)
+    ctx = context(S, w)
+    sy = w.systems[0]
+    X = states(sy, 4, 5) if n > 2 else np.array([[[0.0, 6.0], [0.0, 1.0], [0.0, 2.0]]] * 4, dtype=np.float32)
+    x = dev(X.ravel())
+    z = torch.zeros(4, dtype=torch.float64, device="cuda")
+    g = torch.zeros(3 * 4 * n, dtype=torch.float32, device="cuda")
+    ctx.eval_z_and_grad(x, z, g)
+    z_only = torch.zeros_like(z)
+    ctx.eval_z_and_grad(x, z_only)
+    torch.cuda.synchronize()
+    zg, gg, zo = host(z), host(g).reshape(4, 3, n), host(z_only)
+    osys = O.System.from_inputs(sy, p)
+    for r in range(4):
+        zr, gr = O.z_grad(X[r].astype(np.float64), osys.cidx, osys.native, p["r0_contact"],
+                          p["r_cut_contact"], p["min_seq_sep"])
+        bound = TOL * max(zr, 1e-3 * osys.Z0, 1e-300)
+        assert abs(zg[r] - zr) <= bound, (r, zg[r], zr)
+        assert abs(zo[r] - zr) <= bound
+        if np.abs(gr).max() > 0:
+            assert normwise(gg[r], gr) <= TOL, (r, normwise(gg[r], gr))
+        else:
+            assert np.all(gg[r] == 0)
+
+
+def test_eval_grad_coef_scales_the_gradient(S):
+    import torch
+    p = dict(I._base_params())
+    w = single_system_workload(130, np.arange(130), p, 3)
+    ctx = context(S, w)
+    X = states(w.systems[0], 3, 9)
+    x = dev(X.ravel())
+    z = torch.zeros(3, dtype=torch.float64, device="cuda")
+    g1 = torch.zeros(3 * 3 * 130, dtype=torch.float32, device="cuda")
+    g2 = torch.zeros_like(g1)
+    ctx.eval_z_and_grad(x, z, g1)
+    ctx.eval_z_and_grad(x, z, g2, dev([2.0, -0.5, 0.0], "f64"))
+    a, b = host(g1).reshape(3, -1), host(g2).reshape(3, -1)
+    np.testing.assert_allclose(b[0], 2.0 * a[0], rtol=1e-6, atol=0)
+    np.testing.assert_allclose(b[1], -0.5 * a[1], rtol=1e-6, atol=0)
+    assert np.all(b[2] == 0)
+
+
+# ---------------------------------------------------------------------------
+# forces of one step (rMD), both execution paths
+# ---------------------------------------------------------------------------
+def _force_readback_params(base, **kw):
+    p = dict(base)
+    p.update(integrator=1, kT=0.0, gamma=1e-3, dt=0.002)
+    p.update(kw)
+    return p
+
+
+def _gpu_forces_one_step(S, w, p, X, cv0, exec_mode):
+    import torch
+    R = w.n_replicas
+    ctx = context(S, w, params=p, exec_mode=exec_mode)
+    x = dev(X.ravel())
+    v = torch.zeros_like(x)
+    cv = dev(cv0, "f64")
+    ctx.step_replicas(x, v, cv, 1, step0=3)
+    ctx.sync()
+    c1 = math.exp(-p["gamma"] * p["dt"])
+    V = host(v)
+    out = []
+    off = 0
+    for r in range(R):
+        sy = w.systems[w.replica_system[r]]
+        n = sy.n
+        m = sy.mass.astype(np.float64)
+        out.append(V[3 * off:3 * (off + n)].reshape(3, n).astype(np.float64) * m / (c1 * p["dt"]))
+        off += n
+    return out, host(cv)
+
+
+@pytest.mark.parametrize("exec_mode", [0, 1], ids=["persistent", "per_step"])
+@pytest.mark.parametrize("case", ["fip35_shaped", "bias_only", "ragged_all"])
+def test_step_forces_match_oracle(S, exec_mode, case):
+    if case == "fip35_shaped":
+        w = I.config2(n_replicas=6, n_steps=1)
+        p = _force_readback_params(w.params, k_R=2e-3)
+    elif case == "bias_only":
+        w = I.config2(n_replicas=6, n_steps=1)
+        p = _force_readback_params(w.params, k_R=0.5, k_bond=0.0, lj_eps=0.0, dh_prefactor=0.0)
+    else:
+        base = dict(I._base_params())
+        w = single_system_workload(333, np.arange(333), base, 5)
+        p = _force_readback_params(base, k_R=1e-2)
+    sy = w.systems[0]
+    R = w.n_replicas
+    X = states(sy, R, 21)
+    osys = O.System.from_inputs(sy, p)
+    cv0 = np.zeros((R, 8))
+    cv0[:, 1] = np.inf
+    zs = [O.z_grad(X[r].astype(np.float64), osys.cidx, osys.native, grad=False) for r in range(R)]
+    for r in range(1, R):         # replica 0 starts its running minimum; the others are biased
+        cv0[r, 1] = 0.7 * zs[r] if r % 2 else 1.3 * zs[r]
+    Fg, cvg = _gpu_forces_one_step(S, w, p, X, cv0, exec_mode)
+    for r in range(R):
+        F, Fb, cvr = O.total_force(p, osys, X[r].astype(np.float64), cv0[r])
+        err = normwise(Fg[r], F)
+        assert err <= TOL, (r, err)
+        assert abs(cvg[r, 0] - cvr[0]) <= TOL * max(cvr[0], 1e-3 * osys.Z0)
+        assert abs(cvg[r, 1] - cvr[1]) <= TOL * max(cvr[1], 1e-3 * osys.Z0)
+        assert abs(cvg[r, 2] - cvr[2]) <= 1e-4 * max(cvr[2], 1e-12) + 1e-12
+
+
+# ---------------------------------------------------------------------------
+# noise: the counter layout and the normals
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("exec_mode", [0, 1], ids=["persistent", "per_step"])
+def test_noise_matches_oracle_philox(S, exec_mode):
+    import torch
+    n, R = 150, 5
+    p = dict(I._base_params())
+    # free overdamped particles with unit noise amplitude: x1 = x0 + xi
+    p.update(integrator=0, dt=1.0, gamma=1.0, kT=0.5, k_bond=0.0, lj_eps=0.0, dh_prefactor=0.0, k_R=0.0,
+             seed=0x1234_5678_9ABC)
+    w = single_system_workload(n, np.arange(0, n, 2), p, R, charges=False)
+    w.systems[0].mass[:] = 1.0
+    ctx = context(S, w, params=p, exec_mode=exec_mode, replica_base=7)
+    x = torch.zeros(3 * n * R, dtype=torch.float32, device="cuda")
+    cv = dev(np.tile([0, np.inf, 0, 0, 0, np.inf, np.inf, 0], (R, 1)), "f64")
+    step = (1 << 32) + 5
+    ctx.step_replicas(x, None, cv, 1, step0=step)
+    got = host(x).reshape(R, 3, n)
+    for r in range(R):
+        want = O.normals(p["seed"], np.arange(n), 7 + r, step).T
+        np.testing.assert_allclose(got[r], want, rtol=3e-7, atol=3e-7)
+
+
+# ---------------------------------------------------------------------------
+# one full noisy step and short trajectories
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("exec_mode", [0, 1], ids=["persistent", "per_step"])
+def test_one_noisy_baoab_step_matches_oracle(S, exec_mode):
+    import torch
+    w = I.config2(n_replicas=4, n_steps=1)
+    p = dict(w.params)
+    sy = w.systems[0]
+    X = states(sy, 4, 3)
+    V = np.stack([w.initial_v(5)[3 * sy.n * r:3 * sy.n * (r + 1)].reshape(3, sy.n) for r in range(4)])
+    ctx = context(S, w, exec_mode=exec_mode)
+    x, v = dev(X.ravel()), dev(V.ravel())
+    cv = dev(w.initial_cvstate(), "f64")
+    ctx.step_replicas(x, v, cv, 1, step0=11)
+    Xg, Vg = host(x).reshape(4, 3, -1), host(v).reshape(4, 3, -1)
+    osys = O.System.from_inputs(sy, p)
+    for r in range(4):
+        xo, vo, cvo, _ = O.steps(p, osys, r, X[r].astype(np.float64), V[r].astype(np.float64),
+                                 w.initial_cvstate()[r], 1, step0=11)
+        disp = np.abs(xo - X[r]).max()
+        assert np.abs(Xg[r] - xo).max() <= TOL * disp + 2.0 ** -24 * np.abs(xo).max()
+        assert np.abs(Vg[r] - vo).max() <= TOL * np.abs(vo).max()
+
+
+def test_short_trajectory_pathwise_config1(S):
+    import torch
+    w = I.config1(n_replicas=16, n_steps=10)
+    p = dict(w.params)
+    ctx = context(S, w)
+    x = dev(w.initial_x())
+    cv = dev(w.initial_cvstate(), "f64")
+    ctx.step_replicas(x, None, cv, 10)
+    ctx.sync()
+    osys = O.System.from_inputs(w.systems[0], p)
+    X0 = w.initial_x().reshape(16, 3, 20).astype(np.float64)
+    Xg = host(x).reshape(16, 3, 20)
+    CVg = host(cv)
+    for r in range(16):
+        xo, _, cvo, _ = O.steps(p, osys, r, X0[r], None, w.initial_cvstate()[r], 10)
+        disp = np.abs(xo - X0[r]).max()
+        assert np.abs(Xg[r] - xo).max() <= 1e-4 * disp, (r, np.abs(Xg[r] - xo).max() / disp)
+        assert abs(CVg[r, 1] - cvo[1]) <= 1e-4 * cvo[1]
+
+
+def test_persistent_and_per_step_paths_agree(S):
+    import torch
+    w = I.config2(n_replicas=8, n_steps=20)
+    res = []
+    for mode in (0, 1):
+        ctx = context(S, w, exec_mode=mode)
+        x, v = dev(w.initial_x()), dev(w.initial_v(1))
+        cv = dev(w.initial_cvstate(), "f64")
+        ctx.step_replicas(x, v, cv, 20, step0=100)
+        ctx.sync()
+        res.append((host(x), host(v), host(cv)))
+    x0 = w.initial_x()
+    disp = np.abs(res[0][0] - x0).max()
+    assert np.abs(res[0][0] - res[1][0]).max() <= 1e-4 * disp
+    np.testing.assert_allclose(res[0][2][:, :2], res[1][2][:, :2], rtol=1e-5)
+
+
+def test_batched_equals_one_replica_contexts(S):
+    import torch
+    w = I.config2(n_replicas=4, n_steps=6)
+    xb, vb = dev(w.initial_x()), dev(w.initial_v(2))
+    cvb = dev(w.initial_cvstate(), "f64")
+    ctx = context(S, w)
+    ctx.step_replicas(xb, vb, cvb, 6)
+    n3 = 3 * w.systems[0].n
+    X0, V0 = w.initial_x(), w.initial_v(2)
+    for r in range(4):
+        c1 = context(S, w, replica_system=[0], replica_base=r)
+        x1, v1 = dev(X0[r * n3:(r + 1) * n3]), dev(V0[r * n3:(r + 1) * n3])
+        cv1 = dev(w.initial_cvstate()[r:r + 1], "f64")
+        c1.step_replicas(x1, v1, cv1, 6)
+        disp = np.abs(host(xb)[r * n3:(r + 1) * n3] - X0[r * n3:(r + 1) * n3]).max()
+        assert np.abs(host(x1) - host(xb)[r * n3:(r + 1) * n3]).max() <= 1e-4 * disp
+
+
+def test_split_calls_equal_one_call(S):
+    w = I.config1(n_replicas=4, n_steps=8)
+    ctx = context(S, w)
+    xa, cva = dev(w.initial_x()), dev(w.initial_cvstate(), "f64")
+    ctx.step_replicas(xa, None, cva, 8, step0=40)
+    xb, cvb = dev(w.initial_x()), dev(w.initial_cvstate(), "f64")
+    ctx.step_replicas(xb, None, cvb, 3, step0=40)
+    ctx.step_replicas(xb, None, cvb, 5, step0=43)
+    # float64 atomics from different wavefronts commute only up to rounding
+    disp = np.abs(host(xa) - w.initial_x()).max()
+    assert np.abs(host(xa) - host(xb)).max() <= 1e-5 * disp
+    np.testing.assert_allclose(host(cva)[:, :3], host(cvb)[:, :3], rtol=1e-6)
+
+
+def test_frames_are_recorded(S):
+    import torch
+    w = I.config1(n_replicas=3, n_steps=10)
+    for mode in (0, 1):
+        ctx = context(S, w, exec_mode=mode)
+        x, cv = dev(w.initial_x()), dev(w.initial_cvstate(), "f64")
+        fr = torch.full((10 // 4 + 1, 3 * 60), -1.0, dtype=torch.float32, device="cuda")
+        ctx.step_replicas(x, None, cv, 10, record_every=4, frames=fr)
+        x2, cv2 = dev(w.initial_x()), dev(w.initial_cvstate(), "f64")
+        ctx.step_replicas(x2, None, cv2, 8)
+        F = host(fr)
+        np.testing.assert_array_equal(F[0], w.initial_x())
+        disp = np.abs(host(x2) - w.initial_x()).max()
+        assert np.abs(F[2] - host(x2)).max() <= 1e-5 * disp
+        assert np.abs(F[1] - w.initial_x()).max() > 0
+
+
+def test_nonfinite_replica_is_reported(S):
+    import torch
+    w = I.config1(n_replicas=3, n_steps=2)
+    ctx = context(S, w)
+    X = w.initial_x()
+    X[60 + 5] = np.nan
+    x, cv = dev(X), dev(w.initial_cvstate(), "f64")
+    ctx.step_replicas(x, None, cv, 2)
+    with pytest.raises(S.ScpsError) as e:
+        ctx.sync()
+    assert e.value.status == -6 and "[1]" in str(e.value)
+
+
+# ---------------------------------------------------------------------------
+# eq (avCij) and the SCPS bias
+# ---------------------------------------------------------------------------
+def _ensemble_frames(sy, n_frames, n_paths, seed):
+    rng = np.random.default_rng(seed)
+    out = np.empty((n_frames, n_paths, 3, sy.n), dtype=np.float32)
+    for k in range(n_frames):
+        lam = k / max(n_frames - 1, 1)
+        base = (1 - lam) * sy.start + lam * sy.native
+        for q in range(n_paths):
+            out[k, q] = base + rng.normal(0, 0.8, size=base.shape)
+    return out
+
+
+def test_update_reference_matches_oracle(S):
+    base = dict(I._base_params())
+    w = single_system_workload(200, np.arange(0, 200, 2), base, 2)
+    sy = w.systems[0]
+    ctx = context(S, w)
+    fr = _ensemble_frames(sy, 6, 5, 4)
+    succ = np.array([1, 0, 1, 1, 1], dtype=np.uint8)
+    maps = ctx.update_reference_from_paths(0, dev(fr.ravel()), 5, 6, succ, want_maps=True)
+    want, ns = O.update_reference(sy.n, sy.contact_idx, fr.astype(np.float64), succ)
+    assert ns == 4
+    np.testing.assert_allclose(maps, want, rtol=1e-12, atol=1e-15)
+    with pytest.raises(S.ScpsError) as e:
+        ctx.update_reference_from_paths(0, dev(fr.ravel()), 5, 6, np.zeros(5, dtype=np.uint8))
+    assert e.value.status == -7
+
+
+@pytest.mark.parametrize("n,kind,bias_only", [(180, "all", False), (300, "every3", False), (180, "all", True)],
+                         ids=["all_180", "every3_300", "bias_only_180"])
+def test_scps_step_forces_match_oracle(S, n, kind, bias_only):
+    base = dict(I._base_params())
+    p = _force_readback_params(base, bias_mode=1, lam=13.5, k_s=50.0, k_w=5.0)
+    if bias_only:
+        p.update(k_bond=0.0, lj_eps=0.0, dh_prefactor=0.0)
+    w = single_system_workload(n, _cidx(n, kind), p, 4)
+    sy = w.systems[0]
+    K = 9
+    fr = _ensemble_frames(sy, K, 4, 8)
+    ctx = context(S, w, params=p)
+    maps = ctx.update_reference_from_paths(0, dev(fr.ravel()), 4, K, np.ones(4, dtype=np.uint8), want_maps=True)
+    stack, _ = O.update_reference(sy.n, sy.contact_idx, fr.astype(np.float64), np.ones(4, dtype=np.uint8))
+    np.testing.assert_allclose(maps, stack, rtol=1e-12, atol=1e-15)
+    osys = O.System(sy.n, sy.contact_idx, sy.mass, sy.charge, p, native_xyz=sy.native, stack=stack)
+    X = np.stack([fr[3, 0], fr[5, 1], fr[1, 2], fr[7, 3]]).astype(np.float32)
+    cv0 = np.zeros((4, 8))
+    cv0[:, 5:7] = np.inf
+    for r in (1, 2, 3):
+        sv, wv, *_ = O.tube(X[r].astype(np.float64), osys.cidx, stack, osys.Z0, p["lam"], grads=False)
+        cv0[r, 5] = sv - 0.05 * r
+        cv0[r, 6] = wv - 0.01 * r
+    import torch
+    R = 4
+    ctx2 = context(S, w, params=p)
+    ctx2.set_reference_map(0, maps=stack)
+    x = dev(X.ravel())
+    v = torch.zeros_like(x)
+    cv = dev(cv0, "f64")
+    ctx2.step_replicas(x, v, cv, 1)
+    ctx2.sync()
+    c1 = math.exp(-p["gamma"] * p["dt"])
+    V = host(v).reshape(R, 3, n).astype(np.float64) * sy.mass.astype(np.float64) / (c1 * p["dt"])
+    CV = host(cv)
+    for r in range(R):
+        F, Fb, cvr = O.total_force(p, osys, X[r].astype(np.float64), cv0[r])
+        if np.abs(F).max() > 0:
+            assert normwise(V[r], F) <= TOL, (r, normwise(V[r], F))
+        else:
+            assert np.all(V[r] == 0)
+        if bias_only:
+            assert r == 0 or np.abs(Fb).max() > 0          # the ratchets are active
+        np.testing.assert_allclose(CV[r, 3:7], cvr[3:7], rtol=0, atol=1e-5)
+
+
+# ---------------------------------------------------------------------------
+# autograd wrapper
+# ---------------------------------------------------------------------------
+def test_zbias_autograd_matches_oracle_gradient(S):
+    import torch
+    base = dict(I._base_params())
+    base["k_R"] = 3e-3
+    w = single_system_workload(400, np.arange(400), base, 3)
+    sy = w.systems[0]
+    ctx = context(S, w)
+    X = states(sy, 3, 13)
+    osys = O.System.from_inputs(sy, base)
+    zr = [O.z_grad(X[r].astype(np.float64), osys.cidx, osys.native) for r in range(3)]
+    zm = np.array([0.8 * zr[0][0], 1.2 * zr[1][0], 0.5 * zr[2][0]])
+    x = dev(X.ravel()).requires_grad_(True)
+    z, Eb = S.zbias(x, dev(zm, "f64"), ctx)
+    (z.sum() + Eb.sum()).backward()
+    G = host(x.grad).reshape(3, 3, -1)
+    for r in range(3):
+        d = zr[r][0] - zm[r]
+        th = 1.0 if d >= 0 else 0.0
+        assert abs(host(Eb)[r] - 0.5 * base["k_R"] * d * d * th) <= 1e-4 * max(0.5 * base["k_R"] * d * d, 1e-12)
+        want = (1.0 + base["k_R"] * d * th) * zr[r][1]
+        assert normwise(G[r], want) <= TOL
+    # central differences of the oracle's z (float64, h = 1e-4 A) on 8 particles
+    rng = np.random.default_rng(0)
+    for r in range(3):
+        xr = X[r].astype(np.float64)
+        for i in rng.choice(sy.n, 8, replace=False):
+            for c in range(3):
+                xp = xr.copy(); xp[c, i] += 1e-4
+                xm = xr.copy(); xm[c, i] -= 1e-4
+                fd = (O.z_grad(xp, osys.cidx, osys.native, grad=False) -
+                      O.z_grad(xm, osys.cidx, osys.native, grad=False)) / 2e-4
+                d = zr[r][0] - zm[r]
+                want = (1.0 + base["k_R"] * d * (d >= 0)) * fd
+                assert abs(G[r, c, i] - want) <= 2e-4 * np.abs(G[r]).max()
+
+
+# ---------------------------------------------------------------------------
+# the benchmark configuration at full size, sampled replicas
+# ---------------------------------------------------------------------------
+def test_full_config2_sampled(S):
+    import torch
+    w = I.config2()                       # 256 replicas x 560 particles
+    p = _force_readback_params(w.params, k_R=2e-3)
+    sy = w.systems[0]
+    R = w.n_replicas
+    rng = np.random.default_rng(17)
+    X = np.stack([sy.start + rng.normal(0, 0.5, size=sy.start.shape) for _ in range(R)]).astype(np.float32)
+    osys = O.System.from_inputs(sy, p)
+    cv0 = np.zeros((R, 8))
+    cv0[:, 1] = np.inf
+    sample = [0, 1, 77, 128, 200, 255]
+    for r in sample[1:]:
+        cv0[r, 1] = 0.9 * O.z_grad(X[r].astype(np.float64), osys.cidx, osys.native, grad=False)
+    Fg, cvg = _gpu_forces_one_step(S, w, p, X, cv0, 0)
+    for r in sample:
+        F, _, cvr = O.total_force(p, osys, X[r].astype(np.float64), cv0[r])
+        assert normwise(Fg[r], F) <= TOL, (r, normwise(Fg[r], F))
+        assert abs(cvg[r, 0] - cvr[0]) <= TOL * max(cvr[0], 1e-3 * osys.Z0)
