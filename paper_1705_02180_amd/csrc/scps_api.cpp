@@ -29,6 +29,9 @@ scps_status fail(scps_status s, const std::string &msg) {
 struct SysHost {
     int n = 0, n_pad = 0, nb = 0, nc = 0, ncb = 0, ntile_c = 0;
     std::vector<int> perm, bond_next;
+    std::vector<int> tile_flags;        // [nb * nb], entry I * nb + J for I <= J
+    std::vector<int2> sched;            // persistent-kernel tile list, costliest first
+    int2 *d_sched = nullptr;
     std::vector<float> mass, charge;
     int *d_perm = nullptr, *d_bond_next = nullptr;
     float *d_mass = nullptr, *d_charge = nullptr;
@@ -66,6 +69,8 @@ struct scps_ctx {
     double *d_dsum = nullptr, *d_csum = nullptr;
     float *d_coef = nullptr;
     int kmax = KMAX;
+    int wg = 64;     // persistent workgroup size
+    int nbk = 0;     // nonbonded terms: bit 0 LJ, bit 1 Debye-Hueckel
     std::vector<void *> owned;
 };
 
@@ -100,6 +105,10 @@ KParams make_kparams(const scps_params &p) {
     KParams k{};
     k.inv_r0sq = (float)(1.0 / (p.r0_contact * p.r0_contact));
     k.g_scale = (float)(4.0 / (p.r0_contact * p.r0_contact));
+    k.cp[0] = (float)(-2.0 * 4.0 / (p.r0_contact * p.r0_contact));
+    k.cp[1] = (float)(-4.0 * 4.0 / (p.r0_contact * p.r0_contact));
+    k.cp[2] = (float)(-6.0 * 4.0 / (p.r0_contact * p.r0_contact));
+    k.cp[3] = (float)(-3.0 * 4.0 / (p.r0_contact * p.r0_contact));
     k.has_cut = p.r_cut_contact > 0.0;
     k.r_cut2 = (float)(p.r_cut_contact * p.r_cut_contact);
     k.lj_sig2 = (float)(p.lj_sigma * p.lj_sigma);
@@ -147,6 +156,8 @@ scps_status upload_sysdesc(scps_ctx *c) {
         o.charge = h.d_charge;
         o.ref = h.d_ref;
         o.stack = h.d_stack;
+        o.tiles = h.d_sched;
+        o.ntile = (int)h.sched.size();
         o.Z0 = h.Z0;
     }
     HIP_TRY(c, hipMemcpy(c->d_sysd, d.data(), d.size() * sizeof(SysDesc), hipMemcpyHostToDevice));
@@ -171,6 +182,58 @@ int pick_wg(int nb) {
     if (ntile >= 8) return 512;
     if (ntile >= 4) return 256;
     return 64;
+}
+
+// Per-tile flags of a system (see TILE_* in scps_internal.h).
+void compute_tile_flags(SysHost &h, const scps_params &p) {
+    const int nb = h.nb;
+    h.tile_flags.assign((size_t)nb * nb, 0);
+    std::vector<int> inv(h.n);
+    for (int a = 0; a < h.n; ++a) inv[h.perm[a]] = a;
+    std::vector<char> masked((size_t)nb * nb, 0);
+    for (int a = 0; a < h.n; ++a) {
+        const int o = h.perm[a];
+        for (int d = 1; d <= std::max(p.nb_excl, p.min_seq_sep) && o + d < h.n; ++d) {
+            const int b = inv[o + d];
+            const int lo = std::min(a, b), hi = std::max(a, b);
+            const bool contact_close = d <= p.min_seq_sep && a < h.nc && b < h.nc;
+            if (d <= p.nb_excl || contact_close) masked[(size_t)(lo / TILE) * nb + hi / TILE] = 1;
+        }
+    }
+    for (int I = 0; I < nb; ++I)
+        for (int J = I; J < nb; ++J) {
+            int f = 0;
+            if (I == J) f |= TILE_DIAG;
+            bool mask = masked[(size_t)I * nb + J];
+            if (I < h.ncb && J < h.ncb) {
+                f |= TILE_CONTACT;
+                mask = mask || (J + 1) * TILE > h.nc || p.r_cut_contact > 0.0;
+            }
+            if (mask) f |= TILE_MASK;
+            h.tile_flags[(size_t)I * nb + J] = f;
+        }
+}
+
+// Relative cost of a tile pair, for load balancing.
+double tile_cost(int f) {
+    double c = (f & TILE_CONTACT) ? 1.85 : 1.0;
+    if (f & TILE_MASK) c *= 1.15;
+    if (f & TILE_DIAG) c *= 0.5;
+    return c;
+}
+
+// The persistent kernel's tile list: every tile pair of the system, costliest
+// first.  Its wavefronts claim tiles dynamically in this order.
+void build_schedule(SysHost &h) {
+    std::vector<std::pair<double, int2>> all;
+    for (int I = 0; I < h.nb; ++I)
+        for (int J = I; J < h.nb; ++J) {
+            const int f = h.tile_flags[(size_t)I * h.nb + J];
+            all.push_back({tile_cost(f), make_int2((I << 16) | J, f)});
+        }
+    std::stable_sort(all.begin(), all.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
+    h.sched.clear();
+    for (const auto &t : all) h.sched.push_back(t.second);
 }
 
 scps_status init_impl(const scps_params *params, const scps_topology *topo, int32_t R, const int32_t *rsys,
@@ -258,6 +321,12 @@ scps_status init_impl(const scps_params *params, const scps_topology *topo, int3
     }
     c->sumN = c->rep_off[R];
     c->sumNpad = c->rep_poff[R];
+    c->wg = pick_wg(c->n_pad_max / TILE);
+    c->nbk = (p.lj_eps != 0.0 ? 1 : 0) | (p.dh_prefactor != 0.0 ? 2 : 0);
+    for (auto &h : c->sys) {
+        compute_tile_flags(h, p);
+        build_schedule(h);
+    }
 
     // device buffers
     for (auto &h : c->sys) {
@@ -269,6 +338,8 @@ scps_status init_impl(const scps_params *params, const scps_topology *topo, int3
         HIP_TRY(c, hipMemcpy(h.d_bond_next, h.bond_next.data(), h.n_pad * sizeof(int), hipMemcpyHostToDevice));
         HIP_TRY(c, hipMemcpy(h.d_mass, h.mass.data(), h.n_pad * sizeof(float), hipMemcpyHostToDevice));
         HIP_TRY(c, hipMemcpy(h.d_charge, h.charge.data(), h.n_pad * sizeof(float), hipMemcpyHostToDevice));
+        HIP_TRY(c, dalloc(c, &h.d_sched, h.sched.size()));
+        HIP_TRY(c, hipMemcpy(h.d_sched, h.sched.data(), h.sched.size() * sizeof(int2), hipMemcpyHostToDevice));
     }
     HIP_TRY(c, dalloc(c, &c->d_sysd, c->sys.size()));
     scps_status st = upload_sysdesc(c);
@@ -297,7 +368,7 @@ scps_status init_impl(const scps_params *params, const scps_topology *topo, int3
         const SysHost &h = c->sys[rsys[r]];
         for (int I = 0; I < h.nb; ++I)
             for (int J = I; J < h.nb; ++J) {
-                TileItem t{r, I, J, 0};
+                TileItem t{r, I, J, h.tile_flags[(size_t)I * h.nb + J]};
                 all.push_back(t);
                 if (I < h.ncb && J < h.ncb) con.push_back(t);
             }
@@ -314,7 +385,7 @@ scps_status init_impl(const scps_params *params, const scps_topology *topo, int3
 
     HIP_TRY(c, dalloc(c, &c->d_flags, R));
     HIP_TRY(c, hipMemset(c->d_flags, 0, R * sizeof(int)));
-    HIP_TRY(c, dalloc(c, &c->d_xs, c->sumNpad));
+    HIP_TRY(c, dalloc(c, &c->d_xs, 2 * c->sumNpad));
     HIP_TRY(c, dalloc(c, &c->d_vs, c->sumNpad));
     HIP_TRY(c, dalloc(c, &c->d_acc, 6 * c->sumNpad));
     HIP_TRY(c, hipMemset(c->d_acc, 0, 6 * c->sumNpad * sizeof(double)));
@@ -404,11 +475,10 @@ scps_status step_impl(scps_ctx *c, float *x, float *v, double *cv, int64_t n_ste
     }
     const int64_t frame_stride = 3 * c->sumN;
     bool persistent = !scps && c->prm.exec_mode == SCPS_EXEC_AUTO;
-    int nbmax = c->n_pad_max / TILE;
-    const int wg = pick_wg(nbmax);
+    const int wg = c->wg;
     if (persistent && c->n_pad_max > persistent_max_npad(wg)) persistent = false;
     if (persistent) {
-        HIP_TRY(c, launch_persistent_rmd(wg, c->kp, c->d_sysd, c->d_reps, c->d_order, c->R, c->n_pad_max, x, v, cv,
+        HIP_TRY(c, launch_persistent_rmd(wg, c->nbk, c->kp, c->d_sysd, c->d_reps, c->d_order, c->R, c->n_pad_max, x, v, cv,
                                          n_steps, step0, record_every, frames, frame_stride, c->d_flags,
                                          c->stream));
         return SCPS_OK;
@@ -421,18 +491,18 @@ scps_status step_impl(scps_ctx *c, float *x, float *v, double *cv, int64_t n_ste
                                       frames + (m / record_every) * frame_stride, c->stream));
         if (m == n_steps) break;
         if (!scps) {
-            HIP_TRY(c, launch_pairs(0, c->kp, c->d_sysd, c->d_reps, c->d_items_all, c->n_items_all, c->d_xs,
+            HIP_TRY(c, launch_pairs(0, c->nbk, c->kp, c->d_sysd, c->d_reps, c->d_items_all, c->n_items_all, c->d_xs,
                                     c->d_acc, c->d_zbuf, nullptr, nullptr, nullptr, c->kmax, c->stream));
             HIP_TRY(c, launch_finalize_rmd(c->kp, c->R, c->d_zbuf, cv, c->d_scale, c->stream));
             HIP_TRY(c, launch_integrate(c->kp, c->d_sysd, c->d_reps, c->R, c->n_pad_max, c->d_xs, c->d_vs, c->d_acc,
                                         c->d_scale, step0 + (uint64_t)m, c->d_flags, c->stream));
         } else {
-            HIP_TRY(c, launch_pairs(3, c->kp, c->d_sysd, c->d_reps, c->d_items_contact, c->n_items_contact,
+            HIP_TRY(c, launch_pairs(3, c->nbk, c->kp, c->d_sysd, c->d_reps, c->d_items_contact, c->n_items_contact,
                                     c->d_xs, c->d_acc, c->d_zbuf, c->d_dsum, nullptr, nullptr, c->kmax,
                                     c->stream));
             HIP_TRY(c, launch_finalize_scps(c->kp, c->d_sysd, c->d_reps, c->R, c->kmax, c->d_dsum, cv, c->d_coef,
                                             c->d_csum, c->stream));
-            HIP_TRY(c, launch_pairs(4, c->kp, c->d_sysd, c->d_reps, c->d_items_all, c->n_items_all, c->d_xs,
+            HIP_TRY(c, launch_pairs(4, c->nbk, c->kp, c->d_sysd, c->d_reps, c->d_items_all, c->n_items_all, c->d_xs,
                                     c->d_acc, c->d_zbuf, c->d_dsum, c->d_coef, c->d_csum, c->kmax, c->stream));
             HIP_TRY(c, launch_integrate(c->kp, c->d_sysd, c->d_reps, c->R, c->n_pad_max, c->d_xs, c->d_vs, c->d_acc,
                                         c->d_negone, step0 + (uint64_t)m, c->d_flags, c->stream));
@@ -449,7 +519,7 @@ scps_status eval_impl(scps_ctx *c, const float *x, double *z, float *grad, const
         if (!c->sys[c->rep_sys[r]].has_native)
             return fail(SCPS_ERR_STATE, "a system has no native map (scps_set_reference_map)");
     HIP_TRY(c, launch_gather(c->d_sysd, c->d_reps, c->R, c->n_pad_max, x, nullptr, c->d_xs, nullptr, c->stream));
-    HIP_TRY(c, launch_pairs(grad ? 2 : 1, c->kp, c->d_sysd, c->d_reps, c->d_items_contact, c->n_items_contact,
+    HIP_TRY(c, launch_pairs(grad ? 2 : 1, c->nbk, c->kp, c->d_sysd, c->d_reps, c->d_items_contact, c->n_items_contact,
                             c->d_xs, c->d_acc, c->d_zbuf, nullptr, nullptr, nullptr, c->kmax, c->stream));
     HIP_TRY(c, launch_eval_out(c->d_sysd, c->d_reps, c->R, c->n_pad_max, c->d_acc, c->d_zbuf, z, grad, coef,
                                c->stream));

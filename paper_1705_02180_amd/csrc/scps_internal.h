@@ -15,6 +15,7 @@ enum { CV_Z = 0, CV_ZM = 1, CV_EB = 2, CV_S = 3, CV_W = 4, CV_SM = 5, CV_WM = 6 
 struct KParams {
     float inv_r0sq;      // 1/r0^2
     float g_scale;       // 4/r0^2: dz/dx_i = sum_j g_scale (C - R) C'(q) (x_i - x_j)
+    float cp[4];         // -g_scale * {2, 4, 6, 3}: coefficients of -g_scale (3 + 6q + 4q^2 + 2q^3)
     float r_cut2;        // contact cutoff squared (used when has_cut)
     float lj_sig2;       // sigma^2
     float lj_24eps;      // 24 epsilon
@@ -45,6 +46,9 @@ struct SysDesc {
     const float *charge;     // [n_pad] internal order (pads: 0)
     const float *ref;        // native map tiles [ntile_c][64*64]
     const float *stack;      // SCPS frames [K][ntile_c][64*64]
+    const int2 *tiles;       // every tile pair, costliest first: {I << 16 | J, flags}
+    int ntile;
+    int pad1;
     double Z0;
 };
 
@@ -57,8 +61,15 @@ struct RepDesc {
 
 // A unit of pair work for the per-step kernels: one tile pair of one replica.
 struct TileItem {
-    int rep, I, J, pad0;
+    int rep, I, J, flags;
 };
+
+// Tile flags, computed on the host.  CONTACT: both blocks hold contact-set
+// particles.  MASK: a per-pair predicate is needed, because the tile holds a
+// pair excluded from the nonbonded sum (|i-j| <= nb_excl) or its contact sum
+// does (a block that straddles the end of the contact set, a pair within
+// min_seq_sep, or a contact cutoff).
+enum { TILE_DIAG = 1, TILE_CONTACT = 2, TILE_MASK = 4 };
 
 // Contact tile pairs (I <= J < ncb) are numbered row by row.
 __host__ __device__ inline int tile_index(int I, int J, int ncb) {
@@ -69,7 +80,7 @@ __host__ __device__ inline int tile_index(int I, int J, int ncb) {
 size_t persistent_lds_bytes(int n_pad, int wg);
 int persistent_max_npad(int wg);
 
-hipError_t launch_persistent_rmd(int wg, const KParams &P, const SysDesc *sysd, const RepDesc *reps,
+hipError_t launch_persistent_rmd(int wg, int nbk, const KParams &P, const SysDesc *sysd, const RepDesc *reps,
                                  const int *order, int R, int n_pad_max, float *x, float *v,
                                  double *cv, int64_t n_steps, uint64_t step0, int record_every,
                                  float *frames, int64_t frame_stride, int *flags, hipStream_t st);
@@ -82,7 +93,8 @@ hipError_t launch_scatter(const SysDesc *sysd, const RepDesc *reps, int R, int n
 
 // mode: 0 rMD forces (contact z + grad, nonbonded, bonds); 1 z only; 2 z and grad;
 //       3 SCPS pass 1 (distances to every frame); 4 SCPS pass 2 (bias + nonbonded + bonds)
-hipError_t launch_pairs(int mode, const KParams &P, const SysDesc *sysd, const RepDesc *reps,
+// nbk: nonbonded terms, bit 0 Lennard-Jones, bit 1 Debye-Hueckel
+hipError_t launch_pairs(int mode, int nbk, const KParams &P, const SysDesc *sysd, const RepDesc *reps,
                         const TileItem *items, int n_items, const float4 *xs, double *acc,
                         double *zbuf, double *dsum, const float *coef, const double *csum,
                         int kmax, hipStream_t st);

@@ -23,6 +23,10 @@
 
 #include "scps_internal.h"
 
+#ifndef SCPS_PAIR_GROUP
+#define SCPS_PAIR_GROUP 4
+#endif
+
 namespace scps {
 
 // ---------------------------------------------------------------------------
@@ -32,9 +36,19 @@ __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x)
 __device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ float fexp2(float x) { return __builtin_amdgcn_exp2f(x); }
 
-// Lane l receives what lane (l + 1) mod 64 holds (DPP wave_rol:1).
+// Lane l receives what lane (l + 1) mod 64 holds (DPP wave_rol:1).  Every
+// lane has a valid source, so the "old" operand is never used; passing the
+// value itself lets the move happen in place.
 __device__ __forceinline__ float rot1(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x134, 0xF, 0xF, false));
+    const int u = __float_as_int(v);
+    return __int_as_float(__builtin_amdgcn_update_dpp(u, u, 0x134, 0xF, 0xF, false));
+}
+
+// Reference maps live in global memory; telling the compiler so lets it use
+// global loads with a scalar base instead of flat loads.
+typedef const float __attribute__((address_space(1))) gfloat;
+__device__ __forceinline__ float ldg(const float *p, int64_t i) {
+    return ((gfloat *)p)[i];
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -59,23 +73,25 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32
     }
 }
 
-__device__ __forceinline__ double unit_open(uint32_t w) {
-    return (2.0 * (double)(w >> 9) + 1.0) * 0x1p-24;
+__device__ __forceinline__ float unit_open_f(uint32_t w) {
+    return (float)(2u * (w >> 9) + 1u) * 0x1p-24f;
 }
 
-// Three standard normals for (particle, replica, step); Box-Muller in float64.
+// Three standard normals for (particle, replica, step).  The uniforms are odd
+// multiples of 2^-24, exact in float32; Box-Muller runs in float32 (logf,
+// sqrtf, sincospif: within a few ulp of the float64 transform).
 __device__ __forceinline__ void normals3(const KParams &P, uint32_t atom, uint32_t rep, uint64_t step,
                                          double &g0, double &g1, double &g2) {
     uint32_t c[4] = {atom, rep, (uint32_t)step, (uint32_t)(step >> 32)};
     philox4x32_10(c, P.seed_lo, P.seed_hi);
-    const double r01 = sqrt(-2.0 * log(unit_open(c[0])));
-    const double r23 = sqrt(-2.0 * log(unit_open(c[2])));
-    double s, co;
-    sincospi(2.0 * unit_open(c[1]), &s, &co);
-    g0 = r01 * co;
-    g1 = r01 * s;
-    sincospi(2.0 * unit_open(c[3]), &s, &co);
-    g2 = r23 * co;
+    const float r01 = sqrtf(-2.f * logf(unit_open_f(c[0])));
+    const float r23 = sqrtf(-2.f * logf(unit_open_f(c[2])));
+    float sn, cs;
+    sincospif(2.f * unit_open_f(c[1]), &sn, &cs);
+    g0 = (double)(r01 * cs);
+    g1 = (double)(r01 * sn);
+    sincospif(2.f * unit_open_f(c[3]), &sn, &cs);
+    g2 = (double)(r23 * cs);
 }
 
 // ---------------------------------------------------------------------------
@@ -92,74 +108,116 @@ template <int MODE> struct ModeTraits {
 // Lane-side state of a tile pass.
 struct LaneI {
     float4 p;     // x, y, z, charge of particle i
+    float qp;     // k_e/eps_r * charge of i
     int o;        // chain index of i
     bool valid;   // i < n
     bool contact; // i in the contact set
 };
 
-// Outputs: fi[0..2] nonbonded, fi[3..5] contact gradient (i side);
-// fj likewise for the j particle lane l holds at the end, which is
-// jl_out = (l + kend + 1) mod 64 of block J.  zt: this lane's z partial.
-// SCPS pass 1 uses dk[0..K) instead (squared distances to every frame).
-template <int MODE, bool DIAG, bool CONTACT>
-__device__ __forceinline__ void tile_pass(const KParams &P, const int lane, const LaneI &A,
-                                          const float4 *__restrict__ posj, const int *__restrict__ orgj,
-                                          const int nvj, const int ncj,
-                                          const float *__restrict__ rt, const int64_t kstride,
-                                          const int K, const float *__restrict__ ck, const float csum,
-                                          float fi[6], float fj[6], float &zt, float *dk) {
-    using T = ModeTraits<MODE>;
-    constexpr int kbeg = DIAG ? 1 : 0;
-    constexpr int kend = DIAG ? 32 : 63;
-#pragma unroll 2
-    for (int k = kbeg; k <= kend; ++k) {
-        const int jl = (lane + k) & 63;
-        const float4 pj = posj[jl];
-        const int oj = orgj[jl];
-        const float dx = A.p.x - pj.x;
-        const float dy = A.p.y - pj.y;
-        const float dz = A.p.z - pj.z;
-        const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-        const bool act = (!DIAG || k < 32 || lane < 32) && A.valid && (jl < nvj);
-        const int sep = abs(A.o - oj);
-        if constexpr (T::nb) {
-            const float inv_r = frsq(r2);
-            const float inv_r2 = inv_r * inv_r;
-            float f = 0.f;
-            if (P.has_lj) {
-                const float s2 = P.lj_sig2 * inv_r2;
-                const float s6 = s2 * s2 * s2;
-                f = P.lj_24eps * s6 * fmaf(2.f, s6, -1.f) * inv_r2;
-            }
-            if (P.has_dh) {
-                const float r = r2 * inv_r;
-                const float u = P.dh_pref * A.p.w * pj.w * fexp2(P.dh_kl2 * r) * inv_r;
-                f = fmaf(u * (P.dh_kappa + inv_r), inv_r, f);
-            }
-            f = (act && sep > P.nb_excl) ? f : 0.f;
-            fi[0] = fmaf(f, dx, fi[0]);
-            fi[1] = fmaf(f, dy, fi[1]);
-            fi[2] = fmaf(f, dz, fi[2]);
-            fj[0] = fmaf(-f, dx, fj[0]);
-            fj[1] = fmaf(-f, dy, fj[1]);
-            fj[2] = fmaf(-f, dz, fj[2]);
+// After a tile pass the j-side partials have rotated once per sub-step, so
+// lane l holds particle (l + 33) mod 64 (diagonal tile: 32 sub-steps from
+// k = 1) or l (64 sub-steps) of block J.
+template <bool DIAG>
+__device__ __forceinline__ int jflush_lane(int lane) {
+    return (lane + (DIAG ? 33 : 64)) & 63;
+}
+
+// Squared distance of a pair, and the vector d = x_i - x_j.
+__device__ __forceinline__ float pair_r2(const float4 &pi, const float4 &pj, float &dx, float &dy, float &dz) {
+    dx = pi.x - pj.x;
+    dy = pi.y - pj.y;
+    dz = pi.z - pj.z;
+    return fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+}
+
+// Nonbonded scalar f with F_i += f (x_i - x_j):
+// f = [24 eps (2 s^12 - s^6) + k_e/eps_r q_i q_j e^{-kappa r} (kappa + 1/r)] / r^2, s = sigma / r.
+// qp_i = k_e/eps_r * q_i.  NBK bit 0: Lennard-Jones, bit 1: Debye-Hueckel.
+template <int NBK>
+__device__ __forceinline__ float nb_scalar(const KParams &P, const float r2, const float qp_i, const float q_j) {
+    if constexpr (NBK == 1) {
+        const float inv_r2 = frcp(r2);
+        const float s2 = P.lj_sig2 * inv_r2;
+        const float s6 = s2 * s2 * s2;
+        return fmaf(s6, 2.f * P.lj_24eps, -P.lj_24eps) * s6 * inv_r2;
+    } else if constexpr (NBK == 0) {
+        return 0.f;
+    } else {
+        const float inv_r = frsq(r2);
+        const float inv_r2 = inv_r * inv_r;
+        const float r = r2 * inv_r;
+        const float e = fexp2(P.dh_kl2 * r) * (qp_i * q_j);
+        float S = e * (P.dh_kappa + inv_r);
+        if constexpr (NBK == 3) {
+            const float s2 = P.lj_sig2 * inv_r2;
+            const float s6 = s2 * s2 * s2;
+            S = fmaf(fmaf(s6, 2.f * P.lj_24eps, -P.lj_24eps), s6, S);
         }
-        if constexpr (CONTACT) {
-            const bool con = act && A.contact && (jl < ncj) && sep > P.min_sep;
-            // beyond the optional cutoff the entry C_ij is set to 0 (R_ij still counts)
-            const bool inside = !P.has_cut || (r2 <= P.r_cut2);
-            const float q = r2 * P.inv_r0sq;
+        return S * inv_r2;
+    }
+}
+
+// One sub-step k of a tile pass: lane l meets particle j = 64 J + ((l + k) mod 64).
+// posj2 points at block J stored twice in a row, so posj2[l + k] needs no wrap.
+// Padding particles sit far away with zero charge, so their nonbonded and
+// contact terms vanish without a mask.  MASK tiles (host-computed flag) hold
+// a pair excluded from the nonbonded sum (chain neighbours) or need the
+// contact predicate (a block that straddles the end of the contact set, a
+// sequence separation, a cutoff); every other tile runs predicate-free.
+// act0 is false only for lanes 32..63 at k = 32 of a diagonal tile, where the
+// pair was already met at the mirrored sub-step.
+template <int MODE, bool DIAG, bool CONTACT, bool MASK, int NBK, int U>
+__device__ __forceinline__ void pair_group(const KParams &P, const int lane, const int k0, const bool low,
+                                           const LaneI &A, const float4 *__restrict__ posj2,
+                                           const int *__restrict__ orgj, const int ncj,
+                                           const float *__restrict__ rt, const int64_t kstride, const int K,
+                                           const float *__restrict__ ck, const float csum, float fi[6],
+                                           float fj[6], float &zt, float *dk) {
+    // Sub-steps k0 .. k0+U-1, computed phase by phase so that the U pair
+    // evaluations are independent instruction streams; only the
+    // accumulation (and the rotation of the j-side partials) is sequential.
+    using T = ModeTraits<MODE>;
+    float dx[U], dy[U], dz[U], r2[U], f[U], g[U];
+    bool nbon[U], con[U], inside[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int k = k0 + u;
+        const float4 pj = posj2[lane + k];
+        r2[u] = pair_r2(A.p, pj, dx[u], dy[u], dz[u]);
+        const bool act0 = DIAG ? (low | (k != 32)) : true;
+        nbon[u] = act0;
+        con[u] = act0;
+        inside[u] = true;
+        if constexpr (MASK) {
+            const int jl = (lane + k) & 63;
+            const int sep = abs(A.o - orgj[jl]);
+            nbon[u] = act0 & (sep > P.nb_excl);
+            con[u] = act0 & A.contact & (jl < ncj) & (sep > P.min_sep);
+            inside[u] = !P.has_cut | (r2[u] <= P.r_cut2);   // beyond a cutoff C_ij = 0 (R_ij still counts)
+        }
+        f[u] = 0.f;
+        if constexpr (T::nb && NBK != 0) {
+            const float fs = nb_scalar<NBK>(P, r2[u], A.qp, pj.w);
+            f[u] = nbon[u] ? fs : 0.f;
+        }
+    }
+    if constexpr (CONTACT) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = k0 + u;
+            const float q = r2[u] * P.inv_r0sq;
             const float q2 = q * q;
             const float num = 1.f + q + q2;
             const float den = fmaf(q2, q + q2, num);
-            const float inv_den = inside ? frcp(den) : 0.f;
+            const float inv_den = inside[u] ? frcp(den) : 0.f;
             const float C = num * inv_den;
+            g[u] = 0.f;
             if constexpr (MODE == PM_SCPS1) {
                 const float *rk = rt + k * 64 + lane;
 #pragma unroll
                 for (int kk = 0; kk < KMAX; ++kk) {
                     if (kk < K) {
-                        const float d = con ? (C - rk[kk * kstride]) : 0.f;
+                        const float d = con[u] ? (C - ldg(rk, kk * kstride)) : 0.f;
                         dk[kk] = fmaf(d, d, dk[kk]);
                     }
                 }
@@ -167,45 +225,114 @@ __device__ __forceinline__ void tile_pass(const KParams &P, const int lane, cons
                 float diff;
                 if constexpr (MODE == PM_SCPS2) {
                     float eff = csum * C;
-                    for (int kk = 0; kk < K; ++kk) eff = fmaf(-ck[kk], rt[kk * kstride + k * 64 + lane], eff);
+                    for (int kk = 0; kk < K; ++kk) eff = fmaf(-ck[kk], ldg(rt, kk * kstride + k * 64 + lane), eff);
                     diff = eff;
                 } else {
-                    diff = C - rt[k * 64 + lane];
+                    diff = C - ldg(rt, k * 64 + lane);
                 }
-                diff = con ? diff : 0.f;
+                diff = con[u] ? diff : 0.f;
                 if constexpr (T::z) zt = fmaf(diff, diff, zt);
                 if constexpr (T::grad) {
-                    const float poly = fmaf(q, fmaf(q, fmaf(q, 2.f, 4.f), 6.f), 3.f);
-                    const float Cp = -(q2 * poly) * (inv_den * inv_den);
-                    const float g = P.g_scale * diff * Cp;
-                    fi[3] = fmaf(g, dx, fi[3]);
-                    fi[4] = fmaf(g, dy, fi[4]);
-                    fi[5] = fmaf(g, dz, fi[5]);
-                    fj[3] = fmaf(-g, dx, fj[3]);
-                    fj[4] = fmaf(-g, dy, fj[4]);
-                    fj[5] = fmaf(-g, dz, fj[5]);
+                    // C'(q) = -q^2 (3 + 6q + 4q^2 + 2q^3) / den^2, evaluated as
+                    // (q^2/den) (poly/den) so nothing overflows at large q;
+                    // g = (4/r0^2) (C - R) C'(q), the factor -4/r0^2 folded into poly
+                    const float poly = fmaf(q, fmaf(q, fmaf(q, P.cp[0], P.cp[1]), P.cp[2]), P.cp[3]);
+                    g[u] = (diff * (q2 * inv_den)) * (poly * inv_den);
                 }
             }
         }
-        if constexpr (T::nb) {
-            fj[0] = rot1(fj[0]);
-            fj[1] = rot1(fj[1]);
-            fj[2] = rot1(fj[2]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        if constexpr (T::nb && NBK != 0) {
+            fi[0] = fmaf(f[u], dx[u], fi[0]);
+            fi[1] = fmaf(f[u], dy[u], fi[1]);
+            fi[2] = fmaf(f[u], dz[u], fi[2]);
+            fj[0] = rot1(fmaf(-f[u], dx[u], fj[0]));
+            fj[1] = rot1(fmaf(-f[u], dy[u], fj[1]));
+            fj[2] = rot1(fmaf(-f[u], dz[u], fj[2]));
         }
-        if constexpr (T::grad) {
-            if constexpr (CONTACT) {
-                fj[3] = rot1(fj[3]);
-                fj[4] = rot1(fj[4]);
-                fj[5] = rot1(fj[5]);
-            }
+        if constexpr (T::grad && CONTACT) {
+            fi[3] = fmaf(g[u], dx[u], fi[3]);
+            fi[4] = fmaf(g[u], dy[u], fi[4]);
+            fi[5] = fmaf(g[u], dz[u], fi[5]);
+            fj[3] = rot1(fmaf(-g[u], dx[u], fj[3]));
+            fj[4] = rot1(fmaf(-g[u], dy[u], fj[4]));
+            fj[5] = rot1(fmaf(-g[u], dz[u], fj[5]));
         }
     }
 }
 
-template <bool DIAG>
-__device__ __forceinline__ int jflush_lane(int lane) {
-    return (lane + (DIAG ? 33 : 64)) & 63;
+// Pair evaluations grouped per sub-step batch: more independent work per
+// wavefront for the modes with few registers per pair.
+template <int MODE> constexpr int group_width() {
+    return (MODE == PM_SCPS1 || MODE == PM_SCPS2) ? 1 : SCPS_PAIR_GROUP;
 }
+
+// A whole tile pair.  Outputs: fi[0..2] nonbonded, fi[3..5] contact gradient
+// (i side); fj likewise for the j particle lane l holds at the end, which is
+// (l + 33) mod 64 for a diagonal tile and l otherwise; zt: this lane's z
+// partial; dk[0..K): squared distances to every frame (SCPS pass 1).
+template <int MODE, bool DIAG, bool CONTACT, bool MASK, int NBK>
+__device__ __forceinline__ void tile_pass(const KParams &P, const int lane, const LaneI &A,
+                                          const float4 *__restrict__ posj2, const int *__restrict__ orgj,
+                                          const int ncj, const float *__restrict__ rt, const int64_t kstride,
+                                          const int K, const float *__restrict__ ck, const float csum, float fi[6],
+                                          float fj[6], float &zt, float *dk) {
+    constexpr int U = group_width<MODE>();
+    const bool low = lane < 32;
+    if constexpr (DIAG) {
+#pragma unroll 1
+        for (int k0 = 1; k0 <= 32; k0 += U)
+            pair_group<MODE, true, CONTACT, MASK, NBK, U>(P, lane, k0, low, A, posj2, orgj, ncj, rt, kstride, K, ck,
+                                                          csum, fi, fj, zt, dk);
+    } else {
+#pragma unroll 1
+        for (int k0 = 0; k0 < 64; k0 += U)
+            pair_group<MODE, false, CONTACT, MASK, NBK, U>(P, lane, k0, low, A, posj2, orgj, ncj, rt, kstride, K,
+                                                           ck, csum, fi, fj, zt, dk);
+    }
+}
+
+// Dispatch on the tile's flags (uniform across the wavefront).
+enum { TF_DIAG = TILE_DIAG, TF_CONTACT = TILE_CONTACT, TF_MASK = TILE_MASK };
+
+template <int MODE, int NBK>
+__device__ __forceinline__ void tile_dispatch(const int flags, const KParams &P, const int lane, const LaneI &A,
+                                              const float4 *__restrict__ posj2, const int *__restrict__ orgj,
+                                              const int ncj, const float *__restrict__ rt, const int64_t kstride,
+                                              const int K, const float *__restrict__ ck, const float csum,
+                                              float fi[6], float fj[6], float &zt, float *dk) {
+#define SCPS_TILE(D, C, M)                                                                                  \
+    tile_pass<MODE, D, C, M, NBK>(P, lane, A, posj2, orgj, ncj, rt, kstride, K, ck, csum, fi, fj, zt, dk)
+    const bool diag = flags & TF_DIAG, con = flags & TF_CONTACT, mask = flags & TF_MASK;
+    if (ModeTraits<MODE>::nb) {
+        if (diag) {
+            if (con) { if (mask) SCPS_TILE(true, true, true); else SCPS_TILE(true, true, false); }
+            else     { if (mask) SCPS_TILE(true, false, true); else SCPS_TILE(true, false, false); }
+        } else {
+            if (con) { if (mask) SCPS_TILE(false, true, true); else SCPS_TILE(false, true, false); }
+            else     { if (mask) SCPS_TILE(false, false, true); else SCPS_TILE(false, false, false); }
+        }
+    } else if (con) {
+        if (diag) { if (mask) SCPS_TILE(true, true, true); else SCPS_TILE(true, true, false); }
+        else      { if (mask) SCPS_TILE(false, true, true); else SCPS_TILE(false, true, false); }
+    }
+#undef SCPS_TILE
+}
+
+
+// Padding particle a: uncharged, 1e6 A away from the chain and 1e3 A from
+// every other pad, so its Lennard-Jones, Debye-Hueckel and contact terms are
+// zero in float32 (the contact denominator overflows to inf, C = C' = 0).
+__device__ __forceinline__ float4 pad_position(int a) {
+    return make_float4(1.0e6f + 1.0e3f * (float)(a & 7), 1.0e3f * (float)((a >> 3) & 7), 1.0e3f * (float)(a >> 6),
+                       0.f);
+}
+
+// Index of internal particle a in a position array that stores every block of
+// 64 twice in a row (block b occupies [128 b, 128 b + 128)).
+__device__ __forceinline__ int dup_index(int a) { return ((a >> 6) << 7) + (a & 63); }
 
 // Harmonic bond between internal particle a and its chain successor b, float64.
 __device__ __forceinline__ void bond_force(const KParams &P, float4 pa, float4 pb, double f[3]) {
@@ -222,14 +349,22 @@ __device__ __forceinline__ void bond_force(const KParams &P, float4 pa, float4 p
 // ---------------------------------------------------------------------------
 // persistent rMD kernel: one workgroup runs one replica for all n_steps
 // ---------------------------------------------------------------------------
+// LDS per padded particle: positions twice (2 x float4), chain index (int),
+// six float64 accumulators, velocity (3 x float).
+// Plus a reduction slot per wavefront.
+constexpr size_t PERSIST_BYTES_PER_PARTICLE = 32 + 4 + 48 + 12;
+
+static size_t persistent_fixed_bytes(int wg) {
+    return (size_t)(wg / 64) * 8 + 64;
+}
+
 size_t persistent_lds_bytes(int n_pad, int wg) {
-    // pos float4, chain index int, acc 6 x double, vel 3 x float, reduction
-    return (size_t)n_pad * (16 + 4 + 48 + 12) + (size_t)(wg / 64) * 8 + 64;
+    return (size_t)n_pad * PERSIST_BYTES_PER_PARTICLE + persistent_fixed_bytes(wg);
 }
 
 int persistent_max_npad(int wg) {
     const size_t lds = 160 * 1024;
-    int n = (int)((lds - (size_t)(wg / 64) * 8 - 64) / (16 + 4 + 48 + 12));
+    int n = (int)((lds - persistent_fixed_bytes(wg)) / PERSIST_BYTES_PER_PARTICLE);
     return (n / 64) * 64;
 }
 
@@ -243,8 +378,11 @@ __device__ __forceinline__ void tile_decode(int t, int nb, int &I, int &J) {
     J = row + t;
 }
 
-template <int WG>
-__global__ __launch_bounds__(WG) void k_rmd_persistent(
+// One workgroup per replica is resident per CU in the benchmark shapes, so
+// the register budget is WG/64/4 waves per SIMD: let the scheduler use it for
+// latency hiding instead of aiming for a higher occupancy it cannot reach.
+template <int WG, int NBK>
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WG / 256 > 0 ? WG / 256 : 1, WG / 256 > 0 ? WG / 256 : 1))) void k_rmd_persistent(
     const KParams P, const SysDesc *__restrict__ sysd, const RepDesc *__restrict__ reps,
     const int *__restrict__ order, float *__restrict__ x, float *__restrict__ v,
     double *__restrict__ cv, const int64_t n_steps, const uint64_t step0, const int record_every,
@@ -254,47 +392,52 @@ __global__ __launch_bounds__(WG) void k_rmd_persistent(
     const int r = order[blockIdx.x];
     const RepDesc rd = reps[r];
     const SysDesc S = sysd[rd.sys];
-    const int n = S.n, n_pad = S.n_pad, nb = S.nb;
+    const int n = S.n, n_pad = S.n_pad;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
-    float4 *pos = reinterpret_cast<float4 *>(smem);
-    double *acc = reinterpret_cast<double *>(pos + n_pad);           // [6][n_pad]
+    float4 *pos = reinterpret_cast<float4 *>(smem);                   // [2 n_pad], blocks twice
+    double *acc = reinterpret_cast<double *>(pos + 2 * n_pad);        // [6][n_pad]
     float *vel = reinterpret_cast<float *>(acc + 6 * (size_t)n_pad);  // [3][n_pad]
     int *org = reinterpret_cast<int *>(vel + 3 * (size_t)n_pad);      // [n_pad]
-    double *red = reinterpret_cast<double *>(org + n_pad + ((n_pad & 1) ? 1 : 0));
+    double *red = reinterpret_cast<double *>(org + n_pad);            // [NW]
     __shared__ double sh_scale;
+    __shared__ int sh_next;   // dynamic tile queue
 
     float *xr = x + 3 * rd.off;
     float *vr = v ? v + 3 * rd.off : nullptr;
     for (int a = tid; a < n_pad; a += WG) {
         const int o = S.perm[a];
+        float4 p;
         if (a < n) {
-            pos[a] = make_float4(xr[o], xr[n + o], xr[2 * n + o], S.charge[a]);
+            p = make_float4(xr[o], xr[n + o], xr[2 * n + o], S.charge[a]);
             vel[a] = vr ? vr[o] : 0.f;
             vel[n_pad + a] = vr ? vr[n + o] : 0.f;
             vel[2 * n_pad + a] = vr ? vr[2 * n + o] : 0.f;
         } else {
-            pos[a] = make_float4(1.0e4f + 50.f * (float)a, 1.0e4f, 1.0e4f, 0.f);
+            p = pad_position(a);
             vel[a] = vel[n_pad + a] = vel[2 * n_pad + a] = 0.f;
         }
+        pos[dup_index(a)] = p;
+        pos[dup_index(a) + 64] = p;
         org[a] = o;
 #pragma unroll
         for (int c = 0; c < 6; ++c) acc[c * n_pad + a] = 0.0;
     }
+    if (tid == 0) sh_next = NW;
     double zm = cv[(int64_t)r * CV_STRIDE + CV_ZM];
     double z_last = cv[(int64_t)r * CV_STRIDE + CV_Z];
     double eb_last = cv[(int64_t)r * CV_STRIDE + CV_EB];
     bool bad = false;
     __syncthreads();
 
-    const int ntile = nb * (nb + 1) / 2;
+    const int ntile = S.ntile;
     const double c1 = P.c1;
     for (int64_t m = 0;; ++m) {
         if (record_every > 0 && frames && (m % record_every) == 0) {
             float *fr = frames + (m / record_every) * frame_stride + 3 * rd.off;
             for (int a = tid; a < n; a += WG) {
                 const int o = org[a];
-                const float4 p = pos[a];
+                const float4 p = pos[dup_index(a)];
                 fr[o] = p.x;
                 fr[n + o] = p.y;
                 fr[2 * n + o] = p.z;
@@ -304,51 +447,40 @@ __global__ __launch_bounds__(WG) void k_rmd_persistent(
 
         // ---- pair phase: nonbonded + contact z and grad z, bonds ----------
         double zacc = 0.0;
-        for (int t = wave; t < ntile; t += NW) {
-            int I, J;
-            tile_decode(t, nb, I, J);
+        // tiles are sorted costliest first; wavefront w starts with tile w and
+        // then takes the next unclaimed one
+        for (int t = wave; t < ntile;) {
+            const int2 td = S.tiles[t];
+            const int I = td.x >> 16, J = td.x & 0xFFFF, tf = td.y;
             LaneI A;
             const int i = I * 64 + lane;
-            A.p = pos[i];
+            A.p = pos[I * 128 + lane];
+            A.qp = P.dh_pref * A.p.w;
             A.o = org[i];
             A.valid = i < n;
             A.contact = i < S.nc;
-            const int nvj = n - J * 64, ncj = S.nc - J * 64;
             float fi[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
             float fj[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
             float zt = 0.f;
-            const bool contact_tile = (I < S.ncb) && (J < S.ncb);
-            const float *rt = contact_tile ? S.ref + (int64_t)tile_index(I, J, S.ncb) * 4096 : nullptr;
-            int jo;
-            if (I == J) {
-                if (contact_tile)
-                    tile_pass<PM_RMD, true, true>(P, lane, A, pos + J * 64, org + J * 64, nvj, ncj, rt, 0, 0,
-                                                  nullptr, 0.f, fi, fj, zt, nullptr);
-                else
-                    tile_pass<PM_RMD, true, false>(P, lane, A, pos + J * 64, org + J * 64, nvj, ncj, rt, 0, 0,
-                                                   nullptr, 0.f, fi, fj, zt, nullptr);
-                jo = J * 64 + jflush_lane<true>(lane);
-            } else {
-                if (contact_tile)
-                    tile_pass<PM_RMD, false, true>(P, lane, A, pos + J * 64, org + J * 64, nvj, ncj, rt, 0, 0,
-                                                   nullptr, 0.f, fi, fj, zt, nullptr);
-                else
-                    tile_pass<PM_RMD, false, false>(P, lane, A, pos + J * 64, org + J * 64, nvj, ncj, rt, 0, 0,
-                                                    nullptr, 0.f, fi, fj, zt, nullptr);
-                jo = J * 64 + jflush_lane<false>(lane);
-            }
+            const float *rt = (tf & TF_CONTACT) ? S.ref + (int64_t)tile_index(I, J, S.ncb) * 4096 : nullptr;
+            int nxt = 0;
+            if (lane == 0) nxt = atomicAdd(&sh_next, 1);
+            tile_dispatch<PM_RMD, NBK>(tf, P, lane, A, pos + J * 128, org + J * 64, S.nc - J * 64, rt, 0, 0,
+                                       nullptr, 0.f, fi, fj, zt, nullptr);
             zacc += (double)zt;
-#pragma unroll
-            for (int c = 0; c < 6; ++c) {
+            const int jo = J * 64 + ((tf & TF_DIAG) ? jflush_lane<true>(lane) : jflush_lane<false>(lane));
+            const int ncomp = (tf & TF_CONTACT) ? 6 : 3;
+            for (int c = 0; c < ncomp; ++c) {
                 unsafeAtomicAdd(&acc[c * n_pad + i], (double)fi[c]);
                 unsafeAtomicAdd(&acc[c * n_pad + jo], (double)fj[c]);
             }
+            t = __builtin_amdgcn_readfirstlane(nxt);
         }
         for (int a = tid; a < n && P.has_bond; a += WG) {
             const int b = S.bond_next[a];
             if (b >= 0) {
                 double f[3];
-                bond_force(P, pos[a], pos[b], f);
+                bond_force(P, pos[dup_index(a)], pos[dup_index(b)], f);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     unsafeAtomicAdd(&acc[c * n_pad + a], f[c]);
@@ -362,6 +494,7 @@ __global__ __launch_bounds__(WG) void k_rmd_persistent(
 
         // ---- ratchet, eq (FrMD): z_m updated before the force is used -----
         if (tid == 0) {
+            sh_next = NW;
             double z = 0.0;
             for (int w = 0; w < NW; ++w) z += red[w];
             zm = fmin(zm, z);
@@ -386,7 +519,8 @@ __global__ __launch_bounds__(WG) void k_rmd_persistent(
             }
             double g[3];
             normals3(P, (uint32_t)org[a], P.rep_base + (uint32_t)r, step, g[0], g[1], g[2]);
-            const float4 p = pos[a];
+            const int da = dup_index(a);
+            const float4 p = pos[da];
             double X[3] = {(double)p.x, (double)p.y, (double)p.z};
             if (P.integrator == 0) {
                 const double mob = P.dt * inv_m / P.gamma;
@@ -406,14 +540,15 @@ __global__ __launch_bounds__(WG) void k_rmd_persistent(
             }
             const float4 np = make_float4((float)X[0], (float)X[1], (float)X[2], p.w);
             bad |= !(isfinite(np.x) && isfinite(np.y) && isfinite(np.z));
-            pos[a] = np;
+            pos[da] = np;
+            pos[da + 64] = np;
         }
         __syncthreads();
     }
 
     for (int a = tid; a < n; a += WG) {
         const int o = org[a];
-        const float4 p = pos[a];
+        const float4 p = pos[dup_index(a)];
         xr[o] = p.x;
         xr[n + o] = p.y;
         xr[2 * n + o] = p.z;
@@ -431,27 +566,44 @@ __global__ __launch_bounds__(WG) void k_rmd_persistent(
     }
 }
 
-hipError_t launch_persistent_rmd(int wg, const KParams &P, const SysDesc *sysd, const RepDesc *reps,
+template <int WG>
+static void launch_persistent_wg(int nbk, const KParams &P, const SysDesc *sysd, const RepDesc *reps,
+                                 const int *order, int R, size_t lds, float *x, float *v, double *cv,
+                                 int64_t n_steps, uint64_t step0, int record_every, float *frames,
+                                 int64_t frame_stride, int *flags, hipStream_t st) {
+#define SCPS_LAUNCH(K)                                                                                      \
+    hipLaunchKernelGGL((k_rmd_persistent<WG, K>), dim3(R), dim3(WG), lds, st, P, sysd, reps, order, x, v, cv, \
+                       n_steps, step0, record_every, frames, frame_stride, flags)
+    switch (nbk) {
+    case 0: SCPS_LAUNCH(0); break;
+    case 1: SCPS_LAUNCH(1); break;
+    case 2: SCPS_LAUNCH(2); break;
+    default: SCPS_LAUNCH(3); break;
+    }
+#undef SCPS_LAUNCH
+}
+
+hipError_t launch_persistent_rmd(int wg, int nbk, const KParams &P, const SysDesc *sysd, const RepDesc *reps,
                                  const int *order, int R, int n_pad_max, float *x, float *v,
                                  double *cv, int64_t n_steps, uint64_t step0, int record_every,
                                  float *frames, int64_t frame_stride, int *flags, hipStream_t st) {
     const size_t lds = persistent_lds_bytes(n_pad_max, wg);
     switch (wg) {
     case 256:
-        hipLaunchKernelGGL(k_rmd_persistent<256>, dim3(R), dim3(256), lds, st, P, sysd, reps, order, x, v,
-                           cv, n_steps, step0, record_every, frames, frame_stride, flags);
+        launch_persistent_wg<256>(nbk, P, sysd, reps, order, R, lds, x, v, cv, n_steps, step0, record_every,
+                                  frames, frame_stride, flags, st);
         break;
     case 512:
-        hipLaunchKernelGGL(k_rmd_persistent<512>, dim3(R), dim3(512), lds, st, P, sysd, reps, order, x, v,
-                           cv, n_steps, step0, record_every, frames, frame_stride, flags);
+        launch_persistent_wg<512>(nbk, P, sysd, reps, order, R, lds, x, v, cv, n_steps, step0, record_every,
+                                  frames, frame_stride, flags, st);
         break;
     case 1024:
-        hipLaunchKernelGGL(k_rmd_persistent<1024>, dim3(R), dim3(1024), lds, st, P, sysd, reps, order, x, v,
-                           cv, n_steps, step0, record_every, frames, frame_stride, flags);
+        launch_persistent_wg<1024>(nbk, P, sysd, reps, order, R, lds, x, v, cv, n_steps, step0, record_every,
+                                   frames, frame_stride, flags, st);
         break;
     default:
-        hipLaunchKernelGGL(k_rmd_persistent<64>, dim3(R), dim3(64), lds, st, P, sysd, reps, order, x, v,
-                           cv, n_steps, step0, record_every, frames, frame_stride, flags);
+        launch_persistent_wg<64>(nbk, P, sysd, reps, order, R, lds, x, v, cv, n_steps, step0, record_every,
+                                 frames, frame_stride, flags, st);
         break;
     }
     return hipGetLastError();
@@ -459,6 +611,9 @@ hipError_t launch_persistent_rmd(int wg, const KParams &P, const SysDesc *sysd, 
 
 // ---------------------------------------------------------------------------
 // per-step path: gather / pairs / finalize / integrate / scatter
+// Positions live in xs as float4 (x, y, z, charge), internal order, every
+// block of 64 stored twice (replica r at 2 poff_r); velocities in vs
+// (float4, single copy, at poff_r).
 // ---------------------------------------------------------------------------
 __global__ void k_gather(const SysDesc *__restrict__ sysd, const RepDesc *__restrict__ reps,
                          const float *__restrict__ x, const float *__restrict__ v, float4 *__restrict__ xs,
@@ -479,9 +634,11 @@ __global__ void k_gather(const SysDesc *__restrict__ sysd, const RepDesc *__rest
             q = make_float4(vr[o], vr[n + o], vr[2 * n + o], 0.f);
         }
     } else {
-        p = make_float4(1.0e4f + 50.f * (float)a, 1.0e4f, 1.0e4f, 0.f);
+        p = pad_position(a);
     }
-    xs[rd.poff + a] = p;
+    float4 *xr2 = xs + 2 * rd.poff;
+    xr2[dup_index(a)] = p;
+    xr2[dup_index(a) + 64] = p;
     if (vs) vs[rd.poff + a] = q;
 }
 
@@ -501,7 +658,7 @@ __global__ void k_scatter(const SysDesc *__restrict__ sysd, const RepDesc *__res
     if (a >= S.n) return;
     const int n = S.n;
     const int o = S.perm[a];
-    const float4 p = xs[rd.poff + a];
+    const float4 p = xs[2 * rd.poff + dup_index(a)];
     if (x) {
         float *xr = x + 3 * rd.off;
         xr[o] = p.x;
@@ -532,7 +689,7 @@ hipError_t launch_scatter(const SysDesc *sysd, const RepDesc *reps, int R, int n
 
 // One wavefront per tile item; four per workgroup.  Partial sums go to the
 // float64 accumulators in global memory with hardware float64 atomics.
-template <int MODE>
+template <int MODE, int NBK>
 __global__ __launch_bounds__(256) void k_pairs(const KParams P, const SysDesc *__restrict__ sysd,
                                                const RepDesc *__restrict__ reps,
                                                const TileItem *__restrict__ items, const int n_items,
@@ -547,21 +704,21 @@ __global__ __launch_bounds__(256) void k_pairs(const KParams P, const SysDesc *_
     const TileItem it = items[item];
     const RepDesc rd = reps[it.rep];
     const SysDesc S = sysd[rd.sys];
-    const int I = it.I, J = it.J;
+    const int I = it.I, J = it.J, tf = it.flags;
     const int n = S.n, n_pad = S.n_pad;
-    const float4 *xr = xs + rd.poff;
+    const float4 *xr2 = xs + 2 * rd.poff;
     LaneI A;
     const int i = I * 64 + lane;
-    A.p = xr[i];
+    A.p = xr2[I * 128 + lane];
+    A.qp = P.dh_pref * A.p.w;
     A.o = S.perm[i];
     A.valid = i < n;
     A.contact = i < S.nc;
-    const int nvj = n - J * 64, ncj = S.nc - J * 64;
     float fi[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     float fj[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     float zt = 0.f;
     float dk[KMAX];
-    const bool contact_tile = (I < S.ncb) && (J < S.ncb);
+    const bool contact_tile = tf & TF_CONTACT;
     const int64_t toff = contact_tile ? (int64_t)tile_index(I, J, S.ncb) * 4096 : 0;
     const float *rt;
     int64_t kstride = 0;
@@ -585,22 +742,9 @@ __global__ __launch_bounds__(256) void k_pairs(const KParams P, const SysDesc *_
     if constexpr (!T::nb) {
         if (!contact_tile) return;
     }
-    const float4 *pj = xr + J * 64;
-    const int *oj = S.perm + J * 64;
-    int jo;
-    if (I == J) {
-        if (contact_tile)
-            tile_pass<MODE, true, true>(P, lane, A, pj, oj, nvj, ncj, rt, kstride, K, ck, cs, fi, fj, zt, dk);
-        else
-            tile_pass<MODE, true, false>(P, lane, A, pj, oj, nvj, ncj, rt, kstride, K, ck, cs, fi, fj, zt, dk);
-        jo = J * 64 + jflush_lane<true>(lane);
-    } else {
-        if (contact_tile)
-            tile_pass<MODE, false, true>(P, lane, A, pj, oj, nvj, ncj, rt, kstride, K, ck, cs, fi, fj, zt, dk);
-        else
-            tile_pass<MODE, false, false>(P, lane, A, pj, oj, nvj, ncj, rt, kstride, K, ck, cs, fi, fj, zt, dk);
-        jo = J * 64 + jflush_lane<false>(lane);
-    }
+    tile_dispatch<MODE, NBK>(tf, P, lane, A, xr2 + J * 128, S.perm + J * 64, S.nc - J * 64, rt, kstride, K, ck,
+                             cs, fi, fj, zt, dk);
+    const int jo = J * 64 + ((tf & TF_DIAG) ? jflush_lane<true>(lane) : jflush_lane<false>(lane));
     double *ar = acc + 6 * rd.poff;
     if constexpr (T::nb) {
 #pragma unroll
@@ -609,11 +753,11 @@ __global__ __launch_bounds__(256) void k_pairs(const KParams P, const SysDesc *_
             unsafeAtomicAdd(&ar[c * n_pad + jo], (double)fj[c]);
         }
         // bonds of the particles of block I, once per block (diagonal tile)
-        if (I == J && A.valid && P.has_bond) {
+        if ((tf & TF_DIAG) && A.valid && P.has_bond) {
             const int b = S.bond_next[i];
             if (b >= 0) {
                 double f[3];
-                bond_force(P, A.p, xr[b], f);
+                bond_force(P, A.p, xr2[dup_index(b)], f);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     unsafeAtomicAdd(&ar[c * n_pad + i], f[c]);
@@ -646,31 +790,52 @@ __global__ __launch_bounds__(256) void k_pairs(const KParams P, const SysDesc *_
     }
 }
 
-hipError_t launch_pairs(int mode, const KParams &P, const SysDesc *sysd, const RepDesc *reps,
+template <int MODE>
+static void launch_pairs_mode(int nbk, dim3 grid, dim3 block, hipStream_t st, const KParams &P,
+                              const SysDesc *sysd, const RepDesc *reps, const TileItem *items, int n_items,
+                              const float4 *xs, double *acc, double *zbuf, double *dsum, const float *coef,
+                              const double *csum, int kmax) {
+#define SCPS_LAUNCH(K)                                                                                   \
+    hipLaunchKernelGGL((k_pairs<MODE, K>), grid, block, 0, st, P, sysd, reps, items, n_items, xs, acc, zbuf, \
+                       dsum, coef, csum, kmax)
+    if constexpr (!ModeTraits<MODE>::nb) {
+        SCPS_LAUNCH(0);
+    } else {
+        switch (nbk) {
+        case 0: SCPS_LAUNCH(0); break;
+        case 1: SCPS_LAUNCH(1); break;
+        case 2: SCPS_LAUNCH(2); break;
+        default: SCPS_LAUNCH(3); break;
+        }
+    }
+#undef SCPS_LAUNCH
+}
+
+hipError_t launch_pairs(int mode, int nbk, const KParams &P, const SysDesc *sysd, const RepDesc *reps,
                         const TileItem *items, int n_items, const float4 *xs, double *acc, double *zbuf,
                         double *dsum, const float *coef, const double *csum, int kmax, hipStream_t st) {
     if (n_items == 0) return hipSuccess;
     const dim3 grid((n_items + 3) / 4), block(256);
     switch (mode) {
     case PM_RMD:
-        hipLaunchKernelGGL(k_pairs<PM_RMD>, grid, block, 0, st, P, sysd, reps, items, n_items, xs, acc, zbuf,
-                           dsum, coef, csum, kmax);
+        launch_pairs_mode<PM_RMD>(nbk, grid, block, st, P, sysd, reps, items, n_items, xs, acc, zbuf, dsum, coef,
+                                  csum, kmax);
         break;
     case PM_Z:
-        hipLaunchKernelGGL(k_pairs<PM_Z>, grid, block, 0, st, P, sysd, reps, items, n_items, xs, acc, zbuf,
-                           dsum, coef, csum, kmax);
+        launch_pairs_mode<PM_Z>(nbk, grid, block, st, P, sysd, reps, items, n_items, xs, acc, zbuf, dsum, coef,
+                                csum, kmax);
         break;
     case PM_ZG:
-        hipLaunchKernelGGL(k_pairs<PM_ZG>, grid, block, 0, st, P, sysd, reps, items, n_items, xs, acc, zbuf,
-                           dsum, coef, csum, kmax);
+        launch_pairs_mode<PM_ZG>(nbk, grid, block, st, P, sysd, reps, items, n_items, xs, acc, zbuf, dsum, coef,
+                                 csum, kmax);
         break;
     case PM_SCPS1:
-        hipLaunchKernelGGL(k_pairs<PM_SCPS1>, grid, block, 0, st, P, sysd, reps, items, n_items, xs, acc, zbuf,
-                           dsum, coef, csum, kmax);
+        launch_pairs_mode<PM_SCPS1>(nbk, grid, block, st, P, sysd, reps, items, n_items, xs, acc, zbuf, dsum,
+                                    coef, csum, kmax);
         break;
     default:
-        hipLaunchKernelGGL(k_pairs<PM_SCPS2>, grid, block, 0, st, P, sysd, reps, items, n_items, xs, acc, zbuf,
-                           dsum, coef, csum, kmax);
+        launch_pairs_mode<PM_SCPS2>(nbk, grid, block, st, P, sysd, reps, items, n_items, xs, acc, zbuf, dsum,
+                                    coef, csum, kmax);
         break;
     }
     return hipGetLastError();
@@ -780,7 +945,9 @@ __global__ void k_integrate(const KParams P, const SysDesc *__restrict__ sysd, c
     }
     double g[3];
     normals3(P, (uint32_t)S.perm[a], P.rep_base + (uint32_t)r, step, g[0], g[1], g[2]);
-    const float4 p = xs[rd.poff + a];
+    float4 *xr2 = xs + 2 * rd.poff;
+    const int da = dup_index(a);
+    const float4 p = xr2[da];
     double X[3] = {(double)p.x, (double)p.y, (double)p.z};
     const double inv_m = 1.0 / (double)S.mass[a];
     if (P.integrator == 0) {
@@ -803,7 +970,8 @@ __global__ void k_integrate(const KParams P, const SysDesc *__restrict__ sysd, c
     }
     const float4 np = make_float4((float)X[0], (float)X[1], (float)X[2], p.w);
     if (!(isfinite(np.x) && isfinite(np.y) && isfinite(np.z))) flags[r] = 1;
-    xs[rd.poff + a] = np;
+    xr2[da] = np;
+    xr2[da + 64] = np;
 }
 
 hipError_t launch_integrate(const KParams &P, const SysDesc *sysd, const RepDesc *reps, int R, int n_pad_max,

@@ -233,7 +233,9 @@ def test_noise_matches_oracle_philox(S, exec_mode):
     got = host(x).reshape(R, 3, n)
     for r in range(R):
         want = O.normals(p["seed"], np.arange(n), 7 + r, step).T
-        np.testing.assert_allclose(got[r], want, rtol=3e-7, atol=3e-7)
+        # same Philox words and uniforms; Box-Muller in float32 on the GPU
+        # (a few ulp of |xi| <= ~5.5) against float64 in the oracle
+        np.testing.assert_allclose(got[r], want, rtol=1e-6, atol=1e-6)
 
 
 # ---------------------------------------------------------------------------
