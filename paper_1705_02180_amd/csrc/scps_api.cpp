@@ -222,15 +222,40 @@ double tile_cost(int f) {
     return c;
 }
 
-// The persistent kernel's tile list: every tile pair of the system, costliest
-// first.  Its wavefronts claim tiles dynamically in this order.
+// The persistent kernel's work list, costliest first; its wavefronts claim
+// entries dynamically in this order.  Off-diagonal tiles (I1, J), (I2, J) of
+// the same class (contact, mask) are paired; every tile or pair is cut into
+// segments of SEG_STEPS sub-steps (see SEG_STEPS for the encoding).
 void build_schedule(SysHost &h) {
     std::vector<std::pair<double, int2>> all;
-    for (int I = 0; I < h.nb; ++I)
-        for (int J = I; J < h.nb; ++J) {
+    auto push = [&](int I1, int I2, int J, int f, double cost) {
+        const int kb = (f & TILE_DIAG) ? 1 : 0, ke = (f & TILE_DIAG) ? 33 : 64;
+        for (int k = kb; k < ke; k += SEG_STEPS)
+            all.push_back({cost * std::min(SEG_STEPS, ke - k) / 64.0,
+                           make_int2((I1 << 16) | J, f | ((I2 + 1) << 8) | (k << 24))});
+    };
+    for (int J = 0; J < h.nb; ++J) {
+        std::vector<int> waiting(8, -1);   // per class, an unpaired row I
+        for (int I = 0; I <= J; ++I) {
             const int f = h.tile_flags[(size_t)I * h.nb + J];
-            all.push_back({tile_cost(f), make_int2((I << 16) | J, f)});
+            if (I == J) {
+                push(I, -1, J, f, 2.0 * tile_cost(f));   // half the sub-steps, same cost per sub-step
+                continue;
+            }
+            const int cls = f & (TILE_CONTACT | TILE_MASK);
+            if (waiting[cls] < 0) {
+                waiting[cls] = I;
+            } else {
+                push(waiting[cls], I, J, f, 2.0 * tile_cost(f));
+                waiting[cls] = -1;
+            }
         }
+        for (int cls = 0; cls < 8; ++cls)
+            if (waiting[cls] >= 0) {
+                const int f = h.tile_flags[(size_t)waiting[cls] * h.nb + J];
+                push(waiting[cls], -1, J, f, tile_cost(f));
+            }
+    }
     std::stable_sort(all.begin(), all.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
     h.sched.clear();
     for (const auto &t : all) h.sched.push_back(t.second);

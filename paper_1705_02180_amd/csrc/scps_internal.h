@@ -46,7 +46,7 @@ struct SysDesc {
     const float *charge;     // [n_pad] internal order (pads: 0)
     const float *ref;        // native map tiles [ntile_c][64*64]
     const float *stack;      // SCPS frames [K][ntile_c][64*64]
-    const int2 *tiles;       // every tile pair, costliest first: {I << 16 | J, flags}
+    const int2 *tiles;       // persistent work list, costliest first (see build_schedule)
     int ntile;
     int pad1;
     double Z0;
@@ -70,6 +70,14 @@ struct TileItem {
 // does (a block that straddles the end of the contact set, a pair within
 // min_seq_sep, or a contact cutoff).
 enum { TILE_DIAG = 1, TILE_CONTACT = 2, TILE_MASK = 4 };
+
+// The persistent kernel's work items are segments of SEG_STEPS sub-steps of a
+// tile (or of two tiles that share the J block): {I1 << 16 | J,
+// flags | (I2 + 1) << 8 | k_begin << 24}, I2 = -1 for a single tile.
+#ifndef SCPS_SEG_STEPS
+#define SCPS_SEG_STEPS 32
+#endif
+constexpr int SEG_STEPS = SCPS_SEG_STEPS;
 
 // Contact tile pairs (I <= J < ncb) are numbered row by row.
 __host__ __device__ inline int tile_index(int I, int J, int ncb) {

@@ -26,6 +26,9 @@
 #ifndef SCPS_PAIR_GROUP
 #define SCPS_PAIR_GROUP 4
 #endif
+#ifndef SCPS_PAIR_GROUP2
+#define SCPS_PAIR_GROUP2 2
+#endif
 
 namespace scps {
 
@@ -113,14 +116,6 @@ struct LaneI {
     bool valid;   // i < n
     bool contact; // i in the contact set
 };
-
-// After a tile pass the j-side partials have rotated once per sub-step, so
-// lane l holds particle (l + 33) mod 64 (diagonal tile: 32 sub-steps from
-// k = 1) or l (64 sub-steps) of block J.
-template <bool DIAG>
-__device__ __forceinline__ int jflush_lane(int lane) {
-    return (lane + (DIAG ? 33 : 64)) & 63;
-}
 
 // Squared distance of a pair, and the vector d = x_i - x_j.
 __device__ __forceinline__ float pair_r2(const float4 &pi, const float4 &pj, float &dx, float &dy, float &dz) {
@@ -263,6 +258,125 @@ __device__ __forceinline__ void pair_group(const KParams &P, const int lane, con
     }
 }
 
+// Two off-diagonal tiles (I1, J) and (I2, J) in one pass: lane l holds
+// particle l of blocks I1 (A) and I2 (B); at sub-step k both meet the same j,
+// so their j-side terms share one register and one rotation, and the j
+// position is read once.  Sub-steps k0 .. k0+U-1.
+template <int MODE, bool CONTACT, bool MASK, int NBK, int U>
+__device__ __forceinline__ void pair_group2(const KParams &P, const int lane, const int k0, const LaneI &A,
+                                            const LaneI &B, const float4 *__restrict__ posj2,
+                                            const int *__restrict__ orgj, const int ncj,
+                                            const float *__restrict__ rtA, const float *__restrict__ rtB,
+                                            float fa[6], float fb[6], float fj[6], float &zt) {
+    using T = ModeTraits<MODE>;
+    static_assert(MODE != PM_SCPS1 && MODE != PM_SCPS2, "double tiles are for the rMD and z modes");
+    float dxa[U], dya[U], dza[U], fA[U], gA[U];
+    float dxb[U], dyb[U], dzb[U], fB[U], gB[U];
+    float r2a[U], r2b[U];
+    bool nba[U], nbb[U], ca[U], cb[U], ina[U], inb[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int k = k0 + u;
+        const float4 pj = posj2[lane + k];
+        r2a[u] = pair_r2(A.p, pj, dxa[u], dya[u], dza[u]);
+        r2b[u] = pair_r2(B.p, pj, dxb[u], dyb[u], dzb[u]);
+        nba[u] = nbb[u] = ca[u] = cb[u] = ina[u] = inb[u] = true;
+        if constexpr (MASK) {
+            const int jl = (lane + k) & 63;
+            const int oj = orgj[jl];
+            const int sa = abs(A.o - oj), sb = abs(B.o - oj);
+            nba[u] = sa > P.nb_excl;
+            nbb[u] = sb > P.nb_excl;
+            ca[u] = A.contact & (jl < ncj) & (sa > P.min_sep);
+            cb[u] = B.contact & (jl < ncj) & (sb > P.min_sep);
+            ina[u] = !P.has_cut | (r2a[u] <= P.r_cut2);
+            inb[u] = !P.has_cut | (r2b[u] <= P.r_cut2);
+        }
+        fA[u] = fB[u] = 0.f;
+        if constexpr (T::nb && NBK != 0) {
+            const float xa = nb_scalar<NBK>(P, r2a[u], A.qp, pj.w);
+            const float xb = nb_scalar<NBK>(P, r2b[u], B.qp, pj.w);
+            fA[u] = nba[u] ? xa : 0.f;
+            fB[u] = nbb[u] ? xb : 0.f;
+        }
+    }
+    if constexpr (CONTACT) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = k0 + u;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const float r2 = h ? r2b[u] : r2a[u];
+                const float q = r2 * P.inv_r0sq;
+                const float q2 = q * q;
+                const float num = 1.f + q + q2;
+                const float den = fmaf(q2, q + q2, num);
+                const float inv_den = (h ? inb[u] : ina[u]) ? frcp(den) : 0.f;
+                float diff = num * inv_den - ldg(h ? rtB : rtA, k * 64 + lane);
+                diff = (h ? cb[u] : ca[u]) ? diff : 0.f;
+                if constexpr (T::z) zt = fmaf(diff, diff, zt);
+                if constexpr (T::grad) {
+                    const float poly = fmaf(q, fmaf(q, fmaf(q, P.cp[0], P.cp[1]), P.cp[2]), P.cp[3]);
+                    const float g = (diff * (q2 * inv_den)) * (poly * inv_den);
+                    if (h) gB[u] = g; else gA[u] = g;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        if constexpr (T::nb && NBK != 0) {
+            fa[0] = fmaf(fA[u], dxa[u], fa[0]);
+            fa[1] = fmaf(fA[u], dya[u], fa[1]);
+            fa[2] = fmaf(fA[u], dza[u], fa[2]);
+            fb[0] = fmaf(fB[u], dxb[u], fb[0]);
+            fb[1] = fmaf(fB[u], dyb[u], fb[1]);
+            fb[2] = fmaf(fB[u], dzb[u], fb[2]);
+            fj[0] = rot1(fmaf(-fB[u], dxb[u], fmaf(-fA[u], dxa[u], fj[0])));
+            fj[1] = rot1(fmaf(-fB[u], dyb[u], fmaf(-fA[u], dya[u], fj[1])));
+            fj[2] = rot1(fmaf(-fB[u], dzb[u], fmaf(-fA[u], dza[u], fj[2])));
+        }
+        if constexpr (T::grad && CONTACT) {
+            fa[3] = fmaf(gA[u], dxa[u], fa[3]);
+            fa[4] = fmaf(gA[u], dya[u], fa[4]);
+            fa[5] = fmaf(gA[u], dza[u], fa[5]);
+            fb[3] = fmaf(gB[u], dxb[u], fb[3]);
+            fb[4] = fmaf(gB[u], dyb[u], fb[4]);
+            fb[5] = fmaf(gB[u], dzb[u], fb[5]);
+            fj[3] = rot1(fmaf(-gB[u], dxb[u], fmaf(-gA[u], dxa[u], fj[3])));
+            fj[4] = rot1(fmaf(-gB[u], dyb[u], fmaf(-gA[u], dya[u], fj[4])));
+            fj[5] = rot1(fmaf(-gB[u], dzb[u], fmaf(-gA[u], dza[u], fj[5])));
+        }
+    }
+}
+
+template <int MODE, bool CONTACT, bool MASK, int NBK>
+__device__ __forceinline__ void tile_pass2(const KParams &P, const int lane, const int kb, const int ke,
+                                           const LaneI &A, const LaneI &B, const float4 *__restrict__ posj2,
+                                           const int *__restrict__ orgj, const int ncj,
+                                           const float *__restrict__ rtA, const float *__restrict__ rtB, float fa[6],
+                                           float fb[6], float fj[6], float &zt) {
+    constexpr int U = SCPS_PAIR_GROUP2;
+#pragma unroll 1
+    for (int k0 = kb; k0 < ke; k0 += U)
+        pair_group2<MODE, CONTACT, MASK, NBK, U>(P, lane, k0, A, B, posj2, orgj, ncj, rtA, rtB, fa, fb, fj, zt);
+}
+
+template <int MODE, int NBK>
+__device__ __forceinline__ void tile_dispatch2(const int flags, const int kb, const int ke, const KParams &P,
+                                               const int lane, const LaneI &A, const LaneI &B,
+                                               const float4 *__restrict__ posj2, const int *__restrict__ orgj,
+                                               const int ncj, const float *__restrict__ rtA,
+                                               const float *__restrict__ rtB, float fa[6], float fb[6], float fj[6],
+                                               float &zt) {
+#define SCPS_TILE2(C, M)                                                                                     \
+    tile_pass2<MODE, C, M, NBK>(P, lane, kb, ke, A, B, posj2, orgj, ncj, rtA, rtB, fa, fb, fj, zt)
+    const bool con = flags & TILE_CONTACT, mask = flags & TILE_MASK;
+    if (con) { if (mask) SCPS_TILE2(true, true); else SCPS_TILE2(true, false); }
+    else     { if (mask) SCPS_TILE2(false, true); else SCPS_TILE2(false, false); }
+#undef SCPS_TILE2
+}
+
 // Pair evaluations grouped per sub-step batch: more independent work per
 // wavefront for the modes with few registers per pair.
 template <int MODE> constexpr int group_width() {
@@ -274,37 +388,40 @@ template <int MODE> constexpr int group_width() {
 // (l + 33) mod 64 for a diagonal tile and l otherwise; zt: this lane's z
 // partial; dk[0..K): squared distances to every frame (SCPS pass 1).
 template <int MODE, bool DIAG, bool CONTACT, bool MASK, int NBK>
-__device__ __forceinline__ void tile_pass(const KParams &P, const int lane, const LaneI &A,
-                                          const float4 *__restrict__ posj2, const int *__restrict__ orgj,
-                                          const int ncj, const float *__restrict__ rt, const int64_t kstride,
-                                          const int K, const float *__restrict__ ck, const float csum, float fi[6],
-                                          float fj[6], float &zt, float *dk) {
+__device__ __forceinline__ void tile_pass(const KParams &P, const int lane, const int kb, const int ke,
+                                          const LaneI &A, const float4 *__restrict__ posj2,
+                                          const int *__restrict__ orgj, const int ncj, const float *__restrict__ rt,
+                                          const int64_t kstride, const int K, const float *__restrict__ ck,
+                                          const float csum, float fi[6], float fj[6], float &zt, float *dk) {
     constexpr int U = group_width<MODE>();
     const bool low = lane < 32;
-    if constexpr (DIAG) {
 #pragma unroll 1
-        for (int k0 = 1; k0 <= 32; k0 += U)
-            pair_group<MODE, true, CONTACT, MASK, NBK, U>(P, lane, k0, low, A, posj2, orgj, ncj, rt, kstride, K, ck,
-                                                          csum, fi, fj, zt, dk);
-    } else {
-#pragma unroll 1
-        for (int k0 = 0; k0 < 64; k0 += U)
-            pair_group<MODE, false, CONTACT, MASK, NBK, U>(P, lane, k0, low, A, posj2, orgj, ncj, rt, kstride, K,
-                                                           ck, csum, fi, fj, zt, dk);
-    }
+    for (int k0 = kb; k0 < ke; k0 += U)
+        pair_group<MODE, DIAG, CONTACT, MASK, NBK, U>(P, lane, k0, low, A, posj2, orgj, ncj, rt, kstride, K, ck,
+                                                      csum, fi, fj, zt, dk);
 }
+
+// Sub-step range of a whole tile: 1..32 on a diagonal tile (lanes 0..31 only
+// at k = 32), 0..63 otherwise.
+__device__ __forceinline__ int tile_kbeg(bool diag) { return diag ? 1 : 0; }
+__device__ __forceinline__ int tile_kend(bool diag) { return diag ? 33 : 64; }
+
+// After sub-steps kb .. ke-1 the j-side partials have rotated ke - kb times:
+// lane l holds particle (l + ke) mod 64 of block J.
+__device__ __forceinline__ int jflush_at(int lane, int ke) { return (lane + ke) & 63; }
 
 // Dispatch on the tile's flags (uniform across the wavefront).
 enum { TF_DIAG = TILE_DIAG, TF_CONTACT = TILE_CONTACT, TF_MASK = TILE_MASK };
 
 template <int MODE, int NBK>
-__device__ __forceinline__ void tile_dispatch(const int flags, const KParams &P, const int lane, const LaneI &A,
+__device__ __forceinline__ void tile_dispatch(const int flags, const int kb, const int ke, const KParams &P,
+                                              const int lane, const LaneI &A,
                                               const float4 *__restrict__ posj2, const int *__restrict__ orgj,
                                               const int ncj, const float *__restrict__ rt, const int64_t kstride,
                                               const int K, const float *__restrict__ ck, const float csum,
                                               float fi[6], float fj[6], float &zt, float *dk) {
 #define SCPS_TILE(D, C, M)                                                                                  \
-    tile_pass<MODE, D, C, M, NBK>(P, lane, A, posj2, orgj, ncj, rt, kstride, K, ck, csum, fi, fj, zt, dk)
+    tile_pass<MODE, D, C, M, NBK>(P, lane, kb, ke, A, posj2, orgj, ncj, rt, kstride, K, ck, csum, fi, fj, zt, dk)
     const bool diag = flags & TF_DIAG, con = flags & TF_CONTACT, mask = flags & TF_MASK;
     if (ModeTraits<MODE>::nb) {
         if (diag) {
@@ -451,7 +568,43 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WG / 256 > 0
         // then takes the next unclaimed one
         for (int t = wave; t < ntile;) {
             const int2 td = S.tiles[t];
-            const int I = td.x >> 16, J = td.x & 0xFFFF, tf = td.y;
+            const int I = td.x >> 16, J = td.x & 0xFFFF, tf = td.y & 0xFF, I2 = ((td.y >> 8) & 0xFFFF) - 1;
+            const int kb = (td.y >> 24) & 63, ke = min(kb + SEG_STEPS, tile_kend(tf & TF_DIAG));
+            if (I2 >= 0) {
+                // two off-diagonal tiles (I, J) and (I2, J) of the same class
+                LaneI A, B;
+                A.p = pos[I * 128 + lane];
+                B.p = pos[I2 * 128 + lane];
+                A.qp = P.dh_pref * A.p.w;
+                B.qp = P.dh_pref * B.p.w;
+                A.o = org[I * 64 + lane];
+                B.o = org[I2 * 64 + lane];
+                A.valid = I * 64 + lane < n;
+                B.valid = I2 * 64 + lane < n;
+                A.contact = I * 64 + lane < S.nc;
+                B.contact = I2 * 64 + lane < S.nc;
+                float fa[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                float fb[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                float fj[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                float zt = 0.f;
+                const bool con = tf & TF_CONTACT;
+                const float *rtA = con ? S.ref + (int64_t)tile_index(I, J, S.ncb) * 4096 : nullptr;
+                const float *rtB = con ? S.ref + (int64_t)tile_index(I2, J, S.ncb) * 4096 : nullptr;
+                int nxt = 0;
+                if (lane == 0) nxt = atomicAdd(&sh_next, 1);
+                tile_dispatch2<PM_RMD, NBK>(tf, kb, ke, P, lane, A, B, pos + J * 128, org + J * 64, S.nc - J * 64,
+                                            rtA, rtB, fa, fb, fj, zt);
+                zacc += (double)zt;
+                const int ncomp = con ? 6 : 3;
+                const int jo = J * 64 + jflush_at(lane, ke);
+                for (int c = 0; c < ncomp; ++c) {
+                    unsafeAtomicAdd(&acc[c * n_pad + I * 64 + lane], (double)fa[c]);
+                    unsafeAtomicAdd(&acc[c * n_pad + I2 * 64 + lane], (double)fb[c]);
+                    unsafeAtomicAdd(&acc[c * n_pad + jo], (double)fj[c]);
+                }
+                t = __builtin_amdgcn_readfirstlane(nxt);
+                continue;
+            }
             LaneI A;
             const int i = I * 64 + lane;
             A.p = pos[I * 128 + lane];
@@ -465,10 +618,10 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WG / 256 > 0
             const float *rt = (tf & TF_CONTACT) ? S.ref + (int64_t)tile_index(I, J, S.ncb) * 4096 : nullptr;
             int nxt = 0;
             if (lane == 0) nxt = atomicAdd(&sh_next, 1);
-            tile_dispatch<PM_RMD, NBK>(tf, P, lane, A, pos + J * 128, org + J * 64, S.nc - J * 64, rt, 0, 0,
-                                       nullptr, 0.f, fi, fj, zt, nullptr);
+            tile_dispatch<PM_RMD, NBK>(tf, kb, ke, P, lane, A, pos + J * 128, org + J * 64, S.nc - J * 64, rt, 0,
+                                       0, nullptr, 0.f, fi, fj, zt, nullptr);
             zacc += (double)zt;
-            const int jo = J * 64 + ((tf & TF_DIAG) ? jflush_lane<true>(lane) : jflush_lane<false>(lane));
+            const int jo = J * 64 + jflush_at(lane, ke);
             const int ncomp = (tf & TF_CONTACT) ? 6 : 3;
             for (int c = 0; c < ncomp; ++c) {
                 unsafeAtomicAdd(&acc[c * n_pad + i], (double)fi[c]);
@@ -742,9 +895,11 @@ __global__ __launch_bounds__(256) void k_pairs(const KParams P, const SysDesc *_
     if constexpr (!T::nb) {
         if (!contact_tile) return;
     }
-    tile_dispatch<MODE, NBK>(tf, P, lane, A, xr2 + J * 128, S.perm + J * 64, S.nc - J * 64, rt, kstride, K, ck,
-                             cs, fi, fj, zt, dk);
-    const int jo = J * 64 + ((tf & TF_DIAG) ? jflush_lane<true>(lane) : jflush_lane<false>(lane));
+    const bool diag = tf & TF_DIAG;
+    const int kb = tile_kbeg(diag), ke = tile_kend(diag);
+    tile_dispatch<MODE, NBK>(tf, kb, ke, P, lane, A, xr2 + J * 128, S.perm + J * 64, S.nc - J * 64, rt, kstride, K,
+                             ck, cs, fi, fj, zt, dk);
+    const int jo = J * 64 + jflush_at(lane, ke);
     double *ar = acc + 6 * rd.poff;
     if constexpr (T::nb) {
 #pragma unroll
