@@ -37,7 +37,7 @@ def parse():
     ap.add_argument("--replicas", type=int, default=256)
     ap.add_argument("--plain-replicas", type=int, default=8)
     ap.add_argument("--plain-steps", type=int, default=20)
-    ap.add_argument("--cpu-steps", type=int, default=100)
+    ap.add_argument("--cpu-steps", type=int, default=300)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
