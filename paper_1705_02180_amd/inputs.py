@@ -60,31 +60,44 @@ def _backbite(path: np.ndarray, dims: np.ndarray, n_moves: int,
     If the neighbour is inside the box and is not the end's own path
     neighbour, the bond end-neighbour is added and the path is re-opened
     next to it, which reverses a prefix (or suffix) of the path.  Every
-    site stays visited exactly once.
+    site stays visited exactly once.  Sites are handled as integer ids of
+    the box with a precomputed neighbour table.
     """
-    path = path.copy()
     n = len(path)
-    index = np.empty(tuple(int(d) for d in dims), dtype=np.int64)
-    index[path[:, 0], path[:, 1], path[:, 2]] = np.arange(n)
+    L0, L1, L2 = (int(d) for d in dims)
+    sid = (path[:, 0] * L1 + path[:, 1]) * L2 + path[:, 2]
+    nsite = L0 * L1 * L2
+    index = np.full(nsite, -1, dtype=np.int64)
+    index[sid] = np.arange(n)
+    g = np.arange(nsite)
+    cx, cy, cz = g // (L1 * L2), (g // L2) % L1, g % L2
+    neigh = np.full((nsite, 6), -1, dtype=np.int64)
+    for k, (dx, dy, dz) in enumerate(_NEIGH):
+        x, y, z = cx + dx, cy + dy, cz + dz
+        inside = (x >= 0) & (x < L0) & (y >= 0) & (y < L1) & (z >= 0) & (z < L2)
+        neigh[inside, k] = ((x * L1 + y) * L2 + z)[inside]
+    neigh = neigh.tolist()
     ends = rng.random(n_moves) < 0.5
     dirs = rng.integers(6, size=n_moves)
-    for end_first, dk in zip(ends, dirs):
+    for end_first, dk in zip(ends.tolist(), dirs.tolist()):
         e = 0 if end_first else n - 1
-        u = path[e] + _NEIGH[dk]
-        if (u < 0).any() or (u >= dims).any():
+        u = neigh[int(sid[e])][dk]
+        if u < 0:
             continue
-        j = int(index[u[0], u[1], u[2]])
+        j = int(index[u])
         if end_first:
             if j <= 1:
                 continue
-            path[:j] = path[:j][::-1].copy()
-            index[path[:j, 0], path[:j, 1], path[:j, 2]] = np.arange(j)
+            seg = sid[:j][::-1].copy()
+            sid[:j] = seg
+            index[seg] = np.arange(j)
         else:
             if j >= n - 2:
                 continue
-            path[j + 1:] = path[j + 1:][::-1].copy()
-            index[path[j + 1:, 0], path[j + 1:, 1], path[j + 1:, 2]] = np.arange(j + 1, n)
-    return path
+            seg = sid[j + 1:][::-1].copy()
+            sid[j + 1:] = seg
+            index[seg] = np.arange(j + 1, n)
+    return np.stack([sid // (L1 * L2), (sid // L2) % L1, sid % L2], axis=1)
 
 
 def compact_native(n: int, seed: int) -> np.ndarray:
@@ -119,22 +132,25 @@ def persistent_start(n: int, seed: int, persistence: float = 10.0,
     """
     rng = np.random.default_rng(seed)
     p_turn = 1.0 / persistence
+    steps = [tuple(int(c) for c in row) for row in _NEIGH]
     while True:
-        pos = [np.zeros(3, dtype=np.int64)]
-        occ = {(0, 0, 0)}
-        d = _NEIGH[rng.integers(6)]
+        cur = (0, 0, 0)
+        pos = [cur]
+        occ = {cur}
+        d = steps[int(rng.integers(6))]
         ok = True
         for _ in range(n - 1):
             cand = []
             if rng.random() >= p_turn:
                 cand.append(d)
-            order = rng.permutation(6)
-            cand += [_NEIGH[k] for k in order if not np.array_equal(_NEIGH[k], -d)]
+            back = (-d[0], -d[1], -d[2])
+            cand += [steps[k] for k in rng.permutation(6).tolist() if steps[k] != back]
             for c in cand:
-                nxt = pos[-1] + c
-                if tuple(nxt) not in occ:
+                nxt = (cur[0] + c[0], cur[1] + c[1], cur[2] + c[2])
+                if nxt not in occ:
                     pos.append(nxt)
-                    occ.add(tuple(nxt))
+                    occ.add(nxt)
+                    cur = nxt
                     d = c
                     break
             else:
