@@ -1,16 +1,22 @@
-"""Throughput of batched rMD stepping on one MI355X.
+"""Throughput of batched rMD / SCPS stepping on one MI355X.
 
-Workload: 256 replicas of a 560-particle chain (35 groups of 16, contacts over
-the 280 heavy particles: 39,060 contact pairs, 155,403 nonbonded pairs),
-Lennard-Jones + Debye-Hueckel, BAOAB at dt = 2 fs, T = 300 K, ratchet on z.
-One benchmark step = one scps_step_replicas call that advances every replica
-by --block Langevin steps (one persistent kernel launch).  Inputs are seeded
-and synthetic and resident in HBM before timing starts.
+Default workload (the headline line): 256 replicas of a 560-particle chain
+(35 groups of 16, contacts over the 280 heavy particles: 39,060 contact pairs,
+155,403 nonbonded pairs), Lennard-Jones + Debye-Hueckel, BAOAB at dt = 2 fs,
+T = 300 K, ratchet on z.  One benchmark step = one scps_step_replicas call that
+advances every replica by --block Langevin steps (one persistent kernel
+launch).  Inputs are seeded and synthetic and resident in HBM before timing.
 
-Printed: one JSON line with replica-steps/s (value), contact-pair evals/s,
-the plain one-replica-per-launch form on the same GPU, the roofline of the
-stepping kernel (algorithmic FP32 work / HIP-event time of each launch) and
-the FP64 CPU oracle timed on this host.
+Other workloads (--workload), each printed as its own JSON line:
+  uneven512     512 chains, N ~ U{200..3000}, each with its own native map
+  autograd3000  z and E_b forward + backward for 64 chains of 3000 particles
+  scps6000      32 replicas of a 6000-particle chain: the ensemble mean of
+                51 recorded frames over 32 paths, then SCPS-biased stepping
+
+Printed: replica-steps/s (value), contact-pair evals/s, the plain
+one-replica-per-launch form (headline workload), the roofline of the timed
+launch (algorithmic FP32 work / HIP-event time of each launch) and the FP64
+CPU oracle timed on this host on a bounded sample of the same workload.
 """
 import argparse
 import json
@@ -22,19 +28,34 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "replica-steps/s & contact-pair evals/s, batched vs plain, 1 MI355X, 1e-5 rel"
-# algorithmic FP32 flops per unordered pair (an FMA counts 2; rcp, rsqrt, exp count 1)
-FLOPS_CONTACT = 43      # C(q), C'(q), (C-R)^2 and both gradient sides
-FLOPS_NONBONDED = 40    # Lennard-Jones 12-6 + Debye-Hueckel and both force sides
+# Algorithmic FP32 flops (an FMA counts 2; rcp, rsqrt, exp count 1):
+FLOPS_CONTACT = 43      # contact pair: geometry 8, C(q) 10, C'(q) 11, (C-R)^2 3, both gradient sides 11
+FLOPS_CONTACT_Z = 21    # contact pair, z only: geometry 8, C(q) 10, (C-R)^2 3
+FLOPS_NONBONDED = 40    # LJ 12-6 + Debye-Hueckel pair incl. geometry 8 and both force sides
+FLOPS_GEOMETRY = 8      # shared by the two terms when a pair is both (a fused pair counts 75)
+FLOPS_MAP = 18          # one C(q) for the ensemble mean (float64)
+
+
+def flops_scps_contact(K):
+    """SCPS step per contact pair: pass 1 (geometry, C, K squared differences)
+    18 + 3K; pass 2 (a contact-gradient pair with the effective reference
+    sum_k c_k R_k) 43 + 2K."""
+    return 18 + 3 * K + 43 + 2 * K
+
+
 PEAK_FP32 = 157.3e12    # MI355X vector FP32, 256 CUs x 2.4 GHz
+PEAK_FP64 = 78.6e12
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", default="chain560",
+                    choices=["chain560", "uneven512", "autograd3000", "scps6000"])
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--block", type=int, default=100, help="Langevin steps per benchmark step")
-    ap.add_argument("--replicas", type=int, default=256)
+    ap.add_argument("--replicas", type=int, default=0, help="0: the workload's own count")
     ap.add_argument("--plain-replicas", type=int, default=8)
     ap.add_argument("--plain-steps", type=int, default=20)
     ap.add_argument("--cpu-steps", type=int, default=300)
@@ -79,17 +100,70 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}), flush=True)
 
 
-def pair_counts(w):
-    s = w.systems[0]
-    n, nc = s.n, len(s.contact_idx)
-    ex = w.params["nb_excl"]
-    nb = n * (n - 1) // 2 - sum(n - d for d in range(1, ex + 1))
-    ci = s.contact_idx
-    msep = w.params["min_seq_sep"]
-    con = sum(1 for a in range(nc) for b in range(a + 1, nc) if ci[b] - ci[a] > msep)
-    return con, nb
+def pair_counts(sy, params):
+    """(contact pairs, nonbonded pairs, pairs that are both) of one chain."""
+    n, ci = sy.n, sy.contact_idx
+    nc = len(ci)
+    ex, msep = params["nb_excl"], params["min_seq_sep"]
+    nb = n * (n - 1) // 2 - sum(n - d for d in range(1, ex + 1) if d < n)
+    if nc == n and msep <= ex:
+        # every particle is a contact: all nonbonded pairs are also contacts
+        con = n * (n - 1) // 2 - sum(n - d for d in range(1, msep + 1) if d < n)
+        return con, nb, nb
+    import numpy as np
+    d = ci[None, :] - ci[:, None]
+    con = int(np.count_nonzero(d > msep))
+    both = int(np.count_nonzero(d > max(msep, ex)))
+    return con, nb, both
 
 
+def step_flops(con, nb, both):
+    return FLOPS_CONTACT * con + FLOPS_NONBONDED * nb - FLOPS_GEOMETRY * both
+
+
+def timed_calls(torch, fn, n_calls):
+    """Run fn() n_calls times on torch's current stream (the one the library
+    launches on); returns (wall seconds, per-call milliseconds from HIP events)."""
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(n_calls + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for k in range(n_calls):
+        fn(k)
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, [ev[k].elapsed_time(ev[k + 1]) for k in range(n_calls)]
+
+
+def median(v):
+    s = sorted(v)
+    m = len(s) // 2
+    return s[m] if len(s) % 2 else 0.5 * (s[m - 1] + s[m])
+
+
+def base_line(args, value, unit, wall, n_calls, config, dtype="f32"):
+    return {"metric": METRIC, "value": value, "unit": unit, "n_gpus": 1, "steps": n_calls,
+            "warmup": args.warmup, "ms_per_step": 1e3 * wall / n_calls, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
+
+
+def roofline(flops_per_call, per_call_ms, kernel, traffic=None, peak=PEAK_FP32):
+    avg_s = sum(per_call_ms) / len(per_call_ms) / 1e3
+    achieved = flops_per_call / avg_s
+    return {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / peak, "traffic": traffic, "kernel": kernel, "avg_launch_ms": 1e3 * avg_s,
+            "median_launch_ms": median(per_call_ms)}
+
+
+def host_threads():
+    return len(os.sched_getaffinity(0))
+
+
+# ---------------------------------------------------------------------------
+# 256 x 560: the headline workload
+# ---------------------------------------------------------------------------
 def run_plain(scps, torch, w, n_rep, n_steps):
     """One replica per context and per launch sequence (a few kernels per step)."""
     sy = w.systems[0]
@@ -118,22 +192,249 @@ def run_plain(scps, torch, w, n_rep, n_steps):
     return n_rep * n_steps / dt
 
 
-def cpu_baseline(w, n_steps):
+def cpu_baseline_steps(w, n_steps, replicas=None, what=""):
+    """The FP64 oracle (OpenMP over replicas) on replicas x n_steps, from the
+    workload's start states."""
     import numpy as np
     import oracle as O
-
-    threads = len(os.sched_getaffinity(0))
-    systems = [O.System.from_inputs(s, w.params) for s in w.systems]
-    x = w.initial_x().astype(np.float64)
-    v = w.initial_v(7).astype(np.float64)
-    cv = w.initial_cvstate()
+    rs = np.asarray(w.replica_system if replicas is None else w.replica_system[replicas], dtype=np.int32)
+    used_sys = sorted(set(rs.tolist()))
+    remap = {s: k for k, s in enumerate(used_sys)}
+    systems = [O.System.from_inputs(w.systems[s], w.params) for s in used_sys]
+    rs_local = np.array([remap[s] for s in rs.tolist()], dtype=np.int32)
+    x = np.concatenate([w.systems[s].start.ravel() for s in rs.tolist()])
+    v = np.zeros_like(x) if w.params["integrator"] == 1 else None
+    cv = np.zeros((len(rs), 8))
+    cv[:, 1] = cv[:, 5] = cv[:, 6] = np.inf
     t0 = time.perf_counter()
-    _, _, _, used = O.run_batch(w.params, systems, w.replica_system, x, v, cv, n_steps, 0, threads)
+    _, _, _, used = O.run_batch(w.params, systems, rs_local, x, v, cv, n_steps, 0, host_threads())
     dt = time.perf_counter() - t0
-    rate = w.n_replicas * n_steps / dt
-    return {"value": rate, "unit": "replica-steps/s", "cores": int(used), "kind": "oracle",
-            "sample": f"{w.n_replicas} replicas x {n_steps} Langevin steps of the same workload, "
-                      f"FP64, OpenMP over replicas ({dt:.1f} s)"}
+    return {"value": len(rs) * n_steps / dt, "unit": "replica-steps/s", "cores": int(used), "kind": "oracle",
+            "sample": f"{len(rs)} replicas x {n_steps} Langevin steps{what}, FP64, OpenMP over replicas "
+                      f"({dt:.1f} s)"}
+
+
+def bench_chain560(args, torch, I, scps):
+    R = args.replicas or 256
+    w = I.config2(n_replicas=R)
+    sy = w.systems[0]
+    con, nb, both = pair_counts(sy, w.params)
+    ctx = scps.Context.from_workload(w)
+    ctx.set_reference_map(0, native_xyz=sy.native)
+    x = torch.as_tensor(w.initial_x(), device="cuda")
+    v = torch.as_tensor(w.initial_v(7), device="cuda")
+    cv = torch.as_tensor(w.initial_cvstate(), device="cuda")
+    step = [0]
+
+    def call(_):
+        ctx.step_replicas(x, v, cv, args.block, step0=step[0])
+        step[0] += args.block
+
+    for _ in range(args.warmup):
+        call(0)
+    ctx.sync()
+    wall, per_ms = timed_calls(torch, call, args.steps)
+    ctx.sync()
+    value = R * args.block * args.steps / wall
+    out = base_line(args, value, "replica-steps/s", wall, args.steps, {
+        "workload": f"chain560_fip35_shaped: {R} replicas x 560 particles, {con} contact pairs + "
+                    f"{nb} LJ/Debye-Hueckel pairs ({both} both), BAOAB dt=2 fs, {args.block} Langevin "
+                    f"steps per benchmark step",
+        "replicas": R, "particles": sy.n, "block": args.block})
+    out["contact_pair_evals_per_s"] = value * con
+    out["nonbonded_pair_evals_per_s"] = value * nb
+    out["roofline"] = roofline(R * args.block * step_flops(con, nb, both), per_ms, "k_rmd_persistent",
+                               measured_traffic())
+    if not args.no_plain:
+        plain = run_plain(scps, torch, w, args.plain_replicas, args.plain_steps)
+        out["plain"] = {"value": plain, "unit": "replica-steps/s",
+                        "form": f"one replica per context, one launch sequence per Langevin step "
+                                f"({args.plain_replicas} replicas x {args.plain_steps} steps)"}
+        out["speedup_vs_plain"] = value / plain
+    ctx.close()
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline_steps(w, args.cpu_steps, what=" of the same workload")
+    return out
+
+
+# ---------------------------------------------------------------------------
+# 512 uneven chains
+# ---------------------------------------------------------------------------
+def bench_uneven512(args, torch, I, scps):
+    import numpy as np
+    R = args.replicas or 512
+    w = I.config3(n_replicas=R)
+    counts = [pair_counts(s, w.params) for s in w.systems]
+    con = sum(c[0] for c in counts)
+    flops = sum(step_flops(*c) for c in counts)
+    ctx = scps.Context.from_workload(w)
+    for s, sy in enumerate(w.systems):
+        ctx.set_reference_map(s, native_xyz=sy.native)
+    x = torch.as_tensor(w.initial_x(), device="cuda")
+    v = torch.as_tensor(w.initial_v(7), device="cuda")
+    cv = torch.as_tensor(w.initial_cvstate(), device="cuda")
+    step = [0]
+
+    def call(_):
+        ctx.step_replicas(x, v, cv, args.block, step0=step[0])
+        step[0] += args.block
+
+    for _ in range(args.warmup):
+        call(0)
+    ctx.sync()
+    wall, per_ms = timed_calls(torch, call, args.steps)
+    ctx.sync()
+    value = R * args.block * args.steps / wall
+    sizes = w.replica_sizes()
+    out = base_line(args, value, "replica-steps/s", wall, args.steps, {
+        "workload": f"uneven_chains: {R} chains, N ~ U{{200..3000}} (sum {int(sizes.sum())}, max "
+                    f"{int(sizes.max())}), own native map each, all particles in the contact set "
+                    f"({con} contact pairs per batched step), LJ + Debye-Hueckel, BAOAB dt=2 fs, "
+                    f"{args.block} Langevin steps per benchmark step",
+        "replicas": R, "particles_total": int(sizes.sum()), "block": args.block})
+    out["contact_pair_evals_per_s"] = value / R * con
+    out["roofline"] = roofline(args.block * flops, per_ms, "scps_step_replicas (all kernels of a block)")
+    ctx.close()
+    if not args.no_cpu:
+        rng = np.random.default_rng(5)
+        sample = np.sort(rng.choice(R, size=min(R, 64), replace=False))
+        out["cpu_baseline"] = cpu_baseline_steps(w, max(1, args.cpu_steps // 8), replicas=sample,
+                                                 what=" (a random 64 of the chains)")
+    return out
+
+
+# ---------------------------------------------------------------------------
+# 64 x 3000: autograd forward + backward
+# ---------------------------------------------------------------------------
+def bench_autograd3000(args, torch, I, scps):
+    import numpy as np
+    R = args.replicas or 64
+    w = I.config4(n_chains=R)
+    n = w.systems[0].n
+    P = n * (n - 1) // 2
+    ctx = scps.Context.from_workload(w)
+    for s, sy in enumerate(w.systems):
+        ctx.set_reference_map(s, native_xyz=sy.native)
+    X = np.concatenate([I.random_coil(n, 9000 + s).astype(np.float32).ravel() for s in range(R)])
+    x = torch.as_tensor(X, device="cuda").requires_grad_(True)
+    z0 = torch.empty(R, dtype=torch.float64, device="cuda")
+    ctx.eval_z_and_grad(x.detach(), z0)
+    zm = 0.9 * z0
+
+    def call(_):
+        x.grad = None
+        z, eb = scps.zbias(x, zm, ctx)
+        (z.sum() + eb.sum()).backward()
+
+    for _ in range(args.warmup):
+        call(0)
+    torch.cuda.synchronize()
+    wall, per_ms = timed_calls(torch, call, args.steps)
+    value = R * args.steps / wall
+    out = base_line(args, value, "chain fwd+bwd/s", wall, args.steps, {
+        "workload": f"autograd_chains: {R} chains x {n} particles, {P} contact pairs each, z and E_b "
+                    f"forward + backward (C_ij recomputed in the backward pass)",
+        "chains": R, "particles": n})
+    out["contact_pair_evals_per_s"] = value * P * 2
+    out["roofline"] = roofline(R * P * (FLOPS_CONTACT_Z + FLOPS_CONTACT), per_ms,
+                               "forward + backward (eval kernels)")
+    ctx.close()
+    if not args.no_cpu:
+        import oracle as O
+        m = R
+        t0 = time.perf_counter()
+        for s in range(m):
+            osys = O.System.from_inputs(w.systems[s], w.params)
+            xs = X[3 * n * s:3 * n * (s + 1)].reshape(3, n).astype(np.float64)
+            O.z_grad(xs, osys.cidx, osys.native, grad=False)
+            O.z_grad(xs, osys.cidx, osys.native, grad=True)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": m / dt, "unit": "chain fwd+bwd/s", "cores": 1, "kind": "oracle",
+                               "sample": f"{m} chains, z then z and grad z, FP64, one thread ({dt:.1f} s)"}
+    return out
+
+
+# ---------------------------------------------------------------------------
+# 32 x 6000: ensemble mean of recorded paths, then SCPS stepping
+# ---------------------------------------------------------------------------
+def bench_scps6000(args, torch, I, scps):
+    import numpy as np
+    R = args.replicas or 32
+    w = I.config5(n_replicas=R)
+    sy = w.systems[0]
+    n = sy.n
+    con, nb, both = pair_counts(sy, w.params)
+    K = 51
+    every = 2                                   # a short rMD run records the K frames
+    rmd = scps.Context.from_workload(w)
+    rmd.set_reference_map(0, native_xyz=sy.native)
+    x = torch.as_tensor(w.initial_x(), device="cuda")
+    v = torch.as_tensor(w.initial_v(7), device="cuda")
+    cv = torch.as_tensor(w.initial_cvstate(), device="cuda")
+    frames = torch.empty(K * 3 * R * n, dtype=torch.float32, device="cuda")
+    rmd.step_replicas(x, v, cv, every * (K - 1), record_every=every, frames=frames)
+    rmd.sync()
+    rmd.close()
+    p = dict(w.params, bias_mode=1)
+    ctx = scps.Context.from_workload(w, params=p)
+    ctx.set_reference_map(0, native_xyz=sy.native)
+    succ = np.ones(R, dtype=np.uint8)
+    # eq (avCij) over all paths x frames, timed on its own
+    for _ in range(2):
+        ctx.update_reference_from_paths(0, frames, R, K, succ)
+    torch.cuda.synchronize()
+    wall_u, per_u = timed_calls(torch, lambda _: ctx.update_reference_from_paths(0, frames, R, K, succ), 3)
+    cvs = torch.as_tensor(w.initial_cvstate(), device="cuda")
+    step = [0]
+    blk = max(1, args.block // 10)
+
+    def call(_):
+        ctx.step_replicas(x, v, cvs, blk, step0=step[0])
+        step[0] += blk
+
+    for _ in range(args.warmup):
+        call(0)
+    ctx.sync()
+    n_calls = max(3, args.steps // 4)
+    wall, per_ms = timed_calls(torch, call, n_calls)
+    ctx.sync()
+    value = R * blk * n_calls / wall
+    out = base_line(args, value, "replica-steps/s", wall, n_calls, {
+        "workload": f"chain6000_serpin_shaped: {R} replicas x {n} particles, SCPS bias on a stack of {K} "
+                    f"frame maps x {con} contact pairs, LJ + Debye-Hueckel, BAOAB dt=2 fs, {blk} Langevin "
+                    f"steps per benchmark step",
+        "replicas": R, "particles": n, "frames": K, "block": blk})
+    out["contact_pair_evals_per_s"] = value * con
+    per_step = flops_scps_contact(K) * con + FLOPS_NONBONDED * nb - FLOPS_GEOMETRY * both
+    out["roofline"] = roofline(R * blk * per_step, per_ms,
+                               "scps_step_replicas (pass 1, ratchets, pass 2, update)")
+    avg_u = sum(per_u) / len(per_u) / 1e3
+    work_u = R * K * con
+    out["update_reference"] = {
+        "value": work_u / avg_u, "unit": "path-frame contact pairs/s", "avg_call_ms": 1e3 * avg_u,
+        "paths": R, "frames": K,
+        "roofline": {"bound": "alu", "achieved": work_u * FLOPS_MAP / avg_u / 1e12, "peak": PEAK_FP64 / 1e12,
+                     "unit": "TFLOP/s", "frac": work_u * FLOPS_MAP / avg_u / PEAK_FP64,
+                     "kernel": "k_update_reference"}}
+    ctx.close()
+    if not args.no_cpu:
+        import oracle as O
+        osys = O.System.from_inputs(sy, p)
+        rng = np.random.default_rng(3)
+        # a stack of K shifted native maps: the oracle's cost does not depend on the values
+        osys.stack = np.ascontiguousarray(np.clip(osys.native[None, :] + rng.normal(0, 0.02, size=(K, 1)), 0, 1))
+        osys.K = K
+        xs = sy.start.ravel().astype(np.float64)
+        vs = np.zeros_like(xs)
+        cv0 = np.zeros((1, 8))
+        cv0[:, 1] = cv0[:, 5] = cv0[:, 6] = np.inf
+        t0 = time.perf_counter()
+        _, _, _, used = O.run_batch(p, [osys], np.zeros(1, dtype=np.int32), xs, vs, cv0, 1, 0, 1)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": 1 / dt, "unit": "replica-steps/s", "cores": int(used), "kind": "oracle",
+                               "sample": f"1 replica x 1 SCPS step of the same chain and stack size, FP64 "
+                                         f"({dt:.1f} s)"}
+    return out
 
 
 def main():
@@ -145,72 +446,15 @@ def main():
     if args.copy_calibration:
         copy_calibration()
         return
-    import numpy as np
     import torch
 
     from paper_1705_02180_amd import inputs as I
     from paper_1705_02180_amd import scps
 
     torch.cuda.set_device(0)
-    w = I.config2(n_replicas=args.replicas)
-    sy = w.systems[0]
-    n_con, n_nb = pair_counts(w)
-    ctx = scps.Context.from_workload(w)
-    ctx.set_reference_map(0, native_xyz=sy.native)
-    x = torch.as_tensor(w.initial_x(), device="cuda")
-    v = torch.as_tensor(w.initial_v(7), device="cuda")
-    cv = torch.as_tensor(w.initial_cvstate(), device="cuda")
-    step = 0
-    for _ in range(args.warmup):
-        ctx.step_replicas(x, v, cv, args.block, step0=step)
-        step += args.block
-    ctx.sync()
-
-    stream = torch.cuda.current_stream()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev[0].record(stream)
-    for k in range(args.steps):
-        ctx.step_replicas(x, v, cv, args.block, step0=step)
-        step += args.block
-        ev[k + 1].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ctx.sync()
-    per_launch_ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)]
-    gpu_s = sum(per_launch_ms) / 1e3
-    rep_steps = args.replicas * args.block * args.steps
-    value = rep_steps / wall
-    avg_launch_s = gpu_s / args.steps
-    flops_launch = args.replicas * args.block * (n_con * FLOPS_CONTACT + n_nb * FLOPS_NONBONDED)
-    achieved = flops_launch / avg_launch_s
-
-    out = {
-        "metric": METRIC, "value": value, "unit": "replica-steps/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": f"chain560_fip35_shaped: {args.replicas} replicas x 560 particles, "
-                               f"{n_con} contact pairs + {n_nb} LJ/Debye-Hueckel pairs, BAOAB dt=2 fs, "
-                               f"{args.block} Langevin steps per benchmark step",
-                   "replicas": args.replicas, "particles": sy.n, "block": args.block},
-        "contact_pair_evals_per_s": value * n_con,
-        "nonbonded_pair_evals_per_s": value * n_nb,
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": measured_traffic(),
-                     "kernel": "k_rmd_persistent", "avg_launch_ms": 1e3 * avg_launch_s},
-    }
-    if not args.no_plain:
-        plain = run_plain(scps, torch, w, args.plain_replicas, args.plain_steps)
-        out["plain"] = {"value": plain, "unit": "replica-steps/s",
-                        "form": f"one replica per context, one launch sequence per Langevin step "
-                                f"({args.plain_replicas} replicas x {args.plain_steps} steps)"}
-        out["speedup_vs_plain"] = value / plain
-    if not args.no_cpu:
-        wc = I.config2(n_replicas=args.replicas)
-        out["cpu_baseline"] = cpu_baseline(wc, args.cpu_steps)
-    ctx.close()
+    fn = {"chain560": bench_chain560, "uneven512": bench_uneven512, "autograd3000": bench_autograd3000,
+          "scps6000": bench_scps6000}[args.workload]
+    out = fn(args, torch, I, scps)
     print(json.dumps(out), flush=True)
 
 

@@ -38,7 +38,9 @@ struct SysHost {
     float *d_ref = nullptr;
     bool has_native = false;
     double Z0 = 0.0;
-    float *d_stack = nullptr;
+    float *d_stack = nullptr;      // [K][ntile_c][4096]
+    float *d_stack_pm = nullptr;   // [ntile_c][4096][stack_pm_width(K)]
+    double *d_R2 = nullptr;        // [K]
     int K = 0;
 };
 
@@ -66,8 +68,12 @@ struct scps_ctx {
     int n_items_contact = 0;
     float4 *d_xs = nullptr, *d_vs = nullptr;
     double *d_acc = nullptr, *d_zbuf = nullptr, *d_scale = nullptr, *d_negone = nullptr;
-    double *d_dsum = nullptr, *d_csum = nullptr;
-    float *d_coef = nullptr;
+    double *d_X = nullptr, *d_Q = nullptr, *d_csum = nullptr;   // SCPS: sum C R_k, sum C^2, sum c_k
+    float *d_coef = nullptr;      // SCPS: c_k / Z0 per replica
+    float *d_E = nullptr;         // SCPS: effective references, replica r at RepDesc::eoff
+    ScpsGroup *d_groups = nullptr;
+    ScpsItem *d_sitems = nullptr;
+    int n_sitems = 0;
     int kmax = KMAX;
     int wg = 64;     // persistent workgroup size
     int nbk = 0;     // nonbonded terms: bit 0 LJ, bit 1 Debye-Hueckel
@@ -156,6 +162,8 @@ scps_status upload_sysdesc(scps_ctx *c) {
         o.charge = h.d_charge;
         o.ref = h.d_ref;
         o.stack = h.d_stack;
+        o.stack_pm = h.d_stack_pm;
+        o.R2 = h.d_R2;
         o.tiles = h.d_sched;
         o.ntile = (int)h.sched.size();
         o.Z0 = h.Z0;
@@ -371,10 +379,13 @@ scps_status init_impl(const scps_params *params, const scps_topology *topo, int3
     if (st != SCPS_OK) return st;
 
     std::vector<RepDesc> reps(R);
+    int64_t eoff = 0;
     for (int r = 0; r < R; ++r) {
         reps[r].sys = rsys[r];
         reps[r].off = c->rep_off[r];
         reps[r].poff = c->rep_poff[r];
+        reps[r].eoff = eoff;
+        eoff += (int64_t)c->sys[rsys[r]].ntile_c * 4096;
     }
     HIP_TRY(c, dalloc(c, &c->d_reps, R));
     HIP_TRY(c, hipMemcpy(c->d_reps, reps.data(), R * sizeof(RepDesc), hipMemcpyHostToDevice));
@@ -421,12 +432,59 @@ scps_status init_impl(const scps_params *params, const scps_topology *topo, int3
     std::vector<double> neg(R, -1.0);
     HIP_TRY(c, hipMemcpy(c->d_negone, neg.data(), R * sizeof(double), hipMemcpyHostToDevice));
     if (p.bias_mode == SCPS_BIAS_SCPS) {
-        HIP_TRY(c, dalloc(c, &c->d_dsum, (size_t)R * c->kmax));
-        HIP_TRY(c, hipMemset(c->d_dsum, 0, (size_t)R * c->kmax * sizeof(double)));
+        HIP_TRY(c, dalloc(c, &c->d_X, (size_t)R * c->kmax));
+        HIP_TRY(c, hipMemset(c->d_X, 0, (size_t)R * c->kmax * sizeof(double)));
+        HIP_TRY(c, dalloc(c, &c->d_Q, R));
+        HIP_TRY(c, hipMemset(c->d_Q, 0, R * sizeof(double)));
         HIP_TRY(c, dalloc(c, &c->d_coef, (size_t)R * c->kmax));
         HIP_TRY(c, dalloc(c, &c->d_csum, R));
+        HIP_TRY(c, dalloc(c, &c->d_E, (size_t)eoff));
+        // replicas of a system in groups of up to SCPS_GROUP; one item per
+        // (group, contact tile pair)
+        std::vector<ScpsGroup> groups;
+        std::vector<ScpsItem> items;
+        for (int s = 0; s < (int)c->sys.size(); ++s) {
+            std::vector<int> mine;
+            for (int r = 0; r < R; ++r)
+                if (rsys[r] == s) mine.push_back(r);
+            const SysHost &h = c->sys[s];
+            for (size_t b = 0; b < mine.size(); b += SCPS_GROUP) {
+                ScpsGroup g{};
+                g.sys = s;
+                g.nrep = (int)std::min<size_t>(SCPS_GROUP, mine.size() - b);
+                for (int k = 0; k < g.nrep; ++k) g.rep[k] = mine[b + k];
+                const int gi = (int)groups.size();
+                groups.push_back(g);
+                for (int I = 0; I < h.ncb; ++I)
+                    for (int J = I; J < h.ncb; ++J)
+                        items.push_back(ScpsItem{gi, tile_index(I, J, h.ncb), (I << 16) | J,
+                                                 h.tile_flags[(size_t)I * h.nb + J]});
+            }
+        }
+        c->n_sitems = (int)items.size();
+        HIP_TRY(c, dalloc(c, &c->d_groups, groups.size()));
+        HIP_TRY(c, hipMemcpy(c->d_groups, groups.data(), groups.size() * sizeof(ScpsGroup), hipMemcpyHostToDevice));
+        HIP_TRY(c, dalloc(c, &c->d_sitems, items.size()));
+        if (!items.empty())
+            HIP_TRY(c, hipMemcpy(c->d_sitems, items.data(), items.size() * sizeof(ScpsItem), hipMemcpyHostToDevice));
     }
     *out = guard.release();
+    return SCPS_OK;
+}
+
+// The pair-major copy of a system's frame stack and sum_p R_kp^2 per frame,
+// rebuilt whenever the stack changes.
+scps_status make_pairmajor(scps_ctx *c, SysHost &h) {
+    dfree(c, h.d_stack_pm);
+    dfree(c, h.d_R2);
+    h.d_stack_pm = nullptr;
+    h.d_R2 = nullptr;
+    HIP_TRY(c, dalloc(c, &h.d_stack_pm, (size_t)stack_pm_width(h.K) * h.ntile_c * 4096));
+    HIP_TRY(c, dalloc(c, &h.d_R2, h.K));
+    HIP_TRY(c, hipMemsetAsync(h.d_R2, 0, h.K * sizeof(double), c->stream));
+    HIP_TRY(c, launch_stack_pairmajor(h.nc, h.ncb, h.K, c->prm.min_seq_sep, h.d_perm, h.d_stack, h.d_stack_pm,
+                                      h.d_R2, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
     return SCPS_OK;
 }
 
@@ -481,6 +539,8 @@ scps_status set_ref_impl(scps_ctx *c, int32_t s, int32_t n_maps, const double *m
         HIP_TRY(c, hipStreamSynchronize(c->stream));
         dfree(c, d_packed);
         h.K = n_maps;
+        scps_status st = make_pairmajor(c, h);
+        if (st != SCPS_OK) return st;
     }
     return upload_sysdesc(c);
 }
@@ -517,18 +577,21 @@ scps_status step_impl(scps_ctx *c, float *x, float *v, double *cv, int64_t n_ste
         if (m == n_steps) break;
         if (!scps) {
             HIP_TRY(c, launch_pairs(0, c->nbk, c->kp, c->d_sysd, c->d_reps, c->d_items_all, c->n_items_all, c->d_xs,
-                                    c->d_acc, c->d_zbuf, nullptr, nullptr, nullptr, c->kmax, c->stream));
+                                    c->d_acc, c->d_zbuf, nullptr, nullptr, c->stream));
             HIP_TRY(c, launch_finalize_rmd(c->kp, c->R, c->d_zbuf, cv, c->d_scale, c->stream));
             HIP_TRY(c, launch_integrate(c->kp, c->d_sysd, c->d_reps, c->R, c->n_pad_max, c->d_xs, c->d_vs, c->d_acc,
                                         c->d_scale, step0 + (uint64_t)m, c->d_flags, c->stream));
         } else {
-            HIP_TRY(c, launch_pairs(3, c->nbk, c->kp, c->d_sysd, c->d_reps, c->d_items_contact, c->n_items_contact,
-                                    c->d_xs, c->d_acc, c->d_zbuf, c->d_dsum, nullptr, nullptr, c->kmax,
-                                    c->stream));
-            HIP_TRY(c, launch_finalize_scps(c->kp, c->d_sysd, c->d_reps, c->R, c->kmax, c->d_dsum, cv, c->d_coef,
-                                            c->d_csum, c->stream));
-            HIP_TRY(c, launch_pairs(4, c->nbk, c->kp, c->d_sysd, c->d_reps, c->d_items_all, c->n_items_all, c->d_xs,
-                                    c->d_acc, c->d_zbuf, c->d_dsum, c->d_coef, c->d_csum, c->kmax, c->stream));
+            // distances to every frame (matrix cores), tube variables and
+            // ratchets, effective references (matrix cores), bias + physics
+            HIP_TRY(c, launch_scps_dist(c->kp, c->d_sysd, c->d_reps, c->d_groups, c->d_sitems, c->n_sitems, c->d_xs,
+                                        c->d_X, c->d_Q, c->kmax, c->stream));
+            HIP_TRY(c, launch_finalize_scps(c->kp, c->d_sysd, c->d_reps, c->R, c->kmax, c->d_X, c->d_Q, cv,
+                                            c->d_coef, c->d_csum, c->stream));
+            HIP_TRY(c, launch_scps_eff(c->d_sysd, c->d_reps, c->d_groups, c->d_sitems, c->n_sitems, c->d_coef,
+                                       c->kmax, c->d_E, c->stream));
+            HIP_TRY(c, launch_pairs(3, c->nbk, c->kp, c->d_sysd, c->d_reps, c->d_items_all, c->n_items_all, c->d_xs,
+                                    c->d_acc, c->d_zbuf, c->d_E, c->d_csum, c->stream));
             HIP_TRY(c, launch_integrate(c->kp, c->d_sysd, c->d_reps, c->R, c->n_pad_max, c->d_xs, c->d_vs, c->d_acc,
                                         c->d_negone, step0 + (uint64_t)m, c->d_flags, c->stream));
         }
@@ -545,7 +608,7 @@ scps_status eval_impl(scps_ctx *c, const float *x, double *z, float *grad, const
             return fail(SCPS_ERR_STATE, "a system has no native map (scps_set_reference_map)");
     HIP_TRY(c, launch_gather(c->d_sysd, c->d_reps, c->R, c->n_pad_max, x, nullptr, c->d_xs, nullptr, c->stream));
     HIP_TRY(c, launch_pairs(grad ? 2 : 1, c->nbk, c->kp, c->d_sysd, c->d_reps, c->d_items_contact, c->n_items_contact,
-                            c->d_xs, c->d_acc, c->d_zbuf, nullptr, nullptr, nullptr, c->kmax, c->stream));
+                            c->d_xs, c->d_acc, c->d_zbuf, nullptr, nullptr, c->stream));
     HIP_TRY(c, launch_eval_out(c->d_sysd, c->d_reps, c->R, c->n_pad_max, c->d_acc, c->d_zbuf, z, grad, coef,
                                c->stream));
     return SCPS_OK;
@@ -581,6 +644,8 @@ scps_status update_ref_impl(scps_ctx *c, int32_t s, const float *frames, int32_t
     dfree(c, h.d_stack);
     h.d_stack = d_new;
     h.K = n_frames;
+    scps_status st = make_pairmajor(c, h);
+    if (st != SCPS_OK) return st;
     return upload_sysdesc(c);
 }
 

@@ -46,6 +46,8 @@ struct SysDesc {
     const float *charge;     // [n_pad] internal order (pads: 0)
     const float *ref;        // native map tiles [ntile_c][64*64]
     const float *stack;      // SCPS frames [K][ntile_c][64*64]
+    const float *stack_pm;   // the same frames pair-major: [ntile_c][64*64][stack_pm_width(K)]
+    const double *R2;        // [K] sum over the counted contact pairs of R_k^2
     const int2 *tiles;       // persistent work list, costliest first (see build_schedule)
     int ntile;
     int pad1;
@@ -57,6 +59,19 @@ struct RepDesc {
     int pad0;
     int64_t off;             // particle offset of the replica in the flat x layout
     int64_t poff;            // particle offset in the padded internal-order buffers
+    int64_t eoff;            // SCPS: offset of its effective reference [ntile_c][64*64]
+};
+
+// SCPS: up to 32 replicas of one system share every read of the frame stack.
+constexpr int SCPS_GROUP = 32;
+struct ScpsGroup {
+    int sys, nrep;
+    int rep[SCPS_GROUP];
+};
+// A unit of SCPS stack work: one contact tile pair (I, J) = (IJ >> 16, IJ &
+// 0xFFFF), numbered tile, for every replica of a group.
+struct ScpsItem {
+    int group, tile, IJ, flags;
 };
 
 // A unit of pair work for the per-step kernels: one tile pair of one replica.
@@ -79,6 +94,10 @@ enum { TILE_DIAG = 1, TILE_CONTACT = 2, TILE_MASK = 4 };
 #endif
 constexpr int SEG_STEPS = SCPS_SEG_STEPS;
 
+// Frames per pair in the pair-major stack: K rounded up to a multiple of 4
+// (zero-filled), so a lane reads four frames of a pair with one 16-byte load.
+__host__ __device__ inline int stack_pm_width(int K) { return (K + 3) & ~3; }
+
 // Contact tile pairs (I <= J < ncb) are numbered row by row.
 __host__ __device__ inline int tile_index(int I, int J, int ncb) {
     return I * ncb - (I * (I - 1)) / 2 + (J - I);
@@ -100,17 +119,23 @@ hipError_t launch_scatter(const SysDesc *sysd, const RepDesc *reps, int R, int n
                           hipStream_t st);
 
 // mode: 0 rMD forces (contact z + grad, nonbonded, bonds); 1 z only; 2 z and grad;
-//       3 SCPS pass 1 (distances to every frame); 4 SCPS pass 2 (bias + nonbonded + bonds)
+//       3 SCPS bias against the effective references eff (+ nonbonded + bonds)
 // nbk: nonbonded terms, bit 0 Lennard-Jones, bit 1 Debye-Hueckel
 hipError_t launch_pairs(int mode, int nbk, const KParams &P, const SysDesc *sysd, const RepDesc *reps,
                         const TileItem *items, int n_items, const float4 *xs, double *acc,
-                        double *zbuf, double *dsum, const float *coef, const double *csum,
-                        int kmax, hipStream_t st);
+                        double *zbuf, const float *eff, const double *csum, hipStream_t st);
+hipError_t launch_scps_dist(const KParams &P, const SysDesc *sysd, const RepDesc *reps, const ScpsGroup *groups,
+                            const ScpsItem *items, int n_items, const float4 *xs, double *X, double *Q, int kmax,
+                            hipStream_t st);
+hipError_t launch_scps_eff(const SysDesc *sysd, const RepDesc *reps, const ScpsGroup *groups, const ScpsItem *items,
+                           int n_items, const float *coef, int kmax, float *E, hipStream_t st);
+hipError_t launch_stack_pairmajor(int nc, int ncb, int K, int min_sep, const int *perm, const float *stack,
+                                  float *stack_pm, double *R2, hipStream_t st);
 
 hipError_t launch_finalize_rmd(const KParams &P, int R, double *zbuf, double *cv, double *scale,
                                hipStream_t st);
 hipError_t launch_finalize_scps(const KParams &P, const SysDesc *sysd, const RepDesc *reps, int R,
-                                int kmax, double *dsum, double *cv, float *coef, double *csum,
+                                int kmax, double *X, double *Q, double *cv, float *coef, double *csum,
                                 hipStream_t st);
 hipError_t launch_integrate(const KParams &P, const SysDesc *sysd, const RepDesc *reps, int R,
                             int n_pad_max, float4 *xs, float4 *vs, double *acc,

@@ -100,11 +100,13 @@ __device__ __forceinline__ void normals3(const KParams &P, uint32_t atom, uint32
 // ---------------------------------------------------------------------------
 // the pair tile pass
 // ---------------------------------------------------------------------------
-enum { PM_RMD = 0, PM_Z = 1, PM_ZG = 2, PM_SCPS1 = 3, PM_SCPS2 = 4 };
+// PM_SCPS: the SCPS bias (contact gradient against each replica's effective
+// reference E) plus the nonbonded forces.
+enum { PM_RMD = 0, PM_Z = 1, PM_ZG = 2, PM_SCPS = 3 };
 
 template <int MODE> struct ModeTraits {
-    static constexpr bool nb = (MODE == PM_RMD || MODE == PM_SCPS2);
-    static constexpr bool grad = (MODE == PM_RMD || MODE == PM_ZG || MODE == PM_SCPS2);
+    static constexpr bool nb = (MODE == PM_RMD || MODE == PM_SCPS);
+    static constexpr bool grad = (MODE == PM_RMD || MODE == PM_ZG || MODE == PM_SCPS);
     static constexpr bool z = (MODE == PM_RMD || MODE == PM_Z || MODE == PM_ZG);
 };
 
@@ -160,14 +162,15 @@ __device__ __forceinline__ float nb_scalar(const KParams &P, const float r2, con
 // contact predicate (a block that straddles the end of the contact set, a
 // sequence separation, a cutoff); every other tile runs predicate-free.
 // act0 is false only for lanes 32..63 at k = 32 of a diagonal tile, where the
-// pair was already met at the mirrored sub-step.
+// pair was already met at the mirrored sub-step.  rt is the tile's reference
+// block (the native map, or in PM_SCPS the replica's effective reference
+// E = sum_k c_k R_k, against which the difference is csum C - E).
 template <int MODE, bool DIAG, bool CONTACT, bool MASK, int NBK, int U>
 __device__ __forceinline__ void pair_group(const KParams &P, const int lane, const int k0, const bool low,
                                            const LaneI &A, const float4 *__restrict__ posj2,
                                            const int *__restrict__ orgj, const int ncj,
-                                           const float *__restrict__ rt, const int64_t kstride, const int K,
-                                           const float *__restrict__ ck, const float csum, float fi[6],
-                                           float fj[6], float &zt, float *dk) {
+                                           const float *__restrict__ rt, const float csum, float fi[6],
+                                           float fj[6], float &zt) {
     // Sub-steps k0 .. k0+U-1, computed phase by phase so that the U pair
     // evaluations are independent instruction streams; only the
     // accumulation (and the rotation of the j-side partials) is sequential.
@@ -207,33 +210,19 @@ __device__ __forceinline__ void pair_group(const KParams &P, const int lane, con
             const float inv_den = inside[u] ? frcp(den) : 0.f;
             const float C = num * inv_den;
             g[u] = 0.f;
-            if constexpr (MODE == PM_SCPS1) {
-                const float *rk = rt + k * 64 + lane;
-#pragma unroll
-                for (int kk = 0; kk < KMAX; ++kk) {
-                    if (kk < K) {
-                        const float d = con[u] ? (C - ldg(rk, kk * kstride)) : 0.f;
-                        dk[kk] = fmaf(d, d, dk[kk]);
-                    }
-                }
-            } else {
-                float diff;
-                if constexpr (MODE == PM_SCPS2) {
-                    float eff = csum * C;
-                    for (int kk = 0; kk < K; ++kk) eff = fmaf(-ck[kk], ldg(rt, kk * kstride + k * 64 + lane), eff);
-                    diff = eff;
-                } else {
-                    diff = C - ldg(rt, k * 64 + lane);
-                }
-                diff = con[u] ? diff : 0.f;
-                if constexpr (T::z) zt = fmaf(diff, diff, zt);
-                if constexpr (T::grad) {
-                    // C'(q) = -q^2 (3 + 6q + 4q^2 + 2q^3) / den^2, evaluated as
-                    // (q^2/den) (poly/den) so nothing overflows at large q;
-                    // g = (4/r0^2) (C - R) C'(q), the factor -4/r0^2 folded into poly
-                    const float poly = fmaf(q, fmaf(q, fmaf(q, P.cp[0], P.cp[1]), P.cp[2]), P.cp[3]);
-                    g[u] = (diff * (q2 * inv_den)) * (poly * inv_den);
-                }
+            float diff;
+            if constexpr (MODE == PM_SCPS)
+                diff = fmaf(csum, C, -ldg(rt, k * 64 + lane));
+            else
+                diff = C - ldg(rt, k * 64 + lane);
+            diff = con[u] ? diff : 0.f;
+            if constexpr (T::z) zt = fmaf(diff, diff, zt);
+            if constexpr (T::grad) {
+                // C'(q) = -q^2 (3 + 6q + 4q^2 + 2q^3) / den^2, evaluated as
+                // (q^2/den) (poly/den) so nothing overflows at large q;
+                // g = (4/r0^2) (C - R) C'(q), the factor -4/r0^2 folded into poly
+                const float poly = fmaf(q, fmaf(q, fmaf(q, P.cp[0], P.cp[1]), P.cp[2]), P.cp[3]);
+                g[u] = (diff * (q2 * inv_den)) * (poly * inv_den);
             }
         }
     }
@@ -269,7 +258,7 @@ __device__ __forceinline__ void pair_group2(const KParams &P, const int lane, co
                                             const float *__restrict__ rtA, const float *__restrict__ rtB,
                                             float fa[6], float fb[6], float fj[6], float &zt) {
     using T = ModeTraits<MODE>;
-    static_assert(MODE != PM_SCPS1 && MODE != PM_SCPS2, "double tiles are for the rMD and z modes");
+    static_assert(MODE != PM_SCPS, "double tiles are for the rMD and z modes");
     float dxa[U], dya[U], dza[U], fA[U], gA[U];
     float dxb[U], dyb[U], dzb[U], fB[U], gB[U];
     float r2a[U], r2b[U];
@@ -377,28 +366,20 @@ __device__ __forceinline__ void tile_dispatch2(const int flags, const int kb, co
 #undef SCPS_TILE2
 }
 
-// Pair evaluations grouped per sub-step batch: more independent work per
-// wavefront for the modes with few registers per pair.
-template <int MODE> constexpr int group_width() {
-    return (MODE == PM_SCPS1 || MODE == PM_SCPS2) ? 1 : SCPS_PAIR_GROUP;
-}
-
-// A whole tile pair.  Outputs: fi[0..2] nonbonded, fi[3..5] contact gradient
-// (i side); fj likewise for the j particle lane l holds at the end, which is
-// (l + 33) mod 64 for a diagonal tile and l otherwise; zt: this lane's z
-// partial; dk[0..K): squared distances to every frame (SCPS pass 1).
+// A whole tile pair (sub-steps kb .. ke-1, evaluated SCPS_PAIR_GROUP at a
+// time).  Outputs: fi[0..2] nonbonded, fi[3..5] contact gradient (i side); fj
+// likewise for the j particle lane l holds at the end (see jflush_at); zt:
+// this lane's z partial.
 template <int MODE, bool DIAG, bool CONTACT, bool MASK, int NBK>
 __device__ __forceinline__ void tile_pass(const KParams &P, const int lane, const int kb, const int ke,
                                           const LaneI &A, const float4 *__restrict__ posj2,
                                           const int *__restrict__ orgj, const int ncj, const float *__restrict__ rt,
-                                          const int64_t kstride, const int K, const float *__restrict__ ck,
-                                          const float csum, float fi[6], float fj[6], float &zt, float *dk) {
-    constexpr int U = group_width<MODE>();
+                                          const float csum, float fi[6], float fj[6], float &zt) {
+    constexpr int U = SCPS_PAIR_GROUP;
     const bool low = lane < 32;
 #pragma unroll 1
     for (int k0 = kb; k0 < ke; k0 += U)
-        pair_group<MODE, DIAG, CONTACT, MASK, NBK, U>(P, lane, k0, low, A, posj2, orgj, ncj, rt, kstride, K, ck,
-                                                      csum, fi, fj, zt, dk);
+        pair_group<MODE, DIAG, CONTACT, MASK, NBK, U>(P, lane, k0, low, A, posj2, orgj, ncj, rt, csum, fi, fj, zt);
 }
 
 // Sub-step range of a whole tile: 1..32 on a diagonal tile (lanes 0..31 only
@@ -417,11 +398,10 @@ template <int MODE, int NBK>
 __device__ __forceinline__ void tile_dispatch(const int flags, const int kb, const int ke, const KParams &P,
                                               const int lane, const LaneI &A,
                                               const float4 *__restrict__ posj2, const int *__restrict__ orgj,
-                                              const int ncj, const float *__restrict__ rt, const int64_t kstride,
-                                              const int K, const float *__restrict__ ck, const float csum,
-                                              float fi[6], float fj[6], float &zt, float *dk) {
+                                              const int ncj, const float *__restrict__ rt, const float csum,
+                                              float fi[6], float fj[6], float &zt) {
 #define SCPS_TILE(D, C, M)                                                                                  \
-    tile_pass<MODE, D, C, M, NBK>(P, lane, kb, ke, A, posj2, orgj, ncj, rt, kstride, K, ck, csum, fi, fj, zt, dk)
+    tile_pass<MODE, D, C, M, NBK>(P, lane, kb, ke, A, posj2, orgj, ncj, rt, csum, fi, fj, zt)
     const bool diag = flags & TF_DIAG, con = flags & TF_CONTACT, mask = flags & TF_MASK;
     if (ModeTraits<MODE>::nb) {
         if (diag) {
@@ -618,8 +598,8 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WG / 256 > 0
             const float *rt = (tf & TF_CONTACT) ? S.ref + (int64_t)tile_index(I, J, S.ncb) * 4096 : nullptr;
             int nxt = 0;
             if (lane == 0) nxt = atomicAdd(&sh_next, 1);
-            tile_dispatch<PM_RMD, NBK>(tf, kb, ke, P, lane, A, pos + J * 128, org + J * 64, S.nc - J * 64, rt, 0,
-                                       0, nullptr, 0.f, fi, fj, zt, nullptr);
+            tile_dispatch<PM_RMD, NBK>(tf, kb, ke, P, lane, A, pos + J * 128, org + J * 64, S.nc - J * 64, rt, 0.f,
+                                       fi, fj, zt);
             zacc += (double)zt;
             const int jo = J * 64 + jflush_at(lane, ke);
             const int ncomp = (tf & TF_CONTACT) ? 6 : 3;
@@ -841,15 +821,16 @@ hipError_t launch_scatter(const SysDesc *sysd, const RepDesc *reps, int R, int n
 }
 
 // One wavefront per tile item; four per workgroup.  Partial sums go to the
-// float64 accumulators in global memory with hardware float64 atomics.
+// float64 accumulators in global memory with hardware float64 atomics.  In
+// PM_SCPS the contact reference of replica r is its effective reference
+// E + eoff_r (written by k_scps_eff) and csum[r] = sum_k c_k.
 template <int MODE, int NBK>
 __global__ __launch_bounds__(256) void k_pairs(const KParams P, const SysDesc *__restrict__ sysd,
                                                const RepDesc *__restrict__ reps,
                                                const TileItem *__restrict__ items, const int n_items,
                                                const float4 *__restrict__ xs, double *__restrict__ acc,
-                                               double *__restrict__ zbuf, double *__restrict__ dsum,
-                                               const float *__restrict__ coef, const double *__restrict__ csum,
-                                               const int kmax) {
+                                               double *__restrict__ zbuf, const float *__restrict__ eff,
+                                               const double *__restrict__ csum) {
     using T = ModeTraits<MODE>;
     const int lane = threadIdx.x & 63;
     const int item = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -870,25 +851,13 @@ __global__ __launch_bounds__(256) void k_pairs(const KParams P, const SysDesc *_
     float fi[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     float fj[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     float zt = 0.f;
-    float dk[KMAX];
     const bool contact_tile = tf & TF_CONTACT;
     const int64_t toff = contact_tile ? (int64_t)tile_index(I, J, S.ncb) * 4096 : 0;
     const float *rt;
-    int64_t kstride = 0;
-    int K = 0;
     float cs = 0.f;
-    const float *ck = nullptr;
-    if constexpr (MODE == PM_SCPS1 || MODE == PM_SCPS2) {
-        rt = S.stack + toff;
-        kstride = (int64_t)S.ntile_c * 4096;
-        K = S.K;
-        if constexpr (MODE == PM_SCPS1) {
-#pragma unroll
-            for (int kk = 0; kk < KMAX; ++kk) dk[kk] = 0.f;
-        } else {
-            ck = coef + (int64_t)it.rep * kmax;
-            cs = (float)csum[it.rep];
-        }
+    if constexpr (MODE == PM_SCPS) {
+        rt = eff + rd.eoff + toff;
+        cs = (float)csum[it.rep];
     } else {
         rt = S.ref + toff;
     }
@@ -897,8 +866,8 @@ __global__ __launch_bounds__(256) void k_pairs(const KParams P, const SysDesc *_
     }
     const bool diag = tf & TF_DIAG;
     const int kb = tile_kbeg(diag), ke = tile_kend(diag);
-    tile_dispatch<MODE, NBK>(tf, kb, ke, P, lane, A, xr2 + J * 128, S.perm + J * 64, S.nc - J * 64, rt, kstride, K,
-                             ck, cs, fi, fj, zt, dk);
+    tile_dispatch<MODE, NBK>(tf, kb, ke, P, lane, A, xr2 + J * 128, S.perm + J * 64, S.nc - J * 64, rt, cs, fi, fj,
+                             zt);
     const int jo = J * 64 + jflush_at(lane, ke);
     double *ar = acc + 6 * rd.poff;
     if constexpr (T::nb) {
@@ -934,25 +903,15 @@ __global__ __launch_bounds__(256) void k_pairs(const KParams P, const SysDesc *_
         const double zw = wave_sum((double)zt);
         if (lane == 0 && contact_tile) unsafeAtomicAdd(&zbuf[it.rep], zw);
     }
-    if constexpr (MODE == PM_SCPS1) {
-#pragma unroll
-        for (int kk = 0; kk < KMAX; ++kk) {
-            if (kk < K) {
-                const double s = wave_sum((double)dk[kk]);
-                if (lane == 0) unsafeAtomicAdd(&dsum[(int64_t)it.rep * kmax + kk], s);
-            }
-        }
-    }
 }
 
 template <int MODE>
 static void launch_pairs_mode(int nbk, dim3 grid, dim3 block, hipStream_t st, const KParams &P,
                               const SysDesc *sysd, const RepDesc *reps, const TileItem *items, int n_items,
-                              const float4 *xs, double *acc, double *zbuf, double *dsum, const float *coef,
-                              const double *csum, int kmax) {
+                              const float4 *xs, double *acc, double *zbuf, const float *eff, const double *csum) {
 #define SCPS_LAUNCH(K)                                                                                   \
     hipLaunchKernelGGL((k_pairs<MODE, K>), grid, block, 0, st, P, sysd, reps, items, n_items, xs, acc, zbuf, \
-                       dsum, coef, csum, kmax)
+                       eff, csum)
     if constexpr (!ModeTraits<MODE>::nb) {
         SCPS_LAUNCH(0);
     } else {
@@ -968,29 +927,21 @@ static void launch_pairs_mode(int nbk, dim3 grid, dim3 block, hipStream_t st, co
 
 hipError_t launch_pairs(int mode, int nbk, const KParams &P, const SysDesc *sysd, const RepDesc *reps,
                         const TileItem *items, int n_items, const float4 *xs, double *acc, double *zbuf,
-                        double *dsum, const float *coef, const double *csum, int kmax, hipStream_t st) {
+                        const float *eff, const double *csum, hipStream_t st) {
     if (n_items == 0) return hipSuccess;
     const dim3 grid((n_items + 3) / 4), block(256);
     switch (mode) {
     case PM_RMD:
-        launch_pairs_mode<PM_RMD>(nbk, grid, block, st, P, sysd, reps, items, n_items, xs, acc, zbuf, dsum, coef,
-                                  csum, kmax);
+        launch_pairs_mode<PM_RMD>(nbk, grid, block, st, P, sysd, reps, items, n_items, xs, acc, zbuf, eff, csum);
         break;
     case PM_Z:
-        launch_pairs_mode<PM_Z>(nbk, grid, block, st, P, sysd, reps, items, n_items, xs, acc, zbuf, dsum, coef,
-                                csum, kmax);
+        launch_pairs_mode<PM_Z>(nbk, grid, block, st, P, sysd, reps, items, n_items, xs, acc, zbuf, eff, csum);
         break;
     case PM_ZG:
-        launch_pairs_mode<PM_ZG>(nbk, grid, block, st, P, sysd, reps, items, n_items, xs, acc, zbuf, dsum, coef,
-                                 csum, kmax);
-        break;
-    case PM_SCPS1:
-        launch_pairs_mode<PM_SCPS1>(nbk, grid, block, st, P, sysd, reps, items, n_items, xs, acc, zbuf, dsum,
-                                    coef, csum, kmax);
+        launch_pairs_mode<PM_ZG>(nbk, grid, block, st, P, sysd, reps, items, n_items, xs, acc, zbuf, eff, csum);
         break;
     default:
-        launch_pairs_mode<PM_SCPS2>(nbk, grid, block, st, P, sysd, reps, items, n_items, xs, acc, zbuf, dsum,
-                                    coef, csum, kmax);
+        launch_pairs_mode<PM_SCPS>(nbk, grid, block, st, P, sysd, reps, items, n_items, xs, acc, zbuf, eff, csum);
         break;
     }
     return hipGetLastError();
@@ -1018,30 +969,47 @@ hipError_t launch_finalize_rmd(const KParams &P, int R, double *zbuf, double *cv
 }
 
 // SCPS tube variables per replica (one wavefront each), from the squared
-// distances d_k*Z0 to every frame k = 0..M of the stack:
+// distances d_k Z0 = sum_p (C_p - R_kp)^2 to every frame k = 0..M of the
+// stack, assembled in float64 as Q - 2 X_k + R2_k (Q = sum C^2 and
+// X_k = sum C R_k from k_scps_dist, R2_k = sum R_k^2 of the stack):
 //   s = 1 - (1/M) sum_k k p_k,  w = -(1/lambda) log sum_k exp(-lambda d_k),
 //   p_k = softmax(-lambda d_k); ratchets on s and w, eqs (Fw),(Fs).
 // The bias force is -sum_k c_k grad d_k with
 //   c_k = p_k [k_s (s - s_m)(lambda/M)(k - kbar) + k_w (w - w_m)];
 // coef receives c_k / Z0 and csum sum_k c_k / Z0 for the gradient pass.
+// X and Q are consumed and cleared.
 __global__ void k_finalize_scps(const KParams P, const SysDesc *__restrict__ sysd, const RepDesc *__restrict__ reps,
-                                const int kmax, double *__restrict__ dsum, double *__restrict__ cv,
-                                float *__restrict__ coef, double *__restrict__ csum) {
+                                const int kmax, double *__restrict__ X, double *__restrict__ Q,
+                                double *__restrict__ cv, float *__restrict__ coef, double *__restrict__ csum) {
     const int r = blockIdx.x;
     const int lane = threadIdx.x;
     const SysDesc S = sysd[reps[r].sys];
     const int K = S.K, M = K - 1;
-    double *dr = dsum + (int64_t)r * kmax;
+    double *xr = X + (int64_t)r * kmax;
+    const double q = Q[r];
     const double lam = P.lambda;
+    // d_k for the (at most two) frames this lane holds
+    double dk[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int k = lane + 64 * h;
+        dk[h] = k < K ? fmax(q - 2.0 * xr[k] + S.R2[k], 0.0) / S.Z0 : 0.0;
+    }
     double a = -INFINITY;
-    for (int k = lane; k < K; k += 64) a = fmax(a, -lam * dr[k] / S.Z0);
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+        if (lane + 64 * h < K) a = fmax(a, -lam * dk[h]);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) a = fmax(a, __shfl_xor(a, o, 64));
-    double s0 = 0.0, s1 = 0.0;
-    for (int k = lane; k < K; k += 64) {
-        const double e = exp(-lam * dr[k] / S.Z0 - a);
-        s0 += e;
-        s1 += (double)k * e;
+    double s0 = 0.0, s1 = 0.0, e[2] = {0.0, 0.0};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int k = lane + 64 * h;
+        if (k < K) {
+            e[h] = exp(-lam * dk[h] - a);
+            s0 += e[h];
+            s1 += (double)k * e[h];
+        }
     }
     s0 = wave_sum(s0);
     s1 = wave_sum(s1);
@@ -1053,16 +1021,20 @@ __global__ void k_finalize_scps(const KParams P, const SysDesc *__restrict__ sys
     const double wm = fmin(c[CV_WM], wv);
     const double ds = sv - sm, dw = wv - wm;
     double tot = 0.0;
-    for (int k = lane; k < K; k += 64) {
-        const double pk = exp(-lam * dr[k] / S.Z0 - a) / s0;
-        const double ckv = pk * (P.k_s * ds * (lam / (double)M) * ((double)k - kbar) + P.k_w * dw);
-        coef[(int64_t)r * kmax + k] = (float)(ckv / S.Z0);
-        tot += ckv;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int k = lane + 64 * h;
+        if (k < K) {
+            const double pk = e[h] / s0;
+            const double ckv = pk * (P.k_s * ds * (lam / (double)M) * ((double)k - kbar) + P.k_w * dw);
+            coef[(int64_t)r * kmax + k] = (float)(ckv / S.Z0);
+            tot += ckv;
+            xr[k] = 0.0;
+        }
     }
     tot = wave_sum(tot);
-    __syncthreads();
-    for (int k = lane; k < K; k += 64) dr[k] = 0.0;
     if (lane == 0) {
+        Q[r] = 0.0;
         csum[r] = tot / S.Z0;
         c[CV_S] = sv;
         c[CV_W] = wv;
@@ -1073,8 +1045,314 @@ __global__ void k_finalize_scps(const KParams P, const SysDesc *__restrict__ sys
 }
 
 hipError_t launch_finalize_scps(const KParams &P, const SysDesc *sysd, const RepDesc *reps, int R, int kmax,
-                                double *dsum, double *cv, float *coef, double *csum, hipStream_t st) {
-    hipLaunchKernelGGL(k_finalize_scps, dim3(R), dim3(64), 0, st, P, sysd, reps, kmax, dsum, cv, coef, csum);
+                                double *X, double *Q, double *cv, float *coef, double *csum, hipStream_t st) {
+    hipLaunchKernelGGL(k_finalize_scps, dim3(R), dim3(64), 0, st, P, sysd, reps, kmax, X, Q, cv, coef, csum);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// SCPS on matrix cores.  The squared distance of replica r to frame k,
+// d_k Z0 = sum_p (C_rp - R_kp)^2, splits into sum_p C_rp^2 - 2 X_rk +
+// sum_p R_kp^2 with X_rk = sum_p C_rp R_kp: for a group of up to 32 replicas
+// of one system that is a dense contraction over the contact pairs p, done
+// here with float64 MFMA (products of float32 values are exact in float64, so
+// the three sums keep the precision of the direct form).  The bias pass needs
+// each replica's effective reference E_rp = sum_k c_rk R_kp, a contraction
+// over the frames, done with float32 MFMA (the same rounding as a float32
+// dot product).  Both read every stack tile once per group instead of once
+// per replica.
+// ---------------------------------------------------------------------------
+typedef double dvec4 __attribute__((ext_vector_type(4)));
+typedef float fvec16 __attribute__((ext_vector_type(16)));
+
+// Unordered contact pair (64 I + l, 64 J + ((l + s) mod 64)) of a tile in the
+// diagonal-major layout: in a diagonal tile every pair appears twice; the
+// copy at sub-steps 1..31, or at 32 for l < 32, is the one that counts.
+__device__ __forceinline__ bool tile_pair_counts(bool diag, int s, int l) {
+    return !diag || (s >= 1 && (s < 32 || (s == 32 && l < 32)));
+}
+
+// Pair-major copy of a frame stack: stack_pm[tile][p][k] = stack[k][tile][p]
+// for k < K (zero for K <= k < K4), and R2[k] += sum over the counted pairs of
+// R_kp^2 (float64; pairs within min_seq_sep, outside the contact set or
+// repeated in a diagonal tile are not counted).  One workgroup per (tile,
+// sub-step s): the 64 pairs of that sub-step.  R2 must be zero on entry.
+__global__ __launch_bounds__(256) void k_stack_pairmajor(int nc, int ncb, int ntile, int K, int min_sep,
+                                                         const int *__restrict__ perm,
+                                                         const float *__restrict__ stack,
+                                                         float *__restrict__ stack_pm, double *__restrict__ R2) {
+    __shared__ float buf[64][KMAX + 1];
+    __shared__ double r2s[KMAX];
+    const int tile = blockIdx.x, s = blockIdx.y;
+    int I, J;
+    tile_decode(tile, ncb, I, J);
+    const int tid = threadIdx.x;
+    if (tid < KMAX) r2s[tid] = 0.0;
+    __syncthreads();
+    const int64_t kstride = (int64_t)ntile * 4096;
+    for (int e = tid; e < 64 * K; e += 256) {
+        const int k = e >> 6, l = e & 63;
+        const float v = stack[k * kstride + (int64_t)tile * 4096 + s * 64 + l];
+        buf[l][k] = v;
+        const int a = I * 64 + l, b = J * 64 + ((l + s) & 63);
+        const bool counts = a < nc && b < nc && tile_pair_counts(I == J, s, l) && abs(perm[a] - perm[b]) > min_sep;
+        if (counts) atomicAdd(&r2s[k], (double)v * (double)v);
+    }
+    __syncthreads();
+    const int K4 = stack_pm_width(K);
+    float *out = stack_pm + ((int64_t)tile * 4096 + s * 64) * K4;
+    for (int e = tid; e < 64 * K4; e += 256) {
+        const int l = e / K4, k = e - l * K4;
+        out[e] = k < K ? buf[l][k] : 0.f;
+    }
+    if (tid < K) unsafeAtomicAdd(&R2[tid], r2s[tid]);
+}
+
+hipError_t launch_stack_pairmajor(int nc, int ncb, int K, int min_sep, const int *perm, const float *stack,
+                                  float *stack_pm, double *R2, hipStream_t st) {
+    const int nt = ncb * (ncb + 1) / 2;
+    if (nt == 0 || K == 0) return hipSuccess;
+    if (K > KMAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_stack_pairmajor, dim3(nt, 64), dim3(256), 0, st, nc, ncb, nt, K, min_sep, perm, stack,
+                       stack_pm, R2);
+    return hipGetLastError();
+}
+
+// Contact value of one replica-pair for the MFMA operand (0 when the pair
+// does not count).
+__device__ __forceinline__ float contact_operand(const KParams &P, const float4 &pi, const float4 &pj, bool ok) {
+    float dx, dy, dz;
+    const float r2 = pair_r2(pi, pj, dx, dy, dz);
+    const float q = r2 * P.inv_r0sq;
+    const float q2 = q * q;
+    const float num = 1.f + q + q2;
+    const float den = fmaf(q2, q + q2, num);
+    const bool inside = !P.has_cut | (r2 <= P.r_cut2);
+    return (ok & inside) ? num * frcp(den) : 0.f;
+}
+
+// Pass 1: X[r][k] += sum_p C_rp R_kp and Q[r] += sum_p C_rp^2 over the contact
+// pairs of each work item (group of replicas, tile); workgroups stride over
+// the items and flush their sums when the group changes and at the end.
+// Wavefront w takes sub-steps w, w+4, ... of the tile; each MFMA step takes 4
+// pairs of a sub-step: lane l evaluates pair 4m + (l >> 4) for replicas
+// l & 15 and 16 + (l & 15) (A operands of the 16x16x4 float64 MFMAs) and
+// loads frames 4 (l & 15) .. 4 (l & 15) + 3 of the same pair with one 16-byte
+// load; frame block f holds frames 4j + f (j = 0..15), so component f of that
+// load is the lane's B operand of block f.  Accumulator acc[h][f] element v of
+// lane l is replica 16 h + (l >> 4) + 4 v, frame 4 (l & 15) + f.
+template <bool MASK>
+__device__ __forceinline__ void scps_dist_tile(const KParams &P, const SysDesc &S, const int nrep,
+                                               const ScpsItem &it, const float4 (*pos)[64][32],
+                                               const int (*org)[64], const int lane, const int wave,
+                                               dvec4 acc[2][4], double &q0, double &q1) {
+    const int I = it.IJ >> 16, J = it.IJ & 0xFFFF;
+    const bool diag = I == J;
+    const int K4 = stack_pm_width(S.K);
+    const int rs = lane & 15, pq = lane >> 4;
+    const bool rep0 = rs < nrep, rep1 = rs + 16 < nrep;
+    const bool bload = 4 * rs < K4;
+    const float *Rt = S.stack_pm + (int64_t)it.tile * 4096 * K4;
+    const int sb = diag ? 1 : 0, se = diag ? 33 : 64;
+#pragma unroll 1
+    for (int s = sb + wave; s < se; s += 4) {
+        const float *Rs = Rt + (int64_t)(s * 64 + pq) * K4 + 4 * rs;
+#pragma unroll 4
+        for (int m = 0; m < 16; ++m) {
+            const int l = 4 * m + pq;                 // i within block I
+            const int jl = (l + s) & 63;              // j within block J
+            bool ok = tile_pair_counts(diag, s, l);
+            if constexpr (MASK) {
+                ok = ok & (I * 64 + l < S.nc) & (J * 64 + jl < S.nc) & (abs(org[0][l] - org[1][jl]) > P.min_sep);
+            }
+            const float4 b4 = bload ? *reinterpret_cast<const float4 *>(Rs + (int64_t)(4 * m) * K4)
+                                    : make_float4(0.f, 0.f, 0.f, 0.f);
+            const float c0 = contact_operand(P, pos[0][l][rs], pos[1][jl][rs], ok & rep0);
+            const float c1 = contact_operand(P, pos[0][l][rs + 16], pos[1][jl][rs + 16], ok & rep1);
+            const double a0 = (double)c0, a1 = (double)c1;
+            q0 = fma(a0, a0, q0);
+            q1 = fma(a1, a1, q1);
+            const double b[4] = {(double)b4.x, (double)b4.y, (double)b4.z, (double)b4.w};
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                acc[0][f] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b[f], acc[0][f], 0, 0, 0);
+                acc[1][f] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b[f], acc[1][f], 0, 0, 0);
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_scps_dist(const KParams P, const SysDesc *__restrict__ sysd,
+                                                   const RepDesc *__restrict__ reps,
+                                                   const ScpsGroup *__restrict__ groups,
+                                                   const ScpsItem *__restrict__ items, const int n_items,
+                                                   const float4 *__restrict__ xs, double *__restrict__ X,
+                                                   double *__restrict__ Q, const int kmax) {
+    __shared__ __align__(16) float4 pos[2][64][32];   // [block I / J][particle][replica slot]; reused to reduce
+    __shared__ int org[2][64];
+    __shared__ int sh_rep[32];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    dvec4 acc[2][4];
+    double q0 = 0.0, q1 = 0.0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int f = 0; f < 4; ++f) acc[h][f] = (dvec4){0.0, 0.0, 0.0, 0.0};
+    int cur = -1, nrep = 0;
+    SysDesc S;
+    for (int t = blockIdx.x;; t += gridDim.x) {
+        const bool more = t < n_items;
+        const ScpsItem it = more ? items[t] : ScpsItem{-1, 0, 0, 0};
+        if (cur >= 0 && it.group != cur) {
+            // flush: reduce the four wavefronts' sums through LDS, then float64 atomics
+            __syncthreads();
+            double *red = reinterpret_cast<double *>(&pos[0][0][0]);   // [4 waves][32 values][64 lanes]
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int f = 0; f < 4; ++f)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) red[(wave * 32 + h * 16 + f * 4 + v) * 64 + lane] = acc[h][f][v];
+            __syncthreads();
+            for (int e = tid; e < 32 * 64; e += 256) {
+                const int reg = e >> 6, ln = e & 63;
+                const double sum = red[e] + red[2048 + e] + red[4096 + e] + red[6144 + e];
+                const int h = reg >> 4, f = (reg >> 2) & 3, v = reg & 3;
+                const int slot = 16 * h + (ln >> 4) + 4 * v, k = 4 * (ln & 15) + f;
+                if (slot < nrep && k < S.K) unsafeAtomicAdd(&X[(int64_t)sh_rep[slot] * kmax + k], sum);
+            }
+            __syncthreads();
+            red[wave * 128 + lane] = q0;
+            red[wave * 128 + 64 + lane] = q1;
+            __syncthreads();
+            if (tid < 32) {
+                const int h = tid >> 4, rsl = tid & 15;
+                double sum = 0.0;
+                for (int w = 0; w < 4; ++w)
+                    for (int g = 0; g < 4; ++g) sum += red[w * 128 + h * 64 + g * 16 + rsl];
+                if (tid < nrep) unsafeAtomicAdd(&Q[sh_rep[tid]], sum);
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int f = 0; f < 4; ++f) acc[h][f] = (dvec4){0.0, 0.0, 0.0, 0.0};
+            q0 = q1 = 0.0;
+        }
+        if (!more) break;
+        __syncthreads();
+        if (it.group != cur) {
+            cur = it.group;
+            const ScpsGroup *gp = groups + cur;
+            nrep = gp->nrep;
+            S = sysd[gp->sys];
+            if (tid < 32) sh_rep[tid] = tid < nrep ? gp->rep[tid] : 0;
+            __syncthreads();
+        }
+        // stage the positions of blocks I and J of every replica of the group
+        const int I = it.IJ >> 16, J = it.IJ & 0xFFFF;
+        for (int e = tid; e < 2 * 64 * 32; e += 256) {
+            const int blk = e >> 11, pl = (e >> 5) & 63, slot = e & 31;
+            float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (slot < nrep) p = xs[2 * reps[sh_rep[slot]].poff + (blk ? J : I) * 128 + pl];
+            pos[blk][pl][slot] = p;
+        }
+        if (tid < 128) org[tid >> 6][tid & 63] = S.perm[((tid >> 6) ? J : I) * 64 + (tid & 63)];
+        __syncthreads();
+        if (it.flags & TILE_MASK)
+            scps_dist_tile<true>(P, S, nrep, it, pos, org, lane, wave, acc, q0, q1);
+        else
+            scps_dist_tile<false>(P, S, nrep, it, pos, org, lane, wave, acc, q0, q1);
+    }
+}
+
+// Pass 2 operand: E[eoff_r + tile * 4096 + p] = sum_k c_rk R_kp for every
+// pair p of each work item's tile and replica r of its group (coef holds
+// c_rk).  Wavefront w takes chunks of 128 pairs w, w+4, ...; a chunk is four
+// 32-pair MFMA blocks interleaved so that block b holds pairs 4j + b: lane l
+// reads pairs 4 (l & 31) .. +3 of frame 2 kk + (l >> 5) with one 16-byte load
+// (component b is its B operand of block b) and supplies c of replica l & 31
+// for that frame (A operand, 32x32x2 float32 MFMA).  Result element v of lane
+// l in block b is replica 8 (v >> 2) + 4 (l >> 5) + (v & 3), pair 4 (l & 31)
+// + b: the four blocks give one 16-byte store per replica.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_scps_eff(const SysDesc *__restrict__ sysd,
+                                                  const RepDesc *__restrict__ reps,
+                                                  const ScpsGroup *__restrict__ groups,
+                                                  const ScpsItem *__restrict__ items, const int n_items,
+                                                  const float *__restrict__ coef, const int kmax,
+                                                  float *__restrict__ E) {
+    __shared__ int64_t sh_eoff[SCPS_GROUP];   // -1 for an empty slot
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int slot = lane & 31, half = lane >> 5;
+    int cur = -1;
+    SysDesc S;
+    float creg[KMAX / 2];
+    for (int t = blockIdx.x; t < n_items; t += gridDim.x) {
+        const ScpsItem it = items[t];
+        if (it.group != cur) {
+            cur = it.group;
+            const ScpsGroup *gp = groups + cur;
+            const int nrep = gp->nrep;
+            S = sysd[gp->sys];
+            const int myrep = slot < nrep ? gp->rep[slot] : 0;
+#pragma unroll
+            for (int kk = 0; kk < KMAX / 2; ++kk) {
+                const int k = 2 * kk + half;
+                creg[kk] = (slot < nrep && k < S.K) ? coef[(int64_t)myrep * kmax + k] : 0.f;
+            }
+            __syncthreads();
+            if (tid < SCPS_GROUP) sh_eoff[tid] = tid < nrep ? reps[gp->rep[tid]].eoff : -1;
+            __syncthreads();
+        }
+        const int K = S.K;
+        const int64_t kstride = (int64_t)S.ntile_c * 4096;
+        const float *Rt = S.stack + (int64_t)it.tile * 4096;
+#pragma unroll 1
+        for (int ch = wave; ch < 32; ch += 4) {
+            const int p = ch * 128 + 4 * slot;
+            fvec16 acc[4];
+#pragma unroll
+            for (int bl = 0; bl < 4; ++bl)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) acc[bl][v] = 0.f;
+#pragma unroll
+            for (int kk = 0; kk < KMAX / 2; ++kk) {
+                if (2 * kk < K) {
+                    const int k = 2 * kk + half;
+                    const float4 b = k < K ? *reinterpret_cast<const float4 *>(Rt + k * kstride + p)
+                                           : make_float4(0.f, 0.f, 0.f, 0.f);
+                    acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(creg[kk], b.x, acc[0], 0, 0, 0);
+                    acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(creg[kk], b.y, acc[1], 0, 0, 0);
+                    acc[2] = __builtin_amdgcn_mfma_f32_32x32x2f32(creg[kk], b.z, acc[2], 0, 0, 0);
+                    acc[3] = __builtin_amdgcn_mfma_f32_32x32x2f32(creg[kk], b.w, acc[3], 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int64_t eo = sh_eoff[8 * (v >> 2) + 4 * half + (v & 3)];
+                if (eo >= 0)
+                    *reinterpret_cast<float4 *>(E + eo + (int64_t)it.tile * 4096 + p) =
+                        make_float4(acc[0][v], acc[1][v], acc[2][v], acc[3][v]);
+            }
+        }
+    }
+}
+
+hipError_t launch_scps_dist(const KParams &P, const SysDesc *sysd, const RepDesc *reps, const ScpsGroup *groups,
+                            const ScpsItem *items, int n_items, const float4 *xs, double *X, double *Q, int kmax,
+                            hipStream_t st) {
+    if (n_items == 0) return hipSuccess;
+    const int grid = n_items < 512 ? n_items : 512;
+    hipLaunchKernelGGL(k_scps_dist, dim3(grid), dim3(256), 0, st, P, sysd, reps, groups, items, n_items, xs, X, Q,
+                       kmax);
+    return hipGetLastError();
+}
+
+hipError_t launch_scps_eff(const SysDesc *sysd, const RepDesc *reps, const ScpsGroup *groups, const ScpsItem *items,
+                           int n_items, const float *coef, int kmax, float *E, hipStream_t st) {
+    if (n_items == 0) return hipSuccess;
+    const int grid = n_items < 1024 ? n_items : 1024;
+    hipLaunchKernelGGL(k_scps_eff, dim3(grid), dim3(256), 0, st, sysd, reps, groups, items, n_items, coef, kmax,
+                       E);
     return hipGetLastError();
 }
 

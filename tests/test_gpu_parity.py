@@ -392,50 +392,93 @@ def test_update_reference_matches_oracle(S):
     assert e.value.status == -7
 
 
-@pytest.mark.parametrize("n,kind,bias_only", [(180, "all", False), (300, "every3", False), (180, "all", True)],
-                         ids=["all_180", "every3_300", "bias_only_180"])
-def test_scps_step_forces_match_oracle(S, n, kind, bias_only):
+SCPS_CASES = [
+    # id, chain sizes, contact sets, frames K, replicas, bias only, parameters
+    ("all_180_K9", [180], ["all"], 9, 4, False, {}),
+    ("every3_300_K9", [300], ["every3"], 9, 4, False, {}),
+    ("bias_only_180_K9", [180], ["all"], 9, 4, True, {}),
+    ("all_130_K51_R40", [130], ["all"], 51, 40, False, {}),
+    ("bias_only_150_K33_seqsep5", [150], ["all"], 33, 6, True, {"min_seq_sep": 5}),
+    ("bias_only_160_K17_cutoff12", [160], ["all"], 17, 4, True, {"r_cut_contact": 12.0}),
+    ("two_systems_K20", [150, 200], ["all", "every3"], 20, 6, False, {}),
+]
+
+
+@pytest.mark.parametrize("name,sizes,kinds,K,R,bias_only,extra", SCPS_CASES, ids=[c[0] for c in SCPS_CASES])
+def test_scps_step_forces_match_oracle(S, name, sizes, kinds, K, R, bias_only, extra):
+    """One SCPS step (distances to all K frames, tube variables and ratchets,
+    bias + physics) against the oracle, with the frame stack built on the GPU
+    from recorded paths and, separately, uploaded from the oracle's FP64 maps.
+    K > 16 uses several frame blocks of the distance pass; R > 32 several
+    replica groups; two systems two stacks."""
+    import torch
     base = dict(I._base_params())
-    p = _force_readback_params(base, bias_mode=1, lam=13.5, k_s=50.0, k_w=5.0)
+    p = _force_readback_params(base, bias_mode=1, lam=13.5, k_s=50.0, k_w=5.0, **extra)
     if bias_only:
         p.update(k_bond=0.0, lj_eps=0.0, dh_prefactor=0.0)
-    w = single_system_workload(n, _cidx(n, kind), p, 4)
-    sy = w.systems[0]
-    K = 9
-    fr = _ensemble_frames(sy, K, 4, 8)
-    ctx = context(S, w, params=p)
-    maps = ctx.update_reference_from_paths(0, dev(fr.ravel()), 4, K, np.ones(4, dtype=np.uint8), want_maps=True)
-    stack, _ = O.update_reference(sy.n, sy.contact_idx, fr.astype(np.float64), np.ones(4, dtype=np.uint8))
-    np.testing.assert_allclose(maps, stack, rtol=1e-12, atol=1e-15)
-    osys = O.System(sy.n, sy.contact_idx, sy.mass, sy.charge, p, native_xyz=sy.native, stack=stack)
-    X = np.stack([fr[3, 0], fr[5, 1], fr[1, 2], fr[7, 3]]).astype(np.float32)
-    cv0 = np.zeros((4, 8))
+    n_paths = 4
+    systems, stacks, frames = [], [], []
+    for s_id, (n, kind) in enumerate(zip(sizes, kinds)):
+        rng = np.random.default_rng(11 + s_id)
+        sy = I.System(n=n, contact_idx=np.asarray(_cidx(n, kind), dtype=np.int32),
+                      mass=np.full(n, 12.011 * I.AMU, dtype=np.float32),
+                      charge=rng.normal(0, 0.3, n).astype(np.float32),
+                      native=I.compact_native(n, 11 + s_id), start=I.persistent_start(n, 12 + s_id))
+        fr = _ensemble_frames(sy, K, n_paths, 8 + s_id)
+        st, ns = O.update_reference(sy.n, sy.contact_idx, fr.astype(np.float64), np.ones(n_paths, dtype=np.uint8),
+                                    p["r0_contact"], p["r_cut_contact"])
+        assert ns == n_paths
+        systems.append(sy)
+        stacks.append(st)
+        frames.append(fr)
+    rsys = np.arange(R, dtype=np.int32) % len(sizes)
+    w = I.Workload(name, dict(p), systems, rsys, 1)
+    osys = [O.System(sy.n, sy.contact_idx, sy.mass, sy.charge, p, native_xyz=sy.native, stack=st)
+            for sy, st in zip(systems, stacks)]
+    X, cv0 = [], np.zeros((R, 8))
     cv0[:, 5:7] = np.inf
-    for r in (1, 2, 3):
-        sv, wv, *_ = O.tube(X[r].astype(np.float64), osys.cidx, stack, osys.Z0, p["lam"], grads=False)
-        cv0[r, 5] = sv - 0.05 * r
-        cv0[r, 6] = wv - 0.01 * r
-    import torch
-    R = 4
-    ctx2 = context(S, w, params=p)
-    ctx2.set_reference_map(0, maps=stack)
-    x = dev(X.ravel())
-    v = torch.zeros_like(x)
-    cv = dev(cv0, "f64")
-    ctx2.step_replicas(x, v, cv, 1)
-    ctx2.sync()
-    c1 = math.exp(-p["gamma"] * p["dt"])
-    V = host(v).reshape(R, 3, n).astype(np.float64) * sy.mass.astype(np.float64) / (c1 * p["dt"])
-    CV = host(cv)
     for r in range(R):
-        F, Fb, cvr = O.total_force(p, osys, X[r].astype(np.float64), cv0[r])
-        if np.abs(F).max() > 0:
-            assert normwise(V[r], F) <= TOL, (r, normwise(V[r], F))
-        else:
-            assert np.all(V[r] == 0)
-        if bias_only:
-            assert r == 0 or np.abs(Fb).max() > 0          # the ratchets are active
-        np.testing.assert_allclose(CV[r, 3:7], cvr[3:7], rtol=0, atol=1e-5)
+        fr = frames[rsys[r]]
+        X.append(fr[(3 + 2 * r) % K, r % n_paths].astype(np.float32))
+        if r >= 1:
+            sv, wv, *_ = O.tube(X[r].astype(np.float64), osys[rsys[r]].cidx, stacks[rsys[r]], osys[rsys[r]].Z0,
+                                p["lam"], p["r0_contact"], p["r_cut_contact"], p["min_seq_sep"], grads=False)
+            cv0[r, 5] = sv - 0.05 * (1 + r % 3)
+            cv0[r, 6] = wv - 0.01 * (1 + r % 3)
+    want = [O.total_force(p, osys[rsys[r]], X[r].astype(np.float64), cv0[r]) for r in range(R)]
+    xflat = np.concatenate([x.ravel() for x in X])
+    c1 = math.exp(-p["gamma"] * p["dt"])
+    for how in ("update", "upload"):
+        ctx = context(S, w, params=p)
+        for s_id, sy in enumerate(systems):
+            if how == "update":
+                maps = ctx.update_reference_from_paths(s_id, dev(frames[s_id].ravel()), n_paths, K,
+                                                       np.ones(n_paths, dtype=np.uint8), want_maps=True)
+                np.testing.assert_allclose(maps, stacks[s_id], rtol=1e-12, atol=1e-15)
+            else:
+                ctx.set_reference_map(s_id, maps=stacks[s_id])
+        x = dev(xflat)
+        v = torch.zeros_like(x)
+        cv = dev(cv0, "f64")
+        ctx.step_replicas(x, v, cv, 1)
+        ctx.sync()
+        V = host(v)
+        CV = host(cv)
+        off = 0
+        for r in range(R):
+            sy = systems[rsys[r]]
+            n = sy.n
+            Vr = V[3 * off:3 * (off + n)].reshape(3, n).astype(np.float64) * sy.mass.astype(np.float64) / (c1 * p["dt"])
+            off += n
+            F, Fb, cvr = want[r]
+            if np.abs(F).max() > 0:
+                assert normwise(Vr, F) <= TOL, (how, r, normwise(Vr, F))
+            else:
+                assert np.all(Vr == 0)
+            if bias_only:
+                assert r == 0 or np.abs(Fb).max() > 0          # the ratchets are active
+            np.testing.assert_allclose(CV[r, 3:7], cvr[3:7], rtol=0, atol=1e-5, err_msg=f"{how} replica {r}")
+        ctx.close()
 
 
 # ---------------------------------------------------------------------------
