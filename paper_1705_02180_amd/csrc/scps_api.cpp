@@ -38,7 +38,7 @@ struct SysHost {
     float *d_ref = nullptr;
     bool has_native = false;
     double Z0 = 0.0;
-    float *d_stack = nullptr;      // [K][ntile_c][4096]
+    float *d_stack = nullptr;      // [ntile_c][K][4096]
     float *d_stack_pm = nullptr;   // [ntile_c][4096][stack_pm_width(K)]
     double *d_R2 = nullptr;        // [K]
     int K = 0;
@@ -67,7 +67,9 @@ struct scps_ctx {
     TileItem *d_items_contact = nullptr;
     int n_items_contact = 0;
     float4 *d_xs = nullptr, *d_vs = nullptr;
-    double *d_acc = nullptr, *d_zbuf = nullptr, *d_scale = nullptr, *d_negone = nullptr;
+    double *d_acc = nullptr, *d_scale = nullptr, *d_negone = nullptr;
+    double *d_zpart = nullptr;                       // z partial of every tile item
+    int *d_first_all = nullptr, *d_first_con = nullptr;   // [R+1] item ranges per replica
     double *d_X = nullptr, *d_Q = nullptr, *d_csum = nullptr;   // SCPS: sum C R_k, sum C^2, sum c_k
     float *d_coef = nullptr;      // SCPS: c_k / Z0 per replica
     float *d_E = nullptr;         // SCPS: effective references, replica r at RepDesc::eoff
@@ -398,9 +400,13 @@ scps_status init_impl(const scps_params *params, const scps_topology *topo, int3
     HIP_TRY(c, dalloc(c, &c->d_order, R));
     HIP_TRY(c, hipMemcpy(c->d_order, order.data(), R * sizeof(int), hipMemcpyHostToDevice));
 
-    // per-step work lists: every tile pair, and the contact tile pairs
+    // per-step work lists: every tile pair, and the contact tile pairs,
+    // replica by replica
     std::vector<TileItem> all, con;
+    std::vector<int> first_all(R + 1), first_con(R + 1);
     for (int r = 0; r < R; ++r) {
+        first_all[r] = (int)all.size();
+        first_con[r] = (int)con.size();
         const SysHost &h = c->sys[rsys[r]];
         for (int I = 0; I < h.nb; ++I)
             for (int J = I; J < h.nb; ++J) {
@@ -409,8 +415,15 @@ scps_status init_impl(const scps_params *params, const scps_topology *topo, int3
                 if (I < h.ncb && J < h.ncb) con.push_back(t);
             }
     }
+    first_all[R] = (int)all.size();
+    first_con[R] = (int)con.size();
     c->n_items_all = (int)all.size();
     c->n_items_contact = (int)con.size();
+    HIP_TRY(c, dalloc(c, &c->d_zpart, all.size()));
+    HIP_TRY(c, dalloc(c, &c->d_first_all, R + 1));
+    HIP_TRY(c, dalloc(c, &c->d_first_con, R + 1));
+    HIP_TRY(c, hipMemcpy(c->d_first_all, first_all.data(), (R + 1) * sizeof(int), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->d_first_con, first_con.data(), (R + 1) * sizeof(int), hipMemcpyHostToDevice));
     HIP_TRY(c, dalloc(c, &c->d_items_all, all.size()));
     HIP_TRY(c, dalloc(c, &c->d_items_contact, con.size()));
     if (!all.empty())
@@ -425,8 +438,6 @@ scps_status init_impl(const scps_params *params, const scps_topology *topo, int3
     HIP_TRY(c, dalloc(c, &c->d_vs, c->sumNpad));
     HIP_TRY(c, dalloc(c, &c->d_acc, 6 * c->sumNpad));
     HIP_TRY(c, hipMemset(c->d_acc, 0, 6 * c->sumNpad * sizeof(double)));
-    HIP_TRY(c, dalloc(c, &c->d_zbuf, R));
-    HIP_TRY(c, hipMemset(c->d_zbuf, 0, R * sizeof(double)));
     HIP_TRY(c, dalloc(c, &c->d_scale, R));
     HIP_TRY(c, dalloc(c, &c->d_negone, R));
     std::vector<double> neg(R, -1.0);
@@ -577,8 +588,8 @@ scps_status step_impl(scps_ctx *c, float *x, float *v, double *cv, int64_t n_ste
         if (m == n_steps) break;
         if (!scps) {
             HIP_TRY(c, launch_pairs(0, c->nbk, c->kp, c->d_sysd, c->d_reps, c->d_items_all, c->n_items_all, c->d_xs,
-                                    c->d_acc, c->d_zbuf, nullptr, nullptr, c->stream));
-            HIP_TRY(c, launch_finalize_rmd(c->kp, c->R, c->d_zbuf, cv, c->d_scale, c->stream));
+                                    c->d_acc, c->d_zpart, nullptr, nullptr, c->stream));
+            HIP_TRY(c, launch_finalize_rmd(c->kp, c->R, c->d_first_all, c->d_zpart, cv, c->d_scale, c->stream));
             HIP_TRY(c, launch_integrate(c->kp, c->d_sysd, c->d_reps, c->R, c->n_pad_max, c->d_xs, c->d_vs, c->d_acc,
                                         c->d_scale, step0 + (uint64_t)m, c->d_flags, c->stream));
         } else {
@@ -591,7 +602,7 @@ scps_status step_impl(scps_ctx *c, float *x, float *v, double *cv, int64_t n_ste
             HIP_TRY(c, launch_scps_eff(c->d_sysd, c->d_reps, c->d_groups, c->d_sitems, c->n_sitems, c->d_coef,
                                        c->kmax, c->d_E, c->stream));
             HIP_TRY(c, launch_pairs(3, c->nbk, c->kp, c->d_sysd, c->d_reps, c->d_items_all, c->n_items_all, c->d_xs,
-                                    c->d_acc, c->d_zbuf, c->d_E, c->d_csum, c->stream));
+                                    c->d_acc, c->d_zpart, c->d_E, c->d_csum, c->stream));
             HIP_TRY(c, launch_integrate(c->kp, c->d_sysd, c->d_reps, c->R, c->n_pad_max, c->d_xs, c->d_vs, c->d_acc,
                                         c->d_negone, step0 + (uint64_t)m, c->d_flags, c->stream));
         }
@@ -608,8 +619,9 @@ scps_status eval_impl(scps_ctx *c, const float *x, double *z, float *grad, const
             return fail(SCPS_ERR_STATE, "a system has no native map (scps_set_reference_map)");
     HIP_TRY(c, launch_gather(c->d_sysd, c->d_reps, c->R, c->n_pad_max, x, nullptr, c->d_xs, nullptr, c->stream));
     HIP_TRY(c, launch_pairs(grad ? 2 : 1, c->nbk, c->kp, c->d_sysd, c->d_reps, c->d_items_contact, c->n_items_contact,
-                            c->d_xs, c->d_acc, c->d_zbuf, nullptr, nullptr, c->stream));
-    HIP_TRY(c, launch_eval_out(c->d_sysd, c->d_reps, c->R, c->n_pad_max, c->d_acc, c->d_zbuf, z, grad, coef,
+                            c->d_xs, c->d_acc, c->d_zpart, nullptr, nullptr, c->stream));
+    HIP_TRY(c, launch_eval_out(c->d_sysd, c->d_reps, c->R, c->n_pad_max, c->d_acc, c->d_first_con, c->d_zpart, z,
+                               grad, coef,
                                c->stream));
     return SCPS_OK;
 }

@@ -45,7 +45,7 @@ struct SysDesc {
     const float *mass;       // [n_pad] internal order (pads: 1)
     const float *charge;     // [n_pad] internal order (pads: 0)
     const float *ref;        // native map tiles [ntile_c][64*64]
-    const float *stack;      // SCPS frames [K][ntile_c][64*64]
+    const float *stack;      // SCPS frames [ntile_c][K][64*64]
     const float *stack_pm;   // the same frames pair-major: [ntile_c][64*64][stack_pm_width(K)]
     const double *R2;        // [K] sum over the counted contact pairs of R_k^2
     const int2 *tiles;       // persistent work list, costliest first (see build_schedule)
@@ -123,7 +123,7 @@ hipError_t launch_scatter(const SysDesc *sysd, const RepDesc *reps, int R, int n
 // nbk: nonbonded terms, bit 0 Lennard-Jones, bit 1 Debye-Hueckel
 hipError_t launch_pairs(int mode, int nbk, const KParams &P, const SysDesc *sysd, const RepDesc *reps,
                         const TileItem *items, int n_items, const float4 *xs, double *acc,
-                        double *zbuf, const float *eff, const double *csum, hipStream_t st);
+                        double *zpart, const float *eff, const double *csum, hipStream_t st);
 hipError_t launch_scps_dist(const KParams &P, const SysDesc *sysd, const RepDesc *reps, const ScpsGroup *groups,
                             const ScpsItem *items, int n_items, const float4 *xs, double *X, double *Q, int kmax,
                             hipStream_t st);
@@ -132,8 +132,9 @@ hipError_t launch_scps_eff(const SysDesc *sysd, const RepDesc *reps, const ScpsG
 hipError_t launch_stack_pairmajor(int nc, int ncb, int K, int min_sep, const int *perm, const float *stack,
                                   float *stack_pm, double *R2, hipStream_t st);
 
-hipError_t launch_finalize_rmd(const KParams &P, int R, double *zbuf, double *cv, double *scale,
-                               hipStream_t st);
+// first[r] .. first[r+1]: replica r's items in the list whose z partials are in zpart
+hipError_t launch_finalize_rmd(const KParams &P, int R, const int *first, const double *zpart, double *cv,
+                               double *scale, hipStream_t st);
 hipError_t launch_finalize_scps(const KParams &P, const SysDesc *sysd, const RepDesc *reps, int R,
                                 int kmax, double *X, double *Q, double *cv, float *coef, double *csum,
                                 hipStream_t st);
@@ -141,8 +142,8 @@ hipError_t launch_integrate(const KParams &P, const SysDesc *sysd, const RepDesc
                             int n_pad_max, float4 *xs, float4 *vs, double *acc,
                             const double *scale, uint64_t step, int *flags, hipStream_t st);
 
-hipError_t launch_eval_out(const SysDesc *sysd, const RepDesc *reps, int R, int n_pad_max,
-                           double *acc, double *zbuf, double *z_out, float *grad,
+hipError_t launch_eval_out(const SysDesc *sysd, const RepDesc *reps, int R, int n_pad_max, double *acc,
+                           const int *first, const double *zpart, double *z_out, float *grad,
                            const double *grad_coef, hipStream_t st);
 hipError_t launch_ratchet_energy(int R, double k_R, const double *z, const double *zm, double *Eb,
                                  const double *gz, const double *gE, double *coef, hipStream_t st);

@@ -162,15 +162,15 @@ __device__ __forceinline__ float nb_scalar(const KParams &P, const float r2, con
 // contact predicate (a block that straddles the end of the contact set, a
 // sequence separation, a cutoff); every other tile runs predicate-free.
 // act0 is false only for lanes 32..63 at k = 32 of a diagonal tile, where the
-// pair was already met at the mirrored sub-step.  rt is the tile's reference
-// block (the native map, or in PM_SCPS the replica's effective reference
-// E = sum_k c_k R_k, against which the difference is csum C - E).
+// pair was already met at the mirrored sub-step.  rv[u] is the lane's
+// reference value at sub-step k0 + u (the native map, or in PM_SCPS the
+// replica's effective reference E = sum_k c_k R_k, against which the
+// difference is csum C - E).
 template <int MODE, bool DIAG, bool CONTACT, bool MASK, int NBK, int U>
 __device__ __forceinline__ void pair_group(const KParams &P, const int lane, const int k0, const bool low,
                                            const LaneI &A, const float4 *__restrict__ posj2,
-                                           const int *__restrict__ orgj, const int ncj,
-                                           const float *__restrict__ rt, const float csum, float fi[6],
-                                           float fj[6], float &zt) {
+                                           const int *__restrict__ orgj, const int ncj, const float *rv,
+                                           const float csum, float fi[6], float fj[6], float &zt) {
     // Sub-steps k0 .. k0+U-1, computed phase by phase so that the U pair
     // evaluations are independent instruction streams; only the
     // accumulation (and the rotation of the j-side partials) is sequential.
@@ -202,7 +202,6 @@ __device__ __forceinline__ void pair_group(const KParams &P, const int lane, con
     if constexpr (CONTACT) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int k = k0 + u;
             const float q = r2[u] * P.inv_r0sq;
             const float q2 = q * q;
             const float num = 1.f + q + q2;
@@ -212,9 +211,9 @@ __device__ __forceinline__ void pair_group(const KParams &P, const int lane, con
             g[u] = 0.f;
             float diff;
             if constexpr (MODE == PM_SCPS)
-                diff = fmaf(csum, C, -ldg(rt, k * 64 + lane));
+                diff = fmaf(csum, C, -rv[u]);
             else
-                diff = C - ldg(rt, k * 64 + lane);
+                diff = C - rv[u];
             diff = con[u] ? diff : 0.f;
             if constexpr (T::z) zt = fmaf(diff, diff, zt);
             if constexpr (T::grad) {
@@ -366,20 +365,45 @@ __device__ __forceinline__ void tile_dispatch2(const int flags, const int kb, co
 #undef SCPS_TILE2
 }
 
-// A whole tile pair (sub-steps kb .. ke-1, evaluated SCPS_PAIR_GROUP at a
-// time).  Outputs: fi[0..2] nonbonded, fi[3..5] contact gradient (i side); fj
+// A whole tile pair, or a segment of one: sub-steps kb .. ke-1, a multiple of
+// D (every caller uses 32 or 64), evaluated SCPS_PAIR_GROUP at a time.  The
+// lane's reference values are loaded D sub-steps ahead of their use into a
+// ring of registers: D = 4 groups in the per-step kernels, whose maps stream
+// from HBM, one group where the map is cache-resident (persistent kernel).
+// Outputs: fi[0..2] nonbonded, fi[3..5] contact gradient (i side); fj
 // likewise for the j particle lane l holds at the end (see jflush_at); zt:
 // this lane's z partial.
-template <int MODE, bool DIAG, bool CONTACT, bool MASK, int NBK>
+template <int MODE, bool DIAG, bool CONTACT, bool MASK, int NBK, int D>
 __device__ __forceinline__ void tile_pass(const KParams &P, const int lane, const int kb, const int ke,
                                           const LaneI &A, const float4 *__restrict__ posj2,
                                           const int *__restrict__ orgj, const int ncj, const float *__restrict__ rt,
                                           const float csum, float fi[6], float fj[6], float &zt) {
     constexpr int U = SCPS_PAIR_GROUP;
+    static_assert(D % U == 0, "prefetch depth is whole groups");
     const bool low = lane < 32;
+    float ring[D];
+    if constexpr (CONTACT) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) ring[d] = ldg(rt, (kb + d) * 64 + lane);
+    }
 #pragma unroll 1
-    for (int k0 = kb; k0 < ke; k0 += U)
-        pair_group<MODE, DIAG, CONTACT, MASK, NBK, U>(P, lane, k0, low, A, posj2, orgj, ncj, rt, csum, fi, fj, zt);
+    for (int k0 = kb; k0 < ke; k0 += D) {
+#pragma unroll
+        for (int g = 0; g < D / U; ++g) {
+            float rv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) rv[u] = CONTACT ? ring[g * U + u] : 0.f;
+            if constexpr (CONTACT) {
+                const int kn = k0 + D + g * U;
+                if (kn < ke) {
+#pragma unroll
+                    for (int u = 0; u < U; ++u) ring[g * U + u] = ldg(rt, (kn + u) * 64 + lane);
+                }
+            }
+            pair_group<MODE, DIAG, CONTACT, MASK, NBK, U>(P, lane, k0 + g * U, low, A, posj2, orgj, ncj, rv, csum,
+                                                          fi, fj, zt);
+        }
+    }
 }
 
 // Sub-step range of a whole tile: 1..32 on a diagonal tile (lanes 0..31 only
@@ -394,14 +418,14 @@ __device__ __forceinline__ int jflush_at(int lane, int ke) { return (lane + ke) 
 // Dispatch on the tile's flags (uniform across the wavefront).
 enum { TF_DIAG = TILE_DIAG, TF_CONTACT = TILE_CONTACT, TF_MASK = TILE_MASK };
 
-template <int MODE, int NBK>
+template <int MODE, int NBK, int D>
 __device__ __forceinline__ void tile_dispatch(const int flags, const int kb, const int ke, const KParams &P,
                                               const int lane, const LaneI &A,
                                               const float4 *__restrict__ posj2, const int *__restrict__ orgj,
                                               const int ncj, const float *__restrict__ rt, const float csum,
                                               float fi[6], float fj[6], float &zt) {
-#define SCPS_TILE(D, C, M)                                                                                  \
-    tile_pass<MODE, D, C, M, NBK>(P, lane, kb, ke, A, posj2, orgj, ncj, rt, csum, fi, fj, zt)
+#define SCPS_TILE(DG, C, M)                                                                                 \
+    tile_pass<MODE, DG, C, M, NBK, D>(P, lane, kb, ke, A, posj2, orgj, ncj, rt, csum, fi, fj, zt)
     const bool diag = flags & TF_DIAG, con = flags & TF_CONTACT, mask = flags & TF_MASK;
     if (ModeTraits<MODE>::nb) {
         if (diag) {
@@ -598,8 +622,8 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WG / 256 > 0
             const float *rt = (tf & TF_CONTACT) ? S.ref + (int64_t)tile_index(I, J, S.ncb) * 4096 : nullptr;
             int nxt = 0;
             if (lane == 0) nxt = atomicAdd(&sh_next, 1);
-            tile_dispatch<PM_RMD, NBK>(tf, kb, ke, P, lane, A, pos + J * 128, org + J * 64, S.nc - J * 64, rt, 0.f,
-                                       fi, fj, zt);
+            tile_dispatch<PM_RMD, NBK, SCPS_PAIR_GROUP>(tf, kb, ke, P, lane, A, pos + J * 128, org + J * 64,
+                                                        S.nc - J * 64, rt, 0.f, fi, fj, zt);
             zacc += (double)zt;
             const int jo = J * 64 + jflush_at(lane, ke);
             const int ncomp = (tf & TF_CONTACT) ? 6 : 3;
@@ -820,8 +844,10 @@ hipError_t launch_scatter(const SysDesc *sysd, const RepDesc *reps, int R, int n
     return hipGetLastError();
 }
 
-// One wavefront per tile item; four per workgroup.  Partial sums go to the
-// float64 accumulators in global memory with hardware float64 atomics.  In
+// One wavefront per tile item; four per workgroup.  Force partial sums go to
+// the float64 accumulators in global memory with hardware float64 atomics;
+// the item's z partial to zpart[item] (summed per replica in a fixed order by
+// k_finalize_rmd / k_reduce_z, so no two tiles meet on one address).  In
 // PM_SCPS the contact reference of replica r is its effective reference
 // E + eoff_r (written by k_scps_eff) and csum[r] = sum_k c_k.
 template <int MODE, int NBK>
@@ -829,18 +855,26 @@ __global__ __launch_bounds__(256) void k_pairs(const KParams P, const SysDesc *_
                                                const RepDesc *__restrict__ reps,
                                                const TileItem *__restrict__ items, const int n_items,
                                                const float4 *__restrict__ xs, double *__restrict__ acc,
-                                               double *__restrict__ zbuf, const float *__restrict__ eff,
+                                               double *__restrict__ zpart, const float *__restrict__ eff,
                                                const double *__restrict__ csum) {
     using T = ModeTraits<MODE>;
-    const int lane = threadIdx.x & 63;
-    const int item = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (item >= n_items) return;
-    const TileItem it = items[item];
+    __shared__ float4 shpos[4][128];   // block J of each wavefront's item, stored twice
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int item = blockIdx.x * 4 + wave;
+    const bool live = item < n_items;
+    const TileItem it = items[live ? item : 0];
     const RepDesc rd = reps[it.rep];
     const SysDesc S = sysd[rd.sys];
     const int I = it.I, J = it.J, tf = it.flags;
     const int n = S.n, n_pad = S.n_pad;
     const float4 *xr2 = xs + 2 * rd.poff;
+    {
+        const float4 pj = xr2[J * 128 + lane];
+        shpos[wave][lane] = pj;
+        shpos[wave][64 + lane] = pj;
+    }
+    __syncthreads();
+    if (!live) return;
     LaneI A;
     const int i = I * 64 + lane;
     A.p = xr2[I * 128 + lane];
@@ -866,8 +900,8 @@ __global__ __launch_bounds__(256) void k_pairs(const KParams P, const SysDesc *_
     }
     const bool diag = tf & TF_DIAG;
     const int kb = tile_kbeg(diag), ke = tile_kend(diag);
-    tile_dispatch<MODE, NBK>(tf, kb, ke, P, lane, A, xr2 + J * 128, S.perm + J * 64, S.nc - J * 64, rt, cs, fi, fj,
-                             zt);
+    tile_dispatch<MODE, NBK, 4 * SCPS_PAIR_GROUP>(tf, kb, ke, P, lane, A, shpos[wave], S.perm + J * 64,
+                                                  S.nc - J * 64, rt, cs, fi, fj, zt);
     const int jo = J * 64 + jflush_at(lane, ke);
     double *ar = acc + 6 * rd.poff;
     if constexpr (T::nb) {
@@ -901,16 +935,16 @@ __global__ __launch_bounds__(256) void k_pairs(const KParams P, const SysDesc *_
     }
     if constexpr (T::z) {
         const double zw = wave_sum((double)zt);
-        if (lane == 0 && contact_tile) unsafeAtomicAdd(&zbuf[it.rep], zw);
+        if (lane == 0) zpart[item] = contact_tile ? zw : 0.0;
     }
 }
 
 template <int MODE>
 static void launch_pairs_mode(int nbk, dim3 grid, dim3 block, hipStream_t st, const KParams &P,
                               const SysDesc *sysd, const RepDesc *reps, const TileItem *items, int n_items,
-                              const float4 *xs, double *acc, double *zbuf, const float *eff, const double *csum) {
+                              const float4 *xs, double *acc, double *zpart, const float *eff, const double *csum) {
 #define SCPS_LAUNCH(K)                                                                                   \
-    hipLaunchKernelGGL((k_pairs<MODE, K>), grid, block, 0, st, P, sysd, reps, items, n_items, xs, acc, zbuf, \
+    hipLaunchKernelGGL((k_pairs<MODE, K>), grid, block, 0, st, P, sysd, reps, items, n_items, xs, acc, zpart, \
                        eff, csum)
     if constexpr (!ModeTraits<MODE>::nb) {
         SCPS_LAUNCH(0);
@@ -926,34 +960,43 @@ static void launch_pairs_mode(int nbk, dim3 grid, dim3 block, hipStream_t st, co
 }
 
 hipError_t launch_pairs(int mode, int nbk, const KParams &P, const SysDesc *sysd, const RepDesc *reps,
-                        const TileItem *items, int n_items, const float4 *xs, double *acc, double *zbuf,
+                        const TileItem *items, int n_items, const float4 *xs, double *acc, double *zpart,
                         const float *eff, const double *csum, hipStream_t st) {
     if (n_items == 0) return hipSuccess;
     const dim3 grid((n_items + 3) / 4), block(256);
     switch (mode) {
     case PM_RMD:
-        launch_pairs_mode<PM_RMD>(nbk, grid, block, st, P, sysd, reps, items, n_items, xs, acc, zbuf, eff, csum);
+        launch_pairs_mode<PM_RMD>(nbk, grid, block, st, P, sysd, reps, items, n_items, xs, acc, zpart, eff, csum);
         break;
     case PM_Z:
-        launch_pairs_mode<PM_Z>(nbk, grid, block, st, P, sysd, reps, items, n_items, xs, acc, zbuf, eff, csum);
+        launch_pairs_mode<PM_Z>(nbk, grid, block, st, P, sysd, reps, items, n_items, xs, acc, zpart, eff, csum);
         break;
     case PM_ZG:
-        launch_pairs_mode<PM_ZG>(nbk, grid, block, st, P, sysd, reps, items, n_items, xs, acc, zbuf, eff, csum);
+        launch_pairs_mode<PM_ZG>(nbk, grid, block, st, P, sysd, reps, items, n_items, xs, acc, zpart, eff, csum);
         break;
     default:
-        launch_pairs_mode<PM_SCPS>(nbk, grid, block, st, P, sysd, reps, items, n_items, xs, acc, zbuf, eff, csum);
+        launch_pairs_mode<PM_SCPS>(nbk, grid, block, st, P, sysd, reps, items, n_items, xs, acc, zpart, eff, csum);
         break;
     }
     return hipGetLastError();
 }
 
-// rMD ratchet per replica, eq (FrMD); zbuf is consumed and cleared.
-__global__ void k_finalize_rmd(const KParams P, const int R, double *__restrict__ zbuf, double *__restrict__ cv,
-                               double *__restrict__ scale) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= R) return;
-    const double z = zbuf[r];
-    zbuf[r] = 0.0;
+// z of replica r: the sum of its items' partials zpart[first[r] .. first[r+1])
+// (items are stored replica by replica), one wavefront per replica, in a
+// fixed order.
+__device__ __forceinline__ double replica_z(const int *__restrict__ first, const double *__restrict__ zpart, int r,
+                                           int lane) {
+    double z = 0.0;
+    for (int t = first[r] + lane; t < first[r + 1]; t += 64) z += zpart[t];
+    return wave_sum(z);
+}
+
+// rMD ratchet per replica, eq (FrMD), from the replica's z.
+__global__ void k_finalize_rmd(const KParams P, const int *__restrict__ first, const double *__restrict__ zpart,
+                               double *__restrict__ cv, double *__restrict__ scale) {
+    const int r = blockIdx.x;
+    const double z = replica_z(first, zpart, r, threadIdx.x);
+    if (threadIdx.x != 0) return;
     double *c = cv + (int64_t)r * CV_STRIDE;
     const double zm = fmin(c[CV_ZM], z);
     const double dz = z - zm;
@@ -963,10 +1006,18 @@ __global__ void k_finalize_rmd(const KParams P, const int R, double *__restrict_
     scale[r] = -P.k_R * dz;
 }
 
-hipError_t launch_finalize_rmd(const KParams &P, int R, double *zbuf, double *cv, double *scale, hipStream_t st) {
-    hipLaunchKernelGGL(k_finalize_rmd, dim3((R + 255) / 256), dim3(256), 0, st, P, R, zbuf, cv, scale);
+hipError_t launch_finalize_rmd(const KParams &P, int R, const int *first, const double *zpart, double *cv,
+                               double *scale, hipStream_t st) {
+    hipLaunchKernelGGL(k_finalize_rmd, dim3(R), dim3(64), 0, st, P, first, zpart, cv, scale);
     return hipGetLastError();
 }
+
+__global__ void k_reduce_z(const int *__restrict__ first, const double *__restrict__ zpart, double *__restrict__ z) {
+    const int r = blockIdx.x;
+    const double v = replica_z(first, zpart, r, threadIdx.x);
+    if (threadIdx.x == 0) z[r] = v;
+}
+
 
 // SCPS tube variables per replica (one wavefront each), from the squared
 // distances d_k Z0 = sum_p (C_p - R_kp)^2 to every frame k = 0..M of the
@@ -1072,7 +1123,7 @@ __device__ __forceinline__ bool tile_pair_counts(bool diag, int s, int l) {
     return !diag || (s >= 1 && (s < 32 || (s == 32 && l < 32)));
 }
 
-// Pair-major copy of a frame stack: stack_pm[tile][p][k] = stack[k][tile][p]
+// Pair-major copy of a frame stack: stack_pm[tile][p][k] = stack[tile][k][p]
 // for k < K (zero for K <= k < K4), and R2[k] += sum over the counted pairs of
 // R_kp^2 (float64; pairs within min_seq_sep, outside the contact set or
 // repeated in a diagonal tile are not counted).  One workgroup per (tile,
@@ -1089,10 +1140,9 @@ __global__ __launch_bounds__(256) void k_stack_pairmajor(int nc, int ncb, int nt
     const int tid = threadIdx.x;
     if (tid < KMAX) r2s[tid] = 0.0;
     __syncthreads();
-    const int64_t kstride = (int64_t)ntile * 4096;
     for (int e = tid; e < 64 * K; e += 256) {
         const int k = e >> 6, l = e & 63;
-        const float v = stack[k * kstride + (int64_t)tile * 4096 + s * 64 + l];
+        const float v = stack[((int64_t)tile * K + k) * 4096 + s * 64 + l];
         buf[l][k] = v;
         const int a = I * 64 + l, b = J * 64 + ((l + s) & 63);
         const bool counts = a < nc && b < nc && tile_pair_counts(I == J, s, l) && abs(perm[a] - perm[b]) > min_sep;
@@ -1152,32 +1202,52 @@ __device__ __forceinline__ void scps_dist_tile(const KParams &P, const SysDesc &
     const int rs = lane & 15, pq = lane >> 4;
     const bool rep0 = rs < nrep, rep1 = rs + 16 < nrep;
     const bool bload = 4 * rs < K4;
-    const float *Rt = S.stack_pm + (int64_t)it.tile * 4096 * K4;
+    const float *Rt = S.stack_pm + (int64_t)it.tile * 4096 * K4 + 4 * rs;
     const int sb = diag ? 1 : 0, se = diag ? 33 : 64;
+    // B operands of a group of 4 MFMA steps (pairs s*64 + 4m + pq), loaded one
+    // group ahead of their use so that the loads overlap the MFMAs
+    float4 cur[4], nxt[4];
+    const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    {
+        const int s0 = sb + wave;
+        const float *Rn = Rt + (int64_t)(s0 * 64 + pq) * K4;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            cur[u] = (bload && s0 < se) ? *reinterpret_cast<const float4 *>(Rn + (int64_t)(4 * u) * K4) : zero4;
+    }
 #pragma unroll 1
     for (int s = sb + wave; s < se; s += 4) {
-        const float *Rs = Rt + (int64_t)(s * 64 + pq) * K4 + 4 * rs;
-#pragma unroll 4
-        for (int m = 0; m < 16; ++m) {
-            const int l = 4 * m + pq;                 // i within block I
-            const int jl = (l + s) & 63;              // j within block J
-            bool ok = tile_pair_counts(diag, s, l);
-            if constexpr (MASK) {
-                ok = ok & (I * 64 + l < S.nc) & (J * 64 + jl < S.nc) & (abs(org[0][l] - org[1][jl]) > P.min_sep);
-            }
-            const float4 b4 = bload ? *reinterpret_cast<const float4 *>(Rs + (int64_t)(4 * m) * K4)
-                                    : make_float4(0.f, 0.f, 0.f, 0.f);
-            const float c0 = contact_operand(P, pos[0][l][rs], pos[1][jl][rs], ok & rep0);
-            const float c1 = contact_operand(P, pos[0][l][rs + 16], pos[1][jl][rs + 16], ok & rep1);
-            const double a0 = (double)c0, a1 = (double)c1;
-            q0 = fma(a0, a0, q0);
-            q1 = fma(a1, a1, q1);
-            const double b[4] = {(double)b4.x, (double)b4.y, (double)b4.z, (double)b4.w};
+#pragma unroll 1
+        for (int mg = 0; mg < 4; ++mg) {
+            const int ns = mg == 3 ? s + 4 : s, nm = mg == 3 ? 0 : 4 * (mg + 1);
+            const bool pf = bload && ns < se;
+            const float *Rn = Rt + (int64_t)(ns * 64 + pq + 4 * nm) * K4;
 #pragma unroll
-            for (int f = 0; f < 4; ++f) {
-                acc[0][f] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b[f], acc[0][f], 0, 0, 0);
-                acc[1][f] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b[f], acc[1][f], 0, 0, 0);
+            for (int u = 0; u < 4; ++u)
+                nxt[u] = pf ? *reinterpret_cast<const float4 *>(Rn + (int64_t)(4 * u) * K4) : zero4;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int l = 4 * (4 * mg + u) + pq;  // i within block I
+                const int jl = (l + s) & 63;           // j within block J
+                bool ok = tile_pair_counts(diag, s, l);
+                if constexpr (MASK) {
+                    ok = ok & (I * 64 + l < S.nc) & (J * 64 + jl < S.nc) &
+                         (abs(org[0][l] - org[1][jl]) > P.min_sep);
+                }
+                const float c0 = contact_operand(P, pos[0][l][rs], pos[1][jl][rs], ok & rep0);
+                const float c1 = contact_operand(P, pos[0][l][rs + 16], pos[1][jl][rs + 16], ok & rep1);
+                const double a0 = (double)c0, a1 = (double)c1;
+                q0 = fma(a0, a0, q0);
+                q1 = fma(a1, a1, q1);
+                const double b[4] = {(double)cur[u].x, (double)cur[u].y, (double)cur[u].z, (double)cur[u].w};
+#pragma unroll
+                for (int f = 0; f < 4; ++f) {
+                    acc[0][f] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b[f], acc[0][f], 0, 0, 0);
+                    acc[1][f] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b[f], acc[1][f], 0, 0, 0);
+                }
             }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) cur[u] = nxt[u];
         }
     }
 }
@@ -1304,8 +1374,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             __syncthreads();
         }
         const int K = S.K;
-        const int64_t kstride = (int64_t)S.ntile_c * 4096;
-        const float *Rt = S.stack + (int64_t)it.tile * 4096;
+        const float *Rt = S.stack + (int64_t)it.tile * K * 4096;
 #pragma unroll 1
         for (int ch = wave; ch < 32; ch += 4) {
             const int p = ch * 128 + 4 * slot;
@@ -1318,7 +1387,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             for (int kk = 0; kk < KMAX / 2; ++kk) {
                 if (2 * kk < K) {
                     const int k = 2 * kk + half;
-                    const float4 b = k < K ? *reinterpret_cast<const float4 *>(Rt + k * kstride + p)
+                    const float4 b = k < K ? *reinterpret_cast<const float4 *>(Rt + k * 4096 + p)
                                            : make_float4(0.f, 0.f, 0.f, 0.f);
                     acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(creg[kk], b.x, acc[0], 0, 0, 0);
                     acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(creg[kk], b.y, acc[1], 0, 0, 0);
@@ -1417,15 +1486,12 @@ hipError_t launch_integrate(const KParams &P, const SysDesc *sysd, const RepDesc
 
 // z and coef * grad z out of the accumulators (eval_z_and_grad); clears them.
 __global__ void k_eval_out(const SysDesc *__restrict__ sysd, const RepDesc *__restrict__ reps,
-                           double *__restrict__ acc, double *__restrict__ zbuf, double *__restrict__ z_out,
-                           float *__restrict__ grad, const double *__restrict__ grad_coef) {
+                           double *__restrict__ acc, float *__restrict__ grad, const double *__restrict__ grad_coef) {
     const int r = blockIdx.y;
     const RepDesc rd = reps[r];
     const SysDesc S = sysd[rd.sys];
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
-    if (a == 0 && blockIdx.x == 0 && z_out) z_out[r] = zbuf[r];
     if (a >= S.n) return;
-    if (!grad) return;
     const int n = S.n, n_pad = S.n_pad;
     double *ar = acc + 6 * rd.poff;
     const double cf = grad_coef ? grad_coef[r] : 1.0;
@@ -1438,16 +1504,13 @@ __global__ void k_eval_out(const SysDesc *__restrict__ sysd, const RepDesc *__re
     }
 }
 
-__global__ void k_clear_z(int R, double *zbuf) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r < R) zbuf[r] = 0.0;
-}
-
 hipError_t launch_eval_out(const SysDesc *sysd, const RepDesc *reps, int R, int n_pad_max, double *acc,
-                           double *zbuf, double *z_out, float *grad, const double *grad_coef, hipStream_t st) {
-    hipLaunchKernelGGL(k_eval_out, dim3((n_pad_max + 255) / 256, R), dim3(256), 0, st, sysd, reps, acc, zbuf, z_out,
-                       grad, grad_coef);
-    hipLaunchKernelGGL(k_clear_z, dim3((R + 255) / 256), dim3(256), 0, st, R, zbuf);
+                           const int *first, const double *zpart, double *z_out, float *grad, const double *grad_coef,
+                           hipStream_t st) {
+    hipLaunchKernelGGL(k_reduce_z, dim3(R), dim3(64), 0, st, first, zpart, z_out);
+    if (grad)
+        hipLaunchKernelGGL(k_eval_out, dim3((n_pad_max + 255) / 256, R), dim3(256), 0, st, sysd, reps, acc, grad,
+                           grad_coef);
     return hipGetLastError();
 }
 
@@ -1527,7 +1590,7 @@ __global__ void k_pack_to_tiles(int nc, int ncb, int ntile, const double *__rest
     tile_decode(tile, ncb, I, J);
     const int64_t P = (int64_t)nc * (nc - 1) / 2;
     const double *pm = packed + (int64_t)map * P;
-    float *t = tiles + ((int64_t)map * ntile + tile) * 4096;
+    float *t = tiles + ((int64_t)tile * gridDim.y + map) * 4096;   // [tile][map][4096]
     const int l = threadIdx.x & 63;
     const int a = I * 64 + l;
     for (int k = threadIdx.x >> 6; k < 64; k += 4) {
@@ -1603,7 +1666,7 @@ __global__ __launch_bounds__(256) void k_update_reference(int n, int nc, int ncb
             sum[kk] += contact_f64(dx * dx + dy * dy + dz * dz, r0, r_cut);
         }
     }
-    float *t = tiles + ((int64_t)f * ntile + tile) * 4096;
+    float *t = tiles + ((int64_t)tile * gridDim.y + f) * 4096;     // [tile][frame][4096]
     const int64_t P = (int64_t)nc * (nc - 1) / 2;
 #pragma unroll
     for (int kk = 0; kk < 16; ++kk) {
