@@ -510,7 +510,7 @@ scps_status set_ref_impl(scps_ctx *c, int32_t s, int32_t n_maps, const double *m
         if (!h.d_ref) HIP_TRY(c, dalloc(c, &h.d_ref, (size_t)h.ntile_c * 4096));
         double *d_packed = nullptr, *d_sum = nullptr;
         HIP_TRY(c, dalloc(c, &d_packed, (size_t)std::max<int64_t>(P, 1)));
-        HIP_TRY(c, dalloc(c, &d_sum, 1));
+        HIP_TRY(c, dalloc(c, &d_sum, 1 + sum_squares_scratch()));
         if (maps) {
             HIP_TRY(c, hipMemcpy(d_packed, maps, P * sizeof(double), hipMemcpyHostToDevice));
             HIP_TRY(c, launch_pack_to_tiles(1, h.nc, h.ncb, d_packed, h.d_ref, c->stream));
@@ -525,7 +525,7 @@ scps_status set_ref_impl(scps_ctx *c, int32_t s, int32_t n_maps, const double *m
         }
         double zz = z0;
         if (!(z0 > 0.0)) {
-            HIP_TRY(c, launch_sum_squares(P, d_packed, d_sum, c->stream));
+            HIP_TRY(c, launch_sum_squares(P, d_packed, d_sum + 1, d_sum, c->stream));
             HIP_TRY(c, hipStreamSynchronize(c->stream));
             HIP_TRY(c, hipMemcpy(&zz, d_sum, sizeof(double), hipMemcpyDeviceToHost));
         }

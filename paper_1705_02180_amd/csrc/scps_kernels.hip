@@ -1608,18 +1608,37 @@ hipError_t launch_pack_to_tiles(int n_maps, int nc, int ncb, const double *packe
     return hipGetLastError();
 }
 
-__global__ void k_sum_squares(int64_t m, const double *__restrict__ v, double *__restrict__ out) {
-    __shared__ double part[4];
+// sum_i v_i^2 in two fixed-order phases: SUMSQ_BLOCKS workgroups each reduce
+// a contiguous chunk into part[], then one workgroup adds the partials.
+constexpr int SUMSQ_BLOCKS = 256;
+__global__ void k_sum_squares(int64_t m, const double *__restrict__ v, double *__restrict__ part,
+                              double *__restrict__ out) {
+    __shared__ double red[4];
+    const int64_t chunk = (m + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = (int64_t)blockIdx.x * chunk, hi = lo + chunk < m ? lo + chunk : m;
     double s = 0.0;
-    for (int64_t e = threadIdx.x; e < m; e += blockDim.x) s += v[e] * v[e];
+    for (int64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) s += v[e] * v[e];
     s = wave_sum(s);
-    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();
-    if (threadIdx.x == 0) *out = part[0] + part[1] + part[2] + part[3];
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
-hipError_t launch_sum_squares(int64_t m, const double *v, double *out, hipStream_t st) {
-    hipLaunchKernelGGL(k_sum_squares, dim3(1), dim3(256), 0, st, m, v, out);
+__global__ void k_sum_parts(int n, const double *__restrict__ part, double *__restrict__ out) {
+    __shared__ double red[4];
+    double s = 0.0;
+    for (int e = threadIdx.x; e < n; e += blockDim.x) s += part[e];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) *out = red[0] + red[1] + red[2] + red[3];
+}
+
+int sum_squares_scratch() { return SUMSQ_BLOCKS; }
+
+hipError_t launch_sum_squares(int64_t m, const double *v, double *part, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_sum_squares, dim3(SUMSQ_BLOCKS), dim3(256), 0, st, m, v, part, out);
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, st, SUMSQ_BLOCKS, part, out);
     return hipGetLastError();
 }
 
