@@ -38,7 +38,7 @@
  * - cvstate: float64 [R][SCPS_CV_STRIDE], see the SCPS_CV_* slots.  The
  *   running minima z_m, s_m, w_m start at +INFINITY; the first force
  *   evaluation then sets them to the current value (z_m(0) = z(X(0)), as in
- *   the rMD section of the paper).
+ *   the rMD section of the paper); the bias functional T starts at 0.
  * - Contact maps are packed upper triangles over a system's contact set:
  *   for contact positions a<b (indices into contact_idx) the entry sits at
  *   a*n_c - a*(a+1)/2 + (b-a-1); P = n_c*(n_c-1)/2 entries per map.
@@ -73,7 +73,13 @@ enum {
     SCPS_CV_S = 3,   /* s_lambda (SCPS) */
     SCPS_CV_W = 4,   /* w_lambda (SCPS), without the constant w0 */
     SCPS_CV_SM = 5,  /* running minimum s_m (SCPS) */
-    SCPS_CV_WM = 6   /* running minimum w_m (SCPS) */
+    SCPS_CV_WM = 6,  /* running minimum w_m (SCPS) */
+    SCPS_CV_T = 7    /* bias functional T[X] accumulated along the path:
+                        every force evaluation adds dt * sum_i |F_bias,i|^2 /
+                        (m_i gamma) (rMD section and eq (T); the paper's
+                        Gamma_i = 1/(4 gamma_i m_i k_B T) only rescales T).
+                        The least biased path of an ensemble is the replica
+                        with the smallest T.  Start it at 0. */
 };
 
 enum { SCPS_INTEGRATOR_OVERDAMPED = 0, SCPS_INTEGRATOR_BAOAB = 1 };

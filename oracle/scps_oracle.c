@@ -21,7 +21,10 @@
  *     driven by Philox4x32-10 noise (Salmon, Moraes, Dror, Shaw, SC'11);
  *   - the path-ensemble mean contact map, eq (avCij);
  *   - the mean-field tube variables s_lambda, w_lambda, eqs (asXa),(awXa)
- *     discretised as in the appendix, and their ratchet forces (Fw),(Fs).
+ *     discretised as in the appendix, and their ratchet forces (Fw),(Fs);
+ *   - the bias functional T[X] of the bias-functional variational principle
+ *     (rMD section, eq (T) and the protocol's variational correction),
+ *     accumulated over the path as T += dt sum_i |F_bias,i|^2 / (m_i gamma).
  *
  * Readings where the paper is silent (all documented in the design notes):
  *   - the sum in eq (zrMD) runs over unordered pairs i<j of the contact
@@ -32,7 +35,11 @@
  *     because only differences w - w_m and gradients enter the forces;
  *   - the SCPS ratchets use (s - s_m) and (w - w_m) as in eqs (Fw),(Fs);
  *   - BAOAB is used for the underdamped equation and its state velocity
- *     is the one right after the friction/noise substep.
+ *     is the one right after the friction/noise substep;
+ *   - T[X] takes the prefactor 1/(m_i gamma_i) of the rMD section and of the
+ *     protocol (eq (T) writes Gamma_i = 1/(4 gamma_i m_i k_B T), which only
+ *     rescales every path's T by the same constant), and the time integral
+ *     as a left Riemann sum over the force evaluations of the steps taken.
  */
 #include <math.h>
 #include <stdint.h>
@@ -43,7 +50,7 @@
 #endif
 
 #define ORC_CV_STRIDE 8
-enum { CV_Z = 0, CV_ZM = 1, CV_EB = 2, CV_S = 3, CV_W = 4, CV_SM = 5, CV_WM = 6 };
+enum { CV_Z = 0, CV_ZM = 1, CV_EB = 2, CV_S = 3, CV_W = 4, CV_SM = 5, CV_WM = 6, CV_T = 7 };
 
 typedef struct {
     int32_t integrator;      /* 0 overdamped Euler-Maruyama, 1 BAOAB */
@@ -393,6 +400,8 @@ void orc_total_force(const orc_params *p, const orc_system *s, const double *x,
  *                    opening half kick of this one)
  *     x += dt/2 v;  v = c1 v + sqrt((1-c1^2) kT/m) xi, c1 = exp(-gamma dt);
  *     x += dt/2 v
+ * Every force evaluation also adds dt sum_i |F_bias,i|^2 / (m_i gamma) to
+ * the bias functional cv[CV_T].
  * Frames (may be NULL) receive X at local step indices 0, E, 2E, ... <=
  * n_steps, each as [3][n], stride frame_stride doubles.
  * ---------------------------------------------------------------------- */
@@ -402,13 +411,22 @@ void orc_steps(const orc_params *p, const orc_system *s, uint32_t replica_id,
 {
     int n = s->n;
     double *F = (double *)malloc(sizeof(double) * 3 * n);
+    double *Fb = (double *)malloc(sizeof(double) * 3 * n);
     double c1 = exp(-p->gamma * p->dt);
     for (int64_t m = 0; m <= n_steps; ++m) {
         if (frames && record_every > 0 && m % record_every == 0)
             memcpy(frames + (m / record_every) * frame_stride, x, sizeof(double) * 3 * n);
         if (m == n_steps) break;
         uint64_t step = step0 + (uint64_t)m;
-        orc_total_force(p, s, x, cv, F, NULL);
+        orc_total_force(p, s, x, cv, F, Fb);
+        /* bias functional: T += dt sum_i |F_bias,i|^2 / (m_i gamma) */
+        double t = 0.0;
+        for (int i = 0; i < n; ++i) {
+            double f2 = 0.0;
+            for (int c = 0; c < 3; ++c) f2 += Fb[c * n + i] * Fb[c * n + i];
+            t += f2 / ((double)s->mass[i] * p->gamma);
+        }
+        cv[CV_T] += p->dt * t;
         for (int i = 0; i < n; ++i) {
             double xi[3];
             orc_normals(p->seed, (uint32_t)i, replica_id, step, xi);
@@ -428,6 +446,7 @@ void orc_steps(const orc_params *p, const orc_system *s, uint32_t replica_id,
         }
     }
     free(F);
+    free(Fb);
 }
 
 /* Batched driver: replicas r = 0..R-1 of systems replica_system[r], state

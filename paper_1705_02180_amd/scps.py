@@ -22,7 +22,7 @@ if not os.path.exists(LIB_PATH):
                       "(or __graft_entry__.build())")
 
 CV_STRIDE = 8
-CV_Z, CV_ZM, CV_EB, CV_S, CV_W, CV_SM, CV_WM = range(7)
+CV_Z, CV_ZM, CV_EB, CV_S, CV_W, CV_SM, CV_WM, CV_T = range(8)   # CV_T: bias functional T[X]
 STATUS = {0: "OK", -1: "INVALID_ARG", -2: "SHAPE", -3: "OOM", -4: "HIP", -5: "STATE",
           -6: "NONFINITE", -7: "NO_SUCCESS"}
 
