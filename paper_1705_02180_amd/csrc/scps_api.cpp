@@ -30,8 +30,11 @@ struct SysHost {
     int n = 0, n_pad = 0, nb = 0, nc = 0, ncb = 0, ntile_c = 0;
     std::vector<int> perm, bond_next;
     std::vector<int> tile_flags;        // [nb * nb], entry I * nb + J for I <= J
+    std::vector<uint64_t> tile_mask;    // [nb * nb]: sub-steps that need the per-pair predicates
     std::vector<int2> sched;            // persistent-kernel tile list, costliest first
+    std::vector<uint64_t> sched_mask;   // its sub-step masks
     int2 *d_sched = nullptr;
+    uint64_t *d_sched_mask = nullptr;
     std::vector<float> mass, charge;
     int *d_perm = nullptr, *d_bond_next = nullptr;
     float *d_mass = nullptr, *d_charge = nullptr;
@@ -119,8 +122,8 @@ KParams make_kparams(const scps_params &p) {
     k.cp[3] = (float)(-3.0 * 4.0 / (p.r0_contact * p.r0_contact));
     k.has_cut = p.r_cut_contact > 0.0;
     k.r_cut2 = (float)(p.r_cut_contact * p.r_cut_contact);
-    k.lj_sig2 = (float)(p.lj_sigma * p.lj_sigma);
-    k.lj_24eps = (float)(24.0 * p.lj_eps);
+    k.lj_A = (float)(48.0 * p.lj_eps * pow(p.lj_sigma, 12));
+    k.lj_B = (float)(24.0 * p.lj_eps * pow(p.lj_sigma, 6));
     k.has_lj = p.lj_eps != 0.0;
     k.dh_pref = (float)p.dh_prefactor;
     k.dh_kappa = (float)p.dh_kappa;
@@ -167,6 +170,7 @@ scps_status upload_sysdesc(scps_ctx *c) {
         o.stack_pm = h.d_stack_pm;
         o.R2 = h.d_R2;
         o.tiles = h.d_sched;
+        o.tmask = h.d_sched_mask;
         o.ntile = (int)h.sched.size();
         o.Z0 = h.Z0;
     }
@@ -194,40 +198,48 @@ int pick_wg(int nb) {
     return 64;
 }
 
-// Per-tile flags of a system (see TILE_* in scps_internal.h).
+// Per-tile flags and sub-step masks of a system (see TILE_* in scps_internal.h).
 void compute_tile_flags(SysHost &h, const scps_params &p) {
     const int nb = h.nb;
     h.tile_flags.assign((size_t)nb * nb, 0);
+    h.tile_mask.assign((size_t)nb * nb, 0);
     std::vector<int> inv(h.n);
     for (int a = 0; a < h.n; ++a) inv[h.perm[a]] = a;
-    std::vector<char> masked((size_t)nb * nb, 0);
+    // pairs that need a predicate: chain neighbours excluded from the
+    // nonbonded sum, contact pairs within min_seq_sep
     for (int a = 0; a < h.n; ++a) {
         const int o = h.perm[a];
         for (int d = 1; d <= std::max(p.nb_excl, p.min_seq_sep) && o + d < h.n; ++d) {
             const int b = inv[o + d];
-            const int lo = std::min(a, b), hi = std::max(a, b);
             const bool contact_close = d <= p.min_seq_sep && a < h.nc && b < h.nc;
-            if (d <= p.nb_excl || contact_close) masked[(size_t)(lo / TILE) * nb + hi / TILE] = 1;
+            if (!(d <= p.nb_excl || contact_close)) continue;
+            const int lo = std::min(a, b), hi = std::max(a, b);
+            const int I = lo / TILE, J = hi / TILE;
+            int k = ((hi % TILE) - (lo % TILE) + TILE) % TILE;
+            if (I == J) k = std::min(k, TILE - k);   // a diagonal tile meets the pair at separations 1..32
+            h.tile_mask[(size_t)I * nb + J] |= 1ull << k;
         }
     }
     for (int I = 0; I < nb; ++I)
         for (int J = I; J < nb; ++J) {
             int f = 0;
+            uint64_t &m = h.tile_mask[(size_t)I * nb + J];
             if (I == J) f |= TILE_DIAG;
-            bool mask = masked[(size_t)I * nb + J];
             if (I < h.ncb && J < h.ncb) {
                 f |= TILE_CONTACT;
-                mask = mask || (J + 1) * TILE > h.nc || p.r_cut_contact > 0.0;
+                if ((J + 1) * TILE > h.nc || p.r_cut_contact > 0.0) m = ~0ull;
             }
-            if (mask) f |= TILE_MASK;
+            if (m) f |= TILE_MASK;
             h.tile_flags[(size_t)I * nb + J] = f;
         }
 }
 
-// Relative cost of a tile pair, for load balancing.
-double tile_cost(int f) {
+// Relative cost of a tile pair, for load balancing: a contact tile costs
+// about 1.85 nonbonded-only tiles; the predicated sub-steps about 25 % more.
+double tile_cost(int f, uint64_t mask) {
     double c = (f & TILE_CONTACT) ? 1.85 : 1.0;
-    if (f & TILE_MASK) c *= 1.15;
+    const double steps = (f & TILE_DIAG) ? 32.0 : 64.0;
+    c *= 1.0 + 0.25 * std::min(1.0, __builtin_popcountll(mask) / steps);
     if (f & TILE_DIAG) c *= 0.5;
     return c;
 }
@@ -237,38 +249,52 @@ double tile_cost(int f) {
 // the same class (contact, mask) are paired; every tile or pair is cut into
 // segments of SEG_STEPS sub-steps (see SEG_STEPS for the encoding).
 void build_schedule(SysHost &h) {
-    std::vector<std::pair<double, int2>> all;
+    struct Item {
+        double cost;
+        int2 code;
+        uint64_t mask;
+    };
+    std::vector<Item> all;
     auto push = [&](int I1, int I2, int J, int f, double cost) {
         const int kb = (f & TILE_DIAG) ? 1 : 0, ke = (f & TILE_DIAG) ? 33 : 64;
+        uint64_t m = h.tile_mask[(size_t)I1 * h.nb + J];
+        if (I2 >= 0) m |= h.tile_mask[(size_t)I2 * h.nb + J];
+        if (m) f |= TILE_MASK;
         for (int k = kb; k < ke; k += SEG_STEPS)
             all.push_back({cost * std::min(SEG_STEPS, ke - k) / 64.0,
-                           make_int2((I1 << 16) | J, f | ((I2 + 1) << 8) | (k << 24))});
+                           make_int2((I1 << 16) | J, f | ((I2 + 1) << 8) | (k << 24)), m});
     };
     for (int J = 0; J < h.nb; ++J) {
         std::vector<int> waiting(8, -1);   // per class, an unpaired row I
         for (int I = 0; I <= J; ++I) {
             const int f = h.tile_flags[(size_t)I * h.nb + J];
             if (I == J) {
-                push(I, -1, J, f, 2.0 * tile_cost(f));   // half the sub-steps, same cost per sub-step
+                push(I, -1, J, f, 2.0 * tile_cost(f, h.tile_mask[(size_t)I * h.nb + J]));   // half the sub-steps, same cost per sub-step
                 continue;
             }
             const int cls = f & (TILE_CONTACT | TILE_MASK);
             if (waiting[cls] < 0) {
                 waiting[cls] = I;
             } else {
-                push(waiting[cls], I, J, f, 2.0 * tile_cost(f));
+                push(waiting[cls], I, J, f,
+                     2.0 * tile_cost(f, h.tile_mask[(size_t)I * h.nb + J] |
+                                            h.tile_mask[(size_t)waiting[cls] * h.nb + J]));
                 waiting[cls] = -1;
             }
         }
         for (int cls = 0; cls < 8; ++cls)
             if (waiting[cls] >= 0) {
                 const int f = h.tile_flags[(size_t)waiting[cls] * h.nb + J];
-                push(waiting[cls], -1, J, f, tile_cost(f));
+                push(waiting[cls], -1, J, f, tile_cost(f, h.tile_mask[(size_t)waiting[cls] * h.nb + J]));
             }
     }
-    std::stable_sort(all.begin(), all.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
+    std::stable_sort(all.begin(), all.end(), [](const Item &a, const Item &b) { return a.cost > b.cost; });
     h.sched.clear();
-    for (const auto &t : all) h.sched.push_back(t.second);
+    h.sched_mask.clear();
+    for (const auto &t : all) {
+        h.sched.push_back(t.code);
+        h.sched_mask.push_back(t.mask);
+    }
 }
 
 scps_status init_impl(const scps_params *params, const scps_topology *topo, int32_t R, const int32_t *rsys,
@@ -375,6 +401,9 @@ scps_status init_impl(const scps_params *params, const scps_topology *topo, int3
         HIP_TRY(c, hipMemcpy(h.d_charge, h.charge.data(), h.n_pad * sizeof(float), hipMemcpyHostToDevice));
         HIP_TRY(c, dalloc(c, &h.d_sched, h.sched.size()));
         HIP_TRY(c, hipMemcpy(h.d_sched, h.sched.data(), h.sched.size() * sizeof(int2), hipMemcpyHostToDevice));
+        HIP_TRY(c, dalloc(c, &h.d_sched_mask, h.sched_mask.size()));
+        HIP_TRY(c, hipMemcpy(h.d_sched_mask, h.sched_mask.data(), h.sched_mask.size() * sizeof(uint64_t),
+                             hipMemcpyHostToDevice));
     }
     HIP_TRY(c, dalloc(c, &c->d_sysd, c->sys.size()));
     scps_status st = upload_sysdesc(c);
@@ -410,7 +439,7 @@ scps_status init_impl(const scps_params *params, const scps_topology *topo, int3
         const SysHost &h = c->sys[rsys[r]];
         for (int I = 0; I < h.nb; ++I)
             for (int J = I; J < h.nb; ++J) {
-                TileItem t{r, I, J, h.tile_flags[(size_t)I * h.nb + J]};
+                TileItem t{r, I, J, h.tile_flags[(size_t)I * h.nb + J], h.tile_mask[(size_t)I * h.nb + J]};
                 all.push_back(t);
                 if (I < h.ncb && J < h.ncb) con.push_back(t);
             }
@@ -591,7 +620,7 @@ scps_status step_impl(scps_ctx *c, float *x, float *v, double *cv, int64_t n_ste
                                     c->d_acc, c->d_zpart, nullptr, nullptr, c->stream));
             HIP_TRY(c, launch_finalize_rmd(c->kp, c->R, c->d_first_all, c->d_zpart, cv, c->d_scale, c->stream));
             HIP_TRY(c, launch_integrate(c->kp, c->d_sysd, c->d_reps, c->R, c->n_pad_max, c->d_xs, c->d_vs, c->d_acc,
-                                        c->d_scale, step0 + (uint64_t)m, c->d_flags, c->stream));
+                                        c->d_scale, cv, step0 + (uint64_t)m, c->d_flags, c->stream));
         } else {
             // distances to every frame (matrix cores), tube variables and
             // ratchets, effective references (matrix cores), bias + physics
@@ -604,7 +633,7 @@ scps_status step_impl(scps_ctx *c, float *x, float *v, double *cv, int64_t n_ste
             HIP_TRY(c, launch_pairs(3, c->nbk, c->kp, c->d_sysd, c->d_reps, c->d_items_all, c->n_items_all, c->d_xs,
                                     c->d_acc, c->d_zpart, c->d_E, c->d_csum, c->stream));
             HIP_TRY(c, launch_integrate(c->kp, c->d_sysd, c->d_reps, c->R, c->n_pad_max, c->d_xs, c->d_vs, c->d_acc,
-                                        c->d_negone, step0 + (uint64_t)m, c->d_flags, c->stream));
+                                        c->d_negone, cv, step0 + (uint64_t)m, c->d_flags, c->stream));
         }
     }
     HIP_TRY(c, launch_scatter(c->d_sysd, c->d_reps, c->R, c->n_pad_max, c->d_xs, v ? c->d_vs : nullptr, x, v,

@@ -9,7 +9,7 @@ namespace scps {
 constexpr int TILE = 64;          // tile edge = wavefront width
 constexpr int KMAX = 64;          // largest SCPS frame stack handled per pass
 constexpr int CV_STRIDE = 8;
-enum { CV_Z = 0, CV_ZM = 1, CV_EB = 2, CV_S = 3, CV_W = 4, CV_SM = 5, CV_WM = 6 };
+enum { CV_Z = 0, CV_ZM = 1, CV_EB = 2, CV_S = 3, CV_W = 4, CV_SM = 5, CV_WM = 6, CV_T = 7 };
 
 // Scalars every kernel needs, passed by value.
 struct KParams {
@@ -17,8 +17,8 @@ struct KParams {
     float g_scale;       // 4/r0^2: dz/dx_i = sum_j g_scale (C - R) C'(q) (x_i - x_j)
     float cp[4];         // -g_scale * {2, 4, 6, 3}: coefficients of -g_scale (3 + 6q + 4q^2 + 2q^3)
     float r_cut2;        // contact cutoff squared (used when has_cut)
-    float lj_sig2;       // sigma^2
-    float lj_24eps;      // 24 epsilon
+    float lj_A;          // 48 epsilon sigma^12
+    float lj_B;          // 24 epsilon sigma^6
     float dh_pref;       // k_e/eps_r
     float dh_kappa;
     float dh_kl2;        // -kappa * log2(e)
@@ -49,6 +49,7 @@ struct SysDesc {
     const float *stack_pm;   // the same frames pair-major: [ntile_c][64*64][stack_pm_width(K)]
     const double *R2;        // [K] sum over the counted contact pairs of R_k^2
     const int2 *tiles;       // persistent work list, costliest first (see build_schedule)
+    const uint64_t *tmask;   // per work-list item: sub-steps that need the per-pair predicates
     int ntile;
     int pad1;
     double Z0;
@@ -75,15 +76,21 @@ struct ScpsItem {
 };
 
 // A unit of pair work for the per-step kernels: one tile pair of one replica.
+// mask: bit k set when some pair the tile meets at sub-step k needs a per-pair
+// predicate (only MASK tiles evaluate them, and only on those sub-steps).
 struct TileItem {
     int rep, I, J, flags;
+    uint64_t mask;
 };
 
 // Tile flags, computed on the host.  CONTACT: both blocks hold contact-set
 // particles.  MASK: a per-pair predicate is needed, because the tile holds a
 // pair excluded from the nonbonded sum (|i-j| <= nb_excl) or its contact sum
 // does (a block that straddles the end of the contact set, a pair within
-// min_seq_sep, or a contact cutoff).
+// min_seq_sep, or a contact cutoff).  With it goes a 64-bit mask of the
+// sub-steps k at which such a pair is met: lane l of block I meets particle
+// (l + k) mod 64 of block J (a diagonal tile meets each pair at the smaller
+// of its two separations); a straddling block or a cutoff sets every bit.
 enum { TILE_DIAG = 1, TILE_CONTACT = 2, TILE_MASK = 4 };
 
 // The persistent kernel's work items are segments of SEG_STEPS sub-steps of a
@@ -140,7 +147,7 @@ hipError_t launch_finalize_scps(const KParams &P, const SysDesc *sysd, const Rep
                                 hipStream_t st);
 hipError_t launch_integrate(const KParams &P, const SysDesc *sysd, const RepDesc *reps, int R,
                             int n_pad_max, float4 *xs, float4 *vs, double *acc,
-                            const double *scale, uint64_t step, int *flags, hipStream_t st);
+                            const double *scale, double *cv, uint64_t step, int *flags, hipStream_t st);
 
 hipError_t launch_eval_out(const SysDesc *sysd, const RepDesc *reps, int R, int n_pad_max, double *acc,
                            const int *first, const double *zpart, double *z_out, float *grad,

@@ -128,15 +128,15 @@ __device__ __forceinline__ float pair_r2(const float4 &pi, const float4 &pj, flo
 }
 
 // Nonbonded scalar f with F_i += f (x_i - x_j):
-// f = [24 eps (2 s^12 - s^6) + k_e/eps_r q_i q_j e^{-kappa r} (kappa + 1/r)] / r^2, s = sigma / r.
+// f = [24 eps (2 s^12 - s^6) + k_e/eps_r q_i q_j e^{-kappa r} (kappa + 1/r)] / r^2, s = sigma / r,
+// the Lennard-Jones part evaluated as r^-6 (A r^-6 - B), A = 48 eps sigma^12, B = 24 eps sigma^6.
 // qp_i = k_e/eps_r * q_i.  NBK bit 0: Lennard-Jones, bit 1: Debye-Hueckel.
 template <int NBK>
 __device__ __forceinline__ float nb_scalar(const KParams &P, const float r2, const float qp_i, const float q_j) {
     if constexpr (NBK == 1) {
         const float inv_r2 = frcp(r2);
-        const float s2 = P.lj_sig2 * inv_r2;
-        const float s6 = s2 * s2 * s2;
-        return fmaf(s6, 2.f * P.lj_24eps, -P.lj_24eps) * s6 * inv_r2;
+        const float inv_r6 = inv_r2 * inv_r2 * inv_r2;
+        return fmaf(inv_r6, P.lj_A, -P.lj_B) * inv_r6 * inv_r2;
     } else if constexpr (NBK == 0) {
         return 0.f;
     } else {
@@ -146,9 +146,8 @@ __device__ __forceinline__ float nb_scalar(const KParams &P, const float r2, con
         const float e = fexp2(P.dh_kl2 * r) * (qp_i * q_j);
         float S = e * (P.dh_kappa + inv_r);
         if constexpr (NBK == 3) {
-            const float s2 = P.lj_sig2 * inv_r2;
-            const float s6 = s2 * s2 * s2;
-            S = fmaf(fmaf(s6, 2.f * P.lj_24eps, -P.lj_24eps), s6, S);
+            const float inv_r6 = inv_r2 * inv_r2 * inv_r2;
+            S = fmaf(fmaf(inv_r6, P.lj_A, -P.lj_B), inv_r6, S);
         }
         return S * inv_r2;
     }
@@ -338,27 +337,35 @@ __device__ __forceinline__ void pair_group2(const KParams &P, const int lane, co
     }
 }
 
+// MASK tiles evaluate the per-pair predicates only on the sub-step groups
+// whose bits are set in mk (bit k: some pair met at sub-step k needs one).
 template <int MODE, bool CONTACT, bool MASK, int NBK>
 __device__ __forceinline__ void tile_pass2(const KParams &P, const int lane, const int kb, const int ke,
-                                           const LaneI &A, const LaneI &B, const float4 *__restrict__ posj2,
-                                           const int *__restrict__ orgj, const int ncj,
-                                           const float *__restrict__ rtA, const float *__restrict__ rtB, float fa[6],
-                                           float fb[6], float fj[6], float &zt) {
+                                           const uint64_t mk, const LaneI &A, const LaneI &B,
+                                           const float4 *__restrict__ posj2, const int *__restrict__ orgj,
+                                           const int ncj, const float *__restrict__ rtA,
+                                           const float *__restrict__ rtB, float fa[6], float fb[6], float fj[6],
+                                           float &zt) {
     constexpr int U = SCPS_PAIR_GROUP2;
+    constexpr uint64_t GB = (1ull << U) - 1;
 #pragma unroll 1
-    for (int k0 = kb; k0 < ke; k0 += U)
-        pair_group2<MODE, CONTACT, MASK, NBK, U>(P, lane, k0, A, B, posj2, orgj, ncj, rtA, rtB, fa, fb, fj, zt);
+    for (int k0 = kb; k0 < ke; k0 += U) {
+        if (MASK && ((mk >> k0) & GB))
+            pair_group2<MODE, CONTACT, true, NBK, U>(P, lane, k0, A, B, posj2, orgj, ncj, rtA, rtB, fa, fb, fj, zt);
+        else
+            pair_group2<MODE, CONTACT, false, NBK, U>(P, lane, k0, A, B, posj2, orgj, ncj, rtA, rtB, fa, fb, fj, zt);
+    }
 }
 
 template <int MODE, int NBK>
-__device__ __forceinline__ void tile_dispatch2(const int flags, const int kb, const int ke, const KParams &P,
-                                               const int lane, const LaneI &A, const LaneI &B,
+__device__ __forceinline__ void tile_dispatch2(const int flags, const int kb, const int ke, const uint64_t mk,
+                                               const KParams &P, const int lane, const LaneI &A, const LaneI &B,
                                                const float4 *__restrict__ posj2, const int *__restrict__ orgj,
                                                const int ncj, const float *__restrict__ rtA,
                                                const float *__restrict__ rtB, float fa[6], float fb[6], float fj[6],
                                                float &zt) {
 #define SCPS_TILE2(C, M)                                                                                     \
-    tile_pass2<MODE, C, M, NBK>(P, lane, kb, ke, A, B, posj2, orgj, ncj, rtA, rtB, fa, fb, fj, zt)
+    tile_pass2<MODE, C, M, NBK>(P, lane, kb, ke, mk, A, B, posj2, orgj, ncj, rtA, rtB, fa, fb, fj, zt)
     const bool con = flags & TILE_CONTACT, mask = flags & TILE_MASK;
     if (con) { if (mask) SCPS_TILE2(true, true); else SCPS_TILE2(true, false); }
     else     { if (mask) SCPS_TILE2(false, true); else SCPS_TILE2(false, false); }
@@ -366,7 +373,9 @@ __device__ __forceinline__ void tile_dispatch2(const int flags, const int kb, co
 }
 
 // A whole tile pair, or a segment of one: sub-steps kb .. ke-1, a multiple of
-// D (every caller uses 32 or 64), evaluated SCPS_PAIR_GROUP at a time.  The
+// D (every caller uses 32 or 64), evaluated SCPS_PAIR_GROUP at a time; a
+// MASK tile evaluates the per-pair predicates only on the groups whose
+// sub-step bits are set in mk.  The
 // lane's reference values are loaded D sub-steps ahead of their use into a
 // ring of registers: D = 4 groups in the per-step kernels, whose maps stream
 // from HBM, one group where the map is cache-resident (persistent kernel).
@@ -375,7 +384,7 @@ __device__ __forceinline__ void tile_dispatch2(const int flags, const int kb, co
 // this lane's z partial.
 template <int MODE, bool DIAG, bool CONTACT, bool MASK, int NBK, int D>
 __device__ __forceinline__ void tile_pass(const KParams &P, const int lane, const int kb, const int ke,
-                                          const LaneI &A, const float4 *__restrict__ posj2,
+                                          const uint64_t mk, const LaneI &A, const float4 *__restrict__ posj2,
                                           const int *__restrict__ orgj, const int ncj, const float *__restrict__ rt,
                                           const float csum, float fi[6], float fj[6], float &zt) {
     constexpr int U = SCPS_PAIR_GROUP;
@@ -400,8 +409,12 @@ __device__ __forceinline__ void tile_pass(const KParams &P, const int lane, cons
                     for (int u = 0; u < U; ++u) ring[g * U + u] = ldg(rt, (kn + u) * 64 + lane);
                 }
             }
-            pair_group<MODE, DIAG, CONTACT, MASK, NBK, U>(P, lane, k0 + g * U, low, A, posj2, orgj, ncj, rv, csum,
-                                                          fi, fj, zt);
+            if (MASK && ((mk >> (k0 + g * U)) & ((1ull << U) - 1)))
+                pair_group<MODE, DIAG, CONTACT, true, NBK, U>(P, lane, k0 + g * U, low, A, posj2, orgj, ncj, rv,
+                                                              csum, fi, fj, zt);
+            else
+                pair_group<MODE, DIAG, CONTACT, false, NBK, U>(P, lane, k0 + g * U, low, A, posj2, orgj, ncj, rv,
+                                                               csum, fi, fj, zt);
         }
     }
 }
@@ -419,13 +432,14 @@ __device__ __forceinline__ int jflush_at(int lane, int ke) { return (lane + ke) 
 enum { TF_DIAG = TILE_DIAG, TF_CONTACT = TILE_CONTACT, TF_MASK = TILE_MASK };
 
 template <int MODE, int NBK, int D>
-__device__ __forceinline__ void tile_dispatch(const int flags, const int kb, const int ke, const KParams &P,
+__device__ __forceinline__ void tile_dispatch(const int flags, const int kb, const int ke, const uint64_t mk,
+                                              const KParams &P,
                                               const int lane, const LaneI &A,
                                               const float4 *__restrict__ posj2, const int *__restrict__ orgj,
                                               const int ncj, const float *__restrict__ rt, const float csum,
                                               float fi[6], float fj[6], float &zt) {
 #define SCPS_TILE(DG, C, M)                                                                                 \
-    tile_pass<MODE, DG, C, M, NBK, D>(P, lane, kb, ke, A, posj2, orgj, ncj, rt, csum, fi, fj, zt)
+    tile_pass<MODE, DG, C, M, NBK, D>(P, lane, kb, ke, mk, A, posj2, orgj, ncj, rt, csum, fi, fj, zt)
     const bool diag = flags & TF_DIAG, con = flags & TF_CONTACT, mask = flags & TF_MASK;
     if (ModeTraits<MODE>::nb) {
         if (diag) {
@@ -548,6 +562,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WG / 256 > 0
     double zm = cv[(int64_t)r * CV_STRIDE + CV_ZM];
     double z_last = cv[(int64_t)r * CV_STRIDE + CV_Z];
     double eb_last = cv[(int64_t)r * CV_STRIDE + CV_EB];
+    double tsum = 0.0;   // this thread's share of sum over steps, particles of |F_bias|^2 / m
     bool bad = false;
     __syncthreads();
 
@@ -574,6 +589,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WG / 256 > 0
             const int2 td = S.tiles[t];
             const int I = td.x >> 16, J = td.x & 0xFFFF, tf = td.y & 0xFF, I2 = ((td.y >> 8) & 0xFFFF) - 1;
             const int kb = (td.y >> 24) & 63, ke = min(kb + SEG_STEPS, tile_kend(tf & TF_DIAG));
+            const uint64_t mk = S.tmask[t];
             if (I2 >= 0) {
                 // two off-diagonal tiles (I, J) and (I2, J) of the same class
                 LaneI A, B;
@@ -596,7 +612,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WG / 256 > 0
                 const float *rtB = con ? S.ref + (int64_t)tile_index(I2, J, S.ncb) * 4096 : nullptr;
                 int nxt = 0;
                 if (lane == 0) nxt = atomicAdd(&sh_next, 1);
-                tile_dispatch2<PM_RMD, NBK>(tf, kb, ke, P, lane, A, B, pos + J * 128, org + J * 64, S.nc - J * 64,
+                tile_dispatch2<PM_RMD, NBK>(tf, kb, ke, mk, P, lane, A, B, pos + J * 128, org + J * 64, S.nc - J * 64,
                                             rtA, rtB, fa, fb, fj, zt);
                 zacc += (double)zt;
                 const int ncomp = con ? 6 : 3;
@@ -622,7 +638,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WG / 256 > 0
             const float *rt = (tf & TF_CONTACT) ? S.ref + (int64_t)tile_index(I, J, S.ncb) * 4096 : nullptr;
             int nxt = 0;
             if (lane == 0) nxt = atomicAdd(&sh_next, 1);
-            tile_dispatch<PM_RMD, NBK, SCPS_PAIR_GROUP>(tf, kb, ke, P, lane, A, pos + J * 128, org + J * 64,
+            tile_dispatch<PM_RMD, NBK, SCPS_PAIR_GROUP>(tf, kb, ke, mk, P, lane, A, pos + J * 128, org + J * 64,
                                                         S.nc - J * 64, rt, 0.f, fi, fj, zt);
             zacc += (double)zt;
             const int jo = J * 64 + jflush_at(lane, ke);
@@ -667,13 +683,16 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WG / 256 > 0
         const uint64_t step = step0 + (uint64_t)m;
         for (int a = tid; a < n; a += WG) {
             const double inv_m = 1.0 / (double)S.mass[a];
-            double F[3];
+            double F[3], fb2 = 0.0;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                F[c] = acc[c * n_pad + a] + scale * acc[(c + 3) * n_pad + a];
+                const double fb = scale * acc[(c + 3) * n_pad + a];
+                F[c] = acc[c * n_pad + a] + fb;
+                fb2 = fma(fb, fb, fb2);
                 acc[c * n_pad + a] = 0.0;
                 acc[(c + 3) * n_pad + a] = 0.0;
             }
+            tsum = fma(fb2, inv_m, tsum);
             double g[3];
             normals3(P, (uint32_t)org[a], P.rep_base + (uint32_t)r, step, g[0], g[1], g[2]);
             const int da = dup_index(a);
@@ -716,10 +735,17 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WG / 256 > 0
         }
     }
     if (bad) flags[r] = 1;
+    // bias functional: T += dt sum_steps sum_i |F_bias,i|^2 / (m_i gamma)
+    tsum = wave_sum(tsum);
+    if (lane == 0) red[wave] = tsum;
+    __syncthreads();
     if (tid == 0 && n_steps > 0) {
+        double t = 0.0;
+        for (int w = 0; w < NW; ++w) t += red[w];
         cv[(int64_t)r * CV_STRIDE + CV_Z] = z_last;
         cv[(int64_t)r * CV_STRIDE + CV_ZM] = zm;
         cv[(int64_t)r * CV_STRIDE + CV_EB] = eb_last;
+        cv[(int64_t)r * CV_STRIDE + CV_T] += P.dt / P.gamma * t;
     }
 }
 
@@ -900,7 +926,7 @@ __global__ __launch_bounds__(256) void k_pairs(const KParams P, const SysDesc *_
     }
     const bool diag = tf & TF_DIAG;
     const int kb = tile_kbeg(diag), ke = tile_kend(diag);
-    tile_dispatch<MODE, NBK, 4 * SCPS_PAIR_GROUP>(tf, kb, ke, P, lane, A, shpos[wave], S.perm + J * 64,
+    tile_dispatch<MODE, NBK, 4 * SCPS_PAIR_GROUP>(tf, kb, ke, it.mask, P, lane, A, shpos[wave], S.perm + J * 64,
                                                   S.nc - J * 64, rt, cs, fi, fj, zt);
     const int jo = J * 64 + jflush_at(lane, ke);
     double *ar = acc + 6 * rd.poff;
@@ -1426,61 +1452,78 @@ hipError_t launch_scps_eff(const SysDesc *sysd, const RepDesc *reps, const ScpsG
 }
 
 // Langevin update of every particle; consumes and clears the accumulators.
-// The force is acc[0..2] + scale[r] * acc[3..5].
-__global__ void k_integrate(const KParams P, const SysDesc *__restrict__ sysd, const RepDesc *__restrict__ reps,
-                            float4 *__restrict__ xs, float4 *__restrict__ vs, double *__restrict__ acc,
-                            const double *__restrict__ scale, const uint64_t step, int *__restrict__ flags) {
+// The force is acc[0..2] + scale[r] * acc[3..5], the second term being the
+// bias; each workgroup adds its particles' dt |F_bias|^2 / (m gamma) to the
+// replica's bias functional cv[r][CV_T].
+__global__ __launch_bounds__(256) void k_integrate(const KParams P, const SysDesc *__restrict__ sysd,
+                                                   const RepDesc *__restrict__ reps, float4 *__restrict__ xs,
+                                                   float4 *__restrict__ vs, double *__restrict__ acc,
+                                                   const double *__restrict__ scale, double *__restrict__ cv,
+                                                   const uint64_t step, int *__restrict__ flags) {
+    __shared__ double tred[4];
     const int r = blockIdx.y;
     const RepDesc rd = reps[r];
     const SysDesc S = sysd[rd.sys];
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= S.n) return;
-    const int n_pad = S.n_pad;
-    double *ar = acc + 6 * rd.poff;
-    const double sc = scale[r];
-    double F[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        F[c] = ar[c * n_pad + a] + sc * ar[(c + 3) * n_pad + a];
-        ar[c * n_pad + a] = 0.0;
-        ar[(c + 3) * n_pad + a] = 0.0;
-    }
-    double g[3];
-    normals3(P, (uint32_t)S.perm[a], P.rep_base + (uint32_t)r, step, g[0], g[1], g[2]);
-    float4 *xr2 = xs + 2 * rd.poff;
-    const int da = dup_index(a);
-    const float4 p = xr2[da];
-    double X[3] = {(double)p.x, (double)p.y, (double)p.z};
-    const double inv_m = 1.0 / (double)S.mass[a];
-    if (P.integrator == 0) {
-        const double mob = P.dt * inv_m / P.gamma;
-        const double amp = sqrt(2.0 * P.kT * mob);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) X[c] += mob * F[c] + amp * g[c];
-    } else {
-        const float4 q = vs[rd.poff + a];
-        double V[3] = {(double)q.x, (double)q.y, (double)q.z};
-        const double amp = sqrt((1.0 - P.c1 * P.c1) * P.kT * inv_m);
+    double tb = 0.0;
+    if (a < S.n) {
+        const int n_pad = S.n_pad;
+        double *ar = acc + 6 * rd.poff;
+        const double sc = scale[r];
+        const double inv_m = 1.0 / (double)S.mass[a];
+        double F[3], fb2 = 0.0;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            V[c] += P.dt * F[c] * inv_m;
-            X[c] += 0.5 * P.dt * V[c];
-            V[c] = P.c1 * V[c] + amp * g[c];
-            X[c] += 0.5 * P.dt * V[c];
+            const double fb = sc * ar[(c + 3) * n_pad + a];
+            F[c] = ar[c * n_pad + a] + fb;
+            fb2 = fma(fb, fb, fb2);
+            ar[c * n_pad + a] = 0.0;
+            ar[(c + 3) * n_pad + a] = 0.0;
         }
-        vs[rd.poff + a] = make_float4((float)V[0], (float)V[1], (float)V[2], 0.f);
+        tb = fb2 * inv_m;
+        double g[3];
+        normals3(P, (uint32_t)S.perm[a], P.rep_base + (uint32_t)r, step, g[0], g[1], g[2]);
+        float4 *xr2 = xs + 2 * rd.poff;
+        const int da = dup_index(a);
+        const float4 p = xr2[da];
+        double X[3] = {(double)p.x, (double)p.y, (double)p.z};
+        if (P.integrator == 0) {
+            const double mob = P.dt * inv_m / P.gamma;
+            const double amp = sqrt(2.0 * P.kT * mob);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) X[c] += mob * F[c] + amp * g[c];
+        } else {
+            const float4 q = vs[rd.poff + a];
+            double V[3] = {(double)q.x, (double)q.y, (double)q.z};
+            const double amp = sqrt((1.0 - P.c1 * P.c1) * P.kT * inv_m);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                V[c] += P.dt * F[c] * inv_m;
+                X[c] += 0.5 * P.dt * V[c];
+                V[c] = P.c1 * V[c] + amp * g[c];
+                X[c] += 0.5 * P.dt * V[c];
+            }
+            vs[rd.poff + a] = make_float4((float)V[0], (float)V[1], (float)V[2], 0.f);
+        }
+        const float4 np = make_float4((float)X[0], (float)X[1], (float)X[2], p.w);
+        if (!(isfinite(np.x) && isfinite(np.y) && isfinite(np.z))) flags[r] = 1;
+        xr2[da] = np;
+        xr2[da + 64] = np;
     }
-    const float4 np = make_float4((float)X[0], (float)X[1], (float)X[2], p.w);
-    if (!(isfinite(np.x) && isfinite(np.y) && isfinite(np.z))) flags[r] = 1;
-    xr2[da] = np;
-    xr2[da + 64] = np;
+    tb = wave_sum(tb);
+    if ((threadIdx.x & 63) == 0) tred[threadIdx.x >> 6] = tb;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double t = tred[0] + tred[1] + tred[2] + tred[3];
+        if (t != 0.0) unsafeAtomicAdd(&cv[(int64_t)r * CV_STRIDE + CV_T], P.dt / P.gamma * t);
+    }
 }
 
 hipError_t launch_integrate(const KParams &P, const SysDesc *sysd, const RepDesc *reps, int R, int n_pad_max,
-                            float4 *xs, float4 *vs, double *acc, const double *scale, uint64_t step, int *flags,
-                            hipStream_t st) {
+                            float4 *xs, float4 *vs, double *acc, const double *scale, double *cv, uint64_t step,
+                            int *flags, hipStream_t st) {
     hipLaunchKernelGGL(k_integrate, dim3((n_pad_max + 255) / 256, R), dim3(256), 0, st, P, sysd, reps, xs, vs, acc,
-                       scale, step, flags);
+                       scale, cv, step, flags);
     return hipGetLastError();
 }
 

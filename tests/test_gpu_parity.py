@@ -210,6 +210,10 @@ def test_step_forces_match_oracle(S, exec_mode, case):
         assert abs(cvg[r, 0] - cvr[0]) <= TOL * max(cvr[0], 1e-3 * osys.Z0)
         assert abs(cvg[r, 1] - cvr[1]) <= TOL * max(cvr[1], 1e-3 * osys.Z0)
         assert abs(cvg[r, 2] - cvr[2]) <= 1e-4 * max(cvr[2], 1e-12) + 1e-12
+        # bias functional after the step (the oracle's own one-step accumulation)
+        _, _, cvs, _ = O.steps(p, osys, r, X[r].astype(np.float64), np.zeros(X[r].shape), cv0[r], 1, step0=3)
+        assert abs(cvg[r, 7] - cvs[7]) <= TOL * cvs[7] + 1e-300, (r, cvg[r, 7], cvs[7])
+        assert (cvs[7] > 0) == (r % 2 == 1)                  # only the replicas below their z_m are biased
 
 
 # ---------------------------------------------------------------------------
@@ -281,6 +285,13 @@ def test_short_trajectory_pathwise_config1(S):
         disp = np.abs(xo - X0[r]).max()
         assert np.abs(Xg[r] - xo).max() <= 1e-4 * disp, (r, np.abs(Xg[r] - xo).max() / disp)
         assert abs(CVg[r, 1] - cvo[1]) <= 1e-4 * cvo[1]
+        # bias functional T = dt sum |F_bias|^2 / (m gamma): a bias-force error below
+        # tol * max|F| bounds |sqrt(T_gpu) - sqrt(T)| by tol * max|F| sqrt(dt steps sum 1/(m gamma))
+        F0 = O.total_force(p, osys, X0[r], w.initial_cvstate()[r])[0]
+        fmax = np.linalg.norm(F0, axis=0).max()
+        m = osys.mass.astype(np.float64)
+        tol_t = 1e-4 * fmax * np.sqrt(p["dt"] * 10 * np.sum(1.0 / (m * p["gamma"])))
+        assert cvo[7] > 0 and abs(np.sqrt(CVg[r, 7]) - np.sqrt(cvo[7])) <= tol_t
 
 
 def test_persistent_and_per_step_paths_agree(S):
@@ -478,6 +489,8 @@ def test_scps_step_forces_match_oracle(S, name, sizes, kinds, K, R, bias_only, e
             if bias_only:
                 assert r == 0 or np.abs(Fb).max() > 0          # the ratchets are active
             np.testing.assert_allclose(CV[r, 3:7], cvr[3:7], rtol=0, atol=1e-5, err_msg=f"{how} replica {r}")
+            _, _, cvs, _ = O.steps(p, osys[rsys[r]], r, X[r].astype(np.float64), np.zeros(X[r].shape), cv0[r], 1)
+            assert abs(CV[r, 7] - cvs[7]) <= TOL * cvs[7] + 1e-300, (how, r, CV[r, 7], cvs[7])
         ctx.close()
 
 
