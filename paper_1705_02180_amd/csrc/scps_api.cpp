@@ -255,14 +255,18 @@ void build_schedule(SysHost &h) {
         uint64_t mask;
     };
     std::vector<Item> all;
+    auto code = [](int I1, int I2, int J, int f, int kb, int ke) {
+        return make_int2((I1 << 16) | J, f | ((I2 + 1) << 8) | (kb << 16) | (ke << 23));
+    };
     auto push = [&](int I1, int I2, int J, int f, double cost) {
         const int kb = (f & TILE_DIAG) ? 1 : 0, ke = (f & TILE_DIAG) ? 33 : 64;
         uint64_t m = h.tile_mask[(size_t)I1 * h.nb + J];
         if (I2 >= 0) m |= h.tile_mask[(size_t)I2 * h.nb + J];
         if (m) f |= TILE_MASK;
-        for (int k = kb; k < ke; k += SEG_STEPS)
-            all.push_back({cost * std::min(SEG_STEPS, ke - k) / 64.0,
-                           make_int2((I1 << 16) | J, f | ((I2 + 1) << 8) | (k << 24)), m});
+        for (int k = kb; k < ke; k += SEG_STEPS) {
+            const int k2 = std::min(k + SEG_STEPS, ke);
+            all.push_back({cost * (k2 - k) / 64.0, code(I1, I2, J, f, k, k2), m});
+        }
     };
     for (int J = 0; J < h.nb; ++J) {
         std::vector<int> waiting(8, -1);   // per class, an unpaired row I
@@ -288,7 +292,24 @@ void build_schedule(SysHost &h) {
                 push(waiting[cls], -1, J, f, tile_cost(f, h.tile_mask[(size_t)waiting[cls] * h.nb + J]));
             }
     }
-    std::stable_sort(all.begin(), all.end(), [](const Item &a, const Item &b) { return a.cost > b.cost; });
+    auto by_cost = [](const Item &a, const Item &b) { return a.cost > b.cost; };
+    std::stable_sort(all.begin(), all.end(), by_cost);
+    // cut the cheapest items into TAIL_STEPS-long pieces
+    const size_t first_tail = all.size() > (size_t)TAIL_ITEMS ? all.size() - TAIL_ITEMS : 0;
+    std::vector<Item> tail;
+    for (size_t t = first_tail; t < all.size(); ++t) {
+        const Item &it = all[t];
+        const int f = it.code.y & 0xFF, I2 = ((it.code.y >> 8) & 0xFF) - 1;
+        const int kb = (it.code.y >> 16) & 0x7F, ke = (it.code.y >> 23) & 0x7F;
+        for (int k = kb; k < ke; k += TAIL_STEPS) {
+            const int k2 = std::min(k + TAIL_STEPS, ke);
+            tail.push_back({it.cost * (k2 - k) / (ke - kb), code(it.code.x >> 16, I2, it.code.x & 0xFFFF, f, k, k2),
+                            it.mask});
+        }
+    }
+    all.resize(first_tail);
+    std::stable_sort(tail.begin(), tail.end(), by_cost);
+    all.insert(all.end(), tail.begin(), tail.end());
     h.sched.clear();
     h.sched_mask.clear();
     for (const auto &t : all) {

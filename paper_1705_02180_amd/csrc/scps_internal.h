@@ -93,13 +93,25 @@ struct TileItem {
 // of its two separations); a straddling block or a cutoff sets every bit.
 enum { TILE_DIAG = 1, TILE_CONTACT = 2, TILE_MASK = 4 };
 
-// The persistent kernel's work items are segments of SEG_STEPS sub-steps of a
-// tile (or of two tiles that share the J block): {I1 << 16 | J,
-// flags | (I2 + 1) << 8 | k_begin << 24}, I2 = -1 for a single tile.
+// The persistent kernel's work items are segments of sub-steps k_begin ..
+// k_end-1 of a tile (or of two tiles that share the J block): {I1 << 16 | J,
+// flags | (I2 + 1) << 8 | k_begin << 16 | k_end << 23}, I2 = -1 for a single
+// tile (so I2 < 255: the persistent kernel's chains have far fewer blocks).
+// Segments are SEG_STEPS long; the TAIL_ITEMS cheapest items of the
+// cost-sorted list are cut further into TAIL_STEPS-long pieces, so that the
+// wavefronts of a workgroup run out of work at nearly the same time.
 #ifndef SCPS_SEG_STEPS
 #define SCPS_SEG_STEPS 32
 #endif
+#ifndef SCPS_TAIL_ITEMS
+#define SCPS_TAIL_ITEMS 32
+#endif
+#ifndef SCPS_TAIL_STEPS
+#define SCPS_TAIL_STEPS 16
+#endif
 constexpr int SEG_STEPS = SCPS_SEG_STEPS;
+constexpr int TAIL_ITEMS = SCPS_TAIL_ITEMS;
+constexpr int TAIL_STEPS = SCPS_TAIL_STEPS;
 
 // Frames per pair in the pair-major stack: K rounded up to a multiple of 4
 // (zero-filled), so a lane reads four frames of a pair with one 16-byte load.

@@ -587,8 +587,8 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WG / 256 > 0
         // then takes the next unclaimed one
         for (int t = wave; t < ntile;) {
             const int2 td = S.tiles[t];
-            const int I = td.x >> 16, J = td.x & 0xFFFF, tf = td.y & 0xFF, I2 = ((td.y >> 8) & 0xFFFF) - 1;
-            const int kb = (td.y >> 24) & 63, ke = min(kb + SEG_STEPS, tile_kend(tf & TF_DIAG));
+            const int I = td.x >> 16, J = td.x & 0xFFFF, tf = td.y & 0xFF, I2 = ((td.y >> 8) & 0xFF) - 1;
+            const int kb = (td.y >> 16) & 0x7F, ke = (td.y >> 23) & 0x7F;
             const uint64_t mk = S.tmask[t];
             if (I2 >= 0) {
                 // two off-diagonal tiles (I, J) and (I2, J) of the same class
