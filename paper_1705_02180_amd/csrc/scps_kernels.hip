@@ -1132,14 +1132,14 @@ hipError_t launch_finalize_scps(const KParams &P, const SysDesc *sysd, const Rep
 // d_k Z0 = sum_p (C_rp - R_kp)^2, splits into sum_p C_rp^2 - 2 X_rk +
 // sum_p R_kp^2 with X_rk = sum_p C_rp R_kp: for a group of up to 32 replicas
 // of one system that is a dense contraction over the contact pairs p, done
-// here with float64 MFMA (products of float32 values are exact in float64, so
-// the three sums keep the precision of the direct form).  The bias pass needs
-// each replica's effective reference E_rp = sum_k c_rk R_kp, a contraction
-// over the frames, done with float32 MFMA (the same rounding as a float32
-// dot product).  Both read every stack tile once per group instead of once
-// per replica.
+// here with float32 MFMA whose sums are moved into float64 every 64 pairs
+// (the three terms are then accurate to float64 rounding of float32-exact
+// partial sums, which keeps the cancellation in Q - 2X + R2 harmless).  The
+// bias pass needs each replica's effective reference E_rp = sum_k c_rk R_kp, a
+// contraction over the frames, also float32 MFMA (the same rounding as a
+// float32 dot product).  Both read every stack tile once per group instead of
+// once per replica.
 // ---------------------------------------------------------------------------
-typedef double dvec4 __attribute__((ext_vector_type(4)));
 typedef float fvec16 __attribute__((ext_vector_type(16)));
 
 // Unordered contact pair (64 I + l, 64 J + ((l + s) mod 64)) of a tile in the
@@ -1207,74 +1207,76 @@ __device__ __forceinline__ float contact_operand(const KParams &P, const float4 
     return (ok & inside) ? num * frcp(den) : 0.f;
 }
 
+#ifndef SCPS_DIST_AHEAD
+#define SCPS_DIST_AHEAD 8
+#endif
 // Pass 1: X[r][k] += sum_p C_rp R_kp and Q[r] += sum_p C_rp^2 over the contact
 // pairs of each work item (group of replicas, tile); workgroups stride over
 // the items and flush their sums when the group changes and at the end.
-// Wavefront w takes sub-steps w, w+4, ... of the tile; each MFMA step takes 4
-// pairs of a sub-step: lane l evaluates pair 4m + (l >> 4) for replicas
-// l & 15 and 16 + (l & 15) (A operands of the 16x16x4 float64 MFMAs) and
-// loads frames 4 (l & 15) .. 4 (l & 15) + 3 of the same pair with one 16-byte
-// load; frame block f holds frames 4j + f (j = 0..15), so component f of that
-// load is the lane's B operand of block f.  Accumulator acc[h][f] element v of
-// lane l is replica 16 h + (l >> 4) + 4 v, frame 4 (l & 15) + f.
+// Wavefront w takes sub-steps w, w+4, ... of the tile; an MFMA step takes 2
+// pairs of a sub-step: lane l evaluates pair 2m + (l >> 5) for replica l & 31
+// (A operand of 32x32x2 float32 MFMAs) and loads frames 2 (l & 31) and
+// 2 (l & 31) + 1 of the same pair with one 8-byte load, SCPS_DIST_AHEAD
+// steps ahead of their use; frame block h holds frames 2j + h, so component h of that load
+// is the lane's B operand of block h.  The float32 accumulators hold one
+// sub-step (64 pairs per element) and are added into float64 sums after
+// every sub-step, so the rounding stays at the level of a 64-term float32 sum
+// per float64 addend.  Element v of lane l in block h is replica
+// 8 (v >> 2) + 4 (l >> 5) + (v & 3), frame 2 (l & 31) + h.
 template <bool MASK>
 __device__ __forceinline__ void scps_dist_tile(const KParams &P, const SysDesc &S, const int nrep,
                                                const ScpsItem &it, const float4 (*pos)[64][32],
                                                const int (*org)[64], const int lane, const int wave,
-                                               dvec4 acc[2][4], double &q0, double &q1) {
+                                               double xs[2][16], double &q) {
     const int I = it.IJ >> 16, J = it.IJ & 0xFFFF;
     const bool diag = I == J;
     const int K4 = stack_pm_width(S.K);
-    const int rs = lane & 15, pq = lane >> 4;
-    const bool rep0 = rs < nrep, rep1 = rs + 16 < nrep;
-    const bool bload = 4 * rs < K4;
-    const float *Rt = S.stack_pm + (int64_t)it.tile * 4096 * K4 + 4 * rs;
+    const int rs = lane & 31, pq = lane >> 5;
+    const bool rep = rs < nrep;
+    const bool bload = 2 * rs < K4;
+    const float *Rt = S.stack_pm + (int64_t)it.tile * 4096 * K4 + 2 * rs;
     const int sb = diag ? 1 : 0, se = diag ? 33 : 64;
-    // B operands of a group of 4 MFMA steps (pairs s*64 + 4m + pq), loaded one
-    // group ahead of their use so that the loads overlap the MFMAs
-    float4 cur[4], nxt[4];
-    const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
-    {
-        const int s0 = sb + wave;
-        const float *Rn = Rt + (int64_t)(s0 * 64 + pq) * K4;
+    constexpr int D = SCPS_DIST_AHEAD;         // MFMA steps loaded ahead
+    const float2 zero2 = make_float2(0.f, 0.f);
+    auto bop = [&](int s_, int m_) {
+        return (bload && s_ < se) ? *reinterpret_cast<const float2 *>(Rt + (int64_t)(s_ * 64 + 2 * m_ + pq) * K4)
+                                  : zero2;
+    };
+    float2 ring[D];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-            cur[u] = (bload && s0 < se) ? *reinterpret_cast<const float4 *>(Rn + (int64_t)(4 * u) * K4) : zero4;
-    }
+    for (int u = 0; u < D; ++u) ring[u] = bop(sb + wave, u);
 #pragma unroll 1
     for (int s = sb + wave; s < se; s += 4) {
+        fvec16 acc[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[h][v] = 0.f;
 #pragma unroll 1
-        for (int mg = 0; mg < 4; ++mg) {
-            const int ns = mg == 3 ? s + 4 : s, nm = mg == 3 ? 0 : 4 * (mg + 1);
-            const bool pf = bload && ns < se;
-            const float *Rn = Rt + (int64_t)(ns * 64 + pq + 4 * nm) * K4;
+        for (int mg = 0; mg < 32 / D; ++mg) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
-                nxt[u] = pf ? *reinterpret_cast<const float4 *>(Rn + (int64_t)(4 * u) * K4) : zero4;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int l = 4 * (4 * mg + u) + pq;  // i within block I
+            for (int u = 0; u < D; ++u) {
+                const int m = D * mg + u;
+                const float2 b = ring[u];
+                const int nm = m + D < 32 ? m + D : m + D - 32, ns = m + D < 32 ? s : s + 4;
+                ring[u] = bop(ns, nm);
+                const int l = 2 * m + pq;              // i within block I
                 const int jl = (l + s) & 63;           // j within block J
                 bool ok = tile_pair_counts(diag, s, l);
                 if constexpr (MASK) {
                     ok = ok & (I * 64 + l < S.nc) & (J * 64 + jl < S.nc) &
                          (abs(org[0][l] - org[1][jl]) > P.min_sep);
                 }
-                const float c0 = contact_operand(P, pos[0][l][rs], pos[1][jl][rs], ok & rep0);
-                const float c1 = contact_operand(P, pos[0][l][rs + 16], pos[1][jl][rs + 16], ok & rep1);
-                const double a0 = (double)c0, a1 = (double)c1;
-                q0 = fma(a0, a0, q0);
-                q1 = fma(a1, a1, q1);
-                const double b[4] = {(double)cur[u].x, (double)cur[u].y, (double)cur[u].z, (double)cur[u].w};
-#pragma unroll
-                for (int f = 0; f < 4; ++f) {
-                    acc[0][f] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b[f], acc[0][f], 0, 0, 0);
-                    acc[1][f] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b[f], acc[1][f], 0, 0, 0);
-                }
+                const float c = contact_operand(P, pos[0][l][rs], pos[1][jl][rs], ok & rep);
+                q = fma((double)c, (double)c, q);
+                acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(c, b.x, acc[0], 0, 0, 0);
+                acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(c, b.y, acc[1], 0, 0, 0);
             }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) cur[u] = nxt[u];
         }
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) xs[h][v] += (double)acc[h][v];
     }
 }
 
@@ -1288,12 +1290,12 @@ __global__ __launch_bounds__(256) void k_scps_dist(const KParams P, const SysDes
     __shared__ int org[2][64];
     __shared__ int sh_rep[32];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    dvec4 acc[2][4];
-    double q0 = 0.0, q1 = 0.0;
+    double xsum[2][16];
+    double q = 0.0;
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int f = 0; f < 4; ++f) acc[h][f] = (dvec4){0.0, 0.0, 0.0, 0.0};
+        for (int v = 0; v < 16; ++v) xsum[h][v] = 0.0;
     int cur = -1, nrep = 0;
     SysDesc S;
     for (int t = blockIdx.x;; t += gridDim.x) {
@@ -1306,33 +1308,28 @@ __global__ __launch_bounds__(256) void k_scps_dist(const KParams P, const SysDes
 #pragma unroll
             for (int h = 0; h < 2; ++h)
 #pragma unroll
-                for (int f = 0; f < 4; ++f)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) red[(wave * 32 + h * 16 + f * 4 + v) * 64 + lane] = acc[h][f][v];
+                for (int v = 0; v < 16; ++v) red[(wave * 32 + h * 16 + v) * 64 + lane] = xsum[h][v];
             __syncthreads();
             for (int e = tid; e < 32 * 64; e += 256) {
                 const int reg = e >> 6, ln = e & 63;
                 const double sum = red[e] + red[2048 + e] + red[4096 + e] + red[6144 + e];
-                const int h = reg >> 4, f = (reg >> 2) & 3, v = reg & 3;
-                const int slot = 16 * h + (ln >> 4) + 4 * v, k = 4 * (ln & 15) + f;
+                const int h = reg >> 4, v = reg & 15;
+                const int slot = 8 * (v >> 2) + 4 * (ln >> 5) + (v & 3), k = 2 * (ln & 31) + h;
                 if (slot < nrep && k < S.K) unsafeAtomicAdd(&X[(int64_t)sh_rep[slot] * kmax + k], sum);
             }
             __syncthreads();
-            red[wave * 128 + lane] = q0;
-            red[wave * 128 + 64 + lane] = q1;
+            red[wave * 64 + lane] = q;
             __syncthreads();
             if (tid < 32) {
-                const int h = tid >> 4, rsl = tid & 15;
                 double sum = 0.0;
-                for (int w = 0; w < 4; ++w)
-                    for (int g = 0; g < 4; ++g) sum += red[w * 128 + h * 64 + g * 16 + rsl];
+                for (int w = 0; w < 4; ++w) sum += red[w * 64 + tid] + red[w * 64 + 32 + tid];
                 if (tid < nrep) unsafeAtomicAdd(&Q[sh_rep[tid]], sum);
             }
 #pragma unroll
             for (int h = 0; h < 2; ++h)
 #pragma unroll
-                for (int f = 0; f < 4; ++f) acc[h][f] = (dvec4){0.0, 0.0, 0.0, 0.0};
-            q0 = q1 = 0.0;
+                for (int v = 0; v < 16; ++v) xsum[h][v] = 0.0;
+            q = 0.0;
         }
         if (!more) break;
         __syncthreads();
@@ -1355,9 +1352,9 @@ __global__ __launch_bounds__(256) void k_scps_dist(const KParams P, const SysDes
         if (tid < 128) org[tid >> 6][tid & 63] = S.perm[((tid >> 6) ? J : I) * 64 + (tid & 63)];
         __syncthreads();
         if (it.flags & TILE_MASK)
-            scps_dist_tile<true>(P, S, nrep, it, pos, org, lane, wave, acc, q0, q1);
+            scps_dist_tile<true>(P, S, nrep, it, pos, org, lane, wave, xsum, q);
         else
-            scps_dist_tile<false>(P, S, nrep, it, pos, org, lane, wave, acc, q0, q1);
+            scps_dist_tile<false>(P, S, nrep, it, pos, org, lane, wave, xsum, q);
     }
 }
 

@@ -412,6 +412,8 @@ SCPS_CASES = [
     ("bias_only_150_K33_seqsep5", [150], ["all"], 33, 6, True, {"min_seq_sep": 5}),
     ("bias_only_160_K17_cutoff12", [160], ["all"], 17, 4, True, {"r_cut_contact": 12.0}),
     ("two_systems_K20", [150, 200], ["all", "every3"], 20, 6, False, {}),
+    ("smallest_stack_K2", [100], ["all"], 2, 3, False, {}),
+    ("largest_stack_K64_bias_only", [120], ["all"], 64, 5, True, {}),
 ]
 
 
@@ -555,3 +557,54 @@ def test_full_config2_sampled(S):
         F, _, cvr = O.total_force(p, osys, X[r].astype(np.float64), cv0[r])
         assert normwise(Fg[r], F) <= TOL, (r, normwise(Fg[r], F))
         assert abs(cvg[r, 0] - cvr[0]) <= TOL * max(cvr[0], 1e-3 * osys.Z0)
+
+
+# ---------------------------------------------------------------------------
+# degenerate calls and limits
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("exec_mode", [0, 1], ids=["persistent", "per_step"])
+def test_zero_steps_leave_state_unchanged(S, exec_mode):
+    w = I.config2(n_replicas=3, n_steps=1)
+    ctx = context(S, w, exec_mode=exec_mode)
+    x0, v0, cv0 = w.initial_x(), w.initial_v(2), w.initial_cvstate()
+    cv0[:, 7] = 1.25
+    x, v, cv = dev(x0), dev(v0), dev(cv0, "f64")
+    ctx.step_replicas(x, v, cv, 0, step0=5)
+    ctx.sync()
+    np.testing.assert_array_equal(host(x), x0)
+    np.testing.assert_array_equal(host(v), v0)
+    np.testing.assert_array_equal(host(cv), cv0)
+
+
+@pytest.mark.parametrize("exec_mode", [0, 1], ids=["persistent", "per_step"])
+def test_two_particle_chain_matches_oracle(S, exec_mode):
+    base = dict(I._base_params())
+    p = _force_readback_params(base, k_R=0.3)
+    w = single_system_workload(2, np.arange(2), p, 2)
+    sy = w.systems[0]
+    X = np.stack([sy.native + 0.7, sy.native * 1.6]).astype(np.float32)
+    osys = O.System.from_inputs(sy, p)
+    cv0 = np.zeros((2, 8))
+    cv0[:, 1] = np.inf
+    cv0[1, 1] = 0.5 * O.z_grad(X[1].astype(np.float64), osys.cidx, osys.native, grad=False)
+    Fg, cvg = _gpu_forces_one_step(S, w, p, X, cv0, exec_mode)
+    for r in range(2):
+        F, _, cvr = O.total_force(p, osys, X[r].astype(np.float64), cv0[r])
+        assert normwise(Fg[r], F) <= TOL, (r, normwise(Fg[r], F))
+        assert abs(cvg[r, 0] - cvr[0]) <= TOL * max(cvr[0], 1e-3 * osys.Z0)
+
+
+def test_frame_stack_limit_is_enforced(S):
+    base = dict(I._base_params(), bias_mode=1)
+    w = single_system_workload(70, np.arange(70), base, 2)
+    sy = w.systems[0]
+    ctx = context(S, w, params=base)
+    fr = _ensemble_frames(sy, 65, 1, 3)
+    with pytest.raises(S.ScpsError) as e:
+        ctx.update_reference_from_paths(0, dev(fr.ravel()), 1, 65, np.ones(1, dtype=np.uint8))
+    assert e.value.status == -2
+    import torch
+    x = dev(np.stack([sy.start, sy.start]).astype(np.float32).ravel())
+    with pytest.raises(S.ScpsError) as e:        # SCPS stepping needs a stack of >= 2 frames
+        ctx.step_replicas(x, torch.zeros_like(x), dev(w.initial_cvstate(), "f64"), 1)
+    assert e.value.status == -5
