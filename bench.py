@@ -225,6 +225,7 @@ def bench_chain560(args, torch, I, scps):
     v = torch.as_tensor(w.initial_v(7), device="cuda")
     cv = torch.as_tensor(w.initial_cvstate(), device="cuda")
     step = [0]
+    path, threads = ctx.autotune(x, v, cv, args.block)      # on copies of the state, before timing
 
     def call(_):
         ctx.step_replicas(x, v, cv, args.block, step0=step[0])
@@ -240,7 +241,8 @@ def bench_chain560(args, torch, I, scps):
         "workload": f"chain560_fip35_shaped: {R} replicas x 560 particles, {con} contact pairs + "
                     f"{nb} LJ/Debye-Hueckel pairs ({both} both), BAOAB dt=2 fs, {args.block} Langevin "
                     f"steps per benchmark step",
-        "replicas": R, "particles": sy.n, "block": args.block})
+        "replicas": R, "particles": sy.n, "block": args.block,
+        "launch": "persistent, %d threads per replica" % threads if path == 0 else "per-step"})
     out["contact_pair_evals_per_s"] = value * con
     out["nonbonded_pair_evals_per_s"] = value * nb
     out["roofline"] = roofline(R * args.block * step_flops(con, nb, both), per_ms, "k_rmd_persistent",
@@ -274,6 +276,7 @@ def bench_uneven512(args, torch, I, scps):
     v = torch.as_tensor(w.initial_v(7), device="cuda")
     cv = torch.as_tensor(w.initial_cvstate(), device="cuda")
     step = [0]
+    ctx.autotune(x, v, cv, 5)                                # on copies of the state, before timing
 
     def call(_):
         ctx.step_replicas(x, v, cv, args.block, step0=step[0])

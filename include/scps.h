@@ -207,6 +207,23 @@ scps_status scps_set_stream(scps_ctx *ctx, void *hip_stream);
  * poisons the context), HIP on a runtime error, OK otherwise. */
 scps_status scps_sync(scps_ctx *ctx, int32_t *bad_replicas, int32_t *n_bad);
 
+/* Autotuner for the batched stepping (running many replicas at once, SCPS
+ * steps 2 and 4): times every launch configuration the context can use for
+ * scps_step_replicas -- the persistent kernel with 256, 512 or 1024 threads per
+ * replica where a replica's state fits in one workgroup's LDS, and the
+ * per-step path -- for n_steps steps on private device copies of
+ * (x, v, cvstate), and keeps the fastest for the context's later calls
+ * (exec_mode AUTO only; an SCPS context has the per-step path alone).
+ *   x, v, cvstate: device buffers as for scps_step_replicas; read only.
+ *   n_steps: steps timed per configuration, >= 1.
+ *   chosen: nullable host int32[2]; receives {0 persistent / 1 per-step,
+ *           threads per workgroup of the persistent kernel (0 for per-step)}.
+ * Results of later calls differ from an untuned context's only by the order
+ * of float64 additions.  Allocates three scratch buffers for the duration of
+ * the call and synchronises the stream.  Errors: INVALID_ARG, OOM, HIP. */
+scps_status scps_autotune(scps_ctx *ctx, const float *x, const float *v, const double *cvstate,
+                          int64_t n_steps, int32_t *chosen);
+
 /* Free the context and everything it owns; NULL is accepted. */
 void scps_destroy(scps_ctx *ctx);
 

@@ -81,6 +81,7 @@ struct scps_ctx {
     int n_sitems = 0;
     int kmax = KMAX;
     int wg = 64;     // persistent workgroup size
+    int tuned = -1;  // -1 untuned; else 0 persistent (with wg) or 1 per-step, from scps_autotune
     int nbk = 0;     // nonbonded terms: bit 0 LJ, bit 1 Debye-Hueckel
     std::vector<void *> owned;
 };
@@ -620,7 +621,7 @@ scps_status step_impl(scps_ctx *c, float *x, float *v, double *cv, int64_t n_ste
         if (scps && h.K < 2) return fail(SCPS_ERR_STATE, "SCPS mode needs a frame stack of >= 2 maps");
     }
     const int64_t frame_stride = 3 * c->sumN;
-    bool persistent = !scps && c->prm.exec_mode == SCPS_EXEC_AUTO;
+    bool persistent = !scps && c->prm.exec_mode == SCPS_EXEC_AUTO && c->tuned != 1;
     const int wg = c->wg;
     if (persistent && c->n_pad_max > persistent_max_npad(wg)) persistent = false;
     if (persistent) {
@@ -711,6 +712,82 @@ scps_status update_ref_impl(scps_ctx *c, int32_t s, const float *frames, int32_t
     return upload_sysdesc(c);
 }
 
+scps_status autotune_impl(scps_ctx *c, const float *x, const float *v, const double *cv, int64_t n_steps,
+                          int32_t *chosen) {
+    if (!x || !cv) return fail(SCPS_ERR_INVALID_ARG, "x and cvstate must not be NULL");
+    if (n_steps < 1) return fail(SCPS_ERR_INVALID_ARG, "n_steps must be >= 1");
+    if (c->prm.integrator == SCPS_INTEGRATOR_BAOAB && !v) return fail(SCPS_ERR_INVALID_ARG, "BAOAB needs velocities");
+    for (int r = 0; r < c->R; ++r)
+        if (!c->sys[c->rep_sys[r]].has_native)
+            return fail(SCPS_ERR_STATE, "a system has no native map (scps_set_reference_map)");
+    // candidates: {path, workgroup}
+    std::vector<std::pair<int, int>> cand;
+    const bool scps = c->prm.bias_mode == SCPS_BIAS_SCPS;
+    if (!scps && c->prm.exec_mode == SCPS_EXEC_AUTO)
+        for (int wg : {256, 512, 1024})
+            if (c->n_pad_max <= persistent_max_npad(wg)) cand.push_back({0, wg});
+    cand.push_back({1, 0});
+    const size_t nx = 3 * (size_t)c->sumN;
+    float *tx = nullptr, *tv = nullptr;
+    double *tcv = nullptr;
+    int *tflags = nullptr;   // the caller's non-finite flags, kept across the trial runs
+    HIP_TRY(c, dalloc(c, &tflags, c->R));
+    HIP_TRY(c, hipMemcpyAsync(tflags, c->d_flags, c->R * sizeof(int), hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(c, dalloc(c, &tx, nx));
+    if (v) HIP_TRY(c, dalloc(c, &tv, nx));
+    HIP_TRY(c, dalloc(c, &tcv, (size_t)c->R * CV_STRIDE));
+    hipEvent_t e0, e1;
+    HIP_TRY(c, hipEventCreate(&e0));
+    HIP_TRY(c, hipEventCreate(&e1));
+    const int saved_tuned = c->tuned, saved_wg = c->wg;
+    float best = 0.f;
+    int best_i = -1;
+    scps_status st = SCPS_OK;
+    for (size_t i = 0; i < cand.size() && st == SCPS_OK; ++i) {
+        c->tuned = cand[i].first;
+        if (cand[i].first == 0) c->wg = cand[i].second;
+        // one untimed call (first-launch costs), then the timed one, each from the caller's state
+        float ms = 0.f;
+        for (int rep = 0; rep < 2 && st == SCPS_OK; ++rep) {
+            HIP_TRY(c, hipMemcpyAsync(tx, x, nx * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+            if (v) HIP_TRY(c, hipMemcpyAsync(tv, v, nx * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+            HIP_TRY(c, hipMemcpyAsync(tcv, cv, (size_t)c->R * CV_STRIDE * sizeof(double), hipMemcpyDeviceToDevice,
+                                      c->stream));
+            HIP_TRY(c, hipEventRecord(e0, c->stream));
+            st = step_impl(c, tx, tv, tcv, rep ? n_steps : 1, 0, 0, nullptr);
+            HIP_TRY(c, hipEventRecord(e1, c->stream));
+            HIP_TRY(c, hipEventSynchronize(e1));
+            HIP_TRY(c, hipEventElapsedTime(&ms, e0, e1));
+        }
+        if (st == SCPS_OK && (best_i < 0 || ms < best)) {
+            best = ms;
+            best_i = (int)i;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    // flags raised by the trial runs on the copies do not count
+    HIP_TRY(c, hipMemcpyAsync(c->d_flags, tflags, c->R * sizeof(int), hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    dfree(c, tflags);
+    dfree(c, tx);
+    dfree(c, tv);
+    dfree(c, tcv);
+    if (st != SCPS_OK) {
+        c->tuned = saved_tuned;
+        c->wg = saved_wg;
+        return st;
+    }
+    c->tuned = cand[best_i].first;
+    if (c->tuned == 0) c->wg = cand[best_i].second;
+    else c->wg = saved_wg;
+    if (chosen) {
+        chosen[0] = c->tuned;
+        chosen[1] = c->tuned == 0 ? c->wg : 0;
+    }
+    return SCPS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -765,6 +842,17 @@ scps_status scps_update_reference_from_paths(scps_ctx *ctx, int32_t system, cons
     if (!usable(ctx, &st)) return st;
     try {
         return update_ref_impl(ctx, system, frames, n_paths, n_frames, success, maps_out);
+    } catch (const std::bad_alloc &) {
+        return fail(SCPS_ERR_OOM, "host allocation failed");
+    }
+}
+
+scps_status scps_autotune(scps_ctx *ctx, const float *x, const float *v, const double *cvstate, int64_t n_steps,
+                          int32_t *chosen) {
+    scps_status st;
+    if (!usable(ctx, &st)) return st;
+    try {
+        return autotune_impl(ctx, x, v, cvstate, n_steps, chosen);
     } catch (const std::bad_alloc &) {
         return fail(SCPS_ERR_OOM, "host allocation failed");
     }

@@ -74,6 +74,8 @@ _lib.scps_set_stream.restype = C.c_int
 _lib.scps_set_stream.argtypes = [_vp, _vp]
 _lib.scps_sync.restype = C.c_int
 _lib.scps_sync.argtypes = [_vp, _vp, _vp]
+_lib.scps_autotune.restype = C.c_int
+_lib.scps_autotune.argtypes = [_vp, _vp, _vp, _vp, _i64, _vp]
 _lib.scps_destroy.restype = None
 _lib.scps_destroy.argtypes = [_vp]
 _lib.scps_last_error.restype = C.c_char_p
@@ -81,7 +83,7 @@ _lib.scps_last_error.argtypes = []
 
 EXPORTS = ["scps_init_system", "scps_set_reference_map", "scps_step_replicas", "scps_eval_z_and_grad",
            "scps_ratchet_energy", "scps_update_reference_from_paths", "scps_set_stream", "scps_sync",
-           "scps_destroy", "scps_last_error"]
+           "scps_autotune", "scps_destroy", "scps_last_error"]
 
 
 def _check(status: int):
@@ -242,6 +244,16 @@ class Context:
             None if out is None else out.ctypes.data_as(C.c_void_p)))
         return out
 
+    def autotune(self, x: torch.Tensor, v: Optional[torch.Tensor], cvstate: torch.Tensor, n_steps: int):
+        """Time the launch configurations on copies of the state and keep the
+        fastest; returns (path, threads): path 0 persistent, 1 per-step."""
+        px = _dev(x, torch.float32, 3 * self.sumN, "x")
+        pv = _dev(v, torch.float32, 3 * self.sumN, "v")
+        pc = _dev(cvstate, torch.float64, self.R * CV_STRIDE, "cvstate")
+        out = np.zeros(2, dtype=np.int32)
+        _check(_lib.scps_autotune(self._ctx(), px, pv, pc, int(n_steps), out.ctypes.data_as(C.c_void_p)))
+        return int(out[0]), int(out[1])
+
     def sync(self):
         bad = np.zeros(self.R, dtype=np.int32)
         nb = C.c_int32(0)
@@ -258,6 +270,10 @@ def init_system(params: dict, n_particles, contact_idx, mass, charge, replica_sy
 
 def set_reference_map(ctx: Context, system: int, maps=None, native_xyz=None, z0_norm: float = 0.0):
     return ctx.set_reference_map(system, maps, native_xyz, z0_norm)
+
+
+def autotune(ctx: Context, x, v, cvstate, n_steps):
+    return ctx.autotune(x, v, cvstate, n_steps)
 
 
 def step_replicas(ctx: Context, x, v, cvstate, n_steps, step0=0, record_every=0, frames=None):

@@ -608,3 +608,33 @@ def test_frame_stack_limit_is_enforced(S):
     with pytest.raises(S.ScpsError) as e:        # SCPS stepping needs a stack of >= 2 frames
         ctx.step_replicas(x, torch.zeros_like(x), dev(w.initial_cvstate(), "f64"), 1)
     assert e.value.status == -5
+
+
+def test_autotune_picks_a_valid_launch_and_keeps_results(S):
+    w = I.config2(n_replicas=8, n_steps=20)
+    x0, v0, cv0 = w.initial_x(), w.initial_v(1), w.initial_cvstate()
+    tuned = context(S, w)
+    x, v, cv = dev(x0), dev(v0), dev(cv0, "f64")
+    path, threads = tuned.autotune(x, v, cv, 5)
+    assert (path == 0 and threads in (256, 512, 1024)) or (path == 1 and threads == 0)
+    np.testing.assert_array_equal(host(x), x0)           # the state it timed on is untouched
+    np.testing.assert_array_equal(host(cv), cv0)
+    plain = context(S, w)
+    res = []
+    for ctx in (tuned, plain):
+        x, v, cv = dev(x0), dev(v0), dev(cv0, "f64")
+        ctx.step_replicas(x, v, cv, 20, step0=100)
+        ctx.sync()
+        res.append((host(x), host(cv)))
+    disp = np.abs(res[1][0] - x0).max()
+    assert np.abs(res[0][0] - res[1][0]).max() <= 1e-4 * disp
+    np.testing.assert_allclose(res[0][1][:, :2], res[1][1][:, :2], rtol=1e-5)
+    # an SCPS context has only the per-step path
+    base = dict(I._base_params(), bias_mode=1)
+    ws = single_system_workload(90, np.arange(90), base, 2)
+    sc = context(S, ws, params=base)
+    sc.update_reference_from_paths(0, dev(_ensemble_frames(ws.systems[0], 4, 2, 5).ravel()), 2, 4,
+                                   np.ones(2, dtype=np.uint8))
+    xs = dev(np.stack([ws.systems[0].start] * 2).astype(np.float32).ravel())
+    import torch
+    assert sc.autotune(xs, torch.zeros_like(xs), dev(ws.initial_cvstate(), "f64"), 2) == (1, 0)
