@@ -120,7 +120,7 @@ typedef struct {
     const float *charge;          /* concatenated per particle */
 } scps_topology;
 
-/* Create a context for n_replicas replicas; replica r runs system
+/* Create a context for n_replicas replicas (1 .. 65535); replica r runs system
  * replica_system[r] (host array).  hip_stream: a hipStream_t, or NULL for the
  * null stream.  Allocates the context's device buffers.  Reference maps are
  * unset until scps_set_reference_map.  Errors: INVALID_ARG, SHAPE, OOM, HIP. */

@@ -340,6 +340,7 @@ scps_status init_impl(const scps_params *params, const scps_topology *topo, int3
     if (topo->n_systems < 1 || !topo->n_particles || !topo->n_contact || !topo->mass || !topo->charge)
         return fail(SCPS_ERR_INVALID_ARG, "topology needs n_systems >= 1 and non-NULL arrays");
     if (R < 1) return fail(SCPS_ERR_INVALID_ARG, "n_replicas must be >= 1");
+    if (R > 65535) return fail(SCPS_ERR_SHAPE, "n_replicas must be <= 65535 (one grid row per replica)");
 
     scps_ctx *c = new (std::nothrow) scps_ctx();
     if (!c) return fail(SCPS_ERR_OOM, "host allocation failed");

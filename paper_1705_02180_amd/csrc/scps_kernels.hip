@@ -1360,20 +1360,30 @@ __global__ __launch_bounds__(256) void k_scps_dist(const KParams P, const SysDes
 
 // Pass 2 operand: E[eoff_r + tile * 4096 + p] = sum_k c_rk R_kp for every
 // pair p of each work item's tile and replica r of its group (coef holds
-// c_rk).  Wavefront w takes chunks of 128 pairs w, w+4, ...; a chunk is four
-// 32-pair MFMA blocks interleaved so that block b holds pairs 4j + b: lane l
-// reads pairs 4 (l & 31) .. +3 of frame 2 kk + (l >> 5) with one 16-byte load
-// (component b is its B operand of block b) and supplies c of replica l & 31
-// for that frame (A operand, 32x32x2 float32 MFMA).  Result element v of lane
-// l in block b is replica 8 (v >> 2) + 4 (l >> 5) + (v & 3), pair 4 (l & 31)
-// + b: the four blocks give one 16-byte store per replica.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_scps_eff(const SysDesc *__restrict__ sysd,
-                                                  const RepDesc *__restrict__ reps,
-                                                  const ScpsGroup *__restrict__ groups,
-                                                  const ScpsItem *__restrict__ items, const int n_items,
-                                                  const float *__restrict__ coef, const int kmax,
-                                                  float *__restrict__ E) {
+// c_rk).  Wavefront w takes chunks of 32 EFF_NB pairs w, w+4, ...; a chunk is
+// EFF_NB 32-pair MFMA blocks interleaved so that block b holds pairs
+// EFF_NB j + b: lane l reads pairs EFF_NB (l & 31) .. +EFF_NB-1 of frame
+// 2 kk + (l >> 5) with one load (component b is its B operand of block b)
+// and supplies c of replica l & 31 for that frame (A operand, 32x32x2
+// float32 MFMA).  Result element v of lane l in block b is replica
+// 8 (v >> 2) + 4 (l >> 5) + (v & 3), pair EFF_NB (l & 31) + b: the blocks give
+// one EFF_NB-wide store per replica.
+#ifndef SCPS_EFF_BLOCKS
+#define SCPS_EFF_BLOCKS 4
+#endif
+#ifndef SCPS_EFF_WPE
+#define SCPS_EFF_WPE (SCPS_EFF_BLOCKS == 4 ? 2 : 3)
+#endif
+constexpr int EFF_NB = SCPS_EFF_BLOCKS;
+static_assert(EFF_NB == 2 || EFF_NB == 4, "chunks of 2 or 4 MFMA blocks");
+typedef float effvec __attribute__((ext_vector_type(EFF_NB)));
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SCPS_EFF_WPE, SCPS_EFF_WPE))) void k_scps_eff(
+    const SysDesc *__restrict__ sysd, const RepDesc *__restrict__ reps, const ScpsGroup *__restrict__ groups,
+    const ScpsItem *__restrict__ items, const int n_items, const float *__restrict__ coef, const int kmax,
+    float *__restrict__ E) {
     __shared__ int64_t sh_eoff[SCPS_GROUP];   // -1 for an empty slot
+    constexpr int CH = 32 * EFF_NB;            // pairs per chunk
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int slot = lane & 31, half = lane >> 5;
     int cur = -1;
@@ -1399,31 +1409,37 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         const int K = S.K;
         const float *Rt = S.stack + (int64_t)it.tile * K * 4096;
 #pragma unroll 1
-        for (int ch = wave; ch < 32; ch += 4) {
-            const int p = ch * 128 + 4 * slot;
-            fvec16 acc[4];
+        for (int ch = wave; ch < 4096 / CH; ch += 4) {
+            const int p = ch * CH + EFF_NB * slot;
+            fvec16 acc[EFF_NB];
 #pragma unroll
-            for (int bl = 0; bl < 4; ++bl)
+            for (int bl = 0; bl < EFF_NB; ++bl)
 #pragma unroll
                 for (int v = 0; v < 16; ++v) acc[bl][v] = 0.f;
 #pragma unroll
             for (int kk = 0; kk < KMAX / 2; ++kk) {
                 if (2 * kk < K) {
                     const int k = 2 * kk + half;
-                    const float4 b = k < K ? *reinterpret_cast<const float4 *>(Rt + k * 4096 + p)
-                                           : make_float4(0.f, 0.f, 0.f, 0.f);
-                    acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(creg[kk], b.x, acc[0], 0, 0, 0);
-                    acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(creg[kk], b.y, acc[1], 0, 0, 0);
-                    acc[2] = __builtin_amdgcn_mfma_f32_32x32x2f32(creg[kk], b.z, acc[2], 0, 0, 0);
-                    acc[3] = __builtin_amdgcn_mfma_f32_32x32x2f32(creg[kk], b.w, acc[3], 0, 0, 0);
+                    effvec b;
+                    if (k < K)
+                        b = *reinterpret_cast<const effvec *>(Rt + k * 4096 + p);
+                    else
+#pragma unroll
+                        for (int bl = 0; bl < EFF_NB; ++bl) b[bl] = 0.f;
+#pragma unroll
+                    for (int bl = 0; bl < EFF_NB; ++bl)
+                        acc[bl] = __builtin_amdgcn_mfma_f32_32x32x2f32(creg[kk], b[bl], acc[bl], 0, 0, 0);
                 }
             }
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
                 const int64_t eo = sh_eoff[8 * (v >> 2) + 4 * half + (v & 3)];
-                if (eo >= 0)
-                    *reinterpret_cast<float4 *>(E + eo + (int64_t)it.tile * 4096 + p) =
-                        make_float4(acc[0][v], acc[1][v], acc[2][v], acc[3][v]);
+                if (eo >= 0) {
+                    effvec o;
+#pragma unroll
+                    for (int bl = 0; bl < EFF_NB; ++bl) o[bl] = acc[bl][v];
+                    *reinterpret_cast<effvec *>(E + eo + (int64_t)it.tile * 4096 + p) = o;
+                }
             }
         }
     }

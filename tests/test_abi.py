@@ -61,6 +61,9 @@ def test_host_validation_rejects_bad_arguments(lib):
     with pytest.raises(scps.ScpsError) as e:
         scps.Context(w.params, [20], [[1, 2]], [w.systems[0].mass], [w.systems[0].charge], [1])
     assert e.value.status == -1
+    with pytest.raises(scps.ScpsError) as e:      # one grid row per replica
+        scps.Context(w.params, [20], [[1, 2]], [w.systems[0].mass], [w.systems[0].charge], [0] * 65536)
+    assert e.value.status == -2
     assert lib.scps_step_replicas(None, None, None, None, C.c_int64(1), C.c_uint64(0), 0, None) == -1
     lib.scps_last_error.restype = C.c_char_p
     assert b"NULL" in lib.scps_last_error()
