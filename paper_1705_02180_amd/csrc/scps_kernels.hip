@@ -1213,21 +1213,24 @@ __device__ __forceinline__ float contact_operand(const KParams &P, const float4 
 // Pass 1: X[r][k] += sum_p C_rp R_kp and Q[r] += sum_p C_rp^2 over the contact
 // pairs of each work item (group of replicas, tile); workgroups stride over
 // the items and flush their sums when the group changes and at the end.
-// Wavefront w takes sub-steps w, w+4, ... of the tile; an MFMA step takes 2
-// pairs of a sub-step: lane l evaluates pair 2m + (l >> 5) for replica l & 31
-// (A operand of 32x32x2 float32 MFMAs) and loads frames 2 (l & 31) and
-// 2 (l & 31) + 1 of the same pair with one 8-byte load, SCPS_DIST_AHEAD
-// steps ahead of their use; frame block h holds frames 2j + h, so component h of that load
-// is the lane's B operand of block h.  The float32 accumulators hold one
-// sub-step (64 pairs per element) and are added into float64 sums after
-// every sub-step, so the rounding stays at the level of a 64-term float32 sum
-// per float64 addend.  Element v of lane l in block h is replica
-// 8 (v >> 2) + 4 (l >> 5) + (v & 3), frame 2 (l & 31) + h.
+// The pairs of a tile are taken row by row: wavefront w takes rows
+// i = w, w+4, ... of block I and, per row, 32 MFMA steps of 2 pairs
+// (i, 2m + (l >> 5)); lane l evaluates that pair for replica l & 31 (A operand
+// of 32x32x2 float32 MFMAs) with particle i's position held in a register and
+// particle j's read from the block-J positions in LDS, and loads frames
+// 2 (l & 31) and 2 (l & 31) + 1 of the pair with one 8-byte load,
+// SCPS_DIST_AHEAD steps ahead of their use; frame block h holds frames 2j + h,
+// so component h of that load is the lane's B operand of block h.  A diagonal
+// tile counts the pairs j > i.  The float32 accumulators hold one row (64
+// pairs per element) and are added after every row into the workgroup's
+// float64 sums xl[slot][frame] in LDS.  Element v of lane l in block h is
+// replica slot 8 (v >> 2) + 4 (l >> 5) + (v & 3), frame 2 (l & 31) + h.
 template <bool MASK>
 __device__ __forceinline__ void scps_dist_tile(const KParams &P, const SysDesc &S, const int nrep,
-                                               const ScpsItem &it, const float4 (*pos)[64][32],
-                                               const int (*org)[64], const int lane, const int wave,
-                                               double xs[2][16], double &q) {
+                                               const ScpsItem &it, const float4 (*posj)[32], const int *orgj,
+                                               const float4 *__restrict__ xs, const RepDesc *__restrict__ reps,
+                                               const int myrep, const int lane, const int wave, double *xl,
+                                               double &q) {
     const int I = it.IJ >> 16, J = it.IJ & 0xFFFF;
     const bool diag = I == J;
     const int K4 = stack_pm_width(S.K);
@@ -1235,18 +1238,22 @@ __device__ __forceinline__ void scps_dist_tile(const KParams &P, const SysDesc &
     const bool rep = rs < nrep;
     const bool bload = 2 * rs < K4;
     const float *Rt = S.stack_pm + (int64_t)it.tile * 4096 * K4 + 2 * rs;
-    const int sb = diag ? 1 : 0, se = diag ? 33 : 64;
-    constexpr int D = SCPS_DIST_AHEAD;         // MFMA steps loaded ahead
+    const float4 *xr = xs + 2 * reps[myrep].poff + I * 128;
+    constexpr int D = SCPS_DIST_AHEAD;
     const float2 zero2 = make_float2(0.f, 0.f);
-    auto bop = [&](int s_, int m_) {
-        return (bload && s_ < se) ? *reinterpret_cast<const float2 *>(Rt + (int64_t)(s_ * 64 + 2 * m_ + pq) * K4)
-                                  : zero2;
+    // pair (i, j) sits at s * 64 + i in the tile, s = (j - i) mod 64
+    auto bop = [&](int i_, int m_) {
+        const int s_ = (2 * m_ + pq - i_) & 63;
+        return (bload && i_ < 64) ? *reinterpret_cast<const float2 *>(Rt + (int64_t)(s_ * 64 + i_) * K4) : zero2;
     };
     float2 ring[D];
 #pragma unroll
-    for (int u = 0; u < D; ++u) ring[u] = bop(sb + wave, u);
+    for (int u = 0; u < D; ++u) ring[u] = bop(wave, u);
 #pragma unroll 1
-    for (int s = sb + wave; s < se; s += 4) {
+    for (int i = wave; i < 64; i += 4) {
+        const float4 pi = rep ? xr[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const int oi = MASK ? S.perm[I * 64 + i] : 0;
+        const bool icon = I * 64 + i < S.nc;
         fvec16 acc[2];
 #pragma unroll
         for (int h = 0; h < 2; ++h)
@@ -1258,16 +1265,14 @@ __device__ __forceinline__ void scps_dist_tile(const KParams &P, const SysDesc &
             for (int u = 0; u < D; ++u) {
                 const int m = D * mg + u;
                 const float2 b = ring[u];
-                const int nm = m + D < 32 ? m + D : m + D - 32, ns = m + D < 32 ? s : s + 4;
-                ring[u] = bop(ns, nm);
-                const int l = 2 * m + pq;              // i within block I
-                const int jl = (l + s) & 63;           // j within block J
-                bool ok = tile_pair_counts(diag, s, l);
+                const int nm = m + D < 32 ? m + D : m + D - 32, ni = m + D < 32 ? i : i + 4;
+                ring[u] = bop(ni, nm);
+                const int jl = 2 * m + pq;
+                bool ok = !diag | (jl > i);
                 if constexpr (MASK) {
-                    ok = ok & (I * 64 + l < S.nc) & (J * 64 + jl < S.nc) &
-                         (abs(org[0][l] - org[1][jl]) > P.min_sep);
+                    ok = ok & icon & (J * 64 + jl < S.nc) & (abs(oi - orgj[jl]) > P.min_sep);
                 }
-                const float c = contact_operand(P, pos[0][l][rs], pos[1][jl][rs], ok & rep);
+                const float c = contact_operand(P, pi, posj[jl][rs], ok & rep);
                 q = fma((double)c, (double)c, q);
                 acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(c, b.x, acc[0], 0, 0, 0);
                 acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(c, b.y, acc[1], 0, 0, 0);
@@ -1276,59 +1281,47 @@ __device__ __forceinline__ void scps_dist_tile(const KParams &P, const SysDesc &
 #pragma unroll
         for (int h = 0; h < 2; ++h)
 #pragma unroll
-            for (int v = 0; v < 16; ++v) xs[h][v] += (double)acc[h][v];
+            for (int v = 0; v < 16; ++v)
+                atomicAdd(&xl[(8 * (v >> 2) + 4 * pq + (v & 3)) * 64 + 2 * rs + h], (double)acc[h][v]);
     }
 }
 
-__global__ __launch_bounds__(256) void k_scps_dist(const KParams P, const SysDesc *__restrict__ sysd,
+#ifndef SCPS_DIST_WPE
+#define SCPS_DIST_WPE 3
+#endif
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SCPS_DIST_WPE, SCPS_DIST_WPE))) void k_scps_dist(const KParams P, const SysDesc *__restrict__ sysd,
                                                    const RepDesc *__restrict__ reps,
                                                    const ScpsGroup *__restrict__ groups,
                                                    const ScpsItem *__restrict__ items, const int n_items,
                                                    const float4 *__restrict__ xs, double *__restrict__ X,
                                                    double *__restrict__ Q, const int kmax) {
-    __shared__ __align__(16) float4 pos[2][64][32];   // [block I / J][particle][replica slot]; reused to reduce
-    __shared__ int org[2][64];
+    __shared__ __align__(16) float4 posj[64][32];   // block J of every replica slot
+    __shared__ double xl[32 * 64];                   // float64 sums X[slot][frame] of the current group
+    __shared__ double ql[4][64];
+    __shared__ int orgj[64];
     __shared__ int sh_rep[32];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    double xsum[2][16];
+    for (int e = tid; e < 32 * 64; e += 256) xl[e] = 0.0;
     double q = 0.0;
-#pragma unroll
-    for (int h = 0; h < 2; ++h)
-#pragma unroll
-        for (int v = 0; v < 16; ++v) xsum[h][v] = 0.0;
     int cur = -1, nrep = 0;
     SysDesc S;
     for (int t = blockIdx.x;; t += gridDim.x) {
         const bool more = t < n_items;
         const ScpsItem it = more ? items[t] : ScpsItem{-1, 0, 0, 0};
         if (cur >= 0 && it.group != cur) {
-            // flush: reduce the four wavefronts' sums through LDS, then float64 atomics
-            __syncthreads();
-            double *red = reinterpret_cast<double *>(&pos[0][0][0]);   // [4 waves][32 values][64 lanes]
-#pragma unroll
-            for (int h = 0; h < 2; ++h)
-#pragma unroll
-                for (int v = 0; v < 16; ++v) red[(wave * 32 + h * 16 + v) * 64 + lane] = xsum[h][v];
+            // flush the group's sums to the replicas' float64 totals
+            ql[wave][lane] = q;
             __syncthreads();
             for (int e = tid; e < 32 * 64; e += 256) {
-                const int reg = e >> 6, ln = e & 63;
-                const double sum = red[e] + red[2048 + e] + red[4096 + e] + red[6144 + e];
-                const int h = reg >> 4, v = reg & 15;
-                const int slot = 8 * (v >> 2) + 4 * (ln >> 5) + (v & 3), k = 2 * (ln & 31) + h;
-                if (slot < nrep && k < S.K) unsafeAtomicAdd(&X[(int64_t)sh_rep[slot] * kmax + k], sum);
+                const int slot = e >> 6, k = e & 63;
+                if (slot < nrep && k < S.K) unsafeAtomicAdd(&X[(int64_t)sh_rep[slot] * kmax + k], xl[e]);
+                xl[e] = 0.0;
             }
-            __syncthreads();
-            red[wave * 64 + lane] = q;
-            __syncthreads();
             if (tid < 32) {
                 double sum = 0.0;
-                for (int w = 0; w < 4; ++w) sum += red[w * 64 + tid] + red[w * 64 + 32 + tid];
+                for (int w = 0; w < 4; ++w) sum += ql[w][tid] + ql[w][32 + tid];
                 if (tid < nrep) unsafeAtomicAdd(&Q[sh_rep[tid]], sum);
             }
-#pragma unroll
-            for (int h = 0; h < 2; ++h)
-#pragma unroll
-                for (int v = 0; v < 16; ++v) xsum[h][v] = 0.0;
             q = 0.0;
         }
         if (!more) break;
@@ -1341,20 +1334,21 @@ __global__ __launch_bounds__(256) void k_scps_dist(const KParams P, const SysDes
             if (tid < 32) sh_rep[tid] = tid < nrep ? gp->rep[tid] : 0;
             __syncthreads();
         }
-        // stage the positions of blocks I and J of every replica of the group
-        const int I = it.IJ >> 16, J = it.IJ & 0xFFFF;
-        for (int e = tid; e < 2 * 64 * 32; e += 256) {
-            const int blk = e >> 11, pl = (e >> 5) & 63, slot = e & 31;
+        // stage block J of every replica of the group
+        const int J = it.IJ & 0xFFFF;
+        for (int e = tid; e < 64 * 32; e += 256) {
+            const int pl = e >> 5, slot = e & 31;
             float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (slot < nrep) p = xs[2 * reps[sh_rep[slot]].poff + (blk ? J : I) * 128 + pl];
-            pos[blk][pl][slot] = p;
+            if (slot < nrep) p = xs[2 * reps[sh_rep[slot]].poff + J * 128 + pl];
+            posj[pl][slot] = p;
         }
-        if (tid < 128) org[tid >> 6][tid & 63] = S.perm[((tid >> 6) ? J : I) * 64 + (tid & 63)];
+        if (tid < 64) orgj[tid] = S.perm[J * 64 + tid];
         __syncthreads();
+        const int myrep = sh_rep[lane & 31];
         if (it.flags & TILE_MASK)
-            scps_dist_tile<true>(P, S, nrep, it, pos, org, lane, wave, xsum, q);
+            scps_dist_tile<true>(P, S, nrep, it, posj, orgj, xs, reps, myrep, lane, wave, xl, q);
         else
-            scps_dist_tile<false>(P, S, nrep, it, pos, org, lane, wave, xsum, q);
+            scps_dist_tile<false>(P, S, nrep, it, posj, orgj, xs, reps, myrep, lane, wave, xl, q);
     }
 }
 
@@ -1449,7 +1443,8 @@ hipError_t launch_scps_dist(const KParams &P, const SysDesc *sysd, const RepDesc
                             const ScpsItem *items, int n_items, const float4 *xs, double *X, double *Q, int kmax,
                             hipStream_t st) {
     if (n_items == 0) return hipSuccess;
-    const int grid = n_items < 512 ? n_items : 512;
+    const int cap = 256 * SCPS_DIST_WPE;   // resident workgroups: WPE per SIMD, four waves each
+    const int grid = n_items < cap ? n_items : cap;
     hipLaunchKernelGGL(k_scps_dist, dim3(grid), dim3(256), 0, st, P, sysd, reps, groups, items, n_items, xs, X, Q,
                        kmax);
     return hipGetLastError();
