@@ -66,14 +66,19 @@ def parse():
     return ap.parse_args()
 
 
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1705_02180_amd", "csrc", "scps_kernels.hip")
+# sources of the persistent rMD kernel: its counter summary is valid for these
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1705_02180_amd", "csrc", f)
+                  for f in ("scps_kernels.hip", "scps_device.h", "scps_internal.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_rmd_persistent_traffic.json")
 
 
 def source_sha256():
     import hashlib
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def measured_traffic():

@@ -21,6 +21,7 @@
 // (4/r0^2) (C - R) C'(q) (x_i - x_j).
 #include <math.h>
 
+#include "scps_device.h"
 #include "scps_internal.h"
 
 #ifndef SCPS_PAIR_GROUP
@@ -35,9 +36,6 @@ namespace scps {
 // ---------------------------------------------------------------------------
 // device helpers
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
-__device__ __forceinline__ float fexp2(float x) { return __builtin_amdgcn_exp2f(x); }
 
 // Lane l receives what lane (l + 1) mod 64 holds (DPP wave_rol:1).  Every
 // lane has a valid source, so the "old" operand is never used; passing the
@@ -52,12 +50,6 @@ __device__ __forceinline__ float rot1(float v) {
 typedef const float __attribute__((address_space(1))) gfloat;
 __device__ __forceinline__ float ldg(const float *p, int64_t i) {
     return ((gfloat *)p)[i];
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
 }
 
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds, Weyl key schedule.
@@ -119,13 +111,6 @@ struct LaneI {
     bool contact; // i in the contact set
 };
 
-// Squared distance of a pair, and the vector d = x_i - x_j.
-__device__ __forceinline__ float pair_r2(const float4 &pi, const float4 &pj, float &dx, float &dy, float &dz) {
-    dx = pi.x - pj.x;
-    dy = pi.y - pj.y;
-    dz = pi.z - pj.z;
-    return fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-}
 
 // Nonbonded scalar f with F_i += f (x_i - x_j):
 // f = [24 eps (2 s^12 - s^6) + k_e/eps_r q_i q_j e^{-kappa r} (kappa + 1/r)] / r^2, s = sigma / r,
@@ -503,15 +488,6 @@ int persistent_max_npad(int wg) {
     return (n / 64) * 64;
 }
 
-__device__ __forceinline__ void tile_decode(int t, int nb, int &I, int &J) {
-    int row = 0;
-    while (t >= nb - row) {
-        t -= nb - row;
-        ++row;
-    }
-    I = row;
-    J = row + t;
-}
 
 // One workgroup per replica is resident per CU in the benchmark shapes, so
 // the register budget is WG/64/4 waves per SIMD: let the scheduler use it for
@@ -1127,338 +1103,6 @@ hipError_t launch_finalize_scps(const KParams &P, const SysDesc *sysd, const Rep
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------------------
-// SCPS on matrix cores.  The squared distance of replica r to frame k,
-// d_k Z0 = sum_p (C_rp - R_kp)^2, splits into sum_p C_rp^2 - 2 X_rk +
-// sum_p R_kp^2 with X_rk = sum_p C_rp R_kp: for a group of up to 32 replicas
-// of one system that is a dense contraction over the contact pairs p, done
-// here with float32 MFMA whose sums are moved into float64 every 64 pairs
-// (the three terms are then accurate to float64 rounding of float32-exact
-// partial sums, which keeps the cancellation in Q - 2X + R2 harmless).  The
-// bias pass needs each replica's effective reference E_rp = sum_k c_rk R_kp, a
-// contraction over the frames, also float32 MFMA (the same rounding as a
-// float32 dot product).  Both read every stack tile once per group instead of
-// once per replica.
-// ---------------------------------------------------------------------------
-typedef float fvec16 __attribute__((ext_vector_type(16)));
-
-// Unordered contact pair (64 I + l, 64 J + ((l + s) mod 64)) of a tile in the
-// diagonal-major layout: in a diagonal tile every pair appears twice; the
-// copy at sub-steps 1..31, or at 32 for l < 32, is the one that counts.
-__device__ __forceinline__ bool tile_pair_counts(bool diag, int s, int l) {
-    return !diag || (s >= 1 && (s < 32 || (s == 32 && l < 32)));
-}
-
-// Pair-major copy of a frame stack: stack_pm[tile][p][k] = stack[tile][k][p]
-// for k < K (zero for K <= k < K4), and R2[k] += sum over the counted pairs of
-// R_kp^2 (float64; pairs within min_seq_sep, outside the contact set or
-// repeated in a diagonal tile are not counted).  One workgroup per (tile,
-// sub-step s): the 64 pairs of that sub-step.  R2 must be zero on entry.
-__global__ __launch_bounds__(256) void k_stack_pairmajor(int nc, int ncb, int ntile, int K, int min_sep,
-                                                         const int *__restrict__ perm,
-                                                         const float *__restrict__ stack,
-                                                         float *__restrict__ stack_pm, double *__restrict__ R2) {
-    __shared__ float buf[64][KMAX + 1];
-    __shared__ double r2s[KMAX];
-    const int tile = blockIdx.x, s = blockIdx.y;
-    int I, J;
-    tile_decode(tile, ncb, I, J);
-    const int tid = threadIdx.x;
-    if (tid < KMAX) r2s[tid] = 0.0;
-    __syncthreads();
-    for (int e = tid; e < 64 * K; e += 256) {
-        const int k = e >> 6, l = e & 63;
-        const float v = stack[((int64_t)tile * K + k) * 4096 + s * 64 + l];
-        buf[l][k] = v;
-        const int a = I * 64 + l, b = J * 64 + ((l + s) & 63);
-        const bool counts = a < nc && b < nc && tile_pair_counts(I == J, s, l) && abs(perm[a] - perm[b]) > min_sep;
-        if (counts) atomicAdd(&r2s[k], (double)v * (double)v);
-    }
-    __syncthreads();
-    const int K4 = stack_pm_width(K);
-    float *out = stack_pm + ((int64_t)tile * 4096 + s * 64) * K4;
-    for (int e = tid; e < 64 * K4; e += 256) {
-        const int l = e / K4, k = e - l * K4;
-        out[e] = k < K ? buf[l][k] : 0.f;
-    }
-    if (tid < K) unsafeAtomicAdd(&R2[tid], r2s[tid]);
-}
-
-hipError_t launch_stack_pairmajor(int nc, int ncb, int K, int min_sep, const int *perm, const float *stack,
-                                  float *stack_pm, double *R2, hipStream_t st) {
-    const int nt = ncb * (ncb + 1) / 2;
-    if (nt == 0 || K == 0) return hipSuccess;
-    if (K > KMAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_stack_pairmajor, dim3(nt, 64), dim3(256), 0, st, nc, ncb, nt, K, min_sep, perm, stack,
-                       stack_pm, R2);
-    return hipGetLastError();
-}
-
-// Contact value of one replica-pair for the MFMA operand (0 when the pair
-// does not count).
-__device__ __forceinline__ float contact_operand(const KParams &P, const float4 &pi, const float4 &pj, bool ok) {
-    float dx, dy, dz;
-    const float r2 = pair_r2(pi, pj, dx, dy, dz);
-    const float q = r2 * P.inv_r0sq;
-    const float q2 = q * q;
-    const float num = 1.f + q + q2;
-    const float den = fmaf(q2, q + q2, num);
-    const bool inside = !P.has_cut | (r2 <= P.r_cut2);
-    return (ok & inside) ? num * frcp(den) : 0.f;
-}
-
-#ifndef SCPS_DIST_AHEAD
-#define SCPS_DIST_AHEAD 8
-#endif
-// Pass 1: X[r][k] += sum_p C_rp R_kp and Q[r] += sum_p C_rp^2 over the contact
-// pairs of each work item (group of replicas, tile); workgroups stride over
-// the items and flush their sums when the group changes and at the end.
-// The pairs of a tile are taken row by row: wavefront w takes rows
-// i = w, w+4, ... of block I and, per row, 32 MFMA steps of 2 pairs
-// (i, 2m + (l >> 5)); lane l evaluates that pair for replica l & 31 (A operand
-// of 32x32x2 float32 MFMAs) with particle i's position held in a register and
-// particle j's read from the block-J positions in LDS, and loads frames
-// 2 (l & 31) and 2 (l & 31) + 1 of the pair with one 8-byte load,
-// SCPS_DIST_AHEAD steps ahead of their use; frame block h holds frames 2j + h,
-// so component h of that load is the lane's B operand of block h.  A diagonal
-// tile counts the pairs j > i.  The float32 accumulators hold one row (64
-// pairs per element) and are added after every row into the workgroup's
-// float64 sums xl[slot][frame] in LDS.  Element v of lane l in block h is
-// replica slot 8 (v >> 2) + 4 (l >> 5) + (v & 3), frame 2 (l & 31) + h.
-template <bool MASK>
-__device__ __forceinline__ void scps_dist_tile(const KParams &P, const SysDesc &S, const int nrep,
-                                               const ScpsItem &it, const float4 (*posj)[32], const int *orgj,
-                                               const float4 *__restrict__ xs, const RepDesc *__restrict__ reps,
-                                               const int myrep, const int lane, const int wave, double *xl,
-                                               double &q) {
-    const int I = it.IJ >> 16, J = it.IJ & 0xFFFF;
-    const bool diag = I == J;
-    const int K4 = stack_pm_width(S.K);
-    const int rs = lane & 31, pq = lane >> 5;
-    const bool rep = rs < nrep;
-    const bool bload = 2 * rs < K4;
-    const float *Rt = S.stack_pm + (int64_t)it.tile * 4096 * K4 + 2 * rs;
-    const float4 *xr = xs + 2 * reps[myrep].poff + I * 128;
-    constexpr int D = SCPS_DIST_AHEAD;
-    const float2 zero2 = make_float2(0.f, 0.f);
-    // pair (i, j) sits at s * 64 + i in the tile, s = (j - i) mod 64
-    auto bop = [&](int i_, int m_) {
-        const int s_ = (2 * m_ + pq - i_) & 63;
-        return (bload && i_ < 64) ? *reinterpret_cast<const float2 *>(Rt + (int64_t)(s_ * 64 + i_) * K4) : zero2;
-    };
-    float2 ring[D];
-#pragma unroll
-    for (int u = 0; u < D; ++u) ring[u] = bop(wave, u);
-#pragma unroll 1
-    for (int i = wave; i < 64; i += 4) {
-        const float4 pi = rep ? xr[i] : make_float4(0.f, 0.f, 0.f, 0.f);
-        const int oi = MASK ? S.perm[I * 64 + i] : 0;
-        const bool icon = I * 64 + i < S.nc;
-        fvec16 acc[2];
-#pragma unroll
-        for (int h = 0; h < 2; ++h)
-#pragma unroll
-            for (int v = 0; v < 16; ++v) acc[h][v] = 0.f;
-#pragma unroll 1
-        for (int mg = 0; mg < 32 / D; ++mg) {
-#pragma unroll
-            for (int u = 0; u < D; ++u) {
-                const int m = D * mg + u;
-                const float2 b = ring[u];
-                const int nm = m + D < 32 ? m + D : m + D - 32, ni = m + D < 32 ? i : i + 4;
-                ring[u] = bop(ni, nm);
-                const int jl = 2 * m + pq;
-                bool ok = !diag | (jl > i);
-                if constexpr (MASK) {
-                    ok = ok & icon & (J * 64 + jl < S.nc) & (abs(oi - orgj[jl]) > P.min_sep);
-                }
-                const float c = contact_operand(P, pi, posj[jl][rs], ok & rep);
-                q = fma((double)c, (double)c, q);
-                acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(c, b.x, acc[0], 0, 0, 0);
-                acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(c, b.y, acc[1], 0, 0, 0);
-            }
-        }
-#pragma unroll
-        for (int h = 0; h < 2; ++h)
-#pragma unroll
-            for (int v = 0; v < 16; ++v)
-                atomicAdd(&xl[(8 * (v >> 2) + 4 * pq + (v & 3)) * 64 + 2 * rs + h], (double)acc[h][v]);
-    }
-}
-
-#ifndef SCPS_DIST_WPE
-#define SCPS_DIST_WPE 3
-#endif
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SCPS_DIST_WPE, SCPS_DIST_WPE))) void k_scps_dist(const KParams P, const SysDesc *__restrict__ sysd,
-                                                   const RepDesc *__restrict__ reps,
-                                                   const ScpsGroup *__restrict__ groups,
-                                                   const ScpsItem *__restrict__ items, const int n_items,
-                                                   const float4 *__restrict__ xs, double *__restrict__ X,
-                                                   double *__restrict__ Q, const int kmax) {
-    __shared__ __align__(16) float4 posj[64][32];   // block J of every replica slot
-    __shared__ double xl[32 * 64];                   // float64 sums X[slot][frame] of the current group
-    __shared__ double ql[4][64];
-    __shared__ int orgj[64];
-    __shared__ int sh_rep[32];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int e = tid; e < 32 * 64; e += 256) xl[e] = 0.0;
-    double q = 0.0;
-    int cur = -1, nrep = 0;
-    SysDesc S;
-    for (int t = blockIdx.x;; t += gridDim.x) {
-        const bool more = t < n_items;
-        const ScpsItem it = more ? items[t] : ScpsItem{-1, 0, 0, 0};
-        if (cur >= 0 && it.group != cur) {
-            // flush the group's sums to the replicas' float64 totals
-            ql[wave][lane] = q;
-            __syncthreads();
-            for (int e = tid; e < 32 * 64; e += 256) {
-                const int slot = e >> 6, k = e & 63;
-                if (slot < nrep && k < S.K) unsafeAtomicAdd(&X[(int64_t)sh_rep[slot] * kmax + k], xl[e]);
-                xl[e] = 0.0;
-            }
-            if (tid < 32) {
-                double sum = 0.0;
-                for (int w = 0; w < 4; ++w) sum += ql[w][tid] + ql[w][32 + tid];
-                if (tid < nrep) unsafeAtomicAdd(&Q[sh_rep[tid]], sum);
-            }
-            q = 0.0;
-        }
-        if (!more) break;
-        __syncthreads();
-        if (it.group != cur) {
-            cur = it.group;
-            const ScpsGroup *gp = groups + cur;
-            nrep = gp->nrep;
-            S = sysd[gp->sys];
-            if (tid < 32) sh_rep[tid] = tid < nrep ? gp->rep[tid] : 0;
-            __syncthreads();
-        }
-        // stage block J of every replica of the group
-        const int J = it.IJ & 0xFFFF;
-        for (int e = tid; e < 64 * 32; e += 256) {
-            const int pl = e >> 5, slot = e & 31;
-            float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (slot < nrep) p = xs[2 * reps[sh_rep[slot]].poff + J * 128 + pl];
-            posj[pl][slot] = p;
-        }
-        if (tid < 64) orgj[tid] = S.perm[J * 64 + tid];
-        __syncthreads();
-        const int myrep = sh_rep[lane & 31];
-        if (it.flags & TILE_MASK)
-            scps_dist_tile<true>(P, S, nrep, it, posj, orgj, xs, reps, myrep, lane, wave, xl, q);
-        else
-            scps_dist_tile<false>(P, S, nrep, it, posj, orgj, xs, reps, myrep, lane, wave, xl, q);
-    }
-}
-
-// Pass 2 operand: E[eoff_r + tile * 4096 + p] = sum_k c_rk R_kp for every
-// pair p of each work item's tile and replica r of its group (coef holds
-// c_rk).  Wavefront w takes chunks of 32 EFF_NB pairs w, w+4, ...; a chunk is
-// EFF_NB 32-pair MFMA blocks interleaved so that block b holds pairs
-// EFF_NB j + b: lane l reads pairs EFF_NB (l & 31) .. +EFF_NB-1 of frame
-// 2 kk + (l >> 5) with one load (component b is its B operand of block b)
-// and supplies c of replica l & 31 for that frame (A operand, 32x32x2
-// float32 MFMA).  Result element v of lane l in block b is replica
-// 8 (v >> 2) + 4 (l >> 5) + (v & 3), pair EFF_NB (l & 31) + b: the blocks give
-// one EFF_NB-wide store per replica.
-#ifndef SCPS_EFF_BLOCKS
-#define SCPS_EFF_BLOCKS 4
-#endif
-#ifndef SCPS_EFF_WPE
-#define SCPS_EFF_WPE (SCPS_EFF_BLOCKS == 4 ? 2 : 3)
-#endif
-constexpr int EFF_NB = SCPS_EFF_BLOCKS;
-static_assert(EFF_NB == 2 || EFF_NB == 4, "chunks of 2 or 4 MFMA blocks");
-typedef float effvec __attribute__((ext_vector_type(EFF_NB)));
-
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SCPS_EFF_WPE, SCPS_EFF_WPE))) void k_scps_eff(
-    const SysDesc *__restrict__ sysd, const RepDesc *__restrict__ reps, const ScpsGroup *__restrict__ groups,
-    const ScpsItem *__restrict__ items, const int n_items, const float *__restrict__ coef, const int kmax,
-    float *__restrict__ E) {
-    __shared__ int64_t sh_eoff[SCPS_GROUP];   // -1 for an empty slot
-    constexpr int CH = 32 * EFF_NB;            // pairs per chunk
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int slot = lane & 31, half = lane >> 5;
-    int cur = -1;
-    SysDesc S;
-    float creg[KMAX / 2];
-    for (int t = blockIdx.x; t < n_items; t += gridDim.x) {
-        const ScpsItem it = items[t];
-        if (it.group != cur) {
-            cur = it.group;
-            const ScpsGroup *gp = groups + cur;
-            const int nrep = gp->nrep;
-            S = sysd[gp->sys];
-            const int myrep = slot < nrep ? gp->rep[slot] : 0;
-#pragma unroll
-            for (int kk = 0; kk < KMAX / 2; ++kk) {
-                const int k = 2 * kk + half;
-                creg[kk] = (slot < nrep && k < S.K) ? coef[(int64_t)myrep * kmax + k] : 0.f;
-            }
-            __syncthreads();
-            if (tid < SCPS_GROUP) sh_eoff[tid] = tid < nrep ? reps[gp->rep[tid]].eoff : -1;
-            __syncthreads();
-        }
-        const int K = S.K;
-        const float *Rt = S.stack + (int64_t)it.tile * K * 4096;
-#pragma unroll 1
-        for (int ch = wave; ch < 4096 / CH; ch += 4) {
-            const int p = ch * CH + EFF_NB * slot;
-            fvec16 acc[EFF_NB];
-#pragma unroll
-            for (int bl = 0; bl < EFF_NB; ++bl)
-#pragma unroll
-                for (int v = 0; v < 16; ++v) acc[bl][v] = 0.f;
-#pragma unroll
-            for (int kk = 0; kk < KMAX / 2; ++kk) {
-                if (2 * kk < K) {
-                    const int k = 2 * kk + half;
-                    effvec b;
-                    if (k < K)
-                        b = *reinterpret_cast<const effvec *>(Rt + k * 4096 + p);
-                    else
-#pragma unroll
-                        for (int bl = 0; bl < EFF_NB; ++bl) b[bl] = 0.f;
-#pragma unroll
-                    for (int bl = 0; bl < EFF_NB; ++bl)
-                        acc[bl] = __builtin_amdgcn_mfma_f32_32x32x2f32(creg[kk], b[bl], acc[bl], 0, 0, 0);
-                }
-            }
-#pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const int64_t eo = sh_eoff[8 * (v >> 2) + 4 * half + (v & 3)];
-                if (eo >= 0) {
-                    effvec o;
-#pragma unroll
-                    for (int bl = 0; bl < EFF_NB; ++bl) o[bl] = acc[bl][v];
-                    *reinterpret_cast<effvec *>(E + eo + (int64_t)it.tile * 4096 + p) = o;
-                }
-            }
-        }
-    }
-}
-
-hipError_t launch_scps_dist(const KParams &P, const SysDesc *sysd, const RepDesc *reps, const ScpsGroup *groups,
-                            const ScpsItem *items, int n_items, const float4 *xs, double *X, double *Q, int kmax,
-                            hipStream_t st) {
-    if (n_items == 0) return hipSuccess;
-    const int cap = 256 * SCPS_DIST_WPE;   // resident workgroups: WPE per SIMD, four waves each
-    const int grid = n_items < cap ? n_items : cap;
-    hipLaunchKernelGGL(k_scps_dist, dim3(grid), dim3(256), 0, st, P, sysd, reps, groups, items, n_items, xs, X, Q,
-                       kmax);
-    return hipGetLastError();
-}
-
-hipError_t launch_scps_eff(const SysDesc *sysd, const RepDesc *reps, const ScpsGroup *groups, const ScpsItem *items,
-                           int n_items, const float *coef, int kmax, float *E, hipStream_t st) {
-    if (n_items == 0) return hipSuccess;
-    const int grid = n_items < 1024 ? n_items : 1024;
-    hipLaunchKernelGGL(k_scps_eff, dim3(grid), dim3(256), 0, st, sysd, reps, groups, items, n_items, coef, kmax,
-                       E);
-    return hipGetLastError();
-}
-
 // Langevin update of every particle; consumes and clears the accumulators.
 // The force is acc[0..2] + scale[r] * acc[3..5], the second term being the
 // bias; each workgroup adds its particles' dt |F_bias|^2 / (m gamma) to the
@@ -1579,186 +1223,6 @@ __global__ void k_ratchet_energy(int R, double k_R, const double *__restrict__ z
 hipError_t launch_ratchet_energy(int R, double k_R, const double *z, const double *zm, double *Eb,
                                  const double *gz, const double *gE, double *coef, hipStream_t st) {
     hipLaunchKernelGGL(k_ratchet_energy, dim3((R + 255) / 256), dim3(256), 0, st, R, k_R, z, zm, Eb, gz, gE, coef);
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// reference maps
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ double contact_f64(double r2, double r0, double r_cut) {
-    if (r_cut > 0.0 && r2 > r_cut * r_cut) return 0.0;
-    const double q = r2 / (r0 * r0);
-    const double q2 = q * q;
-    const double num = 1.0 + q + q2;
-    return num / (num + q2 * (q + q2));
-}
-
-__device__ __forceinline__ int64_t packed_index(int nc, int a, int b) {
-    return (int64_t)a * nc - (int64_t)a * (a + 1) / 2 + (b - a - 1);
-}
-
-// One workgroup of 256 threads per contact tile pair; thread (w, l) fills
-// rows k = w, w+4, ... of the diagonal-major layout element [k][l] =
-// R(64I + l, 64J + ((l + k) mod 64)).  Internal contact positions equal the
-// positions in contact_idx, so tiles and packed maps share indices.
-__global__ void k_native_map(int n, int nc, int ncb, const int *__restrict__ perm, const double *__restrict__ xyz,
-                             double r0, double r_cut, float *__restrict__ tiles, double *__restrict__ packed) {
-    int I, J;
-    tile_decode(blockIdx.x, ncb, I, J);
-    const int l = threadIdx.x & 63;
-    const int a = I * 64 + l;
-    float *t = tiles + (int64_t)blockIdx.x * 4096;
-    for (int k = threadIdx.x >> 6; k < 64; k += 4) {
-        const int b = J * 64 + ((l + k) & 63);
-        double C = 0.0;
-        if (a < nc && b < nc && a != b) {
-            const int oa = perm[a], ob = perm[b];
-            const double dx = xyz[oa] - xyz[ob];
-            const double dy = xyz[n + oa] - xyz[n + ob];
-            const double dz = xyz[2 * n + oa] - xyz[2 * n + ob];
-            C = contact_f64(dx * dx + dy * dy + dz * dz, r0, r_cut);
-            if (packed && a < b) packed[packed_index(nc, a, b)] = C;
-        }
-        t[k * 64 + l] = (float)C;
-    }
-}
-
-hipError_t launch_native_map(int n, int n_pad, int nc, int ncb, const int *perm_dev, const double *xyz_dev,
-                             double r0, double r_cut, float *tiles, double *packed, hipStream_t st) {
-    (void)n_pad;
-    const int nt = ncb * (ncb + 1) / 2;
-    if (nt == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_native_map, dim3(nt), dim3(256), 0, st, n, nc, ncb, perm_dev, xyz_dev, r0, r_cut, tiles,
-                       packed);
-    return hipGetLastError();
-}
-
-__global__ void k_pack_to_tiles(int nc, int ncb, int ntile, const double *__restrict__ packed,
-                                float *__restrict__ tiles) {
-    const int tile = blockIdx.x;
-    const int map = blockIdx.y;
-    int I, J;
-    tile_decode(tile, ncb, I, J);
-    const int64_t P = (int64_t)nc * (nc - 1) / 2;
-    const double *pm = packed + (int64_t)map * P;
-    float *t = tiles + ((int64_t)tile * gridDim.y + map) * 4096;   // [tile][map][4096]
-    const int l = threadIdx.x & 63;
-    const int a = I * 64 + l;
-    for (int k = threadIdx.x >> 6; k < 64; k += 4) {
-        const int b = J * 64 + ((l + k) & 63);
-        float v = 0.f;
-        if (a < nc && b < nc && a != b) v = (float)pm[a < b ? packed_index(nc, a, b) : packed_index(nc, b, a)];
-        t[k * 64 + l] = v;
-    }
-}
-
-hipError_t launch_pack_to_tiles(int n_maps, int nc, int ncb, const double *packed, float *tiles, hipStream_t st) {
-    const int nt = ncb * (ncb + 1) / 2;
-    if (nt == 0 || n_maps == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pack_to_tiles, dim3(nt, n_maps), dim3(256), 0, st, nc, ncb, nt, packed, tiles);
-    return hipGetLastError();
-}
-
-// sum_i v_i^2 in two fixed-order phases: SUMSQ_BLOCKS workgroups each reduce
-// a contiguous chunk into part[], then one workgroup adds the partials.
-constexpr int SUMSQ_BLOCKS = 256;
-__global__ void k_sum_squares(int64_t m, const double *__restrict__ v, double *__restrict__ part,
-                              double *__restrict__ out) {
-    __shared__ double red[4];
-    const int64_t chunk = (m + gridDim.x - 1) / gridDim.x;
-    const int64_t lo = (int64_t)blockIdx.x * chunk, hi = lo + chunk < m ? lo + chunk : m;
-    double s = 0.0;
-    for (int64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) s += v[e] * v[e];
-    s = wave_sum(s);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
-}
-
-__global__ void k_sum_parts(int n, const double *__restrict__ part, double *__restrict__ out) {
-    __shared__ double red[4];
-    double s = 0.0;
-    for (int e = threadIdx.x; e < n; e += blockDim.x) s += part[e];
-    s = wave_sum(s);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) *out = red[0] + red[1] + red[2] + red[3];
-}
-
-int sum_squares_scratch() { return SUMSQ_BLOCKS; }
-
-hipError_t launch_sum_squares(int64_t m, const double *v, double *part, double *out, hipStream_t st) {
-    hipLaunchKernelGGL(k_sum_squares, dim3(SUMSQ_BLOCKS), dim3(256), 0, st, m, v, part, out);
-    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, st, SUMSQ_BLOCKS, part, out);
-    return hipGetLastError();
-}
-
-// eq (avCij): mean over successful paths of C(X_p(t_k)), float64 sums.
-// Grid (contact tile pair, frame); thread (w, l) owns 16 rows k of the
-// diagonal-major tile and loops over the successful paths.
-__global__ __launch_bounds__(256) void k_update_reference(int n, int nc, int ncb, int ntile,
-                                                          const int *__restrict__ perm,
-                                                          const float *__restrict__ frames, int n_paths,
-                                                          const int *__restrict__ succ, int n_succ, double r0,
-                                                          double r_cut, float *__restrict__ tiles,
-                                                          double *__restrict__ packed) {
-    __shared__ float4 blk[2][64];
-    const int tile = blockIdx.x, f = blockIdx.y;
-    int I, J;
-    tile_decode(tile, ncb, I, J);
-    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int a = I * 64 + l;
-    double sum[16];
-#pragma unroll
-    for (int k = 0; k < 16; ++k) sum[k] = 0.0;
-    for (int s = 0; s < n_succ; ++s) {
-        const float *X = frames + ((int64_t)f * n_paths + succ[s]) * 3 * (int64_t)n;
-        __syncthreads();
-        if (threadIdx.x < 128) {
-            const int which = threadIdx.x >> 6;
-            const int c = (which ? J : I) * 64 + l;
-            float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (c < nc) {
-                const int o = perm[c];
-                p = make_float4(X[o], X[n + o], X[2 * n + o], 0.f);
-            }
-            blk[which][l] = p;
-        }
-        __syncthreads();
-        const float4 pa = blk[0][l];
-#pragma unroll
-        for (int kk = 0; kk < 16; ++kk) {
-            const int k = w * 16 + kk;
-            const float4 pb = blk[1][(l + k) & 63];
-            const double dx = (double)pa.x - (double)pb.x;
-            const double dy = (double)pa.y - (double)pb.y;
-            const double dz = (double)pa.z - (double)pb.z;
-            sum[kk] += contact_f64(dx * dx + dy * dy + dz * dz, r0, r_cut);
-        }
-    }
-    float *t = tiles + ((int64_t)tile * gridDim.y + f) * 4096;     // [tile][frame][4096]
-    const int64_t P = (int64_t)nc * (nc - 1) / 2;
-#pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-        const int k = w * 16 + kk;
-        const int b = J * 64 + ((l + k) & 63);
-        double mean = 0.0;
-        if (a < nc && b < nc && a != b) {
-            mean = sum[kk] / (double)n_succ;
-            if (packed && a < b) packed[(int64_t)f * P + packed_index(nc, a, b)] = mean;
-        }
-        t[k * 64 + l] = (float)mean;
-    }
-}
-
-hipError_t launch_update_reference(int n, int n_pad, int nc, int ncb, const int *perm_dev, const float *frames,
-                                   int n_paths, int n_frames, const int *succ_idx, int n_succ, double r0,
-                                   double r_cut, float *tiles, double *packed, hipStream_t st) {
-    (void)n_pad;
-    const int nt = ncb * (ncb + 1) / 2;
-    if (nt == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_update_reference, dim3(nt, n_frames), dim3(256), 0, st, n, nc, ncb, nt, perm_dev, frames,
-                       n_paths, succ_idx, n_succ, r0, r_cut, tiles, packed);
     return hipGetLastError();
 }
 
