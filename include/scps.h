@@ -198,6 +198,22 @@ scps_status scps_update_reference_from_paths(scps_ctx *ctx, int32_t system, cons
                                              int32_t n_paths, int32_t n_frames,
                                              const uint8_t *success, double *maps_out);
 
+/* Least-biased path selection, the last step of an SCPS iteration (the
+ * method ranks the paths it generated by the bias functional T[X] of eq (T),
+ * the weighted time integral of the squared bias force, and keeps the one
+ * with the smallest value as its prediction of the most probable path).
+ * Finds the replica r with the smallest cvstate[r][SCPS_CV_T] among those with
+ * success[r] != 0; equal values go to the lowest r.
+ *   cvstate: device float64 [R][SCPS_CV_STRIDE], as scps_step_replicas left it.
+ *   success: host uint8 [R], nonzero = candidate; NULL = every replica.
+ *   index:   host int32, receives r.
+ *   t_min:   nullable host float64, receives T of replica r.
+ * Queued behind earlier work on the context's stream; blocks until done.
+ * Errors: INVALID_ARG (NULL cvstate or index, or a candidate whose T is NaN
+ * or infinite; nothing is written), NO_SUCCESS (no candidate), OOM, HIP. */
+scps_status scps_least_biased_path(scps_ctx *ctx, const double *cvstate, const uint8_t *success,
+                                   int32_t *index, double *t_min);
+
 /* Replace the stream later calls queue work on (a hipStream_t or NULL). */
 scps_status scps_set_stream(scps_ctx *ctx, void *hip_stream);
 

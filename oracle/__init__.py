@@ -26,7 +26,7 @@ import numpy as np
 from . import build as _build
 
 CV_STRIDE = 8
-CV_Z, CV_ZM, CV_EB, CV_S, CV_W, CV_SM, CV_WM = range(7)
+CV_Z, CV_ZM, CV_EB, CV_S, CV_W, CV_SM, CV_WM, CV_T = range(8)
 
 _lib = None
 
@@ -89,6 +89,8 @@ def lib():
                                     i64, u64, C.c_int]
         L.orc_update_reference.restype = C.c_int
         L.orc_update_reference.argtypes = [C.c_int, C.c_int, vp, d, d, C.c_int, C.c_int, vp, vp, vp]
+        L.orc_least_biased.restype = C.c_int
+        L.orc_least_biased.argtypes = [C.c_int, vp, vp]
         _lib = L
     return _lib
 
@@ -290,3 +292,15 @@ def update_reference(n, cidx, frames, success, r0: float = 7.5, r_cut: float = 0
     ns = lib().orc_update_reference(int(n), nc, _p(cidx), r0, r_cut, nf, npth, _p(frames),
                                     _p(succ), _p(out))
     return out, ns
+
+
+def least_biased(cv, success=None) -> int:
+    """Final selection of an iteration: the path with the smallest bias
+    functional T[X] (cvstate slot CV_T) among the successful ones, ties to the
+    lowest index.  Returns -1 when there is no candidate, -2 when a
+    candidate's T is not finite."""
+    cv = np.ascontiguousarray(cv, dtype=np.float64).reshape(-1, CV_STRIDE)
+    succ = None if success is None else np.ascontiguousarray(success, dtype=np.uint8)
+    if succ is not None and succ.size != cv.shape[0]:
+        raise ValueError("success needs one entry per path")
+    return int(lib().orc_least_biased(cv.shape[0], _p(cv), _p(succ)))

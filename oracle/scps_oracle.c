@@ -501,6 +501,23 @@ int orc_update_reference(int n, int nc, const int32_t *cidx, double r0, double r
     return nsucc;
 }
 
+/* Least-biased path (the protocol's final selection): the path with the
+ * smallest bias functional T[X], eq (T), among those with success[r] != 0
+ * (success NULL = all).  T of path r is cv[r * ORC_CV_STRIDE + CV_T].  Equal
+ * values go to the lowest r.  Returns r, -1 when there is no candidate, -2
+ * when a candidate's T is not finite. */
+int orc_least_biased(int R, const double *cv, const uint8_t *success)
+{
+    int best = -1;
+    for (int r = 0; r < R; ++r) {
+        if (success && !success[r]) continue;
+        double t = cv[(int64_t)r * ORC_CV_STRIDE + CV_T];
+        if (!isfinite(t)) return -2;
+        if (best < 0 || t < cv[(int64_t)best * ORC_CV_STRIDE + CV_T]) best = r;
+    }
+    return best;
+}
+
 /* ---- array helpers for the test suite -------------------------------- */
 void orc_contact_array(int64_t m, const double *r2, double r0, double r_cut,
                        double *C, double *dC_dr2)

@@ -713,6 +713,34 @@ scps_status update_ref_impl(scps_ctx *c, int32_t s, const float *frames, int32_t
     return upload_sysdesc(c);
 }
 
+scps_status least_biased_impl(scps_ctx *c, const double *cv, const uint8_t *success, int32_t *index,
+                              double *t_min) {
+    if (!cv || !index) return fail(SCPS_ERR_INVALID_ARG, "cvstate and index must not be NULL");
+    std::vector<int> list;
+    for (int r = 0; r < c->R; ++r)
+        if (!success || success[r]) list.push_back(r);
+    if (list.empty()) return fail(SCPS_ERR_NO_SUCCESS, "no successful path to select from");
+    const int n = (int)list.size();
+    int *d_list = nullptr;             // n replica ids, then {index, non-finite count}
+    double *d_t = nullptr;
+    HIP_TRY(c, dalloc(c, &d_list, (size_t)n + 2));
+    HIP_TRY(c, dalloc(c, &d_t, 1));
+    HIP_TRY(c, hipMemcpyAsync(d_list, list.data(), n * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, launch_least_biased(cv, d_list, n, d_list + n, d_t, c->stream));
+    int out[2];
+    double t = 0.0;
+    HIP_TRY(c, hipMemcpyAsync(out, d_list + n, sizeof(out), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(&t, d_t, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    dfree(c, d_list);
+    dfree(c, d_t);
+    if (out[1] > 0)
+        return fail(SCPS_ERR_INVALID_ARG, std::to_string(out[1]) + " listed replica(s) have a non-finite T");
+    *index = out[0];
+    if (t_min) *t_min = t;
+    return SCPS_OK;
+}
+
 scps_status autotune_impl(scps_ctx *c, const float *x, const float *v, const double *cv, int64_t n_steps,
                           int32_t *chosen) {
     if (!x || !cv) return fail(SCPS_ERR_INVALID_ARG, "x and cvstate must not be NULL");
@@ -854,6 +882,17 @@ scps_status scps_autotune(scps_ctx *ctx, const float *x, const float *v, const d
     if (!usable(ctx, &st)) return st;
     try {
         return autotune_impl(ctx, x, v, cvstate, n_steps, chosen);
+    } catch (const std::bad_alloc &) {
+        return fail(SCPS_ERR_OOM, "host allocation failed");
+    }
+}
+
+scps_status scps_least_biased_path(scps_ctx *ctx, const double *cvstate, const uint8_t *success, int32_t *index,
+                                  double *t_min) {
+    scps_status st;
+    if (!usable(ctx, &st)) return st;
+    try {
+        return least_biased_impl(ctx, cvstate, success, index, t_min);
     } catch (const std::bad_alloc &) {
         return fail(SCPS_ERR_OOM, "host allocation failed");
     }

@@ -174,6 +174,7 @@ hipError_t launch_pack_to_tiles(int n_maps, int nc, int ncb, const double *packe
                                 hipStream_t st);
 int sum_squares_scratch();   // doubles of scratch launch_sum_squares needs
 hipError_t launch_sum_squares(int64_t m, const double *v, double *part, double *out, hipStream_t st);
+hipError_t launch_least_biased(const double *cv, const int *list, int n, int *out_i, double *out_t, hipStream_t st);
 hipError_t launch_update_reference(int n, int n_pad, int nc, int ncb, const int *perm_dev,
                                    const float *frames, int n_paths, int n_frames,
                                    const int *succ_idx, int n_succ, double r0, double r_cut,

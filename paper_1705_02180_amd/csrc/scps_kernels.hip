@@ -19,6 +19,7 @@
 // (the numerator of the quotient rule expanded, so no cancellation at small q).
 // z = sum over contact pairs of (C - R)^2, eq (zrMD); dz/dx_i = sum_j
 // (4/r0^2) (C - R) C'(q) (x_i - x_j).
+#include <limits.h>
 #include <math.h>
 
 #include "scps_device.h"
@@ -1223,6 +1224,55 @@ __global__ void k_ratchet_energy(int R, double k_R, const double *__restrict__ z
 hipError_t launch_ratchet_energy(int R, double k_R, const double *z, const double *zm, double *Eb,
                                  const double *gz, const double *gE, double *coef, hipStream_t st) {
     hipLaunchKernelGGL(k_ratchet_energy, dim3((R + 255) / 256), dim3(256), 0, st, R, k_R, z, zm, Eb, gz, gE, coef);
+    return hipGetLastError();
+}
+
+// Least-biased path: the replica with the smallest bias functional T[X]
+// (cvstate slot CV_T) among the listed ones, ties to the lowest replica id.
+// One workgroup; out_i = {index, number of listed replicas with a non-finite T},
+// out_t = that replica's T.
+__global__ __launch_bounds__(256) void k_least_biased(const double *__restrict__ cv, const int *__restrict__ list,
+                                                      int n, int *__restrict__ out_i, double *__restrict__ out_t) {
+    __shared__ double st[256];
+    __shared__ int si[256], sbad[256];
+    const int tid = threadIdx.x;
+    double best = INFINITY;
+    int bi = INT_MAX, bad = 0;
+    for (int s = tid; s < n; s += 256) {
+        const int r = list[s];
+        const double t = cv[(int64_t)r * CV_STRIDE + CV_T];
+        if (!isfinite(t)) {
+            ++bad;
+        } else if (t < best || (t == best && r < bi)) {
+            best = t;
+            bi = r;
+        }
+    }
+    st[tid] = best;
+    si[tid] = bi;
+    sbad[tid] = bad;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (tid < h) {
+            const double t = st[tid + h];
+            const int r = si[tid + h];
+            if (t < st[tid] || (t == st[tid] && r < si[tid])) {
+                st[tid] = t;
+                si[tid] = r;
+            }
+            sbad[tid] += sbad[tid + h];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        out_i[0] = si[0];
+        out_i[1] = sbad[0];
+        out_t[0] = st[0];
+    }
+}
+
+hipError_t launch_least_biased(const double *cv, const int *list, int n, int *out_i, double *out_t, hipStream_t st) {
+    hipLaunchKernelGGL(k_least_biased, dim3(1), dim3(256), 0, st, cv, list, n, out_i, out_t);
     return hipGetLastError();
 }
 

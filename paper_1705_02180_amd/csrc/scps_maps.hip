@@ -130,47 +130,79 @@ hipError_t launch_sum_squares(int64_t m, const double *v, double *part, double *
     return hipGetLastError();
 }
 
+// Contact function in float64 with the quotient from the hardware reciprocal
+// estimate: two Newton steps r <- r (2 - den r), then one residual correction
+// of num * r.  den >= 1 here, so no scaling or special cases are needed; the
+// result is within an ulp or two of the correctly rounded quotient.
+__device__ __forceinline__ double contact_f64_fast(double r2, double inv_r0sq) {
+    const double q = r2 * inv_r0sq;
+    const double q2 = q * q;
+    const double t = q + q2;
+    const double num = t + 1.0;
+    const double den = fma(q2, t, num);
+    double r = __builtin_amdgcn_rcp(den);
+    r = fma(r, fma(-den, r, 1.0), r);
+    r = fma(r, fma(-den, r, 1.0), r);
+    const double c = num * r;
+    return fma(fma(-den, c, num), r, c);
+}
+
+#ifndef UPDREF_PATHS
+#define UPDREF_PATHS 8
+#endif
 // eq (avCij): mean over successful paths of C(X_p(t_k)), float64 sums.
-// Grid (contact tile pair, frame); thread (w, l) owns 16 rows k of the
-// diagonal-major tile and loops over the successful paths.
-__global__ __launch_bounds__(256) void k_update_reference(int n, int nc, int ncb, int ntile,
-                                                          const int *__restrict__ perm,
+// Grid (contact tile pair, frame); thread (w, l) owns rows k = 16 w .. 16 w + 15
+// of the diagonal-major tile.  The positions of blocks I and J of
+// UPDREF_PATHS paths at a time are staged in LDS as float64 components (the
+// differences of float32 coordinates are then exact); every thread adds its
+// 16 contact values per path in path order, so the sums do not depend on the
+// launch shape.
+template <bool CUT>
+__global__ __launch_bounds__(256) void k_update_reference(int n, int nc, int ncb, const int *__restrict__ perm,
                                                           const float *__restrict__ frames, int n_paths,
-                                                          const int *__restrict__ succ, int n_succ, double r0,
-                                                          double r_cut, float *__restrict__ tiles,
+                                                          const int *__restrict__ succ, int n_succ,
+                                                          double inv_r0sq, double r_cut2, float *__restrict__ tiles,
                                                           double *__restrict__ packed) {
-    __shared__ float4 blk[2][64];
+    constexpr int PB = UPDREF_PATHS;
+    __shared__ double pos[2][3][PB][64];   // [block I/J][component][path][particle]
     const int tile = blockIdx.x, f = blockIdx.y;
     int I, J;
     tile_decode(tile, ncb, I, J);
-    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
     const int a = I * 64 + l;
     double sum[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) sum[k] = 0.0;
-    for (int s = 0; s < n_succ; ++s) {
-        const float *X = frames + ((int64_t)f * n_paths + succ[s]) * 3 * (int64_t)n;
+    for (int s0 = 0; s0 < n_succ; s0 += PB) {
+        const int np = min(PB, n_succ - s0);
         __syncthreads();
-        if (threadIdx.x < 128) {
-            const int which = threadIdx.x >> 6;
-            const int c = (which ? J : I) * 64 + l;
-            float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (c < nc) {
+        for (int e = tid; e < 2 * PB * 64; e += 256) {
+            const int which = e / (PB * 64), pp = (e >> 6) % PB, c = (which ? J : I) * 64 + (e & 63);
+            double x = 0.0, y = 0.0, z = 0.0;
+            if (pp < np && c < nc) {
+                const float *X = frames + ((int64_t)f * n_paths + succ[s0 + pp]) * 3 * (int64_t)n;
                 const int o = perm[c];
-                p = make_float4(X[o], X[n + o], X[2 * n + o], 0.f);
+                x = X[o];
+                y = X[n + o];
+                z = X[2 * n + o];
             }
-            blk[which][l] = p;
+            pos[which][0][pp][e & 63] = x;
+            pos[which][1][pp][e & 63] = y;
+            pos[which][2][pp][e & 63] = z;
         }
         __syncthreads();
-        const float4 pa = blk[0][l];
+        for (int pp = 0; pp < np; ++pp) {
+            const double ax = pos[0][0][pp][l], ay = pos[0][1][pp][l], az = pos[0][2][pp][l];
 #pragma unroll
-        for (int kk = 0; kk < 16; ++kk) {
-            const int k = w * 16 + kk;
-            const float4 pb = blk[1][(l + k) & 63];
-            const double dx = (double)pa.x - (double)pb.x;
-            const double dy = (double)pa.y - (double)pb.y;
-            const double dz = (double)pa.z - (double)pb.z;
-            sum[kk] += contact_f64(dx * dx + dy * dy + dz * dz, r0, r_cut);
+            for (int kk = 0; kk < 16; ++kk) {
+                const int j = (l + w * 16 + kk) & 63;
+                const double dx = ax - pos[1][0][pp][j];
+                const double dy = ay - pos[1][1][pp][j];
+                const double dz = az - pos[1][2][pp][j];
+                const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+                const double c = contact_f64_fast(r2, inv_r0sq);
+                sum[kk] += (CUT && r2 > r_cut2) ? 0.0 : c;
+            }
         }
     }
     float *t = tiles + ((int64_t)tile * gridDim.y + f) * 4096;     // [tile][frame][4096]
@@ -194,8 +226,13 @@ hipError_t launch_update_reference(int n, int n_pad, int nc, int ncb, const int 
     (void)n_pad;
     const int nt = ncb * (ncb + 1) / 2;
     if (nt == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_update_reference, dim3(nt, n_frames), dim3(256), 0, st, n, nc, ncb, nt, perm_dev, frames,
-                       n_paths, succ_idx, n_succ, r0, r_cut, tiles, packed);
+    const double inv_r0sq = 1.0 / (r0 * r0);
+    if (r_cut > 0.0)
+        hipLaunchKernelGGL(k_update_reference<true>, dim3(nt, n_frames), dim3(256), 0, st, n, nc, ncb, perm_dev,
+                           frames, n_paths, succ_idx, n_succ, inv_r0sq, r_cut * r_cut, tiles, packed);
+    else
+        hipLaunchKernelGGL(k_update_reference<false>, dim3(nt, n_frames), dim3(256), 0, st, n, nc, ncb, perm_dev,
+                           frames, n_paths, succ_idx, n_succ, inv_r0sq, 0.0, tiles, packed);
     return hipGetLastError();
 }
 
@@ -224,36 +261,64 @@ __device__ __forceinline__ bool tile_pair_counts(bool diag, int s, int l) {
 // Pair-major copy of a frame stack: stack_pm[tile][p][k] = stack[tile][k][p]
 // for k < K (zero for K <= k < K4), and R2[k] += sum over the counted pairs of
 // R_kp^2 (float64; pairs within min_seq_sep, outside the contact set or
-// repeated in a diagonal tile are not counted).  One workgroup per (tile,
-// sub-step s): the 64 pairs of that sub-step.  R2 must be zero on entry.
-__global__ __launch_bounds__(256) void k_stack_pairmajor(int nc, int ncb, int ntile, int K, int min_sep,
+// repeated in a diagonal tile are not counted).  Grid (tile, STACKPM_SPLIT):
+// each workgroup transposes 64 / STACKPM_SPLIT sub-steps of one tile, 64
+// pairs at a time through LDS.  Thread (w, l) reads rows k = w, w + 4, ...
+// and keeps their sums of squares in registers; each wavefront reduces them
+// at the end and adds one value per row to R2.  R2 must be zero on entry.
+#ifndef STACKPM_SPLIT
+#define STACKPM_SPLIT 1
+#endif
+__global__ __launch_bounds__(256) void k_stack_pairmajor(int nc, int ncb, int K, int min_sep,
                                                          const int *__restrict__ perm,
                                                          const float *__restrict__ stack,
                                                          float *__restrict__ stack_pm, double *__restrict__ R2) {
     __shared__ float buf[64][KMAX + 1];
-    __shared__ double r2s[KMAX];
-    const int tile = blockIdx.x, s = blockIdx.y;
+    __shared__ int orig[2][64];
+    const int tile = blockIdx.x;
     int I, J;
     tile_decode(tile, ncb, I, J);
-    const int tid = threadIdx.x;
-    if (tid < KMAX) r2s[tid] = 0.0;
-    __syncthreads();
-    for (int e = tid; e < 64 * K; e += 256) {
-        const int k = e >> 6, l = e & 63;
-        const float v = stack[((int64_t)tile * K + k) * 4096 + s * 64 + l];
-        buf[l][k] = v;
-        const int a = I * 64 + l, b = J * 64 + ((l + s) & 63);
-        const bool counts = a < nc && b < nc && tile_pair_counts(I == J, s, l) && abs(perm[a] - perm[b]) > min_sep;
-        if (counts) atomicAdd(&r2s[k], (double)v * (double)v);
+    const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
+    if (tid < 128) {
+        const int c = ((tid >> 6) ? J : I) * 64 + l;
+        orig[tid >> 6][l] = c < nc ? perm[c] : 0;
     }
-    __syncthreads();
     const int K4 = stack_pm_width(K);
-    float *out = stack_pm + ((int64_t)tile * 4096 + s * 64) * K4;
-    for (int e = tid; e < 64 * K4; e += 256) {
-        const int l = e / K4, k = e - l * K4;
-        out[e] = k < K ? buf[l][k] : 0.f;
+    constexpr int NR = KMAX / 4;           // rows per thread: k = w + 4 i
+    double r2[NR];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) r2[i] = 0.0;
+    const int per = 64 / STACKPM_SPLIT, s_beg = blockIdx.y * per;
+    const float *src = stack + (int64_t)tile * K * 4096 + l;
+    for (int s = s_beg; s < s_beg + per; ++s) {
+        __syncthreads();
+        const int a = I * 64 + l, jl = (l + s) & 63, b = J * 64 + jl;
+        const bool counts = a < nc && b < nc && tile_pair_counts(I == J, s, l) &&
+                            abs(orig[0][l] - orig[1][jl]) > min_sep;
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            const int k = w + 4 * i;
+            if (k < K) {
+                const float v = src[(int64_t)k * 4096 + s * 64];
+                buf[l][k] = v;
+                if (counts) r2[i] = fma((double)v, (double)v, r2[i]);
+            }
+        }
+        __syncthreads();
+        float *out = stack_pm + ((int64_t)tile * 4096 + s * 64) * K4;
+        for (int e = tid; e < 64 * K4; e += 256) {
+            const int pl = e / K4, k = e - pl * K4;
+            out[e] = k < K ? buf[pl][k] : 0.f;
+        }
     }
-    if (tid < K) unsafeAtomicAdd(&R2[tid], r2s[tid]);
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        const int k = w + 4 * i;
+        if (k < K) {
+            const double t = wave_sum(r2[i]);
+            if (l == 0) unsafeAtomicAdd(&R2[k], t);
+        }
+    }
 }
 
 hipError_t launch_stack_pairmajor(int nc, int ncb, int K, int min_sep, const int *perm, const float *stack,
@@ -261,8 +326,8 @@ hipError_t launch_stack_pairmajor(int nc, int ncb, int K, int min_sep, const int
     const int nt = ncb * (ncb + 1) / 2;
     if (nt == 0 || K == 0) return hipSuccess;
     if (K > KMAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_stack_pairmajor, dim3(nt, 64), dim3(256), 0, st, nc, ncb, nt, K, min_sep, perm, stack,
-                       stack_pm, R2);
+    hipLaunchKernelGGL(k_stack_pairmajor, dim3(nt, STACKPM_SPLIT), dim3(256), 0, st, nc, ncb, K, min_sep, perm,
+                       stack, stack_pm, R2);
     return hipGetLastError();
 }
 

@@ -76,6 +76,8 @@ _lib.scps_sync.restype = C.c_int
 _lib.scps_sync.argtypes = [_vp, _vp, _vp]
 _lib.scps_autotune.restype = C.c_int
 _lib.scps_autotune.argtypes = [_vp, _vp, _vp, _vp, _i64, _vp]
+_lib.scps_least_biased_path.restype = C.c_int
+_lib.scps_least_biased_path.argtypes = [_vp, _vp, _vp, _vp, _vp]
 _lib.scps_destroy.restype = None
 _lib.scps_destroy.argtypes = [_vp]
 _lib.scps_last_error.restype = C.c_char_p
@@ -83,7 +85,7 @@ _lib.scps_last_error.argtypes = []
 
 EXPORTS = ["scps_init_system", "scps_set_reference_map", "scps_step_replicas", "scps_eval_z_and_grad",
            "scps_ratchet_energy", "scps_update_reference_from_paths", "scps_set_stream", "scps_sync",
-           "scps_autotune", "scps_destroy", "scps_last_error"]
+           "scps_autotune", "scps_least_biased_path", "scps_destroy", "scps_last_error"]
 
 
 def _check(status: int):
@@ -253,6 +255,21 @@ class Context:
         out = np.zeros(2, dtype=np.int32)
         _check(_lib.scps_autotune(self._ctx(), px, pv, pc, int(n_steps), out.ctypes.data_as(C.c_void_p)))
         return int(out[0]), int(out[1])
+
+    def least_biased_path(self, cvstate: torch.Tensor, success: Optional[Sequence[int]] = None):
+        """(replica id, T) of the candidate with the smallest bias functional
+        T (cvstate[:, CV_T]); success selects the candidates (None = all)."""
+        pc = _dev(cvstate, torch.float64, self.R * CV_STRIDE, "cvstate")
+        ps = None
+        if success is not None:
+            succ = np.ascontiguousarray(np.asarray(success, dtype=np.uint8))
+            if succ.size != self.R:
+                raise ValueError("success must have one entry per replica")
+            ps = succ.ctypes.data_as(C.c_void_p)
+        idx = C.c_int32(-1)
+        t = C.c_double(0.0)
+        _check(_lib.scps_least_biased_path(self._ctx(), pc, ps, C.byref(idx), C.byref(t)))
+        return int(idx.value), float(t.value)
 
     def sync(self):
         bad = np.zeros(self.R, dtype=np.int32)

@@ -638,3 +638,64 @@ def test_autotune_picks_a_valid_launch_and_keeps_results(S):
     xs = dev(np.stack([ws.systems[0].start] * 2).astype(np.float32).ravel())
     import torch
     assert sc.autotune(xs, torch.zeros_like(xs), dev(ws.initial_cvstate(), "f64"), 2) == (1, 0)
+
+
+# ---------------------------------------------------------------------------
+# least-biased path selection (smallest bias functional T among successful paths)
+# ---------------------------------------------------------------------------
+def test_least_biased_path_matches_oracle(S):
+    w = I.config1(n_replicas=1000, n_steps=1)
+    ctx = context(S, w)
+    R = w.n_replicas
+    for seed in range(5):
+        rng = np.random.default_rng(700 + seed)
+        cv = rng.normal(size=(R, 8))
+        cv[:, 7] = np.round(rng.uniform(0, 4, R), 2)      # many exact ties
+        succ = None if seed == 0 else (rng.uniform(size=R) < [0.5, 0.05, 0.9, 0.002][seed - 1]).astype(np.uint8)
+        if succ is not None and not succ.any():
+            succ[rng.integers(R)] = 1
+        want = O.least_biased(cv, succ)
+        got, t = ctx.least_biased_path(dev(cv, "f64"), succ)
+        print(f"  seed {seed}: candidates {R if succ is None else int(succ.sum())}, index {got}", flush=True)
+        assert got == want and t == cv[want, 7]
+    # every value equal: the lowest candidate id
+    cv = np.zeros((R, 8)); cv[:, 7] = 1.25
+    succ = np.zeros(R, dtype=np.uint8); succ[[17, 400, 999]] = 1
+    assert ctx.least_biased_path(dev(cv, "f64"), succ) == (17, 1.25)
+    # errors: no candidate; a candidate with a non-finite T (a non-candidate's is ignored)
+    with pytest.raises(S.ScpsError) as e:
+        ctx.least_biased_path(dev(cv, "f64"), np.zeros(R, dtype=np.uint8))
+    assert e.value.status == -7
+    cv[5, 7] = np.nan
+    with pytest.raises(S.ScpsError) as e:
+        ctx.least_biased_path(dev(cv, "f64"))
+    assert e.value.status == -1
+    succ = np.ones(R, dtype=np.uint8); succ[5] = 0
+    assert ctx.least_biased_path(dev(cv, "f64"), succ) == (0, 1.25)
+    ctx.close()
+
+
+def test_least_biased_after_stepping_matches_oracle(S):
+    w = I.config1(n_replicas=16, n_steps=20)
+    p = dict(w.params)
+    ctx = context(S, w)
+    x = dev(w.initial_x())
+    cv = dev(w.initial_cvstate(), "f64")
+    ctx.step_replicas(x, None, cv, 20)
+    ctx.sync()
+    osys = O.System.from_inputs(w.systems[0], p)
+    X0 = w.initial_x().reshape(16, 3, 20).astype(np.float64)
+    cvo = np.stack([O.steps(p, osys, r, X0[r], None, w.initial_cvstate()[r], 20)[2] for r in range(16)])
+    CVg = host(cv)
+    succ = np.array([r % 4 != 1 for r in range(16)], dtype=np.uint8)
+    got, t = ctx.least_biased_path(cv, succ)
+    want = O.least_biased(cvo, succ)
+    assert t == CVg[got, 7] and succ[got]
+    T = np.where(succ > 0, cvo[:, 7], np.inf)
+    order = np.argsort(T)
+    print(f"  T oracle {T[order[:3]]}, GPU pick {got} (T {t:.6e}), oracle pick {want}", flush=True)
+    if T[order[1]] - T[order[0]] > 1e-3 * T[order[0]]:   # a clear winner: both sides pick it
+        assert got == want
+    else:                                                # near tie: the pick is one of the tied paths
+        assert T[got] <= T[order[0]] * (1 + 1e-3)
+    ctx.close()

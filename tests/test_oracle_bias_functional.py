@@ -89,3 +89,48 @@ def test_additive_over_split_calls_and_ranks_paths():
     q = dict(p, k_R=0.0)
     _, _, cvd1, _ = O.steps(q, s, 3, x, None, cv, 120)
     assert cvd1[7] == 0.0 < cva[7]
+
+
+# ---------------------------------------------------------------------------
+# least-biased path selection: smallest T among the successful paths
+# ---------------------------------------------------------------------------
+def _cv_with_T(T):
+    cv = np.zeros((len(T), 8))
+    cv[:, 7] = T
+    return cv
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_least_biased_equals_brute_force(seed):
+    rng = np.random.default_rng(seed)
+    R = int(rng.integers(1, 40))
+    T = np.round(rng.uniform(0, 3, R), 1)                  # coarse values: many ties
+    succ = (rng.uniform(size=R) < 0.6).astype(np.uint8)
+    succ[rng.integers(R)] = 1
+    # brute force: lexicographic minimum of (T, index) over the candidates
+    want = min((T[r], r) for r in range(R) if succ[r])[1]
+    assert O.least_biased(_cv_with_T(T), succ) == want
+    assert O.least_biased(_cv_with_T(T)) == min((T[r], r) for r in range(R))[1]
+
+
+def test_least_biased_special_cases():
+    T = np.array([2.0, 0.5, 0.5, 1.0])
+    assert O.least_biased(_cv_with_T(T)) == 1                       # tie -> lowest index
+    assert O.least_biased(_cv_with_T(T), [1, 0, 0, 1]) == 3         # the global minimum is masked out
+    assert O.least_biased(_cv_with_T(T), [0, 0, 0, 0]) == -1        # no candidate
+    assert O.least_biased(_cv_with_T([np.nan, 1.0]), [1, 1]) == -2  # a candidate with T = NaN
+    assert O.least_biased(_cv_with_T([np.nan, 1.0]), [0, 1]) == 1   # a non-candidate's NaN is ignored
+    assert O.least_biased(_cv_with_T([np.inf, 1.0])) == -2
+    assert O.least_biased(_cv_with_T([7.0])) == 0
+
+
+def test_least_biased_picks_the_path_the_bias_never_pushed():
+    p, s, native = _chain()
+    p.update(k_R=0.05)
+    x = I.straight_start(s.n, 7)
+    cv = np.zeros(8); cv[1] = np.inf
+    cvs = [O.steps(dict(p, k_R=k), s, r, x, None, cv, 80)[2] for r, k in enumerate([0.05, 0.0, 0.02])]
+    cvs = np.stack(cvs)
+    assert cvs[1, 7] == 0.0 and cvs[0, 7] > 0 and cvs[2, 7] > 0
+    assert O.least_biased(cvs) == 1
+    assert O.least_biased(cvs, [1, 0, 1]) == int(np.argmin(cvs[[0, 2], 7])) * 2
