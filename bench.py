@@ -12,6 +12,9 @@ Other workloads (--workload), each printed as its own JSON line:
   autograd3000  z and E_b forward + backward for 64 chains of 3000 particles
   scps6000      32 replicas of a 6000-particle chain: the ensemble mean of
                 51 recorded frames over 32 paths, then SCPS-biased stepping
+  cutoff6000    the same chain under rMD with contact and nonbonded cutoffs of
+                12 A from compact states: per-step tile culling against the
+                all-tiles path
 
 Printed: replica-steps/s (value), contact-pair evals/s, the plain
 one-replica-per-launch form (headline workload), the roofline of the timed
@@ -51,7 +54,7 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default="chain560",
-                    choices=["chain560", "uneven512", "autograd3000", "scps6000"])
+                    choices=["chain560", "uneven512", "autograd3000", "scps6000", "cutoff6000"])
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--block", type=int, default=100, help="Langevin steps per benchmark step")
@@ -207,7 +210,10 @@ def cpu_baseline_steps(w, n_steps, replicas=None, what=""):
     remap = {s: k for k, s in enumerate(used_sys)}
     systems = [O.System.from_inputs(w.systems[s], w.params) for s in used_sys]
     rs_local = np.array([remap[s] for s in rs.tolist()], dtype=np.int32)
-    x = np.concatenate([w.systems[s].start.ravel() for s in rs.tolist()])
+    ids = np.arange(w.n_replicas) if replicas is None else np.asarray(replicas)
+    own = w.notes.get("replica_starts")
+    x = np.concatenate([(own[r] if own is not None else w.systems[w.replica_system[r]].start).ravel()
+                        for r in ids.tolist()]).astype(np.float64)
     v = np.zeros_like(x) if w.params["integrator"] == 1 else None
     cv = np.zeros((len(rs), 8))
     cv[:, 1] = cv[:, 5] = cv[:, 6] = np.inf
@@ -445,6 +451,74 @@ def bench_scps6000(args, torch, I, scps):
     return out
 
 
+# ---------------------------------------------------------------------------
+# 32 x 6000 with 12 A cutoffs: the linear-scaling variant
+# ---------------------------------------------------------------------------
+def pairs_within(x, r_cut, nb_excl, min_sep):
+    """(contact, nonbonded, both) pairs of one all-contact chain closer than
+    r_cut, at coordinates x [3][n] (float64)."""
+    import numpy as np
+    from scipy.spatial import cKDTree
+    pr = cKDTree(np.ascontiguousarray(x.T)).query_pairs(r_cut, output_type="ndarray")
+    sep = np.abs(pr[:, 0] - pr[:, 1])
+    con = int(np.count_nonzero(sep > min_sep))
+    nb = int(np.count_nonzero(sep > nb_excl))
+    both = int(np.count_nonzero(sep > max(min_sep, nb_excl)))
+    return con, nb, both
+
+
+def bench_cutoff6000(args, torch, I, scps):
+    import numpy as np
+    R = args.replicas or 32
+    w = I.config6(n_replicas=R)
+    sy = w.systems[0]
+    p = w.params
+    X0 = w.initial_x().reshape(R, 3, sy.n).astype(np.float64)
+    within = [pairs_within(X0[r], p["r_cut_contact"], p["nb_excl"], p["min_seq_sep"]) for r in range(R)]
+    con = sum(c[0] for c in within) / R
+    flops = sum(step_flops(*c) for c in within)             # per batched step, pairs inside the cutoff
+    all_con, all_nb, all_both = pair_counts(sy, p)
+    rates = {}
+    for mode, label in ((1, "culled"), (2, "all_tiles")):
+        ctx = scps.Context.from_workload(w, exec_mode=mode)
+        ctx.set_reference_map(0, native_xyz=sy.native)
+        x = torch.as_tensor(w.initial_x(), device="cuda")
+        v = torch.as_tensor(w.initial_v(7), device="cuda")
+        cv = torch.as_tensor(w.initial_cvstate(), device="cuda")
+        step = [0]
+
+        def call(_):
+            ctx.step_replicas(x, v, cv, args.block, step0=step[0])
+            step[0] += args.block
+
+        for _ in range(args.warmup):
+            call(0)
+        ctx.sync()
+        n_calls = args.steps if mode == 1 else max(2, args.steps // 10)
+        wall, per_ms = timed_calls(torch, call, n_calls)
+        ctx.sync()
+        ctx.close()
+        rates[label] = (R * args.block * n_calls / wall, wall, n_calls, per_ms)
+    value, wall, n_calls, per_ms = rates["culled"]
+    out = base_line(args, value, "replica-steps/s", wall, n_calls, {
+        "workload": f"chain6000_cutoff: {R} replicas x {sy.n} particles, rMD, contact and LJ/Debye-Hueckel "
+                    f"cutoffs {p['r_cut_contact']:g} A, compact starts (native + 0.05 A jitter), "
+                    f"{con:.0f} contact pairs inside the cutoff per replica (of {all_con}), BAOAB dt=2 fs, "
+                    f"{args.block} Langevin steps per benchmark step",
+        "replicas": R, "particles": sy.n, "block": args.block, "launch": "per-step, tile culling"})
+    out["pairs_within_cutoff_per_s"] = value * con
+    out["roofline"] = roofline(args.block * flops, per_ms,
+                               "scps_step_replicas (culling + pair pass + update, pairs inside the cutoff)")
+    out["all_tiles"] = {"value": rates["all_tiles"][0], "unit": "replica-steps/s",
+                        "form": "the same library and state on the per-step path over every tile pair",
+                        "steps": rates["all_tiles"][2]}
+    out["speedup_vs_all_tiles"] = value / rates["all_tiles"][0]
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline_steps(w, max(1, args.cpu_steps // 100), replicas=np.arange(min(R, 16)),
+                                                 what=" of the same workload (all pairs, the plain loop)")
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -461,7 +535,7 @@ def main():
 
     torch.cuda.set_device(0)
     fn = {"chain560": bench_chain560, "uneven512": bench_uneven512, "autograd3000": bench_autograd3000,
-          "scps6000": bench_scps6000}[args.workload]
+          "scps6000": bench_scps6000, "cutoff6000": bench_cutoff6000}[args.workload]
     out = fn(args, torch, I, scps)
     print(json.dumps(out), flush=True)
 

@@ -84,7 +84,7 @@ enum {
 
 enum { SCPS_INTEGRATOR_OVERDAMPED = 0, SCPS_INTEGRATOR_BAOAB = 1 };
 enum { SCPS_BIAS_RMD = 0, SCPS_BIAS_SCPS = 1 };
-enum { SCPS_EXEC_AUTO = 0, SCPS_EXEC_PER_STEP = 1 };
+enum { SCPS_EXEC_AUTO = 0, SCPS_EXEC_PER_STEP = 1, SCPS_EXEC_PER_STEP_ALL_TILES = 2 };
 
 /* Physics and bias parameters (any consistent unit system; the protein-shaped
  * workloads use A, ps, kJ/mol, e and masses in kJ/mol ps^2/A^2). */
@@ -94,7 +94,12 @@ typedef struct {
                              v += dt F/m; x += dt/2 v; v = c1 v + sqrt((1-c1^2) kT/m) xi; x += dt/2 v, c1 = exp(-gamma dt) */
     int32_t bias_mode;    /* SCPS_BIAS_RMD: ratchet on z, eq (FrMD).  SCPS_BIAS_SCPS: ratchets on s, w, eqs (Fw),(Fs) */
     int32_t exec_mode;    /* SCPS_EXEC_AUTO: one persistent launch per call where a replica fits one workgroup;
-                             SCPS_EXEC_PER_STEP: a few kernel launches per step (always used for SCPS and large chains) */
+                             SCPS_EXEC_PER_STEP: a few kernel launches per step (always used for SCPS and large chains);
+                             with r_cut_contact and r_cut_nb both > 0 in rMD mode, this path skips every tile pair of
+                             64 x 64 particles whose blocks' bounding spheres are farther apart than the larger cutoff
+                             (re-tested each step; the skipped tiles hold no force and add their reference sum of
+                             R^2 to z);
+                             SCPS_EXEC_PER_STEP_ALL_TILES: the per-step path over every tile pair (no culling) */
     int32_t nb_excl;      /* nonbonded pairs need |i-j| > nb_excl (>= 1) */
     int32_t min_seq_sep;  /* contact pairs need |i-j| > min_seq_sep; the paper's all-atom value is 35 */
     int32_t replica_base; /* replica r uses replica_base + r as its noise counter word, so a context that
@@ -104,7 +109,11 @@ typedef struct {
     double lj_eps, lj_sigma;      /* Lennard-Jones 12-6; lj_eps = 0 disables */
     double dh_prefactor, dh_kappa;/* Debye-Hueckel k_e/eps_r * q_i q_j exp(-kappa r)/r; prefactor 0 disables */
     double r0_contact;            /* r0 of eq (Cij) */
-    double r_cut_contact;         /* <= 0: no cutoff; else C = 0 for r > r_cut */
+    double r_cut_contact;         /* <= 0: no cutoff; else C = 0 for r > r_cut (the linear-scaling remark after eq (Cij)) */
+    double r_cut_nb;              /* <= 0: no cutoff; else a Lennard-Jones / Debye-Hueckel pair with r > r_cut_nb
+                                     contributes nothing (plain truncation, like the contact cutoff).  With both
+                                     cutoffs set, the per-step rMD path skips the tile pairs whose blocks are
+                                     farther apart than the larger cutoff (see SCPS_EXEC_PER_STEP_ALL_TILES) */
     double k_R;                   /* rMD ratchet constant */
     double lambda, k_s, k_w;      /* SCPS tube variables and ratchet constants */
     uint64_t seed;                /* Philox4x32-10 key */

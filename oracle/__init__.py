@@ -39,7 +39,7 @@ class OrcParams(C.Structure):
         ("lj_eps", C.c_double), ("lj_sigma", C.c_double),
         ("dh_prefactor", C.c_double), ("dh_kappa", C.c_double),
         ("nb_excl", C.c_int32), ("min_seq_sep", C.c_int32),
-        ("r0", C.c_double), ("r_cut", C.c_double),
+        ("r0", C.c_double), ("r_cut", C.c_double), ("r_cut_nb", C.c_double),
         ("k_R", C.c_double),
         ("lam", C.c_double), ("k_s", C.c_double), ("k_w", C.c_double),
         ("seed", C.c_uint64),
@@ -109,7 +109,7 @@ def make_params(d: dict) -> OrcParams:
         dt=d["dt"], gamma=d["gamma"], kT=d["kT"], k_bond=d["k_bond"], r_bond=d["r_bond"],
         lj_eps=d["lj_eps"], lj_sigma=d["lj_sigma"], dh_prefactor=d["dh_prefactor"],
         dh_kappa=d["dh_kappa"], nb_excl=int(d["nb_excl"]), min_seq_sep=int(d["min_seq_sep"]),
-        r0=d["r0_contact"], r_cut=d["r_cut_contact"], k_R=d["k_R"], lam=d["lam"],
+        r0=d["r0_contact"], r_cut=d["r_cut_contact"], r_cut_nb=d.get("r_cut_nb", 0.0), k_R=d["k_R"], lam=d["lam"],
         k_s=d["k_s"], k_w=d["k_w"], seed=int(d["seed"]))
 
 

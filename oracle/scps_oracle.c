@@ -36,6 +36,11 @@
  *   - the SCPS ratchets use (s - s_m) and (w - w_m) as in eqs (Fw),(Fs);
  *   - BAOAB is used for the underdamped equation and its state velocity
  *     is the one right after the friction/noise substep;
+ *   - the cutoff the paper introduces for linear scaling (C = 0 beyond r_c,
+ *     remark after eq (Cij)) is offered for the synthetic nonbonded terms as
+ *     well: with r_cut_nb > 0 a Lennard-Jones / Debye-Hueckel pair farther
+ *     apart than r_cut_nb contributes no force and no energy (plain
+ *     truncation, like the contact cutoff);
  *   - T[X] takes the prefactor 1/(m_i gamma_i) of the rMD section and of the
  *     protocol (eq (T) writes Gamma_i = 1/(4 gamma_i m_i k_B T), which only
  *     rescales every path's T by the same constant), and the time integral
@@ -63,6 +68,7 @@ typedef struct {
     int32_t min_seq_sep;     /* contact pairs need |i-j| > min_seq_sep */
     double r0;               /* contact reference distance */
     double r_cut;            /* <= 0: no cutoff */
+    double r_cut_nb;         /* <= 0: no cutoff; else nonbonded pairs with r > r_cut_nb contribute nothing */
     double k_R;
     double lambda, k_s, k_w;
     uint64_t seed;
@@ -175,6 +181,7 @@ double orc_phys_forces(int n, const double *x, const float *charge,
             if (j - i <= p->nb_excl) continue;
             double d[3];
             double r2 = dist2(x, n, i, j, d);
+            if (p->r_cut_nb > 0.0 && r2 > p->r_cut_nb * p->r_cut_nb) continue;   /* truncated, as the contact cutoff */
             double r = sqrt(r2);
             double f_over_r = 0.0;          /* -dU/dr / r */
             if (p->lj_eps != 0.0) {

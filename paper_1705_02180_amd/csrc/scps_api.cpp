@@ -45,6 +45,8 @@ struct SysHost {
     float *d_stack_pm = nullptr;   // [ntile_c][4096][stack_pm_width(K)]
     double *d_R2 = nullptr;        // [K]
     int K = 0;
+    double *d_R2tile = nullptr;    // [ntile_c] native map: sum of R^2 over each tile's counted pairs
+    double R2total = 0.0;          // their sum (added to z for the tiles the culled path skips)
 };
 
 }  // namespace
@@ -83,6 +85,16 @@ struct scps_ctx {
     int wg = 64;     // persistent workgroup size
     int tuned = -1;  // -1 untuned; else 0 persistent (with wg) or 1 per-step, from scps_autotune
     int nbk = 0;     // nonbonded terms: bit 0 LJ, bit 1 Debye-Hueckel
+    // cutoff variant: per-step tile culling (rMD with both cutoffs set)
+    bool cull = false;
+    float r_keep = 0.f;
+    int nb_max = 0;
+    float4 *d_bounds = nullptr;      // [R][nb_max] block bounding spheres
+    int *d_cull_local = nullptr;     // [n_items_all]
+    int *d_cull_boff = nullptr;      // [ceil(n_items_all / 256) + 1]
+    TileItem *d_items_dyn = nullptr; // [n_items_all] kept items of the current step
+    int *d_first_dyn = nullptr;      // [R + 1]
+    double *d_zbase = nullptr;       // [R] R2total of each replica's system
     std::vector<void *> owned;
 };
 
@@ -123,6 +135,8 @@ KParams make_kparams(const scps_params &p) {
     k.cp[3] = (float)(-3.0 * 4.0 / (p.r0_contact * p.r0_contact));
     k.has_cut = p.r_cut_contact > 0.0;
     k.r_cut2 = (float)(p.r_cut_contact * p.r_cut_contact);
+    k.has_cut_nb = p.r_cut_nb > 0.0;
+    k.r_cut_nb2 = (float)(p.r_cut_nb * p.r_cut_nb);
     k.lj_A = (float)(48.0 * p.lj_eps * pow(p.lj_sigma, 12));
     k.lj_B = (float)(24.0 * p.lj_eps * pow(p.lj_sigma, 6));
     k.has_lj = p.lj_eps != 0.0;
@@ -170,6 +184,7 @@ scps_status upload_sysdesc(scps_ctx *c) {
         o.stack = h.d_stack;
         o.stack_pm = h.d_stack_pm;
         o.R2 = h.d_R2;
+        o.R2tile = h.d_R2tile;
         o.tiles = h.d_sched;
         o.tmask = h.d_sched_mask;
         o.ntile = (int)h.sched.size();
@@ -230,6 +245,7 @@ void compute_tile_flags(SysHost &h, const scps_params &p) {
                 f |= TILE_CONTACT;
                 if ((J + 1) * TILE > h.nc || p.r_cut_contact > 0.0) m = ~0ull;
             }
+            if (p.r_cut_nb > 0.0) m = ~0ull;   // every pair tests the nonbonded cutoff
             if (m) f |= TILE_MASK;
             h.tile_flags[(size_t)I * nb + J] = f;
         }
@@ -328,8 +344,9 @@ scps_status init_impl(const scps_params *params, const scps_topology *topo, int3
         return fail(SCPS_ERR_INVALID_ARG, "integrator must be 0 (overdamped) or 1 (BAOAB)");
     if (p.bias_mode != SCPS_BIAS_RMD && p.bias_mode != SCPS_BIAS_SCPS)
         return fail(SCPS_ERR_INVALID_ARG, "bias_mode must be 0 (rMD) or 1 (SCPS)");
-    if (p.exec_mode != SCPS_EXEC_AUTO && p.exec_mode != SCPS_EXEC_PER_STEP)
-        return fail(SCPS_ERR_INVALID_ARG, "exec_mode must be 0 or 1");
+    if (p.exec_mode != SCPS_EXEC_AUTO && p.exec_mode != SCPS_EXEC_PER_STEP &&
+        p.exec_mode != SCPS_EXEC_PER_STEP_ALL_TILES)
+        return fail(SCPS_ERR_INVALID_ARG, "exec_mode must be 0, 1 or 2");
     if (!(p.dt > 0) || !(p.gamma > 0) || !(p.kT >= 0) || !(p.r0_contact > 0))
         return fail(SCPS_ERR_INVALID_ARG, "dt, gamma, r0_contact must be > 0 and kT >= 0");
     if (p.nb_excl < 1 || p.min_seq_sep < 0 || p.replica_base < 0)
@@ -484,6 +501,19 @@ scps_status init_impl(const scps_params *params, const scps_topology *topo, int3
         HIP_TRY(c, hipMemcpy(c->d_items_contact, con.data(), con.size() * sizeof(TileItem),
                              hipMemcpyHostToDevice));
 
+    c->cull = p.bias_mode == SCPS_BIAS_RMD && p.r_cut_contact > 0.0 && p.r_cut_nb > 0.0 &&
+              p.exec_mode != SCPS_EXEC_PER_STEP_ALL_TILES && !all.empty();
+    if (c->cull) {
+        c->r_keep = (float)std::max(p.r_cut_contact, p.r_cut_nb);
+        for (const SysHost &h : c->sys) c->nb_max = std::max(c->nb_max, h.nb);
+        HIP_TRY(c, dalloc(c, &c->d_bounds, (size_t)R * c->nb_max));
+        HIP_TRY(c, dalloc(c, &c->d_cull_local, all.size()));
+        HIP_TRY(c, dalloc(c, &c->d_cull_boff, (all.size() + 255) / 256 + 1));
+        HIP_TRY(c, dalloc(c, &c->d_items_dyn, all.size()));
+        HIP_TRY(c, dalloc(c, &c->d_first_dyn, R + 1));
+        HIP_TRY(c, dalloc(c, &c->d_zbase, R));
+        HIP_TRY(c, hipMemset(c->d_zbase, 0, R * sizeof(double)));
+    }
     HIP_TRY(c, dalloc(c, &c->d_flags, R));
     HIP_TRY(c, hipMemset(c->d_flags, 0, R * sizeof(int)));
     HIP_TRY(c, dalloc(c, &c->d_xs, 2 * c->sumNpad));
@@ -586,6 +616,24 @@ scps_status set_ref_impl(scps_ctx *c, int32_t s, int32_t n_maps, const double *m
         dfree(c, d_sum);
         h.Z0 = zz;
         h.has_native = true;
+        // per-tile sums of R^2 (the culled path's z offset)
+        if (h.ntile_c > 0) {
+            if (!h.d_R2tile) HIP_TRY(c, dalloc(c, &h.d_R2tile, h.ntile_c));
+            HIP_TRY(c, launch_tile_sumsq(h.nc, h.ncb, c->prm.min_seq_sep, h.d_perm, h.d_ref, h.d_R2tile, c->stream));
+            std::vector<double> r2(h.ntile_c);
+            HIP_TRY(c, hipMemcpyAsync(r2.data(), h.d_R2tile, h.ntile_c * sizeof(double), hipMemcpyDeviceToHost,
+                                      c->stream));
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            h.R2total = 0.0;
+            for (double v : r2) h.R2total += v;
+        }
+        if (c->cull) {
+            std::vector<double> zb(c->R);
+            for (int r = 0; r < c->R; ++r) zb[r] = c->sys[c->rep_sys[r]].R2total;
+            HIP_TRY(c, hipMemcpyAsync(c->d_zbase, zb.data(), c->R * sizeof(double), hipMemcpyHostToDevice,
+                                      c->stream));
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+        }
     } else {
         if (!maps || xyz) return fail(SCPS_ERR_INVALID_ARG, "a frame stack needs maps and no native_xyz");
         if (n_maps > KMAX) return fail(SCPS_ERR_SHAPE, "at most 64 frames in an SCPS stack");
@@ -638,10 +686,23 @@ scps_status step_impl(scps_ctx *c, float *x, float *v, double *cv, int64_t n_ste
             HIP_TRY(c, launch_scatter(c->d_sysd, c->d_reps, c->R, c->n_pad_max, c->d_xs, nullptr, nullptr, nullptr,
                                       frames + (m / record_every) * frame_stride, c->stream));
         if (m == n_steps) break;
-        if (!scps) {
-            HIP_TRY(c, launch_pairs(0, c->nbk, c->kp, c->d_sysd, c->d_reps, c->d_items_all, c->n_items_all, c->d_xs,
-                                    c->d_acc, c->d_zpart, nullptr, nullptr, c->stream));
-            HIP_TRY(c, launch_finalize_rmd(c->kp, c->R, c->d_first_all, c->d_zpart, cv, c->d_scale, c->stream));
+        if (!scps && c->cull) {
+            // cutoff variant: only the tile pairs whose blocks can hold a pair within the cutoffs
+            HIP_TRY(c, launch_cull_tiles(c->d_sysd, c->d_reps, c->R, c->nb_max, c->d_xs, c->d_bounds, c->d_items_all,
+                                         c->n_items_all, c->d_first_all, c->r_keep, c->d_cull_local,
+                                         c->d_cull_boff, c->d_items_dyn, c->d_first_dyn, c->stream));
+            HIP_TRY(c, launch_pairs(0, c->nbk, c->kp, c->d_sysd, c->d_reps, c->d_items_dyn, c->n_items_all,
+                                    c->d_first_dyn + c->R, 1, c->d_xs, c->d_acc, c->d_zpart, nullptr, nullptr,
+                                    c->stream));
+            HIP_TRY(c, launch_finalize_rmd(c->kp, c->R, c->d_first_dyn, c->d_zpart, c->d_zbase, cv, c->d_scale,
+                                           c->stream));
+            HIP_TRY(c, launch_integrate(c->kp, c->d_sysd, c->d_reps, c->R, c->n_pad_max, c->d_xs, c->d_vs, c->d_acc,
+                                        c->d_scale, cv, step0 + (uint64_t)m, c->d_flags, c->stream));
+        } else if (!scps) {
+            HIP_TRY(c, launch_pairs(0, c->nbk, c->kp, c->d_sysd, c->d_reps, c->d_items_all, c->n_items_all, nullptr,
+                                    0, c->d_xs, c->d_acc, c->d_zpart, nullptr, nullptr, c->stream));
+            HIP_TRY(c, launch_finalize_rmd(c->kp, c->R, c->d_first_all, c->d_zpart, nullptr, cv, c->d_scale,
+                                           c->stream));
             HIP_TRY(c, launch_integrate(c->kp, c->d_sysd, c->d_reps, c->R, c->n_pad_max, c->d_xs, c->d_vs, c->d_acc,
                                         c->d_scale, cv, step0 + (uint64_t)m, c->d_flags, c->stream));
         } else {
@@ -653,8 +714,8 @@ scps_status step_impl(scps_ctx *c, float *x, float *v, double *cv, int64_t n_ste
                                             c->d_coef, c->d_csum, c->stream));
             HIP_TRY(c, launch_scps_eff(c->d_sysd, c->d_reps, c->d_groups, c->d_sitems, c->n_sitems, c->d_coef,
                                        c->kmax, c->d_E, c->stream));
-            HIP_TRY(c, launch_pairs(3, c->nbk, c->kp, c->d_sysd, c->d_reps, c->d_items_all, c->n_items_all, c->d_xs,
-                                    c->d_acc, c->d_zpart, c->d_E, c->d_csum, c->stream));
+            HIP_TRY(c, launch_pairs(3, c->nbk, c->kp, c->d_sysd, c->d_reps, c->d_items_all, c->n_items_all, nullptr,
+                                    0, c->d_xs, c->d_acc, c->d_zpart, c->d_E, c->d_csum, c->stream));
             HIP_TRY(c, launch_integrate(c->kp, c->d_sysd, c->d_reps, c->R, c->n_pad_max, c->d_xs, c->d_vs, c->d_acc,
                                         c->d_negone, cv, step0 + (uint64_t)m, c->d_flags, c->stream));
         }
@@ -671,7 +732,7 @@ scps_status eval_impl(scps_ctx *c, const float *x, double *z, float *grad, const
             return fail(SCPS_ERR_STATE, "a system has no native map (scps_set_reference_map)");
     HIP_TRY(c, launch_gather(c->d_sysd, c->d_reps, c->R, c->n_pad_max, x, nullptr, c->d_xs, nullptr, c->stream));
     HIP_TRY(c, launch_pairs(grad ? 2 : 1, c->nbk, c->kp, c->d_sysd, c->d_reps, c->d_items_contact, c->n_items_contact,
-                            c->d_xs, c->d_acc, c->d_zpart, nullptr, nullptr, c->stream));
+                            nullptr, 0, c->d_xs, c->d_acc, c->d_zpart, nullptr, nullptr, c->stream));
     HIP_TRY(c, launch_eval_out(c->d_sysd, c->d_reps, c->R, c->n_pad_max, c->d_acc, c->d_first_con, c->d_zpart, z,
                                grad, coef,
                                c->stream));

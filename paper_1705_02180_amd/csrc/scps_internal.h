@@ -17,13 +17,14 @@ struct KParams {
     float g_scale;       // 4/r0^2: dz/dx_i = sum_j g_scale (C - R) C'(q) (x_i - x_j)
     float cp[4];         // -g_scale * {2, 4, 6, 3}: coefficients of -g_scale (3 + 6q + 4q^2 + 2q^3)
     float r_cut2;        // contact cutoff squared (used when has_cut)
+    float r_cut_nb2;     // nonbonded cutoff squared (used when has_cut_nb)
     float lj_A;          // 48 epsilon sigma^12
     float lj_B;          // 24 epsilon sigma^6
     float dh_pref;       // k_e/eps_r
     float dh_kappa;
     float dh_kl2;        // -kappa * log2(e)
     int nb_excl, min_sep;
-    int has_lj, has_dh, has_cut, has_bond;
+    int has_lj, has_dh, has_cut, has_cut_nb, has_bond;
     int integrator;
     double dt, kT, gamma, c1;
     double k_bond, r_bond;
@@ -48,6 +49,7 @@ struct SysDesc {
     const float *stack;      // SCPS frames [ntile_c][K][64*64]
     const float *stack_pm;   // the same frames pair-major: [ntile_c][64*64][stack_pm_width(K)]
     const double *R2;        // [K] sum over the counted contact pairs of R_k^2
+    const double *R2tile;    // [ntile_c] per native-map tile: sum over its counted contact pairs of R^2
     const int2 *tiles;       // persistent work list, costliest first (see build_schedule)
     const uint64_t *tmask;   // per work-list item: sub-steps that need the per-pair predicates
     int ntile;
@@ -140,9 +142,13 @@ hipError_t launch_scatter(const SysDesc *sysd, const RepDesc *reps, int R, int n
 // mode: 0 rMD forces (contact z + grad, nonbonded, bonds); 1 z only; 2 z and grad;
 //       3 SCPS bias against the effective references eff (+ nonbonded + bonds)
 // nbk: nonbonded terms, bit 0 Lennard-Jones, bit 1 Debye-Hueckel
+// n_live: NULL, or a device count of the items to run (the first *n_live of
+// the list; the grid covers n_items).  zsub: store each contact item's z
+// partial minus its tile's sum of R^2 (the culled path, which adds the
+// system's total back per replica).
 hipError_t launch_pairs(int mode, int nbk, const KParams &P, const SysDesc *sysd, const RepDesc *reps,
-                        const TileItem *items, int n_items, const float4 *xs, double *acc,
-                        double *zpart, const float *eff, const double *csum, hipStream_t st);
+                        const TileItem *items, int n_items, const int *n_live, int zsub, const float4 *xs,
+                        double *acc, double *zpart, const float *eff, const double *csum, hipStream_t st);
 hipError_t launch_scps_dist(const KParams &P, const SysDesc *sysd, const RepDesc *reps, const ScpsGroup *groups,
                             const ScpsItem *items, int n_items, const float4 *xs, double *X, double *Q, int kmax,
                             hipStream_t st);
@@ -152,8 +158,22 @@ hipError_t launch_stack_pairmajor(int nc, int ncb, int K, int min_sep, const int
                                   float *stack_pm, double *R2, hipStream_t st);
 
 // first[r] .. first[r+1]: replica r's items in the list whose z partials are in zpart
-hipError_t launch_finalize_rmd(const KParams &P, int R, const int *first, const double *zpart, double *cv,
-                               double *scale, hipStream_t st);
+// zbase: NULL, or a per-replica constant added to z (culled path).
+hipError_t launch_finalize_rmd(const KParams &P, int R, const int *first, const double *zpart,
+                               const double *zbase, double *cv, double *scale, hipStream_t st);
+// Tile culling for the cutoff variant: bounding spheres of every block, then
+// the items of items_all whose blocks can hold a pair within r_keep (all
+// diagonal items) copied in order to items_out; first_out[r] .. first_out[r+1]
+// are replica r's kept items and first_out[R] their number.  Scratch: local
+// [n_items], block_off [ceil(n_items / 256) + 1].
+hipError_t launch_cull_tiles(const SysDesc *sysd, const RepDesc *reps, int R, int nb_max, const float4 *xs,
+                             float4 *bounds, const TileItem *items_all, int n_items, const int *first_all,
+                             float r_keep, int *local, int *block_off, TileItem *items_out, int *first_out,
+                             hipStream_t st);
+// Per contact tile of a map: sum over its counted pairs of the squared
+// (float32) entries, in float64.
+hipError_t launch_tile_sumsq(int nc, int ncb, int min_sep, const int *perm, const float *tiles, double *out,
+                             hipStream_t st);
 hipError_t launch_finalize_scps(const KParams &P, const SysDesc *sysd, const RepDesc *reps, int R,
                                 int kmax, double *X, double *Q, double *cv, float *coef, double *csum,
                                 hipStream_t st);

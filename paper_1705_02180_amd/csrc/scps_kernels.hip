@@ -174,7 +174,7 @@ __device__ __forceinline__ void pair_group(const KParams &P, const int lane, con
         if constexpr (MASK) {
             const int jl = (lane + k) & 63;
             const int sep = abs(A.o - orgj[jl]);
-            nbon[u] = act0 & (sep > P.nb_excl);
+            nbon[u] = act0 & (sep > P.nb_excl) & (!P.has_cut_nb | (r2[u] <= P.r_cut_nb2));
             con[u] = act0 & A.contact & (jl < ncj) & (sep > P.min_sep);
             inside[u] = !P.has_cut | (r2[u] <= P.r_cut2);   // beyond a cutoff C_ij = 0 (R_ij still counts)
         }
@@ -258,8 +258,8 @@ __device__ __forceinline__ void pair_group2(const KParams &P, const int lane, co
             const int jl = (lane + k) & 63;
             const int oj = orgj[jl];
             const int sa = abs(A.o - oj), sb = abs(B.o - oj);
-            nba[u] = sa > P.nb_excl;
-            nbb[u] = sb > P.nb_excl;
+            nba[u] = (sa > P.nb_excl) & (!P.has_cut_nb | (r2a[u] <= P.r_cut_nb2));
+            nbb[u] = (sb > P.nb_excl) & (!P.has_cut_nb | (r2b[u] <= P.r_cut_nb2));
             ca[u] = A.contact & (jl < ncj) & (sa > P.min_sep);
             cb[u] = B.contact & (jl < ncj) & (sb > P.min_sep);
             ina[u] = !P.has_cut | (r2a[u] <= P.r_cut2);
@@ -857,6 +857,7 @@ template <int MODE, int NBK>
 __global__ __launch_bounds__(256) void k_pairs(const KParams P, const SysDesc *__restrict__ sysd,
                                                const RepDesc *__restrict__ reps,
                                                const TileItem *__restrict__ items, const int n_items,
+                                               const int *__restrict__ n_live, const int zsub,
                                                const float4 *__restrict__ xs, double *__restrict__ acc,
                                                double *__restrict__ zpart, const float *__restrict__ eff,
                                                const double *__restrict__ csum) {
@@ -864,7 +865,9 @@ __global__ __launch_bounds__(256) void k_pairs(const KParams P, const SysDesc *_
     __shared__ float4 shpos[4][128];   // block J of each wavefront's item, stored twice
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int item = blockIdx.x * 4 + wave;
-    const bool live = item < n_items;
+    const int count = n_live ? *n_live : n_items;
+    if (blockIdx.x * 4 >= count) return;   // whole workgroup past the live items
+    const bool live = item < count;
     const TileItem it = items[live ? item : 0];
     const RepDesc rd = reps[it.rep];
     const SysDesc S = sysd[rd.sys];
@@ -938,17 +941,18 @@ __global__ __launch_bounds__(256) void k_pairs(const KParams P, const SysDesc *_
     }
     if constexpr (T::z) {
         const double zw = wave_sum((double)zt);
-        if (lane == 0) zpart[item] = contact_tile ? zw : 0.0;
+        if (lane == 0) zpart[item] = contact_tile ? zw - (zsub ? S.R2tile[tile_index(I, J, S.ncb)] : 0.0) : 0.0;
     }
 }
 
 template <int MODE>
 static void launch_pairs_mode(int nbk, dim3 grid, dim3 block, hipStream_t st, const KParams &P,
                               const SysDesc *sysd, const RepDesc *reps, const TileItem *items, int n_items,
-                              const float4 *xs, double *acc, double *zpart, const float *eff, const double *csum) {
+                              const int *n_live, int zsub, const float4 *xs, double *acc, double *zpart,
+                              const float *eff, const double *csum) {
 #define SCPS_LAUNCH(K)                                                                                   \
-    hipLaunchKernelGGL((k_pairs<MODE, K>), grid, block, 0, st, P, sysd, reps, items, n_items, xs, acc, zpart, \
-                       eff, csum)
+    hipLaunchKernelGGL((k_pairs<MODE, K>), grid, block, 0, st, P, sysd, reps, items, n_items, n_live, zsub, xs, \
+                       acc, zpart, eff, csum)
     if constexpr (!ModeTraits<MODE>::nb) {
         SCPS_LAUNCH(0);
     } else {
@@ -963,24 +967,20 @@ static void launch_pairs_mode(int nbk, dim3 grid, dim3 block, hipStream_t st, co
 }
 
 hipError_t launch_pairs(int mode, int nbk, const KParams &P, const SysDesc *sysd, const RepDesc *reps,
-                        const TileItem *items, int n_items, const float4 *xs, double *acc, double *zpart,
-                        const float *eff, const double *csum, hipStream_t st) {
+                        const TileItem *items, int n_items, const int *n_live, int zsub, const float4 *xs,
+                        double *acc, double *zpart, const float *eff, const double *csum, hipStream_t st) {
     if (n_items == 0) return hipSuccess;
     const dim3 grid((n_items + 3) / 4), block(256);
+#define SCPS_MODE(M)                                                                                       \
+    launch_pairs_mode<M>(nbk, grid, block, st, P, sysd, reps, items, n_items, n_live, zsub, xs, acc, zpart, eff, \
+                         csum)
     switch (mode) {
-    case PM_RMD:
-        launch_pairs_mode<PM_RMD>(nbk, grid, block, st, P, sysd, reps, items, n_items, xs, acc, zpart, eff, csum);
-        break;
-    case PM_Z:
-        launch_pairs_mode<PM_Z>(nbk, grid, block, st, P, sysd, reps, items, n_items, xs, acc, zpart, eff, csum);
-        break;
-    case PM_ZG:
-        launch_pairs_mode<PM_ZG>(nbk, grid, block, st, P, sysd, reps, items, n_items, xs, acc, zpart, eff, csum);
-        break;
-    default:
-        launch_pairs_mode<PM_SCPS>(nbk, grid, block, st, P, sysd, reps, items, n_items, xs, acc, zpart, eff, csum);
-        break;
+    case PM_RMD: SCPS_MODE(PM_RMD); break;
+    case PM_Z: SCPS_MODE(PM_Z); break;
+    case PM_ZG: SCPS_MODE(PM_ZG); break;
+    default: SCPS_MODE(PM_SCPS); break;
     }
+#undef SCPS_MODE
     return hipGetLastError();
 }
 
@@ -996,9 +996,9 @@ __device__ __forceinline__ double replica_z(const int *__restrict__ first, const
 
 // rMD ratchet per replica, eq (FrMD), from the replica's z.
 __global__ void k_finalize_rmd(const KParams P, const int *__restrict__ first, const double *__restrict__ zpart,
-                               double *__restrict__ cv, double *__restrict__ scale) {
+                               const double *__restrict__ zbase, double *__restrict__ cv, double *__restrict__ scale) {
     const int r = blockIdx.x;
-    const double z = replica_z(first, zpart, r, threadIdx.x);
+    const double z = (zbase ? zbase[r] : 0.0) + replica_z(first, zpart, r, threadIdx.x);
     if (threadIdx.x != 0) return;
     double *c = cv + (int64_t)r * CV_STRIDE;
     const double zm = fmin(c[CV_ZM], z);
@@ -1009,9 +1009,133 @@ __global__ void k_finalize_rmd(const KParams P, const int *__restrict__ first, c
     scale[r] = -P.k_R * dz;
 }
 
-hipError_t launch_finalize_rmd(const KParams &P, int R, const int *first, const double *zpart, double *cv,
-                               double *scale, hipStream_t st) {
-    hipLaunchKernelGGL(k_finalize_rmd, dim3(R), dim3(64), 0, st, P, first, zpart, cv, scale);
+hipError_t launch_finalize_rmd(const KParams &P, int R, const int *first, const double *zpart,
+                               const double *zbase, double *cv, double *scale, hipStream_t st) {
+    hipLaunchKernelGGL(k_finalize_rmd, dim3(R), dim3(64), 0, st, P, first, zpart, zbase, cv, scale);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// tile culling for the cutoff variant (per-step rMD path)
+// ---------------------------------------------------------------------------
+// With both cutoffs set, a tile pair whose blocks' bounding spheres are more
+// than the larger cutoff apart holds no pair with a force or a nonzero C, and
+// it adds its native-map sum of R^2 to z (C = 0 there, R still counts).
+// Every step: bounding spheres, then an order-preserving compaction of the
+// kept items (replica by replica, so the z partials still sum in a fixed
+// order).
+
+// Bounding sphere of block b of replica r (one wavefront): centroid of its
+// real particles and the largest distance from it.
+__global__ __launch_bounds__(64) void k_block_bounds(const SysDesc *__restrict__ sysd,
+                                                     const RepDesc *__restrict__ reps, int nb_max,
+                                                     const float4 *__restrict__ xs, float4 *__restrict__ bounds) {
+    const int b = blockIdx.x, r = blockIdx.y, lane = threadIdx.x;
+    const RepDesc rd = reps[r];
+    const int n = sysd[rd.sys].n, nb = sysd[rd.sys].nb;
+    if (b >= nb) return;
+    const int i = b * 64 + lane;
+    const bool valid = i < n;
+    const float4 p = xs[2 * rd.poff + b * 128 + lane];
+    const double cnt = wave_sum(valid ? 1.0 : 0.0);
+    const double cx = wave_sum(valid ? (double)p.x : 0.0) / cnt;
+    const double cy = wave_sum(valid ? (double)p.y : 0.0) / cnt;
+    const double cz = wave_sum(valid ? (double)p.z : 0.0) / cnt;
+    const double dx = (double)p.x - cx, dy = (double)p.y - cy, dz = (double)p.z - cz;
+    double d2 = valid ? dx * dx + dy * dy + dz * dz : 0.0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) d2 = fmax(d2, __shfl_xor(d2, o, 64));
+    if (lane == 0) bounds[(int64_t)r * nb_max + b] = make_float4((float)cx, (float)cy, (float)cz, (float)sqrt(d2));
+}
+
+// Keep flags and their exclusive prefix within each workgroup of 256 items:
+// local[s] = (prefix << 1) | keep; block_off[w] = the workgroup's count.
+// The sphere test is done in float64 with a 0.01 A margin, so a dropped item
+// has every pair farther apart than r_keep by more than float32 rounding.
+__global__ __launch_bounds__(256) void k_cull_flags(const TileItem *__restrict__ items, int n_items,
+                                                    const float4 *__restrict__ bounds, int nb_max, float r_keep,
+                                                    int *__restrict__ local, int *__restrict__ block_off) {
+    __shared__ int wcount[4];
+    const int s = blockIdx.x * 256 + threadIdx.x, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int keep = 0;
+    if (s < n_items) {
+        const TileItem it = items[s];
+        if (it.I == it.J) {
+            keep = 1;   // diagonal tiles also carry the bonds
+        } else {
+            const float4 a = bounds[(int64_t)it.rep * nb_max + it.I], b = bounds[(int64_t)it.rep * nb_max + it.J];
+            const double dx = (double)a.x - b.x, dy = (double)a.y - b.y, dz = (double)a.z - b.z;
+            const double gap = sqrt(dx * dx + dy * dy + dz * dz) - (double)a.w - (double)b.w;
+            keep = gap <= (double)r_keep + 0.01;
+        }
+    }
+    const uint64_t bal = __ballot(keep);
+    const int below = __popcll(lane ? (bal << (64 - lane)) : 0ull);
+    if (lane == 0) wcount[w] = __popcll(bal);
+    __syncthreads();
+    int off = 0;
+    for (int q = 0; q < w; ++q) off += wcount[q];
+    if (s < n_items) local[s] = ((off + below) << 1) | keep;
+    if (threadIdx.x == 0) block_off[blockIdx.x] = wcount[0] + wcount[1] + wcount[2] + wcount[3];
+}
+
+// Exclusive prefix sum of v[0 .. n) in place, total in v[n] (one workgroup).
+__global__ __launch_bounds__(1024) void k_scan_counts(int *__restrict__ v, int n) {
+    __shared__ int wsum[16];
+    __shared__ int carry;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    if (tid == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < n; base += 1024) {
+        const int i = base + tid;
+        const int x = i < n ? v[i] : 0;
+        int incl = x;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += y;
+        }
+        if (lane == 63) wsum[w] = incl;
+        __syncthreads();
+        int woff = 0;
+        for (int q = 0; q < w; ++q) woff += wsum[q];
+        const int c0 = carry;
+        if (i < n) v[i] = c0 + woff + incl - x;
+        __syncthreads();
+        if (tid == 1023) carry = c0 + woff + incl;
+        __syncthreads();
+    }
+    if (tid == 0) v[n] = carry;
+}
+
+// Copy the kept items to their places and record where each replica starts.
+__global__ __launch_bounds__(256) void k_cull_compact(const TileItem *__restrict__ items, int n_items,
+                                                      const int *__restrict__ local,
+                                                      const int *__restrict__ block_off,
+                                                      const int *__restrict__ first_all, int R,
+                                                      TileItem *__restrict__ out, int *__restrict__ first_out) {
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= n_items) return;
+    const int l = local[s];
+    const int pos = block_off[blockIdx.x] + (l >> 1);
+    const TileItem it = items[s];
+    if (l & 1) out[pos] = it;
+    if (first_all[it.rep] == s) first_out[it.rep] = pos;
+    if (s == n_items - 1) first_out[R] = pos + (l & 1);
+}
+
+hipError_t launch_cull_tiles(const SysDesc *sysd, const RepDesc *reps, int R, int nb_max, const float4 *xs,
+                             float4 *bounds, const TileItem *items_all, int n_items, const int *first_all,
+                             float r_keep, int *local, int *block_off, TileItem *items_out, int *first_out,
+                             hipStream_t st) {
+    if (n_items == 0) return hipSuccess;
+    const int nblk = (n_items + 255) / 256;
+    hipLaunchKernelGGL(k_block_bounds, dim3(nb_max, R), dim3(64), 0, st, sysd, reps, nb_max, xs, bounds);
+    hipLaunchKernelGGL(k_cull_flags, dim3(nblk), dim3(256), 0, st, items_all, n_items, bounds, nb_max, r_keep, local,
+                       block_off);
+    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, block_off, nblk);
+    hipLaunchKernelGGL(k_cull_compact, dim3(nblk), dim3(256), 0, st, items_all, n_items, local, block_off, first_all,
+                       R, items_out, first_out);
     return hipGetLastError();
 }
 

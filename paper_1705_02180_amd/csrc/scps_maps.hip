@@ -251,11 +251,47 @@ hipError_t launch_update_reference(int n, int n_pad, int nc, int ncb, const int 
 // ---------------------------------------------------------------------------
 typedef float fvec16 __attribute__((ext_vector_type(16)));
 
+
 // Unordered contact pair (64 I + l, 64 J + ((l + s) mod 64)) of a tile in the
 // diagonal-major layout: in a diagonal tile every pair appears twice; the
 // copy at sub-steps 1..31, or at 32 for l < 32, is the one that counts.
 __device__ __forceinline__ bool tile_pair_counts(bool diag, int s, int l) {
     return !diag || (s >= 1 && (s < 32 || (s == 32 && l < 32)));
+}
+
+// Per contact tile of a map [tile][4096]: the float64 sum of the squared
+// entries over the tile's counted pairs (both in the contact set, beyond
+// min_seq_sep, each unordered pair once).  One workgroup per tile; thread
+// (w, l) takes sub-steps s = w, w + 4, ... of column l.
+__global__ __launch_bounds__(256) void k_tile_sumsq(int nc, int ncb, int min_sep, const int *__restrict__ perm,
+                                                    const float *__restrict__ tiles, double *__restrict__ out) {
+    __shared__ double ws[4];
+    const int tile = blockIdx.x;
+    int I, J;
+    tile_decode(tile, ncb, I, J);
+    const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
+    const int a = I * 64 + l;
+    const float *t = tiles + (int64_t)tile * 4096;
+    double sum = 0.0;
+    for (int s = w; s < 64; s += 4) {
+        const int b = J * 64 + ((l + s) & 63);
+        if (a < nc && b < nc && tile_pair_counts(I == J, s, l) && abs(perm[a] - perm[b]) > min_sep) {
+            const double v = t[s * 64 + l];
+            sum = fma(v, v, sum);
+        }
+    }
+    sum = wave_sum(sum);
+    if (l == 0) ws[w] = sum;
+    __syncthreads();
+    if (tid == 0) out[tile] = (ws[0] + ws[1]) + (ws[2] + ws[3]);
+}
+
+hipError_t launch_tile_sumsq(int nc, int ncb, int min_sep, const int *perm, const float *tiles, double *out,
+                             hipStream_t st) {
+    const int nt = ncb * (ncb + 1) / 2;
+    if (nt == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tile_sumsq, dim3(nt), dim3(256), 0, st, nc, ncb, min_sep, perm, tiles, out);
+    return hipGetLastError();
 }
 
 // Pair-major copy of a frame stack: stack_pm[tile][p][k] = stack[tile][k][p]

@@ -204,8 +204,13 @@ class Workload:
         return off
 
     def initial_x(self) -> np.ndarray:
-        """float32 flat buffer: replica r occupies [3*off_r, 3*off_{r+1}) as [3][N_r]."""
-        blocks = [self.systems[s].start.astype(np.float32).ravel() for s in self.replica_system]
+        """float32 flat buffer: replica r occupies [3*off_r, 3*off_{r+1}) as [3][N_r].  Every replica
+        starts from its system's start state unless notes["replica_starts"] gives one per replica."""
+        own = self.notes.get("replica_starts")
+        if own is not None:
+            blocks = [np.asarray(own[r], dtype=np.float32).ravel() for r in range(self.n_replicas)]
+        else:
+            blocks = [self.systems[s].start.astype(np.float32).ravel() for s in self.replica_system]
         return np.ascontiguousarray(np.concatenate(blocks))
 
     def initial_v(self, seed: int) -> np.ndarray:
@@ -231,7 +236,7 @@ def _base_params(**kw) -> Dict[str, float]:
     p = dict(integrator=1, bias_mode=0, dt=0.002, gamma=1.0, kT=KB_KJ * 300.0,
              k_bond=100.0, r_bond=LATTICE, lj_eps=1.0, lj_sigma=4.0,
              dh_prefactor=KE_KJ / 80.0, dh_kappa=0.1, nb_excl=2, min_seq_sep=0,
-             r0_contact=7.5, r_cut_contact=0.0, k_R=1e-4, lam=13.5, k_s=2.5,
+             r0_contact=7.5, r_cut_contact=0.0, r_cut_nb=0.0, k_R=1e-4, lam=13.5, k_s=2.5,
              k_w=2.5e-4, seed=SEED0)
     p.update(kw)
     return p
@@ -335,6 +340,23 @@ def config5(n_replicas: int = 32, n: int = 6000, n_steps: int = 10000,
     return Workload("chain6000_serpin_shaped", params, [sys0],
                     np.zeros(n_replicas, dtype=np.int32), n_steps,
                     record_every=record_every, iterations=iterations)
+
+
+def config6(n_replicas: int = 32, n: int = 6000, r_cut: float = 12.0) -> Workload:
+    """Cutoff variant: config 5's chain under rMD with the contact and the
+    nonbonded terms cut at r_cut (the paper's 1.2 nm), started from compact
+    states (the native fold with 0.05 A of seeded jitter per coordinate, one
+    draw per replica), where a cutoff removes the fewest pairs."""
+    cfg = 6
+    base = config5(n_replicas=1, n=n)
+    sy = base.systems[0]
+    rng = np.random.default_rng(SEED0 + 3000 * cfg)
+    starts = [sy.native + rng.normal(0.0, 0.05, size=sy.native.shape) for _ in range(n_replicas)]
+    sys0 = System(n=n, contact_idx=sy.contact_idx, mass=sy.mass, charge=sy.charge, native=sy.native,
+                  start=starts[0])
+    params = _base_params(seed=SEED0 + cfg, r_cut_contact=r_cut, r_cut_nb=r_cut)
+    return Workload("chain6000_cutoff", params, [sys0], np.zeros(n_replicas, dtype=np.int32), 1000,
+                    notes={"replica_starts": np.stack(starts)})
 
 
 def random_coil(n: int, seed: int) -> np.ndarray:

@@ -41,7 +41,7 @@ class Params(C.Structure):
         ("k_bond", C.c_double), ("r_bond", C.c_double),
         ("lj_eps", C.c_double), ("lj_sigma", C.c_double),
         ("dh_prefactor", C.c_double), ("dh_kappa", C.c_double),
-        ("r0_contact", C.c_double), ("r_cut_contact", C.c_double),
+        ("r0_contact", C.c_double), ("r_cut_contact", C.c_double), ("r_cut_nb", C.c_double),
         ("k_R", C.c_double), ("lam", C.c_double), ("k_s", C.c_double), ("k_w", C.c_double),
         ("seed", C.c_uint64),
     ]
@@ -120,7 +120,7 @@ def make_params(d: dict, exec_mode: int = 0, replica_base: int = 0) -> Params:
         dt=d["dt"], gamma=d["gamma"], kT=d["kT"], k_bond=d["k_bond"], r_bond=d["r_bond"],
         lj_eps=d["lj_eps"], lj_sigma=d["lj_sigma"], dh_prefactor=d["dh_prefactor"],
         dh_kappa=d["dh_kappa"], r0_contact=d["r0_contact"], r_cut_contact=d["r_cut_contact"],
-        k_R=d["k_R"], lam=d["lam"], k_s=d["k_s"], k_w=d["k_w"], seed=int(d["seed"]))
+        r_cut_nb=d.get("r_cut_nb", 0.0), k_R=d["k_R"], lam=d["lam"], k_s=d["k_s"], k_w=d["k_w"], seed=int(d["seed"]))
 
 
 class Context:

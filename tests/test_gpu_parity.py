@@ -699,3 +699,71 @@ def test_least_biased_after_stepping_matches_oracle(S):
     else:                                                # near tie: the pick is one of the tied paths
         assert T[got] <= T[order[0]] * (1 + 1e-3)
     ctx.close()
+
+
+# ---------------------------------------------------------------------------
+# cutoff variant: contact and nonbonded cutoffs, per-step tile culling
+# ---------------------------------------------------------------------------
+CUT_CASES = [
+    # name, n, exec_mode, r_cut_contact, r_cut_nb
+    ("both12_persistent", 333, 0, 12.0, 12.0),
+    ("both12_culled", 333, 1, 12.0, 12.0),
+    ("both12_all_tiles", 333, 2, 12.0, 12.0),
+    ("nb_only10_per_step", 257, 1, 0.0, 10.0),
+    ("nb_only10_persistent", 257, 0, 0.0, 10.0),
+    ("cut9_nb10_culled_1500", 1500, 1, 9.0, 10.0),
+]
+
+
+@pytest.mark.parametrize("name,n,exec_mode,rc,rnb", CUT_CASES, ids=[c[0] for c in CUT_CASES])
+def test_cutoff_forces_match_oracle(S, name, n, exec_mode, rc, rnb):
+    base = dict(I._base_params(), r_cut_contact=rc, r_cut_nb=rnb)
+    R = 5
+    w = single_system_workload(n, np.arange(n), base, R)
+    p = _force_readback_params(base, k_R=1e-2)
+    sy = w.systems[0]
+    X = states(sy, R, 41)
+    osys = O.System.from_inputs(sy, p)
+    cv0 = np.zeros((R, 8))
+    cv0[:, 1] = np.inf
+    for r in range(1, R):
+        cv0[r, 1] = 0.8 * O.z_grad(X[r].astype(np.float64), osys.cidx, osys.native, r_cut=rc, grad=False)
+    Fg, cvg = _gpu_forces_one_step(S, w, p, X, cv0, exec_mode)
+    for r in range(R):
+        F, Fb, cvr = O.total_force(p, osys, X[r].astype(np.float64), cv0[r])
+        err = normwise(Fg[r], F)
+        print(f"  {name} replica {r}: force err {err:.2e}, z {cvg[r, 0]:.6f} (oracle {cvr[0]:.6f})", flush=True)
+        assert err <= TOL, (r, err)
+        assert abs(cvg[r, 0] - cvr[0]) <= TOL * max(cvr[0], 1e-3 * osys.Z0)
+        assert abs(cvg[r, 1] - cvr[1]) <= TOL * max(cvr[1], 1e-3 * osys.Z0)
+
+
+def test_culled_steps_equal_all_tile_steps(S):
+    """Culling drops only tiles with no pair inside the cutoffs, so a noisy
+    trajectory agrees with the all-tiles path up to the order of float64 sums."""
+    import torch
+    n, R = 1400, 4
+    base = dict(I._base_params(), r_cut_contact=10.0, r_cut_nb=10.0, k_R=5e-3)
+    w = single_system_workload(n, np.arange(n), base, R)
+    sy = w.systems[0]
+    rng = np.random.default_rng(7)
+    # random coils and the jittered extended start: no overlapping beads, so
+    # the 30 steps stay finite (a perturbed native can put two beads 1.7 A apart)
+    X0 = np.stack([I.random_coil(n, 300 + r) if r % 2 == 0 else sy.start + rng.normal(0, 0.05, sy.start.shape)
+                   for r in range(R)]).astype(np.float32)
+    res = []
+    for mode in (1, 2):
+        ctx = context(S, w, params=base, exec_mode=mode)
+        x = dev(X0.ravel())
+        v = torch.zeros_like(x)
+        cv = dev(w.initial_cvstate(), "f64")
+        ctx.step_replicas(x, v, cv, 30, step0=5)
+        ctx.sync()
+        res.append((host(x).reshape(R, 3, n), host(cv)))
+        ctx.close()
+    disp = np.abs(res[1][0] - X0).max()
+    d = np.abs(res[0][0] - res[1][0]).max()
+    print(f"  culled vs all tiles after 30 steps: max |dx| {d:.2e} (displacement {disp:.2e})", flush=True)
+    assert d <= 1e-5 * disp
+    np.testing.assert_allclose(res[0][1][:, :3], res[1][1][:, :3], rtol=1e-7)
+    np.testing.assert_allclose(res[0][1][:, 7], res[1][1][:, 7], rtol=1e-5)

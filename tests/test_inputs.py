@@ -42,3 +42,15 @@ def test_generated_inputs_are_unchanged():
     assert [digest(w.systems[0].native), digest(w.systems[0].start)] == ["8ebbb67bbf080f07", "7b8d1240829e17c3"]
     assert digest(I.compact_native(1601, 7)) == "656b99f75a60e9ad"
     assert digest(I.persistent_start(3000, 8)) == "9d63c207b17f021f"
+
+
+def test_cutoff_workload_starts_compact_without_overlaps():
+    w = I.config6(n_replicas=3, n=600)
+    assert w.params["r_cut_contact"] == 12.0 and w.params["r_cut_nb"] == 12.0 and w.params["bias_mode"] == 0
+    X = w.initial_x().reshape(3, 3, 600)
+    nat = w.systems[0].native
+    assert np.abs(X - nat[None]).max() < 0.5                     # jittered native
+    assert not np.array_equal(X[0], X[1])                        # one draw per replica
+    d = np.sqrt(((X[1][:, :, None] - X[1][:, None, :]) ** 2).sum(0).astype(np.float64))
+    np.fill_diagonal(d, np.inf)
+    assert d.min() > 3.0                                         # lattice spacing 3.8 A minus the jitter

@@ -146,3 +146,73 @@ def test_running_minimum_is_nonincreasing_along_a_path():
         assert cv[1] <= cv[0]
     assert all(b <= a for a, b in zip(zms, zms[1:]))
     assert zms[-1] < zms[0]
+
+
+# ---------------------------------------------------------------------------
+# nonbonded cutoff (plain truncation, like the contact cutoff after eq (Cij))
+# ---------------------------------------------------------------------------
+def test_nonbonded_cutoff_two_particles():
+    p = params(k_bond=0.0, nb_excl=0, dh_prefactor=17.0, dh_kappa=0.1, r_cut_nb=12.0)
+    q = np.array([0.5, -0.25], dtype=np.float32)
+    for r, inside in ((11.999, True), (12.001, False), (30.0, False), (5.0, True)):
+        x = np.array([[0.0, 0.0], [0.0, r], [0.0, 0.0]])
+        F, U = O.phys_forces(x, q, p)
+        F0, U0 = O.phys_forces(x, q, dict(p, r_cut_nb=0.0))
+        if inside:
+            np.testing.assert_array_equal(F, F0)
+            assert U == U0 and U != 0.0
+        else:
+            assert U == 0.0 and np.abs(F).max() == 0.0
+
+
+def test_nonbonded_cutoff_is_the_sum_of_pairs_inside():
+    """Forces of a chain with a cutoff, rebuilt pair by pair from two-particle
+    evaluations (the closed forms pinned above) over the pairs with r <= r_c."""
+    w = I.config2(n_replicas=1)
+    s = w.systems[0]
+    p = dict(w.params, r_cut_nb=9.0)
+    n = 60
+    x = I.compact_native(n, 8) + np.random.default_rng(2).normal(0, 0.3, (3, n))
+    q = s.charge[:n]
+    F, U = O.phys_forces(x, q, p)
+    Fb, Ub = O.phys_forces(x, q, dict(p, lj_eps=0.0, dh_prefactor=0.0))        # bonds alone
+    pp = dict(p, k_bond=0.0, nb_excl=0, r_cut_nb=0.0)
+    Fs, Us, n_in = Fb.copy(), Ub, 0
+    for i in range(n):
+        for j in range(i + p["nb_excl"] + 1, n):
+            if np.sum((x[:, i] - x[:, j]) ** 2) > 81.0:
+                continue
+            n_in += 1
+            f2, u2 = O.phys_forces(x[:, [i, j]], q[[i, j]], pp)
+            Fs[:, i] += f2[:, 0]
+            Fs[:, j] += f2[:, 1]
+            Us += u2
+    assert 0 < n_in < n * (n - 1) // 2 - 2 * n       # the cutoff removes pairs, and keeps some
+    np.testing.assert_allclose(F, Fs, rtol=0, atol=1e-12 * np.abs(F).max())
+    assert U == pytest.approx(Us, rel=1e-12)
+
+
+def test_nonbonded_cutoff_newton_and_energy_gradient():
+    w = I.config2(n_replicas=1)
+    s = w.systems[0]
+    p = dict(w.params, r_cut_nb=10.0)
+    n = 70
+    x = I.compact_native(n, 3) + np.random.default_rng(5).normal(0, 0.4, (3, n))
+    q = s.charge[:n]
+    d = np.sqrt(((x[:, :, None] - x[:, None, :]) ** 2).sum(axis=0))
+    assert np.abs(d - 10.0).min() > 1e-3                  # no pair within the FD step of the cutoff
+    F, U = O.phys_forces(x, q, p)
+    scale = np.abs(F).max()
+    assert np.abs(F.sum(axis=1)).max() < 1e-11 * scale * n
+    h = 1e-6
+    for i in (0, 21, 69):
+        for c in range(3):
+            xp = x.copy(); xp[c, i] += h
+            xm = x.copy(); xm[c, i] -= h
+            fd = -(O.phys_forces(xp, q, p)[1] - O.phys_forces(xm, q, p)[1]) / (2 * h)
+            assert abs(fd - F[c, i]) < 1e-5 * max(1.0, scale)
+    # a cutoff beyond every distance changes nothing
+    F2, U2 = O.phys_forces(x, q, dict(p, r_cut_nb=1e6))
+    F3, U3 = O.phys_forces(x, q, dict(p, r_cut_nb=0.0))
+    np.testing.assert_array_equal(F2, F3)
+    assert U2 == U3
