@@ -13,7 +13,7 @@ Other workloads (--workload), each printed as its own JSON line:
   scps6000      32 replicas of a 6000-particle chain: the ensemble mean of
                 51 recorded frames over 32 paths, then SCPS-biased stepping
   cutoff6000    the same chain under rMD with contact and nonbonded cutoffs of
-                12 A from compact states: per-step tile culling against the
+                12 A from compact states: neighbour lists against the
                 all-tiles path
 
 Printed: replica-steps/s (value), contact-pair evals/s, the plain
@@ -479,7 +479,7 @@ def bench_cutoff6000(args, torch, I, scps):
     flops = sum(step_flops(*c) for c in within)             # per batched step, pairs inside the cutoff
     all_con, all_nb, all_both = pair_counts(sy, p)
     rates = {}
-    for mode, label in ((1, "culled"), (2, "all_tiles")):
+    for mode, label in ((1, "lists"), (2, "all_tiles")):
         ctx = scps.Context.from_workload(w, exec_mode=mode)
         ctx.set_reference_map(0, native_xyz=sy.native)
         x = torch.as_tensor(w.initial_x(), device="cuda")
@@ -499,16 +499,16 @@ def bench_cutoff6000(args, torch, I, scps):
         ctx.sync()
         ctx.close()
         rates[label] = (R * args.block * n_calls / wall, wall, n_calls, per_ms)
-    value, wall, n_calls, per_ms = rates["culled"]
+    value, wall, n_calls, per_ms = rates["lists"]
     out = base_line(args, value, "replica-steps/s", wall, n_calls, {
         "workload": f"chain6000_cutoff: {R} replicas x {sy.n} particles, rMD, contact and LJ/Debye-Hueckel "
                     f"cutoffs {p['r_cut_contact']:g} A, compact starts (native + 0.05 A jitter), "
                     f"{con:.0f} contact pairs inside the cutoff per replica (of {all_con}), BAOAB dt=2 fs, "
                     f"{args.block} Langevin steps per benchmark step",
-        "replicas": R, "particles": sy.n, "block": args.block, "launch": "per-step, tile culling"})
+        "replicas": R, "particles": sy.n, "block": args.block, "launch": "per-step, neighbour lists"})
     out["pairs_within_cutoff_per_s"] = value * con
     out["roofline"] = roofline(args.block * flops, per_ms,
-                               "scps_step_replicas (culling + pair pass + update, pairs inside the cutoff)")
+                               "scps_step_replicas (list upkeep + list pass + update, pairs inside the cutoff)")
     out["all_tiles"] = {"value": rates["all_tiles"][0], "unit": "replica-steps/s",
                         "form": "the same library and state on the per-step path over every tile pair",
                         "steps": rates["all_tiles"][2]}

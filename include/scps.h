@@ -59,7 +59,7 @@ typedef enum {
     SCPS_ERR_OOM = -3,         /* device or host allocation failed */
     SCPS_ERR_HIP = -4,         /* a HIP runtime call failed (context poisoned) */
     SCPS_ERR_STATE = -5,       /* call not valid in the current state */
-    SCPS_ERR_NONFINITE = -6,   /* a replica produced a non-finite coordinate */
+    SCPS_ERR_NONFINITE = -6,   /* a replica produced a non-finite coordinate (or overflowed its neighbour list) */
     SCPS_ERR_NO_SUCCESS = -7   /* update_reference_from_paths: no successful path */
 } scps_status;
 
@@ -95,11 +95,13 @@ typedef struct {
     int32_t bias_mode;    /* SCPS_BIAS_RMD: ratchet on z, eq (FrMD).  SCPS_BIAS_SCPS: ratchets on s, w, eqs (Fw),(Fs) */
     int32_t exec_mode;    /* SCPS_EXEC_AUTO: one persistent launch per call where a replica fits one workgroup;
                              SCPS_EXEC_PER_STEP: a few kernel launches per step (always used for SCPS and large chains);
-                             with r_cut_contact and r_cut_nb both > 0 in rMD mode, this path skips every tile pair of
-                             64 x 64 particles whose blocks' bounding spheres are farther apart than the larger cutoff
-                             (re-tested each step; the skipped tiles hold no force and add their reference sum of
-                             R^2 to z);
-                             SCPS_EXEC_PER_STEP_ALL_TILES: the per-step path over every tile pair (no culling) */
+                             with r_cut_contact and r_cut_nb both > 0 in rMD mode, this path evaluates the pairs of
+                             per-particle neighbour lists instead of every pair: radius (larger cutoff) + 1.5 A,
+                             rebuilt for a replica when one of its particles has moved more than 0.75 A since the
+                             last build (also by the caller between calls) or the reference map changed, at most
+                             512 entries per particle
+                             (scps_sync reports NONFINITE for a replica that would need more);
+                             SCPS_EXEC_PER_STEP_ALL_TILES: the per-step path over every tile pair (no lists) */
     int32_t nb_excl;      /* nonbonded pairs need |i-j| > nb_excl (>= 1) */
     int32_t min_seq_sep;  /* contact pairs need |i-j| > min_seq_sep; the paper's all-atom value is 35 */
     int32_t replica_base; /* replica r uses replica_base + r as its noise counter word, so a context that
@@ -112,8 +114,7 @@ typedef struct {
     double r_cut_contact;         /* <= 0: no cutoff; else C = 0 for r > r_cut (the linear-scaling remark after eq (Cij)) */
     double r_cut_nb;              /* <= 0: no cutoff; else a Lennard-Jones / Debye-Hueckel pair with r > r_cut_nb
                                      contributes nothing (plain truncation, like the contact cutoff).  With both
-                                     cutoffs set, the per-step rMD path skips the tile pairs whose blocks are
-                                     farther apart than the larger cutoff (see SCPS_EXEC_PER_STEP_ALL_TILES) */
+                                     cutoffs set, the per-step rMD path runs on neighbour lists (see exec_mode) */
     double k_R;                   /* rMD ratchet constant */
     double lambda, k_s, k_w;      /* SCPS tube variables and ratchet constants */
     uint64_t seed;                /* Philox4x32-10 key */

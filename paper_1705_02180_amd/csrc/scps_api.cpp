@@ -85,15 +85,20 @@ struct scps_ctx {
     int wg = 64;     // persistent workgroup size
     int tuned = -1;  // -1 untuned; else 0 persistent (with wg) or 1 per-step, from scps_autotune
     int nbk = 0;     // nonbonded terms: bit 0 LJ, bit 1 Debye-Hueckel
-    // cutoff variant: per-step tile culling (rMD with both cutoffs set)
-    bool cull = false;
-    float r_keep = 0.f;
+    // cutoff variant: neighbour lists on the per-step path (rMD with both cutoffs set)
+    bool nl = false;
+    bool nl_stale = true;            // lists unbuilt, or built on a reference map since replaced
+    float r_list = 0.f;
     int nb_max = 0;
     float4 *d_bounds = nullptr;      // [R][nb_max] block bounding spheres
-    int *d_cull_local = nullptr;     // [n_items_all]
-    int *d_cull_boff = nullptr;      // [ceil(n_items_all / 256) + 1]
-    TileItem *d_items_dyn = nullptr; // [n_items_all] kept items of the current step
-    int *d_first_dyn = nullptr;      // [R + 1]
+    float4 *d_xref = nullptr;        // [sumNpad] positions at the last build
+    float *d_bmax = nullptr;         // [sum nb] largest squared displacement per block since then
+    int *d_rebuild = nullptr;        // [R]
+    int *d_nl_cnt = nullptr;         // [sumNpad]
+    int2 *d_nl = nullptr;            // [sumNpad][NL_CAP]
+    int *d_first_blk = nullptr;      // [R + 1] blocks of 64 particles before each replica
+    int *d_first_chunk = nullptr;    // [R + 1] chunks of the list force kernel before each replica
+    double *d_zpart_nl = nullptr;    // [chunks] z partials of the list force kernel
     double *d_zbase = nullptr;       // [R] R2total of each replica's system
     std::vector<void *> owned;
 };
@@ -501,16 +506,28 @@ scps_status init_impl(const scps_params *params, const scps_topology *topo, int3
         HIP_TRY(c, hipMemcpy(c->d_items_contact, con.data(), con.size() * sizeof(TileItem),
                              hipMemcpyHostToDevice));
 
-    c->cull = p.bias_mode == SCPS_BIAS_RMD && p.r_cut_contact > 0.0 && p.r_cut_nb > 0.0 &&
-              p.exec_mode != SCPS_EXEC_PER_STEP_ALL_TILES && !all.empty();
-    if (c->cull) {
-        c->r_keep = (float)std::max(p.r_cut_contact, p.r_cut_nb);
-        for (const SysHost &h : c->sys) c->nb_max = std::max(c->nb_max, h.nb);
+    c->nl = p.bias_mode == SCPS_BIAS_RMD && p.r_cut_contact > 0.0 && p.r_cut_nb > 0.0 &&
+            p.exec_mode != SCPS_EXEC_PER_STEP_ALL_TILES && !all.empty();
+    if (c->nl) {
+        c->r_list = (float)std::max(p.r_cut_contact, p.r_cut_nb) + NL_SKIN;
+        std::vector<int> fb(R + 1, 0), fc(R + 1, 0);
+        for (int r = 0; r < R; ++r) {
+            const SysHost &h = c->sys[rsys[r]];
+            c->nb_max = std::max(c->nb_max, h.nb);
+            fb[r + 1] = fb[r] + h.nb;
+            fc[r + 1] = fc[r] + nl_chunks(h.n_pad);
+        }
         HIP_TRY(c, dalloc(c, &c->d_bounds, (size_t)R * c->nb_max));
-        HIP_TRY(c, dalloc(c, &c->d_cull_local, all.size()));
-        HIP_TRY(c, dalloc(c, &c->d_cull_boff, (all.size() + 255) / 256 + 1));
-        HIP_TRY(c, dalloc(c, &c->d_items_dyn, all.size()));
-        HIP_TRY(c, dalloc(c, &c->d_first_dyn, R + 1));
+        HIP_TRY(c, dalloc(c, &c->d_xref, c->sumNpad));
+        HIP_TRY(c, dalloc(c, &c->d_bmax, fb[R]));
+        HIP_TRY(c, dalloc(c, &c->d_rebuild, R));
+        HIP_TRY(c, dalloc(c, &c->d_nl_cnt, c->sumNpad));
+        HIP_TRY(c, dalloc(c, &c->d_nl, (size_t)c->sumNpad * NL_CAP));
+        HIP_TRY(c, dalloc(c, &c->d_first_blk, R + 1));
+        HIP_TRY(c, hipMemcpy(c->d_first_blk, fb.data(), (R + 1) * sizeof(int), hipMemcpyHostToDevice));
+        HIP_TRY(c, dalloc(c, &c->d_first_chunk, R + 1));
+        HIP_TRY(c, hipMemcpy(c->d_first_chunk, fc.data(), (R + 1) * sizeof(int), hipMemcpyHostToDevice));
+        HIP_TRY(c, dalloc(c, &c->d_zpart_nl, fc[R]));
         HIP_TRY(c, dalloc(c, &c->d_zbase, R));
         HIP_TRY(c, hipMemset(c->d_zbase, 0, R * sizeof(double)));
     }
@@ -627,7 +644,8 @@ scps_status set_ref_impl(scps_ctx *c, int32_t s, int32_t n_maps, const double *m
             h.R2total = 0.0;
             for (double v : r2) h.R2total += v;
         }
-        if (c->cull) {
+        c->nl_stale = true;
+        if (c->nl) {
             std::vector<double> zb(c->R);
             for (int r = 0; r < c->R; ++r) zb[r] = c->sys[c->rep_sys[r]].R2total;
             HIP_TRY(c, hipMemcpyAsync(c->d_zbase, zb.data(), c->R * sizeof(double), hipMemcpyHostToDevice,
@@ -686,21 +704,21 @@ scps_status step_impl(scps_ctx *c, float *x, float *v, double *cv, int64_t n_ste
             HIP_TRY(c, launch_scatter(c->d_sysd, c->d_reps, c->R, c->n_pad_max, c->d_xs, nullptr, nullptr, nullptr,
                                       frames + (m / record_every) * frame_stride, c->stream));
         if (m == n_steps) break;
-        if (!scps && c->cull) {
-            // cutoff variant: only the tile pairs whose blocks can hold a pair within the cutoffs
-            HIP_TRY(c, launch_cull_tiles(c->d_sysd, c->d_reps, c->R, c->nb_max, c->d_xs, c->d_bounds, c->d_items_all,
-                                         c->n_items_all, c->d_first_all, c->r_keep, c->d_cull_local,
-                                         c->d_cull_boff, c->d_items_dyn, c->d_first_dyn, c->stream));
-            HIP_TRY(c, launch_pairs(0, c->nbk, c->kp, c->d_sysd, c->d_reps, c->d_items_dyn, c->n_items_all,
-                                    c->d_first_dyn + c->R, 1, c->d_xs, c->d_acc, c->d_zpart, nullptr, nullptr,
-                                    c->stream));
-            HIP_TRY(c, launch_finalize_rmd(c->kp, c->R, c->d_first_dyn, c->d_zpart, c->d_zbase, cv, c->d_scale,
+        if (!scps && c->nl) {
+            // cutoff variant: neighbour lists, rebuilt where a particle moved more than half the skin
+            HIP_TRY(c, launch_nl_update(c->kp, c->d_sysd, c->d_reps, c->R, c->nb_max, c->d_first_blk, c->d_xs,
+                                        c->d_bounds, c->d_xref, c->d_bmax, c->d_rebuild, c->nl_stale, c->d_items_all,
+                                        c->d_first_all, c->r_list, c->d_nl_cnt, c->d_nl, c->d_flags, c->stream));
+            c->nl_stale = false;
+            HIP_TRY(c, launch_nl_force(c->nbk, c->kp, c->d_sysd, c->d_reps, c->R, c->n_pad_max, c->d_first_chunk,
+                                       c->d_xs, c->d_nl_cnt, c->d_nl, c->d_acc, c->d_zpart_nl, c->stream));
+            HIP_TRY(c, launch_finalize_rmd(c->kp, c->R, c->d_first_chunk, c->d_zpart_nl, c->d_zbase, cv, c->d_scale,
                                            c->stream));
             HIP_TRY(c, launch_integrate(c->kp, c->d_sysd, c->d_reps, c->R, c->n_pad_max, c->d_xs, c->d_vs, c->d_acc,
                                         c->d_scale, cv, step0 + (uint64_t)m, c->d_flags, c->stream));
         } else if (!scps) {
-            HIP_TRY(c, launch_pairs(0, c->nbk, c->kp, c->d_sysd, c->d_reps, c->d_items_all, c->n_items_all, nullptr,
-                                    0, c->d_xs, c->d_acc, c->d_zpart, nullptr, nullptr, c->stream));
+            HIP_TRY(c, launch_pairs(0, c->nbk, c->kp, c->d_sysd, c->d_reps, c->d_items_all, c->n_items_all, c->d_xs,
+                                    c->d_acc, c->d_zpart, nullptr, nullptr, c->stream));
             HIP_TRY(c, launch_finalize_rmd(c->kp, c->R, c->d_first_all, c->d_zpart, nullptr, cv, c->d_scale,
                                            c->stream));
             HIP_TRY(c, launch_integrate(c->kp, c->d_sysd, c->d_reps, c->R, c->n_pad_max, c->d_xs, c->d_vs, c->d_acc,
@@ -714,8 +732,8 @@ scps_status step_impl(scps_ctx *c, float *x, float *v, double *cv, int64_t n_ste
                                             c->d_coef, c->d_csum, c->stream));
             HIP_TRY(c, launch_scps_eff(c->d_sysd, c->d_reps, c->d_groups, c->d_sitems, c->n_sitems, c->d_coef,
                                        c->kmax, c->d_E, c->stream));
-            HIP_TRY(c, launch_pairs(3, c->nbk, c->kp, c->d_sysd, c->d_reps, c->d_items_all, c->n_items_all, nullptr,
-                                    0, c->d_xs, c->d_acc, c->d_zpart, c->d_E, c->d_csum, c->stream));
+            HIP_TRY(c, launch_pairs(3, c->nbk, c->kp, c->d_sysd, c->d_reps, c->d_items_all, c->n_items_all, c->d_xs,
+                                    c->d_acc, c->d_zpart, c->d_E, c->d_csum, c->stream));
             HIP_TRY(c, launch_integrate(c->kp, c->d_sysd, c->d_reps, c->R, c->n_pad_max, c->d_xs, c->d_vs, c->d_acc,
                                         c->d_negone, cv, step0 + (uint64_t)m, c->d_flags, c->stream));
         }
@@ -732,7 +750,7 @@ scps_status eval_impl(scps_ctx *c, const float *x, double *z, float *grad, const
             return fail(SCPS_ERR_STATE, "a system has no native map (scps_set_reference_map)");
     HIP_TRY(c, launch_gather(c->d_sysd, c->d_reps, c->R, c->n_pad_max, x, nullptr, c->d_xs, nullptr, c->stream));
     HIP_TRY(c, launch_pairs(grad ? 2 : 1, c->nbk, c->kp, c->d_sysd, c->d_reps, c->d_items_contact, c->n_items_contact,
-                            nullptr, 0, c->d_xs, c->d_acc, c->d_zpart, nullptr, nullptr, c->stream));
+                            c->d_xs, c->d_acc, c->d_zpart, nullptr, nullptr, c->stream));
     HIP_TRY(c, launch_eval_out(c->d_sysd, c->d_reps, c->R, c->n_pad_max, c->d_acc, c->d_first_con, c->d_zpart, z,
                                grad, coef,
                                c->stream));
@@ -980,15 +998,19 @@ scps_status scps_sync(scps_ctx *ctx, int32_t *bad_replicas, int32_t *n_bad) {
         ctx->poisoned = true;
         return fail(SCPS_ERR_HIP, std::string("hipMemcpy: ") + hipGetErrorString(e));
     }
-    int nb = 0;
+    int nb = 0, full = 0;
     for (int r = 0; r < ctx->R; ++r)
         if (flags[r]) {
             if (bad_replicas) bad_replicas[nb] = r;
             ++nb;
+            full += flags[r] == 2;
         }
     if (n_bad) *n_bad = nb;
     if (nb) {
         ctx->poisoned = true;
+        if (full)
+            return fail(SCPS_ERR_NONFINITE, std::to_string(full) + " replica(s) had a particle with more than " +
+                                                std::to_string(NL_CAP) + " neighbours within the list radius");
         return fail(SCPS_ERR_NONFINITE, std::to_string(nb) + " replica(s) produced non-finite coordinates");
     }
     return SCPS_OK;

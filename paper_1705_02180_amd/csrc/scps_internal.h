@@ -142,13 +142,9 @@ hipError_t launch_scatter(const SysDesc *sysd, const RepDesc *reps, int R, int n
 // mode: 0 rMD forces (contact z + grad, nonbonded, bonds); 1 z only; 2 z and grad;
 //       3 SCPS bias against the effective references eff (+ nonbonded + bonds)
 // nbk: nonbonded terms, bit 0 Lennard-Jones, bit 1 Debye-Hueckel
-// n_live: NULL, or a device count of the items to run (the first *n_live of
-// the list; the grid covers n_items).  zsub: store each contact item's z
-// partial minus its tile's sum of R^2 (the culled path, which adds the
-// system's total back per replica).
 hipError_t launch_pairs(int mode, int nbk, const KParams &P, const SysDesc *sysd, const RepDesc *reps,
-                        const TileItem *items, int n_items, const int *n_live, int zsub, const float4 *xs,
-                        double *acc, double *zpart, const float *eff, const double *csum, hipStream_t st);
+                        const TileItem *items, int n_items, const float4 *xs, double *acc, double *zpart,
+                        const float *eff, const double *csum, hipStream_t st);
 hipError_t launch_scps_dist(const KParams &P, const SysDesc *sysd, const RepDesc *reps, const ScpsGroup *groups,
                             const ScpsItem *items, int n_items, const float4 *xs, double *X, double *Q, int kmax,
                             hipStream_t st);
@@ -158,18 +154,27 @@ hipError_t launch_stack_pairmajor(int nc, int ncb, int K, int min_sep, const int
                                   float *stack_pm, double *R2, hipStream_t st);
 
 // first[r] .. first[r+1]: replica r's items in the list whose z partials are in zpart
-// zbase: NULL, or a per-replica constant added to z (culled path).
+// zbase: NULL, or a per-replica constant added to z (neighbour-list path).
 hipError_t launch_finalize_rmd(const KParams &P, int R, const int *first, const double *zpart,
                                const double *zbase, double *cv, double *scale, hipStream_t st);
-// Tile culling for the cutoff variant: bounding spheres of every block, then
-// the items of items_all whose blocks can hold a pair within r_keep (all
-// diagonal items) copied in order to items_out; first_out[r] .. first_out[r+1]
-// are replica r's kept items and first_out[R] their number.  Scratch: local
-// [n_items], block_off [ceil(n_items / 256) + 1].
-hipError_t launch_cull_tiles(const SysDesc *sysd, const RepDesc *reps, int R, int nb_max, const float4 *xs,
-                             float4 *bounds, const TileItem *items_all, int n_items, const int *first_all,
-                             float r_keep, int *local, int *block_off, TileItem *items_out, int *first_out,
-                             hipStream_t st);
+// Neighbour lists of the cutoff variant (rMD with both cutoffs): NL_CAP
+// entries per particle, radius (larger cutoff) + NL_SKIN.
+constexpr int NL_CAP = 512;
+constexpr float NL_SKIN = 1.5f;
+// Rebuild the lists of the replicas that need it (force: all of them).
+// first_blk [R+1]: blocks of 64 before each replica; bounds [R][nb_max],
+// xref [sum n_pad], bmax [sum nb], rebuild [R], cnt [sum n_pad],
+// nl [sum n_pad][NL_CAP]; flags[r] = 2 when a list of replica r overflowed.
+hipError_t launch_nl_update(const KParams &P, const SysDesc *sysd, const RepDesc *reps, int R, int nb_max,
+                            const int *first_blk, const float4 *xs, float4 *bounds, float4 *xref, float *bmax,
+                            int *rebuild, int force, const TileItem *items_all, const int *first_all, float r_list,
+                            int *cnt, int2 *nl, int *flags, hipStream_t st);
+// Particle chunks of the list force kernel for a system of n_pad particles.
+int nl_chunks(int n_pad);
+// Forces (added to acc) and z partials zpart[first_chunk[r] + chunk] over the lists.
+hipError_t launch_nl_force(int nbk, const KParams &P, const SysDesc *sysd, const RepDesc *reps, int R,
+                           int n_pad_max, const int *first_chunk, const float4 *xs, const int *cnt, const int2 *nl,
+                           double *acc, double *zpart, hipStream_t st);
 // Per contact tile of a map: sum over its counted pairs of the squared
 // (float32) entries, in float64.
 hipError_t launch_tile_sumsq(int nc, int ncb, int min_sep, const int *perm, const float *tiles, double *out,

@@ -857,7 +857,6 @@ template <int MODE, int NBK>
 __global__ __launch_bounds__(256) void k_pairs(const KParams P, const SysDesc *__restrict__ sysd,
                                                const RepDesc *__restrict__ reps,
                                                const TileItem *__restrict__ items, const int n_items,
-                                               const int *__restrict__ n_live, const int zsub,
                                                const float4 *__restrict__ xs, double *__restrict__ acc,
                                                double *__restrict__ zpart, const float *__restrict__ eff,
                                                const double *__restrict__ csum) {
@@ -865,9 +864,7 @@ __global__ __launch_bounds__(256) void k_pairs(const KParams P, const SysDesc *_
     __shared__ float4 shpos[4][128];   // block J of each wavefront's item, stored twice
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int item = blockIdx.x * 4 + wave;
-    const int count = n_live ? *n_live : n_items;
-    if (blockIdx.x * 4 >= count) return;   // whole workgroup past the live items
-    const bool live = item < count;
+    const bool live = item < n_items;
     const TileItem it = items[live ? item : 0];
     const RepDesc rd = reps[it.rep];
     const SysDesc S = sysd[rd.sys];
@@ -941,18 +938,18 @@ __global__ __launch_bounds__(256) void k_pairs(const KParams P, const SysDesc *_
     }
     if constexpr (T::z) {
         const double zw = wave_sum((double)zt);
-        if (lane == 0) zpart[item] = contact_tile ? zw - (zsub ? S.R2tile[tile_index(I, J, S.ncb)] : 0.0) : 0.0;
+        if (lane == 0) zpart[item] = contact_tile ? zw : 0.0;
     }
 }
 
 template <int MODE>
 static void launch_pairs_mode(int nbk, dim3 grid, dim3 block, hipStream_t st, const KParams &P,
                               const SysDesc *sysd, const RepDesc *reps, const TileItem *items, int n_items,
-                              const int *n_live, int zsub, const float4 *xs, double *acc, double *zpart,
-                              const float *eff, const double *csum) {
+                              const float4 *xs, double *acc, double *zpart, const float *eff,
+                              const double *csum) {
 #define SCPS_LAUNCH(K)                                                                                   \
-    hipLaunchKernelGGL((k_pairs<MODE, K>), grid, block, 0, st, P, sysd, reps, items, n_items, n_live, zsub, xs, \
-                       acc, zpart, eff, csum)
+    hipLaunchKernelGGL((k_pairs<MODE, K>), grid, block, 0, st, P, sysd, reps, items, n_items, xs, acc, zpart, \
+                       eff, csum)
     if constexpr (!ModeTraits<MODE>::nb) {
         SCPS_LAUNCH(0);
     } else {
@@ -967,13 +964,12 @@ static void launch_pairs_mode(int nbk, dim3 grid, dim3 block, hipStream_t st, co
 }
 
 hipError_t launch_pairs(int mode, int nbk, const KParams &P, const SysDesc *sysd, const RepDesc *reps,
-                        const TileItem *items, int n_items, const int *n_live, int zsub, const float4 *xs,
-                        double *acc, double *zpart, const float *eff, const double *csum, hipStream_t st) {
+                        const TileItem *items, int n_items, const float4 *xs, double *acc, double *zpart,
+                        const float *eff, const double *csum, hipStream_t st) {
     if (n_items == 0) return hipSuccess;
     const dim3 grid((n_items + 3) / 4), block(256);
 #define SCPS_MODE(M)                                                                                       \
-    launch_pairs_mode<M>(nbk, grid, block, st, P, sysd, reps, items, n_items, n_live, zsub, xs, acc, zpart, eff, \
-                         csum)
+    launch_pairs_mode<M>(nbk, grid, block, st, P, sysd, reps, items, n_items, xs, acc, zpart, eff, csum)
     switch (mode) {
     case PM_RMD: SCPS_MODE(PM_RMD); break;
     case PM_Z: SCPS_MODE(PM_Z); break;
@@ -1016,14 +1012,19 @@ hipError_t launch_finalize_rmd(const KParams &P, int R, const int *first, const 
 }
 
 // ---------------------------------------------------------------------------
-// tile culling for the cutoff variant (per-step rMD path)
+// cutoff variant: neighbour lists (per-step rMD path)
 // ---------------------------------------------------------------------------
-// With both cutoffs set, a tile pair whose blocks' bounding spheres are more
-// than the larger cutoff apart holds no pair with a force or a nonzero C, and
-// it adds its native-map sum of R^2 to z (C = 0 there, R still counts).
-// Every step: bounding spheres, then an order-preserving compaction of the
-// kept items (replica by replica, so the z partials still sum in a fixed
-// order).
+// With both cutoffs set, every particle keeps a full list of the particles
+// within r_list = (larger cutoff) + NL_SKIN of it, rebuilt for a replica when
+// one of its particles has moved more than NL_SKIN / 2 since the last build
+// (whatever moved it: steps, or the caller between calls), so no pair within
+// the cutoffs is ever missing.  The host forces a rebuild of every replica
+// when the lists are new or the reference map they carry has changed.  The build tests only the tile pairs whose blocks' bounding
+// spheres come within r_list.  Entry: x = j | contact << 30 | nonbonded << 29
+// (j internal, predicates of the pair), y = the bits of R_ij (float32).
+// Skipped contact pairs have C = 0, so
+//   z = sum over all counted pairs of R^2 + sum over listed pairs of C (C - 2R)
+// and each unordered pair is listed twice (once per side).
 
 // Bounding sphere of block b of replica r (one wavefront): centroid of its
 // real particles and the largest distance from it.
@@ -1048,94 +1049,281 @@ __global__ __launch_bounds__(64) void k_block_bounds(const SysDesc *__restrict__
     if (lane == 0) bounds[(int64_t)r * nb_max + b] = make_float4((float)cx, (float)cy, (float)cz, (float)sqrt(d2));
 }
 
-// Keep flags and their exclusive prefix within each workgroup of 256 items:
-// local[s] = (prefix << 1) | keep; block_off[w] = the workgroup's count.
-// The sphere test is done in float64 with a 0.01 A margin, so a dropped item
-// has every pair farther apart than r_keep by more than float32 rounding.
-__global__ __launch_bounds__(256) void k_cull_flags(const TileItem *__restrict__ items, int n_items,
-                                                    const float4 *__restrict__ bounds, int nb_max, float r_keep,
-                                                    int *__restrict__ local, int *__restrict__ block_off) {
-    __shared__ int wcount[4];
-    const int s = blockIdx.x * 256 + threadIdx.x, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    int keep = 0;
-    if (s < n_items) {
-        const TileItem it = items[s];
-        if (it.I == it.J) {
-            keep = 1;   // diagonal tiles also carry the bonds
-        } else {
-            const float4 a = bounds[(int64_t)it.rep * nb_max + it.I], b = bounds[(int64_t)it.rep * nb_max + it.J];
-            const double dx = (double)a.x - b.x, dy = (double)a.y - b.y, dz = (double)a.z - b.z;
-            const double gap = sqrt(dx * dx + dy * dy + dz * dz) - (double)a.w - (double)b.w;
-            keep = gap <= (double)r_keep + 0.01;
-        }
+// Largest squared displacement of the particles of block b since the last
+// build (one wavefront per block); bmax[first[r] + b].
+__global__ __launch_bounds__(64) void k_nl_disp(const SysDesc *__restrict__ sysd, const RepDesc *__restrict__ reps,
+                                                const int *__restrict__ first, const float4 *__restrict__ xs,
+                                                const float4 *__restrict__ xref, float *__restrict__ bmax) {
+    const int b = blockIdx.x, r = blockIdx.y, lane = threadIdx.x;
+    const RepDesc rd = reps[r];
+    const int n = sysd[rd.sys].n, nb = sysd[rd.sys].nb;
+    if (b >= nb) return;
+    const int i = b * 64 + lane;
+    float d2 = 0.f;
+    if (i < n) {
+        const float4 p = xs[2 * rd.poff + b * 128 + lane], q = xref[rd.poff + i];
+        const float dx = p.x - q.x, dy = p.y - q.y, dz = p.z - q.z;
+        d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+        if (!(d2 <= 3.0e38f)) d2 = 3.0e38f;           // a non-finite position forces a rebuild
     }
-    const uint64_t bal = __ballot(keep);
-    const int below = __popcll(lane ? (bal << (64 - lane)) : 0ull);
-    if (lane == 0) wcount[w] = __popcll(bal);
-    __syncthreads();
-    int off = 0;
-    for (int q = 0; q < w; ++q) off += wcount[q];
-    if (s < n_items) local[s] = ((off + below) << 1) | keep;
-    if (threadIdx.x == 0) block_off[blockIdx.x] = wcount[0] + wcount[1] + wcount[2] + wcount[3];
-}
-
-// Exclusive prefix sum of v[0 .. n) in place, total in v[n] (one workgroup).
-__global__ __launch_bounds__(1024) void k_scan_counts(int *__restrict__ v, int n) {
-    __shared__ int wsum[16];
-    __shared__ int carry;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    if (tid == 0) carry = 0;
-    __syncthreads();
-    for (int base = 0; base < n; base += 1024) {
-        const int i = base + tid;
-        const int x = i < n ? v[i] : 0;
-        int incl = x;
 #pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const int y = __shfl_up(incl, o, 64);
-            if (lane >= o) incl += y;
+    for (int o = 32; o > 0; o >>= 1) d2 = fmaxf(d2, __shfl_xor(d2, o, 64));
+    if (lane == 0) bmax[first[r] + b] = d2;
+}
+
+// Decide per replica whether to rebuild (force, or a displacement beyond
+// NL_SKIN / 2 in any of its blocks); for a rebuild, clear the block's counts
+// and record the reference positions.
+__global__ __launch_bounds__(64) void k_nl_reset(const SysDesc *__restrict__ sysd, const RepDesc *__restrict__ reps,
+                                                 const int *__restrict__ first, const float4 *__restrict__ xs,
+                                                 float4 *__restrict__ xref, const float *__restrict__ bmax, int force,
+                                                 int *__restrict__ rebuild, int *__restrict__ cnt) {
+    const int b = blockIdx.x, r = blockIdx.y, lane = threadIdx.x;
+    const RepDesc rd = reps[r];
+    const int nb = sysd[rd.sys].nb;
+    if (b >= nb) return;
+    float d2 = 0.f;
+    for (int q = lane; q < nb; q += 64) d2 = fmaxf(d2, bmax[first[r] + q]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) d2 = fmaxf(d2, __shfl_xor(d2, o, 64));
+    const float half = 0.5f * NL_SKIN;
+    const bool rb = force || d2 > half * half;
+    if (b == 0 && lane == 0) rebuild[r] = rb;
+    if (!rb) return;
+    const int i = b * 64 + lane;
+    xref[rd.poff + i] = xs[2 * rd.poff + b * 128 + lane];
+    cnt[rd.poff + i] = 0;
+}
+
+// List build on a fixed grid of NL_BUILD_WG workgroups: wavefront w takes
+// the work items g = w (mod all wavefronts) of every rebuilding replica (the
+// flags are read 64 replicas at a time), so one replica's rebuild is spread
+// over the whole grid and a step without rebuilds costs a few loads.  A
+// tile pair whose blocks come
+// within r_list is walked twice in the sub-step order of the force kernels
+// (lane l meets j = (l + k) mod 64 of block J, read from LDS): the first walk
+// counts each lane's i-side entries and, in a counter that rotates with the
+// j partner (DPP, as the j-side force partials do), the j-side ones; one
+// atomic per particle and tile reserves the slots; the second walk writes
+// the entries.  A list that would pass NL_CAP entries marks the replica
+// (flags[r] = 2) and keeps its first NL_CAP entries.
+constexpr int NL_BUILD_WG = 2048;
+
+__device__ __forceinline__ int rot1i(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x134, 0xF, 0xF, false); }
+
+__global__ __launch_bounds__(256) void k_nl_build(const KParams P, const SysDesc *__restrict__ sysd,
+                                                  const RepDesc *__restrict__ reps, int R,
+                                                  const TileItem *__restrict__ items,
+                                                  const int *__restrict__ first_all, const float4 *__restrict__ xs,
+                                                  const float4 *__restrict__ bounds, int nb_max, float r_list,
+                                                  const int *__restrict__ rebuild, int *__restrict__ cnt,
+                                                  int2 *__restrict__ nl, int *__restrict__ flags) {
+    __shared__ float4 shpos[4][128];
+    __shared__ int shorg[4][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int W = gridDim.x * 4, w = blockIdx.x * 4 + wave;
+    const float rl2 = r_list * r_list;
+    for (int r0 = 0; r0 < R; r0 += 64) {
+        uint64_t todo = __ballot(r0 + lane < R && rebuild[min(r0 + lane, R - 1)]);
+        while (todo) {
+            const int r = r0 + __builtin_ctzll(todo);
+            todo &= todo - 1;
+            const RepDesc rd = reps[r];
+            const SysDesc S = sysd[rd.sys];
+            const float4 *xr2 = xs + 2 * rd.poff;
+            int *ci = cnt + rd.poff;
+            int2 *li = nl + rd.poff * (int64_t)NL_CAP;
+            const int t0 = first_all[r], t_end = first_all[r + 1];
+            for (int t = t0 + ((w - t0) % W + W) % W; t < t_end; t += W) {
+                const TileItem it = items[t];
+                const int I = it.I, J = it.J;
+                if (I != J) {
+                    const float4 a = bounds[(int64_t)r * nb_max + I], b = bounds[(int64_t)r * nb_max + J];
+                    const double dx = (double)a.x - b.x, dy = (double)a.y - b.y, dz = (double)a.z - b.z;
+                    if (sqrt(dx * dx + dy * dy + dz * dz) - (double)a.w - (double)b.w > (double)r_list + 0.01)
+                        continue;
+                }
+                // block J of this wavefront's tile (stored twice: j = lane + k needs no wrap)
+                const float4 pjl = xr2[J * 128 + lane];
+                shpos[wave][lane] = pjl;
+                shpos[wave][64 + lane] = pjl;
+                shorg[wave][lane] = S.perm[J * 64 + lane];
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                const int i = I * 64 + lane;
+                const float4 pi = xr2[I * 128 + lane];
+                const int oi = S.perm[i];
+                const bool diag = I == J, ival = i < S.n, icon = i < S.nc;
+                const int njv = S.n - J * 64, njc = S.nc - J * 64;
+                // tag of the pair met at sub-step k (0: no entry), without branches; every
+                // tile runs all 64 sub-steps, a diagonal tile counting only k = 1..32
+                // (lanes 0..31 at k = 32), so each unordered pair is met once
+                auto tag_at = [&](int k) -> int {
+                    const int jl = (lane + k) & 63;
+                    float dx, dy, dz;
+                    const float r2 = pair_r2(pi, shpos[wave][lane + k], dx, dy, dz);
+                    const int sep = abs(oi - shorg[wave][jl]);
+                    const bool in_tile = !diag | ((k >= 1) & ((k < 32) | ((k == 32) & (lane < 32))));
+                    const bool act = ival & (jl < njv) & in_tile & (r2 <= rl2);
+                    const int con = (icon & (jl < njc) & (sep > P.min_sep)) ? 1 << 30 : 0;
+                    const int nbp = (sep > P.nb_excl) ? 1 << 29 : 0;
+                    return act ? (con | nbp) : 0;
+                };
+                int n_i = 0, n_j = 0;
+#pragma unroll 8
+                for (int k = 0; k < 64; ++k) {
+                    const int hit = tag_at(k) != 0;
+                    n_i += hit;
+                    n_j = rot1i(n_j + hit);
+                }
+                // after 64 rotations lane l holds the j-side count of particle l of block J
+                const int base_i = n_i ? atomicAdd(&ci[i], n_i) : 0;
+                const int base_j = n_j ? atomicAdd(&ci[J * 64 + lane], n_j) : 0;
+                if (base_i + n_i > NL_CAP || base_j + n_j > NL_CAP) flags[r] = 2;
+                // second walk: the j-side write offset travels with its particle
+                int o_i = base_i, o_j = base_j;
+                const float *rt =
+                    (I < S.ncb && J < S.ncb) ? S.ref + (int64_t)tile_index(I, J, S.ncb) * 4096 : nullptr;
+#pragma unroll 4
+                for (int k = 0; k < 64; ++k) {
+                    const int tag = tag_at(k);
+                    if (tag) {
+                        const int jl = (lane + k) & 63, j = J * 64 + jl;
+                        const float Rv = (tag & (1 << 30)) ? rt[k * 64 + lane] : 0.f;
+                        if (o_i < NL_CAP) li[(int64_t)i * NL_CAP + o_i] = make_int2(j | tag, __float_as_int(Rv));
+                        if (o_j < NL_CAP) li[(int64_t)j * NL_CAP + o_j] = make_int2(i | tag, __float_as_int(Rv));
+                        ++o_i;
+                        ++o_j;
+                    }
+                    o_j = rot1i(o_j);
+                }
+                __builtin_amdgcn_wave_barrier();   // shpos / shorg are rewritten for the next tile
+            }
         }
-        if (lane == 63) wsum[w] = incl;
-        __syncthreads();
-        int woff = 0;
-        for (int q = 0; q < w; ++q) woff += wsum[q];
-        const int c0 = carry;
-        if (i < n) v[i] = c0 + woff + incl - x;
-        __syncthreads();
-        if (tid == 1023) carry = c0 + woff + incl;
-        __syncthreads();
     }
-    if (tid == 0) v[n] = carry;
 }
 
-// Copy the kept items to their places and record where each replica starts.
-__global__ __launch_bounds__(256) void k_cull_compact(const TileItem *__restrict__ items, int n_items,
-                                                      const int *__restrict__ local,
-                                                      const int *__restrict__ block_off,
-                                                      const int *__restrict__ first_all, int R,
-                                                      TileItem *__restrict__ out, int *__restrict__ first_out) {
-    const int s = blockIdx.x * 256 + threadIdx.x;
-    if (s >= n_items) return;
-    const int l = local[s];
-    const int pos = block_off[blockIdx.x] + (l >> 1);
-    const TileItem it = items[s];
-    if (l & 1) out[pos] = it;
-    if (first_all[it.rep] == s) first_out[it.rep] = pos;
-    if (s == n_items - 1) first_out[R] = pos + (l & 1);
+// Forces and z over the lists.  NL_LANES lanes share a particle and take its
+// entries e = t, t + NL_LANES, ... (consecutive entries, so a wavefront's
+// loads are coalesced per particle); a workgroup of 256 threads covers
+// 256 / NL_LANES particles.  Only i's side of each listed pair is added (the
+// pair is listed for j as well).  zpart[first[r] + chunk] = the chunk's sum
+// of C (C - 2R) / 2.
+constexpr int NL_LANES = 8;
+constexpr int NL_CHUNK = 256 / NL_LANES;
+template <int NBK>
+__global__ __launch_bounds__(256) void k_nl_force(const KParams P, const SysDesc *__restrict__ sysd,
+                                                  const RepDesc *__restrict__ reps, const int *__restrict__ first,
+                                                  const float4 *__restrict__ xs, const int *__restrict__ cnt,
+                                                  const int2 *__restrict__ nl, double *__restrict__ acc,
+                                                  double *__restrict__ zpart) {
+    __shared__ double zw[4];
+    const int chunk = blockIdx.x, r = blockIdx.y;
+    const RepDesc rd = reps[r];
+    const SysDesc S = sysd[rd.sys];
+    if (chunk * NL_CHUNK >= S.n_pad) return;
+    const int tid = threadIdx.x, t = tid % NL_LANES;
+    const int i = chunk * NL_CHUNK + tid / NL_LANES;
+    const float4 *xr2 = xs + 2 * rd.poff;
+    const float4 pi = xr2[dup_index(i)];
+    const float qp = P.dh_pref * pi.w;
+    const int m = i < S.n ? min(cnt[rd.poff + i], NL_CAP) : 0;
+    const int2 *li = nl + (rd.poff + i) * (int64_t)NL_CAP;
+    float f[3] = {0.f, 0.f, 0.f}, g[3] = {0.f, 0.f, 0.f};
+    float zt = 0.f;
+    for (int e = t; e < m; e += NL_LANES) {
+        const int2 en = li[e];
+        const int j = en.x & 0x1FFFFFFF;
+        const float4 pj = xr2[dup_index(j)];
+        float dx, dy, dz;
+        const float r2 = pair_r2(pi, pj, dx, dy, dz);
+        if (NBK != 0 && (en.x & (1 << 29)) && (!P.has_cut_nb || r2 <= P.r_cut_nb2)) {
+            const float s = nb_scalar<NBK>(P, r2, qp, pj.w);
+            f[0] = fmaf(s, dx, f[0]);
+            f[1] = fmaf(s, dy, f[1]);
+            f[2] = fmaf(s, dz, f[2]);
+        }
+        if (en.x & (1 << 30)) {
+            const float R = __int_as_float(en.y);
+            const float q = r2 * P.inv_r0sq;
+            const float q2 = q * q;
+            const float num = 1.f + q + q2;
+            const float den = fmaf(q2, q + q2, num);
+            const float inv_den = (!P.has_cut || r2 <= P.r_cut2) ? frcp(den) : 0.f;
+            const float C = num * inv_den;
+            zt = fmaf(C, C - 2.f * R, zt);
+            const float poly = fmaf(q, fmaf(q, fmaf(q, P.cp[0], P.cp[1]), P.cp[2]), P.cp[3]);
+            const float gg = ((C - R) * (q2 * inv_den)) * (poly * inv_den);
+            g[0] = fmaf(gg, dx, g[0]);
+            g[1] = fmaf(gg, dy, g[1]);
+            g[2] = fmaf(gg, dz, g[2]);
+        }
+    }
+#pragma unroll
+    for (int o = 1; o < NL_LANES; o <<= 1) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            f[c] += __shfl_xor(f[c], o, 64);
+            g[c] += __shfl_xor(g[c], o, 64);
+        }
+    }
+    double *ar = acc + 6 * rd.poff;
+    if (t == 0 && i < S.n) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            unsafeAtomicAdd(&ar[c * S.n_pad + i], (double)f[c]);
+            unsafeAtomicAdd(&ar[(3 + c) * S.n_pad + i], (double)g[c]);
+        }
+        if (P.has_bond) {
+            const int bn = S.bond_next[i];
+            if (bn >= 0) {
+                double fb[3];
+                bond_force(P, pi, xr2[dup_index(bn)], fb);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    unsafeAtomicAdd(&ar[c * S.n_pad + i], fb[c]);
+                    unsafeAtomicAdd(&ar[c * S.n_pad + bn], -fb[c]);
+                }
+            }
+        }
+    }
+    const double w = wave_sum(0.5 * (double)zt);
+    if ((tid & 63) == 0) zw[tid >> 6] = w;
+    __syncthreads();
+    if (tid == 0) zpart[first[r] + chunk] = (zw[0] + zw[1]) + (zw[2] + zw[3]);
 }
 
-hipError_t launch_cull_tiles(const SysDesc *sysd, const RepDesc *reps, int R, int nb_max, const float4 *xs,
-                             float4 *bounds, const TileItem *items_all, int n_items, const int *first_all,
-                             float r_keep, int *local, int *block_off, TileItem *items_out, int *first_out,
-                             hipStream_t st) {
-    if (n_items == 0) return hipSuccess;
-    const int nblk = (n_items + 255) / 256;
-    hipLaunchKernelGGL(k_block_bounds, dim3(nb_max, R), dim3(64), 0, st, sysd, reps, nb_max, xs, bounds);
-    hipLaunchKernelGGL(k_cull_flags, dim3(nblk), dim3(256), 0, st, items_all, n_items, bounds, nb_max, r_keep, local,
-                       block_off);
-    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, block_off, nblk);
-    hipLaunchKernelGGL(k_cull_compact, dim3(nblk), dim3(256), 0, st, items_all, n_items, local, block_off, first_all,
-                       R, items_out, first_out);
+hipError_t launch_nl_update(const KParams &P, const SysDesc *sysd, const RepDesc *reps, int R, int nb_max,
+                            const int *first_blk, const float4 *xs, float4 *bounds, float4 *xref, float *bmax,
+                            int *rebuild, int force, const TileItem *items_all, const int *first_all, float r_list,
+                            int *cnt, int2 *nl, int *flags, hipStream_t st) {
+    const dim3 blocks(nb_max, R);
+    hipLaunchKernelGGL(k_block_bounds, blocks, dim3(64), 0, st, sysd, reps, nb_max, xs, bounds);
+    hipLaunchKernelGGL(k_nl_disp, blocks, dim3(64), 0, st, sysd, reps, first_blk, xs, xref, bmax);
+    hipLaunchKernelGGL(k_nl_reset, blocks, dim3(64), 0, st, sysd, reps, first_blk, xs, xref, bmax, force, rebuild,
+                       cnt);
+    hipLaunchKernelGGL(k_nl_build, dim3(NL_BUILD_WG), dim3(256), 0, st, P, sysd, reps, R, items_all, first_all, xs,
+                       bounds, nb_max, r_list, rebuild, cnt, nl, flags);
+    return hipGetLastError();
+}
+
+int nl_chunks(int n_pad) { return (n_pad + NL_CHUNK - 1) / NL_CHUNK; }
+
+hipError_t launch_nl_force(int nbk, const KParams &P, const SysDesc *sysd, const RepDesc *reps, int R,
+                           int n_pad_max, const int *first_chunk, const float4 *xs, const int *cnt, const int2 *nl,
+                           double *acc, double *zpart, hipStream_t st) {
+    const dim3 blocks(nl_chunks(n_pad_max), R);
+#define SCPS_NL(K)                                                                                      \
+    hipLaunchKernelGGL(k_nl_force<K>, blocks, dim3(256), 0, st, P, sysd, reps, first_chunk, xs, cnt, nl, acc, \
+                       zpart)
+    switch (nbk) {
+    case 0: SCPS_NL(0); break;
+    case 1: SCPS_NL(1); break;
+    case 2: SCPS_NL(2); break;
+    default: SCPS_NL(3); break;
+    }
+#undef SCPS_NL
     return hipGetLastError();
 }
 

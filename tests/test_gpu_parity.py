@@ -702,16 +702,17 @@ def test_least_biased_after_stepping_matches_oracle(S):
 
 
 # ---------------------------------------------------------------------------
-# cutoff variant: contact and nonbonded cutoffs, per-step tile culling
+# cutoff variant: contact and nonbonded cutoffs; neighbour lists on the per-step path
 # ---------------------------------------------------------------------------
 CUT_CASES = [
     # name, n, exec_mode, r_cut_contact, r_cut_nb
     ("both12_persistent", 333, 0, 12.0, 12.0),
-    ("both12_culled", 333, 1, 12.0, 12.0),
+    ("both12_lists", 333, 1, 12.0, 12.0),
     ("both12_all_tiles", 333, 2, 12.0, 12.0),
     ("nb_only10_per_step", 257, 1, 0.0, 10.0),
     ("nb_only10_persistent", 257, 0, 0.0, 10.0),
-    ("cut9_nb10_culled_1500", 1500, 1, 9.0, 10.0),
+    ("cut9_nb10_lists_1500", 1500, 1, 9.0, 10.0),
+    ("cut12_nb9_lists_ragged_1100", 1100, 1, 12.0, 9.0),
 ]
 
 
@@ -738,32 +739,112 @@ def test_cutoff_forces_match_oracle(S, name, n, exec_mode, rc, rnb):
         assert abs(cvg[r, 1] - cvr[1]) <= TOL * max(cvr[1], 1e-3 * osys.Z0)
 
 
-def test_culled_steps_equal_all_tile_steps(S):
-    """Culling drops only tiles with no pair inside the cutoffs, so a noisy
-    trajectory agrees with the all-tiles path up to the order of float64 sums."""
+def _list_vs_tiles(S, n, R, base, X0, n_steps, calls=1):
     import torch
-    n, R = 1400, 4
-    base = dict(I._base_params(), r_cut_contact=10.0, r_cut_nb=10.0, k_R=5e-3)
     w = single_system_workload(n, np.arange(n), base, R)
-    sy = w.systems[0]
-    rng = np.random.default_rng(7)
-    # random coils and the jittered extended start: no overlapping beads, so
-    # the 30 steps stay finite (a perturbed native can put two beads 1.7 A apart)
-    X0 = np.stack([I.random_coil(n, 300 + r) if r % 2 == 0 else sy.start + rng.normal(0, 0.05, sy.start.shape)
-                   for r in range(R)]).astype(np.float32)
     res = []
     for mode in (1, 2):
         ctx = context(S, w, params=base, exec_mode=mode)
         x = dev(X0.ravel())
         v = torch.zeros_like(x)
         cv = dev(w.initial_cvstate(), "f64")
-        ctx.step_replicas(x, v, cv, 30, step0=5)
+        for c in range(calls):
+            ctx.step_replicas(x, v, cv, n_steps // calls, step0=5 + c * (n_steps // calls))
         ctx.sync()
         res.append((host(x).reshape(R, 3, n), host(cv)))
         ctx.close()
+    return res
+
+
+def _clean_starts(sy, R, seed):
+    """Random coils and the jittered extended start: no overlapping beads (a
+    perturbed native can put two beads 1.7 A apart and blow a run up)."""
+    rng = np.random.default_rng(seed)
+    return np.stack([I.random_coil(sy.n, 300 + seed + r) if r % 2 == 0
+                     else sy.start + rng.normal(0, 0.05, sy.start.shape) for r in range(R)]).astype(np.float32)
+
+
+def test_list_steps_equal_all_tile_steps(S):
+    """The lists hold every pair within the cutoffs, so a noisy trajectory
+    agrees with the all-tiles path up to the order of the float32 sums."""
+    n, R = 1400, 4
+    base = dict(I._base_params(), r_cut_contact=10.0, r_cut_nb=10.0, k_R=5e-3)
+    sy = single_system_workload(n, np.arange(n), base, R).systems[0]
+    X0 = _clean_starts(sy, R, 7)
+    res = _list_vs_tiles(S, n, R, base, X0, 30)
     disp = np.abs(res[1][0] - X0).max()
     d = np.abs(res[0][0] - res[1][0]).max()
-    print(f"  culled vs all tiles after 30 steps: max |dx| {d:.2e} (displacement {disp:.2e})", flush=True)
-    assert d <= 1e-5 * disp
-    np.testing.assert_allclose(res[0][1][:, :3], res[1][1][:, :3], rtol=1e-7)
-    np.testing.assert_allclose(res[0][1][:, 7], res[1][1][:, 7], rtol=1e-5)
+    print(f"  lists vs all tiles after 30 steps: max |dx| {d:.2e} (displacement {disp:.2e})", flush=True)
+    assert d <= 1e-4 * disp + 1e-4
+    np.testing.assert_allclose(res[0][1][:, :2], res[1][1][:, :2], rtol=1e-7)
+    # E_b = k_R (z - z_m)^2 / 2 takes a small difference of two large z values
+    np.testing.assert_allclose(res[0][1][:, 2], res[1][1][:, 2], rtol=1e-4, atol=1e-7)
+    np.testing.assert_allclose(res[0][1][:, 7], res[1][1][:, 7], rtol=1e-4)
+
+
+def test_lists_are_rebuilt_as_particles_move(S):
+    """A hot run (kT x 6) moves particles by several list skins within a call
+    and between calls: the list path still follows the all-tiles path."""
+    n, R = 900, 4
+    base = dict(I._base_params(), r_cut_contact=9.0, r_cut_nb=9.0, k_R=5e-3)
+    base["kT"] *= 6.0
+    sy = single_system_workload(n, np.arange(n), base, R).systems[0]
+    X0 = _clean_starts(sy, R, 11)
+    res = _list_vs_tiles(S, n, R, base, X0, 150, calls=3)
+    disp = np.abs(res[1][0] - X0).max()
+    d = np.abs(res[0][0] - res[1][0]).max()
+    print(f"  hot run, 150 steps in 3 calls: max displacement {disp:.2f} A, lists vs all tiles {d:.2e}", flush=True)
+    assert disp > 2.0                                        # a rebuild at every 0.75 A: several were needed
+    assert d <= 1e-3 * disp
+    np.testing.assert_allclose(res[0][1][:, :2], res[1][1][:, :2], rtol=1e-4)
+
+
+def test_list_overflow_is_reported(S):
+    """600 beads inside a 4 A ball (no pair forces): every list would need 599
+    entries, more than the capacity; the step reports it instead of dropping pairs."""
+    import torch
+    n = 600
+    base = dict(I._base_params(), r_cut_contact=12.0, r_cut_nb=12.0, lj_eps=0.0, dh_prefactor=0.0, k_bond=0.0)
+    w = single_system_workload(n, np.arange(n), base, 1)
+    ctx = context(S, w, params=base, exec_mode=1)
+    rng = np.random.default_rng(3)
+    u = rng.normal(size=(3, n))
+    X = (4.0 * u / np.linalg.norm(u, axis=0) * rng.uniform(0, 1, n) ** (1 / 3)).astype(np.float32)
+    x = dev(X.ravel())
+    with pytest.raises(S.ScpsError) as e:
+        ctx.step_replicas(x, torch.zeros_like(x), dev(w.initial_cvstate(), "f64"), 1)
+        ctx.sync()
+    assert e.value.status == -6 and "neighbours" in str(e.value)
+
+
+def test_lists_follow_positions_changed_between_calls(S):
+    """The caller replaces every position between two calls on one context:
+    the displacement test rebuilds the lists, and the second call matches a
+    fresh all-tiles context started from the new positions."""
+    import torch
+    n, R = 800, 3
+    base = dict(I._base_params(), r_cut_contact=10.0, r_cut_nb=10.0, k_R=5e-3)
+    w = single_system_workload(n, np.arange(n), base, R)
+    sy = w.systems[0]
+    XA, XB = _clean_starts(sy, R, 21), _clean_starts(sy, R, 22)[::-1].copy()
+    ctx = context(S, w, params=base, exec_mode=1)
+    x = dev(XA.ravel())
+    v = torch.zeros_like(x)
+    cv = dev(w.initial_cvstate(), "f64")
+    ctx.step_replicas(x, v, cv, 10)
+    x.copy_(dev(XB.ravel()))
+    v.zero_()
+    cv.copy_(dev(w.initial_cvstate(), "f64"))
+    ctx.step_replicas(x, v, cv, 10, step0=40)
+    ctx.sync()
+    ref = context(S, w, params=base, exec_mode=2)
+    x2, v2, cv2 = dev(XB.ravel()), torch.zeros_like(x), dev(w.initial_cvstate(), "f64")
+    ref.step_replicas(x2, v2, cv2, 10, step0=40)
+    ref.sync()
+    disp = np.abs(host(x2) - XB.ravel()).max()
+    d = np.abs(host(x) - host(x2)).max()
+    print(f"  new positions between calls: lists vs all tiles {d:.2e} (displacement {disp:.2e})", flush=True)
+    assert d <= 1e-4 * disp + 1e-4
+    np.testing.assert_allclose(host(cv)[:, :2], host(cv2)[:, :2], rtol=1e-7)
+    ctx.close()
+    ref.close()
