@@ -208,6 +208,32 @@ scps_status scps_update_reference_from_paths(scps_ctx *ctx, int32_t system, cons
                                              int32_t n_paths, int32_t n_frames,
                                              const uint8_t *success, double *maps_out);
 
+/* Tube variables s_lambda, w_lambda, eqs (asXa), (awXa) discretised as in the
+ * appendix, of every replica's configuration against the frame stack of system
+ * stack_system, without ratchets or forces: distances d_k = sum_p (C_p -
+ * R_kp)^2 / Z0 (Z0 of stack_system), s = 1 - (1/M) sum_k k p_k, w =
+ * -(1/lambda) log sum_k exp(-lambda d_k), p = softmax(-lambda d).  Several
+ * initial conditions of one protein are several systems of the same chain,
+ * each with the stack of its own runs; this measures any replica against any
+ * of them.  Uses the context's lambda (any bias mode; it must be > 0).
+ *   x: device float32 [3 * sum N], as for scps_step_replicas.
+ *   s, w: device float64 [R] (either may be NULL, not both).
+ * Every replica's system must have the same particles and contact set as
+ * stack_system.  Asynchronous.  Errors: INVALID_ARG, STATE (stack_system has no
+ * native map or no stack of >= 2 frames), SHAPE (a replica's system differs),
+ * OOM, HIP. */
+scps_status scps_eval_tube(scps_ctx *ctx, int32_t stack_system, const float *x, double *s, double *w);
+
+/* Global progress coordinate sigma(X), eq (sigma): the mean over n_stacks
+ * stacks (the systems stack_systems[0..n_stacks), one per initial condition)
+ * of the time-weighted frame average that s_lambda measures, i.e.
+ * sigma = (1/n_stacks) sum_k (1 - s_lambda^k(X)), in [0, 1] from the unfolded
+ * to the folded end of the reference paths.
+ *   stack_systems: host int32 [n_stacks]; sigma: device float64 [R].
+ * Same conditions, asynchrony and errors as scps_eval_tube. */
+scps_status scps_eval_sigma(scps_ctx *ctx, int32_t n_stacks, const int32_t *stack_systems, const float *x,
+                            double *sigma);
+
 /* Least-biased path selection, the last step of an SCPS iteration (the
  * method ranks the paths it generated by the bias functional T[X] of eq (T),
  * the weighted time integral of the squared bias force, and keeps the one

@@ -6,7 +6,7 @@ the seeded inputs of ``paper_1705_02180_amd.inputs`` and nothing else.
 
 Every function here marshals numpy arrays into ``liboracle.so`` (plain C,
 double precision, straightforward loops; see ``scps_oracle.c`` for the paper
-passages each routine follows).  The library is compiled on first use if it
+passages each routine follows), or averages its results (``sigma``).  The library is compiled on first use if it
 is missing.
 
 Parity status: every routine is pinned by the ``-m "not gpu"`` tests against
@@ -304,3 +304,11 @@ def least_biased(cv, success=None) -> int:
     if succ is not None and succ.size != cv.shape[0]:
         raise ValueError("success needs one entry per path")
     return int(lib().orc_least_biased(cv.shape[0], _p(cv), _p(succ)))
+
+
+def sigma(x, cidx, stacks, Z0s, lam, r0: float = 7.5, r_cut: float = 0.0, min_sep: int = 0) -> float:
+    """Global progress coordinate, eq (sigma): the mean over the reference
+    stacks (one per initial condition) of 1 - s_lambda^k(X), each s from the
+    pinned tube routine with its own stack and Z0."""
+    vals = [1.0 - tube(x, cidx, st, z0, lam, r0, r_cut, min_sep, grads=False)[0] for st, z0 in zip(stacks, Z0s)]
+    return float(np.mean(vals))

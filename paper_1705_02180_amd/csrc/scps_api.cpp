@@ -340,6 +340,46 @@ void build_schedule(SysHost &h) {
     }
 }
 
+// Replicas of each system in groups of up to SCPS_GROUP, one item per
+// (group, contact tile pair), and the distance accumulators X, Q: what the
+// matrix-core tube-variable passes need.  Built at init for SCPS contexts and
+// on first use by the evaluation calls otherwise.
+scps_status ensure_scps_groups(scps_ctx *c) {
+    if (c->d_groups) return SCPS_OK;
+    const int R = c->R;
+    HIP_TRY(c, dalloc(c, &c->d_X, (size_t)R * c->kmax));
+    HIP_TRY(c, hipMemset(c->d_X, 0, (size_t)R * c->kmax * sizeof(double)));
+    HIP_TRY(c, dalloc(c, &c->d_Q, R));
+    HIP_TRY(c, hipMemset(c->d_Q, 0, R * sizeof(double)));
+    std::vector<ScpsGroup> groups;
+    std::vector<ScpsItem> items;
+    for (int s = 0; s < (int)c->sys.size(); ++s) {
+        std::vector<int> mine;
+        for (int r = 0; r < R; ++r)
+            if (c->rep_sys[r] == s) mine.push_back(r);
+        const SysHost &h = c->sys[s];
+        for (size_t b = 0; b < mine.size(); b += SCPS_GROUP) {
+            ScpsGroup g{};
+            g.sys = s;
+            g.nrep = (int)std::min<size_t>(SCPS_GROUP, mine.size() - b);
+            for (int k = 0; k < g.nrep; ++k) g.rep[k] = mine[b + k];
+            const int gi = (int)groups.size();
+            groups.push_back(g);
+            for (int I = 0; I < h.ncb; ++I)
+                for (int J = I; J < h.ncb; ++J)
+                    items.push_back(ScpsItem{gi, tile_index(I, J, h.ncb), (I << 16) | J,
+                                             h.tile_flags[(size_t)I * h.nb + J]});
+        }
+    }
+    c->n_sitems = (int)items.size();
+    HIP_TRY(c, dalloc(c, &c->d_groups, groups.size()));
+    HIP_TRY(c, hipMemcpy(c->d_groups, groups.data(), groups.size() * sizeof(ScpsGroup), hipMemcpyHostToDevice));
+    HIP_TRY(c, dalloc(c, &c->d_sitems, items.size()));
+    if (!items.empty())
+        HIP_TRY(c, hipMemcpy(c->d_sitems, items.data(), items.size() * sizeof(ScpsItem), hipMemcpyHostToDevice));
+    return SCPS_OK;
+}
+
 scps_status init_impl(const scps_params *params, const scps_topology *topo, int32_t R, const int32_t *rsys,
                       void *stream, scps_ctx **out) {
     if (!params || !topo || !rsys || !out) return fail(SCPS_ERR_INVALID_ARG, "NULL argument");
@@ -542,41 +582,11 @@ scps_status init_impl(const scps_params *params, const scps_topology *topo, int3
     std::vector<double> neg(R, -1.0);
     HIP_TRY(c, hipMemcpy(c->d_negone, neg.data(), R * sizeof(double), hipMemcpyHostToDevice));
     if (p.bias_mode == SCPS_BIAS_SCPS) {
-        HIP_TRY(c, dalloc(c, &c->d_X, (size_t)R * c->kmax));
-        HIP_TRY(c, hipMemset(c->d_X, 0, (size_t)R * c->kmax * sizeof(double)));
-        HIP_TRY(c, dalloc(c, &c->d_Q, R));
-        HIP_TRY(c, hipMemset(c->d_Q, 0, R * sizeof(double)));
         HIP_TRY(c, dalloc(c, &c->d_coef, (size_t)R * c->kmax));
         HIP_TRY(c, dalloc(c, &c->d_csum, R));
         HIP_TRY(c, dalloc(c, &c->d_E, (size_t)eoff));
-        // replicas of a system in groups of up to SCPS_GROUP; one item per
-        // (group, contact tile pair)
-        std::vector<ScpsGroup> groups;
-        std::vector<ScpsItem> items;
-        for (int s = 0; s < (int)c->sys.size(); ++s) {
-            std::vector<int> mine;
-            for (int r = 0; r < R; ++r)
-                if (rsys[r] == s) mine.push_back(r);
-            const SysHost &h = c->sys[s];
-            for (size_t b = 0; b < mine.size(); b += SCPS_GROUP) {
-                ScpsGroup g{};
-                g.sys = s;
-                g.nrep = (int)std::min<size_t>(SCPS_GROUP, mine.size() - b);
-                for (int k = 0; k < g.nrep; ++k) g.rep[k] = mine[b + k];
-                const int gi = (int)groups.size();
-                groups.push_back(g);
-                for (int I = 0; I < h.ncb; ++I)
-                    for (int J = I; J < h.ncb; ++J)
-                        items.push_back(ScpsItem{gi, tile_index(I, J, h.ncb), (I << 16) | J,
-                                                 h.tile_flags[(size_t)I * h.nb + J]});
-            }
-        }
-        c->n_sitems = (int)items.size();
-        HIP_TRY(c, dalloc(c, &c->d_groups, groups.size()));
-        HIP_TRY(c, hipMemcpy(c->d_groups, groups.data(), groups.size() * sizeof(ScpsGroup), hipMemcpyHostToDevice));
-        HIP_TRY(c, dalloc(c, &c->d_sitems, items.size()));
-        if (!items.empty())
-            HIP_TRY(c, hipMemcpy(c->d_sitems, items.data(), items.size() * sizeof(ScpsItem), hipMemcpyHostToDevice));
+        scps_status st2 = ensure_scps_groups(c);
+        if (st2 != SCPS_OK) return st2;
     }
     *out = guard.release();
     return SCPS_OK;
@@ -727,7 +737,7 @@ scps_status step_impl(scps_ctx *c, float *x, float *v, double *cv, int64_t n_ste
             // distances to every frame (matrix cores), tube variables and
             // ratchets, effective references (matrix cores), bias + physics
             HIP_TRY(c, launch_scps_dist(c->kp, c->d_sysd, c->d_reps, c->d_groups, c->d_sitems, c->n_sitems, c->d_xs,
-                                        c->d_X, c->d_Q, c->kmax, c->stream));
+                                        c->d_X, c->d_Q, c->kmax, -1, c->stream));
             HIP_TRY(c, launch_finalize_scps(c->kp, c->d_sysd, c->d_reps, c->R, c->kmax, c->d_X, c->d_Q, cv,
                                             c->d_coef, c->d_csum, c->stream));
             HIP_TRY(c, launch_scps_eff(c->d_sysd, c->d_reps, c->d_groups, c->d_sitems, c->n_sitems, c->d_coef,
@@ -817,6 +827,38 @@ scps_status least_biased_impl(scps_ctx *c, const double *cv, const uint8_t *succ
         return fail(SCPS_ERR_INVALID_ARG, std::to_string(out[1]) + " listed replica(s) have a non-finite T");
     *index = out[0];
     if (t_min) *t_min = t;
+    return SCPS_OK;
+}
+
+// s, w (nullable) against one stack, or sigma (nullable) as the mean of
+// 1 - s over several stacks; every replica's system must be the same chain
+// and contact set as each stack's system.
+scps_status eval_tube_impl(scps_ctx *c, int32_t n_stacks, const int32_t *stacks, const float *x, double *s,
+                           double *w, double *sigma) {
+    if (!x || !stacks || n_stacks < 1) return fail(SCPS_ERR_INVALID_ARG, "x and at least one stack system are needed");
+    if (c->prm.bias_mode != SCPS_BIAS_SCPS && !(c->prm.lambda > 0))
+        return fail(SCPS_ERR_INVALID_ARG, "lambda must be > 0 to evaluate tube variables");
+    for (int k = 0; k < n_stacks; ++k) {
+        const int b = stacks[k];
+        if (b < 0 || b >= (int)c->sys.size()) return fail(SCPS_ERR_INVALID_ARG, "stack system index out of range");
+        const SysHost &hb = c->sys[b];
+        if (!hb.has_native || hb.K < 2)
+            return fail(SCPS_ERR_STATE, "a stack system has no native map or no frame stack of >= 2 maps");
+        for (int r = 0; r < c->R; ++r) {
+            const SysHost &ha = c->sys[c->rep_sys[r]];
+            if (ha.n != hb.n || ha.nc != hb.nc || ha.perm != hb.perm)
+                return fail(SCPS_ERR_SHAPE, "every replica's chain and contact set must match the stack system's");
+        }
+    }
+    scps_status st = ensure_scps_groups(c);
+    if (st != SCPS_OK) return st;
+    HIP_TRY(c, launch_gather(c->d_sysd, c->d_reps, c->R, c->n_pad_max, x, nullptr, c->d_xs, nullptr, c->stream));
+    for (int k = 0; k < n_stacks; ++k) {
+        HIP_TRY(c, launch_scps_dist(c->kp, c->d_sysd, c->d_reps, c->d_groups, c->d_sitems, c->n_sitems, c->d_xs,
+                                    c->d_X, c->d_Q, c->kmax, stacks[k], c->stream));
+        HIP_TRY(c, launch_tube_eval(c->prm.lambda, c->d_sysd, c->d_reps, c->R, c->kmax, stacks[k], c->d_X, c->d_Q,
+                                    s, w, sigma, 1.0 / n_stacks, k == 0, c->stream));
+    }
     return SCPS_OK;
 }
 
@@ -972,6 +1014,29 @@ scps_status scps_least_biased_path(scps_ctx *ctx, const double *cvstate, const u
     if (!usable(ctx, &st)) return st;
     try {
         return least_biased_impl(ctx, cvstate, success, index, t_min);
+    } catch (const std::bad_alloc &) {
+        return fail(SCPS_ERR_OOM, "host allocation failed");
+    }
+}
+
+scps_status scps_eval_tube(scps_ctx *ctx, int32_t stack_system, const float *x, double *s, double *w) {
+    scps_status st;
+    if (!usable(ctx, &st)) return st;
+    if (!s && !w) return fail(SCPS_ERR_INVALID_ARG, "s and w are both NULL");
+    try {
+        return eval_tube_impl(ctx, 1, &stack_system, x, s, w, nullptr);
+    } catch (const std::bad_alloc &) {
+        return fail(SCPS_ERR_OOM, "host allocation failed");
+    }
+}
+
+scps_status scps_eval_sigma(scps_ctx *ctx, int32_t n_stacks, const int32_t *stack_systems, const float *x,
+                            double *sigma) {
+    scps_status st;
+    if (!usable(ctx, &st)) return st;
+    if (!sigma) return fail(SCPS_ERR_INVALID_ARG, "sigma is NULL");
+    try {
+        return eval_tube_impl(ctx, n_stacks, stack_systems, x, nullptr, nullptr, sigma);
     } catch (const std::bad_alloc &) {
         return fail(SCPS_ERR_OOM, "host allocation failed");
     }

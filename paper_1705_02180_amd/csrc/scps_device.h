@@ -24,6 +24,48 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// Tube variables of one replica from its squared distances to the K <= 128
+// frames of a stack, one wavefront (lane holds frames lane and lane + 64):
+// d_k = max(Q - 2 X_k + R2_k, 0) / Z0, a = max_k (-lambda d_k),
+// e_k = exp(-lambda d_k - a), s0 = sum_k e_k, s1 = sum_k k e_k; then
+// s = 1 - (s1 / s0) / (K - 1) and w = -(a + log s0) / lambda, the discrete
+// forms of eqs (asXa), (awXa) with a log-sum-exp shift.
+struct TubeSums {
+    double e[2];
+    double a, s0, s1;
+};
+__device__ __forceinline__ TubeSums tube_sums(int lane, int K, double q, const double *xr, const double *R2,
+                                              double Z0, double lam) {
+    TubeSums t;
+    double dk[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int k = lane + 64 * h;
+        dk[h] = k < K ? fmax(q - 2.0 * xr[k] + R2[k], 0.0) / Z0 : 0.0;
+    }
+    double a = -INFINITY;
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+        if (lane + 64 * h < K) a = fmax(a, -lam * dk[h]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) a = fmax(a, __shfl_xor(a, o, 64));
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int k = lane + 64 * h;
+        t.e[h] = 0.0;
+        if (k < K) {
+            t.e[h] = exp(-lam * dk[h] - a);
+            s0 += t.e[h];
+            s1 += (double)k * t.e[h];
+        }
+    }
+    t.a = a;
+    t.s0 = wave_sum(s0);
+    t.s1 = wave_sum(s1);
+    return t;
+}
+
 // Tile pair (I, J), I <= J, of linear index t in row-major order over the
 // upper triangle of an nb x nb block grid.
 __device__ __forceinline__ void tile_decode(int t, int nb, int &I, int &J) {

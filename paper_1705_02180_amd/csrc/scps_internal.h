@@ -145,8 +145,14 @@ hipError_t launch_scatter(const SysDesc *sysd, const RepDesc *reps, int R, int n
 hipError_t launch_pairs(int mode, int nbk, const KParams &P, const SysDesc *sysd, const RepDesc *reps,
                         const TileItem *items, int n_items, const float4 *xs, double *acc, double *zpart,
                         const float *eff, const double *csum, hipStream_t st);
+// stack_sys: -1 for each group's own system's stack, else that system's
+// (same chain and contact set as every group's).
 hipError_t launch_scps_dist(const KParams &P, const SysDesc *sysd, const RepDesc *reps, const ScpsGroup *groups,
                             const ScpsItem *items, int n_items, const float4 *xs, double *X, double *Q, int kmax,
+                            int stack_sys, hipStream_t st);
+// s, w, sigma of every replica from the distances in X, Q (which it clears).
+hipError_t launch_tube_eval(double lam, const SysDesc *sysd, const RepDesc *reps, int R, int kmax, int stack_sys,
+                            double *X, double *Q, double *s, double *w, double *sigma, double weight, int first,
                             hipStream_t st);
 hipError_t launch_scps_eff(const SysDesc *sysd, const RepDesc *reps, const ScpsGroup *groups, const ScpsItem *items,
                            int n_items, const float *coef, int kmax, float *E, hipStream_t st);

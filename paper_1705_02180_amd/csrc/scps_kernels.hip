@@ -1352,33 +1352,10 @@ __global__ void k_finalize_scps(const KParams P, const SysDesc *__restrict__ sys
     const SysDesc S = sysd[reps[r].sys];
     const int K = S.K, M = K - 1;
     double *xr = X + (int64_t)r * kmax;
-    const double q = Q[r];
     const double lam = P.lambda;
-    // d_k for the (at most two) frames this lane holds
-    double dk[2];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int k = lane + 64 * h;
-        dk[h] = k < K ? fmax(q - 2.0 * xr[k] + S.R2[k], 0.0) / S.Z0 : 0.0;
-    }
-    double a = -INFINITY;
-#pragma unroll
-    for (int h = 0; h < 2; ++h)
-        if (lane + 64 * h < K) a = fmax(a, -lam * dk[h]);
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) a = fmax(a, __shfl_xor(a, o, 64));
-    double s0 = 0.0, s1 = 0.0, e[2] = {0.0, 0.0};
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int k = lane + 64 * h;
-        if (k < K) {
-            e[h] = exp(-lam * dk[h] - a);
-            s0 += e[h];
-            s1 += (double)k * e[h];
-        }
-    }
-    s0 = wave_sum(s0);
-    s1 = wave_sum(s1);
+    const TubeSums ts = tube_sums(lane, K, Q[r], xr, S.R2, S.Z0, lam);
+    const double *e = ts.e;
+    const double a = ts.a, s0 = ts.s0, s1 = ts.s1;
     const double kbar = s1 / s0;
     const double sv = 1.0 - kbar / (double)M;
     const double wv = -(a + log(s0)) / lam;

@@ -467,7 +467,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SCPS_DIST_W
                                                    const ScpsGroup *__restrict__ groups,
                                                    const ScpsItem *__restrict__ items, const int n_items,
                                                    const float4 *__restrict__ xs, double *__restrict__ X,
-                                                   double *__restrict__ Q, const int kmax) {
+                                                   double *__restrict__ Q, const int kmax, const int stack_sys) {
     __shared__ __align__(16) float4 posj[64][32];   // block J of every replica slot
     __shared__ double xl[32 * 64];                   // float64 sums X[slot][frame] of the current group
     __shared__ double ql[4][64];
@@ -504,6 +504,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SCPS_DIST_W
             const ScpsGroup *gp = groups + cur;
             nrep = gp->nrep;
             S = sysd[gp->sys];
+            if (stack_sys >= 0) {   // another system's stack (same chain and contact set)
+                S.stack_pm = sysd[stack_sys].stack_pm;
+                S.K = sysd[stack_sys].K;
+            }
             if (tid < 32) sh_rep[tid] = tid < nrep ? gp->rep[tid] : 0;
             __syncthreads();
         }
@@ -614,12 +618,47 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SCPS_EFF_WP
 
 hipError_t launch_scps_dist(const KParams &P, const SysDesc *sysd, const RepDesc *reps, const ScpsGroup *groups,
                             const ScpsItem *items, int n_items, const float4 *xs, double *X, double *Q, int kmax,
-                            hipStream_t st) {
+                            int stack_sys, hipStream_t st) {
     if (n_items == 0) return hipSuccess;
     const int cap = 256 * SCPS_DIST_WPE;   // resident workgroups: WPE per SIMD, four waves each
     const int grid = n_items < cap ? n_items : cap;
     hipLaunchKernelGGL(k_scps_dist, dim3(grid), dim3(256), 0, st, P, sysd, reps, groups, items, n_items, xs, X, Q,
-                       kmax);
+                       kmax, stack_sys);
+    return hipGetLastError();
+}
+
+// Tube variables of every replica against the frame stack of system
+// stack_sys (-1: its own system's), from the distances k_scps_dist left in X
+// and Q, which are cleared for the next pass.  s, w: nullable [R]; sigma:
+// nullable [R], set to weight (1 - s) when first, else incremented by it
+// (the mean of 1 - s over several stacks is the progress coordinate sigma).
+__global__ void k_tube_eval(double lam, const SysDesc *__restrict__ sysd, const RepDesc *__restrict__ reps,
+                            int kmax, int stack_sys, double *__restrict__ X, double *__restrict__ Q,
+                            double *__restrict__ s, double *__restrict__ w, double *__restrict__ sigma, double weight,
+                            int first) {
+    const int r = blockIdx.x, lane = threadIdx.x;
+    const SysDesc S = sysd[stack_sys >= 0 ? stack_sys : reps[r].sys];
+    const int K = S.K;
+    double *xr = X + (int64_t)r * kmax;
+    const TubeSums ts = tube_sums(lane, K, Q[r], xr, S.R2, S.Z0, lam);
+    const double sv = 1.0 - (ts.s1 / ts.s0) / (double)(K - 1);
+    const double wv = -(ts.a + log(ts.s0)) / lam;
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+        if (lane + 64 * h < K) xr[lane + 64 * h] = 0.0;
+    if (lane == 0) {
+        Q[r] = 0.0;
+        if (s) s[r] = sv;
+        if (w) w[r] = wv;
+        if (sigma) sigma[r] = (first ? 0.0 : sigma[r]) + weight * (1.0 - sv);
+    }
+}
+
+hipError_t launch_tube_eval(double lam, const SysDesc *sysd, const RepDesc *reps, int R, int kmax, int stack_sys,
+                            double *X, double *Q, double *s, double *w, double *sigma, double weight, int first,
+                            hipStream_t st) {
+    hipLaunchKernelGGL(k_tube_eval, dim3(R), dim3(64), 0, st, lam, sysd, reps, kmax, stack_sys, X, Q, s, w, sigma,
+                       weight, first);
     return hipGetLastError();
 }
 

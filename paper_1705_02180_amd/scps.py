@@ -78,6 +78,10 @@ _lib.scps_autotune.restype = C.c_int
 _lib.scps_autotune.argtypes = [_vp, _vp, _vp, _vp, _i64, _vp]
 _lib.scps_least_biased_path.restype = C.c_int
 _lib.scps_least_biased_path.argtypes = [_vp, _vp, _vp, _vp, _vp]
+_lib.scps_eval_tube.restype = C.c_int
+_lib.scps_eval_tube.argtypes = [_vp, _i32, _vp, _vp, _vp]
+_lib.scps_eval_sigma.restype = C.c_int
+_lib.scps_eval_sigma.argtypes = [_vp, _i32, _vp, _vp, _vp]
 _lib.scps_destroy.restype = None
 _lib.scps_destroy.argtypes = [_vp]
 _lib.scps_last_error.restype = C.c_char_p
@@ -85,7 +89,8 @@ _lib.scps_last_error.argtypes = []
 
 EXPORTS = ["scps_init_system", "scps_set_reference_map", "scps_step_replicas", "scps_eval_z_and_grad",
            "scps_ratchet_energy", "scps_update_reference_from_paths", "scps_set_stream", "scps_sync",
-           "scps_autotune", "scps_least_biased_path", "scps_destroy", "scps_last_error"]
+           "scps_autotune", "scps_least_biased_path", "scps_eval_tube", "scps_eval_sigma", "scps_destroy",
+           "scps_last_error"]
 
 
 def _check(status: int):
@@ -255,6 +260,19 @@ class Context:
         out = np.zeros(2, dtype=np.int32)
         _check(_lib.scps_autotune(self._ctx(), px, pv, pc, int(n_steps), out.ctypes.data_as(C.c_void_p)))
         return int(out[0]), int(out[1])
+
+    def eval_tube(self, stack_system: int, x: torch.Tensor, s: Optional[torch.Tensor] = None,
+                  w: Optional[torch.Tensor] = None):
+        """s_lambda, w_lambda of every replica against system stack_system's frame stack."""
+        _check(_lib.scps_eval_tube(self._ctx(), int(stack_system), _dev(x, torch.float32, 3 * self.sumN, "x"),
+                                   _dev(s, torch.float64, self.R, "s"), _dev(w, torch.float64, self.R, "w")))
+
+    def eval_sigma(self, stack_systems: Sequence[int], x: torch.Tensor, sigma: torch.Tensor):
+        """sigma(X) = mean over the stacks of 1 - s_lambda^k(X)."""
+        st = np.ascontiguousarray(np.asarray(stack_systems, dtype=np.int32))
+        _check(_lib.scps_eval_sigma(self._ctx(), int(st.size), st.ctypes.data_as(C.c_void_p),
+                                    _dev(x, torch.float32, 3 * self.sumN, "x"),
+                                    _dev(sigma, torch.float64, self.R, "sigma")))
 
     def least_biased_path(self, cvstate: torch.Tensor, success: Optional[Sequence[int]] = None):
         """(replica id, T) of the candidate with the smallest bias functional

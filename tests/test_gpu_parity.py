@@ -848,3 +848,76 @@ def test_lists_follow_positions_changed_between_calls(S):
     np.testing.assert_allclose(host(cv)[:, :2], host(cv2)[:, :2], rtol=1e-7)
     ctx.close()
     ref.close()
+
+
+# ---------------------------------------------------------------------------
+# tube variables against any stack, and the global coordinate sigma(X)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("mode", [0, 1], ids=["rmd_context", "scps_context"])
+def test_eval_tube_and_sigma_match_oracle(S, mode):
+    """Three initial conditions of one chain (three systems, each with the
+    stack of its own paths); every replica is measured against every stack,
+    and sigma is the mean of 1 - s over them."""
+    import torch
+    n, K, n_paths, R = 170, 11, 3, 7
+    base = dict(I._base_params(), bias_mode=mode, lam=13.5, k_s=2.5, k_w=2.5e-4)
+    rng = np.random.default_rng(4)
+    proto = I.System(n=n, contact_idx=np.arange(n, dtype=np.int32), mass=np.full(n, 12.011 * I.AMU, np.float32),
+                     charge=rng.normal(0, 0.3, n).astype(np.float32), native=I.compact_native(n, 4),
+                     start=I.persistent_start(n, 5))
+    systems, stacks, frames = [], [], []
+    for k in range(3):
+        sy = I.System(n=n, contact_idx=proto.contact_idx, mass=proto.mass, charge=proto.charge,
+                      native=proto.native, start=I.persistent_start(n, 40 + k))
+        fr = _ensemble_frames(sy, K, n_paths, 60 + k)
+        st, _ = O.update_reference(n, sy.contact_idx, fr.astype(np.float64), np.ones(n_paths, np.uint8), 7.5, 0.0)
+        systems.append(sy)
+        stacks.append(st)
+        frames.append(fr)
+    rsys = np.arange(R, dtype=np.int32) % 3
+    w = I.Workload("three_ics", dict(base), systems, rsys, 1)
+    ctx = context(S, w, params=base)
+    for k in range(3):
+        ctx.set_reference_map(k, maps=stacks[k])
+    X = np.stack([frames[(r + 1) % 3][(2 * r) % K, r % n_paths] + rng.normal(0, 0.3, (3, n))
+                  for r in range(R)]).astype(np.float32)
+    x = dev(X.ravel())
+    Z0 = O.System.from_inputs(proto, base).Z0
+    for b in range(3):
+        s = torch.zeros(R, dtype=torch.float64, device="cuda")
+        wv = torch.zeros_like(s)
+        ctx.eval_tube(b, x, s, wv)
+        ctx.sync()
+        for r in range(R):
+            so, wo, *_ = O.tube(X[r].astype(np.float64), proto.contact_idx, stacks[b], Z0, 13.5, grads=False)
+            print(f"  stack {b} replica {r}: s {host(s)[r]:.6f} (oracle {so:.6f}), w {host(wv)[r]:.6f} "
+                  f"(oracle {wo:.6f})", flush=True)
+            assert abs(host(s)[r] - so) <= 1e-5 and abs(host(wv)[r] - wo) <= 1e-5
+    for sel in ([0, 1, 2], [2], [1, 1, 0]):
+        sg = torch.zeros(R, dtype=torch.float64, device="cuda")
+        ctx.eval_sigma(sel, x, sg)
+        ctx.sync()
+        want = [O.sigma(X[r].astype(np.float64), proto.contact_idx, [stacks[b] for b in sel], [Z0] * len(sel), 13.5)
+                for r in range(R)]
+        np.testing.assert_allclose(host(sg), want, rtol=0, atol=1e-5)
+    ctx.close()
+
+
+def test_eval_tube_rejects_other_chains_and_missing_stacks(S):
+    import torch
+    base = dict(I._base_params(), lam=13.5)
+    sys_a = single_system_workload(120, np.arange(120), base, 1).systems[0]
+    sys_b = single_system_workload(121, np.arange(121), base, 1).systems[0]
+    w = I.Workload("mixed", dict(base), [sys_a, sys_b], np.array([0, 1], dtype=np.int32), 1)
+    ctx = context(S, w, params=base)
+    fr = _ensemble_frames(sys_a, 4, 2, 3)
+    ctx.update_reference_from_paths(0, dev(fr.ravel()), 2, 4, np.ones(2, dtype=np.uint8))
+    x = dev(np.concatenate([sys_a.start.ravel(), sys_b.start.ravel()]).astype(np.float32))
+    s = torch.zeros(2, dtype=torch.float64, device="cuda")
+    with pytest.raises(S.ScpsError) as e:
+        ctx.eval_tube(0, x, s)                   # replica 1 runs a 121-particle chain
+    assert e.value.status == -2
+    with pytest.raises(S.ScpsError) as e:
+        ctx.eval_tube(1, x, s)                   # system 1 has no frame stack
+    assert e.value.status == -5
+    ctx.close()

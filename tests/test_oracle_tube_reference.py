@@ -161,3 +161,49 @@ def test_reference_with_no_success_reports_zero():
     fr = _ensemble()
     out, ns = O.update_reference(25, np.arange(25), fr, np.zeros(6, dtype=np.uint8))
     assert ns == 0 and np.all(out == 0.0)
+
+
+# ---------------------------------------------------------------------------
+# global progress coordinate sigma, eq (sigma)
+# ---------------------------------------------------------------------------
+def _stacks_sharing_frame(l, n=36, K=7, seed=5):
+    """Three reference paths (three initial conditions) whose frame l is the
+    same configuration and whose other frames differ."""
+    native, frames, s = _path(n, K, seed)
+    rng = np.random.default_rng(seed)
+    cidx = s.cidx
+    stacks = []
+    for k in range(3):
+        fr = frames + rng.normal(0, 0.8, frames.shape)
+        fr[l] = frames[l]
+        stacks.append(np.array([O.contact_map(f, cidx) for f in fr]))
+    Z0 = float(np.sum(O.contact_map(native, cidx) ** 2))
+    return frames, cidx, stacks, Z0
+
+
+@pytest.mark.parametrize("l", [0, 2, 6])
+def test_sigma_reaches_l_over_M_at_a_shared_frame(l):
+    """Appendix limit for every stack at once: at the frame all paths share,
+    s^k -> 1 - l/M for large lambda, so sigma -> l/M."""
+    frames, cidx, stacks, Z0 = _stacks_sharing_frame(l)
+    M = len(frames) - 1
+    dmin = min(np.min(np.delete(O.tube(frames[l], cidx, st, Z0, 1.0, grads=False)[4], l)) for st in stacks)
+    lam = 60.0 / dmin
+    sg = O.sigma(frames[l], cidx, stacks, [Z0] * 3, lam)
+    assert abs(sg - l / M) <= len(frames) * np.exp(-60.0) + 1e-14
+
+
+def test_sigma_range_order_and_duplicates():
+    frames, cidx, stacks, Z0 = _stacks_sharing_frame(3)
+    rng = np.random.default_rng(9)
+    for _ in range(5):
+        x = frames[rng.integers(len(frames))] + rng.normal(0, 1.0, frames[0].shape)
+        sg = O.sigma(x, cidx, stacks, [Z0] * 3, 13.5)
+        assert 0.0 <= sg <= 1.0
+        assert O.sigma(x, cidx, stacks[::-1], [Z0] * 3, 13.5) == pytest.approx(sg, rel=1e-14)
+        # a stack counted twice weighs twice; one stack alone gives 1 - s
+        one = 1.0 - O.tube(x, cidx, stacks[1], Z0, 13.5, grads=False)[0]
+        assert O.sigma(x, cidx, [stacks[1]] * 2, [Z0] * 2, 13.5) == pytest.approx(one, rel=1e-14)
+        two = O.sigma(x, cidx, stacks[:2], [Z0] * 2, 13.5)
+        assert O.sigma(x, cidx, [stacks[0], stacks[1], stacks[1], stacks[0]], [Z0] * 4, 13.5) == pytest.approx(two,
+                                                                                                             rel=1e-14)
