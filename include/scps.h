@@ -276,6 +276,23 @@ scps_status scps_sync(scps_ctx *ctx, int32_t *bad_replicas, int32_t *n_bad);
 scps_status scps_autotune(scps_ctx *ctx, const float *x, const float *v, const double *cvstate,
                           int64_t n_steps, int32_t *chosen);
 
+/* Convergence measure of the iteration (the paper's Frobenius distance
+ * between iterations I and J): the recorded frames of each iteration, projected
+ * by the caller onto a plane (for Fip35, the RMSD to native of its two
+ * hairpins), mark the cells they visit on an nx x ny grid of square cells of
+ * side `cell` with lower corner (x0, y0) (cells half-open; points outside the
+ * grid are ignored); each binary occupancy matrix is scaled to unit Frobenius
+ * norm and D is the Frobenius norm of their difference, in [0, sqrt 2].  The
+ * paper deems an iteration converged when D of consecutive pairs changes by
+ * less than 10 %.
+ *   xy_a, xy_b: device float32 [n][2] (x, y per frame); n_a, n_b >= 0.
+ *   hip_stream: a hipStream_t or NULL.  D: host float64.  Needs no context;
+ *   allocates 8 nx ny + 32 bytes of device scratch for the call and blocks.
+ * Errors: INVALID_ARG (NULL arrays, bad grid, a set with no point inside the
+ * grid), OOM, HIP. */
+scps_status scps_path_distance(const float *xy_a, int64_t n_a, const float *xy_b, int64_t n_b, double x0,
+                               double y0, double cell, int32_t nx, int32_t ny, void *hip_stream, double *D);
+
 /* Free the context and everything it owns; NULL is accepted. */
 void scps_destroy(scps_ctx *ctx);
 

@@ -312,3 +312,19 @@ def sigma(x, cidx, stacks, Z0s, lam, r0: float = 7.5, r_cut: float = 0.0, min_se
     pinned tube routine with its own stack and Z0."""
     vals = [1.0 - tube(x, cidx, st, z0, lam, r0, r_cut, min_sep, grads=False)[0] for st, z0 in zip(stacks, Z0s)]
     return float(np.mean(vals))
+
+
+def path_distance(xy_a, xy_b, x0, y0, cell, nx, ny) -> float:
+    """Convergence measure between two iterations: binary occupancy of an
+    nx x ny grid of square cells (half-open, lower corner (x0, y0); points
+    outside are ignored) by each set of 2-D projections, each scaled to unit
+    Frobenius norm, and the Frobenius norm of the difference."""
+    def occupancy(xy):
+        xy = np.asarray(xy, dtype=np.float64).reshape(-1, 2)
+        u = np.floor((xy[:, 0] - x0) / cell)
+        v = np.floor((xy[:, 1] - y0) / cell)
+        keep = (u >= 0) & (u < nx) & (v >= 0) & (v < ny)
+        M = np.zeros((ny, nx))
+        M[v[keep].astype(int), u[keep].astype(int)] = 1.0
+        return M / np.linalg.norm(M)
+    return float(np.linalg.norm(occupancy(xy_a) - occupancy(xy_b)))

@@ -1,6 +1,7 @@
 // Host side of libscps: validation, ownership, work lists and launches.
 // Every entry point of include/scps.h is defined here.
 #include <math.h>
+#include <cmath>
 #include <stdio.h>
 #include <string.h>
 
@@ -1078,6 +1079,33 @@ scps_status scps_sync(scps_ctx *ctx, int32_t *bad_replicas, int32_t *n_bad) {
                                                 std::to_string(NL_CAP) + " neighbours within the list radius");
         return fail(SCPS_ERR_NONFINITE, std::to_string(nb) + " replica(s) produced non-finite coordinates");
     }
+    return SCPS_OK;
+}
+
+scps_status scps_path_distance(const float *xy_a, int64_t n_a, const float *xy_b, int64_t n_b, double x0,
+                               double y0, double cell, int32_t nx, int32_t ny, void *hip_stream, double *D) {
+    if ((!xy_a && n_a > 0) || (!xy_b && n_b > 0) || !D || n_a < 0 || n_b < 0)
+        return fail(SCPS_ERR_INVALID_ARG, "NULL point array or output, or a negative count");
+    if (!(cell > 0) || nx < 1 || ny < 1 || (int64_t)nx * ny > (1 << 24))
+        return fail(SCPS_ERR_INVALID_ARG, "cell must be > 0 and the grid 1 .. 2^24 cells");
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int m = nx * ny;
+    void *buf = nullptr;
+    hipError_t e = hipMalloc(&buf, 2 * (size_t)m * sizeof(int) + 4 * sizeof(long long));
+    if (e != hipSuccess) return fail(SCPS_ERR_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    long long *d_counts = reinterpret_cast<long long *>(buf);
+    int *d_occ = reinterpret_cast<int *>(d_counts + 4);
+    long long counts[3] = {0, 0, 0};
+    e = launch_path_occupancy(xy_a, n_a, xy_b, n_b, x0, y0, cell, nx, ny, d_occ, d_counts, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(counts, d_counts, sizeof(counts), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(buf);
+    if (e != hipSuccess) return fail(SCPS_ERR_HIP, std::string("path distance: ") + hipGetErrorString(e));
+    if (counts[0] == 0 || counts[1] == 0)
+        return fail(SCPS_ERR_INVALID_ARG, "a point set occupies no cell of the grid");
+    // unit-norm binary matrices: |A/|A| - B/|B||^2 = 2 - 2 n_ab / sqrt(n_a n_b)
+    const double c = (double)counts[2] / std::sqrt((double)counts[0] * (double)counts[1]);
+    *D = std::sqrt(std::max(0.0, 2.0 - 2.0 * c));
     return SCPS_OK;
 }
 

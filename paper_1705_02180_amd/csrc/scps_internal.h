@@ -205,6 +205,11 @@ hipError_t launch_pack_to_tiles(int n_maps, int nc, int ncb, const double *packe
                                 hipStream_t st);
 int sum_squares_scratch();   // doubles of scratch launch_sum_squares needs
 hipError_t launch_sum_squares(int64_t m, const double *v, double *part, double *out, hipStream_t st);
+// Binary occupancy of an nx x ny grid by the points of a and of b (occ:
+// scratch int [2 nx ny]) and counts[3] = {cells of a, cells of b, cells of both}.
+hipError_t launch_path_occupancy(const float *xy_a, int64_t n_a, const float *xy_b, int64_t n_b, double x0,
+                                 double y0, double cell, int nx, int ny, int *occ, long long *counts,
+                                 hipStream_t st);
 hipError_t launch_least_biased(const double *cv, const int *list, int n, int *out_i, double *out_t, hipStream_t st);
 hipError_t launch_update_reference(int n, int n_pad, int nc, int ncb, const int *perm_dev,
                                    const float *frames, int n_paths, int n_frames,

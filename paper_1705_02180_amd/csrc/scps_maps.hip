@@ -14,6 +14,8 @@
 // q^3 + q^4), q = (r/r0)^2.
 #include <math.h>
 
+#include <algorithm>
+
 #include "scps_device.h"
 #include "scps_internal.h"
 
@@ -668,6 +670,62 @@ hipError_t launch_scps_eff(const SysDesc *sysd, const RepDesc *reps, const ScpsG
     const int grid = n_items < 1024 ? n_items : 1024;
     hipLaunchKernelGGL(k_scps_eff, dim3(grid), dim3(256), 0, st, sysd, reps, groups, items, n_items, coef, kmax,
                        E);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// convergence measure between iterations
+// ---------------------------------------------------------------------------
+// Occupancy of an nx x ny grid of square cells (side cell, lower corner
+// (x0, y0), half-open) by 2-D points xy [n][2]: occ[cy * nx + cx] = 1 for
+// every cell holding a point; points outside the grid are ignored.  Cell
+// indices are taken in float64.  occ must be zero on entry.
+__global__ void k_occupancy(const float *__restrict__ xy, int64_t n, double x0, double y0, double cell, int nx, int ny,
+                            int *__restrict__ occ) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const double u = floor(((double)xy[2 * e] - x0) / cell), v = floor(((double)xy[2 * e + 1] - y0) / cell);
+        if (u >= 0.0 && u < (double)nx && v >= 0.0 && v < (double)ny) occ[(int)v * nx + (int)u] = 1;
+    }
+}
+
+// Counts of occupied cells in a, in b, and in both (one workgroup).
+__global__ __launch_bounds__(256) void k_occupancy_overlap(const int *__restrict__ a, const int *__restrict__ b,
+                                                           int m, long long *__restrict__ out) {
+    __shared__ long long sh[3][256];
+    long long na = 0, nb = 0, nab = 0;
+    for (int e = threadIdx.x; e < m; e += 256) {
+        na += a[e];
+        nb += b[e];
+        nab += a[e] & b[e];
+    }
+    sh[0][threadIdx.x] = na;
+    sh[1][threadIdx.x] = nb;
+    sh[2][threadIdx.x] = nab;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h)
+            for (int q = 0; q < 3; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) out[threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ void k_fill_int(int *__restrict__ v, int m) {
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < m; e += gridDim.x * blockDim.x) v[e] = 0;
+}
+
+hipError_t launch_path_occupancy(const float *xy_a, int64_t n_a, const float *xy_b, int64_t n_b, double x0,
+                                 double y0, double cell, int nx, int ny, int *occ, long long *counts,
+                                 hipStream_t st) {
+    const int m = nx * ny;
+    hipLaunchKernelGGL(k_fill_int, dim3((2 * m + 255) / 256), dim3(256), 0, st, occ, 2 * m);
+    if (n_a > 0)
+        hipLaunchKernelGGL(k_occupancy, dim3((unsigned)std::min<int64_t>((n_a + 255) / 256, 4096)), dim3(256), 0, st,
+                           xy_a, n_a, x0, y0, cell, nx, ny, occ);
+    if (n_b > 0)
+        hipLaunchKernelGGL(k_occupancy, dim3((unsigned)std::min<int64_t>((n_b + 255) / 256, 4096)), dim3(256), 0, st,
+                           xy_b, n_b, x0, y0, cell, nx, ny, occ + m);
+    hipLaunchKernelGGL(k_occupancy_overlap, dim3(1), dim3(256), 0, st, occ, occ + m, m, counts);
     return hipGetLastError();
 }
 

@@ -82,6 +82,8 @@ _lib.scps_eval_tube.restype = C.c_int
 _lib.scps_eval_tube.argtypes = [_vp, _i32, _vp, _vp, _vp]
 _lib.scps_eval_sigma.restype = C.c_int
 _lib.scps_eval_sigma.argtypes = [_vp, _i32, _vp, _vp, _vp]
+_lib.scps_path_distance.restype = C.c_int
+_lib.scps_path_distance.argtypes = [_vp, _i64, _vp, _i64, _d, _d, _d, _i32, _i32, _vp, C.POINTER(C.c_double)]
 _lib.scps_destroy.restype = None
 _lib.scps_destroy.argtypes = [_vp]
 _lib.scps_last_error.restype = C.c_char_p
@@ -89,7 +91,8 @@ _lib.scps_last_error.argtypes = []
 
 EXPORTS = ["scps_init_system", "scps_set_reference_map", "scps_step_replicas", "scps_eval_z_and_grad",
            "scps_ratchet_energy", "scps_update_reference_from_paths", "scps_set_stream", "scps_sync",
-           "scps_autotune", "scps_least_biased_path", "scps_eval_tube", "scps_eval_sigma", "scps_destroy",
+           "scps_autotune", "scps_least_biased_path", "scps_eval_tube", "scps_eval_sigma", "scps_path_distance",
+           "scps_destroy",
            "scps_last_error"]
 
 
@@ -355,3 +358,17 @@ class ZBias(torch.autograd.Function):
 
 def zbias(x: torch.Tensor, z_m: torch.Tensor, lib_ctx: Context):
     return ZBias.apply(x, z_m, lib_ctx)
+
+
+def path_distance(xy_a: torch.Tensor, xy_b: torch.Tensor, x0: float, y0: float, cell: float, nx: int,
+                  ny: int) -> float:
+    """Frobenius distance between the unit-norm binary occupancy matrices of
+    two sets of 2-D projections (device float32 [n][2]) on an nx x ny grid."""
+    for t, name in ((xy_a, "xy_a"), (xy_b, "xy_b")):
+        if t.dim() != 2 or t.shape[1] != 2:
+            raise ValueError(f"{name} must have shape [n, 2]")
+    D = C.c_double(0.0)
+    _check(_lib.scps_path_distance(_dev(xy_a, torch.float32, None, "xy_a"), int(xy_a.shape[0]),
+                                   _dev(xy_b, torch.float32, None, "xy_b"), int(xy_b.shape[0]), float(x0), float(y0),
+                                   float(cell), int(nx), int(ny), _stream(), C.byref(D)))
+    return float(D.value)

@@ -921,3 +921,24 @@ def test_eval_tube_rejects_other_chains_and_missing_stacks(S):
         ctx.eval_tube(1, x, s)                   # system 1 has no frame stack
     assert e.value.status == -5
     ctx.close()
+
+
+# ---------------------------------------------------------------------------
+# convergence measure between iterations
+# ---------------------------------------------------------------------------
+def test_path_distance_matches_oracle(S):
+    import torch
+    grid = dict(x0=0.0, y0=0.0, cell=0.8, nx=20, ny=20)
+    for seed in range(4):
+        rng = np.random.default_rng(90 + seed)
+        a = rng.normal(8.0, 2.5, size=(20000, 2)).astype(np.float32)
+        b = rng.normal(8.0 + 0.3 * seed, 2.0 + 0.4 * seed, size=(15000 + 1000 * seed, 2)).astype(np.float32)
+        a[:50] = 0.8 * rng.integers(0, 20, size=(50, 2))        # points on cell edges
+        want = O.path_distance(a, b, **grid)
+        got = S.path_distance(dev(a), dev(b), **grid)
+        print(f"  seed {seed}: D {got:.12f} (oracle {want:.12f})", flush=True)
+        assert got == pytest.approx(want, rel=1e-14, abs=1e-15)
+    assert S.path_distance(dev(a), dev(a), **grid) == 0.0
+    with pytest.raises(S.ScpsError) as e:                      # no point inside the grid
+        S.path_distance(dev(a), dev(np.full((3, 2), -5.0, np.float32)), **grid)
+    assert e.value.status == -1
