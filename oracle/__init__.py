@@ -46,6 +46,18 @@ class OrcParams(C.Structure):
     ]
 
 
+class FunnelParams(C.Structure):
+    _fields_ = [
+        ("A1", C.c_double), ("A2", C.c_double), ("A3", C.c_double),
+        ("s1", C.c_double), ("s2", C.c_double), ("s3", C.c_double),
+        ("w", C.c_double), ("xm", C.c_double), ("ym", C.c_double),
+        ("kT", C.c_double), ("mob_dt", C.c_double),
+        ("bias_mode", C.c_int32), ("pad", C.c_int32),
+        ("k_R", C.c_double), ("lam", C.c_double), ("k_s", C.c_double), ("k_w", C.c_double),
+        ("seed", C.c_uint64),
+    ]
+
+
 class OrcSystem(C.Structure):
     _fields_ = [
         ("n", C.c_int), ("nc", C.c_int),
@@ -91,6 +103,13 @@ def lib():
         L.orc_update_reference.argtypes = [C.c_int, C.c_int, vp, d, d, C.c_int, C.c_int, vp, vp, vp]
         L.orc_least_biased.restype = C.c_int
         L.orc_least_biased.argtypes = [C.c_int, vp, vp]
+        L.orc_funnel_force.restype = d
+        L.orc_funnel_force.argtypes = [C.POINTER(FunnelParams), d, d, vp]
+        L.orc_funnel_tube.restype = None
+        L.orc_funnel_tube.argtypes = [d, d, C.c_int, vp, d, vp, vp, vp, vp]
+        L.orc_funnel_batch.restype = C.c_int
+        L.orc_funnel_batch.argtypes = [C.POINTER(FunnelParams), C.c_int, C.c_uint32, vp, vp, i64, u64, C.c_int, vp,
+                                       C.c_int, vp, C.c_int]
         _lib = L
     return _lib
 
@@ -328,3 +347,42 @@ def path_distance(xy_a, xy_b, x0, y0, cell, nx, ny) -> float:
         M[v[keep].astype(int), u[keep].astype(int)] = 1.0
         return M / np.linalg.norm(M)
     return float(np.linalg.norm(occupancy(xy_a) - occupancy(xy_b)))
+
+
+# ---------------------------------------------------------------------------
+# toy model: the two-dimensional asymmetric funnel
+# ---------------------------------------------------------------------------
+def funnel_params(d: dict) -> FunnelParams:
+    return FunnelParams(**{k: d[k] for k in ("A1", "A2", "A3", "s1", "s2", "s3", "w", "xm", "ym", "kT", "mob_dt",
+                                             "k_R", "lam", "k_s", "k_w")},
+                        bias_mode=int(d["bias_mode"]), pad=0, seed=int(d["seed"]))
+
+
+def funnel_force(params: dict, x: float, y: float):
+    """(U, F) of eq (U) at (x, y)."""
+    F = np.empty(2)
+    U = lib().orc_funnel_force(C.byref(funnel_params(params)), float(x), float(y), _p(F))
+    return U, F
+
+
+def funnel_tube(x: float, y: float, mean_path, lam: float):
+    """s, w and their gradients for the Euclidean tube around a mean path [K][2]."""
+    mp = _f64(mean_path).reshape(-1, 2)
+    s, w = C.c_double(), C.c_double()
+    gs, gw = np.empty(2), np.empty(2)
+    lib().orc_funnel_tube(float(x), float(y), mp.shape[0], _p(mp), float(lam), C.byref(s), C.byref(w), _p(gs), _p(gw))
+    return s.value, w.value, gs, gw
+
+
+def funnel_steps(params: dict, xy, cv, n_steps: int, step0: int = 0, record_every: int = 0, mean_path=None,
+                 first_id: int = 0, threads: int = 0):
+    """Trajectories t = 0..n-1 (noise ids first_id + t): returns (xy, cv, frames or None)."""
+    xy = np.array(xy, dtype=np.float64).reshape(-1, 2)
+    cv = np.array(cv, dtype=np.float64).reshape(-1, CV_STRIDE)
+    n = xy.shape[0]
+    frames = np.empty((n_steps // record_every + 1, n, 2)) if record_every > 0 else None
+    mp = None if mean_path is None else _f64(mean_path).reshape(-1, 2)
+    K = 0 if mp is None else mp.shape[0]
+    lib().orc_funnel_batch(C.byref(funnel_params(params)), n, int(first_id), _p(xy), _p(cv), int(n_steps),
+                           int(step0), int(record_every), _p(frames), K, _p(mp), int(threads or os.cpu_count()))
+    return xy, cv, frames

@@ -525,6 +525,160 @@ int orc_least_biased(int R, const double *cv, const uint8_t *success)
     return best;
 }
 
+/* ------------------------------------------------------------------------
+ * Toy model: diffusion of one particle on the two-dimensional asymmetric
+ * funnel of eq (U) with the parameters of Table 1 (section "Diffusion in a
+ * 2-dimensional asymmetric funnel").  Overdamped Langevin steps
+ *   X += D F + sqrt(2 kT D) xi,   D = dt / (m gamma)  (the paper's gamma dt),
+ * with the noise of orc_normals (atom 0, replica = trajectory id; the first
+ * two normals drive x and y).  Bias: rMD on z = |X| (eq (FrMD) with the
+ * running minimum), or the ratchets on the tube variables of eqs (Fw),(Fs)
+ * with the Euclidean distance to the frames of the mean path,
+ *   d_k = |X - <X(t_k)>|^2,  s = 1 - (1/M) sum_k k p_k,  w = -(1/lambda) log sum_k e^{-lambda d_k}.
+ * T accumulates D |F_bias|^2 per step (the 1/(m gamma) weight of T[X]).
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    double A1, A2, A3, s1, s2, s3, w, xm, ym;
+    double kT, mob_dt;
+    int32_t bias_mode, pad;
+    double k_R, lambda, k_s, k_w;
+    uint64_t seed;
+} orc_funnel_params;
+
+/* U(x, y) of eq (U); F = -grad U. */
+double orc_funnel_force(const orc_funnel_params *p, double x, double y, double F[2])
+{
+    double r2 = x * x + y * y;
+    double a1 = r2 + p->s1 * p->s1, a2 = r2 + p->s2 * p->s2;
+    double dx = x - p->xm, dy = y - p->ym;
+    double a3 = dx * dx + dy * dy + p->s3 * p->s3;
+    double U = p->w * p->w * r2 * r2
+             - p->A1 * p->s1 * p->s1 / (a1 * a1)
+             + p->A2 * p->s2 * p->s2 / (a2 * a2)
+             - p->A3 * p->s3 * p->s3 / (a3 * a3);
+    /* dU/dx for each term: 4 w^2 r^2 x, +4 A1 s1^2 x / a1^3, -4 A2 s2^2 x / a2^3, +4 A3 s3^2 (x - xm) / a3^3 */
+    double g_r = 4.0 * p->w * p->w * r2
+               + 4.0 * p->A1 * p->s1 * p->s1 / (a1 * a1 * a1)
+               - 4.0 * p->A2 * p->s2 * p->s2 / (a2 * a2 * a2);
+    double g_3 = 4.0 * p->A3 * p->s3 * p->s3 / (a3 * a3 * a3);
+    F[0] = -(g_r * x + g_3 * dx);
+    F[1] = -(g_r * y + g_3 * dy);
+    return U;
+}
+
+/* Euclidean tube variables of (x, y) on the mean path mp [K][2]; gradients optional. */
+void orc_funnel_tube(double x, double y, int K, const double *mp, double lambda,
+                     double *s, double *w, double gs[2], double gw[2])
+{
+    int M = K - 1;
+    double *d = (double *)malloc(sizeof(double) * (size_t)K);
+    double amax = -INFINITY;
+    for (int k = 0; k < K; ++k) {
+        double ex = x - mp[2 * k], ey = y - mp[2 * k + 1];
+        d[k] = ex * ex + ey * ey;
+        if (-lambda * d[k] > amax) amax = -lambda * d[k];
+    }
+    double z = 0.0, kz = 0.0;
+    for (int k = 0; k < K; ++k) {
+        double e = exp(-lambda * d[k] - amax);
+        z += e;
+        kz += k * e;
+    }
+    double kbar = kz / z;
+    *s = 1.0 - kbar / M;
+    *w = -(amax + log(z)) / lambda;
+    if (gs || gw) {
+        double as[2] = {0.0, 0.0}, aw[2] = {0.0, 0.0};
+        for (int k = 0; k < K; ++k) {
+            double pk = exp(-lambda * d[k] - amax) / z;
+            double gd[2] = {2.0 * (x - mp[2 * k]), 2.0 * (y - mp[2 * k + 1])};
+            for (int c = 0; c < 2; ++c) {
+                as[c] += pk * (k - kbar) * gd[c];
+                aw[c] += pk * gd[c];
+            }
+        }
+        for (int c = 0; c < 2; ++c) {
+            if (gs) gs[c] = (lambda / M) * as[c];
+            if (gw) gw[c] = aw[c];
+        }
+    }
+    free(d);
+}
+
+/* One trajectory, n_steps steps from global step step0.  xy[2], cv[8] in/out
+ * (z, z_m, E_b, s, w, s_m, w_m, T as in the chain model).  frames: NULL or
+ * [n_steps / record_every + 1][2] (frame 0 = the start). */
+void orc_funnel_steps(const orc_funnel_params *p, uint32_t traj, double *xy, double *cv, int64_t n_steps,
+                      uint64_t step0, int record_every, double *frames, int K, const double *mp)
+{
+    double x = xy[0], y = xy[1];
+    double D = p->mob_dt, amp = sqrt(2.0 * p->kT * p->mob_dt);
+    for (int64_t n = 0;; ++n) {
+        if (frames && record_every > 0 && n % record_every == 0) {
+            frames[2 * (n / record_every)] = x;
+            frames[2 * (n / record_every) + 1] = y;
+        }
+        if (n == n_steps) break;
+        double F[2], Fb[2] = {0.0, 0.0};
+        orc_funnel_force(p, x, y, F);
+        if (p->bias_mode == 0) {
+            double z = sqrt(x * x + y * y);
+            double zm = fmin(cv[CV_ZM], z);
+            double dz = z - zm;
+            if (z > 0.0) {
+                Fb[0] = -p->k_R * dz * x / z;
+                Fb[1] = -p->k_R * dz * y / z;
+            }
+            cv[CV_Z] = z;
+            cv[CV_ZM] = zm;
+            cv[CV_EB] = 0.5 * p->k_R * dz * dz;
+        } else {
+            double sv, wv, gs[2], gw[2];
+            orc_funnel_tube(x, y, K, mp, p->lambda, &sv, &wv, gs, gw);
+            double sm = fmin(cv[CV_SM], sv), wm = fmin(cv[CV_WM], wv);
+            for (int c = 0; c < 2; ++c) Fb[c] = -p->k_s * (sv - sm) * gs[c] - p->k_w * (wv - wm) * gw[c];
+            cv[CV_S] = sv;
+            cv[CV_W] = wv;
+            cv[CV_SM] = sm;
+            cv[CV_WM] = wm;
+            cv[CV_EB] = 0.5 * p->k_s * (sv - sm) * (sv - sm) + 0.5 * p->k_w * (wv - wm) * (wv - wm);
+        }
+        cv[CV_T] += D * (Fb[0] * Fb[0] + Fb[1] * Fb[1]);
+        double g[3];
+        orc_normals(p->seed, 0u, traj, step0 + (uint64_t)n, g);
+        x += D * (F[0] + Fb[0]) + amp * g[0];
+        y += D * (F[1] + Fb[1]) + amp * g[1];
+    }
+    xy[0] = x;
+    xy[1] = y;
+}
+
+/* n_traj trajectories side by side (OpenMP); trajectory t uses id t0 + t.
+ * xy [n_traj][2], cv [n_traj][8], frames NULL or [n_rec][n_traj][2]. */
+int orc_funnel_batch(const orc_funnel_params *p, int n_traj, uint32_t t0, double *xy, double *cv, int64_t n_steps,
+                     uint64_t step0, int record_every, double *frames, int K, const double *mp, int threads)
+{
+    int n_rec = (frames && record_every > 0) ? (int)(n_steps / record_every) + 1 : 0;
+    int used = 1;
+#pragma omp parallel num_threads(threads > 0 ? threads : 1)
+    {
+#pragma omp single
+        used = omp_get_num_threads();
+        double *fr = n_rec ? (double *)malloc(sizeof(double) * 2 * (size_t)n_rec) : NULL;
+#pragma omp for schedule(dynamic, 4)
+        for (int t = 0; t < n_traj; ++t) {
+            orc_funnel_steps(p, t0 + (uint32_t)t, xy + 2 * t, cv + (int64_t)ORC_CV_STRIDE * t, n_steps, step0,
+                             record_every, fr, K, mp);
+            for (int f = 0; f < n_rec; ++f) {
+                frames[((int64_t)f * n_traj + t) * 2] = fr[2 * f];
+                frames[((int64_t)f * n_traj + t) * 2 + 1] = fr[2 * f + 1];
+            }
+        }
+        free(fr);
+    }
+    return used;
+}
+
 /* ---- array helpers for the test suite -------------------------------- */
 void orc_contact_array(int64_t m, const double *r2, double r0, double r_cut,
                        double *C, double *dC_dr2)

@@ -359,6 +359,20 @@ def config6(n_replicas: int = 32, n: int = 6000, r_cut: float = 12.0) -> Workloa
                     notes={"replica_starts": np.stack(starts)})
 
 
+def funnel_params(**kw) -> Dict[str, float]:
+    """The toy model's parameters: Table 1 of the paper (the asymmetric funnel
+    of eq (U)), kT = 0.3 and the overdamped step gamma dt = 0.02 (read as
+    dt / (m gamma)), rMD with k_R = 70 on z = |X|, the tube variables with
+    lambda = 0.3 and k_s = k_w = 3; start (0, 5) on the outer ring."""
+    p = dict(A1=30.0, A2=20.0, A3=6.0, s1=1.0, s2=2.0, s3=0.5, w=0.03, xm=1.5, ym=0.0,
+             kT=0.3, mob_dt=0.02, bias_mode=0, k_R=70.0, lam=0.3, k_s=3.0, k_w=3.0, seed=SEED0 + 7)
+    p.update(kw)
+    return p
+
+
+FUNNEL_START = (0.0, 5.0)
+
+
 def random_coil(n: int, seed: int) -> np.ndarray:
     """A non-native state: a persistent lattice walk, float64 [3][n]."""
     return persistent_start(n, seed)
