@@ -293,6 +293,54 @@ scps_status scps_autotune(scps_ctx *ctx, const float *x, const float *v, const d
 scps_status scps_path_distance(const float *xy_a, int64_t n_a, const float *xy_b, int64_t n_b, double x0,
                                double y0, double cell, int32_t nx, int32_t ny, void *hip_stream, double *D);
 
+/* ---------------------------------------------------------------------------
+ * Toy model (section "Diffusion in a 2-dimensional asymmetric funnel"): one
+ * particle on the funnel of eq (U),
+ *   U = w^2 r^4 - A1 s1^2/(r^2 + s1^2)^2 + A2 s2^2/(r^2 + s2^2)^2
+ *       - A3 s3^2/((x - xm)^2 + (y - ym)^2 + s3^2)^2,   r^2 = x^2 + y^2,
+ * (Table 1: A1 = 30, A2 = 20, A3 = 6, s1 = 1, s2 = 2, s3 = 0.5, w = 0.03,
+ * xm = 1.5, ym = 0), many independent trajectories at once, float64.  It runs
+ * the same protocol with the configuration itself in place of the contact
+ * map: rMD on z = |X|, the mean path over the successful trajectories, then
+ * the ratchets on the Euclidean tube variables around it.  Needs no context.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    double A1, A2, A3, s1, s2, s3, w, xm, ym;   /* eq (U), Table 1 */
+    double kT;
+    double mobility_dt;   /* dt / (m gamma): X += mobility_dt F + sqrt(2 kT mobility_dt) xi (the paper's gamma dt) */
+    int32_t bias_mode;    /* SCPS_BIAS_RMD: F_b = -k_R (z - z_m) grad z, z = |X|;
+                             SCPS_BIAS_SCPS: ratchets (Fw),(Fs) on s, w of the Euclidean tube around the mean path */
+    int32_t reserved;     /* 0 */
+    double k_R, lambda, k_s, k_w;
+    uint64_t seed;        /* Philox key; trajectory t draws from counter (0, first_id + t, step_lo, step_hi) and
+                             uses the Box-Muller pair of the first two words for (x, y) */
+} scps_funnel_params;
+
+/* Advance n_traj trajectories by n_steps overdamped steps from global step
+ * step0.  The discrete tube variables: d_k = |X - P_k|^2 over the mean-path
+ * frames P_0..P_M, s = 1 - (1/M) sum_k k p_k, w = -(1/lambda) log sum_k
+ * exp(-lambda d_k), p = softmax(-lambda d).
+ *   xy: device float64 [n_traj][2], in/out.
+ *   cvstate: device float64 [n_traj][SCPS_CV_STRIDE] as for the chains (z, z_m,
+ *            E_b, s, w, s_m, w_m, T; minima start at +INFINITY, T at 0; T adds
+ *            mobility_dt |F_b|^2 per step).
+ *   record_every > 0: frames (device float64 [n_steps/record_every + 1][n_traj][2])
+ *            receives X every record_every steps, the start first.
+ *   mean_path: device float64 [n_path_frames][2], 2 .. 64 frames (bias_mode SCPS).
+ * Asynchronous on hip_stream (a hipStream_t or NULL).  Errors: INVALID_ARG,
+ * SHAPE, HIP. */
+scps_status scps_funnel_steps(const scps_funnel_params *p, int32_t n_traj, int32_t first_id, double *xy,
+                              double *cvstate, int64_t n_steps, uint64_t step0, int32_t record_every, double *frames,
+                              int32_t n_path_frames, const double *mean_path, void *hip_stream);
+
+/* The toy model's counterpart of eq (avCij): the mean over the trajectories
+ * with success[t] != 0 of every recorded frame.
+ *   frames: device float64 [n_frames][n_traj][2]; success: host uint8 [n_traj];
+ *   mean_path: device float64 [n_frames][2].
+ * Blocks until done.  Errors: INVALID_ARG, NO_SUCCESS, OOM, HIP. */
+scps_status scps_funnel_mean_path(int32_t n_traj, int32_t n_frames, const double *frames, const uint8_t *success,
+                                  double *mean_path, void *hip_stream);
+
 /* Free the context and everything it owns; NULL is accepted. */
 void scps_destroy(scps_ctx *ctx);
 

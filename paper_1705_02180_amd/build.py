@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libscps.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("scps_kernels.hip", "scps_maps.hip", "scps_api.cpp")]
+SOURCES = [os.path.join(CSRC, f) for f in ("scps_kernels.hip", "scps_maps.hip", "scps_funnel.hip", "scps_api.cpp")]
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
 FLAGS = [

@@ -15,6 +15,7 @@
 
 #include "../../include/scps.h"
 #include "scps_internal.h"
+#include "scps_funnel.h"
 
 using namespace scps;
 
@@ -1106,6 +1107,60 @@ scps_status scps_path_distance(const float *xy_a, int64_t n_a, const float *xy_b
     // unit-norm binary matrices: |A/|A| - B/|B||^2 = 2 - 2 n_ab / sqrt(n_a n_b)
     const double c = (double)counts[2] / std::sqrt((double)counts[0] * (double)counts[1]);
     *D = std::sqrt(std::max(0.0, 2.0 - 2.0 * c));
+    return SCPS_OK;
+}
+
+scps_status scps_funnel_steps(const scps_funnel_params *p, int32_t n_traj, int32_t first_id, double *xy,
+                              double *cvstate, int64_t n_steps, uint64_t step0, int32_t record_every, double *frames,
+                              int32_t n_path_frames, const double *mean_path, void *hip_stream) {
+    if (!p || !xy || !cvstate) return fail(SCPS_ERR_INVALID_ARG, "params, xy and cvstate must not be NULL");
+    if (n_traj < 1 || first_id < 0 || n_steps < 0 || record_every < 0)
+        return fail(SCPS_ERR_INVALID_ARG, "n_traj >= 1, first_id, n_steps and record_every >= 0 are required");
+    if (record_every > 0 && !frames) return fail(SCPS_ERR_INVALID_ARG, "frames is NULL but record_every > 0");
+    if (!(p->mobility_dt > 0) || !(p->kT >= 0)) return fail(SCPS_ERR_INVALID_ARG, "mobility_dt > 0, kT >= 0");
+    if (p->bias_mode != SCPS_BIAS_RMD && p->bias_mode != SCPS_BIAS_SCPS)
+        return fail(SCPS_ERR_INVALID_ARG, "bias_mode must be 0 (rMD) or 1 (tube ratchets)");
+    if (p->bias_mode == SCPS_BIAS_SCPS) {
+        if (!mean_path) return fail(SCPS_ERR_INVALID_ARG, "the tube ratchets need a mean path");
+        if (n_path_frames < 2 || n_path_frames > FUNNEL_KMAX)
+            return fail(SCPS_ERR_SHAPE, "a mean path has 2 .. 64 frames");
+        if (!(p->lambda > 0)) return fail(SCPS_ERR_INVALID_ARG, "lambda must be > 0");
+    }
+    FunnelK k{};
+    k.A1 = p->A1; k.A2 = p->A2; k.A3 = p->A3;
+    k.s1 = p->s1; k.s2 = p->s2; k.s3 = p->s3;
+    k.w = p->w; k.xm = p->xm; k.ym = p->ym;
+    k.kT = p->kT; k.mob_dt = p->mobility_dt;
+    k.k_R = p->k_R; k.lambda = p->lambda; k.k_s = p->k_s; k.k_w = p->k_w;
+    k.seed_lo = (uint32_t)p->seed; k.seed_hi = (uint32_t)(p->seed >> 32);
+    k.bias_mode = p->bias_mode;
+    hipError_t e = launch_funnel_steps(k, n_traj, first_id, reinterpret_cast<double2 *>(xy), cvstate, n_steps, step0,
+                                       record_every, reinterpret_cast<double2 *>(frames),
+                                       p->bias_mode == SCPS_BIAS_SCPS ? n_path_frames : 0,
+                                       reinterpret_cast<const double2 *>(mean_path), (hipStream_t)hip_stream);
+    if (e != hipSuccess) return fail(SCPS_ERR_HIP, std::string("funnel steps: ") + hipGetErrorString(e));
+    return SCPS_OK;
+}
+
+scps_status scps_funnel_mean_path(int32_t n_traj, int32_t n_frames, const double *frames, const uint8_t *success,
+                                  double *mean_path, void *hip_stream) {
+    if (!frames || !success || !mean_path) return fail(SCPS_ERR_INVALID_ARG, "NULL argument");
+    if (n_traj < 1 || n_frames < 1) return fail(SCPS_ERR_INVALID_ARG, "n_traj and n_frames must be >= 1");
+    std::vector<int> list;
+    for (int t = 0; t < n_traj; ++t)
+        if (success[t]) list.push_back(t);
+    if (list.empty()) return fail(SCPS_ERR_NO_SUCCESS, "no successful trajectory");
+    hipStream_t st = (hipStream_t)hip_stream;
+    void *d_list = nullptr;
+    hipError_t e = hipMalloc(&d_list, list.size() * sizeof(int));
+    if (e != hipSuccess) return fail(SCPS_ERR_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    e = hipMemcpyAsync(d_list, list.data(), list.size() * sizeof(int), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = launch_funnel_mean(n_traj, n_frames, reinterpret_cast<const double2 *>(frames), (const int *)d_list,
+                               (int)list.size(), reinterpret_cast<double2 *>(mean_path), st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(d_list);
+    if (e != hipSuccess) return fail(SCPS_ERR_HIP, std::string("funnel mean path: ") + hipGetErrorString(e));
     return SCPS_OK;
 }
 

@@ -17,6 +17,26 @@ __device__ __forceinline__ float pair_r2(const float4 &pi, const float4 &pj, flo
     return fmaf(dx, dx, fmaf(dy, dy, dz * dz));
 }
 
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds, Weyl key schedule.
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint32_t a = c[0], b = c[2];
+        const uint32_t hi0 = __umulhi(0xD2511F53u, a), lo0 = 0xD2511F53u * a;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, b), lo1 = 0xCD9E8D57u * b;
+        c[0] = hi1 ^ c[1] ^ k0;
+        c[1] = lo1;
+        c[2] = hi0 ^ c[3] ^ k1;
+        c[3] = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+__device__ __forceinline__ float unit_open_f(uint32_t w) {
+    return (float)(2u * (w >> 9) + 1u) * 0x1p-24f;
+}
+
 // Sum over the 64 lanes of a wavefront, returned to every lane.
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

@@ -53,26 +53,6 @@ __device__ __forceinline__ float ldg(const float *p, int64_t i) {
     return ((gfloat *)p)[i];
 }
 
-// Philox4x32-10 (Salmon et al., SC'11): ten rounds, Weyl key schedule.
-__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
-#pragma unroll
-    for (int round = 0; round < 10; ++round) {
-        const uint32_t a = c[0], b = c[2];
-        const uint32_t hi0 = __umulhi(0xD2511F53u, a), lo0 = 0xD2511F53u * a;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, b), lo1 = 0xCD9E8D57u * b;
-        c[0] = hi1 ^ c[1] ^ k0;
-        c[1] = lo1;
-        c[2] = hi0 ^ c[3] ^ k1;
-        c[3] = lo0;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-}
-
-__device__ __forceinline__ float unit_open_f(uint32_t w) {
-    return (float)(2u * (w >> 9) + 1u) * 0x1p-24f;
-}
-
 // Three standard normals for (particle, replica, step).  The uniforms are odd
 // multiples of 2^-24, exact in float32; Box-Muller runs in float32 (logf,
 // sqrtf, sincospif: within a few ulp of the float64 transform).

@@ -84,6 +84,10 @@ _lib.scps_eval_sigma.restype = C.c_int
 _lib.scps_eval_sigma.argtypes = [_vp, _i32, _vp, _vp, _vp]
 _lib.scps_path_distance.restype = C.c_int
 _lib.scps_path_distance.argtypes = [_vp, _i64, _vp, _i64, _d, _d, _d, _i32, _i32, _vp, C.POINTER(C.c_double)]
+_lib.scps_funnel_steps.restype = C.c_int
+_lib.scps_funnel_steps.argtypes = [C.c_void_p, _i32, _i32, _vp, _vp, _i64, _u64, _i32, _vp, _i32, _vp, _vp]
+_lib.scps_funnel_mean_path.restype = C.c_int
+_lib.scps_funnel_mean_path.argtypes = [_i32, _i32, _vp, _vp, _vp, _vp]
 _lib.scps_destroy.restype = None
 _lib.scps_destroy.argtypes = [_vp]
 _lib.scps_last_error.restype = C.c_char_p
@@ -92,7 +96,7 @@ _lib.scps_last_error.argtypes = []
 EXPORTS = ["scps_init_system", "scps_set_reference_map", "scps_step_replicas", "scps_eval_z_and_grad",
            "scps_ratchet_energy", "scps_update_reference_from_paths", "scps_set_stream", "scps_sync",
            "scps_autotune", "scps_least_biased_path", "scps_eval_tube", "scps_eval_sigma", "scps_path_distance",
-           "scps_destroy",
+           "scps_funnel_steps", "scps_funnel_mean_path", "scps_destroy",
            "scps_last_error"]
 
 
@@ -372,3 +376,49 @@ def path_distance(xy_a: torch.Tensor, xy_b: torch.Tensor, x0: float, y0: float, 
                                    _dev(xy_b, torch.float32, None, "xy_b"), int(xy_b.shape[0]), float(x0), float(y0),
                                    float(cell), int(nx), int(ny), _stream(), C.byref(D)))
     return float(D.value)
+
+
+class FunnelParams(C.Structure):
+    _fields_ = [
+        ("A1", C.c_double), ("A2", C.c_double), ("A3", C.c_double),
+        ("s1", C.c_double), ("s2", C.c_double), ("s3", C.c_double),
+        ("w", C.c_double), ("xm", C.c_double), ("ym", C.c_double),
+        ("kT", C.c_double), ("mobility_dt", C.c_double),
+        ("bias_mode", C.c_int32), ("reserved", C.c_int32),
+        ("k_R", C.c_double), ("lam", C.c_double), ("k_s", C.c_double), ("k_w", C.c_double),
+        ("seed", C.c_uint64),
+    ]
+
+
+def funnel_steps(params: dict, xy: torch.Tensor, cvstate: torch.Tensor, n_steps: int, step0: int = 0,
+                 record_every: int = 0, frames: Optional[torch.Tensor] = None,
+                 mean_path: Optional[torch.Tensor] = None, first_id: int = 0):
+    """Toy model: advance the trajectories xy [n][2] (float64) in place."""
+    n = int(xy.shape[0])
+    fp = FunnelParams(A1=params["A1"], A2=params["A2"], A3=params["A3"], s1=params["s1"], s2=params["s2"],
+                      s3=params["s3"], w=params["w"], xm=params["xm"], ym=params["ym"], kT=params["kT"],
+                      mobility_dt=params["mob_dt"], bias_mode=int(params["bias_mode"]), reserved=0,
+                      k_R=params["k_R"], lam=params["lam"], k_s=params["k_s"], k_w=params["k_w"],
+                      seed=int(params["seed"]))
+    K = 0 if mean_path is None else int(mean_path.shape[0])
+    pf = None
+    if record_every > 0:
+        pf = _dev(frames, torch.float64, (n_steps // record_every + 1) * n * 2, "frames")
+    _check(_lib.scps_funnel_steps(C.byref(fp), n, int(first_id), _dev(xy, torch.float64, 2 * n, "xy"),
+                                  _dev(cvstate, torch.float64, n * CV_STRIDE, "cvstate"), int(n_steps), int(step0),
+                                  int(record_every), pf, K,
+                                  None if mean_path is None else _dev(mean_path, torch.float64, 2 * K, "mean_path"),
+                                  _stream()))
+
+
+def funnel_mean_path(frames: torch.Tensor, success: Sequence[int]) -> torch.Tensor:
+    """Mean over the successful trajectories of every frame of frames [F][n][2]."""
+    n_frames, n = int(frames.shape[0]), int(frames.shape[1])
+    succ = np.ascontiguousarray(np.asarray(success, dtype=np.uint8))
+    if succ.size != n:
+        raise ValueError("success must have one entry per trajectory")
+    out = torch.empty((n_frames, 2), dtype=torch.float64, device=frames.device)
+    _check(_lib.scps_funnel_mean_path(n, n_frames, _dev(frames, torch.float64, n_frames * n * 2, "frames"),
+                                      succ.ctypes.data_as(C.c_void_p), _dev(out, torch.float64, 2 * n_frames, "out"),
+                                      _stream()))
+    return out
