@@ -15,6 +15,9 @@ Other workloads (--workload), each printed as its own JSON line:
   cutoff6000    the same chain under rMD with contact and nonbonded cutoffs of
                 12 A from compact states: neighbour lists against the
                 all-tiles path
+  funnel        the toy model: 262,144 trajectories on the asymmetric funnel,
+                rMD from (0, 5), the mean path of the successful ones, then
+                the tube-ratchet iteration (the timed line)
 
 Printed: replica-steps/s (value), contact-pair evals/s, the plain
 one-replica-per-launch form (headline workload), the roofline of the timed
@@ -46,6 +49,10 @@ def flops_scps_contact(K):
     return 18 + 3 * K + 43 + 2 * K
 
 
+FLOPS_FUNNEL = 60       # toy model step: force of eq (U) ~40, rMD bias ~10, update and noise transform ~10
+FLOPS_FUNNEL_FRAME = 37  # per mean-path frame and step: three passes over the frames (largest exponent,
+                         # weights, gradients of s and w), float64
+
 PEAK_FP32 = 157.3e12    # MI355X vector FP32, 256 CUs x 2.4 GHz
 PEAK_FP64 = 78.6e12
 
@@ -54,7 +61,7 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default="chain560",
-                    choices=["chain560", "uneven512", "autograd3000", "scps6000", "cutoff6000"])
+                    choices=["chain560", "uneven512", "autograd3000", "scps6000", "cutoff6000", "funnel"])
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--block", type=int, default=100, help="Langevin steps per benchmark step")
@@ -519,6 +526,66 @@ def bench_cutoff6000(args, torch, I, scps):
     return out
 
 
+# ---------------------------------------------------------------------------
+# the toy model: trajectories on the asymmetric funnel
+# ---------------------------------------------------------------------------
+def bench_funnel(args, torch, I, scps):
+    import numpy as np
+    n = args.replicas or 262144          # 4 wavefronts per SIMD; one thread per trajectory
+    p = I.funnel_params()
+    n_rmd, rec = 2000, 40
+    K = n_rmd // rec + 1
+
+    def fresh():
+        cv = np.zeros((n, 8))
+        cv[:, 1] = cv[:, 5] = cv[:, 6] = np.inf
+        return (torch.as_tensor(np.tile(I.FUNNEL_START, (n, 1)), dtype=torch.float64, device="cuda"),
+                torch.as_tensor(cv, device="cuda"))
+    # rMD ensemble (recorded), its mean path, then the tube-ratchet iteration
+    xy, cv = fresh()
+    frames = torch.zeros((K, n, 2), dtype=torch.float64, device="cuda")
+    wall_r, per_r = timed_calls(torch, lambda _: scps.funnel_steps(p, xy, cv, n_rmd, record_every=rec,
+                                                                   frames=frames), 1)
+    succ = (torch.linalg.norm(xy, dim=1) < 1.0).cpu().numpy().astype(np.uint8)
+    mp = scps.funnel_mean_path(frames, succ)
+    ps = dict(p, bias_mode=1)
+    xy, cv = fresh()
+    step = [0]
+
+    def call(_):
+        scps.funnel_steps(ps, xy, cv, args.block, step0=step[0], mean_path=mp)
+        step[0] += args.block
+
+    for _ in range(args.warmup):
+        call(0)
+    torch.cuda.synchronize()
+    wall, per_ms = timed_calls(torch, call, args.steps)
+    value = n * args.block * args.steps / wall
+    out = base_line(args, value, "trajectory-steps/s", wall, args.steps, {
+        "workload": f"funnel_toy_model: {n} trajectories of one particle on the asymmetric funnel (Table 1), "
+                    f"kT = 0.3, gamma dt = 0.02; rMD (k_R = 70 on |X|) from (0, 5) for {n_rmd} steps, mean path of "
+                    f"{K} frames over the {int(succ.sum())} that reached |X| < 1, then the tube ratchets "
+                    f"(lambda = 0.3, k_s = k_w = 3), {args.block} steps per benchmark step",
+        "trajectories": n, "block": args.block, "path_frames": K}, dtype="f64")
+    out["rmd"] = {"value": n * n_rmd / wall_r, "unit": "trajectory-steps/s", "reached_bottom": float(succ.mean())}
+    out["reached_bottom_after_iteration"] = float((torch.linalg.norm(xy, dim=1) < 1.0).float().mean())
+    out["roofline"] = roofline(n * args.block * (FLOPS_FUNNEL + K * FLOPS_FUNNEL_FRAME), per_ms,
+                               "k_funnel_steps<1>", peak=PEAK_FP64)
+    if not args.no_cpu:
+        import oracle as O
+        m, st = 65536, max(10, 15 * args.cpu_steps)     # about 10 s on 16 host cores
+        cv0 = np.zeros((m, 8))
+        cv0[:, 5] = cv0[:, 6] = np.inf
+        t0 = time.perf_counter()
+        O.funnel_steps(ps, np.tile(I.FUNNEL_START, (m, 1)), cv0, st, mean_path=mp.cpu().numpy(),
+                       threads=host_threads())
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": m * st / dt, "unit": "trajectory-steps/s", "cores": host_threads(),
+                               "kind": "oracle", "sample": f"{m} trajectories x {st} tube-ratchet steps of the same "
+                                                          f"workload, FP64, OpenMP over trajectories ({dt:.1f} s)"}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -535,7 +602,7 @@ def main():
 
     torch.cuda.set_device(0)
     fn = {"chain560": bench_chain560, "uneven512": bench_uneven512, "autograd3000": bench_autograd3000,
-          "scps6000": bench_scps6000, "cutoff6000": bench_cutoff6000}[args.workload]
+          "scps6000": bench_scps6000, "cutoff6000": bench_cutoff6000, "funnel": bench_funnel}[args.workload]
     out = fn(args, torch, I, scps)
     print(json.dumps(out), flush=True)
 
