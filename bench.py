@@ -50,8 +50,9 @@ def flops_scps_contact(K):
 
 
 FLOPS_FUNNEL = 60       # toy model step: force of eq (U) ~40, rMD bias ~10, update and noise transform ~10
-FLOPS_FUNNEL_FRAME = 37  # per mean-path frame and step: three passes over the frames (largest exponent,
-                         # weights, gradients of s and w), float64
+FLOPS_FUNNEL_FRAME = 32  # per mean-path frame and step, float64: the largest exponent (distance 5, scale and
+                         # max 2), then the weight (distance 5, shift 2, exp 1), its sums (3) and the four
+                         # gradient sums (14)
 
 PEAK_FP32 = 157.3e12    # MI355X vector FP32, 256 CUs x 2.4 GHz
 PEAK_FP64 = 78.6e12

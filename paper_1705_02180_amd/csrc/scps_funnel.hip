@@ -10,7 +10,8 @@
 // Bias: the rMD ratchet on z = |X| (eq (FrMD)), or the ratchets on the tube
 // variables of eqs (Fw),(Fs) with the Euclidean distance to the frames of
 // the mean path (d_k = |X - <X(t_k)>|^2), the toy model's stand-in for the
-// contact map.  T accumulates D |F_bias|^2 per step.
+// contact map, one exponential per frame and step.  T accumulates
+// D |F_bias|^2 per step.
 #include <math.h>
 
 #include "scps_device.h"
@@ -70,33 +71,30 @@ __global__ __launch_bounds__(256) void k_funnel_steps(const FunnelK P, int n_tra
             }
             eb = 0.5 * P.k_R * dz * dz;
         } else {
-            // tube variables: the largest exponent, the weights, then the gradients
+            // tube variables: the largest exponent, then the weights with the sums
+            // sum_k e_k grad d_k and sum_k k e_k grad d_k, from which
+            // grad s = (lambda / M) sum_k p_k (k - kbar) grad d_k and grad w = sum_k p_k grad d_k
             double a = -INFINITY;
             for (int k = 0; k < K; ++k) {
                 const double ex = x - path[k].x, ey = y - path[k].y;
                 a = fmax(a, -P.lambda * (ex * ex + ey * ey));
             }
-            double s0 = 0.0, s1 = 0.0;
+            double s0 = 0.0, s1 = 0.0, ax = 0.0, ay = 0.0, bx_ = 0.0, by_ = 0.0;
             for (int k = 0; k < K; ++k) {
                 const double ex = x - path[k].x, ey = y - path[k].y;
                 const double e = exp(-P.lambda * (ex * ex + ey * ey) - a);
                 s0 += e;
                 s1 += k * e;
+                ax += e * 2.0 * ex;
+                ay += e * 2.0 * ey;
+                bx_ += k * e * 2.0 * ex;
+                by_ += k * e * 2.0 * ey;
             }
             const double kbar = s1 / s0;
             sv = 1.0 - kbar / M;
             wv = -(a + log(s0)) / P.lambda;
-            double gsx = 0.0, gsy = 0.0, gwx = 0.0, gwy = 0.0;
-            for (int k = 0; k < K; ++k) {
-                const double ex = x - path[k].x, ey = y - path[k].y;
-                const double pk = exp(-P.lambda * (ex * ex + ey * ey) - a) / s0;
-                gsx += pk * (k - kbar) * 2.0 * ex;
-                gsy += pk * (k - kbar) * 2.0 * ey;
-                gwx += pk * 2.0 * ex;
-                gwy += pk * 2.0 * ey;
-            }
-            gsx *= P.lambda / M;
-            gsy *= P.lambda / M;
+            const double gsx = (P.lambda / M) * (bx_ - kbar * ax) / s0, gsy = (P.lambda / M) * (by_ - kbar * ay) / s0;
+            const double gwx = ax / s0, gwy = ay / s0;
             sm = fmin(sm, sv);
             wm = fmin(wm, wv);
             const double ds = sv - sm, dw = wv - wm;
