@@ -162,7 +162,7 @@ def _gpu_forces_one_step(S, w, p, X, cv0, exec_mode):
     import torch
     R = w.n_replicas
     ctx = context(S, w, params=p, exec_mode=exec_mode)
-    x = dev(X.ravel())
+    x = dev(np.concatenate([np.ravel(a) for a in X]))        # replicas may have different lengths
     v = torch.zeros_like(x)
     cv = dev(cv0, "f64")
     ctx.step_replicas(x, v, cv, 1, step0=3)
@@ -942,3 +942,54 @@ def test_path_distance_matches_oracle(S):
     with pytest.raises(S.ScpsError) as e:                      # no point inside the grid
         S.path_distance(dev(a), dev(np.full((3, 2), -5.0, np.float32)), **grid)
     assert e.value.status == -1
+
+
+def test_lists_with_uneven_systems_and_partial_contact_sets(S):
+    """Lists over replicas of two chains of different lengths (ragged blocks),
+    one with every third particle in the contact set and min_seq_sep 4: one
+    step against the oracle, and 20 noisy steps against the all-tiles path."""
+    import torch
+    base = dict(I._base_params(), r_cut_contact=11.0, r_cut_nb=9.5, min_seq_sep=4)
+    rng = np.random.default_rng(8)
+    systems = []
+    for n, kind, seed in ((301, "all", 21), (1100, "every3", 22)):
+        systems.append(I.System(n=n, contact_idx=np.asarray(_cidx(n, kind), dtype=np.int32),
+                                mass=np.full(n, 12.011 * I.AMU, dtype=np.float32),
+                                charge=rng.normal(0, 0.3, n).astype(np.float32), native=I.compact_native(n, seed),
+                                start=I.persistent_start(n, seed + 1)))
+    rsys = np.array([0, 1, 1, 0, 1], dtype=np.int32)
+    R = len(rsys)
+    X = [_clean_starts(systems[s], 1, 30 + r)[0] for r, s in enumerate(rsys)]
+    p = _force_readback_params(base, k_R=1e-2)
+    w = I.Workload("two_chains_cut", dict(p), systems, rsys, 1)
+    osys = [O.System.from_inputs(sy, p) for sy in systems]
+    cv0 = np.zeros((R, 8))
+    cv0[:, 1] = np.inf
+    for r in range(1, R):
+        o = osys[rsys[r]]
+        cv0[r, 1] = 0.8 * O.z_grad(X[r].astype(np.float64), o.cidx, o.native, r_cut=11.0, min_sep=4, grad=False)
+    Fg, cvg = _gpu_forces_one_step(S, w, p, X, cv0, 1)
+    for r in range(R):
+        F, _, cvr = O.total_force(p, osys[rsys[r]], X[r].astype(np.float64), cv0[r])
+        err = normwise(Fg[r], F)
+        print(f"  replica {r} (N = {systems[rsys[r]].n}): force err {err:.2e}", flush=True)
+        assert err <= TOL, (r, err)
+        assert abs(cvg[r, 0] - cvr[0]) <= TOL * max(cvr[0], 1e-3 * osys[rsys[r]].Z0)
+    # noisy steps: lists against all tiles
+    wn = I.Workload("two_chains_cut", dict(base, k_R=5e-3), systems, rsys, 1)
+    xflat = np.concatenate([x.ravel() for x in X])
+    res = []
+    for mode in (1, 2):
+        ctx = context(S, wn, params=dict(base, k_R=5e-3), exec_mode=mode)
+        x = dev(xflat)
+        v = torch.zeros_like(x)
+        cv = dev(wn.initial_cvstate(), "f64")
+        ctx.step_replicas(x, v, cv, 20)
+        ctx.sync()
+        res.append((host(x), host(cv)))
+        ctx.close()
+    disp = np.abs(res[1][0] - xflat).max()
+    d = np.abs(res[0][0] - res[1][0]).max()
+    print(f"  20 steps: lists vs all tiles {d:.2e} (displacement {disp:.2e})", flush=True)
+    assert d <= 1e-4 * disp + 1e-4
+    np.testing.assert_allclose(res[0][1][:, :2], res[1][1][:, :2], rtol=1e-7)
