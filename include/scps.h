@@ -195,6 +195,14 @@ scps_status scps_ratchet_energy(scps_ctx *ctx, const double *z, const double *z_
                                 double *E_b, const double *gz, const double *gE,
                                 double *coef);
 
+/* out = coef[r] * in over the coordinates of every replica r (x layout; out
+ * may equal in): with in = dz/dx kept from scps_eval_z_and_grad and coef from
+ * scps_ratchet_energy, this is the gradient of gz*z + gE*E_b without a second
+ * pass over the pairs (the backward of the differentiable z wrapper).
+ *   in, out: device float32 [3 * sum N]; coef: device float64 [R].
+ * Asynchronous.  Errors: INVALID_ARG, HIP. */
+scps_status scps_scale_by_replica(scps_ctx *ctx, const float *in, const double *coef, float *out);
+
 /* Path-ensemble mean contact map, eq (avCij): for every recorded frame k,
  * <C(t_k)>_p = (1/|S|) sum over successful paths p of C(X_p(t_k)), summed in
  * float64, and install the result as the system's SCPS frame stack

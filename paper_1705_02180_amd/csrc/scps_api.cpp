@@ -1021,6 +1021,15 @@ scps_status scps_least_biased_path(scps_ctx *ctx, const double *cvstate, const u
     }
 }
 
+scps_status scps_scale_by_replica(scps_ctx *ctx, const float *in, const double *coef, float *out) {
+    scps_status st;
+    if (!usable(ctx, &st)) return st;
+    if (!in || !coef || !out) return fail(SCPS_ERR_INVALID_ARG, "in, coef and out must not be NULL");
+    HIP_TRY(ctx, launch_scale_by_replica(ctx->d_sysd, ctx->d_reps, ctx->R, ctx->n_pad_max, in, coef, out,
+                                         ctx->stream));
+    return SCPS_OK;
+}
+
 scps_status scps_eval_tube(scps_ctx *ctx, int32_t stack_system, const float *x, double *s, double *w) {
     scps_status st;
     if (!usable(ctx, &st)) return st;

@@ -210,6 +210,8 @@ hipError_t launch_sum_squares(int64_t m, const double *v, double *part, double *
 hipError_t launch_path_occupancy(const float *xy_a, int64_t n_a, const float *xy_b, int64_t n_b, double x0,
                                  double y0, double cell, int nx, int ny, int *occ, long long *counts,
                                  hipStream_t st);
+hipError_t launch_scale_by_replica(const SysDesc *sysd, const RepDesc *reps, int R, int n_pad_max, const float *in,
+                                   const double *coef, float *out, hipStream_t st);
 hipError_t launch_least_biased(const double *cv, const int *list, int n, int *out_i, double *out_t, hipStream_t st);
 hipError_t launch_update_reference(int n, int n_pad, int nc, int ncb, const int *perm_dev,
                                    const float *frames, int n_paths, int n_frames,

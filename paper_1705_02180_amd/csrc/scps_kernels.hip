@@ -1479,6 +1479,26 @@ hipError_t launch_eval_out(const SysDesc *sysd, const RepDesc *reps, int R, int 
     return hipGetLastError();
 }
 
+// out = coef[r] * in over replica r's coordinates (x layout), for every
+// replica: the backward of the z wrapper from a kept dz/dx.
+__global__ void k_scale_by_replica(const SysDesc *__restrict__ sysd, const RepDesc *__restrict__ reps,
+                                   const float *__restrict__ in, const double *__restrict__ coef,
+                                   float *__restrict__ out) {
+    const int r = blockIdx.y;
+    const RepDesc rd = reps[r];
+    const int n3 = 3 * sysd[rd.sys].n;
+    const double c = coef[r];
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n3; e += gridDim.x * blockDim.x)
+        out[3 * rd.off + e] = (float)(c * (double)in[3 * rd.off + e]);
+}
+
+hipError_t launch_scale_by_replica(const SysDesc *sysd, const RepDesc *reps, int R, int n_pad_max, const float *in,
+                                   const double *coef, float *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_scale_by_replica, dim3((3 * n_pad_max + 255) / 256, R), dim3(256), 0, st, sysd, reps, in,
+                       coef, out);
+    return hipGetLastError();
+}
+
 __global__ void k_ratchet_energy(int R, double k_R, const double *__restrict__ z, const double *__restrict__ zm,
                                  double *__restrict__ Eb, const double *__restrict__ gz,
                                  const double *__restrict__ gE, double *__restrict__ coef) {

@@ -88,6 +88,8 @@ _lib.scps_funnel_steps.restype = C.c_int
 _lib.scps_funnel_steps.argtypes = [C.c_void_p, _i32, _i32, _vp, _vp, _i64, _u64, _i32, _vp, _i32, _vp, _vp]
 _lib.scps_funnel_mean_path.restype = C.c_int
 _lib.scps_funnel_mean_path.argtypes = [_i32, _i32, _vp, _vp, _vp, _vp]
+_lib.scps_scale_by_replica.restype = C.c_int
+_lib.scps_scale_by_replica.argtypes = [_vp, _vp, _vp, _vp]
 _lib.scps_destroy.restype = None
 _lib.scps_destroy.argtypes = [_vp]
 _lib.scps_last_error.restype = C.c_char_p
@@ -96,7 +98,7 @@ _lib.scps_last_error.argtypes = []
 EXPORTS = ["scps_init_system", "scps_set_reference_map", "scps_step_replicas", "scps_eval_z_and_grad",
            "scps_ratchet_energy", "scps_update_reference_from_paths", "scps_set_stream", "scps_sync",
            "scps_autotune", "scps_least_biased_path", "scps_eval_tube", "scps_eval_sigma", "scps_path_distance",
-           "scps_funnel_steps", "scps_funnel_mean_path", "scps_destroy",
+           "scps_funnel_steps", "scps_funnel_mean_path", "scps_scale_by_replica", "scps_destroy",
            "scps_last_error"]
 
 
@@ -258,6 +260,12 @@ class Context:
             None if out is None else out.ctypes.data_as(C.c_void_p)))
         return out
 
+    def scale_by_replica(self, inp: torch.Tensor, coef: torch.Tensor, out: torch.Tensor):
+        n3 = 3 * self.sumN
+        _check(_lib.scps_scale_by_replica(self._ctx(), _dev(inp, torch.float32, n3, "in"),
+                                          _dev(coef, torch.float64, self.R, "coef"),
+                                          _dev(out, torch.float32, n3, "out")))
+
     def autotune(self, x: torch.Tensor, v: Optional[torch.Tensor], cvstate: torch.Tensor, n_steps: int):
         """Time the launch configurations on copies of the state and keep the
         fastest; returns (path, threads): path 0 persistent, 1 per-step."""
@@ -332,31 +340,33 @@ def update_reference_from_paths(ctx: Context, system, frames, n_paths, n_frames,
 
 class ZBias(torch.autograd.Function):
     """z(X) and the rMD bias energy E_b = 1/2 k_R (z - z_m)^2 theta(z - z_m) as a
-    differentiable function of the coordinates.  forward evaluates z only;
-    backward recomputes every C_ij in the pair-gradient kernel (no stored map)
-    and returns (g_z + g_E k_R (z - z_m) theta) dz/dx."""
+    differentiable function of the coordinates.  When x needs a gradient,
+    forward runs the z + dz/dx pair pass once and keeps dz/dx (O(N) per
+    replica; no map of the current contacts is stored); backward scales it by
+    g_z + g_E k_R (z - z_m) theta per replica.  Otherwise forward evaluates z
+    alone."""
 
     @staticmethod
     def forward(ctx_, x: torch.Tensor, z_m: torch.Tensor, lib_ctx: Context):
         z = torch.empty(lib_ctx.R, dtype=torch.float64, device=x.device)
-        lib_ctx.eval_z_and_grad(x, z)
+        dz = torch.empty_like(x) if ctx_.needs_input_grad[0] else None
+        lib_ctx.eval_z_and_grad(x, z, dz)
         Eb = torch.empty_like(z)
         lib_ctx.ratchet_energy(z, z_m, Eb)
-        ctx_.save_for_backward(x, z, z_m)
+        ctx_.save_for_backward(z, z_m, dz)
         ctx_.lib_ctx = lib_ctx
         return z, Eb
 
     @staticmethod
     def backward(ctx_, gz: torch.Tensor, gE: torch.Tensor):
-        x, z, z_m = ctx_.saved_tensors
+        z, z_m, dz = ctx_.saved_tensors
         lib = ctx_.lib_ctx
         coef = torch.empty_like(z)
         gz = None if gz is None else gz.contiguous().to(torch.float64)
         gE = None if gE is None else gE.contiguous().to(torch.float64)
         lib.ratchet_energy(z, z_m, None, gz, gE, coef)
-        grad = torch.empty_like(x)
-        ztmp = torch.empty_like(z)
-        lib.eval_z_and_grad(x, ztmp, grad, coef)
+        grad = torch.empty_like(dz)
+        lib.scale_by_replica(dz, coef, grad)
         return grad, None, None
 
 

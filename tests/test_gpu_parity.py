@@ -535,6 +535,44 @@ def test_zbias_autograd_matches_oracle_gradient(S):
                 assert abs(G[r, c, i] - want) <= 2e-4 * np.abs(G[r]).max()
 
 
+def test_zbias_partial_gradients_and_no_grad_forward(S):
+    """The kept dz/dx serves any output weights: E_b alone, z alone, and a
+    forward without a gradient gives the same z."""
+    import torch
+    base = dict(I._base_params(), k_R=3e-3)
+    w = single_system_workload(260, np.arange(260), base, 4)
+    sy = w.systems[0]
+    ctx = context(S, w)
+    X = states(sy, 4, 17)
+    osys = O.System.from_inputs(sy, base)
+    zr = [O.z_grad(X[r].astype(np.float64), osys.cidx, osys.native) for r in range(4)]
+    zm = np.array([0.8, 1.3, 0.6, 0.95]) * np.array([z[0] for z in zr])
+    for weights in ((1.0, 0.0), (0.0, 1.0), (2.5, -0.7)):
+        x = dev(X.ravel()).requires_grad_(True)
+        z, Eb = S.zbias(x, dev(zm, "f64"), ctx)
+        (weights[0] * z.sum() + weights[1] * Eb.sum()).backward()
+        G = host(x.grad).reshape(4, 3, -1)
+        for r in range(4):
+            d = zr[r][0] - zm[r]
+            want = (weights[0] + weights[1] * base["k_R"] * d * (d >= 0)) * zr[r][1]
+            if np.abs(want).max() == 0:
+                assert np.all(G[r] == 0)
+            else:
+                assert normwise(G[r], want) <= TOL, (weights, r)
+    with torch.no_grad():
+        z2, _ = S.zbias(dev(X.ravel()), dev(zm, "f64"), ctx)
+    np.testing.assert_allclose(host(z2), host(z), rtol=1e-8)      # z-only and z + gradient passes: float32 partial order
+    # the scaling entry point alone, in place, on seeded values
+    rng = np.random.default_rng(6)
+    g = rng.normal(size=3 * 4 * sy.n).astype(np.float32)
+    coef = rng.normal(size=4)
+    t = dev(g)
+    ctx.scale_by_replica(t, dev(coef, "f64"), t)
+    want = (coef[:, None] * g.reshape(4, -1).astype(np.float64)).astype(np.float32).ravel()
+    np.testing.assert_array_equal(host(t), want)
+    ctx.close()
+
+
 # ---------------------------------------------------------------------------
 # the benchmark configuration at full size, sampled replicas
 # ---------------------------------------------------------------------------
