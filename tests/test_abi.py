@@ -67,3 +67,36 @@ def test_host_validation_rejects_bad_arguments(lib):
     assert lib.scps_step_replicas(None, None, None, None, C.c_int64(1), C.c_uint64(0), 0, None) == -1
     lib.scps_last_error.restype = C.c_char_p
     assert b"NULL" in lib.scps_last_error()
+
+
+def test_context_free_entry_points_validate_on_the_host(lib):
+    """The toy-model and convergence-measure calls need no context; bad
+    arguments come back as status codes before any device work."""
+    from paper_1705_02180_amd import inputs as I
+    from paper_1705_02180_amd import scps
+    D = C.c_double(0.0)
+    fake = C.c_void_p(0x1000)              # never dereferenced: validation fails first
+    f = lib.scps_path_distance
+    f.restype = C.c_int
+    f.argtypes = scps._lib.scps_path_distance.argtypes
+    assert f(None, 5, fake, 5, 0.0, 0.0, 0.8, 20, 20, None, C.byref(D)) == -1     # NULL points with n > 0
+    assert f(fake, 5, fake, 5, 0.0, 0.0, 0.0, 20, 20, None, C.byref(D)) == -1     # cell <= 0
+    assert f(fake, 5, fake, 5, 0.0, 0.0, 0.8, 0, 20, None, C.byref(D)) == -1      # empty grid
+    fs = lib.scps_funnel_steps
+    fs.restype = C.c_int
+    fs.argtypes = scps._lib.scps_funnel_steps.argtypes
+    p = I.funnel_params()
+    fp = scps.FunnelParams(A1=p["A1"], A2=p["A2"], A3=p["A3"], s1=p["s1"], s2=p["s2"], s3=p["s3"], w=p["w"],
+                           xm=p["xm"], ym=p["ym"], kT=p["kT"], mobility_dt=p["mob_dt"], bias_mode=1, reserved=0,
+                           k_R=p["k_R"], lam=p["lam"], k_s=p["k_s"], k_w=p["k_w"], seed=1)
+    assert fs(None, 4, 0, fake, fake, 1, 0, 0, None, 0, None, None) == -1             # no parameters
+    assert fs(C.byref(fp), 4, 0, fake, fake, 1, 0, 0, None, 10, None, None) == -1      # no mean path
+    assert fs(C.byref(fp), 4, 0, fake, fake, 1, 0, 0, None, 65, fake, None) == -2      # 65 frames
+    assert fs(C.byref(fp), 0, 0, fake, fake, 1, 0, 0, None, 10, fake, None) == -1      # no trajectory
+    assert fs(C.byref(fp), 4, 0, fake, fake, 1, 0, 5, None, 10, fake, None) == -1      # frames NULL
+    fm = lib.scps_funnel_mean_path
+    fm.restype = C.c_int
+    fm.argtypes = scps._lib.scps_funnel_mean_path.argtypes
+    zeros = (C.c_uint8 * 4)()
+    assert fm(4, 3, fake, zeros, fake, None) == -7                                    # no successful trajectory
+    assert fm(4, 3, None, zeros, fake, None) == -1

@@ -615,8 +615,9 @@ def test_zero_steps_leave_state_unchanged(S, exec_mode):
 
 
 @pytest.mark.parametrize("exec_mode", [0, 1], ids=["persistent", "per_step"])
-def test_two_particle_chain_matches_oracle(S, exec_mode):
-    base = dict(I._base_params())
+@pytest.mark.parametrize("cut", [0.0, 12.0], ids=["no_cutoff", "cutoffs_lists"])
+def test_two_particle_chain_matches_oracle(S, exec_mode, cut):
+    base = dict(I._base_params(), r_cut_contact=cut, r_cut_nb=cut)
     p = _force_readback_params(base, k_R=0.3)
     w = single_system_workload(2, np.arange(2), p, 2)
     sy = w.systems[0]
