@@ -18,8 +18,7 @@ import torch  # loads the HIP runtime the library binds to
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libscps.so")
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1705_02180_amd.build` "
-                      "(or __graft_entry__.build())")
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1705_02180_amd.build`")
 
 CV_STRIDE = 8
 CV_Z, CV_ZM, CV_EB, CV_S, CV_W, CV_SM, CV_WM, CV_T = range(8)   # CV_T: bias functional T[X]
