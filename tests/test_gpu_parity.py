@@ -1032,3 +1032,33 @@ def test_lists_with_uneven_systems_and_partial_contact_sets(S):
     print(f"  20 steps: lists vs all tiles {d:.2e} (displacement {disp:.2e})", flush=True)
     assert d <= 1e-4 * disp + 1e-4
     np.testing.assert_allclose(res[0][1][:, :2], res[1][1][:, :2], rtol=1e-7)
+
+
+# ---------------------------------------------------------------------------
+# equipartition at the bath temperature (no bias)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("exec_mode", [0, 1], ids=["persistent", "per_step"])
+def test_equipartition_at_bath_temperature(S, exec_mode):
+    """k_R = 0: after 3000 BAOAB steps (6 ps from the extended start, several
+    friction times) the mean of m v^2 per degree of freedom over 256 x 560
+    particles, sampled every 50 steps for 1000 more, equals kT within 1 %
+    (one snapshot's statistical error is ~0.2 %; BAOAB's kinetic-temperature
+    error at dt = 2 fs stays well below that over all modes)."""
+    import torch
+    w = I.config2(n_replicas=256, n_steps=1)
+    p = dict(w.params, k_R=0.0)
+    ctx = context(S, w, params=p, exec_mode=exec_mode)
+    x = dev(w.initial_x())
+    v = dev(w.initial_v(3))
+    cv = dev(w.initial_cvstate(), "f64")
+    ctx.step_replicas(x, v, cv, 3000)
+    m = np.tile(w.systems[0].mass.astype(np.float64), 3 * 256)   # [R][3][n] layout, mass per particle
+    ratios = []
+    for k in range(20):
+        ctx.step_replicas(x, v, cv, 50, step0=3000 + 50 * k)
+        ctx.sync()
+        ratios.append(np.mean(m * host(v).astype(np.float64) ** 2) / p["kT"])
+    r = float(np.mean(ratios))
+    print(f"  <m v^2> / kT = {r:.4f} (snapshots {np.min(ratios):.4f} .. {np.max(ratios):.4f})", flush=True)
+    assert abs(r - 1.0) < 0.01
+    ctx.close()
