@@ -270,7 +270,8 @@ scps_status scps_sync(scps_ctx *ctx, int32_t *bad_replicas, int32_t *n_bad);
 /* Autotuner for the batched stepping (running many replicas at once, SCPS
  * steps 2 and 4): times every launch configuration the context can use for
  * scps_step_replicas -- the persistent kernel with 256, 512 or 1024 threads per
- * replica where a replica's state fits in one workgroup's LDS, and the
+ * replica where a replica's state fits in one workgroup's LDS (also 64, one
+ * wavefront, for chains of at most 256 particles), and the
  * per-step path -- for n_steps steps on private device copies of
  * (x, v, cvstate), and keeps the fastest for the context's later calls
  * (exec_mode AUTO only; an SCPS context has the per-step path alone).

@@ -875,9 +875,12 @@ scps_status autotune_impl(scps_ctx *c, const float *x, const float *v, const dou
     // candidates: {path, workgroup}
     std::vector<std::pair<int, int>> cand;
     const bool scps = c->prm.bias_mode == SCPS_BIAS_SCPS;
-    if (!scps && c->prm.exec_mode == SCPS_EXEC_AUTO)
+    if (!scps && c->prm.exec_mode == SCPS_EXEC_AUTO) {
+        // one wavefront per replica can win for chains of a few blocks (several replicas then share a CU)
+        if (c->n_pad_max <= 4 * TILE) cand.push_back({0, 64});
         for (int wg : {256, 512, 1024})
             if (c->n_pad_max <= persistent_max_npad(wg)) cand.push_back({0, wg});
+    }
     cand.push_back({1, 0});
     const size_t nx = 3 * (size_t)c->sumN;
     float *tx = nullptr, *tv = nullptr;

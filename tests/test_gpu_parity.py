@@ -677,6 +677,21 @@ def test_autotune_picks_a_valid_launch_and_keeps_results(S):
     xs = dev(np.stack([ws.systems[0].start] * 2).astype(np.float32).ravel())
     import torch
     assert sc.autotune(xs, torch.zeros_like(xs), dev(ws.initial_cvstate(), "f64"), 2) == (1, 0)
+    # 20-bead chains: one wavefront per replica is also a candidate (timing noise may pick any of
+    # them: one tile per replica), and results keep matching
+    w1 = I.config1(n_replicas=64, n_steps=1)
+    t1, p1 = context(S, w1), context(S, w1)
+    x1 = dev(w1.initial_x())
+    path, threads = t1.autotune(x1, None, dev(w1.initial_cvstate(), "f64"), 50)
+    print(f"  20-bead chains: autotune picked path {path}, {threads} threads", flush=True)
+    assert (path == 0 and threads in (64, 256, 512, 1024)) or (path == 1 and threads == 0)
+    out = []
+    for ctx in (t1, p1):
+        xa, cva = dev(w1.initial_x()), dev(w1.initial_cvstate(), "f64")
+        ctx.step_replicas(xa, None, cva, 30)
+        ctx.sync()
+        out.append(host(xa))
+    assert np.abs(out[0] - out[1]).max() <= 1e-4 * np.abs(out[1] - w1.initial_x()).max()
 
 
 # ---------------------------------------------------------------------------
