@@ -101,7 +101,11 @@ typedef struct {
                              last build (also by the caller between calls) or the reference map changed, at most
                              512 entries per particle
                              (scps_sync reports NONFINITE for a replica that would need more);
-                             SCPS_EXEC_PER_STEP_ALL_TILES: the per-step path over every tile pair (no lists) */
+                             SCPS_EXEC_PER_STEP_ALL_TILES: the per-step path over every tile pair (no lists).
+                             In SCPS mode the first two form the frame-weighted effective references on the fly,
+                             inside the pass that applies the bias; SCPS_EXEC_PER_STEP_ALL_TILES writes them to
+                             device memory first and reads them back in the pair pass (same results up to float
+                             rounding order; it needs R x (contact tile pairs) x 16 KiB of device memory more) */
     int32_t nb_excl;      /* nonbonded pairs need |i-j| > nb_excl (>= 1) */
     int32_t min_seq_sep;  /* contact pairs need |i-j| > min_seq_sep; the paper's all-atom value is 35 */
     int32_t replica_base; /* replica r uses replica_base + r as its noise counter word, so a context that

@@ -79,7 +79,7 @@ struct scps_ctx {
     int *d_first_all = nullptr, *d_first_con = nullptr;   // [R+1] item ranges per replica
     double *d_X = nullptr, *d_Q = nullptr, *d_csum = nullptr;   // SCPS: sum C R_k, sum C^2, sum c_k
     float *d_coef = nullptr;      // SCPS: c_k / Z0 per replica
-    float *d_E = nullptr;         // SCPS: effective references, replica r at RepDesc::eoff
+    float *d_E = nullptr;         // SCPS, two-pass form: effective references, replica r at RepDesc::eoff
     ScpsGroup *d_groups = nullptr;
     ScpsItem *d_sitems = nullptr;
     int n_sitems = 0;
@@ -367,10 +367,14 @@ scps_status ensure_scps_groups(scps_ctx *c) {
             for (int k = 0; k < g.nrep; ++k) g.rep[k] = mine[b + k];
             const int gi = (int)groups.size();
             groups.push_back(g);
-            for (int I = 0; I < h.ncb; ++I)
-                for (int J = I; J < h.ncb; ++J)
+            // diagonal by diagonal (J - I = d), so that the items that run at the
+            // same time add their forces to different blocks
+            for (int d = 0; d < h.ncb; ++d)
+                for (int I = 0; I + d < h.ncb; ++I) {
+                    const int J = I + d;
                     items.push_back(ScpsItem{gi, tile_index(I, J, h.ncb), (I << 16) | J,
                                              h.tile_flags[(size_t)I * h.nb + J]});
+                }
         }
     }
     c->n_sitems = (int)items.size();
@@ -586,7 +590,8 @@ scps_status init_impl(const scps_params *params, const scps_topology *topo, int3
     if (p.bias_mode == SCPS_BIAS_SCPS) {
         HIP_TRY(c, dalloc(c, &c->d_coef, (size_t)R * c->kmax));
         HIP_TRY(c, dalloc(c, &c->d_csum, R));
-        HIP_TRY(c, dalloc(c, &c->d_E, (size_t)eoff));
+        if (p.exec_mode == SCPS_EXEC_PER_STEP_ALL_TILES)   // the two-pass form keeps E in device memory
+            HIP_TRY(c, dalloc(c, &c->d_E, (size_t)eoff));
         scps_status st2 = ensure_scps_groups(c);
         if (st2 != SCPS_OK) return st2;
     }
@@ -742,10 +747,20 @@ scps_status step_impl(scps_ctx *c, float *x, float *v, double *cv, int64_t n_ste
                                         c->d_X, c->d_Q, c->kmax, -1, c->stream));
             HIP_TRY(c, launch_finalize_scps(c->kp, c->d_sysd, c->d_reps, c->R, c->kmax, c->d_X, c->d_Q, cv,
                                             c->d_coef, c->d_csum, c->stream));
-            HIP_TRY(c, launch_scps_eff(c->d_sysd, c->d_reps, c->d_groups, c->d_sitems, c->n_sitems, c->d_coef,
-                                       c->kmax, c->d_E, c->stream));
-            HIP_TRY(c, launch_pairs(3, c->nbk, c->kp, c->d_sysd, c->d_reps, c->d_items_all, c->n_items_all, c->d_xs,
-                                    c->d_acc, c->d_zpart, c->d_E, c->d_csum, c->stream));
+            if (c->prm.exec_mode == SCPS_EXEC_PER_STEP_ALL_TILES) {
+                // two passes: effective references to device memory, then every tile pair
+                HIP_TRY(c, launch_scps_eff(c->d_sysd, c->d_reps, c->d_groups, c->d_sitems, c->n_sitems, c->d_coef,
+                                           c->kmax, c->d_E, c->stream));
+                HIP_TRY(c, launch_pairs(3, c->nbk, c->kp, c->d_sysd, c->d_reps, c->d_items_all, c->n_items_all,
+                                        c->d_xs, c->d_acc, c->d_zpart, c->d_E, c->d_csum, c->stream));
+            } else {
+                // nonbonded forces and bonds over every tile pair (mode 4), then the
+                // effective references and the bias in one pass over the contact tiles
+                HIP_TRY(c, launch_pairs(4, c->nbk, c->kp, c->d_sysd, c->d_reps, c->d_items_all, c->n_items_all,
+                                        c->d_xs, c->d_acc, c->d_zpart, nullptr, nullptr, c->stream));
+                HIP_TRY(c, launch_scps_bias(c->kp, c->d_sysd, c->d_reps, c->d_groups, c->d_sitems, c->n_sitems,
+                                            c->d_xs, c->d_coef, c->d_csum, c->kmax, c->d_acc, c->stream));
+            }
             HIP_TRY(c, launch_integrate(c->kp, c->d_sysd, c->d_reps, c->R, c->n_pad_max, c->d_xs, c->d_vs, c->d_acc,
                                         c->d_negone, cv, step0 + (uint64_t)m, c->d_flags, c->stream));
         }

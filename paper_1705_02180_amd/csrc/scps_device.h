@@ -9,6 +9,14 @@ __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x)
 __device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ float fexp2(float x) { return __builtin_amdgcn_exp2f(x); }
 
+// Lane l receives what lane (l + 1) mod 64 holds (DPP wave_rol:1).  Every
+// lane has a valid source, so the "old" operand is never used; passing the
+// value itself lets the move happen in place.
+__device__ __forceinline__ float rot1(float v) {
+    const int u = __float_as_int(v);
+    return __int_as_float(__builtin_amdgcn_update_dpp(u, u, 0x134, 0xF, 0xF, false));
+}
+
 // Squared distance of a pair, and the vector d = x_i - x_j.
 __device__ __forceinline__ float pair_r2(const float4 &pi, const float4 &pj, float &dx, float &dy, float &dz) {
     dx = pi.x - pj.x;

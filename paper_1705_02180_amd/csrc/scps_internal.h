@@ -156,6 +156,11 @@ hipError_t launch_tube_eval(double lam, const SysDesc *sysd, const RepDesc *reps
                             hipStream_t st);
 hipError_t launch_scps_eff(const SysDesc *sysd, const RepDesc *reps, const ScpsGroup *groups, const ScpsItem *items,
                            int n_items, const float *coef, int kmax, float *E, hipStream_t st);
+// Effective references and the contact bias forces in one pass (no E in
+// device memory): adds the bias gradient terms to acc components 3..5.
+hipError_t launch_scps_bias(const KParams &P, const SysDesc *sysd, const RepDesc *reps, const ScpsGroup *groups,
+                            const ScpsItem *items, int n_items, const float4 *xs, const float *coef,
+                            const double *csum, int kmax, double *acc, hipStream_t st);
 hipError_t launch_stack_pairmajor(int nc, int ncb, int K, int min_sep, const int *perm, const float *stack,
                                   float *stack_pm, double *R2, hipStream_t st);
 

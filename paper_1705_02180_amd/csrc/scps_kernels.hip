@@ -38,13 +38,6 @@ namespace scps {
 // device helpers
 // ---------------------------------------------------------------------------
 
-// Lane l receives what lane (l + 1) mod 64 holds (DPP wave_rol:1).  Every
-// lane has a valid source, so the "old" operand is never used; passing the
-// value itself lets the move happen in place.
-__device__ __forceinline__ float rot1(float v) {
-    const int u = __float_as_int(v);
-    return __int_as_float(__builtin_amdgcn_update_dpp(u, u, 0x134, 0xF, 0xF, false));
-}
 
 // Reference maps live in global memory; telling the compiler so lets it use
 // global loads with a scalar base instead of flat loads.
@@ -75,10 +68,10 @@ __device__ __forceinline__ void normals3(const KParams &P, uint32_t atom, uint32
 // ---------------------------------------------------------------------------
 // PM_SCPS: the SCPS bias (contact gradient against each replica's effective
 // reference E) plus the nonbonded forces.
-enum { PM_RMD = 0, PM_Z = 1, PM_ZG = 2, PM_SCPS = 3 };
+enum { PM_RMD = 0, PM_Z = 1, PM_ZG = 2, PM_SCPS = 3, PM_NB = 4 };
 
 template <int MODE> struct ModeTraits {
-    static constexpr bool nb = (MODE == PM_RMD || MODE == PM_SCPS);
+    static constexpr bool nb = (MODE == PM_RMD || MODE == PM_SCPS || MODE == PM_NB);
     static constexpr bool grad = (MODE == PM_RMD || MODE == PM_ZG || MODE == PM_SCPS);
     static constexpr bool z = (MODE == PM_RMD || MODE == PM_Z || MODE == PM_ZG);
 };
@@ -169,8 +162,9 @@ __device__ __forceinline__ void pair_group(const KParams &P, const int lane, con
         for (int u = 0; u < U; ++u) {
             const float q = r2[u] * P.inv_r0sq;
             const float q2 = q * q;
-            const float num = 1.f + q + q2;
-            const float den = fmaf(q2, q + q2, num);
+            const float t = q + q2;             // num = 1 + t, den = num + q^2 t
+            const float num = 1.f + t;
+            const float den = fmaf(q2, t, num);
             const float inv_den = inside[u] ? frcp(den) : 0.f;
             const float C = num * inv_den;
             g[u] = 0.f;
@@ -262,8 +256,9 @@ __device__ __forceinline__ void pair_group2(const KParams &P, const int lane, co
                 const float r2 = h ? r2b[u] : r2a[u];
                 const float q = r2 * P.inv_r0sq;
                 const float q2 = q * q;
-                const float num = 1.f + q + q2;
-                const float den = fmaf(q2, q + q2, num);
+                const float t = q + q2;
+                const float num = 1.f + t;
+                const float den = fmaf(q2, t, num);
                 const float inv_den = (h ? inb[u] : ina[u]) ? frcp(den) : 0.f;
                 float diff = num * inv_den - ldg(h ? rtB : rtA, k * 64 + lane);
                 diff = (h ? cb[u] : ca[u]) ? diff : 0.f;
@@ -848,7 +843,8 @@ __global__ __launch_bounds__(256) void k_pairs(const KParams P, const SysDesc *_
     const TileItem it = items[live ? item : 0];
     const RepDesc rd = reps[it.rep];
     const SysDesc S = sysd[rd.sys];
-    const int I = it.I, J = it.J, tf = it.flags;
+    // PM_NB: nonbonded forces and bonds only (the contact terms come from another pass)
+    const int I = it.I, J = it.J, tf = MODE == PM_NB ? (it.flags & ~TF_CONTACT) : it.flags;
     const int n = S.n, n_pad = S.n_pad;
     const float4 *xr2 = xs + 2 * rd.poff;
     {
@@ -954,6 +950,7 @@ hipError_t launch_pairs(int mode, int nbk, const KParams &P, const SysDesc *sysd
     case PM_RMD: SCPS_MODE(PM_RMD); break;
     case PM_Z: SCPS_MODE(PM_Z); break;
     case PM_ZG: SCPS_MODE(PM_ZG); break;
+    case PM_NB: SCPS_MODE(PM_NB); break;
     default: SCPS_MODE(PM_SCPS); break;
     }
 #undef SCPS_MODE
@@ -1228,8 +1225,9 @@ __global__ __launch_bounds__(256) void k_nl_force(const KParams P, const SysDesc
             const float R = __int_as_float(en.y);
             const float q = r2 * P.inv_r0sq;
             const float q2 = q * q;
-            const float num = 1.f + q + q2;
-            const float den = fmaf(q2, q + q2, num);
+            const float t = q + q2;             // num = 1 + t, den = num + q^2 t
+            const float num = 1.f + t;
+            const float den = fmaf(q2, t, num);
             const float inv_den = (!P.has_cut || r2 <= P.r_cut2) ? frcp(den) : 0.f;
             const float C = num * inv_den;
             zt = fmaf(C, C - 2.f * R, zt);

@@ -629,6 +629,248 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SCPS_EFF_WP
     }
 }
 
+// Pass 2 fused with the bias forces: the effective references never leave
+// the chip.  A workgroup takes one work item (group of replicas, contact tile
+// pair I, J) at a time, with blocks I and J of every replica slot in LDS, and
+// walks the tile's sub-steps (lane i of block I meets particle (i + k) mod 64
+// of block J) in chunks of BIAS_CH.  Its wavefronts split into a producer
+// and a consumer half that work on neighbouring chunks at the same time
+// (double-buffered E in LDS, one barrier per chunk):
+//  - matrix wavefront w forms E[slot][i] = sum_f c_f,slot R_f,(i, k) of
+//    sub-step k = chunk + w with 32x32x2 float32 MFMAs (rows: the pairs
+//    i = 2 row + b of block b, read with one 8-byte load per lane from frames
+//    2 kk + (l >> 5); columns: the slots, B operand c of slot l & 31 as in
+//    k_scps_eff), stores it, and issues the stack loads of its next sub-step;
+//  - pair wavefront p takes slots p, p + BIAS_NPW, ... with lane = i, as the
+//    tile kernels do: the contact gradient term (csum C - E) C' of the bias
+//    goes to the lane's i-side partials and to j-side partials that rotate
+//    with the j partner (DPP), over every sub-step of the tile.
+// The partials of each slot go to the replica's float64 bias accumulators
+// (components 3..5) once per item, 64 consecutive particles per atomic
+// instruction.  A diagonal tile takes sub-steps 1..32 (lanes i < 32 at
+// k = 32), so each pair is met once; MASK tiles evaluate the contact
+// predicate and the cutoff per pair.  Nonbonded forces and bonds are not
+// computed here.
+constexpr int BIAS_WG = 768;
+constexpr int BIAS_NMW = 4;                      // matrix wavefronts = sub-steps per chunk
+constexpr int BIAS_NPW = BIAS_WG / 64 - BIAS_NMW;  // pair wavefronts
+constexpr int BIAS_CH = BIAS_NMW;
+constexpr int BIAS_SPW = SCPS_GROUP / BIAS_NPW;  // replica slots per pair wavefront
+
+struct BiasLds {
+    float4 pos[2][SCPS_GROUP][64];        // blocks I, J: [slot][particle]
+    float E[2][BIAS_CH][SCPS_GROUP][65];  // two chunks: [sub-step][slot][i], padded for the matrix stores
+    float c[KMAX / 2][64];                // B operand: c of slot l & 31, frame 2 kk + (l >> 5)
+    float cs[SCPS_GROUP];
+    int org[2][64];
+    int rep[SCPS_GROUP];                  // -1: empty slot
+    int64_t poff[SCPS_GROUP];
+};
+
+typedef float bias_f2 __attribute__((ext_vector_type(2)));
+
+// Frames 2 kk + half of pairs 2 slot, 2 slot + 1 of sub-step k: a uniform
+// tile base and a 32-bit lane offset per load.
+template <int KKN>
+__device__ __forceinline__ void bias_loads(const float *tile_base, const int k, const int K, const int slot,
+                                           const int half, bias_f2 r[KKN]) {
+    typedef const __attribute__((address_space(1))) bias_f2 *gptr;
+    const gptr gb = (gptr)tile_base;
+    const int o = (half * 4096 + k * 64 + 2 * slot) >> 1;   // in float pairs
+#pragma unroll
+    for (int kk = 0; kk < KKN; ++kk) {
+        r[kk] = bias_f2{0.f, 0.f};
+        if (2 * kk + half < K) r[kk] = __builtin_nontemporal_load(gb + (o + kk * 4096));
+    }
+}
+
+// KKN frame pairs per MFMA chain (2 KKN >= K; frames beyond K have zero
+// coefficients and are not loaded), fixed at compile time so that the chain
+// has no branches and its loads are issued together.
+template <bool MASK, int KKN>
+__device__ __forceinline__ void scps_bias_tile(const KParams &P, const SysDesc &S, const ScpsItem &it,
+                                               const int lane, const int wave, BiasLds &L, float fi[][3],
+                                               float fj[][3]) {
+    const int I = it.IJ >> 16, J = it.IJ & 0xFFFF;
+    const bool diag = it.flags & TILE_DIAG;
+    const int kb = diag ? 1 : 0, ke = diag ? 33 : 64;
+    const int nch = (ke - kb + BIAS_CH - 1) / BIAS_CH;
+    if (wave < BIAS_NMW) {
+        // ---- producer: E of sub-step kb + BIAS_CH st + wave, chunk st -> buffer st & 1
+        const int K = S.K;
+        const int slot = lane & 31, half = lane >> 5;
+        const float *Rt = S.stack + (int64_t)it.tile * K * 4096;   // uniform
+        bias_f2 r[KKN];
+        if (kb + wave < ke) bias_loads<KKN>(Rt, kb + wave, K, slot, half, r);
+#pragma unroll 1
+        for (int st = 0; st <= nch; ++st) {
+            const int k = kb + BIAS_CH * st + wave;
+            if (st < nch && k < ke) {
+                fvec16 acc[2];
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) acc[b][v] = 0.f;
+#pragma unroll
+                for (int kk = 0; kk < KKN; ++kk) {
+                    const float c = L.c[kk][lane];
+                    acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(r[kk].x, c, acc[0], 0, 0, 0);
+                    acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(r[kk].y, c, acc[1], 0, 0, 0);
+                }
+                float(*E)[65] = L.E[st & 1][wave];
+#pragma unroll
+                for (int v = 0; v < 16; ++v)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b) E[slot][16 * (v >> 2) + 8 * half + 2 * (v & 3) + b] = acc[b][v];
+                if (k + BIAS_CH < ke) bias_loads<KKN>(Rt, k + BIAS_CH, K, slot, half, r);
+            }
+            __syncthreads();
+        }
+        return;
+    }
+    // ---- consumer: chunk st - 1 from buffer (st - 1) & 1
+    const int pw = wave - BIAS_NMW;
+    const int nc = S.nc, min_sep = P.min_sep;
+    const bool has_cut = P.has_cut;
+    const float inv_r0sq = P.inv_r0sq, r_cut2 = P.r_cut2;
+    const float cp0 = P.cp[0], cp1 = P.cp[1], cp2 = P.cp[2], cp3 = P.cp[3];
+    const bool icon = I * 64 + lane < nc;
+    const int oi = L.org[0][lane];
+    float px[BIAS_SPW], py[BIAS_SPW], pz[BIAS_SPW];
+#pragma unroll
+    for (int m = 0; m < BIAS_SPW; ++m) {
+        const float4 p = L.pos[0][pw + BIAS_NPW * m][lane];
+        px[m] = p.x;
+        py[m] = p.y;
+        pz[m] = p.z;
+    }
+#pragma unroll 1
+    for (int st = 0; st <= nch; ++st) {
+        if (st > 0) {
+            const int c0 = kb + BIAS_CH * (st - 1), nk = min(BIAS_CH, ke - c0);
+            float(*E)[SCPS_GROUP][65] = L.E[(st - 1) & 1];
+            // sub-steps in order (the j-side partials rotate once per sub-step);
+            // the slots of one sub-step are independent, so they run interleaved
+#pragma unroll
+            for (int u = 0; u < BIAS_CH; ++u) {
+                if (u < nk) {
+                    const int k = c0 + u, jl = (lane + k) & 63;
+                    const bool con0 = !diag | (k != 32) | (lane < 32);
+                    bool conm = true;
+                    if constexpr (MASK) conm = icon & (J * 64 + jl < nc) & (abs(oi - L.org[1][jl]) > min_sep);
+#pragma unroll
+                    for (int m = 0; m < BIAS_SPW; ++m) {
+                        const int sl = pw + BIAS_NPW * m;
+                        const float4 pj = L.pos[1][sl][jl];
+                        const float dx = px[m] - pj.x, dy = py[m] - pj.y, dz = pz[m] - pj.z;
+                        const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                        bool inside = true;
+                        if constexpr (MASK) inside = !has_cut | (r2 <= r_cut2);
+                        const float q = r2 * inv_r0sq;
+                        const float q2 = q * q;
+                        const float t = q + q2;
+                        const float num = 1.f + t;
+                        const float den = fmaf(q2, t, num);
+                        const float inv_den = inside ? frcp(den) : 0.f;
+                        float diff = fmaf(L.cs[sl], num * inv_den, -E[u][sl][lane]);
+                        diff = (con0 & conm) ? diff : 0.f;
+                        const float poly = fmaf(q, fmaf(q, fmaf(q, cp0, cp1), cp2), cp3);
+                        const float g = (diff * (q2 * inv_den)) * (poly * inv_den);
+                        fi[m][0] = fmaf(g, dx, fi[m][0]);
+                        fi[m][1] = fmaf(g, dy, fi[m][1]);
+                        fi[m][2] = fmaf(g, dz, fi[m][2]);
+                        fj[m][0] = rot1(fmaf(-g, dx, fj[m][0]));
+                        fj[m][1] = rot1(fmaf(-g, dy, fj[m][1]));
+                        fj[m][2] = rot1(fmaf(-g, dz, fj[m][2]));
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <bool MASK>
+__device__ __forceinline__ void scps_bias_dispatch(const KParams &P, const SysDesc &S, const ScpsItem &it,
+                                                   const int lane, const int wave, BiasLds &L, float fi[][3],
+                                                   float fj[][3]) {
+    if (S.K <= 16)
+        scps_bias_tile<MASK, 8>(P, S, it, lane, wave, L, fi, fj);
+    else if (S.K <= 32)
+        scps_bias_tile<MASK, 16>(P, S, it, lane, wave, L, fi, fj);
+    else if (S.K <= 52)
+        scps_bias_tile<MASK, 26>(P, S, it, lane, wave, L, fi, fj);
+    else
+        scps_bias_tile<MASK, 32>(P, S, it, lane, wave, L, fi, fj);
+}
+
+__global__ __launch_bounds__(BIAS_WG) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_scps_bias(
+    const KParams P, const SysDesc *__restrict__ sysd, const RepDesc *__restrict__ reps,
+    const ScpsGroup *__restrict__ groups, const ScpsItem *__restrict__ items, const int n_items,
+    const float4 *__restrict__ xs, const float *__restrict__ coef, const double *__restrict__ csum, const int kmax,
+    double *__restrict__ acc) {
+    __shared__ BiasLds L;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int cur = -1;
+    SysDesc S;
+    for (int t = blockIdx.x; t < n_items; t += gridDim.x) {
+        const ScpsItem it = items[t];
+        __syncthreads();   // the previous item's positions are no longer read
+        if (it.group != cur) {
+            cur = it.group;
+            const ScpsGroup *gp = groups + cur;
+            const int nrep = gp->nrep;
+            S = sysd[gp->sys];
+            for (int e = tid; e < KMAX / 2 * 64; e += BIAS_WG) {
+                const int kk = e >> 6, l = e & 63, sl = l & 31, k = 2 * kk + (l >> 5);
+                L.c[kk][l] = (sl < nrep && k < S.K) ? coef[(int64_t)gp->rep[sl] * kmax + k] : 0.f;
+            }
+            if (tid < SCPS_GROUP) {
+                const bool live = tid < nrep;
+                L.rep[tid] = live ? gp->rep[tid] : -1;
+                L.poff[tid] = live ? reps[gp->rep[tid]].poff : 0;
+                L.cs[tid] = live ? (float)csum[gp->rep[tid]] : 0.f;
+            }
+            __syncthreads();
+        }
+        const int I = it.IJ >> 16, J = it.IJ & 0xFFFF;
+        for (int e = tid; e < 2 * SCPS_GROUP * 64; e += BIAS_WG) {
+            const int pl = e & 63, sl = (e >> 6) & 31, side = e >> 11;
+            float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (L.rep[sl] >= 0) p = xs[2 * L.poff[sl] + (side ? J : I) * 128 + pl];
+            L.pos[side][sl][pl] = p;
+        }
+        if (tid < 128) L.org[tid >> 6][tid & 63] = S.perm[((tid >> 6) ? J : I) * 64 + (tid & 63)];
+        __syncthreads();
+        float fi[BIAS_SPW][3], fj[BIAS_SPW][3];
+#pragma unroll
+        for (int m = 0; m < BIAS_SPW; ++m)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) fi[m][c] = fj[m][c] = 0.f;
+        if (it.flags & TILE_MASK)
+            scps_bias_dispatch<true>(P, S, it, lane, wave, L, fi, fj);
+        else
+            scps_bias_dispatch<false>(P, S, it, lane, wave, L, fi, fj);
+        if (wave < BIAS_NMW) continue;
+        // after sub-steps kb .. ke-1 lane l holds the j-side partials of particle (l + ke) mod 64
+        const int ke = (it.flags & TILE_DIAG) ? 33 : 64;
+        const int jo = J * 64 + ((lane + ke) & 63);
+        const int n_pad = S.n_pad;
+#pragma unroll
+        for (int m = 0; m < BIAS_SPW; ++m) {
+            const int sl = (wave - BIAS_NMW) + BIAS_NPW * m;
+            if (L.rep[sl] >= 0) {
+                double *ar = acc + 6 * L.poff[sl];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    unsafeAtomicAdd(&ar[(3 + c) * n_pad + I * 64 + lane], (double)fi[m][c]);
+                    unsafeAtomicAdd(&ar[(3 + c) * n_pad + jo], (double)fj[m][c]);
+                }
+            }
+        }
+    }
+}
+
 hipError_t launch_scps_dist(const KParams &P, const SysDesc *sysd, const RepDesc *reps, const ScpsGroup *groups,
                             const ScpsItem *items, int n_items, const float4 *xs, double *X, double *Q, int kmax,
                             int stack_sys, hipStream_t st) {
@@ -681,6 +923,16 @@ hipError_t launch_scps_eff(const SysDesc *sysd, const RepDesc *reps, const ScpsG
     const int grid = n_items < 1024 ? n_items : 1024;
     hipLaunchKernelGGL(k_scps_eff, dim3(grid), dim3(256), 0, st, sysd, reps, groups, items, n_items, coef, kmax,
                        E);
+    return hipGetLastError();
+}
+
+hipError_t launch_scps_bias(const KParams &P, const SysDesc *sysd, const RepDesc *reps, const ScpsGroup *groups,
+                            const ScpsItem *items, int n_items, const float4 *xs, const float *coef,
+                            const double *csum, int kmax, double *acc, hipStream_t st) {
+    if (n_items == 0) return hipSuccess;
+    const int grid = n_items < 256 ? n_items : 256;   // one workgroup per compute unit (LDS)
+    hipLaunchKernelGGL(k_scps_bias, dim3(grid), dim3(BIAS_WG), 0, st, P, sysd, reps, groups, items, n_items, xs,
+                       coef, csum, kmax, acc);
     return hipGetLastError();
 }
 

@@ -417,13 +417,16 @@ SCPS_CASES = [
 ]
 
 
+@pytest.mark.parametrize("exec_mode", [0, 2], ids=["fused", "two_pass"])
 @pytest.mark.parametrize("name,sizes,kinds,K,R,bias_only,extra", SCPS_CASES, ids=[c[0] for c in SCPS_CASES])
-def test_scps_step_forces_match_oracle(S, name, sizes, kinds, K, R, bias_only, extra):
+def test_scps_step_forces_match_oracle(S, name, sizes, kinds, K, R, bias_only, extra, exec_mode):
     """One SCPS step (distances to all K frames, tube variables and ratchets,
     bias + physics) against the oracle, with the frame stack built on the GPU
     from recorded paths and, separately, uploaded from the oracle's FP64 maps.
     K > 16 uses several frame blocks of the distance pass; R > 32 several
-    replica groups; two systems two stacks."""
+    replica groups; two systems two stacks.  Both forms of the bias: the
+    effective references formed inside the bias pass (fused) and written to
+    device memory first (two_pass)."""
     import torch
     base = dict(I._base_params())
     p = _force_readback_params(base, bias_mode=1, lam=13.5, k_s=50.0, k_w=5.0, **extra)
@@ -462,7 +465,7 @@ def test_scps_step_forces_match_oracle(S, name, sizes, kinds, K, R, bias_only, e
     xflat = np.concatenate([x.ravel() for x in X])
     c1 = math.exp(-p["gamma"] * p["dt"])
     for how in ("update", "upload"):
-        ctx = context(S, w, params=p)
+        ctx = context(S, w, params=p, exec_mode=exec_mode)
         for s_id, sy in enumerate(systems):
             if how == "update":
                 maps = ctx.update_reference_from_paths(s_id, dev(frames[s_id].ravel()), n_paths, K,
