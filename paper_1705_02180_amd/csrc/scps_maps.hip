@@ -412,16 +412,23 @@ __device__ __forceinline__ void scps_dist_tile(const KParams &P, const SysDesc &
     const int rs = lane & 31, pq = lane >> 5;
     const bool rep = rs < nrep;
     const bool bload = 2 * rs < K4;
-    const float *Rt = S.stack_pm + (int64_t)it.tile * 4096 * K4 + 2 * rs;
+    // global (not flat) loads from a uniform tile base with 32-bit lane offsets:
+    // flat loads would also count against the LDS wait counter and drain the ring
+    typedef float v2 __attribute__((ext_vector_type(2)));
+    typedef const __attribute__((address_space(1))) v2 *gv2;
+    const gv2 Rt = (gv2)(S.stack_pm + (int64_t)it.tile * 4096 * K4);
     const float4 *xr = xs + 2 * reps[myrep].poff + I * 128;
     constexpr int D = SCPS_DIST_AHEAD;
-    const float2 zero2 = make_float2(0.f, 0.f);
     // pair (i, j) sits at s * 64 + i in the tile, s = (j - i) mod 64
+    // Unconditional loads from clamped in-tile addresses: a lane past the
+    // stack width (2 rs >= K4) feeds output columns of frames >= K, which the
+    // flush drops, and a load past the last row (i_ = 64) is never consumed.
     auto bop = [&](int i_, int m_) {
-        const int s_ = (2 * m_ + pq - i_) & 63;
-        return (bload && i_ < 64) ? *reinterpret_cast<const float2 *>(Rt + (int64_t)(s_ * 64 + i_) * K4) : zero2;
+        const int ic = i_ < 64 ? i_ : 63;
+        const int s_ = (2 * m_ + pq - ic) & 63;
+        return Rt[((s_ * 64 + ic) * K4 >> 1) + (bload ? rs : 0)];
     };
-    float2 ring[D];
+    v2 ring[D];
 #pragma unroll
     for (int u = 0; u < D; ++u) ring[u] = bop(wave, u);
 #pragma unroll 1
@@ -439,7 +446,7 @@ __device__ __forceinline__ void scps_dist_tile(const KParams &P, const SysDesc &
 #pragma unroll
             for (int u = 0; u < D; ++u) {
                 const int m = D * mg + u;
-                const float2 b = ring[u];
+                const v2 b = ring[u];
                 const int nm = m + D < 32 ? m + D : m + D - 32, ni = m + D < 32 ? i : i + 4;
                 ring[u] = bop(ni, nm);
                 const int jl = 2 * m + pq;
