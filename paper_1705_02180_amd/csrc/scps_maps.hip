@@ -743,13 +743,14 @@ __device__ __forceinline__ void scps_bias_tile(const KParams &P, const SysDesc &
     const float cp0 = P.cp[0], cp1 = P.cp[1], cp2 = P.cp[2], cp3 = P.cp[3];
     const bool icon = I * 64 + lane < nc;
     const int oi = L.org[0][lane];
-    float px[BIAS_SPW], py[BIAS_SPW], pz[BIAS_SPW];
+    float px[BIAS_SPW], py[BIAS_SPW], pz[BIAS_SPW], csm[BIAS_SPW];
 #pragma unroll
     for (int m = 0; m < BIAS_SPW; ++m) {
         const float4 p = L.pos[0][pw + BIAS_NPW * m][lane];
         px[m] = p.x;
         py[m] = p.y;
         pz[m] = p.z;
+        csm[m] = L.cs[pw + BIAS_NPW * m];
     }
 #pragma unroll 1
     for (int st = 0; st <= nch; ++st) {
@@ -779,7 +780,7 @@ __device__ __forceinline__ void scps_bias_tile(const KParams &P, const SysDesc &
                         const float num = 1.f + t;
                         const float den = fmaf(q2, t, num);
                         const float inv_den = inside ? frcp(den) : 0.f;
-                        float diff = fmaf(L.cs[sl], num * inv_den, -E[u][sl][lane]);
+                        float diff = fmaf(csm[m], num * inv_den, -E[u][sl][lane]);
                         diff = (con0 & conm) ? diff : 0.f;
                         const float poly = fmaf(q, fmaf(q, fmaf(q, cp0, cp1), cp2), cp3);
                         const float g = (diff * (q2 * inv_den)) * (poly * inv_den);

@@ -499,6 +499,46 @@ def test_scps_step_forces_match_oracle(S, name, sizes, kinds, K, R, bias_only, e
         ctx.close()
 
 
+def test_scps_forms_agree_over_steps(S):
+    """The two forms of the SCPS bias (effective references formed inside the
+    bias pass, and written to device memory first) step the same replicas
+    alike over ten noisy BAOAB steps: they differ only in the float32
+    summation order of the force partials.  300 beads with every third in
+    the contact set (tiles without contacts, blocks straddling the contact
+    set), 36 replicas (two replica groups), 17 frames."""
+    import torch
+    base = dict(I._base_params(), bias_mode=1, lam=13.5, k_s=50.0, k_w=5.0)
+    n, R, K, n_paths = 300, 36, 17, 4
+    rng = np.random.default_rng(21)
+    sy = I.System(n=n, contact_idx=np.asarray(_cidx(n, "every3"), dtype=np.int32),
+                  mass=np.full(n, 12.011 * I.AMU, dtype=np.float32),
+                  charge=rng.normal(0, 0.3, n).astype(np.float32),
+                  native=I.compact_native(n, 21), start=I.persistent_start(n, 22))
+    w = I.Workload("chain300_scps", dict(base), [sy], np.zeros(R, dtype=np.int32), 1)
+    fr = _ensemble_frames(sy, K, n_paths, 23)               # the recorded paths behind the stack
+    x0 = _clean_starts(sy, R, 24).ravel()                   # no overlapping beads: the runs stay finite
+    cv0 = np.zeros((R, 8))
+    cv0[:, 5:7] = np.inf
+    out = []
+    for mode in (0, 2):
+        ctx = context(S, w, params=base, exec_mode=mode)
+        ctx.update_reference_from_paths(0, dev(fr.ravel()), n_paths, K, np.ones(n_paths, dtype=np.uint8))
+        x, v, cv = dev(x0), dev(np.zeros_like(x0)), dev(cv0, "f64")
+        ctx.step_replicas(x, v, cv, 10, step0=7)
+        ctx.sync()
+        out.append((host(x), host(v), host(cv)))
+        ctx.close()
+    (xa, va, cva), (xb, vb, cvb) = out
+    assert np.isfinite(xa).all() and np.isfinite(xb).all()
+    disp = np.abs(xa - x0).max()
+    assert disp > 0
+    assert np.abs(xa - xb).max() <= 1e-4 * disp, (np.abs(xa - xb).max(), disp)
+    assert np.abs(va - vb).max() <= 1e-4 * np.abs(va).max()
+    np.testing.assert_allclose(cva[:, 3:7], cvb[:, 3:7], rtol=0, atol=1e-6)
+    assert (cva[:, 7] > 0).any()                     # the tube ratchets acted
+    np.testing.assert_allclose(cva[:, 7], cvb[:, 7], rtol=1e-4, atol=1e-12 * cva[:, 7].max())
+
+
 # ---------------------------------------------------------------------------
 # autograd wrapper
 # ---------------------------------------------------------------------------
