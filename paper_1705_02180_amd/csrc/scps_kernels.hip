@@ -837,6 +837,7 @@ __global__ __launch_bounds__(256) void k_pairs(const KParams P, const SysDesc *_
                                                const double *__restrict__ csum) {
     using T = ModeTraits<MODE>;
     __shared__ float4 shpos[4][128];   // block J of each wavefront's item, stored twice
+    __shared__ int shorg[4][64];       // and its chain indices (read by the per-pair predicates)
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int item = blockIdx.x * 4 + wave;
     const bool live = item < n_items;
@@ -851,6 +852,7 @@ __global__ __launch_bounds__(256) void k_pairs(const KParams P, const SysDesc *_
         const float4 pj = xr2[J * 128 + lane];
         shpos[wave][lane] = pj;
         shpos[wave][64 + lane] = pj;
+        shorg[wave][lane] = S.perm[J * 64 + lane];
     }
     __syncthreads();
     if (!live) return;
@@ -879,7 +881,7 @@ __global__ __launch_bounds__(256) void k_pairs(const KParams P, const SysDesc *_
     }
     const bool diag = tf & TF_DIAG;
     const int kb = tile_kbeg(diag), ke = tile_kend(diag);
-    tile_dispatch<MODE, NBK, 4 * SCPS_PAIR_GROUP>(tf, kb, ke, it.mask, P, lane, A, shpos[wave], S.perm + J * 64,
+    tile_dispatch<MODE, NBK, 4 * SCPS_PAIR_GROUP>(tf, kb, ke, it.mask, P, lane, A, shpos[wave], shorg[wave],
                                                   S.nc - J * 64, rt, cs, fi, fj, zt);
     const int jo = J * 64 + jflush_at(lane, ke);
     double *ar = acc + 6 * rd.poff;
