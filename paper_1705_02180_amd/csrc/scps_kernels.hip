@@ -1169,7 +1169,7 @@ __global__ __launch_bounds__(256) void k_nl_build(const KParams P, const SysDesc
                     const int tag = tag_at(k);
                     if (tag) {
                         const int jl = (lane + k) & 63, j = J * 64 + jl;
-                        const float Rv = (tag & (1 << 30)) ? rt[k * 64 + lane] : 0.f;
+                        const float Rv = (tag & (1 << 30)) ? ldg(rt, k * 64 + lane) : 0.f;
                         if (o_i < NL_CAP) li[(int64_t)i * NL_CAP + o_i] = make_int2(j | tag, __float_as_int(Rv));
                         if (o_j < NL_CAP) li[(int64_t)j * NL_CAP + o_j] = make_int2(i | tag, __float_as_int(Rv));
                         ++o_i;

@@ -538,7 +538,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SCPS_DIST_W
     }
 }
 
-// Pass 2 operand: E[eoff_r + tile * 4096 + p] = sum_k c_rk R_kp for every
+// Pass 2 operand of the two-pass form (exec mode 2; the default forms it inside
+// k_scps_bias): E[eoff_r + tile * 4096 + p] = sum_k c_rk R_kp for every
 // pair p of each work item's tile and replica r of its group (coef holds
 // c_rk).  Wavefront w takes chunks of 32 EFF_NB pairs w, w+4, ...; a chunk is
 // EFF_NB 32-pair MFMA blocks interleaved so that block b holds pairs

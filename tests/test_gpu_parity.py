@@ -414,6 +414,7 @@ SCPS_CASES = [
     ("two_systems_K20", [150, 200], ["all", "every3"], 20, 6, False, {}),
     ("smallest_stack_K2", [100], ["all"], 2, 3, False, {}),
     ("largest_stack_K64_bias_only", [120], ["all"], 64, 5, True, {}),
+    ("one_block_60_K5", [60], ["all"], 5, 3, False, {}),
 ]
 
 
