@@ -56,6 +56,7 @@ FLOPS_FUNNEL_FRAME = 32  # per mean-path frame and step, float64: the largest ex
 
 PEAK_FP32 = 157.3e12    # MI355X vector FP32, 256 CUs x 2.4 GHz
 PEAK_FP64 = 78.6e12
+PEAK_HBM = 8.0e12       # MI355X HBM3E, bytes/s
 
 
 def parse():
@@ -170,6 +171,14 @@ def roofline(flops_per_call, per_call_ms, kernel, traffic=None, peak=PEAK_FP32):
     achieved = flops_per_call / avg_s
     return {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
             "frac": achieved / peak, "traffic": traffic, "kernel": kernel, "avg_launch_ms": 1e3 * avg_s,
+            "median_launch_ms": median(per_call_ms)}
+
+
+def roofline_hbm(bytes_per_call, per_call_ms, kernel, traffic=None):
+    avg_s = sum(per_call_ms) / len(per_call_ms) / 1e3
+    achieved = bytes_per_call / avg_s
+    return {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+            "frac": achieved / PEAK_HBM, "traffic": traffic, "kernel": kernel, "avg_launch_ms": 1e3 * avg_s,
             "median_launch_ms": median(per_call_ms)}
 
 
@@ -427,8 +436,14 @@ def bench_scps6000(args, torch, I, scps):
         "replicas": R, "particles": n, "frames": K, "block": blk})
     out["contact_pair_evals_per_s"] = value * con
     per_step = flops_scps_contact(K) * con + FLOPS_NONBONDED * nb - FLOPS_GEOMETRY * both
-    out["roofline"] = roofline(R * blk * per_step, per_ms,
-                               "scps_step_replicas (pass 1, ratchets, pass 2, update)")
+    # the step streams the float32 frame stack twice (distances, then the bias with
+    # its effective references) for each group of up to 32 replicas: that is its bound
+    groups = (R + 31) // 32
+    stack_bytes = 2 * groups * K * con * 4
+    out["roofline"] = roofline_hbm(blk * stack_bytes, per_ms,
+                                   "scps_step_replicas (pass 1, ratchets, pass 2, update): frame stack read twice")
+    out["roofline_alu"] = roofline(R * blk * per_step, per_ms,
+                                   "the same calls against the FP32 peak (MFMA contraction flops included)")
     # the same steps with the effective references written to device memory
     # and read back by a separate pair pass, for comparison
     two = scps.Context.from_workload(w, params=p, exec_mode=2)
