@@ -57,6 +57,10 @@ struct scps_ctx {
     scps_params prm{};
     KParams kp{};
     hipStream_t stream = nullptr;
+    // SCPS, fused form: the nonbonded pass runs on a second stream beside the
+    // distance pass (fork and join through events on the caller's stream)
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int R = 0;
     std::vector<SysHost> sys;
     std::vector<int> rep_sys;
@@ -590,8 +594,13 @@ scps_status init_impl(const scps_params *params, const scps_topology *topo, int3
     if (p.bias_mode == SCPS_BIAS_SCPS) {
         HIP_TRY(c, dalloc(c, &c->d_coef, (size_t)R * c->kmax));
         HIP_TRY(c, dalloc(c, &c->d_csum, R));
-        if (p.exec_mode == SCPS_EXEC_PER_STEP_ALL_TILES)   // the two-pass form keeps E in device memory
+        if (p.exec_mode == SCPS_EXEC_PER_STEP_ALL_TILES) {   // the two-pass form keeps E in device memory
             HIP_TRY(c, dalloc(c, &c->d_E, (size_t)eoff));
+        } else {
+            HIP_TRY(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+            HIP_TRY(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+            HIP_TRY(c, hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+        }
         scps_status st2 = ensure_scps_groups(c);
         if (st2 != SCPS_OK) return st2;
     }
@@ -743,6 +752,15 @@ scps_status step_impl(scps_ctx *c, float *x, float *v, double *cv, int64_t n_ste
         } else {
             // distances to every frame (matrix cores), tube variables and
             // ratchets, effective references (matrix cores), bias + physics
+            if (c->side) {
+                // nonbonded forces (acc components 0..2) need only the positions:
+                // they overlap the bandwidth-bound distance pass
+                HIP_TRY(c, hipEventRecord(c->ev_fork, c->stream));
+                HIP_TRY(c, hipStreamWaitEvent(c->side, c->ev_fork, 0));
+                HIP_TRY(c, launch_pairs(4, c->nbk, c->kp, c->d_sysd, c->d_reps, c->d_items_all, c->n_items_all,
+                                        c->d_xs, c->d_acc, c->d_zpart, nullptr, nullptr, c->side));
+                HIP_TRY(c, hipEventRecord(c->ev_join, c->side));
+            }
             HIP_TRY(c, launch_scps_dist(c->kp, c->d_sysd, c->d_reps, c->d_groups, c->d_sitems, c->n_sitems, c->d_xs,
                                         c->d_X, c->d_Q, c->kmax, -1, c->stream));
             HIP_TRY(c, launch_finalize_scps(c->kp, c->d_sysd, c->d_reps, c->R, c->kmax, c->d_X, c->d_Q, cv,
@@ -754,12 +772,16 @@ scps_status step_impl(scps_ctx *c, float *x, float *v, double *cv, int64_t n_ste
                 HIP_TRY(c, launch_pairs(3, c->nbk, c->kp, c->d_sysd, c->d_reps, c->d_items_all, c->n_items_all,
                                         c->d_xs, c->d_acc, c->d_zpart, c->d_E, c->d_csum, c->stream));
             } else {
-                // nonbonded forces and bonds over every tile pair (mode 4), then the
-                // effective references and the bias in one pass over the contact tiles
-                HIP_TRY(c, launch_pairs(4, c->nbk, c->kp, c->d_sysd, c->d_reps, c->d_items_all, c->n_items_all,
-                                        c->d_xs, c->d_acc, c->d_zpart, nullptr, nullptr, c->stream));
+                // the effective references and the bias in one pass over the contact tiles;
+                // the nonbonded forces and bonds (mode 4, every tile pair) ran on the side
+                // stream beside the distance pass and are joined before the update
                 HIP_TRY(c, launch_scps_bias(c->kp, c->d_sysd, c->d_reps, c->d_groups, c->d_sitems, c->n_sitems,
                                             c->d_xs, c->d_coef, c->d_csum, c->kmax, c->d_acc, c->stream));
+                if (c->side)
+                    HIP_TRY(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
+                else
+                    HIP_TRY(c, launch_pairs(4, c->nbk, c->kp, c->d_sysd, c->d_reps, c->d_items_all, c->n_items_all,
+                                            c->d_xs, c->d_acc, c->d_zpart, nullptr, nullptr, c->stream));
             }
             HIP_TRY(c, launch_integrate(c->kp, c->d_sysd, c->d_reps, c->R, c->n_pad_max, c->d_xs, c->d_vs, c->d_acc,
                                         c->d_negone, cv, step0 + (uint64_t)m, c->d_flags, c->stream));
@@ -1194,6 +1216,12 @@ scps_status scps_funnel_mean_path(int32_t n_traj, int32_t n_frames, const double
 void scps_destroy(scps_ctx *ctx) {
     if (!ctx) return;
     (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->side) {
+        (void)hipStreamSynchronize(ctx->side);
+        (void)hipStreamDestroy(ctx->side);
+    }
+    if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+    if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
     for (void *p : ctx->owned) (void)hipFree(p);
     delete ctx;
 }
