@@ -23,7 +23,10 @@
  * - Device work is queued on the context's HIP stream and is asynchronous
  *   with respect to the host unless stated otherwise.  The caller keeps
  *   device buffers alive until that work has completed (torch tensors used
- *   on the same stream satisfy this).
+ *   on the same stream satisfy this).  An SCPS context in the default form
+ *   also runs part of each step on a second stream of its own, forked from
+ *   and joined back to the context's stream through events within the call,
+ *   so ordering with the caller's work on that stream is unchanged.
  * - The library cannot check the extent of a caller's buffer; the sizes
  *   stated below are the caller's contract.
  * - A context is not re-entrant: one thread, one stream at a time.
