@@ -540,6 +540,41 @@ def test_scps_forms_agree_over_steps(S):
     np.testing.assert_allclose(cva[:, 7], cvb[:, 7], rtol=1e-4, atol=1e-12 * cva[:, 7].max())
 
 
+def test_scps_step_on_a_caller_stream(S):
+    """The default SCPS form runs its nonbonded pass on a second stream of its
+    own, forked from and joined back to the caller's stream.  Stepping on a
+    non-default torch stream gives what the default stream gives (up to the
+    float32 summation order of the force partials), and the caller's next
+    work on that stream sees the updated state."""
+    import torch
+    base = dict(I._base_params(), bias_mode=1, lam=13.5, k_s=50.0, k_w=5.0)
+    n, R, K, n_paths = 150, 6, 9, 3
+    w = single_system_workload(n, np.arange(n), base, R, seed=31)
+    sy = w.systems[0]
+    fr = _ensemble_frames(sy, K, n_paths, 32)
+    x0 = _clean_starts(sy, R, 33).ravel()
+    cv0 = np.zeros((R, 8))
+    cv0[:, 5:7] = np.inf
+    out = []
+    for use_side in (False, True):
+        side = torch.cuda.Stream() if use_side else torch.cuda.current_stream()
+        with torch.cuda.stream(side):
+            ctx = context(S, w, params=base)
+            ctx.update_reference_from_paths(0, dev(fr.ravel()), n_paths, K, np.ones(n_paths, dtype=np.uint8))
+            x, v, cv = dev(x0), dev(np.zeros_like(x0)), dev(cv0, "f64")
+            ctx.step_replicas(x, v, cv, 8, step0=11)
+            moved = (x - dev(x0)).abs().max()          # queued on the same stream, after the steps
+        side.synchronize()
+        out.append((host(x), host(v), host(cv), float(moved)))
+        ctx.close()
+    (xa, va, cva, ma), (xb, vb, cvb, mb) = out
+    disp = np.abs(xa - x0).max()
+    assert disp > 0 and abs(ma - disp) <= 1e-6 * disp and abs(mb - np.abs(xb - x0).max()) <= 1e-6 * disp
+    assert np.abs(xa - xb).max() <= 1e-4 * disp, (np.abs(xa - xb).max(), disp)
+    assert np.abs(va - vb).max() <= 1e-4 * np.abs(va).max()
+    np.testing.assert_allclose(cva[:, 3:7], cvb[:, 3:7], rtol=0, atol=1e-6)
+
+
 # ---------------------------------------------------------------------------
 # autograd wrapper
 # ---------------------------------------------------------------------------
