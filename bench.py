@@ -368,7 +368,10 @@ def bench_autograd3000(args, torch, I, scps):
                     f"the kept dz/dx per chain)",
         "chains": R, "particles": n})
     out["contact_pair_evals_per_s"] = value * P
-    out["roofline"] = roofline(R * P * FLOPS_CONTACT, per_ms, "forward + backward (eval kernels)")
+    # each chain has its own float32 reference map, streamed once per forward + backward:
+    # that stream, not the arithmetic, is the bound
+    out["roofline"] = roofline_hbm(R * P * 4, per_ms, "forward + backward: each chain's reference map read once")
+    out["roofline_alu"] = roofline(R * P * FLOPS_CONTACT, per_ms, "the same calls against the FP32 peak")
     ctx.close()
     if not args.no_cpu:
         import oracle as O
