@@ -674,6 +674,9 @@ struct BiasLds {
     int rep[SCPS_GROUP];                  // -1: empty slot
     int64_t poff[SCPS_GROUP];
 };
+static_assert(BIAS_WG % 64 == 0 && BIAS_NPW > 0 && SCPS_GROUP % BIAS_NPW == 0,
+              "every pair wavefront takes the same number of replica slots");
+static_assert(sizeof(BiasLds) <= 160 * 1024, "the fused bias pass keeps one workgroup's state in LDS");
 
 typedef float bias_f2 __attribute__((ext_vector_type(2)));
 
