@@ -370,15 +370,18 @@ hipError_t launch_stack_pairmajor(int nc, int ncb, int K, int min_sep, const int
 }
 
 // Contact value of one replica-pair for the MFMA operand (0 when the pair
-// does not count).
+// does not count).  CUT: test the contact cutoff (a cutoff marks every
+// contact tile MASK, so the other tiles need no test).
+template <bool CUT>
 __device__ __forceinline__ float contact_operand(const KParams &P, const float4 &pi, const float4 &pj, bool ok) {
     float dx, dy, dz;
     const float r2 = pair_r2(pi, pj, dx, dy, dz);
     const float q = r2 * P.inv_r0sq;
     const float q2 = q * q;
-    const float num = 1.f + q + q2;
-    const float den = fmaf(q2, q + q2, num);
-    const bool inside = !P.has_cut | (r2 <= P.r_cut2);
+    const float t = q + q2;   // num = 1 + t, den = num + q^2 t
+    const float num = 1.f + t;
+    const float den = fmaf(q2, t, num);
+    const bool inside = CUT ? (!P.has_cut | (r2 <= P.r_cut2)) : true;
     return (ok & inside) ? num * frcp(den) : 0.f;
 }
 
@@ -454,7 +457,7 @@ __device__ __forceinline__ void scps_dist_tile(const KParams &P, const SysDesc &
                 if constexpr (MASK) {
                     ok = ok & icon & (J * 64 + jl < S.nc) & (abs(oi - orgj[jl]) > P.min_sep);
                 }
-                const float c = contact_operand(P, pi, posj[jl][rs], ok & rep);
+                const float c = contact_operand<MASK>(P, pi, posj[jl][rs], ok & rep);
                 q = fma((double)c, (double)c, q);
                 acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(c, b.x, acc[0], 0, 0, 0);
                 acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(c, b.y, acc[1], 0, 0, 0);
