@@ -325,6 +325,9 @@ def bench_uneven512(args, torch, I, scps):
         "replicas": R, "particles_total": int(sizes.sum()), "block": args.block})
     out["contact_pair_evals_per_s"] = value / R * con
     out["roofline"] = roofline(args.block * flops, per_ms, "scps_step_replicas (all kernels of a block)")
+    # every chain has its own float32 reference map, read once per step: the
+    # map stream is about as binding as the arithmetic here
+    out["roofline_hbm"] = roofline_hbm(args.block * con * 4, per_ms, "each chain's reference map read once per step")
     ctx.close()
     if not args.no_cpu:
         rng = np.random.default_rng(5)
