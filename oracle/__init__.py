@@ -39,6 +39,7 @@ class OrcParams(C.Structure):
         ("lj_eps", C.c_double), ("lj_sigma", C.c_double),
         ("dh_prefactor", C.c_double), ("dh_kappa", C.c_double),
         ("nb_excl", C.c_int32), ("min_seq_sep", C.c_int32),
+        ("w_form", C.c_int32), ("pad_w", C.c_int32),
         ("r0", C.c_double), ("r_cut", C.c_double), ("r_cut_nb", C.c_double),
         ("k_R", C.c_double),
         ("lam", C.c_double), ("k_s", C.c_double), ("k_w", C.c_double),
@@ -52,7 +53,7 @@ class FunnelParams(C.Structure):
         ("s1", C.c_double), ("s2", C.c_double), ("s3", C.c_double),
         ("w", C.c_double), ("xm", C.c_double), ("ym", C.c_double),
         ("kT", C.c_double), ("mob_dt", C.c_double),
-        ("bias_mode", C.c_int32), ("pad", C.c_int32),
+        ("bias_mode", C.c_int32), ("w_form", C.c_int32),
         ("k_R", C.c_double), ("lam", C.c_double), ("k_s", C.c_double), ("k_w", C.c_double),
         ("seed", C.c_uint64),
     ]
@@ -91,8 +92,10 @@ def lib():
         L.orc_uniform.argtypes = [C.c_uint32]
         L.orc_normals.argtypes = [u64, C.c_uint32, C.c_uint32, u64, vp]
         L.orc_normals_array.argtypes = [i64, u64, vp, vp, vp, vp]
-        L.orc_tube.argtypes = [C.c_int, vp, C.c_int, vp, C.c_int, vp, d, d, d, d, C.c_int,
+        L.orc_tube.argtypes = [C.c_int, vp, C.c_int, vp, C.c_int, vp, d, d, d, d, C.c_int, C.c_int,
                                vp, vp, vp, vp, vp]
+        L.orc_norm_z0.restype = d
+        L.orc_norm_z0.argtypes = [C.c_int, vp, vp, C.c_int]
         L.orc_total_force.argtypes = [C.POINTER(OrcParams), C.POINTER(OrcSystem), vp, vp, vp, vp]
         L.orc_steps.argtypes = [C.POINTER(OrcParams), C.POINTER(OrcSystem), C.c_uint32, vp, vp, vp,
                                 i64, u64, C.c_int, vp, i64]
@@ -106,7 +109,7 @@ def lib():
         L.orc_funnel_force.restype = d
         L.orc_funnel_force.argtypes = [C.POINTER(FunnelParams), d, d, vp]
         L.orc_funnel_tube.restype = None
-        L.orc_funnel_tube.argtypes = [d, d, C.c_int, vp, d, vp, vp, vp, vp]
+        L.orc_funnel_tube.argtypes = [d, d, C.c_int, vp, d, C.c_int, vp, vp, vp, vp]
         L.orc_funnel_batch.restype = C.c_int
         L.orc_funnel_batch.argtypes = [C.POINTER(FunnelParams), C.c_int, C.c_uint32, vp, vp, i64, u64, C.c_int, vp,
                                        C.c_int, vp, C.c_int]
@@ -128,8 +131,9 @@ def make_params(d: dict) -> OrcParams:
         dt=d["dt"], gamma=d["gamma"], kT=d["kT"], k_bond=d["k_bond"], r_bond=d["r_bond"],
         lj_eps=d["lj_eps"], lj_sigma=d["lj_sigma"], dh_prefactor=d["dh_prefactor"],
         dh_kappa=d["dh_kappa"], nb_excl=int(d["nb_excl"]), min_seq_sep=int(d["min_seq_sep"]),
-        r0=d["r0_contact"], r_cut=d["r_cut_contact"], r_cut_nb=d.get("r_cut_nb", 0.0), k_R=d["k_R"], lam=d["lam"],
-        k_s=d["k_s"], k_w=d["k_w"], seed=int(d["seed"]))
+        w_form=int(d.get("w_form", 0)), pad_w=0, r0=d["r0_contact"], r_cut=d["r_cut_contact"],
+        r_cut_nb=d.get("r_cut_nb", 0.0), k_R=d["k_R"], lam=d["lam"], k_s=d["k_s"], k_w=d["k_w"],
+        seed=int(d["seed"]))
 
 
 # ---------------------------------------------------------------------------
@@ -197,8 +201,9 @@ def normals(seed: int, atom, replica, step) -> np.ndarray:
 
 
 def tube(x, cidx, stack, Z0, lam, r0: float = 7.5, r_cut: float = 0.0, min_sep: int = 0,
-         grads: bool = True):
-    """s, w (and their gradients, and d_k) of the mean-field tube variables."""
+         grads: bool = True, w_form: int = 0):
+    """s, w (and their gradients, and d_k) of the mean-field tube variables;
+    w_form 0 keeps the 1/lambda of eq (wX) in w, w_form 1 drops it (eq (awXa))."""
     x = _f64(x)
     n = x.shape[-1]
     cidx = np.ascontiguousarray(cidx, dtype=np.int32)
@@ -209,7 +214,7 @@ def tube(x, cidx, stack, Z0, lam, r0: float = 7.5, r_cut: float = 0.0, min_sep: 
     gs = np.empty((3, n)) if grads else None
     gw = np.empty((3, n)) if grads else None
     dk = np.empty(K)
-    lib().orc_tube(n, _p(x), len(cidx), _p(cidx), K, _p(stack), Z0, lam, r0, r_cut, min_sep,
+    lib().orc_tube(n, _p(x), len(cidx), _p(cidx), K, _p(stack), Z0, lam, r0, r_cut, min_sep, int(w_form),
                    C.byref(s), C.byref(w), _p(gs), _p(gw), _p(dk))
     return s.value, w.value, gs, gw, dk
 
@@ -217,6 +222,15 @@ def tube(x, cidx, stack, Z0, lam, r0: float = 7.5, r_cut: float = 0.0, min_sep: 
 # ---------------------------------------------------------------------------
 # systems, forces, stepping
 # ---------------------------------------------------------------------------
+def norm_z0(cidx, native_map, min_sep: int = 0) -> float:
+    """Denominator of the normalised map distance of the SCPS section: the sum
+    of (C0_ij)^2 over the contact pairs with |i - j| > min_sep (the pairs its
+    numerator sums over)."""
+    cidx = np.ascontiguousarray(cidx, dtype=np.int32)
+    native_map = _f64(native_map)
+    return float(lib().orc_norm_z0(len(cidx), _p(cidx), _p(native_map), int(min_sep)))
+
+
 class System:
     """One chain as the oracle sees it (arrays kept alive on the object)."""
 
@@ -230,7 +244,7 @@ class System:
         if native_map is None:
             native_map = contact_map(native_xyz, self.cidx, r0, rc)
         self.native = _f64(native_map)
-        self.Z0 = float(np.sum(self.native ** 2)) if Z0 is None else float(Z0)
+        self.Z0 = norm_z0(self.cidx, self.native, params["min_seq_sep"]) if Z0 is None else float(Z0)
         self.stack = None if stack is None else _f64(stack)
         self.K = 0 if stack is None else int(self.stack.shape[0])
 
@@ -325,11 +339,13 @@ def least_biased(cv, success=None) -> int:
     return int(lib().orc_least_biased(cv.shape[0], _p(cv), _p(succ)))
 
 
-def sigma(x, cidx, stacks, Z0s, lam, r0: float = 7.5, r_cut: float = 0.0, min_sep: int = 0) -> float:
+def sigma(x, cidx, stacks, Z0s, lam, r0: float = 7.5, r_cut: float = 0.0, min_sep: int = 0,
+          w_form: int = 0) -> float:
     """Global progress coordinate, eq (sigma): the mean over the reference
     stacks (one per initial condition) of 1 - s_lambda^k(X), each s from the
     pinned tube routine with its own stack and Z0."""
-    vals = [1.0 - tube(x, cidx, st, z0, lam, r0, r_cut, min_sep, grads=False)[0] for st, z0 in zip(stacks, Z0s)]
+    vals = [1.0 - tube(x, cidx, st, z0, lam, r0, r_cut, min_sep, grads=False, w_form=w_form)[0]
+            for st, z0 in zip(stacks, Z0s)]
     return float(np.mean(vals))
 
 
@@ -355,7 +371,7 @@ def path_distance(xy_a, xy_b, x0, y0, cell, nx, ny) -> float:
 def funnel_params(d: dict) -> FunnelParams:
     return FunnelParams(**{k: d[k] for k in ("A1", "A2", "A3", "s1", "s2", "s3", "w", "xm", "ym", "kT", "mob_dt",
                                              "k_R", "lam", "k_s", "k_w")},
-                        bias_mode=int(d["bias_mode"]), pad=0, seed=int(d["seed"]))
+                        bias_mode=int(d["bias_mode"]), w_form=int(d.get("w_form", 0)), seed=int(d["seed"]))
 
 
 def funnel_force(params: dict, x: float, y: float):
@@ -365,12 +381,14 @@ def funnel_force(params: dict, x: float, y: float):
     return U, F
 
 
-def funnel_tube(x: float, y: float, mean_path, lam: float):
-    """s, w and their gradients for the Euclidean tube around a mean path [K][2]."""
+def funnel_tube(x: float, y: float, mean_path, lam: float, w_form: int = 0):
+    """s, w and their gradients for the Euclidean tube around a mean path [K][2]
+    (w_form 1: w without the 1/lambda, as the toy-model section prints it)."""
     mp = _f64(mean_path).reshape(-1, 2)
     s, w = C.c_double(), C.c_double()
     gs, gw = np.empty(2), np.empty(2)
-    lib().orc_funnel_tube(float(x), float(y), mp.shape[0], _p(mp), float(lam), C.byref(s), C.byref(w), _p(gs), _p(gw))
+    lib().orc_funnel_tube(float(x), float(y), mp.shape[0], _p(mp), float(lam), int(w_form), C.byref(s), C.byref(w),
+                          _p(gs), _p(gw))
     return s.value, w.value, gs, gw
 
 

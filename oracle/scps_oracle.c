@@ -31,8 +31,14 @@
  *     set with |i-j| > min_seq_sep (the paper's all-atom value is 35);
  *   - eq (Cij) is evaluated in the algebraically identical form
  *     (1+q+q^2)/(1+q+q^2+q^3+q^4), q = (r/r0)^2, which has no 0/0 at r0;
- *   - w_lambda keeps the 1/lambda of eq (wX); the constant w0 is dropped
- *     because only differences w - w_m and gradients enter the forces;
+ *   - w_lambda keeps the 1/lambda of eq (wX) by default; w_form = 1 drops
+ *     it, as eq (awXa), the protocol and the toy-model formulas print w
+ *     (then w and its gradient are lambda times larger).  The constant w0
+ *     is dropped because only differences w - w_m and gradients enter the
+ *     forces;
+ *   - the norm of the tube distance divides by Z0 = the sum of (C0_ij)^2 over
+ *     the same pairs as its numerator (|i-j| > min_seq_sep), as the
+ *     normalised Frobenius-type distance of the SCPS section is defined;
  *   - the SCPS ratchets use (s - s_m) and (w - w_m) as in eqs (Fw),(Fs);
  *   - BAOAB is used for the underdamped equation and its state velocity
  *     is the one right after the friction/noise substep;
@@ -66,6 +72,8 @@ typedef struct {
     double dh_prefactor, dh_kappa;
     int32_t nb_excl;         /* nonbonded pairs need |i-j| > nb_excl */
     int32_t min_seq_sep;     /* contact pairs need |i-j| > min_seq_sep */
+    int32_t w_form;          /* 0: w = -(1/lambda) log sum_k e^{-lambda d_k}; 1: without the 1/lambda */
+    int32_t pad_w;
     double r0;               /* contact reference distance */
     double r_cut;            /* <= 0: no cutoff */
     double r_cut_nb;         /* <= 0: no cutoff; else nonbonded pairs with r > r_cut_nb contribute nothing */
@@ -152,6 +160,21 @@ double orc_z_grad(int n, const double *x, int nc, const int32_t *cidx,
             }
         }
     return z;
+}
+
+/* Denominator of the normalised distance between contact maps (SCPS
+ * section): the sum of (C0_ij)^2 over the contact pairs with |i-j| >
+ * min_sep, the same pairs its numerator and z sum over. */
+double orc_norm_z0(int nc, const int32_t *cidx, const double *native, int min_sep)
+{
+    double z0 = 0.0;
+    for (int a = 0; a < nc; ++a)
+        for (int b = a + 1; b < nc; ++b) {
+            if (abs(cidx[a] - cidx[b]) <= min_sep) continue;
+            double c0 = native[pidx(nc, a, b)];
+            z0 += c0 * c0;
+        }
+    return z0;
 }
 
 /* ------------------------------------------------------------------------
@@ -257,12 +280,13 @@ void orc_normals(uint64_t seed, uint32_t atom, uint32_t replica, uint64_t step, 
  * frames k = 0..M as in the appendix) and their gradients.
  *   d_k = ||C(X) - R_k||^2 = sum_p (C_p - R_{k,p})^2 / Z0
  *   s   = 1 - (1/M) sum_k k e^{-lambda d_k} / sum_k e^{-lambda d_k}
- *   w   = -(1/lambda) log sum_k e^{-lambda d_k}
+ *   w   = -(1/lambda) log sum_k e^{-lambda d_k}      (w_form 0, eqs (wX), (wXapp))
+ *   w   = -log sum_k e^{-lambda d_k}                (w_form 1, eq (awXa))
  * grad_s / grad_w may be NULL; dk (length K) may be NULL.
  * ---------------------------------------------------------------------- */
 void orc_tube(int n, const double *x, int nc, const int32_t *cidx, int K,
               const double *stack, double Z0, double lambda, double r0,
-              double r_cut, int min_sep, double *s_out, double *w_out,
+              double r_cut, int min_sep, int w_form, double *s_out, double *w_out,
               double *grad_s, double *grad_w, double *dk)
 {
     int64_t P = npairs(nc);
@@ -299,18 +323,20 @@ void orc_tube(int n, const double *x, int nc, const int32_t *cidx, int K,
     int M = K - 1;
     double kbar = Sk / S;
     *s_out = 1.0 - kbar / (double)M;
-    *w_out = -(amax + log(S)) / lambda;
+    /* w_form 0: w = -(1/lambda) log sum; w_form 1: w = -log sum */
+    double wscale = w_form ? 1.0 : 1.0 / lambda;
+    *w_out = -(amax + log(S)) * wscale;
     if (dk) memcpy(dk, d, sizeof(double) * K);
 
     if (grad_s || grad_w) {
-        /* ds/dd_k = (lambda/M) p_k (k - kbar);  dw/dd_k = p_k;
+        /* ds/dd_k = (lambda/M) p_k (k - kbar);  dw/dd_k = lambda wscale p_k;
          * dd_k/dx = (2/Z0) sum_p (C_p - R_{k,p}) dC_p/dx                     */
         if (grad_s) memset(grad_s, 0, sizeof(double) * 3 * n);
         if (grad_w) memset(grad_w, 0, sizeof(double) * 3 * n);
         for (int k = 0; k < K; ++k) {
             double pk = exp(-lambda * d[k] - amax) / S;
             double cs = (lambda / (double)M) * pk * ((double)k - kbar);
-            double cw = pk;
+            double cw = lambda * wscale * pk;
             for (int a = 0; a < nc; ++a)
                 for (int b = a + 1; b < nc; ++b) {
                     int i = cidx[a], j = cidx[b];
@@ -378,7 +404,7 @@ void orc_total_force(const orc_params *p, const orc_system *s, const double *x,
         double *gw = (double *)malloc(sizeof(double) * 3 * n);
         double sv, wv;
         orc_tube(n, x, s->nc, s->cidx, s->K, s->stack, s->Z0, p->lambda, p->r0,
-                 p->r_cut, p->min_seq_sep, &sv, &wv, gs, gw, NULL);
+                 p->r_cut, p->min_seq_sep, p->w_form, &sv, &wv, gs, gw, NULL);
         double sm = fmin(cv[CV_SM], sv);
         double wm = fmin(cv[CV_WM], wv);
         double ds = sv - sm, dw = wv - wm;
@@ -540,7 +566,7 @@ int orc_least_biased(int R, const double *cv, const uint8_t *success)
 typedef struct {
     double A1, A2, A3, s1, s2, s3, w, xm, ym;
     double kT, mob_dt;
-    int32_t bias_mode, pad;
+    int32_t bias_mode, w_form;   /* w_form as for the chains */
     double k_R, lambda, k_s, k_w;
     uint64_t seed;
 } orc_funnel_params;
@@ -566,8 +592,10 @@ double orc_funnel_force(const orc_funnel_params *p, double x, double y, double F
     return U;
 }
 
-/* Euclidean tube variables of (x, y) on the mean path mp [K][2]; gradients optional. */
-void orc_funnel_tube(double x, double y, int K, const double *mp, double lambda,
+/* Euclidean tube variables of (x, y) on the mean path mp [K][2]; gradients
+ * optional.  w_form 0 keeps the 1/lambda of eq (wX) in w; w_form 1 drops it,
+ * as the toy-model section prints w. */
+void orc_funnel_tube(double x, double y, int K, const double *mp, double lambda, int w_form,
                      double *s, double *w, double gs[2], double gw[2])
 {
     int M = K - 1;
@@ -585,8 +613,9 @@ void orc_funnel_tube(double x, double y, int K, const double *mp, double lambda,
         kz += k * e;
     }
     double kbar = kz / z;
+    double wscale = w_form ? 1.0 : 1.0 / lambda;
     *s = 1.0 - kbar / M;
-    *w = -(amax + log(z)) / lambda;
+    *w = -(amax + log(z)) * wscale;
     if (gs || gw) {
         double as[2] = {0.0, 0.0}, aw[2] = {0.0, 0.0};
         for (int k = 0; k < K; ++k) {
@@ -599,7 +628,7 @@ void orc_funnel_tube(double x, double y, int K, const double *mp, double lambda,
         }
         for (int c = 0; c < 2; ++c) {
             if (gs) gs[c] = (lambda / M) * as[c];
-            if (gw) gw[c] = aw[c];
+            if (gw) gw[c] = lambda * wscale * aw[c];
         }
     }
     free(d);
@@ -634,7 +663,7 @@ void orc_funnel_steps(const orc_funnel_params *p, uint32_t traj, double *xy, dou
             cv[CV_EB] = 0.5 * p->k_R * dz * dz;
         } else {
             double sv, wv, gs[2], gw[2];
-            orc_funnel_tube(x, y, K, mp, p->lambda, &sv, &wv, gs, gw);
+            orc_funnel_tube(x, y, K, mp, p->lambda, p->w_form, &sv, &wv, gs, gw);
             double sm = fmin(cv[CV_SM], sv), wm = fmin(cv[CV_WM], wv);
             for (int c = 0; c < 2; ++c) Fb[c] = -p->k_s * (sv - sm) * gs[c] - p->k_w * (wv - wm) * gw[c];
             cv[CV_S] = sv;

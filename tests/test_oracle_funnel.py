@@ -86,34 +86,40 @@ def _mean_path(K=9):
     return np.stack([1.5 * np.sin(np.pi * t), 5.0 * (1 - t)], axis=1)
 
 
-def test_tube_appendix_limit_and_gradients():
+@pytest.mark.parametrize("w_form", [0, 1], ids=["w_with_1_over_lambda", "w_without_1_over_lambda"])
+def test_tube_appendix_limit_and_gradients(w_form):
     mp = _mean_path()
     M = len(mp) - 1
     for l in (0, 4, M):
-        s, w, _, _ = O.funnel_tube(mp[l, 0], mp[l, 1], mp, 400.0)
+        s, w, _, _ = O.funnel_tube(mp[l, 0], mp[l, 1], mp, 400.0, w_form=w_form)
         assert abs(s - (1 - l / M)) < 1e-12 and abs(w) < 1e-12
     h = 1e-6
     for x, y in [(0.3, 3.1), (1.2, 1.0), (-0.5, 4.4)]:
-        s, w, gs, gw = O.funnel_tube(x, y, mp, 0.3)
+        s, w, gs, gw = O.funnel_tube(x, y, mp, 0.3, w_form=w_form)
+        if w_form:
+            s0, w0, gs0, gw0 = O.funnel_tube(x, y, mp, 0.3)
+            assert s == s0 and w == pytest.approx(0.3 * w0, rel=1e-13)
+            np.testing.assert_allclose(gw, 0.3 * gw0, rtol=1e-12)
         for c, (dx, dy) in enumerate([(h, 0), (0, h)]):
-            sp, wp, _, _ = O.funnel_tube(x + dx, y + dy, mp, 0.3)
-            sm, wm, _, _ = O.funnel_tube(x - dx, y - dy, mp, 0.3)
+            sp, wp, _, _ = O.funnel_tube(x + dx, y + dy, mp, 0.3, w_form=w_form)
+            sm, wm, _, _ = O.funnel_tube(x - dx, y - dy, mp, 0.3, w_form=w_form)
             assert gs[c] == pytest.approx((sp - sm) / (2 * h), rel=1e-6, abs=1e-9)
             assert gw[c] == pytest.approx((wp - wm) / (2 * h), rel=1e-6, abs=1e-9)
 
 
-def test_scps_force_is_minus_gradient_of_ratchet_energy_and_T():
+@pytest.mark.parametrize("w_form", [0, 1], ids=["w_with_1_over_lambda", "w_without_1_over_lambda"])
+def test_scps_force_is_minus_gradient_of_ratchet_energy_and_T(w_form):
     mp = _mean_path()
-    p = I.funnel_params(bias_mode=1, kT=0.0, A1=0.0, A2=0.0, A3=0.0, w=0.0)   # bias alone, no noise
+    p = I.funnel_params(bias_mode=1, kT=0.0, A1=0.0, A2=0.0, A3=0.0, w=0.0, w_form=w_form)   # bias alone, no noise
     x0, y0 = 0.9, 2.2
-    s0, w0, _, _ = O.funnel_tube(x0, y0, mp, p["lam"])
+    s0, w0, _, _ = O.funnel_tube(x0, y0, mp, p["lam"], w_form=w_form)
     sm, wm = s0 - 0.2, w0 - 0.5
     cv = np.zeros((1, 8)); cv[0, 5], cv[0, 6] = sm, wm
     xy1, cv1, _ = O.funnel_steps(p, [[x0, y0]], cv, 1, mean_path=mp)
     Fb = (xy1[0] - [x0, y0]) / p["mob_dt"]
 
     def E(x, y):
-        s, w, _, _ = O.funnel_tube(x, y, mp, p["lam"])
+        s, w, _, _ = O.funnel_tube(x, y, mp, p["lam"], w_form=w_form)
         return 0.5 * p["k_s"] * (s - sm) ** 2 + 0.5 * p["k_w"] * (w - wm) ** 2
     h = 1e-6
     g = [(E(x0 + h, y0) - E(x0 - h, y0)) / (2 * h), (E(x0, y0 + h) - E(x0, y0 - h)) / (2 * h)]

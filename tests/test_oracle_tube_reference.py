@@ -50,7 +50,12 @@ def test_appendix_limit_large_lambda():
         assert abs(sv - (1.0 - l / M)) < 1e-15
 
 
-def test_identical_frames_give_uniform_weights():
+@pytest.mark.parametrize("w_form", [0, 1], ids=["w_with_1_over_lambda", "w_without_1_over_lambda"])
+def test_identical_frames_give_uniform_weights(w_form):
+    """K identical frames: p_k = 1/K, so s = 1/2 and grad s = 0 exactly, and
+    log sum_k exp(-lambda d) = log K - lambda d.  With the 1/lambda of eqs
+    (wX), (wXapp): w = d - log(K)/lambda and grad w = grad d; without it, as
+    eq (awXa) prints w: w = lambda d - log K and grad w = lambda grad d."""
     native, frames, s = _path(30, 5, 8)
     cidx = s.cidx
     one = O.contact_map(frames[2], cidx)
@@ -59,15 +64,86 @@ def test_identical_frames_give_uniform_weights():
     Z0 = 3.7
     lam = 13.5
     x = frames[4]
-    sv, wv, gs, gw, dk = O.tube(x, cidx, stack, Z0, lam)
+    sv, wv, gs, gw, dk = O.tube(x, cidx, stack, Z0, lam, w_form=w_form)
     d = np.sum((O.contact_map(x, cidx) - one) ** 2) / Z0
     assert np.allclose(dk, d, rtol=1e-14)
     assert abs(sv - 0.5) < 1e-14
-    assert abs(wv - (d - np.log(K) / lam)) < 1e-12
-    # grad s = 0 and grad w = grad d = (1/Z0) grad z against the single frame
+    # grad s = 0 and grad w = (scale / Z0) grad z against the single frame
     _, gz = O.z_grad(x, cidx, one)
     assert np.abs(gs).max() < 1e-14 * max(1.0, np.abs(gw).max())
-    np.testing.assert_allclose(gw, gz / Z0, rtol=1e-11, atol=1e-15)
+    if w_form == 0:
+        assert abs(wv - (d - np.log(K) / lam)) < 1e-12
+        np.testing.assert_allclose(gw, gz / Z0, rtol=1e-11, atol=1e-15)
+    else:
+        assert abs(wv - (lam * d - np.log(K))) < 1e-11
+        np.testing.assert_allclose(gw, lam * gz / Z0, rtol=1e-11, atol=1e-14)
+
+
+def _printed_contact(r, r0=R0):
+    """eq (Cij) exactly as printed: (1 - (r/r0)^6) / (1 - (r/r0)^10)."""
+    u = r / r0
+    return (1.0 - u ** 6) / (1.0 - u ** 10)
+
+
+def test_distance_norm_sums_over_the_same_pairs_at_seqsep_35():
+    """The normalised distance of the SCPS section divides the sum over
+    |i - j| > 35 of (C - C')^2 by the sum over the same pairs of (C0)^2.
+    Brute force over a 70-bead chain with the printed form of eq (Cij):
+    Z0 and every d_k of a two-frame stack at min_seq_sep = 35."""
+    n, msep = 70, 35
+    rng = np.random.default_rng(17)
+    native = I.compact_native(n, 17)
+    frames = [I.random_coil(n, 18), native + rng.normal(0, 1.0, native.shape)]
+    x = native + rng.normal(0, 2.0, native.shape)
+    cidx = np.arange(n, dtype=np.int32)
+    p = dict(I.config1().params, min_seq_sep=msep)
+    stack = np.array([O.contact_map(f, cidx) for f in frames])
+    so = O.System(n, cidx, np.ones(n), np.zeros(n), p, native_xyz=native, stack=stack)
+
+    def brute(xa, xb=None, ref=None):
+        tot = 0.0
+        for i in range(n):
+            for j in range(i + 1, n):
+                if j - i <= msep:
+                    continue
+                ca = _printed_contact(np.linalg.norm(xa[:, i] - xa[:, j]))
+                cb = 0.0 if xb is None else _printed_contact(np.linalg.norm(xb[:, i] - xb[:, j]))
+                tot += (ca - cb) ** 2
+        return tot
+
+    z0 = brute(native)
+    assert so.Z0 == pytest.approx(z0, rel=1e-12)
+    everything = float(np.sum(O.contact_map(native, cidx) ** 2))
+    assert so.Z0 < 0.5 * everything            # most of the weight sits within 35 of the diagonal
+    assert O.System(n, cidx, np.ones(n), np.zeros(n), dict(p, min_seq_sep=0), native_xyz=native).Z0 == \
+        pytest.approx(everything, rel=1e-14)
+    _, _, _, _, dk = O.tube(x, cidx, stack, so.Z0, 13.5, min_sep=msep, grads=False)
+    for k, f in enumerate(frames):
+        assert dk[k] == pytest.approx(brute(x, f) / z0, rel=1e-11)
+
+
+def test_w_without_one_over_lambda_is_lambda_times_w():
+    """Dropping the 1/lambda multiplies w and grad w by lambda and leaves s
+    alone; the no-1/lambda form's gradients also match central differences."""
+    native, frames, s = _path(24, 6, 5)
+    cidx = s.cidx
+    stack = np.array([O.contact_map(f, cidx) for f in frames])
+    Z0 = float(np.sum(O.contact_map(native, cidx) ** 2))
+    lam = 40.0
+    x = 0.5 * (frames[2] + frames[3])
+    s0, w0, gs0, gw0, d0 = O.tube(x, cidx, stack, Z0, lam)
+    s1, w1, gs1, gw1, d1 = O.tube(x, cidx, stack, Z0, lam, w_form=1)
+    assert s1 == s0 and np.array_equal(d0, d1) and np.array_equal(gs0, gs1)
+    assert w1 == pytest.approx(lam * w0, rel=1e-13)
+    np.testing.assert_allclose(gw1, lam * gw0, rtol=1e-12, atol=1e-15)
+    h = 1e-5
+    for i in (0, 9, 23):
+        for c in range(3):
+            xp = x.copy(); xp[c, i] += h
+            xm = x.copy(); xm[c, i] -= h
+            wp = O.tube(xp, cidx, stack, Z0, lam, grads=False, w_form=1)[1]
+            wm = O.tube(xm, cidx, stack, Z0, lam, grads=False, w_form=1)[1]
+            assert abs((wp - wm) / (2 * h) - gw1[c, i]) < 1e-6 * max(1e-3, np.abs(gw1).max())
 
 
 def test_tube_gradients_central_differences():
@@ -89,22 +165,23 @@ def test_tube_gradients_central_differences():
             assert abs((wp - wm) / (2 * h) - gw[c, i]) < 1e-6 * max(1e-3, np.abs(gw).max())
 
 
-def test_scps_bias_force_is_minus_gradient_of_ratchet_energies():
+@pytest.mark.parametrize("w_form", [0, 1], ids=["w_with_1_over_lambda", "w_without_1_over_lambda"])
+def test_scps_bias_force_is_minus_gradient_of_ratchet_energies(w_form):
     native, frames, s = _path(24, 6, 5)
     cidx = s.cidx
     stack = np.array([O.contact_map(f, cidx) for f in frames])
     p = dict(I.config1().params)
-    p.update(bias_mode=1, lam=25.0, k_s=2.5, k_w=0.8)
+    p.update(bias_mode=1, lam=25.0, k_s=2.5, k_w=0.8, w_form=w_form)
     so = O.System(s.n, cidx, np.ones(s.n), np.zeros(s.n), p, native_xyz=native, stack=stack)
     x = 0.5 * (frames[2] + frames[4])
-    sv, wv, *_ = O.tube(x, cidx, stack, so.Z0, 25.0, grads=False)
+    sv, wv, *_ = O.tube(x, cidx, stack, so.Z0, 25.0, grads=False, w_form=w_form)
     sm, wm = sv - 0.05, wv - 0.01
     cv = np.zeros(8); cv[5] = sm; cv[6] = wm
     _, Fb, cv2 = O.total_force(p, so, x, cv)
     assert cv2[3] == sv and cv2[4] == wv and cv2[5] == sm and cv2[6] == wm
 
     def E(xx):
-        a, b, *_ = O.tube(xx, cidx, stack, so.Z0, 25.0, grads=False)
+        a, b, *_ = O.tube(xx, cidx, stack, so.Z0, 25.0, grads=False, w_form=w_form)
         return 0.5 * 2.5 * max(a - sm, 0) ** 2 + 0.5 * 0.8 * max(b - wm, 0) ** 2
 
     assert abs(cv2[2] - E(x)) < 1e-12
