@@ -69,6 +69,7 @@ typedef enum {
 typedef struct scps_ctx scps_ctx;
 
 #define SCPS_CV_STRIDE 8
+#define SCPS_MAX_FRAMES 128   /* largest SCPS frame stack (the paper's protocol records ~72 frames per path) */
 enum {
     SCPS_CV_Z = 0,   /* z(X) at the last force evaluation (rMD) */
     SCPS_CV_ZM = 1,  /* running minimum z_m (rMD) */
@@ -88,6 +89,7 @@ enum {
 enum { SCPS_INTEGRATOR_OVERDAMPED = 0, SCPS_INTEGRATOR_BAOAB = 1 };
 enum { SCPS_BIAS_RMD = 0, SCPS_BIAS_SCPS = 1 };
 enum { SCPS_EXEC_AUTO = 0, SCPS_EXEC_PER_STEP = 1, SCPS_EXEC_PER_STEP_ALL_TILES = 2 };
+enum { SCPS_W_INV_LAMBDA = 0, SCPS_W_NO_INV_LAMBDA = 1 };
 
 /* Physics and bias parameters (any consistent unit system; the protein-shaped
  * workloads use A, ps, kJ/mol, e and masses in kJ/mol ps^2/A^2). */
@@ -113,6 +115,11 @@ typedef struct {
     int32_t min_seq_sep;  /* contact pairs need |i-j| > min_seq_sep; the paper's all-atom value is 35 */
     int32_t replica_base; /* replica r uses replica_base + r as its noise counter word, so a context that
                              holds one replica of a larger batch reproduces that replica's noise */
+    int32_t w_form;       /* SCPS_W_*: SCPS_W_INV_LAMBDA (0) w = -(1/lambda) log sum_k exp(-lambda d_k), the
+                             definition of eqs (wX) and (wXapp); SCPS_W_NO_INV_LAMBDA (1) w = -log sum_k
+                             exp(-lambda d_k), as eq (awXa), the protocol and the toy model print it (w and
+                             its gradient lambda times larger, so k_w means something else) */
+    int32_t reserved;     /* 0 */
     double dt, gamma, kT;
     double k_bond, r_bond;        /* harmonic bond i,i+1 */
     double lj_eps, lj_sigma;      /* Lennard-Jones 12-6; lj_eps = 0 disables */
@@ -149,12 +156,18 @@ scps_status scps_init_system(const scps_params *params, const scps_topology *top
  *  n_maps == 1: the native map C0 used by z, eq (zrMD), and by the norm of the
  *    tube distance.  Either maps (host float64 [P]) or, when maps is NULL,
  *    native_xyz (host float64 [3][N]) from which C0 = C(X_N), eq (Cij), is
- *    computed on the device in float64.  z0_norm <= 0 sets
- *    Z0 = sum_p (C0_p)^2, the denominator of the normalised distance
- *    ||C - C'||^2 of the SCPS section; otherwise Z0 = z0_norm.
+ *    computed on the device in float64.  z0_norm <= 0 sets Z0 to the sum of
+ *    (C0_ij)^2 over the contact pairs with |i-j| > min_seq_sep, the
+ *    denominator of the normalised distance ||C - C'||^2 of the SCPS
+ *    section (its numerator sums over the same pairs); otherwise
+ *    Z0 = z0_norm.
  *  n_maps >= 2: the SCPS frame stack <C(t_k)>, k = 0..n_maps-1, host float64
- *    [n_maps][P] in maps; native_xyz must be NULL and z0_norm is ignored.
- * Blocks until the upload is done.  Errors: INVALID_ARG, OOM, HIP. */
+ *    [n_maps][P] in maps, at most SCPS_MAX_FRAMES (128) frames; native_xyz
+ *    must be NULL and z0_norm is ignored.  The stack is kept as float32 for
+ *    the per-step passes, with the float64 frame distances
+ *    sum_p (R_jp - R_kp)^2 of every frame pair.
+ * Blocks until the upload is done.  Errors: INVALID_ARG, SHAPE (more than
+ * SCPS_MAX_FRAMES frames; the context stays usable), OOM, HIP. */
 scps_status scps_set_reference_map(scps_ctx *ctx, int32_t system, int32_t n_maps,
                                    const double *maps, const double *native_xyz,
                                    double z0_norm);
@@ -217,8 +230,9 @@ scps_status scps_scale_by_replica(scps_ctx *ctx, const float *in, const double *
  * layout step_replicas records when all replicas run this system).
  * success: host uint8 [n_paths], nonzero = path used (the paper keeps paths
  * that reached the native state).  maps_out: host float64 [n_frames][P] or
- * NULL.  Blocks until done.  Errors: INVALID_ARG, NO_SUCCESS (stack
- * unchanged), OOM, HIP. */
+ * NULL.  n_frames <= SCPS_MAX_FRAMES (128).  Blocks until done.  Errors:
+ * INVALID_ARG, SHAPE (n_frames > SCPS_MAX_FRAMES; stack unchanged), NO_SUCCESS
+ * (stack unchanged), OOM, HIP. */
 scps_status scps_update_reference_from_paths(scps_ctx *ctx, int32_t system, const float *frames,
                                              int32_t n_paths, int32_t n_frames,
                                              const uint8_t *success, double *maps_out);
@@ -227,7 +241,8 @@ scps_status scps_update_reference_from_paths(scps_ctx *ctx, int32_t system, cons
  * appendix, of every replica's configuration against the frame stack of system
  * stack_system, without ratchets or forces: distances d_k = sum_p (C_p -
  * R_kp)^2 / Z0 (Z0 of stack_system), s = 1 - (1/M) sum_k k p_k, w =
- * -(1/lambda) log sum_k exp(-lambda d_k), p = softmax(-lambda d).  Several
+ * -(1/lambda) log sum_k exp(-lambda d_k) (without the 1/lambda for the
+ * context's w_form SCPS_W_NO_INV_LAMBDA), p = softmax(-lambda d).  Several
  * initial conditions of one protein are several systems of the same chain,
  * each with the stack of its own runs; this measures any replica against any
  * of them.  Uses the context's lambda (any bias mode; it must be > 0).
@@ -265,7 +280,10 @@ scps_status scps_eval_sigma(scps_ctx *ctx, int32_t n_stacks, const int32_t *stac
 scps_status scps_least_biased_path(scps_ctx *ctx, const double *cvstate, const uint8_t *success,
                                    int32_t *index, double *t_min);
 
-/* Replace the stream later calls queue work on (a hipStream_t or NULL). */
+/* Replace the stream later calls queue work on (a hipStream_t or NULL).  The
+ * calls of a context share its device scratch buffers, so the new stream is
+ * first made to wait (hipStreamWaitEvent) for the work still queued on the
+ * previous one; nothing blocks the host.  Errors: HIP. */
 scps_status scps_set_stream(scps_ctx *ctx, void *hip_stream);
 
 /* Wait for the context's stream and report replicas flagged non-finite:
@@ -326,7 +344,8 @@ typedef struct {
     double mobility_dt;   /* dt / (m gamma): X += mobility_dt F + sqrt(2 kT mobility_dt) xi (the paper's gamma dt) */
     int32_t bias_mode;    /* SCPS_BIAS_RMD: F_b = -k_R (z - z_m) grad z, z = |X|;
                              SCPS_BIAS_SCPS: ratchets (Fw),(Fs) on s, w of the Euclidean tube around the mean path */
-    int32_t reserved;     /* 0 */
+    int32_t w_form;       /* SCPS_W_INV_LAMBDA: w = -(1/lambda) log sum_k exp(-lambda d_k); SCPS_W_NO_INV_LAMBDA:
+                             w = -log sum_k exp(-lambda d_k), as the toy-model section prints it */
     double k_R, lambda, k_s, k_w;
     uint64_t seed;        /* Philox key; trajectory t draws from counter (0, first_id + t, step_lo, step_hi) and
                              uses the Box-Muller pair of the first two words for (x, y) */
@@ -335,14 +354,15 @@ typedef struct {
 /* Advance n_traj trajectories by n_steps overdamped steps from global step
  * step0.  The discrete tube variables: d_k = |X - P_k|^2 over the mean-path
  * frames P_0..P_M, s = 1 - (1/M) sum_k k p_k, w = -(1/lambda) log sum_k
- * exp(-lambda d_k), p = softmax(-lambda d).
+ * exp(-lambda d_k) (without the 1/lambda for w_form SCPS_W_NO_INV_LAMBDA),
+ * p = softmax(-lambda d).
  *   xy: device float64 [n_traj][2], in/out.
  *   cvstate: device float64 [n_traj][SCPS_CV_STRIDE] as for the chains (z, z_m,
  *            E_b, s, w, s_m, w_m, T; minima start at +INFINITY, T at 0; T adds
  *            mobility_dt |F_b|^2 per step).
  *   record_every > 0: frames (device float64 [n_steps/record_every + 1][n_traj][2])
  *            receives X every record_every steps, the start first.
- *   mean_path: device float64 [n_path_frames][2], 2 .. 64 frames (bias_mode SCPS).
+ *   mean_path: device float64 [n_path_frames][2], 2 .. 128 frames (bias_mode SCPS).
  * Asynchronous on hip_stream (a hipStream_t or NULL).  Errors: INVALID_ARG,
  * SHAPE, HIP. */
 scps_status scps_funnel_steps(const scps_funnel_params *p, int32_t n_traj, int32_t first_id, double *xy,

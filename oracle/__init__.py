@@ -74,9 +74,12 @@ class OrcSystem(C.Structure):
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_build.LIB) or os.path.getmtime(_build.LIB) < os.path.getmtime(_build.SRC):
-            _build.build()
-        L = C.CDLL(_build.LIB)
+        path = os.environ.get("ORACLE_LIB")          # e.g. a sanitizer build of the same source
+        if not path:
+            path = _build.LIB
+            if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SRC):
+                _build.build()
+        L = C.CDLL(path)
         d, i32, i64, u64, vp = C.c_double, C.c_int32, C.c_int64, C.c_uint64, C.c_void_p
         L.orc_contact.restype = d
         L.orc_contact.argtypes = [d, d, d, vp]

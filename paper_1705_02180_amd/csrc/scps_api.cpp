@@ -19,6 +19,9 @@
 
 using namespace scps;
 
+static_assert(KMAX == SCPS_MAX_FRAMES, "the header states the frame-stack limit the kernels are built for");
+static_assert(FUNNEL_KMAX == SCPS_MAX_FRAMES, "mean paths of the toy model take as many frames as stacks");
+
 namespace {
 
 thread_local std::string g_err;
@@ -45,7 +48,7 @@ struct SysHost {
     double Z0 = 0.0;
     float *d_stack = nullptr;      // [ntile_c][K][4096]
     float *d_stack_pm = nullptr;   // [ntile_c][4096][stack_pm_width(K)]
-    double *d_R2 = nullptr;        // [K]
+    double *d_G = nullptr;         // [K][K] frame distances sum_p (R_j - R_k)^2
     int K = 0;
     double *d_R2tile = nullptr;    // [ntile_c] native map: sum of R^2 over each tile's counted pairs
     double R2total = 0.0;          // their sum (added to z for the tiles the culled path skips)
@@ -61,6 +64,7 @@ struct scps_ctx {
     // distance pass (fork and join through events on the caller's stream)
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_switch = nullptr;   // orders a new stream after the old one (scps_set_stream)
     int R = 0;
     std::vector<SysHost> sys;
     std::vector<int> rep_sys;
@@ -81,7 +85,10 @@ struct scps_ctx {
     double *d_acc = nullptr, *d_scale = nullptr, *d_negone = nullptr;
     double *d_zpart = nullptr;                       // z partial of every tile item
     int *d_first_all = nullptr, *d_first_con = nullptr;   // [R+1] item ranges per replica
-    double *d_X = nullptr, *d_Q = nullptr, *d_csum = nullptr;   // SCPS: sum C R_k, sum C^2, sum c_k
+    double *d_X = nullptr, *d_Q = nullptr, *d_csum = nullptr;   // SCPS: sum u R_k, sum u^2, sum c_k (u = C - R_j)
+    int *d_jref = nullptr;        // SCPS: reference frame j of each replica's distance expansion
+    int *d_jref_eval = nullptr;   // the same for the tube evaluation calls
+    bool jref_init = true;        // a stack changed: pick every replica's reference frame before stepping
     float *d_coef = nullptr;      // SCPS: c_k / Z0 per replica
     float *d_E = nullptr;         // SCPS, two-pass form: effective references, replica r at RepDesc::eoff
     ScpsGroup *d_groups = nullptr;
@@ -169,6 +176,7 @@ KParams make_kparams(const scps_params &p) {
     k.lambda = p.lambda;
     k.k_s = p.k_s;
     k.k_w = p.k_w;
+    k.wscale = p.w_form == SCPS_W_NO_INV_LAMBDA ? 1.0 : (p.lambda > 0 ? 1.0 / p.lambda : 0.0);
     k.seed_lo = (uint32_t)p.seed;
     k.seed_hi = (uint32_t)(p.seed >> 32);
     k.rep_base = (uint32_t)p.replica_base;
@@ -194,7 +202,7 @@ scps_status upload_sysdesc(scps_ctx *c) {
         o.ref = h.d_ref;
         o.stack = h.d_stack;
         o.stack_pm = h.d_stack_pm;
-        o.R2 = h.d_R2;
+        o.G = h.d_G;
         o.R2tile = h.d_R2tile;
         o.tiles = h.d_sched;
         o.tmask = h.d_sched_mask;
@@ -357,6 +365,10 @@ scps_status ensure_scps_groups(scps_ctx *c) {
     HIP_TRY(c, hipMemset(c->d_X, 0, (size_t)R * c->kmax * sizeof(double)));
     HIP_TRY(c, dalloc(c, &c->d_Q, R));
     HIP_TRY(c, hipMemset(c->d_Q, 0, R * sizeof(double)));
+    HIP_TRY(c, dalloc(c, &c->d_jref, R));
+    HIP_TRY(c, hipMemset(c->d_jref, 0, R * sizeof(int)));
+    HIP_TRY(c, dalloc(c, &c->d_jref_eval, R));
+    c->jref_init = true;
     std::vector<ScpsGroup> groups;
     std::vector<ScpsItem> items;
     for (int s = 0; s < (int)c->sys.size(); ++s) {
@@ -404,6 +416,8 @@ scps_status init_impl(const scps_params *params, const scps_topology *topo, int3
         return fail(SCPS_ERR_INVALID_ARG, "exec_mode must be 0, 1 or 2");
     if (!(p.dt > 0) || !(p.gamma > 0) || !(p.kT >= 0) || !(p.r0_contact > 0))
         return fail(SCPS_ERR_INVALID_ARG, "dt, gamma, r0_contact must be > 0 and kT >= 0");
+    if (p.w_form != SCPS_W_INV_LAMBDA && p.w_form != SCPS_W_NO_INV_LAMBDA)
+        return fail(SCPS_ERR_INVALID_ARG, "w_form must be 0 (w with 1/lambda) or 1 (without)");
     if (p.nb_excl < 1 || p.min_seq_sep < 0 || p.replica_base < 0)
         return fail(SCPS_ERR_INVALID_ARG, "nb_excl must be >= 1, min_seq_sep and replica_base >= 0");
     if (p.bias_mode == SCPS_BIAS_SCPS && !(p.lambda > 0))
@@ -608,19 +622,21 @@ scps_status init_impl(const scps_params *params, const scps_topology *topo, int3
     return SCPS_OK;
 }
 
-// The pair-major copy of a system's frame stack and sum_p R_kp^2 per frame,
-// rebuilt whenever the stack changes.
+// The pair-major copy of a system's frame stack and its frame distances G,
+// rebuilt whenever the stack changes; every replica's reference frame is
+// picked again before the next SCPS step.
 scps_status make_pairmajor(scps_ctx *c, SysHost &h) {
     dfree(c, h.d_stack_pm);
-    dfree(c, h.d_R2);
+    dfree(c, h.d_G);
     h.d_stack_pm = nullptr;
-    h.d_R2 = nullptr;
+    h.d_G = nullptr;
     HIP_TRY(c, dalloc(c, &h.d_stack_pm, (size_t)stack_pm_width(h.K) * h.ntile_c * 4096));
-    HIP_TRY(c, dalloc(c, &h.d_R2, h.K));
-    HIP_TRY(c, hipMemsetAsync(h.d_R2, 0, h.K * sizeof(double), c->stream));
-    HIP_TRY(c, launch_stack_pairmajor(h.nc, h.ncb, h.K, c->prm.min_seq_sep, h.d_perm, h.d_stack, h.d_stack_pm,
-                                      h.d_R2, c->stream));
+    HIP_TRY(c, dalloc(c, &h.d_G, (size_t)h.K * h.K));
+    HIP_TRY(c, hipMemsetAsync(h.d_G, 0, (size_t)h.K * h.K * sizeof(double), c->stream));
+    HIP_TRY(c, launch_stack_pairmajor(h.nc, h.ncb, h.K, h.d_stack, h.d_stack_pm, c->stream));
+    HIP_TRY(c, launch_stack_gram(h.nc, h.ncb, h.K, c->prm.min_seq_sep, h.d_perm, h.d_stack, h.d_G, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->jref_init = true;
     return SCPS_OK;
 }
 
@@ -635,7 +651,7 @@ scps_status set_ref_impl(scps_ctx *c, int32_t s, int32_t n_maps, const double *m
         if (!h.d_ref) HIP_TRY(c, dalloc(c, &h.d_ref, (size_t)h.ntile_c * 4096));
         double *d_packed = nullptr, *d_sum = nullptr;
         HIP_TRY(c, dalloc(c, &d_packed, (size_t)std::max<int64_t>(P, 1)));
-        HIP_TRY(c, dalloc(c, &d_sum, 1 + sum_squares_scratch()));
+        HIP_TRY(c, dalloc(c, &d_sum, 1 + std::max(sum_squares_scratch(), h.nc)));
         if (maps) {
             HIP_TRY(c, hipMemcpy(d_packed, maps, P * sizeof(double), hipMemcpyHostToDevice));
             HIP_TRY(c, launch_pack_to_tiles(1, h.nc, h.ncb, d_packed, h.d_ref, c->stream));
@@ -650,7 +666,13 @@ scps_status set_ref_impl(scps_ctx *c, int32_t s, int32_t n_maps, const double *m
         }
         double zz = z0;
         if (!(z0 > 0.0)) {
-            HIP_TRY(c, launch_sum_squares(P, d_packed, d_sum + 1, d_sum, c->stream));
+            // the denominator of the normalised distance sums over the pairs its
+            // numerator does: |i-j| > min_seq_sep
+            if (c->prm.min_seq_sep > 0)
+                HIP_TRY(c, launch_sum_squares_sep(h.nc, c->prm.min_seq_sep, h.d_perm, d_packed, d_sum + 1, d_sum,
+                                                  c->stream));
+            else
+                HIP_TRY(c, launch_sum_squares(P, d_packed, d_sum + 1, d_sum, c->stream));
             HIP_TRY(c, hipStreamSynchronize(c->stream));
             HIP_TRY(c, hipMemcpy(&zz, d_sum, sizeof(double), hipMemcpyDeviceToHost));
         }
@@ -680,7 +702,7 @@ scps_status set_ref_impl(scps_ctx *c, int32_t s, int32_t n_maps, const double *m
         }
     } else {
         if (!maps || xyz) return fail(SCPS_ERR_INVALID_ARG, "a frame stack needs maps and no native_xyz");
-        if (n_maps > KMAX) return fail(SCPS_ERR_SHAPE, "at most 64 frames in an SCPS stack");
+        if (n_maps > KMAX) return fail(SCPS_ERR_SHAPE, "at most " + std::to_string(KMAX) + " frames in an SCPS stack");
         if (h.K != n_maps) {
             dfree(c, h.d_stack);
             h.d_stack = nullptr;
@@ -698,6 +720,13 @@ scps_status set_ref_impl(scps_ctx *c, int32_t s, int32_t n_maps, const double *m
         if (st != SCPS_OK) return st;
     }
     return upload_sysdesc(c);
+}
+
+// The largest frame stack among the systems the replicas run (SCPS passes).
+int max_stack_frames(const scps_ctx *c) {
+    int k = 1;
+    for (int r = 0; r < c->R; ++r) k = std::max(k, c->sys[c->rep_sys[r]].K);
+    return k;
 }
 
 scps_status step_impl(scps_ctx *c, float *x, float *v, double *cv, int64_t n_steps, uint64_t step0,
@@ -752,6 +781,17 @@ scps_status step_impl(scps_ctx *c, float *x, float *v, double *cv, int64_t n_ste
         } else {
             // distances to every frame (matrix cores), tube variables and
             // ratchets, effective references (matrix cores), bias + physics
+            if (c->jref_init) {
+                // a new stack: every replica's reference frame is its nearest frame,
+                // from one distance pass around frame 0
+                HIP_TRY(c, launch_scps_dist(c->kp, c->d_sysd, c->d_reps, c->d_groups, c->d_sitems, c->n_sitems,
+                                            max_stack_frames(c), nullptr, c->d_xs, c->d_X, c->d_Q, c->kmax, -1,
+                                            c->stream));
+                HIP_TRY(c, launch_tube_eval(c->prm.lambda, c->kp.wscale, nullptr, c->d_jref, c->d_sysd, c->d_reps,
+                                            c->R, c->kmax, -1, c->d_X, c->d_Q, nullptr, nullptr, nullptr, 0.0, 1,
+                                            c->stream));
+                c->jref_init = false;
+            }
             if (c->side) {
                 // nonbonded forces (acc components 0..2) need only the positions:
                 // they overlap the bandwidth-bound distance pass
@@ -761,10 +801,11 @@ scps_status step_impl(scps_ctx *c, float *x, float *v, double *cv, int64_t n_ste
                                         c->d_xs, c->d_acc, c->d_zpart, nullptr, nullptr, c->side));
                 HIP_TRY(c, hipEventRecord(c->ev_join, c->side));
             }
-            HIP_TRY(c, launch_scps_dist(c->kp, c->d_sysd, c->d_reps, c->d_groups, c->d_sitems, c->n_sitems, c->d_xs,
-                                        c->d_X, c->d_Q, c->kmax, -1, c->stream));
-            HIP_TRY(c, launch_finalize_scps(c->kp, c->d_sysd, c->d_reps, c->R, c->kmax, c->d_X, c->d_Q, cv,
-                                            c->d_coef, c->d_csum, c->stream));
+            HIP_TRY(c, launch_scps_dist(c->kp, c->d_sysd, c->d_reps, c->d_groups, c->d_sitems, c->n_sitems,
+                                        max_stack_frames(c), c->d_jref, c->d_xs, c->d_X, c->d_Q, c->kmax, -1,
+                                        c->stream));
+            HIP_TRY(c, launch_finalize_scps(c->kp, c->d_sysd, c->d_reps, c->R, c->kmax, c->d_jref, c->d_X, c->d_Q,
+                                            cv, c->d_coef, c->d_csum, c->stream));
             if (c->prm.exec_mode == SCPS_EXEC_PER_STEP_ALL_TILES) {
                 // two passes: effective references to device memory, then every tile pair
                 HIP_TRY(c, launch_scps_eff(c->d_sysd, c->d_reps, c->d_groups, c->d_sitems, c->n_sitems, c->d_coef,
@@ -776,7 +817,8 @@ scps_status step_impl(scps_ctx *c, float *x, float *v, double *cv, int64_t n_ste
                 // the nonbonded forces and bonds (mode 4, every tile pair) ran on the side
                 // stream beside the distance pass and are joined before the update
                 HIP_TRY(c, launch_scps_bias(c->kp, c->d_sysd, c->d_reps, c->d_groups, c->d_sitems, c->n_sitems,
-                                            c->d_xs, c->d_coef, c->d_csum, c->kmax, c->d_acc, c->stream));
+                                            max_stack_frames(c), c->d_xs, c->d_coef, c->d_csum, c->kmax, c->d_acc,
+                                            c->stream));
                 if (c->side)
                     HIP_TRY(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
                 else
@@ -811,7 +853,7 @@ scps_status update_ref_impl(scps_ctx *c, int32_t s, const float *frames, int32_t
     if (s < 0 || s >= (int)c->sys.size()) return fail(SCPS_ERR_INVALID_ARG, "system index out of range");
     if (!frames || !success) return fail(SCPS_ERR_INVALID_ARG, "frames and success must not be NULL");
     if (n_paths < 1 || n_frames < 1) return fail(SCPS_ERR_INVALID_ARG, "n_paths and n_frames must be >= 1");
-    if (n_frames > KMAX) return fail(SCPS_ERR_SHAPE, "at most 64 frames in an SCPS stack");
+    if (n_frames > KMAX) return fail(SCPS_ERR_SHAPE, "at most " + std::to_string(KMAX) + " frames in an SCPS stack");
     SysHost &h = c->sys[s];
     std::vector<int> succ;
     for (int q = 0; q < n_paths; ++q)
@@ -893,10 +935,18 @@ scps_status eval_tube_impl(scps_ctx *c, int32_t n_stacks, const int32_t *stacks,
     if (st != SCPS_OK) return st;
     HIP_TRY(c, launch_gather(c->d_sysd, c->d_reps, c->R, c->n_pad_max, x, nullptr, c->d_xs, nullptr, c->stream));
     for (int k = 0; k < n_stacks; ++k) {
-        HIP_TRY(c, launch_scps_dist(c->kp, c->d_sysd, c->d_reps, c->d_groups, c->d_sitems, c->n_sitems, c->d_xs,
-                                    c->d_X, c->d_Q, c->kmax, stacks[k], c->stream));
-        HIP_TRY(c, launch_tube_eval(c->prm.lambda, c->d_sysd, c->d_reps, c->R, c->kmax, stacks[k], c->d_X, c->d_Q,
-                                    s, w, sigma, 1.0 / n_stacks, k == 0, c->stream));
+        // two passes: around frame 0, to find each replica's nearest frame, then around that frame
+        const int K = c->sys[stacks[k]].K;
+        HIP_TRY(c, launch_scps_dist(c->kp, c->d_sysd, c->d_reps, c->d_groups, c->d_sitems, c->n_sitems, K, nullptr,
+                                    c->d_xs, c->d_X, c->d_Q, c->kmax, stacks[k], c->stream));
+        HIP_TRY(c, launch_tube_eval(c->prm.lambda, c->kp.wscale, nullptr, c->d_jref_eval, c->d_sysd, c->d_reps, c->R,
+                                    c->kmax, stacks[k], c->d_X, c->d_Q, nullptr, nullptr, nullptr, 0.0, 1,
+                                    c->stream));
+        HIP_TRY(c, launch_scps_dist(c->kp, c->d_sysd, c->d_reps, c->d_groups, c->d_sitems, c->n_sitems, K,
+                                    c->d_jref_eval, c->d_xs, c->d_X, c->d_Q, c->kmax, stacks[k], c->stream));
+        HIP_TRY(c, launch_tube_eval(c->prm.lambda, c->kp.wscale, c->d_jref_eval, nullptr, c->d_sysd, c->d_reps, c->R,
+                                    c->kmax, stacks[k], c->d_X, c->d_Q, s, w, sigma, 1.0 / n_stacks, k == 0,
+                                    c->stream));
     }
     return SCPS_OK;
 }
@@ -925,6 +975,12 @@ scps_status autotune_impl(scps_ctx *c, const float *x, const float *v, const dou
     int *tflags = nullptr;   // the caller's non-finite flags, kept across the trial runs
     HIP_TRY(c, dalloc(c, &tflags, c->R));
     HIP_TRY(c, hipMemcpyAsync(tflags, c->d_flags, c->R * sizeof(int), hipMemcpyDeviceToDevice, c->stream));
+    int *tjref = nullptr;    // SCPS: the reference frames, also kept across the trial runs
+    const bool saved_jref_init = c->jref_init;
+    if (c->d_jref) {
+        HIP_TRY(c, dalloc(c, &tjref, c->R));
+        HIP_TRY(c, hipMemcpyAsync(tjref, c->d_jref, c->R * sizeof(int), hipMemcpyDeviceToDevice, c->stream));
+    }
     HIP_TRY(c, dalloc(c, &tx, nx));
     if (v) HIP_TRY(c, dalloc(c, &tv, nx));
     HIP_TRY(c, dalloc(c, &tcv, (size_t)c->R * CV_STRIDE));
@@ -960,8 +1016,11 @@ scps_status autotune_impl(scps_ctx *c, const float *x, const float *v, const dou
     (void)hipEventDestroy(e1);
     // flags raised by the trial runs on the copies do not count
     HIP_TRY(c, hipMemcpyAsync(c->d_flags, tflags, c->R * sizeof(int), hipMemcpyDeviceToDevice, c->stream));
+    if (tjref) HIP_TRY(c, hipMemcpyAsync(c->d_jref, tjref, c->R * sizeof(int), hipMemcpyDeviceToDevice, c->stream));
+    c->jref_init = saved_jref_init;
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     dfree(c, tflags);
+    dfree(c, tjref);
     dfree(c, tx);
     dfree(c, tv);
     dfree(c, tcv);
@@ -1096,7 +1155,14 @@ scps_status scps_eval_sigma(scps_ctx *ctx, int32_t n_stacks, const int32_t *stac
 scps_status scps_set_stream(scps_ctx *ctx, void *hip_stream) {
     scps_status st;
     if (!usable(ctx, &st)) return st;
-    ctx->stream = (hipStream_t)hip_stream;
+    hipStream_t next = (hipStream_t)hip_stream;
+    if (next == ctx->stream) return SCPS_OK;
+    // every call shares the context's scratch buffers: work queued from now on
+    // waits for what is still queued on the old stream
+    if (!ctx->ev_switch) HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->ev_switch, hipEventDisableTiming));
+    HIP_TRY(ctx, hipEventRecord(ctx->ev_switch, ctx->stream));
+    HIP_TRY(ctx, hipStreamWaitEvent(next, ctx->ev_switch, 0));
+    ctx->stream = next;
     return SCPS_OK;
 }
 
@@ -1169,10 +1235,12 @@ scps_status scps_funnel_steps(const scps_funnel_params *p, int32_t n_traj, int32
     if (!(p->mobility_dt > 0) || !(p->kT >= 0)) return fail(SCPS_ERR_INVALID_ARG, "mobility_dt > 0, kT >= 0");
     if (p->bias_mode != SCPS_BIAS_RMD && p->bias_mode != SCPS_BIAS_SCPS)
         return fail(SCPS_ERR_INVALID_ARG, "bias_mode must be 0 (rMD) or 1 (tube ratchets)");
+    if (p->w_form != SCPS_W_INV_LAMBDA && p->w_form != SCPS_W_NO_INV_LAMBDA)
+        return fail(SCPS_ERR_INVALID_ARG, "w_form must be 0 (w with 1/lambda) or 1 (without)");
     if (p->bias_mode == SCPS_BIAS_SCPS) {
         if (!mean_path) return fail(SCPS_ERR_INVALID_ARG, "the tube ratchets need a mean path");
         if (n_path_frames < 2 || n_path_frames > FUNNEL_KMAX)
-            return fail(SCPS_ERR_SHAPE, "a mean path has 2 .. 64 frames");
+            return fail(SCPS_ERR_SHAPE, "a mean path has 2 .. " + std::to_string(FUNNEL_KMAX) + " frames");
         if (!(p->lambda > 0)) return fail(SCPS_ERR_INVALID_ARG, "lambda must be > 0");
     }
     FunnelK k{};
@@ -1181,6 +1249,7 @@ scps_status scps_funnel_steps(const scps_funnel_params *p, int32_t n_traj, int32
     k.w = p->w; k.xm = p->xm; k.ym = p->ym;
     k.kT = p->kT; k.mob_dt = p->mobility_dt;
     k.k_R = p->k_R; k.lambda = p->lambda; k.k_s = p->k_s; k.k_w = p->k_w;
+    k.wscale = p->w_form == SCPS_W_NO_INV_LAMBDA ? 1.0 : (p->lambda > 0 ? 1.0 / p->lambda : 0.0);
     k.seed_lo = (uint32_t)p->seed; k.seed_hi = (uint32_t)(p->seed >> 32);
     k.bias_mode = p->bias_mode;
     hipError_t e = launch_funnel_steps(k, n_traj, first_id, reinterpret_cast<double2 *>(xy), cvstate, n_steps, step0,
@@ -1222,6 +1291,7 @@ void scps_destroy(scps_ctx *ctx) {
     }
     if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
     if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+    if (ctx->ev_switch) (void)hipEventDestroy(ctx->ev_switch);
     for (void *p : ctx->owned) (void)hipFree(p);
     delete ctx;
 }

@@ -6,12 +6,13 @@
 
 namespace scps {
 
-constexpr int FUNNEL_KMAX = 64;   // frames of a mean path
+constexpr int FUNNEL_KMAX = 128;  // frames of a mean path
 
 struct FunnelK {
     double A1, A2, A3, s1, s2, s3, w, xm, ym;
     double kT, mob_dt;            // overdamped step: X += mob_dt F + sqrt(2 kT mob_dt) xi
     double k_R, lambda, k_s, k_w;
+    double wscale;                // w = -wscale log sum_k exp(-lambda d_k): 1/lambda, or 1 without the 1/lambda
     uint32_t seed_lo, seed_hi;
     int bias_mode;                // 0: rMD on z = |X|; 1: tube ratchets on the mean path
 };

@@ -73,7 +73,7 @@ __global__ __launch_bounds__(256) void k_funnel_steps(const FunnelK P, int n_tra
         } else {
             // tube variables: the largest exponent, then the weights with the sums
             // sum_k e_k grad d_k and sum_k k e_k grad d_k, from which
-            // grad s = (lambda / M) sum_k p_k (k - kbar) grad d_k and grad w = sum_k p_k grad d_k
+            // grad s = (lambda / M) sum_k p_k (k - kbar) grad d_k and grad w = lambda wscale sum_k p_k grad d_k
             double a = -INFINITY;
             for (int k = 0; k < K; ++k) {
                 const double ex = x - path[k].x, ey = y - path[k].y;
@@ -92,9 +92,10 @@ __global__ __launch_bounds__(256) void k_funnel_steps(const FunnelK P, int n_tra
             }
             const double kbar = s1 / s0;
             sv = 1.0 - kbar / M;
-            wv = -(a + log(s0)) / P.lambda;
+            wv = tube_w(a, s0, P.wscale);
             const double gsx = (P.lambda / M) * (bx_ - kbar * ax) / s0, gsy = (P.lambda / M) * (by_ - kbar * ay) / s0;
-            const double gwx = ax / s0, gwy = ay / s0;
+            const double lw = P.lambda * P.wscale;
+            const double gwx = lw * ax / s0, gwy = lw * ay / s0;
             sm = fmin(sm, sv);
             wm = fmin(wm, wv);
             const double ds = sv - sm, dw = wv - wm;

@@ -7,7 +7,7 @@
 namespace scps {
 
 constexpr int TILE = 64;          // tile edge = wavefront width
-constexpr int KMAX = 64;          // largest SCPS frame stack handled per pass
+constexpr int KMAX = 128;         // largest SCPS frame stack (the distance pass takes it in blocks of 64)
 constexpr int CV_STRIDE = 8;
 enum { CV_Z = 0, CV_ZM = 1, CV_EB = 2, CV_S = 3, CV_W = 4, CV_SM = 5, CV_WM = 6, CV_T = 7 };
 
@@ -30,6 +30,7 @@ struct KParams {
     double k_bond, r_bond;
     double k_R;
     double lambda, k_s, k_w;
+    double wscale;       // w = -wscale log sum_k exp(-lambda d_k): 1/lambda, or 1 without the 1/lambda
     uint32_t seed_lo, seed_hi;
     uint32_t rep_base;
 };
@@ -48,7 +49,7 @@ struct SysDesc {
     const float *ref;        // native map tiles [ntile_c][64*64]
     const float *stack;      // SCPS frames [ntile_c][K][64*64]
     const float *stack_pm;   // the same frames pair-major: [ntile_c][64*64][stack_pm_width(K)]
-    const double *R2;        // [K] sum over the counted contact pairs of R_k^2
+    const double *G;         // [K][K] sum over the counted contact pairs of (R_j - R_k)^2
     const double *R2tile;    // [ntile_c] per native-map tile: sum over its counted contact pairs of R^2
     const int2 *tiles;       // persistent work list, costliest first (see build_schedule)
     const uint64_t *tmask;   // per work-list item: sub-steps that need the per-pair predicates
@@ -146,23 +147,31 @@ hipError_t launch_pairs(int mode, int nbk, const KParams &P, const SysDesc *sysd
                         const TileItem *items, int n_items, const float4 *xs, double *acc, double *zpart,
                         const float *eff, const double *csum, hipStream_t st);
 // stack_sys: -1 for each group's own system's stack, else that system's
-// (same chain and contact set as every group's).
+// (same chain and contact set as every group's).  max_frames: the largest K
+// of the stacks read (1 .. KMAX), which sets the number of 64-frame blocks.
+// jref [R]: each replica's reference frame j of the distance expansion (NULL:
+// frame 0); X receives Y_k = sum_p (C_p - R_jp) R_kp and Q sum_p (C_p - R_jp)^2.
 hipError_t launch_scps_dist(const KParams &P, const SysDesc *sysd, const RepDesc *reps, const ScpsGroup *groups,
-                            const ScpsItem *items, int n_items, const float4 *xs, double *X, double *Q, int kmax,
-                            int stack_sys, hipStream_t st);
-// s, w, sigma of every replica from the distances in X, Q (which it clears).
-hipError_t launch_tube_eval(double lam, const SysDesc *sysd, const RepDesc *reps, int R, int kmax, int stack_sys,
-                            double *X, double *Q, double *s, double *w, double *sigma, double weight, int first,
-                            hipStream_t st);
+                            const ScpsItem *items, int n_items, int max_frames, const int *jref, const float4 *xs,
+                            double *X, double *Q, int kmax, int stack_sys, hipStream_t st);
+// s, w, sigma of every replica from the distances in X, Q (which it clears);
+// jref_in: the reference frames the distance pass used (NULL: frame 0);
+// jref_out (nullable): each replica's frame of largest weight.
+hipError_t launch_tube_eval(double lam, double wscale, const int *jref_in, int *jref_out, const SysDesc *sysd,
+                            const RepDesc *reps, int R, int kmax, int stack_sys, double *X, double *Q, double *s,
+                            double *w, double *sigma, double weight, int first, hipStream_t st);
 hipError_t launch_scps_eff(const SysDesc *sysd, const RepDesc *reps, const ScpsGroup *groups, const ScpsItem *items,
                            int n_items, const float *coef, int kmax, float *E, hipStream_t st);
 // Effective references and the contact bias forces in one pass (no E in
 // device memory): adds the bias gradient terms to acc components 3..5.
 hipError_t launch_scps_bias(const KParams &P, const SysDesc *sysd, const RepDesc *reps, const ScpsGroup *groups,
-                            const ScpsItem *items, int n_items, const float4 *xs, const float *coef,
+                            const ScpsItem *items, int n_items, int max_frames, const float4 *xs, const float *coef,
                             const double *csum, int kmax, double *acc, hipStream_t st);
-hipError_t launch_stack_pairmajor(int nc, int ncb, int K, int min_sep, const int *perm, const float *stack,
-                                  float *stack_pm, double *R2, hipStream_t st);
+hipError_t launch_stack_pairmajor(int nc, int ncb, int K, const float *stack, float *stack_pm, hipStream_t st);
+// G[j][k] = sum over the counted contact pairs of (R_j - R_k)^2 in float64 from
+// a tile-major stack; G must be zero on entry.
+hipError_t launch_stack_gram(int nc, int ncb, int K, int min_sep, const int *perm, const float *stack, double *G,
+                             hipStream_t st);
 
 // first[r] .. first[r+1]: replica r's items in the list whose z partials are in zpart
 // zbase: NULL, or a per-replica constant added to z (neighbour-list path).
@@ -190,8 +199,10 @@ hipError_t launch_nl_force(int nbk, const KParams &P, const SysDesc *sysd, const
 // (float32) entries, in float64.
 hipError_t launch_tile_sumsq(int nc, int ncb, int min_sep, const int *perm, const float *tiles, double *out,
                              hipStream_t st);
+// jref [R]: read as the distance pass's reference frames, then set to each
+// replica's frame of largest weight for the next step.
 hipError_t launch_finalize_scps(const KParams &P, const SysDesc *sysd, const RepDesc *reps, int R,
-                                int kmax, double *X, double *Q, double *cv, float *coef, double *csum,
+                                int kmax, int *jref, double *X, double *Q, double *cv, float *coef, double *csum,
                                 hipStream_t st);
 hipError_t launch_integrate(const KParams &P, const SysDesc *sysd, const RepDesc *reps, int R,
                             int n_pad_max, float4 *xs, float4 *vs, double *acc,
@@ -210,6 +221,10 @@ hipError_t launch_pack_to_tiles(int n_maps, int nc, int ncb, const double *packe
                                 hipStream_t st);
 int sum_squares_scratch();   // doubles of scratch launch_sum_squares needs
 hipError_t launch_sum_squares(int64_t m, const double *v, double *part, double *out, hipStream_t st);
+// The sum over the packed contact pairs a < b with |perm[a] - perm[b]| >
+// min_sep of v^2 (part: scratch of nc doubles).
+hipError_t launch_sum_squares_sep(int nc, int min_sep, const int *perm, const double *v, double *part, double *out,
+                                  hipStream_t st);
 // Binary occupancy of an nx x ny grid by the points of a and of b (occ:
 // scratch int [2 nx ny]) and counts[3] = {cells of a, cells of b, cells of both}.
 hipError_t launch_path_occupancy(const float *xy_a, int64_t n_a, const float *xy_b, int64_t n_b, double x0,

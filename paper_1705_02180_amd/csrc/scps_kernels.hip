@@ -1316,29 +1316,35 @@ __global__ void k_reduce_z(const int *__restrict__ first, const double *__restri
 
 // SCPS tube variables per replica (one wavefront each), from the squared
 // distances d_k Z0 = sum_p (C_p - R_kp)^2 to every frame k = 0..M of the
-// stack, assembled in float64 as Q - 2 X_k + R2_k (Q = sum C^2 and
-// X_k = sum C R_k from k_scps_dist, R2_k = sum R_k^2 of the stack):
-//   s = 1 - (1/M) sum_k k p_k,  w = -(1/lambda) log sum_k exp(-lambda d_k),
-//   p_k = softmax(-lambda d_k); ratchets on s and w, eqs (Fw),(Fs).
+// stack, assembled in float64 around the replica's reference frame j as
+// Q + 2 (X_j - X_k) + G_jk (Q = sum (C - R_j)^2 and X_k = sum (C - R_j) R_k
+// from k_scps_dist, G_jk = sum (R_j - R_k)^2 of the stack; see tube_sums):
+//   s = 1 - (1/M) sum_k k p_k,  w = -wscale log sum_k exp(-lambda d_k),
+//   p_k = softmax(-lambda d_k), wscale = 1/lambda (eq (wX)) or 1 (eq (awXa));
+//   ratchets on s and w, eqs (Fw),(Fs).
 // The bias force is -sum_k c_k grad d_k with
-//   c_k = p_k [k_s (s - s_m)(lambda/M)(k - kbar) + k_w (w - w_m)];
-// coef receives c_k / Z0 and csum sum_k c_k / Z0 for the gradient pass.
-// X and Q are consumed and cleared.
+//   c_k = p_k [k_s (s - s_m)(lambda/M)(k - kbar) + k_w (w - w_m) lambda wscale];
+// coef receives c_k / Z0 and csum sum_k c_k / Z0 for the gradient pass, and
+// jref[r] the frame of largest weight, the reference of the next step's
+// distance pass.  X and Q are consumed and cleared.
 __global__ void k_finalize_scps(const KParams P, const SysDesc *__restrict__ sysd, const RepDesc *__restrict__ reps,
-                                const int kmax, double *__restrict__ X, double *__restrict__ Q,
-                                double *__restrict__ cv, float *__restrict__ coef, double *__restrict__ csum) {
+                                const int kmax, int *__restrict__ jref, double *__restrict__ X,
+                                double *__restrict__ Q, double *__restrict__ cv, float *__restrict__ coef,
+                                double *__restrict__ csum) {
     const int r = blockIdx.x;
     const int lane = threadIdx.x;
     const SysDesc S = sysd[reps[r].sys];
     const int K = S.K, M = K - 1;
     double *xr = X + (int64_t)r * kmax;
     const double lam = P.lambda;
-    const TubeSums ts = tube_sums(lane, K, Q[r], xr, S.R2, S.Z0, lam);
+    const int j = ref_frame(jref, r, K);
+    const TubeSums ts = tube_sums(lane, K, Q[r], xr, j, S.G + (int64_t)j * K, S.Z0, lam);
     const double *e = ts.e;
     const double a = ts.a, s0 = ts.s0, s1 = ts.s1;
     const double kbar = s1 / s0;
     const double sv = 1.0 - kbar / (double)M;
-    const double wv = -(a + log(s0)) / lam;
+    const double wv = tube_w(a, s0, P.wscale);
+    const double lw = lam * P.wscale;   // dw/dd_k = lw p_k
     double *c = cv + (int64_t)r * CV_STRIDE;
     const double sm = fmin(c[CV_SM], sv);
     const double wm = fmin(c[CV_WM], wv);
@@ -1349,7 +1355,7 @@ __global__ void k_finalize_scps(const KParams P, const SysDesc *__restrict__ sys
         const int k = lane + 64 * h;
         if (k < K) {
             const double pk = e[h] / s0;
-            const double ckv = pk * (P.k_s * ds * (lam / (double)M) * ((double)k - kbar) + P.k_w * dw);
+            const double ckv = pk * (P.k_s * ds * (lam / (double)M) * ((double)k - kbar) + P.k_w * dw * lw);
             coef[(int64_t)r * kmax + k] = (float)(ckv / S.Z0);
             tot += ckv;
             xr[k] = 0.0;
@@ -1359,6 +1365,7 @@ __global__ void k_finalize_scps(const KParams P, const SysDesc *__restrict__ sys
     if (lane == 0) {
         Q[r] = 0.0;
         csum[r] = tot / S.Z0;
+        if (jref) jref[r] = ts.kmax;
         c[CV_S] = sv;
         c[CV_W] = wv;
         c[CV_SM] = sm;
@@ -1368,8 +1375,9 @@ __global__ void k_finalize_scps(const KParams P, const SysDesc *__restrict__ sys
 }
 
 hipError_t launch_finalize_scps(const KParams &P, const SysDesc *sysd, const RepDesc *reps, int R, int kmax,
-                                double *X, double *Q, double *cv, float *coef, double *csum, hipStream_t st) {
-    hipLaunchKernelGGL(k_finalize_scps, dim3(R), dim3(64), 0, st, P, sysd, reps, kmax, X, Q, cv, coef, csum);
+                                int *jref, double *X, double *Q, double *cv, float *coef, double *csum,
+                                hipStream_t st) {
+    hipLaunchKernelGGL(k_finalize_scps, dim3(R), dim3(64), 0, st, P, sysd, reps, kmax, jref, X, Q, cv, coef, csum);
     return hipGetLastError();
 }
 

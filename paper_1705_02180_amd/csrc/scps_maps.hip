@@ -132,6 +132,35 @@ hipError_t launch_sum_squares(int64_t m, const double *v, double *part, double *
     return hipGetLastError();
 }
 
+// The sum over the packed contact pairs a < b with |perm[a] - perm[b]| >
+// min_sep of v^2: one workgroup per row a into part[a], then the rows in
+// order.  perm[a] is the chain index of contact position a.
+__global__ void k_sum_squares_sep(int nc, int min_sep, const int *__restrict__ perm, const double *__restrict__ v,
+                                  double *__restrict__ part) {
+    __shared__ double red[4];
+    const int a = blockIdx.x;
+    const int oa = perm[a];
+    const double *row = v + (packed_index(nc, a, a + 1) - (a + 1));   // row[b] = v(a, b) for b > a
+    double s = 0.0;
+    for (int b = a + 1 + threadIdx.x; b < nc; b += blockDim.x)
+        if (abs(oa - perm[b]) > min_sep) s += row[b] * row[b];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) part[a] = red[0] + red[1] + red[2] + red[3];
+}
+
+hipError_t launch_sum_squares_sep(int nc, int min_sep, const int *perm, const double *v, double *part, double *out,
+                                  hipStream_t st) {
+    if (nc < 2) {
+        hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, st, 0, part, out);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_sum_squares_sep, dim3(nc), dim3(256), 0, st, nc, min_sep, perm, v, part);
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, st, nc, part, out);
+    return hipGetLastError();
+}
+
 // Contact function in float64 with the quotient from the hardware reciprocal
 // estimate: two Newton steps r <- r (2 - den r), then one residual correction
 // of num * r.  den >= 1 here, so no scaling or special cases are needed; the
@@ -297,21 +326,55 @@ hipError_t launch_tile_sumsq(int nc, int ncb, int min_sep, const int *perm, cons
 }
 
 // Pair-major copy of a frame stack: stack_pm[tile][p][k] = stack[tile][k][p]
-// for k < K (zero for K <= k < K4), and R2[k] += sum over the counted pairs of
-// R_kp^2 (float64; pairs within min_seq_sep, outside the contact set or
-// repeated in a diagonal tile are not counted).  Grid (tile, STACKPM_SPLIT):
-// each workgroup transposes 64 / STACKPM_SPLIT sub-steps of one tile, 64
-// pairs at a time through LDS.  Thread (w, l) reads rows k = w, w + 4, ...
-// and keeps their sums of squares in registers; each wavefront reduces them
-// at the end and adds one value per row to R2.  R2 must be zero on entry.
+// for k < K (zero for K <= k < K4).  Grid (tile, STACKPM_SPLIT): each
+// workgroup transposes 64 / STACKPM_SPLIT sub-steps of one tile, 64 pairs at
+// a time through LDS; thread (w, l) reads rows k = w, w + 4, ...
 #ifndef STACKPM_SPLIT
 #define STACKPM_SPLIT 1
 #endif
-__global__ __launch_bounds__(256) void k_stack_pairmajor(int nc, int ncb, int K, int min_sep,
-                                                         const int *__restrict__ perm,
-                                                         const float *__restrict__ stack,
-                                                         float *__restrict__ stack_pm, double *__restrict__ R2) {
+__global__ __launch_bounds__(256) void k_stack_pairmajor(int K, const float *__restrict__ stack,
+                                                         float *__restrict__ stack_pm) {
     __shared__ float buf[64][KMAX + 1];
+    const int tile = blockIdx.x;
+    const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
+    const int K4 = stack_pm_width(K);
+    const int per = 64 / STACKPM_SPLIT, s_beg = blockIdx.y * per;
+    const float *src = stack + (int64_t)tile * K * 4096 + l;
+    for (int s = s_beg; s < s_beg + per; ++s) {
+        __syncthreads();
+        for (int k = w; k < K; k += 4) buf[l][k] = src[(int64_t)k * 4096 + s * 64];
+        __syncthreads();
+        float *out = stack_pm + ((int64_t)tile * 4096 + s * 64) * K4;
+        for (int e = tid; e < 64 * K4; e += 256) {
+            const int pl = e / K4, k = e - pl * K4;
+            out[e] = k < K ? buf[pl][k] : 0.f;
+        }
+    }
+}
+
+hipError_t launch_stack_pairmajor(int nc, int ncb, int K, const float *stack, float *stack_pm, hipStream_t st) {
+    (void)nc;
+    const int nt = ncb * (ncb + 1) / 2;
+    if (nt == 0 || K == 0) return hipSuccess;
+    if (K > KMAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_stack_pairmajor, dim3(nt, STACKPM_SPLIT), dim3(256), 0, st, K, stack, stack_pm);
+    return hipGetLastError();
+}
+
+// The stack's frame distances G[j][k] = sum over the counted contact pairs
+// (both in the contact set, beyond min_seq_sep, each unordered pair once) of
+// (R_jp - R_kp)^2, in float64 from the float32 frames (differences of float32
+// values are exact in float64), for j != k; the diagonal stays 0.  Grid
+// (tile, chunk): the workgroup stages the K frames of 64 pairs at a time in
+// LDS and each thread adds GRAM_EPT frame pairs j < k, numbered row by row,
+// over them; one float64 atomic per frame pair and workgroup at the end
+// (both G[j][k] and G[k][j]).  G must be zero on entry.
+constexpr int GRAM_EPT = 8;
+__global__ __launch_bounds__(256) void k_stack_gram(int nc, int ncb, int K, int min_sep,
+                                                    const int *__restrict__ perm, const float *__restrict__ stack,
+                                                    double *__restrict__ G) {
+    __shared__ float buf[64][KMAX + 1];
+    __shared__ int cnt[64];
     __shared__ int orig[2][64];
     const int tile = blockIdx.x;
     int I, J;
@@ -321,51 +384,57 @@ __global__ __launch_bounds__(256) void k_stack_pairmajor(int nc, int ncb, int K,
         const int c = ((tid >> 6) ? J : I) * 64 + l;
         orig[tid >> 6][l] = c < nc ? perm[c] : 0;
     }
-    const int K4 = stack_pm_width(K);
-    constexpr int NR = KMAX / 4;           // rows per thread: k = w + 4 i
-    double r2[NR];
+    const int E = K * (K - 1) / 2;
+    int fj[GRAM_EPT], fk[GRAM_EPT];
+    double acc[GRAM_EPT];
 #pragma unroll
-    for (int i = 0; i < NR; ++i) r2[i] = 0.0;
-    const int per = 64 / STACKPM_SPLIT, s_beg = blockIdx.y * per;
+    for (int m = 0; m < GRAM_EPT; ++m) {
+        int e = (blockIdx.y * GRAM_EPT + m) * 256 + tid;
+        int j = 0, k = 0;   // an entry past the end reads frame 0 twice and adds 0
+        if (e < E) {
+            while (e >= K - 1 - j) {
+                e -= K - 1 - j;
+                ++j;
+            }
+            k = j + 1 + e;
+        }
+        fj[m] = j;
+        fk[m] = k;
+        acc[m] = 0.0;
+    }
     const float *src = stack + (int64_t)tile * K * 4096 + l;
-    for (int s = s_beg; s < s_beg + per; ++s) {
+    for (int s = 0; s < 64; ++s) {
         __syncthreads();
-        const int a = I * 64 + l, jl = (l + s) & 63, b = J * 64 + jl;
-        const bool counts = a < nc && b < nc && tile_pair_counts(I == J, s, l) &&
-                            abs(orig[0][l] - orig[1][jl]) > min_sep;
+        for (int k = w; k < K; k += 4) buf[l][k] = src[(int64_t)k * 4096 + s * 64];
+        if (w == 0) {
+            const int a = I * 64 + l, jl = (l + s) & 63, b = J * 64 + jl;
+            cnt[l] = a < nc && b < nc && tile_pair_counts(I == J, s, l) && abs(orig[0][l] - orig[1][jl]) > min_sep;
+        }
+        __syncthreads();
+        for (int p = 0; p < 64; ++p) {
+            if (!cnt[p]) continue;   // uniform across the workgroup
 #pragma unroll
-        for (int i = 0; i < NR; ++i) {
-            const int k = w + 4 * i;
-            if (k < K) {
-                const float v = src[(int64_t)k * 4096 + s * 64];
-                buf[l][k] = v;
-                if (counts) r2[i] = fma((double)v, (double)v, r2[i]);
+            for (int m = 0; m < GRAM_EPT; ++m) {
+                const double d = (double)buf[p][fj[m]] - (double)buf[p][fk[m]];
+                acc[m] = fma(d, d, acc[m]);
             }
         }
-        __syncthreads();
-        float *out = stack_pm + ((int64_t)tile * 4096 + s * 64) * K4;
-        for (int e = tid; e < 64 * K4; e += 256) {
-            const int pl = e / K4, k = e - pl * K4;
-            out[e] = k < K ? buf[pl][k] : 0.f;
-        }
     }
 #pragma unroll
-    for (int i = 0; i < NR; ++i) {
-        const int k = w + 4 * i;
-        if (k < K) {
-            const double t = wave_sum(r2[i]);
-            if (l == 0) unsafeAtomicAdd(&R2[k], t);
+    for (int m = 0; m < GRAM_EPT; ++m)
+        if (fj[m] != fk[m]) {
+            unsafeAtomicAdd(&G[fj[m] * K + fk[m]], acc[m]);
+            unsafeAtomicAdd(&G[fk[m] * K + fj[m]], acc[m]);
         }
-    }
 }
 
-hipError_t launch_stack_pairmajor(int nc, int ncb, int K, int min_sep, const int *perm, const float *stack,
-                                  float *stack_pm, double *R2, hipStream_t st) {
+hipError_t launch_stack_gram(int nc, int ncb, int K, int min_sep, const int *perm, const float *stack, double *G,
+                             hipStream_t st) {
     const int nt = ncb * (ncb + 1) / 2;
-    if (nt == 0 || K == 0) return hipSuccess;
+    if (nt == 0 || K < 2) return hipSuccess;
     if (K > KMAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_stack_pairmajor, dim3(nt, STACKPM_SPLIT), dim3(256), 0, st, nc, ncb, K, min_sep, perm,
-                       stack, stack_pm, R2);
+    const int E = K * (K - 1) / 2, chunks = (E + GRAM_EPT * 256 - 1) / (GRAM_EPT * 256);
+    hipLaunchKernelGGL(k_stack_gram, dim3(nt, chunks), dim3(256), 0, st, nc, ncb, K, min_sep, perm, stack, G);
     return hipGetLastError();
 }
 
@@ -388,40 +457,54 @@ __device__ __forceinline__ float contact_operand(const KParams &P, const float4 
 #ifndef SCPS_DIST_AHEAD
 #define SCPS_DIST_AHEAD 8
 #endif
-// Pass 1: X[r][k] += sum_p C_rp R_kp and Q[r] += sum_p C_rp^2 over the contact
-// pairs of each work item (group of replicas, tile); workgroups stride over
-// the items and flush their sums when the group changes and at the end.
+#ifndef SCPS_DIST_REF_AHEAD
+#define SCPS_DIST_REF_AHEAD 4   // the reference values ride a shorter ring (registers)
+#endif
+// Pass 1, around each replica's reference frame j_r (see tube_sums): with
+// u_rp = C_rp - R_{j_r}p, X[r][k] += sum_p u_rp R_kp and Q[r] += sum_p u_rp^2
+// over the contact pairs of each work item (group of replicas, tile);
+// workgroups stride over the items and flush their sums when the group
+// changes and at the end.
 // The pairs of a tile are taken row by row: wavefront w takes rows
 // i = w, w+4, ... of block I and, per row, 32 MFMA steps of 2 pairs
-// (i, 2m + (l >> 5)); lane l evaluates that pair for replica l & 31 (A operand
-// of 32x32x2 float32 MFMAs) with particle i's position held in a register and
-// particle j's read from the block-J positions in LDS, and loads frames
-// 2 (l & 31) and 2 (l & 31) + 1 of the pair with one 8-byte load,
-// SCPS_DIST_AHEAD steps ahead of their use; frame block h holds frames 2j + h,
+// (i, 2m + (l >> 5)); lane l evaluates u of that pair for replica l & 31 (A
+// operand of 32x32x2 float32 MFMAs) with particle i's position held in a
+// register, particle j's read from the block-J positions in LDS and R_j from
+// the pair's frames, and loads frames 2 (l & 31) and 2 (l & 31) + 1 of the
+// pair with one 8-byte load SCPS_DIST_AHEAD steps ahead of their use (the
+// reference value, from the same run of the pair's frames, SCPS_DIST_REF_AHEAD
+// steps ahead); frame block h holds frames 2j + h,
 // so component h of that load is the lane's B operand of block h.  A diagonal
 // tile counts the pairs j > i.  The float32 accumulators hold one row (64
 // pairs per element) and are added after every row into the workgroup's
 // float64 sums xl[slot][frame] in LDS.  Element v of lane l in block h is
-// replica slot 8 (v >> 2) + 4 (l >> 5) + (v & 3), frame 2 (l & 31) + h.
+// replica slot 8 (v >> 2) + 4 (l >> 5) + (v & 3), frame 64 fb + 2 (l & 31) + h:
+// a stack of more than 64 frames is taken in frame blocks fb of 64, each a
+// pass of its own over the tile (the contact values are recomputed; Q is
+// summed in block 0 only).
 template <bool MASK>
 __device__ __forceinline__ void scps_dist_tile(const KParams &P, const SysDesc &S, const int nrep,
-                                               const ScpsItem &it, const float4 (*posj)[32], const int *orgj,
-                                               const float4 *__restrict__ xs, const RepDesc *__restrict__ reps,
-                                               const int myrep, const int lane, const int wave, double *xl,
-                                               double &q) {
+                                               const ScpsItem &it, const int fb, const float4 (*posj)[32],
+                                               const int *orgj, const float4 *__restrict__ xs,
+                                               const RepDesc *__restrict__ reps, const int myrep, const int jr,
+                                               const int lane, const int wave, double *xl, double &q) {
     const int I = it.IJ >> 16, J = it.IJ & 0xFFFF;
     const bool diag = I == J;
     const int K4 = stack_pm_width(S.K);
     const int rs = lane & 31, pq = lane >> 5;
     const bool rep = rs < nrep;
-    const bool bload = 2 * rs < K4;
+    const bool bload = 64 * fb + 2 * rs < K4;
+    const bool sum_q = fb == 0;
     // global (not flat) loads from a uniform tile base with 32-bit lane offsets:
     // flat loads would also count against the LDS wait counter and drain the ring
     typedef float v2 __attribute__((ext_vector_type(2)));
     typedef const __attribute__((address_space(1))) v2 *gv2;
+    typedef const __attribute__((address_space(1))) float *gf;
     const gv2 Rt = (gv2)(S.stack_pm + (int64_t)it.tile * 4096 * K4);
+    const gf Rf = (gf)(S.stack_pm + (int64_t)it.tile * 4096 * K4);
     const float4 *xr = xs + 2 * reps[myrep].poff + I * 128;
-    constexpr int D = SCPS_DIST_AHEAD;
+    constexpr int D = SCPS_DIST_AHEAD, DR = SCPS_DIST_REF_AHEAD;
+    static_assert(D % DR == 0 && 32 % D == 0, "the rings advance together");
     // pair (i, j) sits at s * 64 + i in the tile, s = (j - i) mod 64
     // Unconditional loads from clamped in-tile addresses: a lane past the
     // stack width (2 rs >= K4) feeds output columns of frames >= K, which the
@@ -429,11 +512,19 @@ __device__ __forceinline__ void scps_dist_tile(const KParams &P, const SysDesc &
     auto bop = [&](int i_, int m_) {
         const int ic = i_ < 64 ? i_ : 63;
         const int s_ = (2 * m_ + pq - ic) & 63;
-        return Rt[((s_ * 64 + ic) * K4 >> 1) + (bload ? rs : 0)];
+        return Rt[((s_ * 64 + ic) * K4 >> 1) + (bload ? 32 * fb + rs : 0)];
+    };
+    auto rop = [&](int i_, int m_) {   // R_j of the same pair, the reference of slot rs
+        const int ic = i_ < 64 ? i_ : 63;
+        const int s_ = (2 * m_ + pq - ic) & 63;
+        return Rf[(s_ * 64 + ic) * K4 + jr];
     };
     v2 ring[D];
+    float rring[DR];
 #pragma unroll
     for (int u = 0; u < D; ++u) ring[u] = bop(wave, u);
+#pragma unroll
+    for (int u = 0; u < DR; ++u) rring[u] = rop(wave, u);
 #pragma unroll 1
     for (int i = wave; i < 64; i += 4) {
         const float4 pi = rep ? xr[i] : make_float4(0.f, 0.f, 0.f, 0.f);
@@ -450,15 +541,19 @@ __device__ __forceinline__ void scps_dist_tile(const KParams &P, const SysDesc &
             for (int u = 0; u < D; ++u) {
                 const int m = D * mg + u;
                 const v2 b = ring[u];
+                const float rj = rring[u % DR];
                 const int nm = m + D < 32 ? m + D : m + D - 32, ni = m + D < 32 ? i : i + 4;
                 ring[u] = bop(ni, nm);
+                const int rm = m + DR < 32 ? m + DR : m + DR - 32, ri = m + DR < 32 ? i : i + 4;
+                rring[u % DR] = rop(ri, rm);
                 const int jl = 2 * m + pq;
                 bool ok = !diag | (jl > i);
                 if constexpr (MASK) {
                     ok = ok & icon & (J * 64 + jl < S.nc) & (abs(oi - orgj[jl]) > P.min_sep);
                 }
-                const float c = contact_operand<MASK>(P, pi, posj[jl][rs], ok & rep);
-                q = fma((double)c, (double)c, q);
+                const float cv = contact_operand<MASK>(P, pi, posj[jl][rs], ok & rep);
+                const float c = (ok & rep) ? cv - rj : 0.f;   // u = C - R_j of a counted pair
+                if (sum_q) q = fma((double)c, (double)c, q);
                 acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(c, b.x, acc[0], 0, 0, 0);
                 acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(c, b.y, acc[1], 0, 0, 0);
             }
@@ -474,35 +569,40 @@ __device__ __forceinline__ void scps_dist_tile(const KParams &P, const SysDesc &
 #ifndef SCPS_DIST_WPE
 #define SCPS_DIST_WPE 3
 #endif
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SCPS_DIST_WPE, SCPS_DIST_WPE))) void k_scps_dist(const KParams P, const SysDesc *__restrict__ sysd,
-                                                   const RepDesc *__restrict__ reps,
-                                                   const ScpsGroup *__restrict__ groups,
-                                                   const ScpsItem *__restrict__ items, const int n_items,
-                                                   const float4 *__restrict__ xs, double *__restrict__ X,
-                                                   double *__restrict__ Q, const int kmax, const int stack_sys) {
+// Work unit t covers item t mod n_items in frame block t / n_items (nfb
+// blocks of 64 frames); the sums are flushed when (group, frame block) changes.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SCPS_DIST_WPE, SCPS_DIST_WPE))) void k_scps_dist(
+    const KParams P, const SysDesc *__restrict__ sysd, const RepDesc *__restrict__ reps,
+    const ScpsGroup *__restrict__ groups, const ScpsItem *__restrict__ items, const int n_items, const int nfb,
+    const int *__restrict__ jref, const float4 *__restrict__ xs, double *__restrict__ X, double *__restrict__ Q,
+    const int kmax, const int stack_sys) {
     __shared__ __align__(16) float4 posj[64][32];   // block J of every replica slot
     __shared__ double xl[32 * 64];                   // float64 sums X[slot][frame] of the current group
     __shared__ double ql[4][64];
     __shared__ int orgj[64];
     __shared__ int sh_rep[32];
+    __shared__ int sh_jref[32];                      // reference frame of every replica slot
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (int e = tid; e < 32 * 64; e += 256) xl[e] = 0.0;
     double q = 0.0;
-    int cur = -1, nrep = 0;
+    int cur = -1, cur_fb = 0, nrep = 0;
     SysDesc S;
+    const int n_units = n_items * nfb;
     for (int t = blockIdx.x;; t += gridDim.x) {
-        const bool more = t < n_items;
-        const ScpsItem it = more ? items[t] : ScpsItem{-1, 0, 0, 0};
-        if (cur >= 0 && it.group != cur) {
-            // flush the group's sums to the replicas' float64 totals
+        const bool more = t < n_units;
+        const int fb = more ? t / n_items : 0;
+        const ScpsItem it = more ? items[t - fb * n_items] : ScpsItem{-1, 0, 0, 0};
+        const bool change = it.group != cur || fb != cur_fb;
+        if (cur >= 0 && change) {
+            // flush the sums of (group, frame block) to the replicas' float64 totals
             ql[wave][lane] = q;
             __syncthreads();
             for (int e = tid; e < 32 * 64; e += 256) {
-                const int slot = e >> 6, k = e & 63;
+                const int slot = e >> 6, k = 64 * cur_fb + (e & 63);
                 if (slot < nrep && k < S.K) unsafeAtomicAdd(&X[(int64_t)sh_rep[slot] * kmax + k], xl[e]);
                 xl[e] = 0.0;
             }
-            if (tid < 32) {
+            if (tid < 32 && cur_fb == 0) {
                 double sum = 0.0;
                 for (int w = 0; w < 4; ++w) sum += ql[w][tid] + ql[w][32 + tid];
                 if (tid < nrep) unsafeAtomicAdd(&Q[sh_rep[tid]], sum);
@@ -511,8 +611,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SCPS_DIST_W
         }
         if (!more) break;
         __syncthreads();
-        if (it.group != cur) {
+        if (change) {
             cur = it.group;
+            cur_fb = fb;
             const ScpsGroup *gp = groups + cur;
             nrep = gp->nrep;
             S = sysd[gp->sys];
@@ -520,9 +621,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SCPS_DIST_W
                 S.stack_pm = sysd[stack_sys].stack_pm;
                 S.K = sysd[stack_sys].K;
             }
-            if (tid < 32) sh_rep[tid] = tid < nrep ? gp->rep[tid] : 0;
+            if (tid < 32) {
+                sh_rep[tid] = tid < nrep ? gp->rep[tid] : 0;
+                sh_jref[tid] = tid < nrep ? ref_frame(jref, gp->rep[tid], S.K) : 0;
+            }
             __syncthreads();
         }
+        if (64 * fb >= S.K) continue;   // the group's stack has no frame in this block (uniform per workgroup)
         // stage block J of every replica of the group
         const int J = it.IJ & 0xFFFF;
         for (int e = tid; e < 64 * 32; e += 256) {
@@ -533,11 +638,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SCPS_DIST_W
         }
         if (tid < 64) orgj[tid] = S.perm[J * 64 + tid];
         __syncthreads();
-        const int myrep = sh_rep[lane & 31];
+        const int myrep = sh_rep[lane & 31], myj = sh_jref[lane & 31];
         if (it.flags & TILE_MASK)
-            scps_dist_tile<true>(P, S, nrep, it, posj, orgj, xs, reps, myrep, lane, wave, xl, q);
+            scps_dist_tile<true>(P, S, nrep, it, fb, posj, orgj, xs, reps, myrep, myj, lane, wave, xl, q);
         else
-            scps_dist_tile<false>(P, S, nrep, it, posj, orgj, xs, reps, myrep, lane, wave, xl, q);
+            scps_dist_tile<false>(P, S, nrep, it, fb, posj, orgj, xs, reps, myrep, myj, lane, wave, xl, q);
     }
 }
 
@@ -683,25 +788,27 @@ static_assert(sizeof(BiasLds) <= 160 * 1024, "the fused bias pass keeps one work
 
 typedef float bias_f2 __attribute__((ext_vector_type(2)));
 
-// Frames 2 kk + half of pairs 2 slot, 2 slot + 1 of sub-step k: a uniform
-// tile base and a 32-bit lane offset per load.
+// Frames 2 (f0 + kk) + half of pairs 2 slot, 2 slot + 1 of sub-step k: a
+// uniform tile base and a 32-bit lane offset per load.
 template <int KKN>
-__device__ __forceinline__ void bias_loads(const float *tile_base, const int k, const int K, const int slot,
-                                           const int half, bias_f2 r[KKN]) {
+__device__ __forceinline__ void bias_loads(const float *tile_base, const int k, const int f0, const int K,
+                                           const int slot, const int half, bias_f2 r[KKN]) {
     typedef const __attribute__((address_space(1))) bias_f2 *gptr;
     const gptr gb = (gptr)tile_base;
     const int o = (half * 4096 + k * 64 + 2 * slot) >> 1;   // in float pairs
 #pragma unroll
     for (int kk = 0; kk < KKN; ++kk) {
         r[kk] = bias_f2{0.f, 0.f};
-        if (2 * kk + half < K) r[kk] = __builtin_nontemporal_load(gb + (o + kk * 4096));
+        if (2 * (f0 + kk) + half < K) r[kk] = __builtin_nontemporal_load(gb + (o + (f0 + kk) * 4096));
     }
 }
 
-// KKN frame pairs per MFMA chain (2 KKN >= K; frames beyond K have zero
-// coefficients and are not loaded), fixed at compile time so that the chain
-// has no branches and its loads are issued together.
-template <bool MASK, int KKN>
+// KKN frame pairs per MFMA chain, NH chains per sub-step (2 KKN NH >= K;
+// frames beyond K have zero coefficients and are not loaded), fixed at
+// compile time so that a chain has no branches and its loads are issued
+// together.  With NH = 2 (stacks of more than 64 frames) the loads of the
+// next half are issued after the MFMAs of the current one.
+template <bool MASK, int KKN, int NH>
 __device__ __forceinline__ void scps_bias_tile(const KParams &P, const SysDesc &S, const ScpsItem &it,
                                                const int lane, const int wave, BiasLds &L, float fi[][3],
                                                float fj[][3]) {
@@ -715,7 +822,7 @@ __device__ __forceinline__ void scps_bias_tile(const KParams &P, const SysDesc &
         const int slot = lane & 31, half = lane >> 5;
         const float *Rt = S.stack + (int64_t)it.tile * K * 4096;   // uniform
         bias_f2 r[KKN];
-        if (kb + wave < ke) bias_loads<KKN>(Rt, kb + wave, K, slot, half, r);
+        if (kb + wave < ke) bias_loads<KKN>(Rt, kb + wave, 0, K, slot, half, r);
 #pragma unroll 1
         for (int st = 0; st <= nch; ++st) {
             const int k = kb + BIAS_CH * st + wave;
@@ -725,18 +832,24 @@ __device__ __forceinline__ void scps_bias_tile(const KParams &P, const SysDesc &
                 for (int b = 0; b < 2; ++b)
 #pragma unroll
                     for (int v = 0; v < 16; ++v) acc[b][v] = 0.f;
+                // one chain per KKN frame pairs; a second chain's loads go out after
+                // the first chain's MFMAs, into the same registers
 #pragma unroll
-                for (int kk = 0; kk < KKN; ++kk) {
-                    const float c = L.c[kk][lane];
-                    acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(r[kk].x, c, acc[0], 0, 0, 0);
-                    acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(r[kk].y, c, acc[1], 0, 0, 0);
+                for (int h = 0; h < NH; ++h) {
+#pragma unroll
+                    for (int kk = 0; kk < KKN; ++kk) {
+                        const float c = L.c[KKN * h + kk][lane];
+                        acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(r[kk].x, c, acc[0], 0, 0, 0);
+                        acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(r[kk].y, c, acc[1], 0, 0, 0);
+                    }
+                    if (h + 1 < NH) bias_loads<KKN>(Rt, k, KKN * (h + 1), K, slot, half, r);
                 }
                 float(*E)[65] = L.E[st & 1][wave];
 #pragma unroll
                 for (int v = 0; v < 16; ++v)
 #pragma unroll
                     for (int b = 0; b < 2; ++b) E[slot][16 * (v >> 2) + 8 * half + 2 * (v & 3) + b] = acc[b][v];
-                if (k + BIAS_CH < ke) bias_loads<KKN>(Rt, k + BIAS_CH, K, slot, half, r);
+                if (k + BIAS_CH < ke) bias_loads<KKN>(Rt, k + BIAS_CH, 0, K, slot, half, r);
             }
             __syncthreads();
         }
@@ -805,20 +918,25 @@ __device__ __forceinline__ void scps_bias_tile(const KParams &P, const SysDesc &
     }
 }
 
-template <bool MASK>
+// BIG: stacks of 65 .. KMAX frames, in a kernel of its own so that the
+// common sizes keep their register allocation.
+template <bool MASK, bool BIG>
 __device__ __forceinline__ void scps_bias_dispatch(const KParams &P, const SysDesc &S, const ScpsItem &it,
                                                    const int lane, const int wave, BiasLds &L, float fi[][3],
                                                    float fj[][3]) {
-    if (S.K <= 16)
-        scps_bias_tile<MASK, 8>(P, S, it, lane, wave, L, fi, fj);
+    if constexpr (BIG)
+        scps_bias_tile<MASK, 32, 2>(P, S, it, lane, wave, L, fi, fj);
+    else if (S.K <= 16)
+        scps_bias_tile<MASK, 8, 1>(P, S, it, lane, wave, L, fi, fj);
     else if (S.K <= 32)
-        scps_bias_tile<MASK, 16>(P, S, it, lane, wave, L, fi, fj);
+        scps_bias_tile<MASK, 16, 1>(P, S, it, lane, wave, L, fi, fj);
     else if (S.K <= 52)
-        scps_bias_tile<MASK, 26>(P, S, it, lane, wave, L, fi, fj);
+        scps_bias_tile<MASK, 26, 1>(P, S, it, lane, wave, L, fi, fj);
     else
-        scps_bias_tile<MASK, 32>(P, S, it, lane, wave, L, fi, fj);
+        scps_bias_tile<MASK, 32, 1>(P, S, it, lane, wave, L, fi, fj);
 }
 
+template <bool BIG>
 __global__ __launch_bounds__(BIAS_WG) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_scps_bias(
     const KParams P, const SysDesc *__restrict__ sysd, const RepDesc *__restrict__ reps,
     const ScpsGroup *__restrict__ groups, const ScpsItem *__restrict__ items, const int n_items,
@@ -863,9 +981,9 @@ __global__ __launch_bounds__(BIAS_WG) __attribute__((amdgpu_waves_per_eu(3, 3)))
 #pragma unroll
             for (int c = 0; c < 3; ++c) fi[m][c] = fj[m][c] = 0.f;
         if (it.flags & TILE_MASK)
-            scps_bias_dispatch<true>(P, S, it, lane, wave, L, fi, fj);
+            scps_bias_dispatch<true, BIG>(P, S, it, lane, wave, L, fi, fj);
         else
-            scps_bias_dispatch<false>(P, S, it, lane, wave, L, fi, fj);
+            scps_bias_dispatch<false, BIG>(P, S, it, lane, wave, L, fi, fj);
         if (wave < BIAS_NMW) continue;
         // after sub-steps kb .. ke-1 lane l holds the j-side partials of particle (l + ke) mod 64
         const int ke = (it.flags & TILE_DIAG) ? 33 : 64;
@@ -887,32 +1005,37 @@ __global__ __launch_bounds__(BIAS_WG) __attribute__((amdgpu_waves_per_eu(3, 3)))
 }
 
 hipError_t launch_scps_dist(const KParams &P, const SysDesc *sysd, const RepDesc *reps, const ScpsGroup *groups,
-                            const ScpsItem *items, int n_items, const float4 *xs, double *X, double *Q, int kmax,
-                            int stack_sys, hipStream_t st) {
+                            const ScpsItem *items, int n_items, int max_frames, const int *jref, const float4 *xs,
+                            double *X, double *Q, int kmax, int stack_sys, hipStream_t st) {
     if (n_items == 0) return hipSuccess;
+    if (max_frames < 1 || max_frames > KMAX || max_frames > kmax) return hipErrorInvalidValue;
+    const int nfb = (max_frames + 63) / 64;
     const int cap = 256 * SCPS_DIST_WPE;   // resident workgroups: WPE per SIMD, four waves each
-    const int grid = n_items < cap ? n_items : cap;
-    hipLaunchKernelGGL(k_scps_dist, dim3(grid), dim3(256), 0, st, P, sysd, reps, groups, items, n_items, xs, X, Q,
-                       kmax, stack_sys);
+    const int grid = n_items * nfb < cap ? n_items * nfb : cap;
+    hipLaunchKernelGGL(k_scps_dist, dim3(grid), dim3(256), 0, st, P, sysd, reps, groups, items, n_items, nfb, jref,
+                       xs, X, Q, kmax, stack_sys);
     return hipGetLastError();
 }
 
 // Tube variables of every replica against the frame stack of system
-// stack_sys (-1: its own system's), from the distances k_scps_dist left in X
-// and Q, which are cleared for the next pass.  s, w: nullable [R]; sigma:
-// nullable [R], set to weight (1 - s) when first, else incremented by it
-// (the mean of 1 - s over several stacks is the progress coordinate sigma).
-__global__ void k_tube_eval(double lam, const SysDesc *__restrict__ sysd, const RepDesc *__restrict__ reps,
-                            int kmax, int stack_sys, double *__restrict__ X, double *__restrict__ Q,
-                            double *__restrict__ s, double *__restrict__ w, double *__restrict__ sigma, double weight,
-                            int first) {
+// stack_sys (-1: its own system's), from the sums k_scps_dist left in X and
+// Q around the reference frames jref_in, which are cleared for the next
+// pass.  s, w: nullable [R]; sigma: nullable [R], set to weight (1 - s) when
+// first, else incremented by it (the mean of 1 - s over several stacks is
+// the progress coordinate sigma); jref_out: nullable [R], each replica's
+// frame of largest weight.
+__global__ void k_tube_eval(double lam, double wscale, const int *__restrict__ jref_in, int *__restrict__ jref_out,
+                            const SysDesc *__restrict__ sysd, const RepDesc *__restrict__ reps, int kmax,
+                            int stack_sys, double *__restrict__ X, double *__restrict__ Q, double *__restrict__ s,
+                            double *__restrict__ w, double *__restrict__ sigma, double weight, int first) {
     const int r = blockIdx.x, lane = threadIdx.x;
     const SysDesc S = sysd[stack_sys >= 0 ? stack_sys : reps[r].sys];
     const int K = S.K;
     double *xr = X + (int64_t)r * kmax;
-    const TubeSums ts = tube_sums(lane, K, Q[r], xr, S.R2, S.Z0, lam);
+    const int j = ref_frame(jref_in, r, K);
+    const TubeSums ts = tube_sums(lane, K, Q[r], xr, j, S.G + (int64_t)j * K, S.Z0, lam);
     const double sv = 1.0 - (ts.s1 / ts.s0) / (double)(K - 1);
-    const double wv = -(ts.a + log(ts.s0)) / lam;
+    const double wv = tube_w(ts.a, ts.s0, wscale);
 #pragma unroll
     for (int h = 0; h < 2; ++h)
         if (lane + 64 * h < K) xr[lane + 64 * h] = 0.0;
@@ -921,14 +1044,15 @@ __global__ void k_tube_eval(double lam, const SysDesc *__restrict__ sysd, const 
         if (s) s[r] = sv;
         if (w) w[r] = wv;
         if (sigma) sigma[r] = (first ? 0.0 : sigma[r]) + weight * (1.0 - sv);
+        if (jref_out) jref_out[r] = ts.kmax;
     }
 }
 
-hipError_t launch_tube_eval(double lam, const SysDesc *sysd, const RepDesc *reps, int R, int kmax, int stack_sys,
-                            double *X, double *Q, double *s, double *w, double *sigma, double weight, int first,
-                            hipStream_t st) {
-    hipLaunchKernelGGL(k_tube_eval, dim3(R), dim3(64), 0, st, lam, sysd, reps, kmax, stack_sys, X, Q, s, w, sigma,
-                       weight, first);
+hipError_t launch_tube_eval(double lam, double wscale, const int *jref_in, int *jref_out, const SysDesc *sysd,
+                            const RepDesc *reps, int R, int kmax, int stack_sys, double *X, double *Q, double *s,
+                            double *w, double *sigma, double weight, int first, hipStream_t st) {
+    hipLaunchKernelGGL(k_tube_eval, dim3(R), dim3(64), 0, st, lam, wscale, jref_in, jref_out, sysd, reps, kmax,
+                       stack_sys, X, Q, s, w, sigma, weight, first);
     return hipGetLastError();
 }
 
@@ -942,12 +1066,17 @@ hipError_t launch_scps_eff(const SysDesc *sysd, const RepDesc *reps, const ScpsG
 }
 
 hipError_t launch_scps_bias(const KParams &P, const SysDesc *sysd, const RepDesc *reps, const ScpsGroup *groups,
-                            const ScpsItem *items, int n_items, const float4 *xs, const float *coef,
+                            const ScpsItem *items, int n_items, int max_frames, const float4 *xs, const float *coef,
                             const double *csum, int kmax, double *acc, hipStream_t st) {
     if (n_items == 0) return hipSuccess;
+    if (max_frames < 1 || max_frames > KMAX || max_frames > kmax) return hipErrorInvalidValue;
     const int grid = n_items < 256 ? n_items : 256;   // one workgroup per compute unit (LDS)
-    hipLaunchKernelGGL(k_scps_bias, dim3(grid), dim3(BIAS_WG), 0, st, P, sysd, reps, groups, items, n_items, xs,
-                       coef, csum, kmax, acc);
+    if (max_frames > 64)
+        hipLaunchKernelGGL(k_scps_bias<true>, dim3(grid), dim3(BIAS_WG), 0, st, P, sysd, reps, groups, items, n_items,
+                           xs, coef, csum, kmax, acc);
+    else
+        hipLaunchKernelGGL(k_scps_bias<false>, dim3(grid), dim3(BIAS_WG), 0, st, P, sysd, reps, groups, items,
+                           n_items, xs, coef, csum, kmax, acc);
     return hipGetLastError();
 }
 

@@ -16,7 +16,8 @@ import numpy as np
 import torch  # loads the HIP runtime the library binds to
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libscps.so")
+# SCPS_LIB: another build of the same sources (e.g. one with host-side sanitizers)
+LIB_PATH = os.environ.get("SCPS_LIB") or os.path.join(_HERE, "libscps.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1705_02180_amd.build`")
 
@@ -36,6 +37,7 @@ class Params(C.Structure):
     _fields_ = [
         ("integrator", C.c_int32), ("bias_mode", C.c_int32), ("exec_mode", C.c_int32),
         ("nb_excl", C.c_int32), ("min_seq_sep", C.c_int32), ("replica_base", C.c_int32),
+        ("w_form", C.c_int32), ("reserved", C.c_int32),
         ("dt", C.c_double), ("gamma", C.c_double), ("kT", C.c_double),
         ("k_bond", C.c_double), ("r_bond", C.c_double),
         ("lj_eps", C.c_double), ("lj_sigma", C.c_double),
@@ -130,6 +132,7 @@ def make_params(d: dict, exec_mode: int = 0, replica_base: int = 0) -> Params:
     return Params(
         integrator=int(d["integrator"]), bias_mode=int(d["bias_mode"]), exec_mode=int(exec_mode),
         nb_excl=int(d["nb_excl"]), min_seq_sep=int(d["min_seq_sep"]), replica_base=int(replica_base),
+        w_form=int(d.get("w_form", 0)), reserved=0,
         dt=d["dt"], gamma=d["gamma"], kT=d["kT"], k_bond=d["k_bond"], r_bond=d["r_bond"],
         lj_eps=d["lj_eps"], lj_sigma=d["lj_sigma"], dh_prefactor=d["dh_prefactor"],
         dh_kappa=d["dh_kappa"], r0_contact=d["r0_contact"], r_cut_contact=d["r_cut_contact"],
@@ -393,7 +396,7 @@ class FunnelParams(C.Structure):
         ("s1", C.c_double), ("s2", C.c_double), ("s3", C.c_double),
         ("w", C.c_double), ("xm", C.c_double), ("ym", C.c_double),
         ("kT", C.c_double), ("mobility_dt", C.c_double),
-        ("bias_mode", C.c_int32), ("reserved", C.c_int32),
+        ("bias_mode", C.c_int32), ("w_form", C.c_int32),
         ("k_R", C.c_double), ("lam", C.c_double), ("k_s", C.c_double), ("k_w", C.c_double),
         ("seed", C.c_uint64),
     ]
@@ -406,8 +409,8 @@ def funnel_steps(params: dict, xy: torch.Tensor, cvstate: torch.Tensor, n_steps:
     n = int(xy.shape[0])
     fp = FunnelParams(A1=params["A1"], A2=params["A2"], A3=params["A3"], s1=params["s1"], s2=params["s2"],
                       s3=params["s3"], w=params["w"], xm=params["xm"], ym=params["ym"], kT=params["kT"],
-                      mobility_dt=params["mob_dt"], bias_mode=int(params["bias_mode"]), reserved=0,
-                      k_R=params["k_R"], lam=params["lam"], k_s=params["k_s"], k_w=params["k_w"],
+                      mobility_dt=params["mob_dt"], bias_mode=int(params["bias_mode"]),
+                      w_form=int(params.get("w_form", 0)), k_R=params["k_R"], lam=params["lam"], k_s=params["k_s"], k_w=params["k_w"],
                       seed=int(params["seed"]))
     K = 0 if mean_path is None else int(mean_path.shape[0])
     pf = None

@@ -5,11 +5,13 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
+
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "scps.h")
-LIB = os.path.join(ROOT, "paper_1705_02180_amd", "libscps.so")
+LIB = os.environ.get("SCPS_LIB") or os.path.join(ROOT, "paper_1705_02180_amd", "libscps.so")
 
 
 def declared_symbols():
@@ -87,11 +89,11 @@ def test_context_free_entry_points_validate_on_the_host(lib):
     fs.argtypes = scps._lib.scps_funnel_steps.argtypes
     p = I.funnel_params()
     fp = scps.FunnelParams(A1=p["A1"], A2=p["A2"], A3=p["A3"], s1=p["s1"], s2=p["s2"], s3=p["s3"], w=p["w"],
-                           xm=p["xm"], ym=p["ym"], kT=p["kT"], mobility_dt=p["mob_dt"], bias_mode=1, reserved=0,
+                           xm=p["xm"], ym=p["ym"], kT=p["kT"], mobility_dt=p["mob_dt"], bias_mode=1, w_form=0,
                            k_R=p["k_R"], lam=p["lam"], k_s=p["k_s"], k_w=p["k_w"], seed=1)
     assert fs(None, 4, 0, fake, fake, 1, 0, 0, None, 0, None, None) == -1             # no parameters
     assert fs(C.byref(fp), 4, 0, fake, fake, 1, 0, 0, None, 10, None, None) == -1      # no mean path
-    assert fs(C.byref(fp), 4, 0, fake, fake, 1, 0, 0, None, 65, fake, None) == -2      # 65 frames
+    assert fs(C.byref(fp), 4, 0, fake, fake, 1, 0, 0, None, 129, fake, None) == -2     # 129 frames
     assert fs(C.byref(fp), 0, 0, fake, fake, 1, 0, 0, None, 10, fake, None) == -1      # no trajectory
     assert fs(C.byref(fp), 4, 0, fake, fake, 1, 0, 5, None, 10, fake, None) == -1      # frames NULL
     fm = lib.scps_funnel_mean_path
@@ -100,3 +102,39 @@ def test_context_free_entry_points_validate_on_the_host(lib):
     zeros = (C.c_uint8 * 4)()
     assert fm(4, 3, fake, zeros, fake, None) == -7                                    # no successful trajectory
     assert fm(4, 3, None, zeros, fake, None) == -1
+
+
+def test_init_lays_out_every_chain_shape_before_device_memory(lib):
+    """scps_init_system builds the host-side layout (internal particle order,
+    tile flags and sub-step masks, the persistent schedules, the per-step
+    work lists) before its first device allocation.  Several chain shapes run
+    through it: two particles, a ragged chain with a partial contact set,
+    min_seq_sep 35 on the heavy-particle contact set, both cutoffs (the
+    neighbour-list path), two systems of different lengths, SCPS mode.  With a
+    GPU every context is created and destroyed; without one each call stops
+    at the first device allocation with a HIP status and frees what it held.
+    (Under tests/run_sanitizers.sh this puts that host code under ASan and
+    UBSan.)"""
+    import torch
+    from paper_1705_02180_amd import inputs as I
+    from paper_1705_02180_amd import scps
+    base = dict(I._base_params())
+    w2 = I.config2(n_replicas=3, n_steps=1)
+    cases = [   # params, chain lengths, contact sets, replica systems, exec mode
+        (base, [2], [[0, 1]], [0], 0),
+        (dict(base, min_seq_sep=5), [257], [list(range(0, 257, 3))], [0, 0], 0),
+        (dict(w2.params, min_seq_sep=35), [560], [w2.systems[0].contact_idx], [0, 0, 0], 0),
+        (dict(base, r_cut_contact=12.0, r_cut_nb=12.0), [300], [list(range(300))], [0, 0], 1),
+        (dict(base, bias_mode=1), [150, 200], [list(range(150)), list(range(0, 200, 2))], [0, 1, 1, 0], 0),
+        (dict(base, bias_mode=1), [130], [list(range(130))], [0] * 40, 2),
+    ]
+    for p, sizes, cidx, rsys, exec_mode in cases:
+        mass = [np.full(n, 1.0, np.float32) for n in sizes]
+        charge = [np.zeros(n, np.float32) for n in sizes]
+        try:
+            ctx = scps.Context(p, sizes, cidx, mass, charge, rsys, exec_mode=exec_mode)
+        except scps.ScpsError as e:
+            assert not torch.cuda.is_available() and e.status == -4, (sizes, e)
+        else:
+            assert torch.cuda.is_available()
+            ctx.close()

@@ -5,7 +5,11 @@ Both sides run float64 with the same Philox counters; they differ only in the
 last bits of the transcendentals, which a funnel trajectory amplifies by at
 most ~1e5 over 1000 steps (measured on the oracle itself with a 1e-13
 start perturbation), so positions and frames are compared to 1e-7 and the
-collective variables and T to matching relative bounds.
+collective variables and T to matching relative bounds.  Where a run is
+chaotic (the tube ratchets without the 1/lambda in w: a 1e-13 start
+perturbation moves the oracle's own running minimum s_m by ~3e-4 and T by
+~100 % on some trajectories), each trajectory is held to the oracle's own
+spread under that perturbation, measured in the test, with a factor 10.
 """
 import numpy as np
 import pytest
@@ -55,27 +59,42 @@ def test_funnel_rmd_matches_oracle(S):
     assert np.all(co[:, 7] > 0)
 
 
-def test_funnel_scps_matches_oracle(S):
+@pytest.mark.parametrize("w_form,every", [(0, 40), (1, 40), (0, 20)],
+                         ids=["w_with_1_over_lambda_51_frames", "w_without_1_over_lambda_51_frames",
+                              "w_with_1_over_lambda_101_frames"])
+def test_funnel_scps_matches_oracle(S, w_form, every):
+    """Tube ratchets around the mean path of the oracle's rMD ensemble, both
+    forms of w (with the 1/lambda of eq (wX), and without it as the toy-model
+    section prints it), and a mean path of more than 64 frames."""
     import torch
     p = I.funnel_params()
     # the mean path: the oracle's own rMD ensemble (1000 trajectories, as in the paper)
     xy0, cv0 = start(1000)
-    xo, _, fo = O.funnel_steps(p, xy0, cv0, 2000, record_every=40)
+    xo, _, fo = O.funnel_steps(p, xy0, cv0, 2000, record_every=every)
     succ = np.hypot(*xo.T) < 1.0
     mp = fo[:, succ].mean(axis=1)
-    ps = dict(p, bias_mode=1)
+    ps = dict(p, bias_mode=1, w_form=w_form)
     n, steps = 256, 1000
     xy0, cv0 = start(n)
     xy, cv = dev(xy0), dev(cv0)
     S.funnel_steps(ps, xy, cv, steps, mean_path=dev(mp))
     torch.cuda.synchronize()
     xs, cs, _ = O.funnel_steps(ps, xy0, cv0, steps, mean_path=mp)
+    # the oracle's own spread: the same trajectories from starts moved by 1e-13
+    xp, cp, _ = O.funnel_steps(ps, xy0 + 1e-13, cv0, steps, mean_path=mp)
     g, cg = xy.cpu().numpy(), cv.cpu().numpy()
+    sx = np.abs(xs - xp).max(axis=1, keepdims=True)
+    scv = np.abs(cs[:, 3:7] - cp[:, 3:7])
+    sT = np.abs(cs[:, 7] - cp[:, 7])
+    chaotic = int(np.count_nonzero((sx[:, 0] > 1e-8) | (scv.max(axis=1) > 1e-8)))
     print(f"  SCPS: max |dx| {np.abs(g - xs).max():.2e}, s {np.abs(cg[:, 3] - cs[:, 3]).max():.2e}, "
-          f"reached the bottom: {np.mean(np.hypot(*xs.T) < 1):.2f}", flush=True)
-    np.testing.assert_allclose(g, xs, rtol=0, atol=1e-7)
-    np.testing.assert_allclose(cg[:, 3:7], cs[:, 3:7], rtol=0, atol=1e-7)
-    np.testing.assert_allclose(cg[:, 7], cs[:, 7], rtol=1e-6, atol=1e-12)
+          f"reached the bottom: {np.mean(np.hypot(*xs.T) < 1):.2f}, trajectories the perturbation moves "
+          f"by more than 1e-8: {chaotic}", flush=True)
+    assert np.all(np.abs(g - xs) <= 1e-7 + 10 * sx)
+    assert np.all(np.abs(cg[:, 3:7] - cs[:, 3:7]) <= 1e-7 + 10 * scv)
+    assert np.all(np.abs(cg[:, 7] - cs[:, 7]) <= 1e-6 * cs[:, 7] + 1e-12 + 10 * sT)
+    if w_form == 0:
+        assert chaotic == 0
 
 
 def test_funnel_mean_path_matches_numpy(S):
@@ -97,5 +116,5 @@ def test_funnel_rejects_bad_paths(S):
         S.funnel_steps(ps, dev(xy0), dev(cv0), 1)                          # no mean path
     assert e.value.status == -1
     with pytest.raises(S.ScpsError) as e:
-        S.funnel_steps(ps, dev(xy0), dev(cv0), 1, mean_path=dev(np.zeros((65, 2))))
+        S.funnel_steps(ps, dev(xy0), dev(cv0), 1, mean_path=dev(np.zeros((129, 2))))
     assert e.value.status == -2

@@ -413,24 +413,32 @@ SCPS_CASES = [
     ("bias_only_160_K17_cutoff12", [160], ["all"], 17, 4, True, {"r_cut_contact": 12.0}),
     ("two_systems_K20", [150, 200], ["all", "every3"], 20, 6, False, {}),
     ("smallest_stack_K2", [100], ["all"], 2, 3, False, {}),
-    ("largest_stack_K64_bias_only", [120], ["all"], 64, 5, True, {}),
+    ("K64_bias_only", [120], ["all"], 64, 5, True, {}),
+    ("K72_protocol_frames", [140], ["all"], 72, 5, False, {}),
+    ("K128_largest_stack_R36", [110], ["all"], 128, 36, False, {}),
+    ("two_systems_K48_K100", [130, 150], ["all", "every3"], [48, 100], 4, True, {}),
+    ("seqsep35_200_K21", [200], ["all"], 21, 5, False, {"min_seq_sep": 35}),
     ("one_block_60_K5", [60], ["all"], 5, 3, False, {}),
 ]
+SCPS_FORMS = [(0, 0), (2, 0), (0, 1)]
 
 
-@pytest.mark.parametrize("exec_mode", [0, 2], ids=["fused", "two_pass"])
+@pytest.mark.parametrize("exec_mode,w_form", SCPS_FORMS, ids=["fused", "two_pass", "fused_w_without_1_over_lambda"])
 @pytest.mark.parametrize("name,sizes,kinds,K,R,bias_only,extra", SCPS_CASES, ids=[c[0] for c in SCPS_CASES])
-def test_scps_step_forces_match_oracle(S, name, sizes, kinds, K, R, bias_only, extra, exec_mode):
+def test_scps_step_forces_match_oracle(S, name, sizes, kinds, K, R, bias_only, extra, exec_mode, w_form):
     """One SCPS step (distances to all K frames, tube variables and ratchets,
     bias + physics) against the oracle, with the frame stack built on the GPU
     from recorded paths and, separately, uploaded from the oracle's FP64 maps.
-    K > 16 uses several frame blocks of the distance pass; R > 32 several
-    replica groups; two systems two stacks.  Both forms of the bias: the
+    K > 64 takes the distance pass in two frame blocks and the bias pass in
+    two MFMA chains; R > 32 several replica groups; two systems two stacks
+    (of different sizes when K is a list).  Both forms of the bias: the
     effective references formed inside the bias pass (fused) and written to
-    device memory first (two_pass)."""
+    device memory first (two_pass); and both forms of w (with the 1/lambda of
+    eq (wX), and without it as eq (awXa) prints it)."""
     import torch
     base = dict(I._base_params())
-    p = _force_readback_params(base, bias_mode=1, lam=13.5, k_s=50.0, k_w=5.0, **extra)
+    p = _force_readback_params(base, bias_mode=1, lam=13.5, k_s=50.0, k_w=5.0, w_form=w_form, **extra)
+    Ks = list(K) if isinstance(K, list) else [K] * len(sizes)
     if bias_only:
         p.update(k_bond=0.0, lj_eps=0.0, dh_prefactor=0.0)
     n_paths = 4
@@ -441,7 +449,7 @@ def test_scps_step_forces_match_oracle(S, name, sizes, kinds, K, R, bias_only, e
                       mass=np.full(n, 12.011 * I.AMU, dtype=np.float32),
                       charge=rng.normal(0, 0.3, n).astype(np.float32),
                       native=I.compact_native(n, 11 + s_id), start=I.persistent_start(n, 12 + s_id))
-        fr = _ensemble_frames(sy, K, n_paths, 8 + s_id)
+        fr = _ensemble_frames(sy, Ks[s_id], n_paths, 8 + s_id)
         st, ns = O.update_reference(sy.n, sy.contact_idx, fr.astype(np.float64), np.ones(n_paths, dtype=np.uint8),
                                     p["r0_contact"], p["r_cut_contact"])
         assert ns == n_paths
@@ -456,10 +464,11 @@ def test_scps_step_forces_match_oracle(S, name, sizes, kinds, K, R, bias_only, e
     cv0[:, 5:7] = np.inf
     for r in range(R):
         fr = frames[rsys[r]]
-        X.append(fr[(3 + 2 * r) % K, r % n_paths].astype(np.float32))
+        X.append(fr[(3 + 2 * r) % Ks[rsys[r]], r % n_paths].astype(np.float32))
         if r >= 1:
             sv, wv, *_ = O.tube(X[r].astype(np.float64), osys[rsys[r]].cidx, stacks[rsys[r]], osys[rsys[r]].Z0,
-                                p["lam"], p["r0_contact"], p["r_cut_contact"], p["min_seq_sep"], grads=False)
+                                p["lam"], p["r0_contact"], p["r_cut_contact"], p["min_seq_sep"], grads=False,
+                                w_form=w_form)
             cv0[r, 5] = sv - 0.05 * (1 + r % 3)
             cv0[r, 6] = wv - 0.01 * (1 + r % 3)
     want = [O.total_force(p, osys[rsys[r]], X[r].astype(np.float64), cv0[r]) for r in range(R)]
@@ -469,7 +478,7 @@ def test_scps_step_forces_match_oracle(S, name, sizes, kinds, K, R, bias_only, e
         ctx = context(S, w, params=p, exec_mode=exec_mode)
         for s_id, sy in enumerate(systems):
             if how == "update":
-                maps = ctx.update_reference_from_paths(s_id, dev(frames[s_id].ravel()), n_paths, K,
+                maps = ctx.update_reference_from_paths(s_id, dev(frames[s_id].ravel()), n_paths, Ks[s_id],
                                                        np.ones(n_paths, dtype=np.uint8), want_maps=True)
                 np.testing.assert_allclose(maps, stacks[s_id], rtol=1e-12, atol=1e-15)
             else:
@@ -495,8 +504,12 @@ def test_scps_step_forces_match_oracle(S, name, sizes, kinds, K, R, bias_only, e
             if bias_only:
                 assert r == 0 or np.abs(Fb).max() > 0          # the ratchets are active
             np.testing.assert_allclose(CV[r, 3:7], cvr[3:7], rtol=0, atol=1e-5, err_msg=f"{how} replica {r}")
+            # bias functional T = dt sum_i |F_bias,i|^2 / (m_i gamma): a bias-force error within the
+            # normwise bound TOL max_i |F_i| moves sqrt(T) by at most TOL max_i |F_i| sqrt(dt sum_i 1/(m_i gamma))
             _, _, cvs, _ = O.steps(p, osys[rsys[r]], r, X[r].astype(np.float64), np.zeros(X[r].shape), cv0[r], 1)
-            assert abs(CV[r, 7] - cvs[7]) <= TOL * cvs[7] + 1e-300, (how, r, CV[r, 7], cvs[7])
+            fmax = np.linalg.norm(F, axis=0).max()
+            tol_t = TOL * fmax * np.sqrt(p["dt"] * np.sum(1.0 / (sy.mass.astype(np.float64) * p["gamma"])))
+            assert abs(np.sqrt(CV[r, 7]) - np.sqrt(cvs[7])) <= tol_t + 1e-300, (how, r, CV[r, 7], cvs[7])
         ctx.close()
 
 
@@ -713,19 +726,28 @@ def test_two_particle_chain_matches_oracle(S, exec_mode, cut):
 
 
 def test_frame_stack_limit_is_enforced(S):
+    """Stacks hold 2 .. 128 frames; 129 are rejected with SHAPE by both ways of
+    setting a stack, and the context stays usable."""
     base = dict(I._base_params(), bias_mode=1)
     w = single_system_workload(70, np.arange(70), base, 2)
     sy = w.systems[0]
     ctx = context(S, w, params=base)
-    fr = _ensemble_frames(sy, 65, 1, 3)
+    fr = _ensemble_frames(sy, 129, 1, 3)
     with pytest.raises(S.ScpsError) as e:
-        ctx.update_reference_from_paths(0, dev(fr.ravel()), 1, 65, np.ones(1, dtype=np.uint8))
+        ctx.update_reference_from_paths(0, dev(fr.ravel()), 1, 129, np.ones(1, dtype=np.uint8))
+    assert e.value.status == -2
+    P = 70 * 69 // 2
+    with pytest.raises(S.ScpsError) as e:
+        ctx.set_reference_map(0, maps=np.full((129, P), 0.5))
     assert e.value.status == -2
     import torch
     x = dev(np.stack([sy.start, sy.start]).astype(np.float32).ravel())
     with pytest.raises(S.ScpsError) as e:        # SCPS stepping needs a stack of >= 2 frames
         ctx.step_replicas(x, torch.zeros_like(x), dev(w.initial_cvstate(), "f64"), 1)
     assert e.value.status == -5
+    ctx.set_reference_map(0, maps=np.full((128, P), 0.5))       # the largest stack is accepted
+    ctx.step_replicas(x, torch.zeros_like(x), dev(w.initial_cvstate(), "f64"), 1)
+    ctx.sync()
 
 
 def test_autotune_picks_a_valid_launch_and_keeps_results(S):
@@ -986,14 +1008,15 @@ def test_lists_follow_positions_changed_between_calls(S):
 # ---------------------------------------------------------------------------
 # tube variables against any stack, and the global coordinate sigma(X)
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("mode", [0, 1], ids=["rmd_context", "scps_context"])
-def test_eval_tube_and_sigma_match_oracle(S, mode):
+@pytest.mark.parametrize("mode,w_form", [(0, 0), (1, 0), (1, 1)],
+                         ids=["rmd_context", "scps_context", "scps_context_w_without_1_over_lambda"])
+def test_eval_tube_and_sigma_match_oracle(S, mode, w_form):
     """Three initial conditions of one chain (three systems, each with the
     stack of its own paths); every replica is measured against every stack,
     and sigma is the mean of 1 - s over them."""
     import torch
     n, K, n_paths, R = 170, 11, 3, 7
-    base = dict(I._base_params(), bias_mode=mode, lam=13.5, k_s=2.5, k_w=2.5e-4)
+    base = dict(I._base_params(), bias_mode=mode, lam=13.5, k_s=2.5, k_w=2.5e-4, w_form=w_form)
     rng = np.random.default_rng(4)
     proto = I.System(n=n, contact_idx=np.arange(n, dtype=np.int32), mass=np.full(n, 12.011 * I.AMU, np.float32),
                      charge=rng.normal(0, 0.3, n).astype(np.float32), native=I.compact_native(n, 4),
@@ -1022,10 +1045,11 @@ def test_eval_tube_and_sigma_match_oracle(S, mode):
         ctx.eval_tube(b, x, s, wv)
         ctx.sync()
         for r in range(R):
-            so, wo, *_ = O.tube(X[r].astype(np.float64), proto.contact_idx, stacks[b], Z0, 13.5, grads=False)
+            so, wo, *_ = O.tube(X[r].astype(np.float64), proto.contact_idx, stacks[b], Z0, 13.5, grads=False,
+                                w_form=w_form)
             print(f"  stack {b} replica {r}: s {host(s)[r]:.6f} (oracle {so:.6f}), w {host(wv)[r]:.6f} "
                   f"(oracle {wo:.6f})", flush=True)
-            assert abs(host(s)[r] - so) <= 1e-5 and abs(host(wv)[r] - wo) <= 1e-5
+            assert abs(host(s)[r] - so) <= 1e-5 and abs(host(wv)[r] - wo) <= 1e-5 * max(1.0, abs(wo))
     for sel in ([0, 1, 2], [2], [1, 1, 0]):
         sg = torch.zeros(R, dtype=torch.float64, device="cuda")
         ctx.eval_sigma(sel, x, sg)
