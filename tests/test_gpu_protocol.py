@@ -300,9 +300,11 @@ def test_scps_appendix_limit_on_frames(S, limit_case, exec_mode):
     the forces of one step (with and without the physical forces) to 1e-5
     normwise for replicas on, near and between frames, 34 replicas in two
     replica groups, 51 frames.  Close to a frame the bias force is a sum of
-    small differences C - R_l, so the stack's float32 storage moves it by
-    itself: that part is measured with the oracle on the same stack rounded to
-    float32 and added to the force tolerance."""
+    small differences C - R_l whose two float32 roundings (the contact value
+    of the float32 pair math and the stack's float32 storage, each within an
+    ulp) move it by themselves: the second is measured with the oracle on the
+    same stack rounded to float32, and twice that is added to the force
+    tolerance."""
     import torch
     c = limit_case
     sy, X, lam = c["sy"], c["X"], c["lam"]
@@ -348,7 +350,7 @@ def test_scps_appendix_limit_on_frames(S, limit_case, exec_mode):
                 err = normwise(Fg[r], F)
                 storage = normwise(want32[r][0], F)       # the float32 stack's own effect on the force
                 worst[kind] = max(worst[kind], err)
-                assert err <= TOL + storage, (physics, r, kind, err, storage)
+                assert err <= TOL + 2.0 * storage, (physics, r, kind, err, storage)
             else:
                 # on a frame the bias force is rounding noise on both sides (the
                 # oracle's is exactly 0): it must stay negligible next to the
