@@ -327,6 +327,20 @@ scps_status scps_autotune(scps_ctx *ctx, const float *x, const float *v, const d
 scps_status scps_path_distance(const float *xy_a, int64_t n_a, const float *xy_b, int64_t n_b, double x0,
                                double y0, double cell, int32_t nx, int32_t ny, void *hip_stream, double *D);
 
+/* scps_path_distance for callers that cannot allocate device memory (code
+ * under HIP graph capture or in tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments, kernels and result, with the occupancy grids
+ * and counts in a fixed device array that every GPU the library runs on
+ * holds until the process ends (8 MiB + 32 bytes), so grids are limited to
+ * nx ny <= 2^20 cells.  Calls no hipMalloc or hipFree; the scratch is cleared
+ * by a kernel at every call.  Every call on one GPU shares that GPU's array:
+ * calls that overlap on one GPU (different streams or threads) race.  Blocks
+ * until done.  Errors: INVALID_ARG (as scps_path_distance), SHAPE (more than
+ * 2^20 cells), HIP. */
+scps_status scps_path_distance_noalloc(const float *xy_a, int64_t n_a, const float *xy_b, int64_t n_b, double x0,
+                                       double y0, double cell, int32_t nx, int32_t ny, void *hip_stream,
+                                       double *D);
+
 /* ---------------------------------------------------------------------------
  * Toy model (section "Diffusion in a 2-dimensional asymmetric funnel"): one
  * particle on the funnel of eq (U),

@@ -1225,6 +1225,33 @@ scps_status scps_path_distance(const float *xy_a, int64_t n_a, const float *xy_b
     return SCPS_OK;
 }
 
+scps_status scps_path_distance_noalloc(const float *xy_a, int64_t n_a, const float *xy_b, int64_t n_b, double x0,
+                                       double y0, double cell, int32_t nx, int32_t ny, void *hip_stream,
+                                       double *D) {
+    if ((!xy_a && n_a > 0) || (!xy_b && n_b > 0) || !D || n_a < 0 || n_b < 0)
+        return fail(SCPS_ERR_INVALID_ARG, "NULL point array or output, or a negative count");
+    if (!(cell > 0) || nx < 1 || ny < 1)
+        return fail(SCPS_ERR_INVALID_ARG, "cell must be > 0 and the grid at least 1 x 1");
+    if ((int64_t)nx * ny > PATH_NOALLOC_MAX_CELLS)
+        return fail(SCPS_ERR_SHAPE, "a grid of more than " + std::to_string(PATH_NOALLOC_MAX_CELLS) +
+                                        " cells needs scps_path_distance (this call allocates nothing)");
+    hipStream_t st = (hipStream_t)hip_stream;
+    int *d_occ = nullptr;
+    long long *d_counts = nullptr;
+    hipError_t e = path_scratch(&d_occ, &d_counts);
+    long long counts[3] = {0, 0, 0};
+    if (e == hipSuccess)
+        e = launch_path_occupancy(xy_a, n_a, xy_b, n_b, x0, y0, cell, nx, ny, d_occ, d_counts, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(counts, d_counts, sizeof(counts), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(SCPS_ERR_HIP, std::string("path distance: ") + hipGetErrorString(e));
+    if (counts[0] == 0 || counts[1] == 0)
+        return fail(SCPS_ERR_INVALID_ARG, "a point set occupies no cell of the grid");
+    const double c = (double)counts[2] / std::sqrt((double)counts[0] * (double)counts[1]);
+    *D = std::sqrt(std::max(0.0, 2.0 - 2.0 * c));
+    return SCPS_OK;
+}
+
 scps_status scps_funnel_steps(const scps_funnel_params *p, int32_t n_traj, int32_t first_id, double *xy,
                               double *cvstate, int64_t n_steps, uint64_t step0, int32_t record_every, double *frames,
                               int32_t n_path_frames, const double *mean_path, void *hip_stream) {

@@ -230,6 +230,11 @@ hipError_t launch_sum_squares_sep(int nc, int min_sep, const int *perm, const do
 hipError_t launch_path_occupancy(const float *xy_a, int64_t n_a, const float *xy_b, int64_t n_b, double x0,
                                  double y0, double cell, int nx, int ny, int *occ, long long *counts,
                                  hipStream_t st);
+// The convergence measure without allocation: grids of at most
+// PATH_NOALLOC_MAX_CELLS cells in a file-scope device array (8 MiB per GPU);
+// path_scratch gives the current GPU's address of its grids and counts.
+constexpr int PATH_NOALLOC_MAX_CELLS = 1 << 20;
+hipError_t path_scratch(int **occ, long long **counts);
 hipError_t launch_scale_by_replica(const SysDesc *sysd, const RepDesc *reps, int R, int n_pad_max, const float *in,
                                    const double *coef, float *out, hipStream_t st);
 hipError_t launch_least_biased(const double *cv, const int *list, int n, int *out_i, double *out_t, hipStream_t st);

@@ -15,6 +15,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "scps_device.h"
 #include "scps_internal.h"
@@ -1119,6 +1120,32 @@ __global__ __launch_bounds__(256) void k_occupancy_overlap(const int *__restrict
 
 __global__ void k_fill_int(int *__restrict__ v, int m) {
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < m; e += gridDim.x * blockDim.x) v[e] = 0;
+}
+
+// Scratch of the convergence measure for callers that cannot allocate: the
+// four counts (long long) first, then the two occupancy grids, in a file-scope
+// device array each GPU holds until the process ends.  Host code must not
+// pass `scratch` itself to a kernel (in host code the name is a stand-in, not
+// a device address): path_scratch() returns this GPU's address of it.
+static __device__ __align__(256) int scratch[8 + 2 * PATH_NOALLOC_MAX_CELLS];
+
+hipError_t path_scratch(int **occ, long long **counts) {
+    static std::mutex lock;
+    static void *addr[64] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> guard(lock);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));   // with this device current: its own copy
+        if (e != hipSuccess) return e;
+        addr[dev] = p;
+    }
+    *counts = reinterpret_cast<long long *>(addr[dev]);
+    *occ = reinterpret_cast<int *>(addr[dev]) + 8;
+    return hipSuccess;
 }
 
 hipError_t launch_path_occupancy(const float *xy_a, int64_t n_a, const float *xy_b, int64_t n_b, double x0,

@@ -85,6 +85,8 @@ _lib.scps_eval_sigma.restype = C.c_int
 _lib.scps_eval_sigma.argtypes = [_vp, _i32, _vp, _vp, _vp]
 _lib.scps_path_distance.restype = C.c_int
 _lib.scps_path_distance.argtypes = [_vp, _i64, _vp, _i64, _d, _d, _d, _i32, _i32, _vp, C.POINTER(C.c_double)]
+_lib.scps_path_distance_noalloc.restype = C.c_int
+_lib.scps_path_distance_noalloc.argtypes = _lib.scps_path_distance.argtypes
 _lib.scps_funnel_steps.restype = C.c_int
 _lib.scps_funnel_steps.argtypes = [C.c_void_p, _i32, _i32, _vp, _vp, _i64, _u64, _i32, _vp, _i32, _vp, _vp]
 _lib.scps_funnel_mean_path.restype = C.c_int
@@ -99,6 +101,7 @@ _lib.scps_last_error.argtypes = []
 EXPORTS = ["scps_init_system", "scps_set_reference_map", "scps_step_replicas", "scps_eval_z_and_grad",
            "scps_ratchet_energy", "scps_update_reference_from_paths", "scps_set_stream", "scps_sync",
            "scps_autotune", "scps_least_biased_path", "scps_eval_tube", "scps_eval_sigma", "scps_path_distance",
+           "scps_path_distance_noalloc",
            "scps_funnel_steps", "scps_funnel_mean_path", "scps_scale_by_replica", "scps_destroy",
            "scps_last_error"]
 
@@ -387,6 +390,20 @@ def path_distance(xy_a: torch.Tensor, xy_b: torch.Tensor, x0: float, y0: float, 
     _check(_lib.scps_path_distance(_dev(xy_a, torch.float32, None, "xy_a"), int(xy_a.shape[0]),
                                    _dev(xy_b, torch.float32, None, "xy_b"), int(xy_b.shape[0]), float(x0), float(y0),
                                    float(cell), int(nx), int(ny), _stream(), C.byref(D)))
+    return float(D.value)
+
+
+def path_distance_noalloc(xy_a: torch.Tensor, xy_b: torch.Tensor, x0: float, y0: float, cell: float, nx: int,
+                          ny: int) -> float:
+    """path_distance without device allocation (grids of at most 2^20 cells,
+    scratch in a fixed device array per GPU; overlapping calls on one GPU race)."""
+    for t, name in ((xy_a, "xy_a"), (xy_b, "xy_b")):
+        if t.dim() != 2 or t.shape[1] != 2:
+            raise ValueError(f"{name} must have shape [n, 2]")
+    D = C.c_double(0.0)
+    _check(_lib.scps_path_distance_noalloc(_dev(xy_a, torch.float32, None, "xy_a"), int(xy_a.shape[0]),
+                                           _dev(xy_b, torch.float32, None, "xy_b"), int(xy_b.shape[0]), float(x0),
+                                           float(y0), float(cell), int(nx), int(ny), _stream(), C.byref(D)))
     return float(D.value)
 
 

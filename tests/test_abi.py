@@ -84,6 +84,12 @@ def test_context_free_entry_points_validate_on_the_host(lib):
     assert f(None, 5, fake, 5, 0.0, 0.0, 0.8, 20, 20, None, C.byref(D)) == -1     # NULL points with n > 0
     assert f(fake, 5, fake, 5, 0.0, 0.0, 0.0, 20, 20, None, C.byref(D)) == -1     # cell <= 0
     assert f(fake, 5, fake, 5, 0.0, 0.0, 0.8, 0, 20, None, C.byref(D)) == -1      # empty grid
+    g = lib.scps_path_distance_noalloc                                           # the variant without allocation
+    g.restype = C.c_int
+    g.argtypes = scps._lib.scps_path_distance_noalloc.argtypes
+    assert g(None, 5, fake, 5, 0.0, 0.0, 0.8, 20, 20, None, C.byref(D)) == -1
+    assert g(fake, 5, fake, 5, 0.0, 0.0, -1.0, 20, 20, None, C.byref(D)) == -1
+    assert g(fake, 5, fake, 5, 0.0, 0.0, 0.8, 1025, 1024, None, C.byref(D)) == -2   # beyond its 2^20 cells
     fs = lib.scps_funnel_steps
     fs.restype = C.c_int
     fs.argtypes = scps._lib.scps_funnel_steps.argtypes
