@@ -1,28 +1,34 @@
 """Throughput of batched rMD / SCPS stepping on one MI355X.
 
-Default workload (the headline line): 256 replicas of a 560-particle chain
-(35 groups of 16, contacts over the 280 heavy particles: 39,060 contact pairs,
-155,403 nonbonded pairs), Lennard-Jones + Debye-Hueckel, BAOAB at dt = 2 fs,
-T = 300 K, ratchet on z.  One benchmark step = one scps_step_replicas call that
-advances every replica by --block Langevin steps (one persistent kernel
-launch).  Inputs are seeded and synthetic and resident in HBM before timing.
+Default workload (the headline line, --workload scps6000): one self-consistent
+path-sampling iteration of the serpin-sized chain -- 32 replicas of a
+6000-particle chain (17,997,000 contact pairs, LJ + Debye-Hueckel), BAOAB at
+dt = 2 fs, T = 300 K, under the SCPS tube-variable ratchets on a stack of 51
+frame maps.  One benchmark step = 200 Langevin steps of every replica (one
+frame interval) with its frame recorded; 50 steps make the 10^4-step
+iteration, and the timed region ends with the iteration's eq (avCij) over the
+recorded frames.  Before timing, a parity check at the same configuration
+(forces, s and w of two replicas against the FP64 oracle).  Inputs are seeded
+and synthetic and resident in HBM before timing.
 
 Other workloads (--workload), each printed as its own JSON line:
+  chain560      256 replicas of a 560-particle chain (35 groups of 16,
+                contacts over the 280 heavy particles), ratchet on z, blocks
+                of 100 steps in one persistent launch
   uneven512     512 chains, N ~ U{200..3000}, each with its own native map
   autograd3000  z and E_b forward + backward for 64 chains of 3000 particles
-  scps6000      32 replicas of a 6000-particle chain: the ensemble mean of
-                51 recorded frames over 32 paths, then SCPS-biased stepping
-  cutoff6000    the same chain under rMD with contact and nonbonded cutoffs of
-                12 A from compact states: neighbour lists against the
-                all-tiles path
+  cutoff6000    the 6000-particle chain under rMD with contact and nonbonded
+                cutoffs of 12 A from compact states: neighbour lists against
+                the all-tiles path
   funnel        the toy model: 262,144 trajectories on the asymmetric funnel,
                 rMD from (0, 5), the mean path of the successful ones, then
                 the tube-ratchet iteration (the timed line)
 
 Printed: replica-steps/s (value), contact-pair evals/s, the plain
-one-replica-per-launch form (headline workload), the roofline of the timed
-launch (algorithmic FP32 work / HIP-event time of each launch) and the FP64
-CPU oracle timed on this host on a bounded sample of the same workload.
+one-replica-per-call form, the roofline of the dominant kernel (algorithmic
+bytes or flops per launch / its launch duration from HIP events on its
+stream), HBM traffic from committed counter summaries, and the FP64 CPU oracle
+timed on this host on a bounded sample of the same workload.
 """
 import argparse
 import json
@@ -62,20 +68,31 @@ PEAK_HBM = 8.0e12       # MI355X HBM3E, bytes/s
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="chain560",
+    ap.add_argument("--workload", default="scps6000",
                     choices=["chain560", "uneven512", "autograd3000", "scps6000", "cutoff6000", "funnel"])
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--block", type=int, default=100, help="Langevin steps per benchmark step")
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed benchmark steps (default: 50 for scps6000, one 10^4-step iteration; else 20)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed benchmark steps (default 2 / 3)")
+    ap.add_argument("--block", type=int, default=None,
+                    help="Langevin steps per benchmark step (default: 200 for scps6000, a frame interval; else 100)")
     ap.add_argument("--replicas", type=int, default=0, help="0: the workload's own count")
     ap.add_argument("--plain-replicas", type=int, default=8)
     ap.add_argument("--plain-steps", type=int, default=20)
     ap.add_argument("--cpu-steps", type=int, default=300)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-parity", action="store_true",
+                    help="skip the parity check before timing (short profiler runs only)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 256 MiB (to scale HBM byte counters)")
-    return ap.parse_args()
+    a = ap.parse_args()
+    if a.steps is None:
+        a.steps = SCPS_ITER_STEPS // 200 if a.workload == "scps6000" else 20
+    if a.warmup is None:
+        a.warmup = 2 if a.workload == "scps6000" else 3
+    if a.block is None:
+        a.block = 200 if a.workload == "scps6000" else 100
+    return a
 
 
 # sources of the persistent rMD kernel: its counter summary is valid for these
@@ -102,6 +119,30 @@ def measured_traffic():
     except (OSError, ValueError):
         return None
     if t.get("source_sha256") != source_sha256():
+        return None
+    return t.get("bytes_per_launch")
+
+
+SCPS_KERNEL_SOURCES = [os.path.join(ROOT, "paper_1705_02180_amd", "csrc", f)
+                       for f in ("scps_maps.hip", "scps_device.h", "scps_internal.h")]
+SCPS_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_scps_traffic_chain6000x32.json")
+
+
+def measured_scps_traffic():
+    """HBM bytes per launch of the SCPS step's two passes ({"distance": B,
+    "bias": B}) from the committed counter summary, or None when it is
+    missing or was taken on different kernel sources."""
+    import hashlib
+    try:
+        with open(SCPS_TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for path in SCPS_KERNEL_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    if t.get("source_sha256") != h.hexdigest():
         return None
     return t.get("bytes_per_launch")
 
@@ -391,8 +432,104 @@ def bench_autograd3000(args, torch, I, scps):
 
 
 # ---------------------------------------------------------------------------
-# 32 x 6000: ensemble mean of recorded paths, then SCPS stepping
+# 32 x 6000, 51 frames: one SCPS iteration (the headline workload)
 # ---------------------------------------------------------------------------
+SCPS_FRAMES = 51          # a frame every 200 steps over a 10^4-step iteration
+SCPS_ITER_STEPS = 10000
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _pmap(fn, items, threads):
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max(1, threads)) as ex:      # the oracle's ctypes calls release the GIL
+        return list(ex.map(fn, items))
+
+
+def oracle_stack(sy, frames, params, threads):
+    """eq (avCij) of one path's frames [K][1][3][n] by the oracle, the frames
+    split over threads; float64 [K][P]."""
+    import numpy as np
+    import oracle as O
+    K = frames.shape[0]
+    P = len(sy.contact_idx) * (len(sy.contact_idx) - 1) // 2
+    out = np.empty((K, P))
+    chunks = [list(range(k, min(K, k + 4))) for k in range(0, K, 4)]
+
+    def one(ch):
+        st, _ = O.update_reference(sy.n, sy.contact_idx, frames[ch].astype(np.float64), np.ones(1, dtype=np.uint8),
+                                   params["r0_contact"], params["r_cut_contact"])
+        out[ch] = st
+    _pmap(one, chunks, threads)
+    return out
+
+
+def scps6000_parity(torch, scps, w, threads):
+    """Parity check at the timed configuration before timing: the same chain,
+    replica count, stack size and launch path, with the stack of one path's
+    51 frames computed by both sides; forces read back from one BAOAB step
+    from rest at kT = 0 (v = c1 dt F / m) on two sampled replicas with active
+    tube ratchets, against the oracle's total force (1e-5 normwise), and s, w
+    (1e-5).  Returns (summary, the oracle's stack, its frames)."""
+    import math
+    import numpy as np
+    import oracle as O
+    sy = w.systems[0]
+    n, R, K = sy.n, w.n_replicas, SCPS_FRAMES
+    p = dict(w.params, bias_mode=1, kT=0.0, gamma=1e-3)
+    rng = np.random.default_rng(31)
+    frames = np.empty((K, 1, 3, n), dtype=np.float32)
+    for k in range(K):
+        lam = k / (K - 1)
+        frames[k, 0] = (1 - lam) * sy.start + lam * sy.native + rng.normal(0, 0.5, size=(3, n))
+    t0 = time.perf_counter()
+    stack = oracle_stack(sy, frames, p, threads)
+    osys = O.System(n, sy.contact_idx, sy.mass, sy.charge, p, native_xyz=sy.native, stack=stack)
+    X = np.stack([(frames[(7 + 3 * r) % K, 0] + rng.normal(0, 0.3, size=(3, n))) for r in range(R)]).astype(np.float32)
+    sample = [13, R - 1]
+    cv0 = np.zeros((R, 8))
+    cv0[:, 5:7] = np.inf
+    for r in sample:
+        sv, wv, *_ = O.tube(X[r].astype(np.float64), osys.cidx, stack, osys.Z0, p["lam"], grads=False)
+        cv0[r, 5], cv0[r, 6] = sv - 0.05, wv - 0.01
+    ctx = scps.Context.from_workload(w, params=p)
+    ctx.set_reference_map(0, native_xyz=sy.native)
+    ctx.update_reference_from_paths(0, torch.as_tensor(frames.ravel(), device="cuda"), 1, K,
+                                    np.ones(1, dtype=np.uint8))
+    x = torch.as_tensor(X.ravel(), device="cuda")
+    v = torch.zeros_like(x)
+    cv = torch.as_tensor(cv0, device="cuda")
+    ctx.step_replicas(x, v, cv, 1)
+    ctx.sync()
+    ctx.close()
+    c1 = math.exp(-p["gamma"] * p["dt"])
+    V = v.cpu().numpy().reshape(R, 3, n).astype(np.float64) * sy.mass.astype(np.float64) / (c1 * p["dt"])
+    CV = cv.cpu().numpy()
+    want = _pmap(lambda r: O.total_force(p, osys, X[r].astype(np.float64), cv0[r]), sample, threads)
+    errs, ds, dw = [], [], []
+    for r, (F, Fb, cvo) in zip(sample, want):
+        d = np.linalg.norm(V[r] - F, axis=0).max() / np.linalg.norm(F, axis=0).max()
+        errs.append(float(d))
+        ds.append(float(abs(CV[r, 3] - cvo[3])))
+        dw.append(float(abs(CV[r, 4] - cvo[4])))
+    ok = max(errs) <= 1e-5 and max(ds) <= 1e-5 and max(dw) <= 1e-5
+    summary = {"replicas": sample, "force_err_normwise": errs, "s_err": ds, "w_err": dw, "tol": 1e-5,
+               "passed": bool(ok), "oracle_s": round(time.perf_counter() - t0, 1),
+               "check": f"{R} x {n}, {K}-frame stack of one path (both sides compute it), forces of one BAOAB "
+                        f"step from rest at kT = 0 on replicas {sample} (tube ratchets active), s and w"}
+    print(f"parity at the timed configuration: {summary}", file=sys.stderr, flush=True)
+    return summary, stack, frames
+
+
 def bench_scps6000(args, torch, I, scps):
     import numpy as np
     R = args.replicas or 32
@@ -400,105 +537,150 @@ def bench_scps6000(args, torch, I, scps):
     sy = w.systems[0]
     n = sy.n
     con, nb, both = pair_counts(sy, w.params)
-    K = 51
-    every = 2                                   # a short rMD run records the K frames
+    K = SCPS_FRAMES
+    blk = args.block
+    threads = min(host_threads(), 16)
+    parity, ostack = None, None
+    if not args.no_parity:
+        parity, ostack, _ = scps6000_parity(torch, scps, w, threads)
+    # the stack the timed iteration starts from: the ensemble mean of a short
+    # rMD run's recorded frames (iteration 0, abbreviated here)
     rmd = scps.Context.from_workload(w)
     rmd.set_reference_map(0, native_xyz=sy.native)
     x = torch.as_tensor(w.initial_x(), device="cuda")
     v = torch.as_tensor(w.initial_v(7), device="cuda")
     cv = torch.as_tensor(w.initial_cvstate(), device="cuda")
-    frames = torch.empty(K * 3 * R * n, dtype=torch.float32, device="cuda")
-    rmd.step_replicas(x, v, cv, every * (K - 1), record_every=every, frames=frames)
+    frames0 = torch.empty(K * 3 * R * n, dtype=torch.float32, device="cuda")
+    rmd.step_replicas(x, v, cv, 2 * (K - 1), record_every=2, frames=frames0)
     rmd.sync()
     rmd.close()
     p = dict(w.params, bias_mode=1)
     ctx = scps.Context.from_workload(w, params=p)
     ctx.set_reference_map(0, native_xyz=sy.native)
     succ = np.ones(R, dtype=np.uint8)
-    # eq (avCij) over all paths x frames, timed on its own
-    for _ in range(2):
-        ctx.update_reference_from_paths(0, frames, R, K, succ)
-    torch.cuda.synchronize()
-    wall_u, per_u = timed_calls(torch, lambda _: ctx.update_reference_from_paths(0, frames, R, K, succ), 3)
+    ctx.update_reference_from_paths(0, frames0, R, K, succ)
     cvs = torch.as_tensor(w.initial_cvstate(), device="cuda")
+    x0, v0 = x.clone(), v.clone()
+    n3 = 3 * R * n
+    nrec = min(args.steps + 1, 128)                  # frames of the iteration for eq (avCij)
+    frames = torch.empty((args.steps + 1) * n3, dtype=torch.float32, device="cuda")
     step = [0]
-    blk = max(1, args.block // 10)
 
-    def call(_):
-        ctx.step_replicas(x, v, cvs, blk, step0=step[0])
+    def block_call(b):
+        # one frame interval for every replica: its start and end configurations are recorded
+        ctx.step_replicas(x, v, cvs, blk, step0=step[0], record_every=blk, frames=frames[b * n3:(b + 2) * n3])
         step[0] += blk
 
+    _, overlap = ctx.autotune(x, v, cvs, 10)                # on copies of the state, before timing
     for _ in range(args.warmup):
-        call(0)
+        block_call(0)
     ctx.sync()
-    n_calls = max(3, args.steps // 4)
-    wall, per_ms = timed_calls(torch, call, n_calls)
+    ctx.time_passes(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for b in range(args.steps):
+        block_call(b)
+    # the iteration ends with eq (avCij) over its recorded frames (blocks until done)
+    torch.cuda.synchronize()                             # (only to split the time between the two parts)
+    t_upd = time.perf_counter()
+    ctx.update_reference_from_paths(0, frames[(args.steps + 1 - nrec) * n3:], R, nrec, succ)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    pass_ms, timed = ctx.pass_times()
+    ctx.time_passes(False)
     ctx.sync()
-    value = R * blk * n_calls / wall
-    out = base_line(args, value, "replica-steps/s", wall, n_calls, {
-        "workload": f"chain6000_serpin_shaped: {R} replicas x {n} particles, SCPS bias on a stack of {K} "
-                    f"frame maps x {con} contact pairs, LJ + Debye-Hueckel, BAOAB dt=2 fs, {blk} Langevin "
-                    f"steps per benchmark step",
-        "replicas": R, "particles": n, "frames": K, "block": blk})
+    value = R * blk * args.steps / wall
+    out = base_line(args, value, "replica-steps/s", wall, args.steps, {
+        "workload": f"chain6000_serpin_shaped SCPS iteration: {R} replicas x {n} particles, SCPS bias on a stack "
+                    f"of {K} frame maps x {con} contact pairs, LJ + Debye-Hueckel, BAOAB dt=2 fs; one benchmark "
+                    f"step = {blk} Langevin steps of every replica with its frame recorded; the timed region "
+                    f"ends with eq (avCij) over the {nrec} recorded frames (once per iteration)",
+        "replicas": R, "particles": n, "frames": K, "block": blk,
+        "iteration_steps": blk * args.steps,
+        "launch": "per step: distance pass, ratchets, bias pass, update; nonbonded pass " +
+                  ("beside the distance pass on a second stream" if overlap else "after the bias pass") +
+                  " (autotuned)"})
     out["contact_pair_evals_per_s"] = value * con
-    per_step = flops_scps_contact(K) * con + FLOPS_NONBONDED * nb - FLOPS_GEOMETRY * both
-    # the step streams the float32 frame stack twice (distances, then the bias with
-    # its effective references) for each group of up to 32 replicas: that is its bound
+    out["eq_avCij_ms"] = 1e3 * (t1 - t_upd)
+    out["parity"] = parity
+    # the two passes of a step each stream the float32 frame stack once per
+    # group of up to 32 replicas: the bound of the step
     groups = (R + 31) // 32
-    stack_bytes = 2 * groups * K * con * 4
-    out["roofline"] = roofline_hbm(blk * stack_bytes, per_ms,
-                                   "scps_step_replicas (pass 1, ratchets, pass 2, update): frame stack read twice")
-    out["roofline_alu"] = roofline(R * blk * per_step, per_ms,
-                                   "the same calls against the FP32 peak (MFMA contraction flops included)")
-    # the same steps with the effective references written to device memory
-    # and read back by a separate pair pass, for comparison
-    two = scps.Context.from_workload(w, params=p, exec_mode=2)
-    two.set_reference_map(0, native_xyz=sy.native)
-    two.update_reference_from_paths(0, frames, R, K, succ)
-    x2, v2, cv2 = x.clone(), v.clone(), cvs.clone()
-
-    def call2(_):
-        two.step_replicas(x2, v2, cv2, blk, step0=step[0])
-        step[0] += blk
-
-    call2(0)
-    two.sync()
-    n2 = max(2, n_calls // 2)
-    wall2, _ = timed_calls(torch, call2, n2)
-    two.sync()
-    two.close()
-    rate2 = R * blk * n2 / wall2
-    out["two_pass"] = {"value": rate2, "unit": "replica-steps/s",
-                       "form": "effective references written to device memory, then a pair pass over every "
-                               "tile pair (the library's other SCPS form)", "steps": n2 * blk}
-    out["speedup_vs_two_pass"] = value / rate2
-    avg_u = sum(per_u) / len(per_u) / 1e3
-    work_u = R * K * con
-    out["update_reference"] = {
-        "value": work_u / avg_u, "unit": "path-frame contact pairs/s", "avg_call_ms": 1e3 * avg_u,
-        "paths": R, "frames": K,
-        "roofline": {"bound": "alu", "achieved": work_u * FLOPS_MAP / avg_u / 1e12, "peak": PEAK_FP64 / 1e12,
-                     "unit": "TFLOP/s", "frac": work_u * FLOPS_MAP / avg_u / PEAK_FP64,
-                     "kernel": "k_update_reference"}}
+    stack_bytes = groups * K * con * 4
+    per = {k: pass_ms[k] / max(timed, 1) for k in ("distance", "bias")}
+    dom = max(per, key=per.get)
+    names = {"distance": "k_scps_dist (distances to every frame)",
+             "bias": "k_scps_bias (effective references and bias forces)"}
+    traffic = measured_scps_traffic()
+    out["roofline"] = roofline_hbm(stack_bytes, [per[dom]] * 1, names[dom],
+                                   traffic.get(dom) if traffic else None)
+    out["roofline"]["launches_timed"] = timed
+    other = "bias" if dom == "distance" else "distance"
+    out["roofline_other_pass"] = roofline_hbm(stack_bytes, [per[other]], names[other],
+                                              traffic.get(other) if traffic else None)
+    step_ms = 1e3 * (t_upd - t0) / (args.steps * blk)
+    per_step = flops_scps_contact(K) * con + FLOPS_NONBONDED * nb - FLOPS_GEOMETRY * both
+    out["step_ms"] = step_ms
+    out["roofline_alu"] = roofline(R * per_step, [step_ms], "the whole SCPS step against the FP32 peak "
+                                                           "(MFMA contraction flops included)")
+    out["roofline_step_hbm"] = roofline_hbm(2 * stack_bytes, [step_ms], "the whole SCPS step: stack read twice")
     ctx.close()
+    if args.no_plain:
+        out["cpu_baseline"] = scps6000_cpu(w, p, ostack, threads) if not args.no_cpu else None
+        return out
+    # the plain form: one replica per context and per call, a host loop over replicas
+    plain = scps.Context.from_workload(w, params=p, replica_system=[0])
+    plain.set_reference_map(0, native_xyz=sy.native)
+    plain.update_reference_from_paths(0, frames0, R, K, succ)          # the same stack as the batched run
+    reps = list(range(min(R, args.plain_replicas)))
+    st = [(x0[3 * n * r:3 * n * (r + 1)].clone(), v0[3 * n * r:3 * n * (r + 1)].clone(),
+           torch.as_tensor(w.initial_cvstate()[:1], device="cuda")) for r in reps]
+    for xr, vr, cr in st:
+        plain.step_replicas(xr, vr, cr, 1)
+    plain.sync()
+    n_plain = 2
+    tp = time.perf_counter()
+    for m in range(n_plain):
+        for xr, vr, cr in st:
+            plain.step_replicas(xr, vr, cr, 1, step0=1 + m)
+    plain.sync()
+    rate_plain = len(reps) * n_plain / (time.perf_counter() - tp)
+    plain.close()
+    out["plain"] = {"value": rate_plain, "unit": "replica-steps/s",
+                    "form": f"one replica per context and call, host loop ({len(reps)} replicas x {n_plain} steps)"}
+    out["speedup_vs_plain"] = value / rate_plain
     if not args.no_cpu:
-        import oracle as O
-        osys = O.System.from_inputs(sy, p)
-        rng = np.random.default_rng(3)
-        # a stack of K shifted native maps: the oracle's cost does not depend on the values
-        osys.stack = np.ascontiguousarray(np.clip(osys.native[None, :] + rng.normal(0, 0.02, size=(K, 1)), 0, 1))
-        osys.K = K
-        xs = sy.start.ravel().astype(np.float64)
+        out["cpu_baseline"] = scps6000_cpu(w, p, ostack, threads)
+    return out
+
+
+def scps6000_cpu(w, p, stack, threads):
+    """The oracle on the same chain and stack size: one SCPS step of one
+    replica on one thread, and one step of `threads` replicas side by side."""
+    import numpy as np
+    import oracle as O
+    sy = w.systems[0]
+    if stack is None:          # no parity check ran: a stack of shifted native maps (the cost is the same)
+        nat = O.contact_map(sy.native, sy.contact_idx)
+        stack = np.repeat(nat[None], SCPS_FRAMES, axis=0)
+        stack *= np.linspace(0.9, 1.0, SCPS_FRAMES)[:, None]
+    osys = O.System(sy.n, sy.contact_idx, sy.mass, sy.charge, p, native_xyz=sy.native, stack=stack)
+    res = {}
+    for m in (1, threads):
+        xs = np.concatenate([sy.start.ravel()] * m).astype(np.float64)
         vs = np.zeros_like(xs)
-        cv0 = np.zeros((1, 8))
+        cv0 = np.zeros((m, 8))
         cv0[:, 1] = cv0[:, 5] = cv0[:, 6] = np.inf
         t0 = time.perf_counter()
-        _, _, _, used = O.run_batch(p, [osys], np.zeros(1, dtype=np.int32), xs, vs, cv0, 1, 0, 1)
-        dt = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": 1 / dt, "unit": "replica-steps/s", "cores": int(used), "kind": "oracle",
-                               "sample": f"1 replica x 1 SCPS step of the same chain and stack size, FP64 "
-                                         f"({dt:.1f} s)"}
-    return out
+        _, _, _, used = O.run_batch(p, [osys], np.zeros(m, dtype=np.int32), xs, vs, cv0, 1, 0, m)
+        res[m] = (m / (time.perf_counter() - t0), int(used), time.perf_counter() - t0)
+    v_all, used, dt = res[threads]
+    v_one, _, dt1 = res[1]
+    return {"value": v_all, "unit": "replica-steps/s", "cores": used, "kind": "oracle",
+            "single_thread_value": v_one, "cpu_model": cpu_model(),
+            "sample": f"{threads} replicas x 1 SCPS step of the same chain and stack size, FP64, OpenMP over "
+                      f"replicas ({dt:.1f} s); single thread: 1 replica x 1 step ({dt1:.1f} s)"}
 
 
 # ---------------------------------------------------------------------------

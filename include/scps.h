@@ -286,6 +286,21 @@ scps_status scps_least_biased_path(scps_ctx *ctx, const double *cvstate, const u
  * previous one; nothing blocks the host.  Errors: HIP. */
 scps_status scps_set_stream(scps_ctx *ctx, void *hip_stream);
 
+/* Measurement of the SCPS step's two passes over the frame stack.  With
+ * enable != 0, every later SCPS step records HIP events on the context's
+ * stream right before and after its distance pass and its bias pass (in the
+ * two-pass form: the effective references and the pair pass together); the
+ * events are recycled in a ring of 256 steps whose oldest entry is read back,
+ * waiting for it, before reuse, so timing adds no device work and no full
+ * synchronisation.  Calling it resets the sums; enable = 0 stops recording.
+ * Errors: STATE (not an SCPS context), HIP. */
+scps_status scps_time_passes(scps_ctx *ctx, int32_t enable);
+
+/* The summed durations in ms (host float64 [2]: distance pass, bias pass) and
+ * the number of timed steps (host int64 [2]) since scps_time_passes; waits for
+ * the events still pending.  Errors: INVALID_ARG, HIP. */
+scps_status scps_pass_times(scps_ctx *ctx, double *ms, int64_t *launches);
+
 /* Wait for the context's stream and report replicas flagged non-finite:
  * *n_bad receives their count and, if bad_replicas is not NULL, up to R ids
  * (host int32 [R]).  Returns NONFINITE if any replica was flagged (and
@@ -299,11 +314,15 @@ scps_status scps_sync(scps_ctx *ctx, int32_t *bad_replicas, int32_t *n_bad);
  * wavefront, for chains of at most 256 particles), and the
  * per-step path -- for n_steps steps on private device copies of
  * (x, v, cvstate), and keeps the fastest for the context's later calls
- * (exec_mode AUTO only; an SCPS context has the per-step path alone).
+ * (exec_mode AUTO only).  An SCPS context has the per-step path alone; in its
+ * default form the tuner times the nonbonded pass on the context's second
+ * stream beside the distance pass against the two passes one after the other.
  *   x, v, cvstate: device buffers as for scps_step_replicas; read only.
  *   n_steps: steps timed per configuration, >= 1.
  *   chosen: nullable host int32[2]; receives {0 persistent / 1 per-step,
- *           threads per workgroup of the persistent kernel (0 for per-step)}.
+ *           threads per workgroup of the persistent kernel, or for an SCPS
+ *           context 1 when the nonbonded pass overlaps the distance pass and
+ *           0 when it runs after the bias pass}.
  * Results of later calls differ from an untuned context's only by the order
  * of float64 additions.  Allocates three scratch buffers for the duration of
  * the call and synchronises the stream.  Errors: INVALID_ARG, OOM, HIP. */

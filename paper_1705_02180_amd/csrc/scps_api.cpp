@@ -50,6 +50,7 @@ struct SysHost {
     float *d_stack_pm = nullptr;   // [ntile_c][4096][stack_pm_width(K)]
     double *d_G = nullptr;         // [K][K] frame distances sum_p (R_j - R_k)^2
     int K = 0;
+    int K_pm = 0;                  // K the pair-major copy and G are allocated for
     double *d_R2tile = nullptr;    // [ntile_c] native map: sum of R^2 over each tile's counted pairs
     double R2total = 0.0;          // their sum (added to z for the tiles the culled path skips)
 };
@@ -64,7 +65,15 @@ struct scps_ctx {
     // distance pass (fork and join through events on the caller's stream)
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    bool overlap_nb = true;           // SCPS: nonbonded pass beside the distance pass (scps_autotune may turn it off)
     hipEvent_t ev_switch = nullptr;   // orders a new stream after the old one (scps_set_stream)
+    // scps_time_passes: HIP events around the SCPS step's two stack passes, in a ring
+    // of PASS_RING slots (4 events each) whose oldest slot is read back before reuse
+    static constexpr int PASS_RING = 256;
+    bool timing = false;
+    std::vector<hipEvent_t> pass_ev;  // [PASS_RING][4]: distance start, end, bias start, end
+    int64_t pass_recorded = 0, pass_read = 0;
+    double pass_ms[2] = {0.0, 0.0};
     int R = 0;
     std::vector<SysHost> sys;
     std::vector<int> rep_sys;
@@ -86,6 +95,8 @@ struct scps_ctx {
     double *d_zpart = nullptr;                       // z partial of every tile item
     int *d_first_all = nullptr, *d_first_con = nullptr;   // [R+1] item ranges per replica
     double *d_X = nullptr, *d_Q = nullptr, *d_csum = nullptr;   // SCPS: sum u R_k, sum u^2, sum c_k (u = C - R_j)
+    int *d_succ = nullptr;        // update_reference_from_paths: the successful paths' indices
+    int succ_cap = 0;
     int *d_jref = nullptr;        // SCPS: reference frame j of each replica's distance expansion
     int *d_jref_eval = nullptr;   // the same for the tube evaluation calls
     bool jref_init = true;        // a stack changed: pick every replica's reference frame before stepping
@@ -626,12 +637,16 @@ scps_status init_impl(const scps_params *params, const scps_topology *topo, int3
 // rebuilt whenever the stack changes; every replica's reference frame is
 // picked again before the next SCPS step.
 scps_status make_pairmajor(scps_ctx *c, SysHost &h) {
-    dfree(c, h.d_stack_pm);
-    dfree(c, h.d_G);
-    h.d_stack_pm = nullptr;
-    h.d_G = nullptr;
-    HIP_TRY(c, dalloc(c, &h.d_stack_pm, (size_t)stack_pm_width(h.K) * h.ntile_c * 4096));
-    HIP_TRY(c, dalloc(c, &h.d_G, (size_t)h.K * h.K));
+    if (h.K_pm != h.K) {   // multi-GB buffers: allocated again only when the frame count changes
+        dfree(c, h.d_stack_pm);
+        dfree(c, h.d_G);
+        h.d_stack_pm = nullptr;
+        h.d_G = nullptr;
+        h.K_pm = 0;
+        HIP_TRY(c, dalloc(c, &h.d_stack_pm, (size_t)stack_pm_width(h.K) * h.ntile_c * 4096));
+        HIP_TRY(c, dalloc(c, &h.d_G, (size_t)h.K * h.K));
+        h.K_pm = h.K;
+    }
     HIP_TRY(c, hipMemsetAsync(h.d_G, 0, (size_t)h.K * h.K * sizeof(double), c->stream));
     HIP_TRY(c, launch_stack_pairmajor(h.nc, h.ncb, h.K, h.d_stack, h.d_stack_pm, c->stream));
     HIP_TRY(c, launch_stack_gram(h.nc, h.ncb, h.K, c->prm.min_seq_sep, h.d_perm, h.d_stack, h.d_G, c->stream));
@@ -722,6 +737,32 @@ scps_status set_ref_impl(scps_ctx *c, int32_t s, int32_t n_maps, const double *m
     return upload_sysdesc(c);
 }
 
+// Read back the oldest recorded slot of the pass-timing ring (waits for it).
+scps_status read_pass_slot(scps_ctx *c) {
+    const int slot = (int)(c->pass_read % scps_ctx::PASS_RING);
+    hipEvent_t *e = &c->pass_ev[4 * slot];
+    HIP_TRY(c, hipEventSynchronize(e[3]));
+    float a = 0.f, b = 0.f;
+    HIP_TRY(c, hipEventElapsedTime(&a, e[0], e[1]));
+    HIP_TRY(c, hipEventElapsedTime(&b, e[2], e[3]));
+    c->pass_ms[0] += a;
+    c->pass_ms[1] += b;
+    ++c->pass_read;
+    return SCPS_OK;
+}
+
+// The events of the current step's slot (recycling the oldest one when the
+// ring is full), or nullptr when pass timing is off.
+hipEvent_t *pass_slot(scps_ctx *c, scps_status *st) {
+    *st = SCPS_OK;
+    if (!c->timing) return nullptr;
+    if (c->pass_recorded - c->pass_read == scps_ctx::PASS_RING) {
+        *st = read_pass_slot(c);
+        if (*st != SCPS_OK) return nullptr;
+    }
+    return &c->pass_ev[4 * (int)(c->pass_recorded % scps_ctx::PASS_RING)];
+}
+
 // The largest frame stack among the systems the replicas run (SCPS passes).
 int max_stack_frames(const scps_ctx *c) {
     int k = 1;
@@ -792,7 +833,8 @@ scps_status step_impl(scps_ctx *c, float *x, float *v, double *cv, int64_t n_ste
                                             c->stream));
                 c->jref_init = false;
             }
-            if (c->side) {
+            const bool overlap = c->side && c->overlap_nb;
+            if (overlap) {
                 // nonbonded forces (acc components 0..2) need only the positions:
                 // they overlap the bandwidth-bound distance pass
                 HIP_TRY(c, hipEventRecord(c->ev_fork, c->stream));
@@ -801,17 +843,24 @@ scps_status step_impl(scps_ctx *c, float *x, float *v, double *cv, int64_t n_ste
                                         c->d_xs, c->d_acc, c->d_zpart, nullptr, nullptr, c->side));
                 HIP_TRY(c, hipEventRecord(c->ev_join, c->side));
             }
+            scps_status tst;
+            hipEvent_t *tev = pass_slot(c, &tst);
+            if (tst != SCPS_OK) return tst;
+            if (tev) HIP_TRY(c, hipEventRecord(tev[0], c->stream));
             HIP_TRY(c, launch_scps_dist(c->kp, c->d_sysd, c->d_reps, c->d_groups, c->d_sitems, c->n_sitems,
                                         max_stack_frames(c), c->d_jref, c->d_xs, c->d_X, c->d_Q, c->kmax, -1,
                                         c->stream));
+            if (tev) HIP_TRY(c, hipEventRecord(tev[1], c->stream));
             HIP_TRY(c, launch_finalize_scps(c->kp, c->d_sysd, c->d_reps, c->R, c->kmax, c->d_jref, c->d_X, c->d_Q,
                                             cv, c->d_coef, c->d_csum, c->stream));
+            if (tev) HIP_TRY(c, hipEventRecord(tev[2], c->stream));
             if (c->prm.exec_mode == SCPS_EXEC_PER_STEP_ALL_TILES) {
                 // two passes: effective references to device memory, then every tile pair
                 HIP_TRY(c, launch_scps_eff(c->d_sysd, c->d_reps, c->d_groups, c->d_sitems, c->n_sitems, c->d_coef,
                                            c->kmax, c->d_E, c->stream));
                 HIP_TRY(c, launch_pairs(3, c->nbk, c->kp, c->d_sysd, c->d_reps, c->d_items_all, c->n_items_all,
                                         c->d_xs, c->d_acc, c->d_zpart, c->d_E, c->d_csum, c->stream));
+                if (tev) HIP_TRY(c, hipEventRecord(tev[3], c->stream));
             } else {
                 // the effective references and the bias in one pass over the contact tiles;
                 // the nonbonded forces and bonds (mode 4, every tile pair) ran on the side
@@ -819,12 +868,14 @@ scps_status step_impl(scps_ctx *c, float *x, float *v, double *cv, int64_t n_ste
                 HIP_TRY(c, launch_scps_bias(c->kp, c->d_sysd, c->d_reps, c->d_groups, c->d_sitems, c->n_sitems,
                                             max_stack_frames(c), c->d_xs, c->d_coef, c->d_csum, c->kmax, c->d_acc,
                                             c->stream));
-                if (c->side)
+                if (tev) HIP_TRY(c, hipEventRecord(tev[3], c->stream));
+                if (overlap)
                     HIP_TRY(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
                 else
                     HIP_TRY(c, launch_pairs(4, c->nbk, c->kp, c->d_sysd, c->d_reps, c->d_items_all, c->n_items_all,
                                             c->d_xs, c->d_acc, c->d_zpart, nullptr, nullptr, c->stream));
             }
+            if (tev) ++c->pass_recorded;
             HIP_TRY(c, launch_integrate(c->kp, c->d_sysd, c->d_reps, c->R, c->n_pad_max, c->d_xs, c->d_vs, c->d_acc,
                                         c->d_negone, cv, step0 + (uint64_t)m, c->d_flags, c->stream));
         }
@@ -860,11 +911,19 @@ scps_status update_ref_impl(scps_ctx *c, int32_t s, const float *frames, int32_t
         if (success[q]) succ.push_back(q);
     if (succ.empty()) return fail(SCPS_ERR_NO_SUCCESS, "no successful path; the frame stack is unchanged");
     const int64_t P = (int64_t)h.nc * (h.nc - 1) / 2;
-    int *d_succ = nullptr;
-    HIP_TRY(c, dalloc(c, &d_succ, succ.size()));
-    HIP_TRY(c, hipMemcpy(d_succ, succ.data(), succ.size() * sizeof(int), hipMemcpyHostToDevice));
-    float *d_new = nullptr;
-    HIP_TRY(c, dalloc(c, &d_new, (size_t)n_frames * h.ntile_c * 4096));
+    if (c->succ_cap < (int)succ.size()) {
+        dfree(c, c->d_succ);
+        c->d_succ = nullptr;
+        c->succ_cap = 0;
+        HIP_TRY(c, dalloc(c, &c->d_succ, succ.size()));
+        c->succ_cap = (int)succ.size();
+    }
+    int *d_succ = c->d_succ;
+    HIP_TRY(c, hipMemcpyAsync(d_succ, succ.data(), succ.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    // the new stack replaces the old one in place when it has as many frames
+    // (no kernel reads the old stack while eq (avCij) runs)
+    float *d_new = (h.d_stack && h.K == n_frames) ? h.d_stack : nullptr;
+    if (!d_new) HIP_TRY(c, dalloc(c, &d_new, (size_t)n_frames * h.ntile_c * 4096));
     double *d_packed = nullptr;
     if (maps_out) HIP_TRY(c, dalloc(c, &d_packed, (size_t)std::max<int64_t>(P * n_frames, 1)));
     HIP_TRY(c, launch_update_reference(h.n, h.n_pad, h.nc, h.ncb, h.d_perm, frames, n_paths, n_frames, d_succ,
@@ -874,8 +933,7 @@ scps_status update_ref_impl(scps_ctx *c, int32_t s, const float *frames, int32_t
     if (maps_out)
         HIP_TRY(c, hipMemcpy(maps_out, d_packed, (size_t)P * n_frames * sizeof(double), hipMemcpyDeviceToHost));
     dfree(c, d_packed);
-    dfree(c, d_succ);
-    dfree(c, h.d_stack);
+    if (d_new != h.d_stack) dfree(c, h.d_stack);
     h.d_stack = d_new;
     h.K = n_frames;
     scps_status st = make_pairmajor(c, h);
@@ -959,16 +1017,21 @@ scps_status autotune_impl(scps_ctx *c, const float *x, const float *v, const dou
     for (int r = 0; r < c->R; ++r)
         if (!c->sys[c->rep_sys[r]].has_native)
             return fail(SCPS_ERR_STATE, "a system has no native map (scps_set_reference_map)");
-    // candidates: {path, workgroup}
-    std::vector<std::pair<int, int>> cand;
+    // candidates: {path, workgroup of the persistent kernel, nonbonded pass beside the distance pass (SCPS)}
+    struct Cand {
+        int path, wg;
+        bool overlap;
+    };
+    std::vector<Cand> cand;
     const bool scps = c->prm.bias_mode == SCPS_BIAS_SCPS;
     if (!scps && c->prm.exec_mode == SCPS_EXEC_AUTO) {
         // one wavefront per replica can win for chains of a few blocks (several replicas then share a CU)
-        if (c->n_pad_max <= 4 * TILE) cand.push_back({0, 64});
+        if (c->n_pad_max <= 4 * TILE) cand.push_back({0, 64, false});
         for (int wg : {256, 512, 1024})
-            if (c->n_pad_max <= persistent_max_npad(wg)) cand.push_back({0, wg});
+            if (c->n_pad_max <= persistent_max_npad(wg)) cand.push_back({0, wg, false});
     }
-    cand.push_back({1, 0});
+    if (scps && c->side) cand.push_back({1, 0, true});
+    cand.push_back({1, 0, false});
     const size_t nx = 3 * (size_t)c->sumN;
     float *tx = nullptr, *tv = nullptr;
     double *tcv = nullptr;
@@ -988,12 +1051,14 @@ scps_status autotune_impl(scps_ctx *c, const float *x, const float *v, const dou
     HIP_TRY(c, hipEventCreate(&e0));
     HIP_TRY(c, hipEventCreate(&e1));
     const int saved_tuned = c->tuned, saved_wg = c->wg;
+    const bool saved_overlap = c->overlap_nb;
     float best = 0.f;
     int best_i = -1;
     scps_status st = SCPS_OK;
     for (size_t i = 0; i < cand.size() && st == SCPS_OK; ++i) {
-        c->tuned = cand[i].first;
-        if (cand[i].first == 0) c->wg = cand[i].second;
+        c->tuned = cand[i].path;
+        if (cand[i].path == 0) c->wg = cand[i].wg;
+        if (scps) c->overlap_nb = cand[i].overlap;
         // one untimed call (first-launch costs), then the timed one, each from the caller's state
         float ms = 0.f;
         for (int rep = 0; rep < 2 && st == SCPS_OK; ++rep) {
@@ -1027,14 +1092,16 @@ scps_status autotune_impl(scps_ctx *c, const float *x, const float *v, const dou
     if (st != SCPS_OK) {
         c->tuned = saved_tuned;
         c->wg = saved_wg;
+        c->overlap_nb = saved_overlap;
         return st;
     }
-    c->tuned = cand[best_i].first;
-    if (c->tuned == 0) c->wg = cand[best_i].second;
+    c->tuned = cand[best_i].path;
+    if (c->tuned == 0) c->wg = cand[best_i].wg;
     else c->wg = saved_wg;
+    c->overlap_nb = scps ? cand[best_i].overlap : saved_overlap;
     if (chosen) {
         chosen[0] = c->tuned;
-        chosen[1] = c->tuned == 0 ? c->wg : 0;
+        chosen[1] = c->tuned == 0 ? c->wg : (scps && c->overlap_nb ? 1 : 0);
     }
     return SCPS_OK;
 }
@@ -1163,6 +1230,38 @@ scps_status scps_set_stream(scps_ctx *ctx, void *hip_stream) {
     HIP_TRY(ctx, hipEventRecord(ctx->ev_switch, ctx->stream));
     HIP_TRY(ctx, hipStreamWaitEvent(next, ctx->ev_switch, 0));
     ctx->stream = next;
+    return SCPS_OK;
+}
+
+scps_status scps_time_passes(scps_ctx *ctx, int32_t enable) {
+    scps_status st;
+    if (!usable(ctx, &st)) return st;
+    if (ctx->prm.bias_mode != SCPS_BIAS_SCPS) return fail(SCPS_ERR_STATE, "pass timing needs an SCPS context");
+    if (ctx->pass_ev.empty()) {
+        ctx->pass_ev.assign(4 * scps_ctx::PASS_RING, nullptr);
+        for (auto &e : ctx->pass_ev) HIP_TRY(ctx, hipEventCreate(&e));
+    }
+    while (ctx->pass_read < ctx->pass_recorded) {   // what an earlier period recorded
+        st = read_pass_slot(ctx);
+        if (st != SCPS_OK) return st;
+    }
+    ctx->timing = enable != 0;
+    ctx->pass_ms[0] = ctx->pass_ms[1] = 0.0;
+    ctx->pass_recorded = ctx->pass_read = 0;
+    return SCPS_OK;
+}
+
+scps_status scps_pass_times(scps_ctx *ctx, double *ms, int64_t *launches) {
+    scps_status st;
+    if (!usable(ctx, &st)) return st;
+    if (!ms || !launches) return fail(SCPS_ERR_INVALID_ARG, "ms and launches must not be NULL");
+    while (ctx->pass_read < ctx->pass_recorded) {
+        st = read_pass_slot(ctx);
+        if (st != SCPS_OK) return st;
+    }
+    ms[0] = ctx->pass_ms[0];
+    ms[1] = ctx->pass_ms[1];
+    launches[0] = launches[1] = ctx->pass_read;
     return SCPS_OK;
 }
 
@@ -1319,6 +1418,8 @@ void scps_destroy(scps_ctx *ctx) {
     if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
     if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
     if (ctx->ev_switch) (void)hipEventDestroy(ctx->ev_switch);
+    for (hipEvent_t e : ctx->pass_ev)
+        if (e) (void)hipEventDestroy(e);
     for (void *p : ctx->owned) (void)hipFree(p);
     delete ctx;
 }

@@ -470,11 +470,13 @@ __device__ __forceinline__ float contact_operand(const KParams &P, const float4 
 // i = w, w+4, ... of block I and, per row, 32 MFMA steps of 2 pairs
 // (i, 2m + (l >> 5)); lane l evaluates u of that pair for replica l & 31 (A
 // operand of 32x32x2 float32 MFMAs) with particle i's position held in a
-// register, particle j's read from the block-J positions in LDS and R_j from
-// the pair's frames, and loads frames 2 (l & 31) and 2 (l & 31) + 1 of the
-// pair with one 8-byte load SCPS_DIST_AHEAD steps ahead of their use (the
-// reference value, from the same run of the pair's frames, SCPS_DIST_REF_AHEAD
-// steps ahead); frame block h holds frames 2j + h,
+// register, particle j's read from the block-J positions in LDS and R_j of
+// the pair, and loads frames 2 (l & 31) and 2 (l & 31) + 1 of the pair with
+// one 8-byte load SCPS_DIST_AHEAD steps ahead of their use.  R_j is one of
+// those loaded values (lane (j >> 1) + 32 (l >> 5), component j & 1), fetched
+// across lanes with ds_bpermute; a stack of more than 64 frames (REFLOAD)
+// loads it from the pair's frames instead, SCPS_DIST_REF_AHEAD steps ahead,
+// since frame j need not lie in the current frame block.  Frame block h holds frames 2j + h,
 // so component h of that load is the lane's B operand of block h.  A diagonal
 // tile counts the pairs j > i.  The float32 accumulators hold one row (64
 // pairs per element) and are added after every row into the workgroup's
@@ -483,9 +485,9 @@ __device__ __forceinline__ float contact_operand(const KParams &P, const float4 
 // a stack of more than 64 frames is taken in frame blocks fb of 64, each a
 // pass of its own over the tile (the contact values are recomputed; Q is
 // summed in block 0 only).
-template <bool MASK>
+template <bool MASK, bool REFLOAD>
 __device__ __forceinline__ void scps_dist_tile(const KParams &P, const SysDesc &S, const int nrep,
-                                               const ScpsItem &it, const int fb, const float4 (*posj)[32],
+                                               const ScpsItem &it, const int fb_in, const float4 (*posj)[32],
                                                const int *orgj, const float4 *__restrict__ xs,
                                                const RepDesc *__restrict__ reps, const int myrep, const int jr,
                                                const int lane, const int wave, double *xl, double &q) {
@@ -494,6 +496,9 @@ __device__ __forceinline__ void scps_dist_tile(const KParams &P, const SysDesc &
     const int K4 = stack_pm_width(S.K);
     const int rs = lane & 31, pq = lane >> 5;
     const bool rep = rs < nrep;
+    // a stack of at most 64 frames has the one frame block 0: known at compile
+    // time, so the step loop below has no branch
+    const int fb = REFLOAD ? fb_in : 0;
     const bool bload = 64 * fb + 2 * rs < K4;
     const bool sum_q = fb == 0;
     // global (not flat) loads from a uniform tile base with 32-bit lane offsets:
@@ -521,11 +526,23 @@ __device__ __forceinline__ void scps_dist_tile(const KParams &P, const SysDesc &
         return Rf[(s_ * 64 + ic) * K4 + jr];
     };
     v2 ring[D];
-    float rring[DR];
+    float rring[REFLOAD ? DR : 1];
 #pragma unroll
     for (int u = 0; u < D; ++u) ring[u] = bop(wave, u);
+    if constexpr (REFLOAD) {
 #pragma unroll
-    for (int u = 0; u < DR; ++u) rring[u] = rop(wave, u);
+        for (int u = 0; u < DR; ++u) rring[u] = rop(wave, u);
+    }
+    const int ref_lane = ((jr >> 1) + 32 * pq) << 2;   // ds_bpermute byte address of the lane holding R_j
+    // R_j of a step from the B operands of that step (one step ahead of its use,
+    // so the cross-lane move is off the contact value -> MFMA chain)
+    auto ref_of = [&](const v2 &bb) {
+        const float rx = __int_as_float(__builtin_amdgcn_ds_bpermute(ref_lane, __float_as_int(bb.x)));
+        const float ry = __int_as_float(__builtin_amdgcn_ds_bpermute(ref_lane, __float_as_int(bb.y)));
+        return (jr & 1) ? ry : rx;
+    };
+    float rj_next = 0.f;
+    if constexpr (!REFLOAD) rj_next = ref_of(ring[0]);
 #pragma unroll 1
     for (int i = wave; i < 64; i += 4) {
         const float4 pi = rep ? xr[i] : make_float4(0.f, 0.f, 0.f, 0.f);
@@ -542,11 +559,17 @@ __device__ __forceinline__ void scps_dist_tile(const KParams &P, const SysDesc &
             for (int u = 0; u < D; ++u) {
                 const int m = D * mg + u;
                 const v2 b = ring[u];
-                const float rj = rring[u % DR];
+                float rj;
+                if constexpr (REFLOAD) {
+                    rj = rring[u % DR];
+                    const int rm = m + DR < 32 ? m + DR : m + DR - 32, ri = m + DR < 32 ? i : i + 4;
+                    rring[u % DR] = rop(ri, rm);
+                } else {
+                    rj = rj_next;
+                    rj_next = ref_of(ring[(u + 1) % D]);   // holds the next step's B operands
+                }
                 const int nm = m + D < 32 ? m + D : m + D - 32, ni = m + D < 32 ? i : i + 4;
                 ring[u] = bop(ni, nm);
-                const int rm = m + DR < 32 ? m + DR : m + DR - 32, ri = m + DR < 32 ? i : i + 4;
-                rring[u % DR] = rop(ri, rm);
                 const int jl = 2 * m + pq;
                 bool ok = !diag | (jl > i);
                 if constexpr (MASK) {
@@ -572,6 +595,8 @@ __device__ __forceinline__ void scps_dist_tile(const KParams &P, const SysDesc &
 #endif
 // Work unit t covers item t mod n_items in frame block t / n_items (nfb
 // blocks of 64 frames); the sums are flushed when (group, frame block) changes.
+// BIGK: stacks of more than 64 frames (a kernel of its own).
+template <bool BIGK>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SCPS_DIST_WPE, SCPS_DIST_WPE))) void k_scps_dist(
     const KParams P, const SysDesc *__restrict__ sysd, const RepDesc *__restrict__ reps,
     const ScpsGroup *__restrict__ groups, const ScpsItem *__restrict__ items, const int n_items, const int nfb,
@@ -591,7 +616,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SCPS_DIST_W
     const int n_units = n_items * nfb;
     for (int t = blockIdx.x;; t += gridDim.x) {
         const bool more = t < n_units;
-        const int fb = more ? t / n_items : 0;
+        const int fb = (BIGK && more) ? t / n_items : 0;
         const ScpsItem it = more ? items[t - fb * n_items] : ScpsItem{-1, 0, 0, 0};
         const bool change = it.group != cur || fb != cur_fb;
         if (cur >= 0 && change) {
@@ -641,9 +666,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SCPS_DIST_W
         __syncthreads();
         const int myrep = sh_rep[lane & 31], myj = sh_jref[lane & 31];
         if (it.flags & TILE_MASK)
-            scps_dist_tile<true>(P, S, nrep, it, fb, posj, orgj, xs, reps, myrep, myj, lane, wave, xl, q);
+            scps_dist_tile<true, BIGK>(P, S, nrep, it, fb, posj, orgj, xs, reps, myrep, myj, lane, wave, xl, q);
         else
-            scps_dist_tile<false>(P, S, nrep, it, fb, posj, orgj, xs, reps, myrep, myj, lane, wave, xl, q);
+            scps_dist_tile<false, BIGK>(P, S, nrep, it, fb, posj, orgj, xs, reps, myrep, myj, lane, wave, xl, q);
     }
 }
 
@@ -1013,8 +1038,12 @@ hipError_t launch_scps_dist(const KParams &P, const SysDesc *sysd, const RepDesc
     const int nfb = (max_frames + 63) / 64;
     const int cap = 256 * SCPS_DIST_WPE;   // resident workgroups: WPE per SIMD, four waves each
     const int grid = n_items * nfb < cap ? n_items * nfb : cap;
-    hipLaunchKernelGGL(k_scps_dist, dim3(grid), dim3(256), 0, st, P, sysd, reps, groups, items, n_items, nfb, jref,
-                       xs, X, Q, kmax, stack_sys);
+    if (nfb > 1)
+        hipLaunchKernelGGL(k_scps_dist<true>, dim3(grid), dim3(256), 0, st, P, sysd, reps, groups, items, n_items,
+                           nfb, jref, xs, X, Q, kmax, stack_sys);
+    else
+        hipLaunchKernelGGL(k_scps_dist<false>, dim3(grid), dim3(256), 0, st, P, sysd, reps, groups, items, n_items,
+                           nfb, jref, xs, X, Q, kmax, stack_sys);
     return hipGetLastError();
 }
 

@@ -85,6 +85,10 @@ _lib.scps_eval_sigma.restype = C.c_int
 _lib.scps_eval_sigma.argtypes = [_vp, _i32, _vp, _vp, _vp]
 _lib.scps_path_distance.restype = C.c_int
 _lib.scps_path_distance.argtypes = [_vp, _i64, _vp, _i64, _d, _d, _d, _i32, _i32, _vp, C.POINTER(C.c_double)]
+_lib.scps_time_passes.restype = C.c_int
+_lib.scps_time_passes.argtypes = [_vp, _i32]
+_lib.scps_pass_times.restype = C.c_int
+_lib.scps_pass_times.argtypes = [_vp, _vp, _vp]
 _lib.scps_path_distance_noalloc.restype = C.c_int
 _lib.scps_path_distance_noalloc.argtypes = _lib.scps_path_distance.argtypes
 _lib.scps_funnel_steps.restype = C.c_int
@@ -101,7 +105,7 @@ _lib.scps_last_error.argtypes = []
 EXPORTS = ["scps_init_system", "scps_set_reference_map", "scps_step_replicas", "scps_eval_z_and_grad",
            "scps_ratchet_energy", "scps_update_reference_from_paths", "scps_set_stream", "scps_sync",
            "scps_autotune", "scps_least_biased_path", "scps_eval_tube", "scps_eval_sigma", "scps_path_distance",
-           "scps_path_distance_noalloc",
+           "scps_path_distance_noalloc", "scps_time_passes", "scps_pass_times",
            "scps_funnel_steps", "scps_funnel_mean_path", "scps_scale_by_replica", "scps_destroy",
            "scps_last_error"]
 
@@ -273,7 +277,9 @@ class Context:
 
     def autotune(self, x: torch.Tensor, v: Optional[torch.Tensor], cvstate: torch.Tensor, n_steps: int):
         """Time the launch configurations on copies of the state and keep the
-        fastest; returns (path, threads): path 0 persistent, 1 per-step."""
+        fastest; returns (path, threads): path 0 persistent, 1 per-step, and
+        the persistent kernel's threads per replica (an SCPS context: 1 when
+        its nonbonded pass overlaps the distance pass, else 0)."""
         px = _dev(x, torch.float32, 3 * self.sumN, "x")
         pv = _dev(v, torch.float32, 3 * self.sumN, "v")
         pc = _dev(cvstate, torch.float64, self.R * CV_STRIDE, "cvstate")
@@ -308,6 +314,17 @@ class Context:
         t = C.c_double(0.0)
         _check(_lib.scps_least_biased_path(self._ctx(), pc, ps, C.byref(idx), C.byref(t)))
         return int(idx.value), float(t.value)
+
+    def time_passes(self, enable: bool = True):
+        """Start (or stop) recording HIP events around the SCPS step's distance and bias passes."""
+        _check(_lib.scps_time_passes(self._ctx(), int(bool(enable))))
+
+    def pass_times(self):
+        """({"distance": ms, "bias": ms} summed, steps timed) since time_passes."""
+        ms = (C.c_double * 2)()
+        n = (C.c_int64 * 2)()
+        _check(_lib.scps_pass_times(self._ctx(), ms, n))
+        return {"distance": float(ms[0]), "bias": float(ms[1])}, int(n[0])
 
     def sync(self):
         bad = np.zeros(self.R, dtype=np.int32)

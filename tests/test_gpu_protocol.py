@@ -396,3 +396,86 @@ def test_calls_on_another_stream_wait_for_queued_work(S):
     assert np.array_equal(x1, x2)
     np.testing.assert_allclose(z2, z1, rtol=1e-12)
     assert np.abs(g2 - g1).max() <= 1e-6 * np.abs(g1).max()
+
+
+def test_pass_timing_changes_no_result(S):
+    """scps_time_passes only records events on the context's stream: 300 SCPS
+    steps give bit-identical positions and velocities with and without it (the
+    collective variables to the last bits of their float64 atomic sums), and
+    every step's two passes have a positive duration (more steps than the
+    event ring holds, so the ring is recycled)."""
+    import torch
+    base = dict(I._base_params(), bias_mode=1, lam=13.5, k_s=50.0, k_w=5.0)
+    n, R, K = 150, 5, 9
+    rng = np.random.default_rng(61)
+    sy = I.System(n=n, contact_idx=np.arange(n, dtype=np.int32), mass=np.full(n, 12.011 * I.AMU, np.float32),
+                  charge=rng.normal(0, 0.3, n).astype(np.float32), native=I.compact_native(n, 61),
+                  start=I.persistent_start(n, 62))
+    w = I.Workload("timing", dict(base), [sy], np.zeros(R, dtype=np.int32), 1)
+    t = np.linspace(0.0, 1.0, K)
+    fr = np.stack([((1 - tk) * sy.start + tk * sy.native + rng.normal(0, 0.5, (3, n)))[None] for tk in t])
+    fr = fr.astype(np.float32)
+    x0 = np.stack([sy.start + rng.normal(0, 0.05, (3, n)) for _ in range(R)]).astype(np.float32).ravel()
+    out = []
+    for timed in (False, True):
+        ctx = S.Context.from_workload(w, params=base)
+        ctx.set_reference_map(0, native_xyz=sy.native)
+        ctx.update_reference_from_paths(0, dev(fr.ravel()), 1, K, np.ones(1, np.uint8))
+        if timed:
+            ctx.time_passes(True)
+        x, v, cv = dev(x0), dev(np.zeros_like(x0)), dev(w.initial_cvstate(), "f64")
+        ctx.step_replicas(x, v, cv, 300, step0=5)
+        ctx.sync()
+        if timed:
+            ms, steps = ctx.pass_times()
+            print(f"  300 steps: distance pass {ms['distance'] / steps:.4f} ms, bias pass {ms['bias'] / steps:.4f} ms",
+                  flush=True)
+            assert steps == 300 and ms["distance"] > 0 and ms["bias"] > 0
+            ctx.time_passes(False)
+        out.append((host(x), host(v), host(cv)))
+        ctx.close()
+    (xa, va, ca), (xb, vb, cb) = out
+    assert np.array_equal(xa, xb) and np.array_equal(va, vb)
+    # s, w (distance sums) and T add per-workgroup partials with float64 atomics, whose
+    # order varies from run to run: the last bits of those sums, not the states, may differ
+    np.testing.assert_allclose(ca, cb, rtol=1e-12, atol=0)
+
+
+def test_scps_autotune_picks_an_order_and_keeps_results(S):
+    """scps_autotune on an SCPS context times the nonbonded pass beside the
+    distance pass against the two one after the other, on copies of the state:
+    the caller's state is untouched, and ten steps after tuning match an
+    untuned context's up to the float32 summation order of the forces."""
+    import torch
+    base = dict(I._base_params(), bias_mode=1, lam=13.5, k_s=50.0, k_w=5.0)
+    n, R, K = 200, 6, 11
+    rng = np.random.default_rng(71)
+    sy = I.System(n=n, contact_idx=np.arange(n, dtype=np.int32), mass=np.full(n, 12.011 * I.AMU, np.float32),
+                  charge=rng.normal(0, 0.3, n).astype(np.float32), native=I.compact_native(n, 71),
+                  start=I.persistent_start(n, 72))
+    w = I.Workload("tune", dict(base), [sy], np.zeros(R, dtype=np.int32), 1)
+    t = np.linspace(0.0, 1.0, K)
+    fr = np.stack([((1 - tk) * sy.start + tk * sy.native + rng.normal(0, 0.5, (3, n)))[None] for tk in t])
+    fr = fr.astype(np.float32)
+    x0 = np.stack([sy.start + rng.normal(0, 0.05, (3, n)) for _ in range(R)]).astype(np.float32).ravel()
+    out = []
+    for tune in (False, True):
+        ctx = S.Context.from_workload(w, params=base)
+        ctx.set_reference_map(0, native_xyz=sy.native)
+        ctx.update_reference_from_paths(0, dev(fr.ravel()), 1, K, np.ones(1, np.uint8))
+        x, v, cv = dev(x0), dev(np.zeros_like(x0)), dev(w.initial_cvstate(), "f64")
+        if tune:
+            path, overlap = ctx.autotune(x, v, cv, 3)
+            print(f"  SCPS autotune: path {path}, nonbonded pass beside the distance pass: {bool(overlap)}",
+                  flush=True)
+            assert path == 1 and overlap in (0, 1)
+            assert np.array_equal(host(x), x0) and np.all(host(v) == 0)
+        ctx.step_replicas(x, v, cv, 10, step0=3)
+        ctx.sync()
+        out.append((host(x), host(v), host(cv)))
+        ctx.close()
+    (xa, va, ca), (xb, vb, cb) = out
+    disp = np.abs(xa - x0).max()
+    assert disp > 0 and np.abs(xa - xb).max() <= 1e-4 * disp
+    assert np.abs(va - vb).max() <= 1e-4 * np.abs(va).max()
+    np.testing.assert_allclose(ca[:, 3:7], cb[:, 3:7], rtol=0, atol=1e-6)
