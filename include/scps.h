@@ -24,9 +24,10 @@
  *   with respect to the host unless stated otherwise.  The caller keeps
  *   device buffers alive until that work has completed (torch tensors used
  *   on the same stream satisfy this).  An SCPS context in the default form
- *   also runs part of each step on a second stream of its own, forked from
- *   and joined back to the context's stream through events within the call,
- *   so ordering with the caller's work on that stream is unchanged.
+ *   holds a second stream of its own; when scps_autotune moves the nonbonded
+ *   pass there, that part of each step is forked from and joined back to the
+ *   context's stream through events within the call, so ordering with the
+ *   caller's work on that stream is unchanged.
  * - The library cannot check the extent of a caller's buffer; the sizes
  *   stated below are the caller's contract.
  * - A context is not re-entrant: one thread, one stream at a time.
@@ -88,7 +89,7 @@ enum {
 
 enum { SCPS_INTEGRATOR_OVERDAMPED = 0, SCPS_INTEGRATOR_BAOAB = 1 };
 enum { SCPS_BIAS_RMD = 0, SCPS_BIAS_SCPS = 1 };
-enum { SCPS_EXEC_AUTO = 0, SCPS_EXEC_PER_STEP = 1, SCPS_EXEC_PER_STEP_ALL_TILES = 2 };
+enum { SCPS_EXEC_AUTO = 0, SCPS_EXEC_PER_STEP = 1, SCPS_EXEC_PER_STEP_ALL_TILES = 2, SCPS_EXEC_PER_STEP_OVERLAP = 3 };
 enum { SCPS_W_INV_LAMBDA = 0, SCPS_W_NO_INV_LAMBDA = 1 };
 
 /* Physics and bias parameters (any consistent unit system; the protein-shaped
@@ -110,7 +111,11 @@ typedef struct {
                              In SCPS mode the first two form the frame-weighted effective references on the fly,
                              inside the pass that applies the bias; SCPS_EXEC_PER_STEP_ALL_TILES writes them to
                              device memory first and reads them back in the pair pass (same results up to float
-                             rounding order; it needs R x (contact tile pairs) x 16 KiB of device memory more) */
+                             rounding order; it needs R x (contact tile pairs) x 16 KiB of device memory more).
+                             SCPS_EXEC_PER_STEP_OVERLAP (SCPS bias only): as SCPS_EXEC_PER_STEP, with the
+                             nonbonded pass on the context's second stream beside the distance pass; AUTO and
+                             PER_STEP run it after the bias pass unless scps_autotune (AUTO) finds the
+                             overlapped schedule more than 3% faster */
     int32_t nb_excl;      /* nonbonded pairs need |i-j| > nb_excl (>= 1) */
     int32_t min_seq_sep;  /* contact pairs need |i-j| > min_seq_sep; the paper's all-atom value is 35 */
     int32_t replica_base; /* replica r uses replica_base + r as its noise counter word, so a context that
@@ -313,10 +318,13 @@ scps_status scps_sync(scps_ctx *ctx, int32_t *bad_replicas, int32_t *n_bad);
  * replica where a replica's state fits in one workgroup's LDS (also 64, one
  * wavefront, for chains of at most 256 particles), and the
  * per-step path -- for n_steps steps on private device copies of
- * (x, v, cvstate), and keeps the fastest for the context's later calls
- * (exec_mode AUTO only).  An SCPS context has the per-step path alone; in its
- * default form the tuner times the nonbonded pass on the context's second
- * stream beside the distance pass against the two passes one after the other.
+ * (x, v, cvstate), in three rounds taken in turns after one untimed step
+ * each, and keeps the one with the fastest run for the context's later calls
+ * (exec_mode AUTO only).  An SCPS context has the per-step path alone; with
+ * exec_mode AUTO the tuner times the two passes one after the other (the
+ * default) against the nonbonded pass on the context's second stream beside
+ * the distance pass, which it takes only when that is more than 3% faster;
+ * other exec modes keep their schedule.
  *   x, v, cvstate: device buffers as for scps_step_replicas; read only.
  *   n_steps: steps timed per configuration, >= 1.
  *   chosen: nullable host int32[2]; receives {0 persistent / 1 per-step,

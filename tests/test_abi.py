@@ -57,6 +57,10 @@ def test_host_validation_rejects_bad_arguments(lib):
         with pytest.raises(scps.ScpsError) as e:
             scps.Context.from_workload(w, params=p)
         assert e.value.status == -1, b
+    for mode in (4, 3):                   # no such mode; the overlapped schedule without SCPS bias
+        with pytest.raises(scps.ScpsError) as e:
+            scps.Context.from_workload(w, exec_mode=mode)
+        assert e.value.status == -1, mode
     with pytest.raises(scps.ScpsError) as e:
         scps.Context(w.params, [20], [[3, 2]], [w.systems[0].mass], [w.systems[0].charge], [0])
     assert e.value.status == -1

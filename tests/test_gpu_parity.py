@@ -420,10 +420,11 @@ SCPS_CASES = [
     ("seqsep35_200_K21", [200], ["all"], 21, 5, False, {"min_seq_sep": 35}),
     ("one_block_60_K5", [60], ["all"], 5, 3, False, {}),
 ]
-SCPS_FORMS = [(0, 0), (2, 0), (0, 1)]
+SCPS_FORMS = [(0, 0), (2, 0), (0, 1), (3, 0)]
 
 
-@pytest.mark.parametrize("exec_mode,w_form", SCPS_FORMS, ids=["fused", "two_pass", "fused_w_without_1_over_lambda"])
+@pytest.mark.parametrize("exec_mode,w_form", SCPS_FORMS,
+                         ids=["fused", "two_pass", "fused_w_without_1_over_lambda", "fused_nonbonded_beside"])
 @pytest.mark.parametrize("name,sizes,kinds,K,R,bias_only,extra", SCPS_CASES, ids=[c[0] for c in SCPS_CASES])
 def test_scps_step_forces_match_oracle(S, name, sizes, kinds, K, R, bias_only, extra, exec_mode, w_form):
     """One SCPS step (distances to all K frames, tube variables and ratchets,
@@ -513,11 +514,13 @@ def test_scps_step_forces_match_oracle(S, name, sizes, kinds, K, R, bias_only, e
         ctx.close()
 
 
-def test_scps_forms_agree_over_steps(S):
-    """The two forms of the SCPS bias (effective references formed inside the
-    bias pass, and written to device memory first) step the same replicas
-    alike over ten noisy BAOAB steps: they differ only in the float32
-    summation order of the force partials.  300 beads with every third in
+@pytest.mark.parametrize("other_mode", [2, 3], ids=["two_pass", "nonbonded_beside"])
+def test_scps_forms_agree_over_steps(S, other_mode):
+    """The forms of the SCPS step (effective references formed inside the
+    bias pass, written to device memory first, or formed inside the bias pass
+    with the nonbonded pass on a second stream beside the distance pass) step
+    the same replicas alike over ten noisy BAOAB steps: they differ only in
+    the float32 summation order of the force partials.  300 beads with every third in
     the contact set (tiles without contacts, blocks straddling the contact
     set), 36 replicas (two replica groups), 17 frames."""
     import torch
@@ -534,7 +537,7 @@ def test_scps_forms_agree_over_steps(S):
     cv0 = np.zeros((R, 8))
     cv0[:, 5:7] = np.inf
     out = []
-    for mode in (0, 2):
+    for mode in (0, other_mode):
         ctx = context(S, w, params=base, exec_mode=mode)
         ctx.update_reference_from_paths(0, dev(fr.ravel()), n_paths, K, np.ones(n_paths, dtype=np.uint8))
         x, v, cv = dev(x0), dev(np.zeros_like(x0)), dev(cv0, "f64")
@@ -553,12 +556,13 @@ def test_scps_forms_agree_over_steps(S):
     np.testing.assert_allclose(cva[:, 7], cvb[:, 7], rtol=1e-4, atol=1e-12 * cva[:, 7].max())
 
 
-def test_scps_step_on_a_caller_stream(S):
-    """The default SCPS form runs its nonbonded pass on a second stream of its
-    own, forked from and joined back to the caller's stream.  Stepping on a
-    non-default torch stream gives what the default stream gives (up to the
-    float32 summation order of the force partials), and the caller's next
-    work on that stream sees the updated state."""
+@pytest.mark.parametrize("exec_mode", [0, 3], ids=["one_stream", "nonbonded_beside"])
+def test_scps_step_on_a_caller_stream(S, exec_mode):
+    """Stepping an SCPS context on a non-default torch stream gives what the
+    default stream gives (up to the float32 summation order of the force
+    partials), and the caller's next work on that stream sees the updated
+    state -- also with the nonbonded pass on the context's second stream,
+    forked from and joined back to the caller's stream."""
     import torch
     base = dict(I._base_params(), bias_mode=1, lam=13.5, k_s=50.0, k_w=5.0)
     n, R, K, n_paths = 150, 6, 9, 3
@@ -572,7 +576,7 @@ def test_scps_step_on_a_caller_stream(S):
     for use_side in (False, True):
         side = torch.cuda.Stream() if use_side else torch.cuda.current_stream()
         with torch.cuda.stream(side):
-            ctx = context(S, w, params=base)
+            ctx = context(S, w, params=base, exec_mode=exec_mode)
             ctx.update_reference_from_paths(0, dev(fr.ravel()), n_paths, K, np.ones(n_paths, dtype=np.uint8))
             x, v, cv = dev(x0), dev(np.zeros_like(x0)), dev(cv0, "f64")
             ctx.step_replicas(x, v, cv, 8, step0=11)
