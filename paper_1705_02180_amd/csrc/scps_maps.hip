@@ -461,6 +461,9 @@ __device__ __forceinline__ float contact_operand(const KParams &P, const float4 
 #ifndef SCPS_DIST_REF_AHEAD
 #define SCPS_DIST_REF_AHEAD 4   // the reference values ride a shorter ring (registers)
 #endif
+#ifndef SCPS_DIST_REF_GLOBAL
+#define SCPS_DIST_REF_GLOBAL 0  // 1: R_j from its own load also for stacks of at most 64 frames
+#endif
 // Pass 1, around each replica's reference frame j_r (see tube_sums): with
 // u_rp = C_rp - R_{j_r}p, X[r][k] += sum_p u_rp R_kp and Q[r] += sum_p u_rp^2
 // over the contact pairs of each work item (group of replicas, tile);
@@ -480,19 +483,27 @@ __device__ __forceinline__ float contact_operand(const KParams &P, const float4 
 // so component h of that load is the lane's B operand of block h.  A diagonal
 // tile counts the pairs j > i.  The float32 accumulators hold one row (64
 // pairs per element) and are added after every row into the workgroup's
-// float64 sums xl[slot][frame] in LDS.  Element v of lane l in block h is
+// float64 sums xl[slot][frame] in LDS; u^2 goes to float64 term by term (a
+// Q that carries float32 partial sums moves w by more than the ratchets
+// near the appendix limit allow).  Element v of lane l in block h is
 // replica slot 8 (v >> 2) + 4 (l >> 5) + (v & 3), frame 64 fb + 2 (l & 31) + h:
 // a stack of more than 64 frames is taken in frame blocks fb of 64, each a
 // pass of its own over the tile (the contact values are recomputed; Q is
 // summed in block 0 only).
-template <bool MASK, bool REFLOAD>
+// Addressing: pair (i, j) sits at s * 64 + i in the tile, s = (j - i) mod 64.
+// At step m of row i the uniform row b = (2m - i) mod 64 gives s = b + (l >> 5)
+// except for b = 63 and l >> 5 = 1 (s = 0), so every load is a uniform base
+// (scalar registers) plus one of two per-lane offsets fixed for the tile.
+// Lanes of slots without a replica (l & 31 >= nrep) compute finite values
+// from zero positions that reach only their own output rows and Q partials,
+// which the flush drops; MASK and DIAG tiles zero u of pairs that do not count.
+template <bool MASK, bool REFLOAD, bool DIAG, int NW>
 __device__ __forceinline__ void scps_dist_tile(const KParams &P, const SysDesc &S, const int nrep,
                                                const ScpsItem &it, const int fb_in, const float4 (*posj)[32],
                                                const int *orgj, const float4 *__restrict__ xs,
                                                const RepDesc *__restrict__ reps, const int myrep, const int jr,
                                                const int lane, const int wave, double *xl, double &q) {
     const int I = it.IJ >> 16, J = it.IJ & 0xFFFF;
-    const bool diag = I == J;
     const int K4 = stack_pm_width(S.K);
     const int rs = lane & 31, pq = lane >> 5;
     const bool rep = rs < nrep;
@@ -501,35 +512,44 @@ __device__ __forceinline__ void scps_dist_tile(const KParams &P, const SysDesc &
     const int fb = REFLOAD ? fb_in : 0;
     const bool bload = 64 * fb + 2 * rs < K4;
     const bool sum_q = fb == 0;
-    // global (not flat) loads from a uniform tile base with 32-bit lane offsets:
+    constexpr bool REF_LD = REFLOAD || SCPS_DIST_REF_GLOBAL;
+    // global (not flat) loads from a uniform base with 32-bit lane offsets:
     // flat loads would also count against the LDS wait counter and drain the ring
     typedef float v2 __attribute__((ext_vector_type(2)));
-    typedef const __attribute__((address_space(1))) v2 *gv2;
-    typedef const __attribute__((address_space(1))) float *gf;
-    const gv2 Rt = (gv2)(S.stack_pm + (int64_t)it.tile * 4096 * K4);
-    const gf Rf = (gf)(S.stack_pm + (int64_t)it.tile * 4096 * K4);
+    typedef const __attribute__((address_space(1))) char *gbytes;
+    const gbytes tile_base = (gbytes)(S.stack_pm + (int64_t)it.tile * 4096 * K4);
+    const uint32_t row_bytes = 4u * (uint32_t)K4;   // one pair of the tile, all frames
+    // byte offsets in a row pair: B operands (frames 2 rs, 2 rs + 1 of frame block fb;
+    // lanes past the stack width re-read the pair's first frames, whose columns
+    // the flush drops) and R_j
+    const uint32_t fo = bload ? 8u * (uint32_t)(32 * fb + rs) : 0u, ro = 4u * (uint32_t)jr;
+    const uint32_t up = (uint32_t)pq * 64u * row_bytes;              // s = b + 1 for the upper half
+    const uint32_t wrap = (uint32_t)(1 - pq) * 63u * 64u * row_bytes; // b = 63: lower half s = 63, upper s = 0
     const float4 *xr = xs + 2 * reps[myrep].poff + I * 128;
     constexpr int D = SCPS_DIST_AHEAD, DR = SCPS_DIST_REF_AHEAD;
     static_assert(D % DR == 0 && 32 % D == 0, "the rings advance together");
-    // pair (i, j) sits at s * 64 + i in the tile, s = (j - i) mod 64
-    // Unconditional loads from clamped in-tile addresses: a lane past the
-    // stack width (2 rs >= K4) feeds output columns of frames >= K, which the
-    // flush drops, and a load past the last row (i_ = 64) is never consumed.
-    auto bop = [&](int i_, int m_) {
+    // the base of step m_ of row i_ (a row past the last, i_ = 64, is never consumed:
+    // clamped to 63) and the lane offset
+    auto at = [&](int i_, int m_, uint32_t lane_bytes) {
         const int ic = i_ < 64 ? i_ : 63;
-        const int s_ = (2 * m_ + pq - ic) & 63;
-        return Rt[((s_ * 64 + ic) * K4 >> 1) + (bload ? 32 * fb + rs : 0)];
+        const int b = (2 * m_ - ic) & 63;
+        const bool w = b == 63;
+        const gbytes base = tile_base + (uint32_t)((w ? 0 : b) * 64 + ic) * row_bytes;
+        return base + ((w ? wrap : up) + lane_bytes);
+    };
+    auto bop = [&](int i_, int m_) {
+        typedef const __attribute__((address_space(1))) v2 *gv2;
+        return *(gv2)at(i_, m_, fo);
     };
     auto rop = [&](int i_, int m_) {   // R_j of the same pair, the reference of slot rs
-        const int ic = i_ < 64 ? i_ : 63;
-        const int s_ = (2 * m_ + pq - ic) & 63;
-        return Rf[(s_ * 64 + ic) * K4 + jr];
+        typedef const __attribute__((address_space(1))) float *gf;
+        return *(gf)at(i_, m_, ro);
     };
     v2 ring[D];
-    float rring[REFLOAD ? DR : 1];
+    float rring[REF_LD ? DR : 1];
 #pragma unroll
     for (int u = 0; u < D; ++u) ring[u] = bop(wave, u);
-    if constexpr (REFLOAD) {
+    if constexpr (REF_LD) {
 #pragma unroll
         for (int u = 0; u < DR; ++u) rring[u] = rop(wave, u);
     }
@@ -542,9 +562,9 @@ __device__ __forceinline__ void scps_dist_tile(const KParams &P, const SysDesc &
         return (jr & 1) ? ry : rx;
     };
     float rj_next = 0.f;
-    if constexpr (!REFLOAD) rj_next = ref_of(ring[0]);
+    if constexpr (!REF_LD) rj_next = ref_of(ring[0]);
 #pragma unroll 1
-    for (int i = wave; i < 64; i += 4) {
+    for (int i = wave; i < 64; i += NW) {
         const float4 pi = rep ? xr[i] : make_float4(0.f, 0.f, 0.f, 0.f);
         const int oi = MASK ? S.perm[I * 64 + i] : 0;
         const bool icon = I * 64 + i < S.nc;
@@ -560,23 +580,27 @@ __device__ __forceinline__ void scps_dist_tile(const KParams &P, const SysDesc &
                 const int m = D * mg + u;
                 const v2 b = ring[u];
                 float rj;
-                if constexpr (REFLOAD) {
+                if constexpr (REF_LD) {
                     rj = rring[u % DR];
-                    const int rm = m + DR < 32 ? m + DR : m + DR - 32, ri = m + DR < 32 ? i : i + 4;
+                    const int rm = m + DR < 32 ? m + DR : m + DR - 32, ri = m + DR < 32 ? i : i + NW;
                     rring[u % DR] = rop(ri, rm);
                 } else {
                     rj = rj_next;
                     rj_next = ref_of(ring[(u + 1) % D]);   // holds the next step's B operands
                 }
-                const int nm = m + D < 32 ? m + D : m + D - 32, ni = m + D < 32 ? i : i + 4;
+                const int nm = m + D < 32 ? m + D : m + D - 32, ni = m + D < 32 ? i : i + NW;
                 ring[u] = bop(ni, nm);
                 const int jl = 2 * m + pq;
-                bool ok = !diag | (jl > i);
-                if constexpr (MASK) {
-                    ok = ok & icon & (J * 64 + jl < S.nc) & (abs(oi - orgj[jl]) > P.min_sep);
+                float c;
+                if constexpr (MASK || DIAG) {
+                    bool ok = rep;
+                    if constexpr (DIAG) ok = ok & (jl > i);
+                    if constexpr (MASK) ok = ok & icon & (J * 64 + jl < S.nc) & (abs(oi - orgj[jl]) > P.min_sep);
+                    const float cv = contact_operand<MASK>(P, pi, posj[jl][rs], ok);
+                    c = ok ? cv - rj : 0.f;   // u = C - R_j of a counted pair
+                } else {
+                    c = contact_operand<false>(P, pi, posj[jl][rs], true) - rj;
                 }
-                const float cv = contact_operand<MASK>(P, pi, posj[jl][rs], ok & rep);
-                const float c = (ok & rep) ? cv - rj : 0.f;   // u = C - R_j of a counted pair
                 if (sum_q) q = fma((double)c, (double)c, q);
                 acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(c, b.x, acc[0], 0, 0, 0);
                 acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(c, b.y, acc[1], 0, 0, 0);
@@ -593,23 +617,44 @@ __device__ __forceinline__ void scps_dist_tile(const KParams &P, const SysDesc &
 #ifndef SCPS_DIST_WPE
 #define SCPS_DIST_WPE 3
 #endif
+#ifndef SCPS_DIST_NW
+#define SCPS_DIST_NW 8      // wavefronts per workgroup for stacks of at most 64 frames
+#endif
+#ifndef SCPS_DIST_NW_WPE
+#define SCPS_DIST_NW_WPE 4  // waves per SIMD with that workgroup (two workgroups per CU)
+#endif
+// Launch shape of k_scps_dist: stacks of at most 64 frames take SCPS_DIST_NW
+// wavefronts per workgroup sharing one staging of block J and one set of
+// float64 sums (more wavefronts per CU in the LDS of fewer workgroups); the
+// larger stacks (more registers per lane) take four.
+template <bool BIGK>
+struct DistShape {
+    static constexpr int NW = BIGK ? 4 : SCPS_DIST_NW;
+    static constexpr int WPE = BIGK ? SCPS_DIST_WPE : SCPS_DIST_NW_WPE;
+    static constexpr int WG = 64 * NW;
+    static constexpr int RESIDENT = 4 * WPE / NW;   // workgroups per CU
+};
 // Work unit t covers item t mod n_items in frame block t / n_items (nfb
 // blocks of 64 frames); the sums are flushed when (group, frame block) changes.
 // BIGK: stacks of more than 64 frames (a kernel of its own).
 template <bool BIGK>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SCPS_DIST_WPE, SCPS_DIST_WPE))) void k_scps_dist(
+__global__ __launch_bounds__(DistShape<BIGK>::WG)
+__attribute__((amdgpu_waves_per_eu(DistShape<BIGK>::WPE, DistShape<BIGK>::WPE))) void k_scps_dist(
     const KParams P, const SysDesc *__restrict__ sysd, const RepDesc *__restrict__ reps,
     const ScpsGroup *__restrict__ groups, const ScpsItem *__restrict__ items, const int n_items, const int nfb,
     const int *__restrict__ jref, const float4 *__restrict__ xs, double *__restrict__ X, double *__restrict__ Q,
     const int kmax, const int stack_sys) {
     __shared__ __align__(16) float4 posj[64][32];   // block J of every replica slot
     __shared__ double xl[32 * 64];                   // float64 sums X[slot][frame] of the current group
-    __shared__ double ql[4][64];
+    constexpr int NW = DistShape<BIGK>::NW, WG = DistShape<BIGK>::WG;
+    __shared__ double ql[NW][64];
     __shared__ int orgj[64];
     __shared__ int sh_rep[32];
     __shared__ int sh_jref[32];                      // reference frame of every replica slot
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int e = tid; e < 32 * 64; e += 256) xl[e] = 0.0;
+    // the wavefront index is uniform: in a scalar register, the row and step
+    // arithmetic of the tile loop (and its load bases) stay scalar
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    for (int e = tid; e < 32 * 64; e += WG) xl[e] = 0.0;
     double q = 0.0;
     int cur = -1, cur_fb = 0, nrep = 0;
     SysDesc S;
@@ -623,14 +668,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SCPS_DIST_W
             // flush the sums of (group, frame block) to the replicas' float64 totals
             ql[wave][lane] = q;
             __syncthreads();
-            for (int e = tid; e < 32 * 64; e += 256) {
+            for (int e = tid; e < 32 * 64; e += WG) {
                 const int slot = e >> 6, k = 64 * cur_fb + (e & 63);
                 if (slot < nrep && k < S.K) unsafeAtomicAdd(&X[(int64_t)sh_rep[slot] * kmax + k], xl[e]);
                 xl[e] = 0.0;
             }
             if (tid < 32 && cur_fb == 0) {
                 double sum = 0.0;
-                for (int w = 0; w < 4; ++w) sum += ql[w][tid] + ql[w][32 + tid];
+                for (int w = 0; w < NW; ++w) sum += ql[w][tid] + ql[w][32 + tid];
                 if (tid < nrep) unsafeAtomicAdd(&Q[sh_rep[tid]], sum);
             }
             q = 0.0;
@@ -656,7 +701,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SCPS_DIST_W
         if (64 * fb >= S.K) continue;   // the group's stack has no frame in this block (uniform per workgroup)
         // stage block J of every replica of the group
         const int J = it.IJ & 0xFFFF;
-        for (int e = tid; e < 64 * 32; e += 256) {
+        for (int e = tid; e < 64 * 32; e += WG) {
             const int pl = e >> 5, slot = e & 31;
             float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
             if (slot < nrep) p = xs[2 * reps[sh_rep[slot]].poff + J * 128 + pl];
@@ -665,10 +710,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SCPS_DIST_W
         if (tid < 64) orgj[tid] = S.perm[J * 64 + tid];
         __syncthreads();
         const int myrep = sh_rep[lane & 31], myj = sh_jref[lane & 31];
-        if (it.flags & TILE_MASK)
-            scps_dist_tile<true, BIGK>(P, S, nrep, it, fb, posj, orgj, xs, reps, myrep, myj, lane, wave, xl, q);
-        else
-            scps_dist_tile<false, BIGK>(P, S, nrep, it, fb, posj, orgj, xs, reps, myrep, myj, lane, wave, xl, q);
+        const bool diag = (it.IJ >> 16) == J;
+        if (it.flags & TILE_MASK) {
+            if (diag)
+                scps_dist_tile<true, BIGK, true, NW>(P, S, nrep, it, fb, posj, orgj, xs, reps, myrep, myj, lane, wave,
+                                                 xl, q);
+            else
+                scps_dist_tile<true, BIGK, false, NW>(P, S, nrep, it, fb, posj, orgj, xs, reps, myrep, myj, lane, wave,
+                                                  xl, q);
+        } else if (diag) {
+            scps_dist_tile<false, BIGK, true, NW>(P, S, nrep, it, fb, posj, orgj, xs, reps, myrep, myj, lane, wave, xl,
+                                              q);
+        } else {
+            scps_dist_tile<false, BIGK, false, NW>(P, S, nrep, it, fb, posj, orgj, xs, reps, myrep, myj, lane, wave, xl,
+                                               q);
+        }
     }
 }
 
@@ -1036,14 +1092,18 @@ hipError_t launch_scps_dist(const KParams &P, const SysDesc *sysd, const RepDesc
     if (n_items == 0) return hipSuccess;
     if (max_frames < 1 || max_frames > KMAX || max_frames > kmax) return hipErrorInvalidValue;
     const int nfb = (max_frames + 63) / 64;
-    const int cap = 256 * SCPS_DIST_WPE;   // resident workgroups: WPE per SIMD, four waves each
-    const int grid = n_items * nfb < cap ? n_items * nfb : cap;
-    if (nfb > 1)
-        hipLaunchKernelGGL(k_scps_dist<true>, dim3(grid), dim3(256), 0, st, P, sysd, reps, groups, items, n_items,
+    // a grid of the resident workgroups (256 CUs) striding over the work units
+    if (nfb > 1) {
+        typedef DistShape<true> DS;
+        const int grid = std::min(n_items * nfb, 256 * DS::RESIDENT);
+        hipLaunchKernelGGL(k_scps_dist<true>, dim3(grid), dim3(DS::WG), 0, st, P, sysd, reps, groups, items, n_items,
                            nfb, jref, xs, X, Q, kmax, stack_sys);
-    else
-        hipLaunchKernelGGL(k_scps_dist<false>, dim3(grid), dim3(256), 0, st, P, sysd, reps, groups, items, n_items,
-                           nfb, jref, xs, X, Q, kmax, stack_sys);
+    } else {
+        typedef DistShape<false> DS;
+        const int grid = std::min(n_items, 256 * DS::RESIDENT);
+        hipLaunchKernelGGL(k_scps_dist<false>, dim3(grid), dim3(DS::WG), 0, st, P, sysd, reps, groups, items,
+                           n_items, nfb, jref, xs, X, Q, kmax, stack_sys);
+    }
     return hipGetLastError();
 }
 
