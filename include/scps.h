@@ -316,7 +316,10 @@ scps_status scps_sync(scps_ctx *ctx, int32_t *bad_replicas, int32_t *n_bad);
  * steps 2 and 4): times every launch configuration the context can use for
  * scps_step_replicas -- the persistent kernel with 256, 512 or 1024 threads per
  * replica where a replica's state fits in one workgroup's LDS (also 64, one
- * wavefront, for chains of at most 256 particles), and the
+ * wavefront, for chains of at most 256 particles), the packed persistent
+ * kernel for chains of at most 32 particles (floor(64 / n) replicas per
+ * wavefront, n the longest chain, and 1, 2, 4 or 8 wavefronts per
+ * workgroup), and the
  * per-step path -- for n_steps steps on private device copies of
  * (x, v, cvstate), in three rounds taken in turns after one untimed step
  * each, and keeps the one with the fastest run for the context's later calls
@@ -327,8 +330,9 @@ scps_status scps_sync(scps_ctx *ctx, int32_t *bad_replicas, int32_t *n_bad);
  * other exec modes keep their schedule.
  *   x, v, cvstate: device buffers as for scps_step_replicas; read only.
  *   n_steps: steps timed per configuration, >= 1.
- *   chosen: nullable host int32[2]; receives {0 persistent / 1 per-step,
- *           threads per workgroup of the persistent kernel, or for an SCPS
+ *   chosen: nullable host int32[2]; receives {0 persistent / 1 per-step /
+ *           2 packed, threads per workgroup of the persistent kernel,
+ *           replicas per workgroup of the packed kernel, or for an SCPS
  *           context 1 when the nonbonded pass overlaps the distance pass and
  *           0 when it runs after the bias pass}.
  * Results of later calls differ from an untuned context's only by the order
@@ -336,6 +340,23 @@ scps_status scps_sync(scps_ctx *ctx, int32_t *bad_replicas, int32_t *n_bad);
  * the call and synchronises the stream.  Errors: INVALID_ARG, OOM, HIP. */
 scps_status scps_autotune(scps_ctx *ctx, const float *x, const float *v, const double *cvstate,
                           int64_t n_steps, int32_t *chosen);
+
+/* Fixes the launch configuration of scps_step_replicas for a context with
+ * exec_mode AUTO, as scps_autotune would (e.g. one it chose earlier):
+ *   path 0: the persistent kernel, param = threads per workgroup (64, 256,
+ *           512, 1024; the replica's state must fit one workgroup's LDS);
+ *   path 1: the per-step path (param ignored; the only path of an SCPS
+ *           context);
+ *   path 2: the packed persistent kernel, param = wavefronts per workgroup
+ *           (1 .. 8; every chain of at most 32 particles).
+ * Without a call or a tuning, chains of at most 32 particles run packed with
+ * four wavefronts per workgroup and longer ones on the persistent kernel
+ * where they fit, else per step.  Results differ between configurations
+ * only by the order of float32 and float64 additions.  Host only.
+ * Errors: INVALID_ARG (unknown path or parameter; paths 0 and 2 of an SCPS
+ * context), SHAPE (the chains do not fit the configuration), STATE
+ * (exec_mode not AUTO). */
+scps_status scps_set_launch(scps_ctx *ctx, int32_t path, int32_t param);
 
 /* Convergence measure of the iteration (the paper's Frobenius distance
  * between iterations I and J): the recorded frames of each iteration, projected

@@ -107,7 +107,10 @@ struct scps_ctx {
     int n_sitems = 0;
     int kmax = KMAX;
     int wg = 64;     // persistent workgroup size
-    int tuned = -1;  // -1 untuned; else 0 persistent (with wg) or 1 per-step, from scps_autotune
+    int tuned = -1;  // -1 untuned; else 0 persistent (with wg), 1 per-step, 2 packed (with pk_waves),
+                     // from scps_autotune or scps_set_launch
+    int pk_waves = 4;  // packed kernel: wavefronts per workgroup
+    int n_max = 0;     // longest chain among the replicas' systems
     int nbk = 0;     // nonbonded terms: bit 0 LJ, bit 1 Debye-Hueckel
     // cutoff variant: neighbour lists on the per-step path (rMD with both cutoffs set)
     bool nl = false;
@@ -500,6 +503,7 @@ scps_status init_impl(const scps_params *params, const scps_topology *topo, int3
         if (rsys[r] < 0 || rsys[r] >= topo->n_systems)
             return fail(SCPS_ERR_INVALID_ARG, "replica_system entry out of range");
         c->rep_off[r + 1] = c->rep_off[r] + c->sys[rsys[r]].n;
+        c->n_max = std::max(c->n_max, c->sys[rsys[r]].n);
         c->rep_poff[r + 1] = c->rep_poff[r] + c->sys[rsys[r]].n_pad;
     }
     c->sumN = c->rep_off[R];
@@ -787,7 +791,14 @@ scps_status step_impl(scps_ctx *c, float *x, float *v, double *cv, int64_t n_ste
         if (scps && h.K < 2) return fail(SCPS_ERR_STATE, "SCPS mode needs a frame stack of >= 2 maps");
     }
     const int64_t frame_stride = 3 * c->sumN;
-    bool persistent = !scps && c->prm.exec_mode == SCPS_EXEC_AUTO && c->tuned != 1;
+    const bool autoexec = !scps && c->prm.exec_mode == SCPS_EXEC_AUTO;
+    // untuned, chains of at most 32 particles run packed, several per wavefront
+    if (autoexec && (c->tuned == 2 || (c->tuned == -1 && packed_width_ok(c->n_max)))) {
+        HIP_TRY(c, launch_packed_rmd(c->pk_waves, c->nbk, c->kp, c->d_sysd, c->d_reps, c->R, c->n_max, x, v, cv,
+                                     n_steps, step0, record_every, frames, frame_stride, c->d_flags, c->stream));
+        return SCPS_OK;
+    }
+    bool persistent = autoexec && c->tuned != 1;
     const int wg = c->wg;
     if (persistent && c->n_pad_max > persistent_max_npad(wg)) persistent = false;
     if (persistent) {
@@ -1028,6 +1039,9 @@ scps_status autotune_impl(scps_ctx *c, const float *x, const float *v, const dou
     std::vector<Cand> cand;
     const bool scps = c->prm.bias_mode == SCPS_BIAS_SCPS;
     if (!scps && c->prm.exec_mode == SCPS_EXEC_AUTO) {
+        // chains of at most 32 particles: several replicas per wavefront, 1 .. 8 wavefronts per workgroup
+        if (packed_width_ok(c->n_max))
+            for (int w : {1, 2, 4, 8}) cand.push_back({2, w, false});
         // one wavefront per replica can win for chains of a few blocks (several replicas then share a CU)
         if (c->n_pad_max <= 4 * TILE) cand.push_back({0, 64, false});
         for (int wg : {256, 512, 1024})
@@ -1057,7 +1071,7 @@ scps_status autotune_impl(scps_ctx *c, const float *x, const float *v, const dou
     hipEvent_t e0, e1;
     HIP_TRY(c, hipEventCreate(&e0));
     HIP_TRY(c, hipEventCreate(&e1));
-    const int saved_tuned = c->tuned, saved_wg = c->wg;
+    const int saved_tuned = c->tuned, saved_wg = c->wg, saved_pk = c->pk_waves;
     const bool saved_overlap = c->overlap_nb;
     // every candidate once untimed (first-launch costs), then TUNE_ROUNDS timed
     // runs taken in turns, each from the caller's state; a candidate's time is
@@ -1069,6 +1083,7 @@ scps_status autotune_impl(scps_ctx *c, const float *x, const float *v, const dou
         for (size_t i = 0; i < cand.size() && st == SCPS_OK; ++i) {
             c->tuned = cand[i].path;
             if (cand[i].path == 0) c->wg = cand[i].wg;
+            if (cand[i].path == 2) c->pk_waves = cand[i].wg;
             if (scps) c->overlap_nb = cand[i].overlap;
             float ms = 0.f;
             HIP_TRY(c, hipMemcpyAsync(tx, x, nx * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
@@ -1106,18 +1121,49 @@ scps_status autotune_impl(scps_ctx *c, const float *x, const float *v, const dou
     if (st != SCPS_OK) {
         c->tuned = saved_tuned;
         c->wg = saved_wg;
+        c->pk_waves = saved_pk;
         c->overlap_nb = saved_overlap;
         return st;
     }
     c->tuned = cand[best_i].path;
-    if (c->tuned == 0) c->wg = cand[best_i].wg;
-    else c->wg = saved_wg;
+    c->wg = c->tuned == 0 ? cand[best_i].wg : saved_wg;
+    c->pk_waves = c->tuned == 2 ? cand[best_i].wg : saved_pk;
     c->overlap_nb = scps ? cand[best_i].overlap : saved_overlap;
     if (chosen) {
         chosen[0] = c->tuned;
-        chosen[1] = c->tuned == 0 ? c->wg : (scps && c->overlap_nb ? 1 : 0);
+        chosen[1] = c->tuned == 0   ? c->wg
+                    : c->tuned == 2 ? c->pk_waves * (64 / c->n_max)
+                                    : (scps && c->overlap_nb ? 1 : 0);
     }
     return SCPS_OK;
+}
+
+scps_status set_launch_impl(scps_ctx *c, int32_t path, int32_t param) {
+    if (c->prm.exec_mode != SCPS_EXEC_AUTO)
+        return fail(SCPS_ERR_STATE, "a launch configuration can be set with exec_mode AUTO only");
+    const bool scps = c->prm.bias_mode == SCPS_BIAS_SCPS;
+    if (path == 1) {
+        c->tuned = 1;
+        return SCPS_OK;
+    }
+    if (scps) return fail(SCPS_ERR_INVALID_ARG, "an SCPS context steps on the per-step path (path 1) only");
+    if (path == 0) {
+        if (param != 64 && param != 256 && param != 512 && param != 1024)
+            return fail(SCPS_ERR_INVALID_ARG, "the persistent kernel takes 64, 256, 512 or 1024 threads");
+        if (c->n_pad_max > persistent_max_npad(param))
+            return fail(SCPS_ERR_SHAPE, "a replica's state does not fit one workgroup's LDS");
+        c->tuned = 0;
+        c->wg = param;
+        return SCPS_OK;
+    }
+    if (path == 2) {
+        if (param < 1 || param > 8) return fail(SCPS_ERR_INVALID_ARG, "the packed kernel takes 1 .. 8 wavefronts");
+        if (!packed_width_ok(c->n_max)) return fail(SCPS_ERR_SHAPE, "the packed kernel needs chains of <= 32 particles");
+        c->tuned = 2;
+        c->pk_waves = param;
+        return SCPS_OK;
+    }
+    return fail(SCPS_ERR_INVALID_ARG, "path must be 0 (persistent), 1 (per-step) or 2 (packed)");
 }
 
 }  // namespace
@@ -1188,6 +1234,12 @@ scps_status scps_autotune(scps_ctx *ctx, const float *x, const float *v, const d
     } catch (const std::bad_alloc &) {
         return fail(SCPS_ERR_OOM, "host allocation failed");
     }
+}
+
+scps_status scps_set_launch(scps_ctx *ctx, int32_t path, int32_t param) {
+    scps_status st;
+    if (!usable(ctx, &st)) return st;
+    return set_launch_impl(ctx, path, param);
 }
 
 scps_status scps_least_biased_path(scps_ctx *ctx, const double *cvstate, const uint8_t *success, int32_t *index,

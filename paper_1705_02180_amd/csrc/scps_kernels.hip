@@ -745,6 +745,264 @@ hipError_t launch_persistent_rmd(int wg, int nbk, const KParams &P, const SysDes
 }
 
 // ---------------------------------------------------------------------------
+// packed persistent rMD kernel: several short chains per wavefront
+// ---------------------------------------------------------------------------
+// A chain of at most W <= 32 particles runs in a segment of W lanes: a
+// wavefront holds P = 64 / W replicas (segment s: lanes s W .. s W + W - 1,
+// lane s W + a owns internal particle a), a workgroup blockDim.x / 64
+// wavefronts, and the kernel runs all n_steps of every replica it holds.
+// Each wavefront works alone on its own part of LDS (no workgroup barrier):
+// the lanes publish their positions each step and read their partners'.
+// Pair terms are evaluated on both lanes of a pair, lane a accumulating only
+// its own force (no cross-lane partials), partner b = (a + k) mod n at step
+// k = 1 .. n - 1; z, counted twice that way, is halved.  Float32 pair math over
+// at most 31 partners per lane, then float64 per particle, as in the tile
+// kernels; bonds, the ratchet and the Langevin update in float64.  Segment
+// sums (z each step, T at the end) run over the segment's lanes in a fixed
+// order, so every lane of a replica holds the same z.
+constexpr int PACK_WMAX = 32;
+
+// Lanes of one wavefront exchanging values through LDS: what the lanes stored
+// before this point is visible to every lane's loads after it.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// LDS of one wavefront: positions (x, y, z, charge), chain indices, the
+// lane's native-map value at every partner step, a reduction row and the
+// chain predecessors.
+__host__ __device__ inline size_t packed_wave_lds_bytes(int W) {
+    return 64 * (sizeof(float4) + sizeof(int) + sizeof(double) + sizeof(int)) + (size_t)W * 64 * sizeof(float);
+}
+
+template <int NBK>
+__global__ __launch_bounds__(512) void k_rmd_packed(const KParams P, const SysDesc *__restrict__ sysd,
+                                                    const RepDesc *__restrict__ reps, const int R, const int W,
+                                                    float *__restrict__ x, float *__restrict__ v,
+                                                    double *__restrict__ cv, const int64_t n_steps,
+                                                    const uint64_t step0, const int record_every,
+                                                    float *__restrict__ frames, const int64_t frame_stride,
+                                                    int *__restrict__ flags) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    unsigned char *wl = smem + (size_t)wave * packed_wave_lds_bytes(W);
+    float4 *posl = reinterpret_cast<float4 *>(wl);                 // [64]
+    int *orgl = reinterpret_cast<int *>(posl + 64);                 // [64]
+    double *redl = reinterpret_cast<double *>(orgl + 64);          // [64]
+    int *prevl = reinterpret_cast<int *>(redl + 64);               // [64]
+    float *refl = reinterpret_cast<float *>(prevl + 64);           // [W][64]: R(a, partner at step k)
+
+    const int PR = 64 / W;                           // replicas per wavefront
+    const int seg = lane / W, a = lane - seg * W, sbase = seg * W;
+    const int slot = ((int)blockIdx.x * (int)(blockDim.x >> 6) + wave) * PR + seg;
+    const int r = (seg < PR && slot < R) ? slot : -1;
+    RepDesc rd{};
+    SysDesc S{};
+    int n = 0;
+    if (r >= 0) {
+        rd = reps[r];
+        S = sysd[rd.sys];
+        n = S.n;
+    }
+    const bool act = a < n;                          // a particle of a replica
+    float *xr = r >= 0 ? x + 3 * rd.off : nullptr;
+    float *vr = (r >= 0 && v) ? v + 3 * rd.off : nullptr;
+    int o = lane, nxt = -1;
+    float4 p = pad_position(lane);
+    float vel[3] = {0.f, 0.f, 0.f};
+    double inv_m = 1.0;
+    if (act) {
+        o = S.perm[a];
+        p = make_float4(xr[o], xr[n + o], xr[2 * n + o], S.charge[a]);
+        if (vr) {
+            vel[0] = vr[o];
+            vel[1] = vr[n + o];
+            vel[2] = vr[2 * n + o];
+        }
+        inv_m = 1.0 / (double)S.mass[a];
+        nxt = S.bond_next[a];
+    }
+    const bool icon = act && a < S.nc;
+    const float qp = P.dh_pref * p.w;
+    orgl[lane] = o;
+    prevl[lane] = -1;
+    wave_lds_sync();
+    if (act && nxt >= 0) prevl[sbase + nxt] = a;
+    // native-map value of the pair met at partner step k (0 outside the contact set)
+    for (int k = 1; k < W; ++k) {
+        float rv = 0.f;
+        if (icon && k < n) {
+            const int b = a + k < n ? a + k : a + k - n;
+            if (b < S.nc) rv = S.ref[((b - a) & 63) * 64 + a];
+        }
+        refl[k * 64 + lane] = rv;
+    }
+    wave_lds_sync();
+    const int prv = act ? prevl[lane] : -1;
+
+    double zm = 0.0, z_last = 0.0, eb_last = 0.0;
+    if (r >= 0) {
+        zm = cv[(int64_t)r * CV_STRIDE + CV_ZM];
+        z_last = cv[(int64_t)r * CV_STRIDE + CV_Z];
+        eb_last = cv[(int64_t)r * CV_STRIDE + CV_EB];
+    }
+    double tsum = 0.0;
+    bool bad = false;
+    const double c1 = P.c1;
+    // the sum over the lanes of this lane's segment, in lane order
+    auto seg_sum = [&](double val) {
+        redl[lane] = val;
+        wave_lds_sync();
+        double t = 0.0;
+        for (int e = 0; e < W; ++e)
+            if (e < n) t += redl[sbase + e];
+        wave_lds_sync();
+        return t;
+    };
+    for (int64_t m = 0;; ++m) {
+        if (record_every > 0 && frames && (m % record_every) == 0 && act) {
+            float *fr = frames + (m / record_every) * frame_stride + 3 * rd.off;
+            fr[o] = p.x;
+            fr[n + o] = p.y;
+            fr[2 * n + o] = p.z;
+        }
+        if (m == n_steps) break;
+        posl[lane] = p;
+        wave_lds_sync();
+        // ---- pair phase ----------------------------------------------------
+        float fn[3] = {0.f, 0.f, 0.f}, fg[3] = {0.f, 0.f, 0.f}, zt = 0.f;
+        for (int k = 1; k < W; ++k) {
+            const bool pv = act && k < n;
+            const int b = a + k < n ? a + k : a + k - n;
+            const int bl = pv ? sbase + b : lane;
+            const float4 pj = posl[bl];
+            float dx, dy, dz;
+            const float r2 = pair_r2(p, pj, dx, dy, dz);
+            const int sep = abs(o - orgl[bl]);
+            if constexpr (NBK != 0) {
+                const bool nbon = pv & (sep > P.nb_excl) & (!P.has_cut_nb | (r2 <= P.r_cut_nb2));
+                const float fs = nb_scalar<NBK>(P, r2, qp, pj.w);
+                const float f = nbon ? fs : 0.f;
+                fn[0] = fmaf(f, dx, fn[0]);
+                fn[1] = fmaf(f, dy, fn[1]);
+                fn[2] = fmaf(f, dz, fn[2]);
+            }
+            const bool con = pv & icon & (b < S.nc) & (sep > P.min_sep);
+            const bool inside = !P.has_cut | (r2 <= P.r_cut2);   // beyond a cutoff C = 0 (R still counts)
+            const float q = r2 * P.inv_r0sq;
+            const float q2 = q * q;
+            const float t = q + q2;
+            const float num = 1.f + t;
+            const float den = fmaf(q2, t, num);
+            const float inv_den = inside ? frcp(den) : 0.f;
+            float diff = num * inv_den - refl[k * 64 + lane];
+            diff = con ? diff : 0.f;
+            zt = fmaf(diff, diff, zt);
+            const float poly = fmaf(q, fmaf(q, fmaf(q, P.cp[0], P.cp[1]), P.cp[2]), P.cp[3]);
+            const float g = (diff * (q2 * inv_den)) * (poly * inv_den);
+            fg[0] = fmaf(g, dx, fg[0]);
+            fg[1] = fmaf(g, dy, fg[1]);
+            fg[2] = fmaf(g, dz, fg[2]);
+        }
+        double F[3] = {(double)fn[0], (double)fn[1], (double)fn[2]};
+        if (P.has_bond) {
+            double f[3];
+            if (nxt >= 0) {
+                bond_force(P, p, posl[sbase + nxt], f);
+                for (int c = 0; c < 3; ++c) F[c] += f[c];
+            }
+            if (prv >= 0) {
+                bond_force(P, p, posl[sbase + prv], f);
+                for (int c = 0; c < 3; ++c) F[c] += f[c];
+            }
+        }
+        // ---- ratchet, eq (FrMD): z_m updated before the force is used ----
+        const double z = 0.5 * seg_sum((double)zt);
+        zm = fmin(zm, z);
+        const double dzr = z - zm;
+        const double scale = -P.k_R * dzr;
+        z_last = z;
+        eb_last = 0.5 * P.k_R * dzr * dzr;
+        // ---- Langevin update, float64 per particle ----------------------
+        if (act) {
+            double fb2 = 0.0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double fb = scale * (double)fg[c];
+                F[c] += fb;
+                fb2 = fma(fb, fb, fb2);
+            }
+            tsum = fma(fb2, inv_m, tsum);
+            double gn[3];
+            normals3(P, (uint32_t)o, P.rep_base + (uint32_t)r, step0 + (uint64_t)m, gn[0], gn[1], gn[2]);
+            double X[3] = {(double)p.x, (double)p.y, (double)p.z};
+            if (P.integrator == 0) {
+                const double mob = P.dt * inv_m / P.gamma;
+                const double amp = sqrt(2.0 * P.kT * mob);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) X[c] += mob * F[c] + amp * gn[c];
+            } else {
+                const double amp = sqrt((1.0 - c1 * c1) * P.kT * inv_m);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    double u = (double)vel[c] + P.dt * F[c] * inv_m;
+                    X[c] += 0.5 * P.dt * u;
+                    u = c1 * u + amp * gn[c];
+                    X[c] += 0.5 * P.dt * u;
+                    vel[c] = (float)u;
+                }
+            }
+            p = make_float4((float)X[0], (float)X[1], (float)X[2], p.w);
+            bad |= !(isfinite(p.x) && isfinite(p.y) && isfinite(p.z));
+        }
+        wave_lds_sync();
+    }
+    if (act) {
+        xr[o] = p.x;
+        xr[n + o] = p.y;
+        xr[2 * n + o] = p.z;
+        if (vr) {
+            vr[o] = vel[0];
+            vr[n + o] = vel[1];
+            vr[2 * n + o] = vel[2];
+        }
+        if (bad) flags[r] = 1;
+    }
+    // bias functional: T += dt sum_steps sum_i |F_bias,i|^2 / (m_i gamma)
+    const double tt = seg_sum(tsum);
+    if (r >= 0 && a == 0 && n_steps > 0) {
+        cv[(int64_t)r * CV_STRIDE + CV_Z] = z_last;
+        cv[(int64_t)r * CV_STRIDE + CV_ZM] = zm;
+        cv[(int64_t)r * CV_STRIDE + CV_EB] = eb_last;
+        cv[(int64_t)r * CV_STRIDE + CV_T] += P.dt / P.gamma * tt;
+    }
+}
+
+int packed_width_ok(int n_max) { return n_max >= 2 && n_max <= PACK_WMAX; }
+
+hipError_t launch_packed_rmd(int waves, int nbk, const KParams &P, const SysDesc *sysd, const RepDesc *reps, int R,
+                             int n_max, float *x, float *v, double *cv, int64_t n_steps, uint64_t step0,
+                             int record_every, float *frames, int64_t frame_stride, int *flags, hipStream_t st) {
+    if (!packed_width_ok(n_max) || waves < 1 || waves > 8) return hipErrorInvalidValue;
+    const int W = n_max, per_wg = waves * (64 / W);
+    const int grid = (R + per_wg - 1) / per_wg;
+    const size_t lds = (size_t)waves * packed_wave_lds_bytes(W);
+#define SCPS_LAUNCH(K)                                                                                          \
+    hipLaunchKernelGGL((k_rmd_packed<K>), dim3(grid), dim3(64 * waves), lds, st, P, sysd, reps, R, W, x, v, cv, \
+                       n_steps, step0, record_every, frames, frame_stride, flags)
+    switch (nbk) {
+    case 0: SCPS_LAUNCH(0); break;
+    case 1: SCPS_LAUNCH(1); break;
+    case 2: SCPS_LAUNCH(2); break;
+    default: SCPS_LAUNCH(3); break;
+    }
+#undef SCPS_LAUNCH
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // per-step path: gather / pairs / finalize / integrate / scatter
 // Positions live in xs as float4 (x, y, z, charge), internal order, every
 // block of 64 stored twice (replica r at 2 poff_r); velocities in vs

@@ -77,6 +77,8 @@ _lib.scps_sync.restype = C.c_int
 _lib.scps_sync.argtypes = [_vp, _vp, _vp]
 _lib.scps_autotune.restype = C.c_int
 _lib.scps_autotune.argtypes = [_vp, _vp, _vp, _vp, _i64, _vp]
+_lib.scps_set_launch.restype = C.c_int
+_lib.scps_set_launch.argtypes = [_vp, _i32, _i32]
 _lib.scps_least_biased_path.restype = C.c_int
 _lib.scps_least_biased_path.argtypes = [_vp, _vp, _vp, _vp, _vp]
 _lib.scps_eval_tube.restype = C.c_int
@@ -104,7 +106,7 @@ _lib.scps_last_error.argtypes = []
 
 EXPORTS = ["scps_init_system", "scps_set_reference_map", "scps_step_replicas", "scps_eval_z_and_grad",
            "scps_ratchet_energy", "scps_update_reference_from_paths", "scps_set_stream", "scps_sync",
-           "scps_autotune", "scps_least_biased_path", "scps_eval_tube", "scps_eval_sigma", "scps_path_distance",
+           "scps_autotune", "scps_set_launch", "scps_least_biased_path", "scps_eval_tube", "scps_eval_sigma", "scps_path_distance",
            "scps_path_distance_noalloc", "scps_time_passes", "scps_pass_times",
            "scps_funnel_steps", "scps_funnel_mean_path", "scps_scale_by_replica", "scps_destroy",
            "scps_last_error"]
@@ -277,15 +279,22 @@ class Context:
 
     def autotune(self, x: torch.Tensor, v: Optional[torch.Tensor], cvstate: torch.Tensor, n_steps: int):
         """Time the launch configurations on copies of the state and keep the
-        fastest; returns (path, threads): path 0 persistent, 1 per-step, and
-        the persistent kernel's threads per replica (an SCPS context: 1 when
-        its nonbonded pass overlaps the distance pass, else 0)."""
+        fastest; returns (path, param): path 0 persistent, 1 per-step, 2
+        packed, and the persistent kernel's threads per replica or the packed
+        kernel's replicas per workgroup (an SCPS context: 1 when its
+        nonbonded pass overlaps the distance pass, else 0)."""
         px = _dev(x, torch.float32, 3 * self.sumN, "x")
         pv = _dev(v, torch.float32, 3 * self.sumN, "v")
         pc = _dev(cvstate, torch.float64, self.R * CV_STRIDE, "cvstate")
         out = np.zeros(2, dtype=np.int32)
         _check(_lib.scps_autotune(self._ctx(), px, pv, pc, int(n_steps), out.ctypes.data_as(C.c_void_p)))
         return int(out[0]), int(out[1])
+
+    def set_launch(self, path: int, param: int = 0):
+        """Fix the launch configuration: path 0 persistent (param = threads
+        per workgroup), 1 per-step, 2 packed (param = wavefronts per
+        workgroup)."""
+        _check(_lib.scps_set_launch(self._ctx(), int(path), int(param)))
 
     def eval_tube(self, stack_system: int, x: torch.Tensor, s: Optional[torch.Tensor] = None,
                   w: Optional[torch.Tensor] = None):

@@ -60,9 +60,10 @@ def _stats(X, cv, n):
     return {"z": cv[:, 0], "z_m": cv[:, 1], "bond_mean": b.mean(axis=1), "bond_var": b.var(axis=1)}
 
 
-@pytest.mark.parametrize("exec_mode", [0, 1], ids=["persistent", "per_step"])
+@pytest.mark.parametrize("exec_mode,launch", [(0, (2, 4)), (0, (0, 64)), (1, None)],
+                         ids=["packed", "persistent", "per_step"])
 @pytest.mark.parametrize("R", [16, 256], ids=["16_replicas", "256_replicas"])
-def test_trajectory_statistics_config1(S, R, exec_mode):
+def test_trajectory_statistics_config1(S, R, exec_mode, launch):
     """The 20-bead overdamped chain under rMD for 1000 steps, every replica
     driven by the Philox counters of its own id on both sides: at t = 100,
     200, ..., 1000 the ensemble means of z, z_m and the bond-length mean and
@@ -73,6 +74,8 @@ def test_trajectory_statistics_config1(S, R, exec_mode):
     n = w.systems[0].n
     ctx = S.Context.from_workload(w, exec_mode=exec_mode)
     ctx.set_reference_map(0, native_xyz=w.systems[0].native)
+    if launch is not None:
+        ctx.set_launch(*launch)
     x = dev(w.initial_x())
     cv = dev(w.initial_cvstate(), "f64")
     osys = O.System.from_inputs(w.systems[0], p)
