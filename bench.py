@@ -15,6 +15,8 @@ Other workloads (--workload), each printed as its own JSON line:
   chain560      256 replicas of a 560-particle chain (35 groups of 16,
                 contacts over the 280 heavy particles), ratchet on z, blocks
                 of 100 steps in one persistent launch
+  chain20       16384 replicas of the 20-bead chain (several per wavefront,
+                blocks of 1000 steps), the 16-replica batch beside it
   uneven512     512 chains, N ~ U{200..3000}, each with its own native map
   autograd3000  z and E_b forward + backward for 64 chains of 3000 particles
   cutoff6000    the 6000-particle chain under rMD with contact and nonbonded
@@ -69,7 +71,8 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default="scps6000",
-                    choices=["chain560", "uneven512", "autograd3000", "scps6000", "cutoff6000", "funnel"])
+                    choices=["chain560", "chain20", "uneven512", "autograd3000", "scps6000", "cutoff6000",
+                             "funnel"])
     ap.add_argument("--steps", type=int, default=None,
                     help="timed benchmark steps (default: 50 for scps6000, one 10^4-step iteration; else 20)")
     ap.add_argument("--warmup", type=int, default=None, help="untimed benchmark steps (default 2 / 3)")
@@ -91,7 +94,7 @@ def parse():
     if a.warmup is None:
         a.warmup = 2 if a.workload == "scps6000" else 3
     if a.block is None:
-        a.block = 200 if a.workload == "scps6000" else 100
+        a.block = {"scps6000": 200, "chain20": 1000}.get(a.workload, 100)
     return a
 
 
@@ -325,6 +328,76 @@ def bench_chain560(args, torch, I, scps):
     ctx.close()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline_steps(w, args.cpu_steps, what=" of the same workload")
+    return out
+
+
+# ---------------------------------------------------------------------------
+# the 20-bead chain, many replicas per wavefront
+# ---------------------------------------------------------------------------
+def bench_chain20(args, torch, I, scps):
+    """The 20-bead overdamped chain (LJ, contacts against a compact native
+    map) batched: 16384 replicas by default, floor(64 / 20) = 3 per
+    wavefront on the packed kernel unless the autotuner finds better; the
+    16-replica batch of the CPU-sized configuration is timed beside it."""
+    R = args.replicas or 16384
+    w = I.config1(n_replicas=R)
+    sy = w.systems[0]
+    con, nb, both = pair_counts(sy, w.params)
+
+    def make(wl):
+        c = scps.Context.from_workload(wl)
+        c.set_reference_map(0, native_xyz=sy.native)
+        return (c, torch.as_tensor(wl.initial_x(), device="cuda"),
+                torch.as_tensor(wl.initial_cvstate(), device="cuda"))
+
+    ctx, x, cv = make(w)
+    path, param = ctx.autotune(x, None, cv, args.block // 10)  # on copies of the state, before timing
+    step = [0]
+
+    def call(_):
+        ctx.step_replicas(x, None, cv, args.block, step0=step[0])
+        step[0] += args.block
+
+    for _ in range(args.warmup):
+        call(0)
+    ctx.sync()
+    wall, per_ms = timed_calls(torch, call, args.steps)
+    ctx.sync()
+    value = R * args.block * args.steps / wall
+    launch = {0: f"persistent, {param} threads per replica", 1: "per-step",
+              2: f"packed, {param} replicas per workgroup ({64 // sy.n} per wavefront)"}[path]
+    out = base_line(args, value, "replica-steps/s", wall, args.steps, {
+        "workload": f"chain20_config1: {R} replicas x 20 beads, {con} contact pairs + {nb} LJ pairs, "
+                    f"overdamped dt=0.01, {args.block} Langevin steps per benchmark step",
+        "replicas": R, "particles": sy.n, "block": args.block, "launch": launch + " (autotuned)"})
+    out["contact_pair_evals_per_s"] = value * con
+    out["nonbonded_pair_evals_per_s"] = value * nb
+    kname = {0: "k_rmd_persistent", 1: "k_pairs", 2: "k_rmd_packed"}[path]
+    out["roofline"] = roofline(R * args.block * step_flops(con, nb, both), per_ms, kname, None)
+    out["roofline"]["note"] = ("flop counts each pair once; the packed kernel evaluates each pair on both "
+                               "of its lanes")
+    ctx.close()
+    # the CPU-sized configuration as stated: 16 replicas
+    w16 = I.config1(n_replicas=16)
+    c16, x16, cv16 = make(w16)
+    c16.step_replicas(x16, None, cv16, 10)
+    c16.sync()
+    t0 = time.perf_counter()
+    c16.step_replicas(x16, None, cv16, 1000, step0=10)
+    c16.sync()
+    out["config1_16_replicas"] = {"value": 16 * 1000 / (time.perf_counter() - t0), "unit": "replica-steps/s",
+                                  "launch": "default (packed, 4 wavefronts per workgroup)"}
+    c16.close()
+    if not args.no_plain:
+        plain = run_plain(scps, torch, w, args.plain_replicas, args.plain_steps)
+        out["plain"] = {"value": plain, "unit": "replica-steps/s",
+                        "form": f"one replica per context, one launch sequence per Langevin step "
+                                f"({args.plain_replicas} replicas x {args.plain_steps} steps)"}
+        out["speedup_vs_plain"] = value / plain
+    if not args.no_cpu:
+        # about 20 s of oracle work: the 20-bead chain costs ~0.1 ms per replica-step on one core
+        out["cpu_baseline"] = cpu_baseline_steps(w, max(args.cpu_steps, 30000), replicas=list(range(min(R, 2048))),
+                                                 what=" of the same workload")
     return out
 
 
@@ -826,8 +899,8 @@ def main():
     from paper_1705_02180_amd import scps
 
     torch.cuda.set_device(0)
-    fn = {"chain560": bench_chain560, "uneven512": bench_uneven512, "autograd3000": bench_autograd3000,
-          "scps6000": bench_scps6000, "cutoff6000": bench_cutoff6000, "funnel": bench_funnel}[args.workload]
+    fn = {"chain560": bench_chain560, "chain20": bench_chain20, "uneven512": bench_uneven512,
+          "autograd3000": bench_autograd3000, "scps6000": bench_scps6000, "cutoff6000": bench_cutoff6000, "funnel": bench_funnel}[args.workload]
     out = fn(args, torch, I, scps)
     print(json.dumps(out), flush=True)
 
