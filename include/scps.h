@@ -317,7 +317,7 @@ scps_status scps_sync(scps_ctx *ctx, int32_t *bad_replicas, int32_t *n_bad);
  * scps_step_replicas -- the persistent kernel with 256, 512 or 1024 threads per
  * replica where a replica's state fits in one workgroup's LDS (also 64, one
  * wavefront, for chains of at most 256 particles), the packed persistent
- * kernel for chains of at most 32 particles (floor(64 / n) replicas per
+ * kernel for chains of at most 64 particles (floor(64 / n) replicas per
  * wavefront, n the longest chain, and 1, 2, 4 or 8 wavefronts per
  * workgroup), and the
  * per-step path -- for n_steps steps on private device copies of
@@ -348,7 +348,7 @@ scps_status scps_autotune(scps_ctx *ctx, const float *x, const float *v, const d
  *   path 1: the per-step path (param ignored; the only path of an SCPS
  *           context);
  *   path 2: the packed persistent kernel, param = wavefronts per workgroup
- *           (1 .. 8; every chain of at most 32 particles).
+ *           (1 .. 8; every chain of at most 64 particles).
  * Without a call or a tuning, chains of at most 32 particles run packed with
  * four wavefronts per workgroup and longer ones on the persistent kernel
  * where they fit, else per step.  Results differ between configurations

@@ -793,7 +793,7 @@ scps_status step_impl(scps_ctx *c, float *x, float *v, double *cv, int64_t n_ste
     const int64_t frame_stride = 3 * c->sumN;
     const bool autoexec = !scps && c->prm.exec_mode == SCPS_EXEC_AUTO;
     // untuned, chains of at most 32 particles run packed, several per wavefront
-    if (autoexec && (c->tuned == 2 || (c->tuned == -1 && packed_width_ok(c->n_max)))) {
+    if (autoexec && (c->tuned == 2 || (c->tuned == -1 && packed_default(c->n_max)))) {
         HIP_TRY(c, launch_packed_rmd(c->pk_waves, c->nbk, c->kp, c->d_sysd, c->d_reps, c->R, c->n_max, x, v, cv,
                                      n_steps, step0, record_every, frames, frame_stride, c->d_flags, c->stream));
         return SCPS_OK;
@@ -1039,7 +1039,7 @@ scps_status autotune_impl(scps_ctx *c, const float *x, const float *v, const dou
     std::vector<Cand> cand;
     const bool scps = c->prm.bias_mode == SCPS_BIAS_SCPS;
     if (!scps && c->prm.exec_mode == SCPS_EXEC_AUTO) {
-        // chains of at most 32 particles: several replicas per wavefront, 1 .. 8 wavefronts per workgroup
+        // chains of at most 64 particles: 64 / n replicas per wavefront, 1 .. 8 wavefronts per workgroup
         if (packed_width_ok(c->n_max))
             for (int w : {1, 2, 4, 8}) cand.push_back({2, w, false});
         // one wavefront per replica can win for chains of a few blocks (several replicas then share a CU)
@@ -1158,7 +1158,7 @@ scps_status set_launch_impl(scps_ctx *c, int32_t path, int32_t param) {
     }
     if (path == 2) {
         if (param < 1 || param > 8) return fail(SCPS_ERR_INVALID_ARG, "the packed kernel takes 1 .. 8 wavefronts");
-        if (!packed_width_ok(c->n_max)) return fail(SCPS_ERR_SHAPE, "the packed kernel needs chains of <= 32 particles");
+        if (!packed_width_ok(c->n_max)) return fail(SCPS_ERR_SHAPE, "the packed kernel needs chains of <= 64 particles");
         c->tuned = 2;
         c->pk_waves = param;
         return SCPS_OK;

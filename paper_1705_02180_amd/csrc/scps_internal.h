@@ -133,9 +133,11 @@ hipError_t launch_persistent_rmd(int wg, int nbk, const KParams &P, const SysDes
                                  const int *order, int R, int n_pad_max, float *x, float *v,
                                  double *cv, int64_t n_steps, uint64_t step0, int record_every,
                                  float *frames, int64_t frame_stride, int *flags, hipStream_t st);
-// Several chains of at most 32 particles per wavefront (64 / n_max per
-// wavefront, `waves` wavefronts per workgroup), all n_steps in one launch.
+// Chains of at most 64 particles, 64 / n_max per wavefront, `waves` wavefronts
+// per workgroup, all n_steps in one launch; the untuned default for chains that
+// pack at least two to a wavefront.
 int packed_width_ok(int n_max);
+int packed_default(int n_max);
 hipError_t launch_packed_rmd(int waves, int nbk, const KParams &P, const SysDesc *sysd, const RepDesc *reps, int R,
                              int n_max, float *x, float *v, double *cv, int64_t n_steps, uint64_t step0,
                              int record_every, float *frames, int64_t frame_stride, int *flags, hipStream_t st);

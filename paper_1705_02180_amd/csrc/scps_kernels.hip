@@ -747,7 +747,7 @@ hipError_t launch_persistent_rmd(int wg, int nbk, const KParams &P, const SysDes
 // ---------------------------------------------------------------------------
 // packed persistent rMD kernel: several short chains per wavefront
 // ---------------------------------------------------------------------------
-// A chain of at most W <= 32 particles runs in a segment of W lanes: a
+// A chain of at most W <= 64 particles runs in a segment of W lanes: a
 // wavefront holds P = 64 / W replicas (segment s: lanes s W .. s W + W - 1,
 // lane s W + a owns internal particle a), a workgroup blockDim.x / 64
 // wavefronts, and the kernel runs all n_steps of every replica it holds.
@@ -756,11 +756,11 @@ hipError_t launch_persistent_rmd(int wg, int nbk, const KParams &P, const SysDes
 // Pair terms are evaluated on both lanes of a pair, lane a accumulating only
 // its own force (no cross-lane partials), partner b = (a + k) mod n at step
 // k = 1 .. n - 1; z, counted twice that way, is halved.  Float32 pair math over
-// at most 31 partners per lane, then float64 per particle, as in the tile
+// at most 63 partners per lane, then float64 per particle, as in the tile
 // kernels; bonds, the ratchet and the Langevin update in float64.  Segment
 // sums (z each step, T at the end) run over the segment's lanes in a fixed
 // order, so every lane of a replica holds the same z.
-constexpr int PACK_WMAX = 32;
+constexpr int PACK_WMAX = 64;
 
 // Lanes of one wavefront exchanging values through LDS: what the lanes stored
 // before this point is visible to every lane's loads after it.
@@ -981,6 +981,8 @@ __global__ __launch_bounds__(512) void k_rmd_packed(const KParams P, const SysDe
 }
 
 int packed_width_ok(int n_max) { return n_max >= 2 && n_max <= PACK_WMAX; }
+// without tuning, chains that pack at least two to a wavefront
+int packed_default(int n_max) { return packed_width_ok(n_max) && n_max <= PACK_WMAX / 2; }
 
 hipError_t launch_packed_rmd(int waves, int nbk, const KParams &P, const SysDesc *sysd, const RepDesc *reps, int R,
                              int n_max, float *x, float *v, double *cv, int64_t n_steps, uint64_t step0,

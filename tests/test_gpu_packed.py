@@ -1,7 +1,7 @@
-"""The packed persistent kernel: several chains of at most 32 particles in one
-wavefront (floor(64 / n) replicas per wavefront, 1 .. 8 wavefronts per
-workgroup), all steps of a call in one launch.  Forces, z and the bias
-functional of one step against the FP64 oracle (chains of 2 .. 32 particles,
+"""The packed persistent kernel: chains of at most 64 particles, floor(64 / n)
+replicas per wavefront (one for 33 .. 64), 1 .. 8 wavefronts per workgroup,
+all steps of a call in one launch.  Forces, z and the bias functional of one
+step against the FP64 oracle (chains of 2 .. 64 particles,
 ragged replica counts, two systems of different lengths in one wavefront,
 sequence separation and cutoffs), the Philox noise stream, short noisy
 trajectories and recorded frames against the one-replica-per-workgroup
@@ -76,6 +76,8 @@ CASES = [
     ("seqsep_and_cutoffs", [24], "tail", 7, None,
      {"min_seq_sep": 3, "r_cut_contact": 9.0, "r_cut_nb": 10.0}),
     ("bias_only", [20], "all", 6, None, {"k_bond": 0.0, "lj_eps": 0.0, "dh_prefactor": 0.0, "k_R": 0.5}),
+    ("chain48_one_per_wave", [48], "half", 5, None, {}),
+    ("chain64_full_wave_with_33", [64, 33], "all", 9, [0, 1, 0, 1, 1, 0, 0, 1, 0], {}),
 ]
 
 
@@ -249,6 +251,17 @@ def test_set_launch_validation(S):
         ctx.set_launch(2, 4)
     assert e.value.status == -2
     ctx.close()
+    base = dict(I._base_params())
+    for n, ok in ((64, True), (65, False)):                  # one replica per wavefront at most 64 lanes
+        wn = I.Workload("edge", dict(base), [_system(n, "all", 5)], np.zeros(2, dtype=np.int32), 1)
+        ctx = _context(S, wn, base)
+        if ok:
+            ctx.set_launch(2, 8)
+        else:
+            with pytest.raises(S.ScpsError) as e:
+                ctx.set_launch(2, 1)
+            assert e.value.status == -2
+        ctx.close()
     ctx = _context(S, w, dict(w.params), exec_mode=1)       # a fixed exec mode
     with pytest.raises(S.ScpsError) as e:
         ctx.set_launch(2, 4)
