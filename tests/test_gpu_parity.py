@@ -413,7 +413,9 @@ SCPS_CASES = [
     ("bias_only_160_K17_cutoff12", [160], ["all"], 17, 4, True, {"r_cut_contact": 12.0}),
     ("two_systems_K20", [150, 200], ["all", "every3"], 20, 6, False, {}),
     ("smallest_stack_K2", [100], ["all"], 2, 3, False, {}),
+    ("K53_partial_frame_pairs", [120], ["all"], 53, 4, False, {}),
     ("K64_bias_only", [120], ["all"], 64, 5, True, {}),
+    ("K65_one_frame_past_a_block", [100], ["every3"], 65, 3, False, {}),
     ("K72_protocol_frames", [140], ["all"], 72, 5, False, {}),
     ("K128_largest_stack_R36", [110], ["all"], 128, 36, False, {}),
     ("two_systems_K48_K100", [130, 150], ["all", "every3"], [48, 100], 4, True, {}),
