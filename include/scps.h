@@ -99,7 +99,8 @@ typedef struct {
                              BAOAB: v holds the velocity right after the friction/noise substep, so each step is
                              v += dt F/m; x += dt/2 v; v = c1 v + sqrt((1-c1^2) kT/m) xi; x += dt/2 v, c1 = exp(-gamma dt) */
     int32_t bias_mode;    /* SCPS_BIAS_RMD: ratchet on z, eq (FrMD).  SCPS_BIAS_SCPS: ratchets on s, w, eqs (Fw),(Fs) */
-    int32_t exec_mode;    /* SCPS_EXEC_AUTO: one persistent launch per call where a replica fits one workgroup;
+    int32_t exec_mode;    /* SCPS_EXEC_AUTO: one persistent launch per call where a replica fits one workgroup
+                             (chains of at most 32 particles several to a wavefront; see scps_set_launch);
                              SCPS_EXEC_PER_STEP: a few kernel launches per step (always used for SCPS and large chains);
                              with r_cut_contact and r_cut_nb both > 0 in rMD mode, this path evaluates the pairs of
                              per-particle neighbour lists instead of every pair: radius (larger cutoff) + 1.5 A,
