@@ -388,8 +388,8 @@ def bench_chain20(args, torch, I, scps):
     out["nonbonded_pair_evals_per_s"] = value * nb
     kname = {0: "k_rmd_persistent", 1: "k_pairs", 2: "k_rmd_packed"}[path]
     out["roofline"] = roofline(R * args.block * step_flops(con, nb, both), per_ms, kname, None)
-    out["roofline"]["note"] = ("flop counts each pair once; the packed kernel evaluates each pair on both "
-                               "of its lanes")
+    out["roofline"]["note"] = ("flop counts each pair once, as the packed kernel evaluates it (the j side's "
+                               "partials travel between lanes)")
     out["roofline_fp32_unpacked"] = unpacked_view(out["roofline"])
     ctx.close()
     # the CPU-sized configuration as stated: 16 replicas

@@ -100,7 +100,7 @@ typedef struct {
                              v += dt F/m; x += dt/2 v; v = c1 v + sqrt((1-c1^2) kT/m) xi; x += dt/2 v, c1 = exp(-gamma dt) */
     int32_t bias_mode;    /* SCPS_BIAS_RMD: ratchet on z, eq (FrMD).  SCPS_BIAS_SCPS: ratchets on s, w, eqs (Fw),(Fs) */
     int32_t exec_mode;    /* SCPS_EXEC_AUTO: one persistent launch per call where a replica fits one workgroup
-                             (chains of at most 32 particles several to a wavefront; see scps_set_launch);
+                             (short chains one or several to a wavefront; see scps_set_launch);
                              SCPS_EXEC_PER_STEP: a few kernel launches per step (always used for SCPS and large chains);
                              with r_cut_contact and r_cut_nb both > 0 in rMD mode, this path evaluates the pairs of
                              per-particle neighbour lists instead of every pair: radius (larger cutoff) + 1.5 A,
@@ -350,14 +350,26 @@ scps_status scps_autotune(scps_ctx *ctx, const float *x, const float *v, const d
  *           context);
  *   path 2: the packed persistent kernel, param = wavefronts per workgroup
  *           (1 .. 8; every chain of at most 64 particles).
- * Without a call or a tuning, chains of at most 32 particles run packed with
- * four wavefronts per workgroup and longer ones on the persistent kernel
- * where they fit, else per step.  Results differ between configurations
+ * Without a call or a tuning, chains of at most 48 particles (at most 64
+ * from 2048 replicas up) run packed with four wavefronts per workgroup and
+ * longer ones on the persistent kernel where they fit (256 threads per
+ * replica when a chain of at most 128 particles runs fewer than 512
+ * replicas), else per step.  Results differ between configurations
  * only by the order of float32 and float64 additions.  Host only.
  * Errors: INVALID_ARG (unknown path or parameter; paths 0 and 2 of an SCPS
  * context), SHAPE (the chains do not fit the configuration), STATE
  * (exec_mode not AUTO). */
 scps_status scps_set_launch(scps_ctx *ctx, int32_t path, int32_t param);
+
+/* Reports the launch configuration the next scps_step_replicas call takes,
+ * the untuned defaults above resolved:
+ *   launch: host int32[2]; receives {path, parameter} in scps_autotune's
+ *           encoding (path 0: threads per workgroup; path 2: replicas per
+ *           workgroup; path 1: 1 when an SCPS context overlaps the
+ *           nonbonded pass with the distance pass, else 0).  Exec modes
+ *           other than AUTO, and SCPS contexts, report path 1.
+ * Host only.  Errors: INVALID_ARG (NULL ctx or launch), STATE (poisoned). */
+scps_status scps_get_launch(scps_ctx *ctx, int32_t *launch);
 
 /* Convergence measure of the iteration (the paper's Frobenius distance
  * between iterations I and J): the recorded frames of each iteration, projected

@@ -239,12 +239,14 @@ bool usable(scps_ctx *c, scps_status *st) {
     return true;
 }
 
-int pick_wg(int nb) {
+int pick_wg(int nb, int n_replicas) {
     const int ntile = nb * (nb + 1) / 2;
     if (ntile >= 16) return 1024;
     if (ntile >= 8) return 512;
     if (ntile >= 4) return 256;
-    return 64;
+    // a batch too small to give half the SIMDs (256 CUs x 4) a wavefront:
+    // four wavefronts per replica share its tiles
+    return n_replicas < 512 ? 256 : 64;
 }
 
 // Per-tile flags and sub-step masks of a system (see TILE_* in scps_internal.h).
@@ -508,7 +510,7 @@ scps_status init_impl(const scps_params *params, const scps_topology *topo, int3
     }
     c->sumN = c->rep_off[R];
     c->sumNpad = c->rep_poff[R];
-    c->wg = pick_wg(c->n_pad_max / TILE);
+    c->wg = pick_wg(c->n_pad_max / TILE, c->R);
     c->nbk = (p.lj_eps != 0.0 ? 1 : 0) | (p.dh_prefactor != 0.0 ? 2 : 0);
     for (auto &h : c->sys) {
         compute_tile_flags(h, p);
@@ -777,6 +779,25 @@ int max_stack_frames(const scps_ctx *c) {
     return k;
 }
 
+// The launch scps_step_replicas takes: 0 the persistent kernel (c->wg
+// threads per replica), 1 the per-step path, 2 the packed kernel (c->pk_waves
+// wavefronts per workgroup).
+int launch_path(const scps_ctx *c) {
+    if (c->prm.bias_mode == SCPS_BIAS_SCPS || c->prm.exec_mode != SCPS_EXEC_AUTO) return 1;
+    // untuned, short chains run packed (several, or one, per wavefront)
+    if (c->tuned == 2 || (c->tuned == -1 && packed_default(c->n_max, c->R))) return 2;
+    if (c->tuned == 1 || c->n_pad_max > persistent_max_npad(c->wg)) return 1;
+    return 0;
+}
+
+// {path, parameter} as scps_autotune and scps_get_launch report them.
+void launch_report(const scps_ctx *c, int path, int32_t *out) {
+    out[0] = path;
+    out[1] = path == 0   ? c->wg
+             : path == 2 ? c->pk_waves * (64 / c->n_max)
+                         : (c->prm.bias_mode == SCPS_BIAS_SCPS && c->overlap_nb ? 1 : 0);
+}
+
 scps_status step_impl(scps_ctx *c, float *x, float *v, double *cv, int64_t n_steps, uint64_t step0,
                       int32_t record_every, float *frames) {
     if (!x || !cv) return fail(SCPS_ERR_INVALID_ARG, "x and cvstate must not be NULL");
@@ -791,18 +812,14 @@ scps_status step_impl(scps_ctx *c, float *x, float *v, double *cv, int64_t n_ste
         if (scps && h.K < 2) return fail(SCPS_ERR_STATE, "SCPS mode needs a frame stack of >= 2 maps");
     }
     const int64_t frame_stride = 3 * c->sumN;
-    const bool autoexec = !scps && c->prm.exec_mode == SCPS_EXEC_AUTO;
-    // untuned, chains of at most 32 particles run packed, several per wavefront
-    if (autoexec && (c->tuned == 2 || (c->tuned == -1 && packed_default(c->n_max)))) {
+    const int path = launch_path(c);
+    if (path == 2) {
         HIP_TRY(c, launch_packed_rmd(c->pk_waves, c->nbk, c->kp, c->d_sysd, c->d_reps, c->R, c->n_max, x, v, cv,
                                      n_steps, step0, record_every, frames, frame_stride, c->d_flags, c->stream));
         return SCPS_OK;
     }
-    bool persistent = autoexec && c->tuned != 1;
-    const int wg = c->wg;
-    if (persistent && c->n_pad_max > persistent_max_npad(wg)) persistent = false;
-    if (persistent) {
-        HIP_TRY(c, launch_persistent_rmd(wg, c->nbk, c->kp, c->d_sysd, c->d_reps, c->d_order, c->R, c->n_pad_max, x, v, cv,
+    if (path == 0) {
+        HIP_TRY(c, launch_persistent_rmd(c->wg, c->nbk, c->kp, c->d_sysd, c->d_reps, c->d_order, c->R, c->n_pad_max, x, v, cv,
                                          n_steps, step0, record_every, frames, frame_stride, c->d_flags,
                                          c->stream));
         return SCPS_OK;
@@ -1129,12 +1146,7 @@ scps_status autotune_impl(scps_ctx *c, const float *x, const float *v, const dou
     c->wg = c->tuned == 0 ? cand[best_i].wg : saved_wg;
     c->pk_waves = c->tuned == 2 ? cand[best_i].wg : saved_pk;
     c->overlap_nb = scps ? cand[best_i].overlap : saved_overlap;
-    if (chosen) {
-        chosen[0] = c->tuned;
-        chosen[1] = c->tuned == 0   ? c->wg
-                    : c->tuned == 2 ? c->pk_waves * (64 / c->n_max)
-                                    : (scps && c->overlap_nb ? 1 : 0);
-    }
+    if (chosen) launch_report(c, c->tuned, chosen);
     return SCPS_OK;
 }
 
@@ -1240,6 +1252,14 @@ scps_status scps_set_launch(scps_ctx *ctx, int32_t path, int32_t param) {
     scps_status st;
     if (!usable(ctx, &st)) return st;
     return set_launch_impl(ctx, path, param);
+}
+
+scps_status scps_get_launch(scps_ctx *ctx, int32_t *launch) {
+    scps_status st;
+    if (!usable(ctx, &st)) return st;
+    if (!launch) return fail(SCPS_ERR_INVALID_ARG, "launch must not be NULL");
+    launch_report(ctx, launch_path(ctx), launch);
+    return SCPS_OK;
 }
 
 scps_status scps_least_biased_path(scps_ctx *ctx, const double *cvstate, const uint8_t *success, int32_t *index,

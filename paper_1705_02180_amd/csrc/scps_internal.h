@@ -137,7 +137,7 @@ hipError_t launch_persistent_rmd(int wg, int nbk, const KParams &P, const SysDes
 // per workgroup, all n_steps in one launch; the untuned default for chains that
 // pack at least two to a wavefront.
 int packed_width_ok(int n_max);
-int packed_default(int n_max);
+int packed_default(int n_max, int n_replicas);
 hipError_t launch_packed_rmd(int waves, int nbk, const KParams &P, const SysDesc *sysd, const RepDesc *reps, int R,
                              int n_max, float *x, float *v, double *cv, int64_t n_steps, uint64_t step0,
                              int record_every, float *frames, int64_t frame_stride, int *flags, hipStream_t st);

@@ -753,11 +753,13 @@ hipError_t launch_persistent_rmd(int wg, int nbk, const KParams &P, const SysDes
 // wavefronts, and the kernel runs all n_steps of every replica it holds.
 // Each wavefront works alone on its own part of LDS (no workgroup barrier):
 // the lanes publish their positions each step and read their partners'.
-// Pair terms are evaluated on both lanes of a pair, lane a accumulating only
-// its own force (no cross-lane partials), partner b = (a + k) mod n at step
-// k = 1 .. n - 1; z, counted twice that way, is halved.  Float32 pair math over
-// at most 63 partners per lane, then float64 per particle, as in the tile
-// kernels; bonds, the ratchet and the Langevin update in float64.  Segment
+// Every pair is evaluated once: lane a meets b = (a + k) mod n at step
+// k = 1 .. n/2 (even n: lanes a < n/2 only at the last step), adds its own
+// side and keeps b's side in j-side partials that move one lane back within
+// the segment after each step and reach their owner lane at the end.
+// Float32 pair math over at most 32 steps per lane, then float64 per particle,
+// as in the tile kernels; bonds, the ratchet and the Langevin update in
+// float64.  Segment
 // sums (z each step, T at the end) run over the segment's lanes in a fixed
 // order, so every lane of a replica holds the same z.
 constexpr int PACK_WMAX = 64;
@@ -770,11 +772,12 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// LDS of one wavefront: positions (x, y, z, charge), chain indices, the
-// lane's native-map value at every partner step, a reduction row and the
-// chain predecessors.
+// LDS of one wavefront: positions (x, y, z, charge), chain indices, a
+// reduction row, the chain predecessors and the lane's native-map value at
+// every partner step (rows 1 .. W/2; row 0 unused).
 __host__ __device__ inline size_t packed_wave_lds_bytes(int W) {
-    return 64 * (sizeof(float4) + sizeof(int) + sizeof(double) + sizeof(int)) + (size_t)W * 64 * sizeof(float);
+    return 64 * (sizeof(float4) + sizeof(int) + sizeof(double) + sizeof(int)) +
+           (size_t)(W / 2 + 1) * 64 * sizeof(float);
 }
 
 template <int NBK>
@@ -792,7 +795,7 @@ __global__ __launch_bounds__(512) void k_rmd_packed(const KParams P, const SysDe
     int *orgl = reinterpret_cast<int *>(posl + 64);                 // [64]
     double *redl = reinterpret_cast<double *>(orgl + 64);          // [64]
     int *prevl = reinterpret_cast<int *>(redl + 64);               // [64]
-    float *refl = reinterpret_cast<float *>(prevl + 64);           // [W][64]: R(a, partner at step k)
+    float *refl = reinterpret_cast<float *>(prevl + 64);           // [W/2 + 1][64]: R(a, partner at step k)
 
     const int PR = 64 / W;                           // replicas per wavefront
     const int seg = lane / W, a = lane - seg * W, sbase = seg * W;
@@ -831,7 +834,7 @@ __global__ __launch_bounds__(512) void k_rmd_packed(const KParams P, const SysDe
     wave_lds_sync();
     if (act && nxt >= 0) prevl[sbase + nxt] = a;
     // native-map value of the pair met at partner step k (0 outside the contact set)
-    for (int k = 1; k < W; ++k) {
+    for (int k = 1; k <= (W >> 1); ++k) {
         float rv = 0.f;
         if (icon && k < n) {
             const int b = a + k < n ? a + k : a + k - n;
@@ -850,6 +853,14 @@ __global__ __launch_bounds__(512) void k_rmd_packed(const KParams P, const SysDe
     }
     double tsum = 0.0;
     bool bad = false;
+    // the step loop's partner schedule: this segment's last step, the widest
+    // segment's, the lane each step's j partials come from ((a + 1) mod n) and
+    // the lane holding this particle's partials at the end ((a - kend - 1) mod n)
+    const int kend = n >> 1, kend_max = W >> 1;
+    const int rot_from = (act ? sbase + (a + 1 < n ? a + 1 : 0) : lane) << 2;
+    int home = a - kend - 1 + n;
+    home = home >= n ? home - n : home;
+    const int home_from = (act ? sbase + home : lane) << 2;
     const double c1 = P.c1;
     // the sum over the lanes of this lane's segment, in lane order
     auto seg_sum = [&](double val) {
@@ -871,10 +882,16 @@ __global__ __launch_bounds__(512) void k_rmd_packed(const KParams P, const SysDe
         if (m == n_steps) break;
         posl[lane] = p;
         wave_lds_sync();
-        // ---- pair phase ----------------------------------------------------
-        float fn[3] = {0.f, 0.f, 0.f}, fg[3] = {0.f, 0.f, 0.f}, zt = 0.f;
-        for (int k = 1; k < W; ++k) {
-            const bool pv = act && k < n;
+        // ---- pair phase: every pair once.  Lane a meets b = (a + k) mod n at
+        // step k = 1 .. n/2 (for even n only lanes a < n/2 at k = n/2); its
+        // j-side partials belong to particle (a + k) mod n and move one lane
+        // back within the segment after each step (ds_bpermute: segments are
+        // not DPP rows), and go to their owner lane at the end.
+        float fn[3] = {0.f, 0.f, 0.f}, fg[3] = {0.f, 0.f, 0.f}, jn[3] = {0.f, 0.f, 0.f},
+              jg[3] = {0.f, 0.f, 0.f}, zt = 0.f;
+        for (int k = 1; k <= kend_max; ++k) {
+            const bool step = act && k <= kend;
+            const bool pv = step && (2 * k < n || a < kend);
             const int b = a + k < n ? a + k : a + k - n;
             const int bl = pv ? sbase + b : lane;
             const float4 pj = posl[bl];
@@ -888,6 +905,9 @@ __global__ __launch_bounds__(512) void k_rmd_packed(const KParams P, const SysDe
                 fn[0] = fmaf(f, dx, fn[0]);
                 fn[1] = fmaf(f, dy, fn[1]);
                 fn[2] = fmaf(f, dz, fn[2]);
+                jn[0] = fmaf(-f, dx, jn[0]);
+                jn[1] = fmaf(-f, dy, jn[1]);
+                jn[2] = fmaf(-f, dz, jn[2]);
             }
             const bool con = pv & icon & (b < S.nc) & (sep > P.min_sep);
             const bool inside = !P.has_cut | (r2 <= P.r_cut2);   // beyond a cutoff C = 0 (R still counts)
@@ -905,6 +925,21 @@ __global__ __launch_bounds__(512) void k_rmd_packed(const KParams P, const SysDe
             fg[0] = fmaf(g, dx, fg[0]);
             fg[1] = fmaf(g, dy, fg[1]);
             fg[2] = fmaf(g, dz, fg[2]);
+            jg[0] = fmaf(-g, dx, jg[0]);
+            jg[1] = fmaf(-g, dy, jg[1]);
+            jg[2] = fmaf(-g, dz, jg[2]);
+            const int from = step ? rot_from : (lane << 2);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                if constexpr (NBK != 0) jn[c] = __int_as_float(__builtin_amdgcn_ds_bpermute(from, __float_as_int(jn[c])));
+                jg[c] = __int_as_float(__builtin_amdgcn_ds_bpermute(from, __float_as_int(jg[c])));
+            }
+        }
+        // lane a now holds the j-side partials of particle (a + kend + 1) mod n
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            if constexpr (NBK != 0) fn[c] += __int_as_float(__builtin_amdgcn_ds_bpermute(home_from, __float_as_int(jn[c])));
+            fg[c] += __int_as_float(__builtin_amdgcn_ds_bpermute(home_from, __float_as_int(jg[c])));
         }
         double F[3] = {(double)fn[0], (double)fn[1], (double)fn[2]};
         if (P.has_bond) {
@@ -919,7 +954,7 @@ __global__ __launch_bounds__(512) void k_rmd_packed(const KParams P, const SysDe
             }
         }
         // ---- ratchet, eq (FrMD): z_m updated before the force is used ----
-        const double z = 0.5 * seg_sum((double)zt);
+        const double z = seg_sum((double)zt);
         zm = fmin(zm, z);
         const double dzr = z - zm;
         const double scale = -P.k_R * dzr;
@@ -981,8 +1016,12 @@ __global__ __launch_bounds__(512) void k_rmd_packed(const KParams P, const SysDe
 }
 
 int packed_width_ok(int n_max) { return n_max >= 2 && n_max <= PACK_WMAX; }
-// without tuning, chains that pack at least two to a wavefront
-int packed_default(int n_max) { return packed_width_ok(n_max) && n_max <= PACK_WMAX / 2; }
+// Without tuning: chains of up to 48 particles (one replica per wavefront at
+// most 3/4 full still beats a 64-lane persistent tile, which pads to 64), and
+// up to 64 once the batch gives every SIMD (256 CUs x 4) two wavefronts.
+int packed_default(int n_max, int n_replicas) {
+    return packed_width_ok(n_max) && (4 * n_max <= 3 * PACK_WMAX || n_replicas >= 2048);
+}
 
 hipError_t launch_packed_rmd(int waves, int nbk, const KParams &P, const SysDesc *sysd, const RepDesc *reps, int R,
                              int n_max, float *x, float *v, double *cv, int64_t n_steps, uint64_t step0,

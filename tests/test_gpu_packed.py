@@ -234,6 +234,41 @@ def test_packed_is_the_default_for_short_chains_and_autotune_keeps_results(S):
     assert np.abs(host(x) - untuned[0]).max() <= 1e-4 * disp
 
 
+def test_untuned_launch_defaults(S):
+    """get_launch reports what step_replicas takes: untuned, chains of at most
+    48 particles run packed (four wavefronts per workgroup, floor(64/n)
+    replicas each), 49 .. 64 from 2048 replicas up; longer chains, or smaller
+    batches, take the persistent kernel, with 256 threads per replica below
+    512 replicas of a chain of at most 128 particles; set_launch, other exec
+    modes and SCPS contexts are reported as they run.  A 40-particle untuned
+    run is the packed launch bit for bit."""
+    base = dict(I._base_params())
+    for n, R, want in ((20, 48, (2, 12)), (33, 16, (2, 4)), (48, 5, (2, 4)), (49, 16, (0, 256)),
+                       (64, 600, (0, 64)), (64, 2048, (2, 4)), (65, 16, (0, 256)), (128, 511, (0, 256)),
+                       (128, 512, (0, 64))):
+        w = I.Workload("d", dict(base), [_system(n, "all", 3)], np.zeros(R, dtype=np.int32), 1)
+        ctx = _context(S, w, base)
+        assert ctx.get_launch() == want, (n, R)
+        if n == 20:
+            for launch, got in (((0, 512), (0, 512)), ((1, 0), (1, 0)), ((2, 1), (2, 3))):
+                ctx.set_launch(*launch)
+                assert ctx.get_launch() == got, launch
+        ctx.close()
+    wl = I.config2(n_replicas=2, n_steps=1)                   # 560 particles: 45 tiles, 1024 threads
+    ctx = _context(S, wl, dict(wl.params))
+    assert ctx.get_launch() == (0, 1024)
+    ctx.close()
+    w = I.Workload("d", dict(base), [_system(20, "all", 3)], np.zeros(4, dtype=np.int32), 1)
+    ctx = _context(S, w, base, exec_mode=1)
+    assert ctx.get_launch() == (1, 0)
+    ctx.close()
+    w = I.Workload("d", dict(base), [_system(40, "all", 4)], np.zeros(8, dtype=np.int32), 1)
+    x0 = w.initial_x()
+    untuned = _run(S, w, base, None, 0, x0, np.zeros_like(x0), 10)
+    packed = _run(S, w, base, (2, 4), 0, x0, np.zeros_like(x0), 10)
+    assert np.array_equal(untuned[0], packed[0]) and np.array_equal(untuned[2], packed[2])
+
+
 def test_set_launch_validation(S):
     """set_launch accepts the configurations that fit and rejects the rest."""
     w = I.config1(n_replicas=4, n_steps=1)
