@@ -29,9 +29,10 @@ __device__ __forceinline__ float pair_r2(const float4 &pi, const float4 &pj, flo
 __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
-        const uint32_t a = c[0], b = c[2];
-        const uint32_t hi0 = __umulhi(0xD2511F53u, a), lo0 = 0xD2511F53u * a;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, b), lo1 = 0xCD9E8D57u * b;
+        // one 32 x 32 -> 64-bit product per word gives both halves (v_mad_u64_u32)
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c[0], p1 = (uint64_t)0xCD9E8D57u * c[2];
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
         c[0] = hi1 ^ c[1] ^ k0;
         c[1] = lo1;
         c[2] = hi0 ^ c[3] ^ k1;

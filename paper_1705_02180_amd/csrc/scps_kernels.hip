@@ -435,8 +435,8 @@ __device__ __forceinline__ void bond_force(const KParams &P, float4 pa, float4 p
     const double dx = (double)pa.x - (double)pb.x;
     const double dy = (double)pa.y - (double)pb.y;
     const double dz = (double)pa.z - (double)pb.z;
-    const double r = sqrt(dx * dx + dy * dy + dz * dz);
-    const double s = -P.k_bond * (r - P.r_bond) / r;
+    // -k (r - r0) / r as k (r0 / r - 1): one float64 reciprocal square root, no division
+    const double s = P.k_bond * (P.r_bond * rsqrt(dx * dx + dy * dy + dz * dz) - 1.0);
     f[0] = s * dx;
     f[1] = s * dy;
     f[2] = s * dz;
@@ -759,9 +759,9 @@ hipError_t launch_persistent_rmd(int wg, int nbk, const KParams &P, const SysDes
 // the segment after each step and reach their owner lane at the end.
 // Float32 pair math over at most 32 steps per lane, then float64 per particle,
 // as in the tile kernels; bonds, the ratchet and the Langevin update in
-// float64.  Segment
-// sums (z each step, T at the end) run over the segment's lanes in a fixed
-// order, so every lane of a replica holds the same z.
+// float64.  Segment sums (z each step, T at the end) run as a fixed binary
+// tree over the segment's lanes (ds_bpermute) whose total the first lane
+// hands to the others, so every lane of a replica holds the same z.
 constexpr int PACK_WMAX = 64;
 
 // Lanes of one wavefront exchanging values through LDS: what the lanes stored
@@ -772,12 +772,18 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// LDS of one wavefront: positions (x, y, z, charge), chain indices, a
-// reduction row, the chain predecessors and the lane's native-map value at
-// every partner step (rows 1 .. W/2; row 0 unused).
+// a double from the lane whose byte address (4 x lane) is given
+__device__ __forceinline__ double bpermute_f64(int from, double v) {
+    const int lo = __builtin_amdgcn_ds_bpermute(from, __double2loint(v));
+    const int hi = __builtin_amdgcn_ds_bpermute(from, __double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
+// LDS of one wavefront: positions (x, y, z, charge), chain indices, the
+// chain predecessors and the lane's native-map value at every partner step
+// (rows 1 .. W/2; row 0 unused).
 __host__ __device__ inline size_t packed_wave_lds_bytes(int W) {
-    return 64 * (sizeof(float4) + sizeof(int) + sizeof(double) + sizeof(int)) +
-           (size_t)(W / 2 + 1) * 64 * sizeof(float);
+    return 64 * (sizeof(float4) + sizeof(int) + sizeof(int)) + (size_t)(W / 2 + 1) * 64 * sizeof(float);
 }
 
 template <int NBK>
@@ -793,8 +799,7 @@ __global__ __launch_bounds__(512) void k_rmd_packed(const KParams P, const SysDe
     unsigned char *wl = smem + (size_t)wave * packed_wave_lds_bytes(W);
     float4 *posl = reinterpret_cast<float4 *>(wl);                 // [64]
     int *orgl = reinterpret_cast<int *>(posl + 64);                 // [64]
-    double *redl = reinterpret_cast<double *>(orgl + 64);          // [64]
-    int *prevl = reinterpret_cast<int *>(redl + 64);               // [64]
+    int *prevl = orgl + 64;                                          // [64]
     float *refl = reinterpret_cast<float *>(prevl + 64);           // [W/2 + 1][64]: R(a, partner at step k)
 
     const int PR = 64 / W;                           // replicas per wavefront
@@ -862,15 +867,21 @@ __global__ __launch_bounds__(512) void k_rmd_packed(const KParams P, const SysDe
     home = home >= n ? home - n : home;
     const int home_from = (act ? sbase + home : lane) << 2;
     const double c1 = P.c1;
-    // the sum over the lanes of this lane's segment, in lane order
+    // the particle's update constants (overdamped: mobility dt / (m gamma) and
+    // noise amplitude sqrt(2 kT mob); BAOAB: sqrt((1 - c1^2) kT / m))
+    const double mob = P.dt * inv_m / P.gamma;
+    const double amp = P.integrator == 0 ? sqrt(2.0 * P.kT * mob) : sqrt((1.0 - c1 * c1) * P.kT * inv_m);
+    // the sum over the lanes of this lane's segment: a binary tree in a fixed
+    // order (lane a takes a + s for s = 1, 2, 4, ... while a is a multiple of
+    // 2s), then the segment's first lane's total to every lane, so that all
+    // lanes of a replica hold the same value
     auto seg_sum = [&](double val) {
-        redl[lane] = val;
-        wave_lds_sync();
-        double t = 0.0;
-        for (int e = 0; e < W; ++e)
-            if (e < n) t += redl[sbase + e];
-        wave_lds_sync();
-        return t;
+        for (int s = 1; s < W; s <<= 1) {
+            const bool take = ((a & (2 * s - 1)) == 0) && a + s < n;
+            const double o = bpermute_f64((take ? lane + s : lane) << 2, val);
+            val = take ? val + o : val;
+        }
+        return bpermute_f64(sbase << 2, val);
     };
     for (int64_t m = 0;; ++m) {
         if (record_every > 0 && frames && (m % record_every) == 0 && act) {
@@ -943,14 +954,15 @@ __global__ __launch_bounds__(512) void k_rmd_packed(const KParams P, const SysDe
         }
         double F[3] = {(double)fn[0], (double)fn[1], (double)fn[2]};
         if (P.has_bond) {
-            double f[3];
-            if (nxt >= 0) {
-                bond_force(P, p, posl[sbase + nxt], f);
-                for (int c = 0; c < 3; ++c) F[c] += f[c];
-            }
-            if (prv >= 0) {
-                bond_force(P, p, posl[sbase + prv], f);
-                for (int c = 0; c < 3; ++c) F[c] += f[c];
+            // each bond once, by the lane of its first particle; the second
+            // particle's lane takes the opposite force from it
+            double f[3] = {0.0, 0.0, 0.0};
+            if (nxt >= 0) bond_force(P, p, posl[sbase + nxt], f);
+            const int from = (prv >= 0 ? sbase + prv : lane) << 2;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double g = bpermute_f64(from, f[c]);
+                F[c] += prv >= 0 ? f[c] - g : f[c];
             }
         }
         // ---- ratchet, eq (FrMD): z_m updated before the force is used ----
@@ -974,12 +986,9 @@ __global__ __launch_bounds__(512) void k_rmd_packed(const KParams P, const SysDe
             normals3(P, (uint32_t)o, P.rep_base + (uint32_t)r, step0 + (uint64_t)m, gn[0], gn[1], gn[2]);
             double X[3] = {(double)p.x, (double)p.y, (double)p.z};
             if (P.integrator == 0) {
-                const double mob = P.dt * inv_m / P.gamma;
-                const double amp = sqrt(2.0 * P.kT * mob);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) X[c] += mob * F[c] + amp * gn[c];
             } else {
-                const double amp = sqrt((1.0 - c1 * c1) * P.kT * inv_m);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     double u = (double)vel[c] + P.dt * F[c] * inv_m;
