@@ -858,13 +858,30 @@ __global__ __launch_bounds__(512) void k_rmd_packed(const KParams P, const SysDe
     }
     double tsum = 0.0;
     bool bad = false;
-    // the step loop's partner schedule: this segment's last step, the widest
-    // segment's, the lane each step's j partials come from ((a + 1) mod n) and
-    // the lane holding this particle's partials at the end ((a - kend - 1) mod n)
+    // the step loop's partner schedule, fixed for the call: bit k - 1 of
+    // nbmask / cmask is set when the pair (a, (a + k) mod n) is met at partner
+    // step k (this segment's steps 1 .. n/2; for even n, at k = n/2 only by the
+    // lanes a < n/2) and counts in the nonbonded sum (beyond nb_excl in
+    // sequence) / in the contact set (both particles in it, beyond min_sep)
     const int kend = n >> 1, kend_max = W >> 1;
-    const int rot_from = (act ? sbase + (a + 1 < n ? a + 1 : 0) : lane) << 2;
-    int home = a - kend - 1 + n;
-    home = home >= n ? home - n : home;
+    uint32_t nbmask = 0u, cmask = 0u;
+    for (int k = 1; k <= kend_max; ++k) {
+        if (act && k <= kend && (2 * k < n || a < kend)) {
+            const int b = a + k < n ? a + k : a + k - n;
+            const int sep = abs(o - orgl[sbase + b]);
+            if (sep > P.nb_excl) nbmask |= 1u << (k - 1);
+            if (icon && b < S.nc && sep > P.min_sep) cmask |= 1u << (k - 1);
+        }
+    }
+    // the partner's lane at step 1 and its wrap, the lane each step's j
+    // partials come from ((a + 1) mod n: every lane rotates at every step of
+    // the widest segment) and the lane holding this particle's partials at the
+    // end ((a - kend_max - 1) mod n); lanes without a particle stay on themselves
+    const int bl1 = act ? sbase + (a + 1 < n ? a + 1 : 0) : lane;
+    const int bl_inc = act ? 1 : 0, bl_wrap = act ? sbase + n : -1;
+    const int rot_from = bl1 << 2;
+    int home = act ? (a - kend_max - 1) % n : 0;
+    home = home < 0 ? home + n : home;
     const int home_from = (act ? sbase + home : lane) << 2;
     const double c1 = P.c1;
     // the particle's update constants (overdamped: mobility dt / (m gamma) and
@@ -900,17 +917,16 @@ __global__ __launch_bounds__(512) void k_rmd_packed(const KParams P, const SysDe
         // not DPP rows), and go to their owner lane at the end.
         float fn[3] = {0.f, 0.f, 0.f}, fg[3] = {0.f, 0.f, 0.f}, jn[3] = {0.f, 0.f, 0.f},
               jg[3] = {0.f, 0.f, 0.f}, zt = 0.f;
+        int bl = bl1;
         for (int k = 1; k <= kend_max; ++k) {
-            const bool step = act && k <= kend;
-            const bool pv = step && (2 * k < n || a < kend);
-            const int b = a + k < n ? a + k : a + k - n;
-            const int bl = pv ? sbase + b : lane;
+            const uint32_t bit = 1u << (k - 1);
             const float4 pj = posl[bl];
             float dx, dy, dz;
             const float r2 = pair_r2(p, pj, dx, dy, dz);
-            const int sep = abs(o - orgl[bl]);
+            bl += bl_inc;
+            bl = bl == bl_wrap ? sbase : bl;
             if constexpr (NBK != 0) {
-                const bool nbon = pv & (sep > P.nb_excl) & (!P.has_cut_nb | (r2 <= P.r_cut_nb2));
+                const bool nbon = ((nbmask & bit) != 0u) & (!P.has_cut_nb | (r2 <= P.r_cut_nb2));
                 const float fs = nb_scalar<NBK>(P, r2, qp, pj.w);
                 const float f = nbon ? fs : 0.f;
                 fn[0] = fmaf(f, dx, fn[0]);
@@ -920,7 +936,7 @@ __global__ __launch_bounds__(512) void k_rmd_packed(const KParams P, const SysDe
                 jn[1] = fmaf(-f, dy, jn[1]);
                 jn[2] = fmaf(-f, dz, jn[2]);
             }
-            const bool con = pv & icon & (b < S.nc) & (sep > P.min_sep);
+            const bool con = (cmask & bit) != 0u;
             const bool inside = !P.has_cut | (r2 <= P.r_cut2);   // beyond a cutoff C = 0 (R still counts)
             const float q = r2 * P.inv_r0sq;
             const float q2 = q * q;
@@ -939,14 +955,14 @@ __global__ __launch_bounds__(512) void k_rmd_packed(const KParams P, const SysDe
             jg[0] = fmaf(-g, dx, jg[0]);
             jg[1] = fmaf(-g, dy, jg[1]);
             jg[2] = fmaf(-g, dz, jg[2]);
-            const int from = step ? rot_from : (lane << 2);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                if constexpr (NBK != 0) jn[c] = __int_as_float(__builtin_amdgcn_ds_bpermute(from, __float_as_int(jn[c])));
-                jg[c] = __int_as_float(__builtin_amdgcn_ds_bpermute(from, __float_as_int(jg[c])));
+                if constexpr (NBK != 0)
+                    jn[c] = __int_as_float(__builtin_amdgcn_ds_bpermute(rot_from, __float_as_int(jn[c])));
+                jg[c] = __int_as_float(__builtin_amdgcn_ds_bpermute(rot_from, __float_as_int(jg[c])));
             }
         }
-        // lane a now holds the j-side partials of particle (a + kend + 1) mod n
+        // lane a now holds the j-side partials of particle (a + kend_max + 1) mod n
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             if constexpr (NBK != 0) fn[c] += __int_as_float(__builtin_amdgcn_ds_bpermute(home_from, __float_as_int(jn[c])));
