@@ -33,9 +33,10 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32
         const uint64_t p0 = (uint64_t)0xD2511F53u * c[0], p1 = (uint64_t)0xCD9E8D57u * c[2];
         const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
         const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
-        c[0] = hi1 ^ c[1] ^ k0;
+        // three-input XORs, one v_bitop3_b32 each (truth table 0x96)
+        c[0] = __builtin_amdgcn_bitop3_b32(hi1, c[1], k0, 0x96);
         c[1] = lo1;
-        c[2] = hi0 ^ c[3] ^ k1;
+        c[2] = __builtin_amdgcn_bitop3_b32(hi0, c[3], k1, 0x96);
         c[3] = lo0;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
