@@ -208,7 +208,7 @@ def test_packed_trajectories_agree_with_other_launches(S, integrator):
 
 
 def test_packed_is_the_default_for_short_chains_and_autotune_keeps_results(S):
-    """An untuned context runs chains of at most 32 particles packed; the
+    """An untuned context runs 20-particle chains packed; the
     autotuner's choice (any of the packed, persistent and per-step
     configurations) gives the same trajectory up to summation order, and
     the caller's state is untouched by the trial runs."""
