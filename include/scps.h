@@ -361,6 +361,22 @@ scps_status scps_autotune(scps_ctx *ctx, const float *x, const float *v, const d
  * (exec_mode not AUTO). */
 scps_status scps_set_launch(scps_ctx *ctx, int32_t path, int32_t param);
 
+/* Steps per captured HIP graph on the per-step path (SCPS contexts, and rMD
+ * chains too long for the persistent kernel): whole blocks of `steps` steps
+ * replay one graph of their kernel launches, captured on first use for the
+ * cvstate buffer of the call (again when that buffer, the largest frame stack
+ * or `steps` changes).  The noise is that of the same steps launched one by
+ * one.  Steps run launch by launch where a block does not fit (before a
+ * recorded frame or the end of a call) and with neighbour lists, the
+ * overlapped SCPS schedule or pass timing.
+ *   steps: 0 (no graphs, the default) .. SCPS_MAX_GRAPH_STEPS.  Measured
+ *   on MI355X with ROCm 7.2, a replayed step is not faster than the same
+ *   kernels launched one by one, and on steps of a few microseconds slower.
+ * Synchronises the stream when the value changes.  Host only.
+ * Errors: INVALID_ARG (NULL ctx, steps out of range), STATE (poisoned), HIP. */
+#define SCPS_MAX_GRAPH_STEPS 256
+scps_status scps_set_graph_steps(scps_ctx *ctx, int32_t steps);
+
 /* Reports the launch configuration the next scps_step_replicas call takes,
  * the untuned defaults above resolved:
  *   launch: host int32[2]; receives {path, parameter} in scps_autotune's

@@ -67,6 +67,15 @@ struct scps_ctx {
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     bool overlap_nb = false;          // SCPS: nonbonded pass beside the distance pass (scps_autotune may turn it on)
     hipEvent_t ev_switch = nullptr;   // orders a new stream after the old one (scps_set_stream)
+    // per-step path: whole blocks of graph_steps steps replay one captured
+    // HIP graph (scps_set_graph_steps; 0, the default: every kernel launched
+    // on its own)
+    int graph_steps = 0;
+    hipStream_t cap = nullptr;        // private stream the graph is captured on
+    hipGraphExec_t gexec = nullptr;
+    const double *g_cv = nullptr;     // what the graph was captured for
+    int g_frames = 0, g_steps = 0;
+    uint64_t *d_step = nullptr;       // the replayed block's first step
     // scps_time_passes: HIP events around the SCPS step's two stack passes, in a ring
     // of PASS_RING slots (4 events each) whose oldest slot is read back before reuse
     static constexpr int PASS_RING = 256;
@@ -798,6 +807,108 @@ void launch_report(const scps_ctx *c, int path, int32_t *out) {
                          : (c->prm.bias_mode == SCPS_BIAS_SCPS && c->overlap_nb ? 1 : 0);
 }
 
+// The kernel launches of one step of the per-step path (all tile pairs for
+// rMD; the SCPS passes), on stream st, the update drawing its noise for step
+// step (+ *step_base when given).  eager: the overlapped SCPS schedule and
+// pass timing may be used (never while a graph is being captured).
+scps_status step_launches(scps_ctx *c, double *cv, uint64_t step, const uint64_t *step_base, bool eager,
+                          hipStream_t st) {
+    if (c->prm.bias_mode != SCPS_BIAS_SCPS) {
+        HIP_TRY(c, launch_pairs(0, c->nbk, c->kp, c->d_sysd, c->d_reps, c->d_items_all, c->n_items_all, c->d_xs,
+                                c->d_acc, c->d_zpart, nullptr, nullptr, st));
+        HIP_TRY(c, launch_finalize_rmd(c->kp, c->R, c->d_first_all, c->d_zpart, nullptr, cv, c->d_scale, st));
+        HIP_TRY(c, launch_integrate(c->kp, c->d_sysd, c->d_reps, c->R, c->n_pad_max, c->d_xs, c->d_vs, c->d_acc,
+                                    c->d_scale, cv, step, step_base, c->d_flags, st));
+        return SCPS_OK;
+    }
+    // distances to every frame (matrix cores), tube variables and ratchets,
+    // effective references (matrix cores), bias + physics
+    const bool overlap = eager && c->side && c->overlap_nb;
+    if (overlap) {
+        // nonbonded forces (acc components 0..2) need only the positions:
+        // they overlap the bandwidth-bound distance pass
+        HIP_TRY(c, hipEventRecord(c->ev_fork, st));
+        HIP_TRY(c, hipStreamWaitEvent(c->side, c->ev_fork, 0));
+        HIP_TRY(c, launch_pairs(4, c->nbk, c->kp, c->d_sysd, c->d_reps, c->d_items_all, c->n_items_all, c->d_xs,
+                                c->d_acc, c->d_zpart, nullptr, nullptr, c->side));
+        HIP_TRY(c, hipEventRecord(c->ev_join, c->side));
+    }
+    hipEvent_t *tev = nullptr;
+    if (eager) {
+        scps_status tst;
+        tev = pass_slot(c, &tst);
+        if (tst != SCPS_OK) return tst;
+    }
+    if (tev) HIP_TRY(c, hipEventRecord(tev[0], st));
+    HIP_TRY(c, launch_scps_dist(c->kp, c->d_sysd, c->d_reps, c->d_groups, c->d_sitems, c->n_sitems,
+                                max_stack_frames(c), c->d_jref, c->d_xs, c->d_X, c->d_Q, c->kmax, -1, st));
+    if (tev) HIP_TRY(c, hipEventRecord(tev[1], st));
+    HIP_TRY(c, launch_finalize_scps(c->kp, c->d_sysd, c->d_reps, c->R, c->kmax, c->d_jref, c->d_X, c->d_Q, cv,
+                                    c->d_coef, c->d_csum, st));
+    if (tev) HIP_TRY(c, hipEventRecord(tev[2], st));
+    if (c->prm.exec_mode == SCPS_EXEC_PER_STEP_ALL_TILES) {
+        // two passes: effective references to device memory, then every tile pair
+        HIP_TRY(c, launch_scps_eff(c->d_sysd, c->d_reps, c->d_groups, c->d_sitems, c->n_sitems, c->d_coef, c->kmax,
+                                   c->d_E, st));
+        HIP_TRY(c, launch_pairs(3, c->nbk, c->kp, c->d_sysd, c->d_reps, c->d_items_all, c->n_items_all, c->d_xs,
+                                c->d_acc, c->d_zpart, c->d_E, c->d_csum, st));
+        if (tev) HIP_TRY(c, hipEventRecord(tev[3], st));
+    } else {
+        // the effective references and the bias in one pass over the contact tiles;
+        // the nonbonded forces and bonds (mode 4, every tile pair) after it, or
+        // joined from the side stream
+        HIP_TRY(c, launch_scps_bias(c->kp, c->d_sysd, c->d_reps, c->d_groups, c->d_sitems, c->n_sitems,
+                                    max_stack_frames(c), c->d_xs, c->d_coef, c->d_csum, c->kmax, c->d_acc, st));
+        if (tev) HIP_TRY(c, hipEventRecord(tev[3], st));
+        if (overlap)
+            HIP_TRY(c, hipStreamWaitEvent(st, c->ev_join, 0));
+        else
+            HIP_TRY(c, launch_pairs(4, c->nbk, c->kp, c->d_sysd, c->d_reps, c->d_items_all, c->n_items_all,
+                                    c->d_xs, c->d_acc, c->d_zpart, nullptr, nullptr, st));
+    }
+    if (tev) ++c->pass_recorded;
+    HIP_TRY(c, launch_integrate(c->kp, c->d_sysd, c->d_reps, c->R, c->n_pad_max, c->d_xs, c->d_vs, c->d_acc,
+                                c->d_negone, cv, step, step_base, c->d_flags, st));
+    return SCPS_OK;
+}
+
+void drop_step_graph(scps_ctx *c) {
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+    c->g_cv = nullptr;
+}
+
+// The executable graph of graph_steps consecutive steps (captured on the
+// context's private capture stream; replayed on its stream).  Its kernels
+// read the state from the context's buffers, the replicas' cvstate from cv
+// and the step from d_step, so a new capture is needed only when cv, the
+// largest stack or the block length changes.
+scps_status ensure_step_graph(scps_ctx *c, double *cv) {
+    const int kf = max_stack_frames(c);
+    if (c->gexec && c->g_cv == cv && c->g_frames == kf && c->g_steps == c->graph_steps) return SCPS_OK;
+    drop_step_graph(c);
+    if (!c->cap) HIP_TRY(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+    if (!c->d_step) HIP_TRY(c, dalloc(c, &c->d_step, 1));
+    HIP_TRY(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+    scps_status st = SCPS_OK;
+    for (int u = 0; u < c->graph_steps && st == SCPS_OK; ++u)
+        st = step_launches(c, cv, (uint64_t)u, c->d_step, false, c->cap);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->cap, &g);
+    if (st != SCPS_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    HIP_TRY(c, e);
+    const hipError_t ei = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIP_TRY(c, ei);
+    c->g_cv = cv;
+    c->g_frames = kf;
+    c->g_steps = c->graph_steps;
+    return SCPS_OK;
+}
+
 scps_status step_impl(scps_ctx *c, float *x, float *v, double *cv, int64_t n_steps, uint64_t step0,
                       int32_t record_every, float *frames) {
     if (!x || !cv) return fail(SCPS_ERR_INVALID_ARG, "x and cvstate must not be NULL");
@@ -826,11 +937,36 @@ scps_status step_impl(scps_ctx *c, float *x, float *v, double *cv, int64_t n_ste
     }
     HIP_TRY(c, launch_gather(c->d_sysd, c->d_reps, c->R, c->n_pad_max, x, v, c->d_xs, v ? c->d_vs : nullptr,
                              c->stream));
-    for (int64_t m = 0;; ++m) {
+    // whole blocks of graph_steps steps replay one captured graph (not with
+    // neighbour lists, the overlapped schedule or pass timing); a block never
+    // crosses a recorded frame or the end of the call
+    const int B = c->graph_steps;
+    const bool graphs = B > 0 && !(!scps && c->nl) && !(scps && c->side && c->overlap_nb) && !c->timing;
+    for (int64_t m = 0;;) {
         if (record_every > 0 && m % record_every == 0)
             HIP_TRY(c, launch_scatter(c->d_sysd, c->d_reps, c->R, c->n_pad_max, c->d_xs, nullptr, nullptr, nullptr,
                                       frames + (m / record_every) * frame_stride, c->stream));
         if (m == n_steps) break;
+        if (scps && c->jref_init) {
+            // a new stack: every replica's reference frame is its nearest frame,
+            // from one distance pass around frame 0
+            HIP_TRY(c, launch_scps_dist(c->kp, c->d_sysd, c->d_reps, c->d_groups, c->d_sitems, c->n_sitems,
+                                        max_stack_frames(c), nullptr, c->d_xs, c->d_X, c->d_Q, c->kmax, -1,
+                                        c->stream));
+            HIP_TRY(c, launch_tube_eval(c->prm.lambda, c->kp.wscale, nullptr, c->d_jref, c->d_sysd, c->d_reps,
+                                        c->R, c->kmax, -1, c->d_X, c->d_Q, nullptr, nullptr, nullptr, 0.0, 1,
+                                        c->stream));
+            c->jref_init = false;
+        }
+        const int64_t until = record_every > 0 ? std::min(n_steps, (m / record_every + 1) * record_every) : n_steps;
+        if (graphs && until - m >= B) {
+            scps_status gs = ensure_step_graph(c, cv);
+            if (gs != SCPS_OK) return gs;
+            HIP_TRY(c, launch_set_step(c->d_step, step0 + (uint64_t)m, c->stream));
+            HIP_TRY(c, hipGraphLaunch(c->gexec, c->stream));
+            m += B;
+            continue;
+        }
         if (!scps && c->nl) {
             // cutoff variant: neighbour lists, rebuilt where a particle moved more than half the skin
             HIP_TRY(c, launch_nl_update(c->kp, c->d_sysd, c->d_reps, c->R, c->nb_max, c->d_first_blk, c->d_xs,
@@ -842,74 +978,12 @@ scps_status step_impl(scps_ctx *c, float *x, float *v, double *cv, int64_t n_ste
             HIP_TRY(c, launch_finalize_rmd(c->kp, c->R, c->d_first_chunk, c->d_zpart_nl, c->d_zbase, cv, c->d_scale,
                                            c->stream));
             HIP_TRY(c, launch_integrate(c->kp, c->d_sysd, c->d_reps, c->R, c->n_pad_max, c->d_xs, c->d_vs, c->d_acc,
-                                        c->d_scale, cv, step0 + (uint64_t)m, c->d_flags, c->stream));
-        } else if (!scps) {
-            HIP_TRY(c, launch_pairs(0, c->nbk, c->kp, c->d_sysd, c->d_reps, c->d_items_all, c->n_items_all, c->d_xs,
-                                    c->d_acc, c->d_zpart, nullptr, nullptr, c->stream));
-            HIP_TRY(c, launch_finalize_rmd(c->kp, c->R, c->d_first_all, c->d_zpart, nullptr, cv, c->d_scale,
-                                           c->stream));
-            HIP_TRY(c, launch_integrate(c->kp, c->d_sysd, c->d_reps, c->R, c->n_pad_max, c->d_xs, c->d_vs, c->d_acc,
-                                        c->d_scale, cv, step0 + (uint64_t)m, c->d_flags, c->stream));
+                                        c->d_scale, cv, step0 + (uint64_t)m, nullptr, c->d_flags, c->stream));
         } else {
-            // distances to every frame (matrix cores), tube variables and
-            // ratchets, effective references (matrix cores), bias + physics
-            if (c->jref_init) {
-                // a new stack: every replica's reference frame is its nearest frame,
-                // from one distance pass around frame 0
-                HIP_TRY(c, launch_scps_dist(c->kp, c->d_sysd, c->d_reps, c->d_groups, c->d_sitems, c->n_sitems,
-                                            max_stack_frames(c), nullptr, c->d_xs, c->d_X, c->d_Q, c->kmax, -1,
-                                            c->stream));
-                HIP_TRY(c, launch_tube_eval(c->prm.lambda, c->kp.wscale, nullptr, c->d_jref, c->d_sysd, c->d_reps,
-                                            c->R, c->kmax, -1, c->d_X, c->d_Q, nullptr, nullptr, nullptr, 0.0, 1,
-                                            c->stream));
-                c->jref_init = false;
-            }
-            const bool overlap = c->side && c->overlap_nb;
-            if (overlap) {
-                // nonbonded forces (acc components 0..2) need only the positions:
-                // they overlap the bandwidth-bound distance pass
-                HIP_TRY(c, hipEventRecord(c->ev_fork, c->stream));
-                HIP_TRY(c, hipStreamWaitEvent(c->side, c->ev_fork, 0));
-                HIP_TRY(c, launch_pairs(4, c->nbk, c->kp, c->d_sysd, c->d_reps, c->d_items_all, c->n_items_all,
-                                        c->d_xs, c->d_acc, c->d_zpart, nullptr, nullptr, c->side));
-                HIP_TRY(c, hipEventRecord(c->ev_join, c->side));
-            }
-            scps_status tst;
-            hipEvent_t *tev = pass_slot(c, &tst);
-            if (tst != SCPS_OK) return tst;
-            if (tev) HIP_TRY(c, hipEventRecord(tev[0], c->stream));
-            HIP_TRY(c, launch_scps_dist(c->kp, c->d_sysd, c->d_reps, c->d_groups, c->d_sitems, c->n_sitems,
-                                        max_stack_frames(c), c->d_jref, c->d_xs, c->d_X, c->d_Q, c->kmax, -1,
-                                        c->stream));
-            if (tev) HIP_TRY(c, hipEventRecord(tev[1], c->stream));
-            HIP_TRY(c, launch_finalize_scps(c->kp, c->d_sysd, c->d_reps, c->R, c->kmax, c->d_jref, c->d_X, c->d_Q,
-                                            cv, c->d_coef, c->d_csum, c->stream));
-            if (tev) HIP_TRY(c, hipEventRecord(tev[2], c->stream));
-            if (c->prm.exec_mode == SCPS_EXEC_PER_STEP_ALL_TILES) {
-                // two passes: effective references to device memory, then every tile pair
-                HIP_TRY(c, launch_scps_eff(c->d_sysd, c->d_reps, c->d_groups, c->d_sitems, c->n_sitems, c->d_coef,
-                                           c->kmax, c->d_E, c->stream));
-                HIP_TRY(c, launch_pairs(3, c->nbk, c->kp, c->d_sysd, c->d_reps, c->d_items_all, c->n_items_all,
-                                        c->d_xs, c->d_acc, c->d_zpart, c->d_E, c->d_csum, c->stream));
-                if (tev) HIP_TRY(c, hipEventRecord(tev[3], c->stream));
-            } else {
-                // the effective references and the bias in one pass over the contact tiles;
-                // the nonbonded forces and bonds (mode 4, every tile pair) ran on the side
-                // stream beside the distance pass and are joined before the update
-                HIP_TRY(c, launch_scps_bias(c->kp, c->d_sysd, c->d_reps, c->d_groups, c->d_sitems, c->n_sitems,
-                                            max_stack_frames(c), c->d_xs, c->d_coef, c->d_csum, c->kmax, c->d_acc,
-                                            c->stream));
-                if (tev) HIP_TRY(c, hipEventRecord(tev[3], c->stream));
-                if (overlap)
-                    HIP_TRY(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
-                else
-                    HIP_TRY(c, launch_pairs(4, c->nbk, c->kp, c->d_sysd, c->d_reps, c->d_items_all, c->n_items_all,
-                                            c->d_xs, c->d_acc, c->d_zpart, nullptr, nullptr, c->stream));
-            }
-            if (tev) ++c->pass_recorded;
-            HIP_TRY(c, launch_integrate(c->kp, c->d_sysd, c->d_reps, c->R, c->n_pad_max, c->d_xs, c->d_vs, c->d_acc,
-                                        c->d_negone, cv, step0 + (uint64_t)m, c->d_flags, c->stream));
+            scps_status ss = step_launches(c, cv, step0 + (uint64_t)m, nullptr, true, c->stream);
+            if (ss != SCPS_OK) return ss;
         }
+        ++m;
     }
     HIP_TRY(c, launch_scatter(c->d_sysd, c->d_reps, c->R, c->n_pad_max, c->d_xs, v ? c->d_vs : nullptr, x, v,
                               nullptr, c->stream));
@@ -1254,6 +1328,19 @@ scps_status scps_set_launch(scps_ctx *ctx, int32_t path, int32_t param) {
     return set_launch_impl(ctx, path, param);
 }
 
+scps_status scps_set_graph_steps(scps_ctx *ctx, int32_t steps) {
+    scps_status st;
+    if (!usable(ctx, &st)) return st;
+    if (steps < 0 || steps > SCPS_MAX_GRAPH_STEPS)
+        return fail(SCPS_ERR_INVALID_ARG, "graph steps must be 0 .. " + std::to_string(SCPS_MAX_GRAPH_STEPS));
+    if (steps != ctx->graph_steps) {
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));   // the old graph may still be running
+        drop_step_graph(ctx);
+        ctx->graph_steps = steps;
+    }
+    return SCPS_OK;
+}
+
 scps_status scps_get_launch(scps_ctx *ctx, int32_t *launch) {
     scps_status st;
     if (!usable(ctx, &st)) return st;
@@ -1504,6 +1591,8 @@ void scps_destroy(scps_ctx *ctx) {
     if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
     if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
     if (ctx->ev_switch) (void)hipEventDestroy(ctx->ev_switch);
+    if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+    if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
     for (hipEvent_t e : ctx->pass_ev)
         if (e) (void)hipEventDestroy(e);
     for (void *p : ctx->owned) (void)hipFree(p);

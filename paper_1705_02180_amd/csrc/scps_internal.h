@@ -214,7 +214,10 @@ hipError_t launch_finalize_scps(const KParams &P, const SysDesc *sysd, const Rep
                                 hipStream_t st);
 hipError_t launch_integrate(const KParams &P, const SysDesc *sysd, const RepDesc *reps, int R,
                             int n_pad_max, float4 *xs, float4 *vs, double *acc,
-                            const double *scale, double *cv, uint64_t step, int *flags, hipStream_t st);
+                            const double *scale, double *cv, uint64_t step, const uint64_t *step_base,
+                            int *flags, hipStream_t st);
+// *d = v (one thread), in stream order
+hipError_t launch_set_step(uint64_t *d, uint64_t v, hipStream_t st);
 
 hipError_t launch_eval_out(const SysDesc *sysd, const RepDesc *reps, int R, int n_pad_max, double *acc,
                            const int *first, const double *zpart, double *z_out, float *grad,

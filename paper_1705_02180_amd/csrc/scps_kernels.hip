@@ -1708,13 +1708,17 @@ hipError_t launch_finalize_scps(const KParams &P, const SysDesc *sysd, const Rep
 // Langevin update of every particle; consumes and clears the accumulators.
 // The force is acc[0..2] + scale[r] * acc[3..5], the second term being the
 // bias; each workgroup adds its particles' dt |F_bias|^2 / (m gamma) to the
-// replica's bias functional cv[r][CV_T].
+// replica's bias functional cv[r][CV_T].  The noise is drawn for step
+// step_off + *step_base (step_base: nullable device word, so that a captured
+// sequence of steps can be replayed from any step).
 __global__ __launch_bounds__(256) void k_integrate(const KParams P, const SysDesc *__restrict__ sysd,
                                                    const RepDesc *__restrict__ reps, float4 *__restrict__ xs,
                                                    float4 *__restrict__ vs, double *__restrict__ acc,
                                                    const double *__restrict__ scale, double *__restrict__ cv,
-                                                   const uint64_t step, int *__restrict__ flags) {
+                                                   const uint64_t step_off, const uint64_t *__restrict__ step_base,
+                                                   int *__restrict__ flags) {
     __shared__ double tred[4];
+    const uint64_t step = step_off + (step_base ? *step_base : 0u);
     const int r = blockIdx.y;
     const RepDesc rd = reps[r];
     const SysDesc S = sysd[rd.sys];
@@ -1775,9 +1779,16 @@ __global__ __launch_bounds__(256) void k_integrate(const KParams P, const SysDes
 
 hipError_t launch_integrate(const KParams &P, const SysDesc *sysd, const RepDesc *reps, int R, int n_pad_max,
                             float4 *xs, float4 *vs, double *acc, const double *scale, double *cv, uint64_t step,
-                            int *flags, hipStream_t st) {
+                            const uint64_t *step_base, int *flags, hipStream_t st) {
     hipLaunchKernelGGL(k_integrate, dim3((n_pad_max + 255) / 256, R), dim3(256), 0, st, P, sysd, reps, xs, vs, acc,
-                       scale, cv, step, flags);
+                       scale, cv, step, step_base, flags);
+    return hipGetLastError();
+}
+
+__global__ void k_set_step(uint64_t *__restrict__ d, const uint64_t v) { *d = v; }
+
+hipError_t launch_set_step(uint64_t *d, uint64_t v, hipStream_t st) {
+    hipLaunchKernelGGL(k_set_step, dim3(1), dim3(1), 0, st, d, v);
     return hipGetLastError();
 }
 

@@ -81,6 +81,8 @@ _lib.scps_set_launch.restype = C.c_int
 _lib.scps_set_launch.argtypes = [_vp, _i32, _i32]
 _lib.scps_get_launch.restype = C.c_int
 _lib.scps_get_launch.argtypes = [_vp, _vp]
+_lib.scps_set_graph_steps.restype = C.c_int
+_lib.scps_set_graph_steps.argtypes = [_vp, _i32]
 _lib.scps_least_biased_path.restype = C.c_int
 _lib.scps_least_biased_path.argtypes = [_vp, _vp, _vp, _vp, _vp]
 _lib.scps_eval_tube.restype = C.c_int
@@ -108,7 +110,7 @@ _lib.scps_last_error.argtypes = []
 
 EXPORTS = ["scps_init_system", "scps_set_reference_map", "scps_step_replicas", "scps_eval_z_and_grad",
            "scps_ratchet_energy", "scps_update_reference_from_paths", "scps_set_stream", "scps_sync",
-           "scps_autotune", "scps_set_launch", "scps_get_launch", "scps_least_biased_path", "scps_eval_tube", "scps_eval_sigma", "scps_path_distance",
+           "scps_autotune", "scps_set_launch", "scps_get_launch", "scps_set_graph_steps", "scps_least_biased_path", "scps_eval_tube", "scps_eval_sigma", "scps_path_distance",
            "scps_path_distance_noalloc", "scps_time_passes", "scps_pass_times",
            "scps_funnel_steps", "scps_funnel_mean_path", "scps_scale_by_replica", "scps_destroy",
            "scps_last_error"]
@@ -297,6 +299,10 @@ class Context:
         per workgroup), 1 per-step, 2 packed (param = wavefronts per
         workgroup)."""
         _check(_lib.scps_set_launch(self._ctx(), int(path), int(param)))
+
+    def set_graph_steps(self, steps: int):
+        """Steps per captured HIP graph on the per-step path (0: none)."""
+        _check(_lib.scps_set_graph_steps(self._ctx(), int(steps)))
 
     def get_launch(self):
         """The launch the next step_replicas takes, as (path, parameter) in

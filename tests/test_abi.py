@@ -73,6 +73,7 @@ def test_host_validation_rejects_bad_arguments(lib):
     assert lib.scps_step_replicas(None, None, None, None, C.c_int64(1), C.c_uint64(0), 0, None) == -1
     assert lib.scps_set_launch(None, 2, 4) == -1
     assert lib.scps_get_launch(None, None) == -1
+    assert lib.scps_set_graph_steps(None, 16) == -1
     lib.scps_last_error.restype = C.c_char_p
     assert b"NULL" in lib.scps_last_error()
 
