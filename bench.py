@@ -80,6 +80,9 @@ def parse():
     ap.add_argument("--block", type=int, default=None,
                     help="Langevin steps per benchmark step (default: 200 for scps6000, a frame interval; else 100)")
     ap.add_argument("--replicas", type=int, default=0, help="0: the workload's own count")
+    ap.add_argument("--graph-steps", type=int, default=None,
+                    help="steps per replayed HIP graph on the per-step path (scps_set_graph_steps; "
+                         "uneven512 default: the block, 100; other workloads: the library's default, 0)")
     ap.add_argument("--plain-replicas", type=int, default=8)
     ap.add_argument("--plain-steps", type=int, default=20)
     ap.add_argument("--cpu-steps", type=int, default=300)
@@ -434,6 +437,9 @@ def bench_uneven512(args, torch, I, scps):
     cv = torch.as_tensor(w.initial_cvstate(), device="cuda")
     step = [0]
     ctx.autotune(x, v, cv, 5)                                # on copies of the state, before timing
+    # the per-step path's blocks replayed from one captured HIP graph each
+    gsteps = min(args.block, 256) if args.graph_steps is None else args.graph_steps
+    ctx.set_graph_steps(gsteps)
 
     def call(_):
         ctx.step_replicas(x, v, cv, args.block, step0=step[0])
@@ -451,7 +457,8 @@ def bench_uneven512(args, torch, I, scps):
                     f"{int(sizes.max())}), own native map each, all particles in the contact set "
                     f"({con} contact pairs per batched step), LJ + Debye-Hueckel, BAOAB dt=2 fs, "
                     f"{args.block} Langevin steps per benchmark step",
-        "replicas": R, "particles_total": int(sizes.sum()), "block": args.block})
+        "replicas": R, "particles_total": int(sizes.sum()), "block": args.block,
+        "graph_steps": gsteps})
     out["contact_pair_evals_per_s"] = value / R * con
     out["roofline"] = roofline(args.block * flops, per_ms, "scps_step_replicas (all kernels of a block)")
     out["roofline_fp32_unpacked"] = unpacked_view(out["roofline"])
