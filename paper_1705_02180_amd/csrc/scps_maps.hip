@@ -502,7 +502,8 @@ __device__ __forceinline__ void scps_dist_tile(const KParams &P, const SysDesc &
                                                const ScpsItem &it, const int fb_in, const float4 (*posj)[32],
                                                const int *orgj, const float4 *__restrict__ xs,
                                                const RepDesc *__restrict__ reps, const int myrep, const int jr,
-                                               const int lane, const int wave, double *xl, double &q) {
+                                               const int lane, const int wave, const int r0, const int r1, double *xl,
+                                               double &q) {
     const int I = it.IJ >> 16, J = it.IJ & 0xFFFF;
     const int K4 = stack_pm_width(S.K);
     const int rs = lane & 31, pq = lane >> 5;
@@ -548,10 +549,10 @@ __device__ __forceinline__ void scps_dist_tile(const KParams &P, const SysDesc &
     v2 ring[D];
     float rring[REF_LD ? DR : 1];
 #pragma unroll
-    for (int u = 0; u < D; ++u) ring[u] = bop(wave, u);
+    for (int u = 0; u < D; ++u) ring[u] = bop(r0 + wave, u);
     if constexpr (REF_LD) {
 #pragma unroll
-        for (int u = 0; u < DR; ++u) rring[u] = rop(wave, u);
+        for (int u = 0; u < DR; ++u) rring[u] = rop(r0 + wave, u);
     }
     const int ref_lane = ((jr >> 1) + 32 * pq) << 2;   // ds_bpermute byte address of the lane holding R_j
     // R_j of a step from the B operands of that step (one step ahead of its use,
@@ -564,7 +565,7 @@ __device__ __forceinline__ void scps_dist_tile(const KParams &P, const SysDesc &
     float rj_next = 0.f;
     if constexpr (!REF_LD) rj_next = ref_of(ring[0]);
 #pragma unroll 1
-    for (int i = wave; i < 64; i += NW) {
+    for (int i = r0 + wave; i < r1; i += NW) {
         const float4 pi = rep ? xr[i] : make_float4(0.f, 0.f, 0.f, 0.f);
         const int oi = MASK ? S.perm[I * 64 + i] : 0;
         const bool icon = I * 64 + i < S.nc;
@@ -642,8 +643,8 @@ __global__ __launch_bounds__(DistShape<BIGK>::WG)
 __attribute__((amdgpu_waves_per_eu(DistShape<BIGK>::WPE, DistShape<BIGK>::WPE))) void k_scps_dist(
     const KParams P, const SysDesc *__restrict__ sysd, const RepDesc *__restrict__ reps,
     const ScpsGroup *__restrict__ groups, const ScpsItem *__restrict__ items, const int n_items, const int nfb,
-    const int *__restrict__ jref, const float4 *__restrict__ xs, double *__restrict__ X, double *__restrict__ Q,
-    const int kmax, const int stack_sys) {
+    const int nsplit, const int *__restrict__ jref, const float4 *__restrict__ xs, double *__restrict__ X,
+    double *__restrict__ Q, const int kmax, const int stack_sys) {
     __shared__ __align__(16) float4 posj[64][32];   // block J of every replica slot
     __shared__ double xl[32 * 64];                   // float64 sums X[slot][frame] of the current group
     constexpr int NW = DistShape<BIGK>::NW, WG = DistShape<BIGK>::WG;
@@ -658,11 +659,15 @@ __attribute__((amdgpu_waves_per_eu(DistShape<BIGK>::WPE, DistShape<BIGK>::WPE)))
     double q = 0.0;
     int cur = -1, cur_fb = 0, nrep = 0;
     SysDesc S;
-    const int n_units = n_items * nfb;
+    // work unit t: rows [r0, r0 + 64 / nsplit) of item u mod n_items in frame
+    // block u / n_items, u = t / nsplit (nsplit > 1 when there are too few
+    // items to fill the chip)
+    const int n_units = n_items * nfb * nsplit, rows = 64 / nsplit;
     for (int t = blockIdx.x;; t += gridDim.x) {
         const bool more = t < n_units;
-        const int fb = (BIGK && more) ? t / n_items : 0;
-        const ScpsItem it = more ? items[t - fb * n_items] : ScpsItem{-1, 0, 0, 0};
+        const int u = t / nsplit, r0 = (t - u * nsplit) * rows;
+        const int fb = (BIGK && more) ? u / n_items : 0;
+        const ScpsItem it = more ? items[u - fb * n_items] : ScpsItem{-1, 0, 0, 0};
         const bool change = it.group != cur || fb != cur_fb;
         if (cur >= 0 && change) {
             // flush the sums of (group, frame block) to the replicas' float64 totals
@@ -714,16 +719,16 @@ __attribute__((amdgpu_waves_per_eu(DistShape<BIGK>::WPE, DistShape<BIGK>::WPE)))
         if (it.flags & TILE_MASK) {
             if (diag)
                 scps_dist_tile<true, BIGK, true, NW>(P, S, nrep, it, fb, posj, orgj, xs, reps, myrep, myj, lane, wave,
-                                                 xl, q);
+                                                 r0, r0 + rows, xl, q);
             else
                 scps_dist_tile<true, BIGK, false, NW>(P, S, nrep, it, fb, posj, orgj, xs, reps, myrep, myj, lane, wave,
-                                                  xl, q);
+                                                  r0, r0 + rows, xl, q);
         } else if (diag) {
-            scps_dist_tile<false, BIGK, true, NW>(P, S, nrep, it, fb, posj, orgj, xs, reps, myrep, myj, lane, wave, xl,
-                                              q);
+            scps_dist_tile<false, BIGK, true, NW>(P, S, nrep, it, fb, posj, orgj, xs, reps, myrep, myj, lane, wave, r0,
+                                              r0 + rows, xl, q);
         } else {
-            scps_dist_tile<false, BIGK, false, NW>(P, S, nrep, it, fb, posj, orgj, xs, reps, myrep, myj, lane, wave, xl,
-                                               q);
+            scps_dist_tile<false, BIGK, false, NW>(P, S, nrep, it, fb, posj, orgj, xs, reps, myrep, myj, lane, wave, r0,
+                                               r0 + rows, xl, q);
         }
     }
 }
@@ -892,11 +897,10 @@ __device__ __forceinline__ void bias_loads(const float *tile_base, const int k, 
 // next half are issued after the MFMAs of the current one.
 template <bool MASK, int KKN, int NH>
 __device__ __forceinline__ void scps_bias_tile(const KParams &P, const SysDesc &S, const ScpsItem &it,
-                                               const int lane, const int wave, BiasLds &L, float fi[][3],
-                                               float fj[][3]) {
+                                               const int lane, const int wave, const int kb, const int ke, BiasLds &L,
+                                               float fi[][3], float fj[][3]) {
     const int I = it.IJ >> 16, J = it.IJ & 0xFFFF;
     const bool diag = it.flags & TILE_DIAG;
-    const int kb = diag ? 1 : 0, ke = diag ? 33 : 64;
     const int nch = (ke - kb + BIAS_CH - 1) / BIAS_CH;
     if (wave < BIAS_NMW) {
         // ---- producer: E of sub-step kb + BIAS_CH st + wave, chunk st -> buffer st & 1
@@ -1004,18 +1008,18 @@ __device__ __forceinline__ void scps_bias_tile(const KParams &P, const SysDesc &
 // common sizes keep their register allocation.
 template <bool MASK, bool BIG>
 __device__ __forceinline__ void scps_bias_dispatch(const KParams &P, const SysDesc &S, const ScpsItem &it,
-                                                   const int lane, const int wave, BiasLds &L, float fi[][3],
-                                                   float fj[][3]) {
+                                                   const int lane, const int wave, const int kb, const int ke,
+                                                   BiasLds &L, float fi[][3], float fj[][3]) {
     if constexpr (BIG)
-        scps_bias_tile<MASK, 32, 2>(P, S, it, lane, wave, L, fi, fj);
+        scps_bias_tile<MASK, 32, 2>(P, S, it, lane, wave, kb, ke, L, fi, fj);
     else if (S.K <= 16)
-        scps_bias_tile<MASK, 8, 1>(P, S, it, lane, wave, L, fi, fj);
+        scps_bias_tile<MASK, 8, 1>(P, S, it, lane, wave, kb, ke, L, fi, fj);
     else if (S.K <= 32)
-        scps_bias_tile<MASK, 16, 1>(P, S, it, lane, wave, L, fi, fj);
+        scps_bias_tile<MASK, 16, 1>(P, S, it, lane, wave, kb, ke, L, fi, fj);
     else if (S.K <= 52)
-        scps_bias_tile<MASK, 26, 1>(P, S, it, lane, wave, L, fi, fj);
+        scps_bias_tile<MASK, 26, 1>(P, S, it, lane, wave, kb, ke, L, fi, fj);
     else
-        scps_bias_tile<MASK, 32, 1>(P, S, it, lane, wave, L, fi, fj);
+        scps_bias_tile<MASK, 32, 1>(P, S, it, lane, wave, kb, ke, L, fi, fj);
 }
 
 template <bool BIG>
@@ -1023,13 +1027,19 @@ __global__ __launch_bounds__(BIAS_WG) __attribute__((amdgpu_waves_per_eu(3, 3)))
     const KParams P, const SysDesc *__restrict__ sysd, const RepDesc *__restrict__ reps,
     const ScpsGroup *__restrict__ groups, const ScpsItem *__restrict__ items, const int n_items,
     const float4 *__restrict__ xs, const float *__restrict__ coef, const double *__restrict__ csum, const int kmax,
-    double *__restrict__ acc) {
+    const int ksplit, double *__restrict__ acc) {
     __shared__ BiasLds L;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     int cur = -1;
     SysDesc S;
-    for (int t = blockIdx.x; t < n_items; t += gridDim.x) {
-        const ScpsItem it = items[t];
+    // work unit t: a range of the sub-steps of item t / ksplit (ksplit > 1
+    // when there are too few items to fill the chip), in whole chunks
+    for (int t = blockIdx.x; t < n_items * ksplit; t += gridDim.x) {
+        const ScpsItem it = items[t / ksplit];
+        const bool tdiag = it.flags & TILE_DIAG;
+        const int kb0 = tdiag ? 1 : 0, ke0 = tdiag ? 33 : 64;   // a diagonal tile meets each pair by sub-step 32
+        const int per = ((ke0 - kb0 + ksplit - 1) / ksplit + BIAS_CH - 1) / BIAS_CH * BIAS_CH;
+        const int kb = min(ke0, kb0 + (t % ksplit) * per), ke = min(ke0, kb + per);
         __syncthreads();   // the previous item's positions are no longer read
         if (it.group != cur) {
             cur = it.group;
@@ -1063,12 +1073,11 @@ __global__ __launch_bounds__(BIAS_WG) __attribute__((amdgpu_waves_per_eu(3, 3)))
 #pragma unroll
             for (int c = 0; c < 3; ++c) fi[m][c] = fj[m][c] = 0.f;
         if (it.flags & TILE_MASK)
-            scps_bias_dispatch<true, BIG>(P, S, it, lane, wave, L, fi, fj);
+            scps_bias_dispatch<true, BIG>(P, S, it, lane, wave, kb, ke, L, fi, fj);
         else
-            scps_bias_dispatch<false, BIG>(P, S, it, lane, wave, L, fi, fj);
-        if (wave < BIAS_NMW) continue;
+            scps_bias_dispatch<false, BIG>(P, S, it, lane, wave, kb, ke, L, fi, fj);
+        if (wave < BIAS_NMW || kb == ke) continue;
         // after sub-steps kb .. ke-1 lane l holds the j-side partials of particle (l + ke) mod 64
-        const int ke = (it.flags & TILE_DIAG) ? 33 : 64;
         const int jo = J * 64 + ((lane + ke) & 63);
         const int n_pad = S.n_pad;
 #pragma unroll
@@ -1092,17 +1101,26 @@ hipError_t launch_scps_dist(const KParams &P, const SysDesc *sysd, const RepDesc
     if (n_items == 0) return hipSuccess;
     if (max_frames < 1 || max_frames > KMAX || max_frames > kmax) return hipErrorInvalidValue;
     const int nfb = (max_frames + 63) / 64;
-    // a grid of the resident workgroups (256 CUs) striding over the work units
+    // a grid of the resident workgroups (256 CUs) striding over the work
+    // units; too few items for that (small systems) split each tile's rows
+    // over up to 8 workgroups
+    auto split = [&](int resident) {
+        int ns = 1;
+        while (ns < 8 && n_items * nfb * ns * 2 <= resident) ns *= 2;
+        return ns;
+    };
     if (nfb > 1) {
         typedef DistShape<true> DS;
-        const int grid = std::min(n_items * nfb, 256 * DS::RESIDENT);
+        const int ns = split(256 * DS::RESIDENT);
+        const int grid = std::min(n_items * nfb * ns, 256 * DS::RESIDENT);
         hipLaunchKernelGGL(k_scps_dist<true>, dim3(grid), dim3(DS::WG), 0, st, P, sysd, reps, groups, items, n_items,
-                           nfb, jref, xs, X, Q, kmax, stack_sys);
+                           nfb, ns, jref, xs, X, Q, kmax, stack_sys);
     } else {
         typedef DistShape<false> DS;
-        const int grid = std::min(n_items, 256 * DS::RESIDENT);
+        const int ns = split(256 * DS::RESIDENT);
+        const int grid = std::min(n_items * ns, 256 * DS::RESIDENT);
         hipLaunchKernelGGL(k_scps_dist<false>, dim3(grid), dim3(DS::WG), 0, st, P, sysd, reps, groups, items,
-                           n_items, nfb, jref, xs, X, Q, kmax, stack_sys);
+                           n_items, nfb, ns, jref, xs, X, Q, kmax, stack_sys);
     }
     return hipGetLastError();
 }
@@ -1160,13 +1178,17 @@ hipError_t launch_scps_bias(const KParams &P, const SysDesc *sysd, const RepDesc
                             const double *csum, int kmax, double *acc, hipStream_t st) {
     if (n_items == 0) return hipSuccess;
     if (max_frames < 1 || max_frames > KMAX || max_frames > kmax) return hipErrorInvalidValue;
-    const int grid = n_items < 256 ? n_items : 256;   // one workgroup per compute unit (LDS)
+    // one workgroup per compute unit (LDS); too few items for 256 (small
+    // systems) split each tile's sub-steps over up to 8 workgroups
+    int ks = 1;
+    while (ks < 8 && n_items * ks * 2 <= 256) ks *= 2;
+    const int grid = std::min(n_items * ks, 256);
     if (max_frames > 64)
         hipLaunchKernelGGL(k_scps_bias<true>, dim3(grid), dim3(BIAS_WG), 0, st, P, sysd, reps, groups, items, n_items,
-                           xs, coef, csum, kmax, acc);
+                           xs, coef, csum, kmax, ks, acc);
     else
         hipLaunchKernelGGL(k_scps_bias<false>, dim3(grid), dim3(BIAS_WG), 0, st, P, sysd, reps, groups, items,
-                           n_items, xs, coef, csum, kmax, acc);
+                           n_items, xs, coef, csum, kmax, ks, acc);
     return hipGetLastError();
 }
 
