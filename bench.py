@@ -17,7 +17,10 @@ Other workloads (--workload), each printed as its own JSON line:
                 of 100 steps in one persistent launch
   chain20       16384 replicas of the 20-bead chain (several per wavefront,
                 blocks of 1000 steps), the 16-replica batch beside it
-  uneven512     512 chains, N ~ U{200..3000}, each with its own native map
+  uneven512     512 chains, N ~ U{200..3000}, each with its own native map,
+                100-step blocks replayed from one captured HIP graph
+  scps560       the SCPS iteration of the headline on the 560-particle
+                (Fip35-sized) chain of chain560: 32 replicas, 51 frames
   autograd3000  z and E_b forward + backward for 64 chains of 3000 particles
   cutoff6000    the 6000-particle chain under rMD with contact and nonbonded
                 cutoffs of 12 A from compact states: neighbour lists against
@@ -72,7 +75,7 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default="scps6000",
-                    choices=["chain560", "chain20", "uneven512", "autograd3000", "scps6000", "cutoff6000",
+                    choices=["chain560", "chain20", "uneven512", "autograd3000", "scps6000", "scps560", "cutoff6000",
                              "funnel"])
     ap.add_argument("--steps", type=int, default=None,
                     help="timed benchmark steps (default: 50 for scps6000, one 10^4-step iteration; else 20)")
@@ -94,11 +97,11 @@ def parse():
                     help="only run a plain device copy of 256 MiB (to scale HBM byte counters)")
     a = ap.parse_args()
     if a.steps is None:
-        a.steps = SCPS_ITER_STEPS // 200 if a.workload == "scps6000" else 20
+        a.steps = SCPS_ITER_STEPS // 200 if a.workload in ("scps6000", "scps560") else 20
     if a.warmup is None:
-        a.warmup = 2 if a.workload == "scps6000" else 3
+        a.warmup = 2 if a.workload in ("scps6000", "scps560") else 3
     if a.block is None:
-        a.block = {"scps6000": 200, "chain20": 1000}.get(a.workload, 100)
+        a.block = {"scps6000": 200, "scps560": 200, "chain20": 1000}.get(a.workload, 100)
     return a
 
 
@@ -626,10 +629,11 @@ def scps6000_parity(torch, scps, w, threads):
     return summary, stack, frames
 
 
-def bench_scps6000(args, torch, I, scps):
+def bench_scps6000(args, torch, I, scps, fip=False):
     import numpy as np
     R = args.replicas or 32
-    w = I.config5(n_replicas=R)
+    # the serpin-sized chain of the headline, or (fip) the 560-particle Fip35-sized chain under SCPS
+    w = I.config2(n_replicas=R) if fip else I.config5(n_replicas=R)
     sy = w.systems[0]
     n = sy.n
     con, nb, both = pair_counts(sy, w.params)
@@ -688,7 +692,7 @@ def bench_scps6000(args, torch, I, scps):
     ctx.sync()
     value = R * blk * args.steps / wall
     out = base_line(args, value, "replica-steps/s", wall, args.steps, {
-        "workload": f"chain6000_serpin_shaped SCPS iteration: {R} replicas x {n} particles, SCPS bias on a stack "
+        "workload": f"{w.name} SCPS iteration: {R} replicas x {n} particles, SCPS bias on a stack "
                     f"of {K} frame maps x {con} contact pairs, LJ + Debye-Hueckel, BAOAB dt=2 fs; one benchmark "
                     f"step = {blk} Langevin steps of every replica with its frame recorded; the timed region "
                     f"ends with eq (avCij) over the {nrec} recorded frames (once per iteration)",
@@ -708,7 +712,7 @@ def bench_scps6000(args, torch, I, scps):
     dom = max(per, key=per.get)
     names = {"distance": "k_scps_dist (distances to every frame)",
              "bias": "k_scps_bias (effective references and bias forces)"}
-    traffic = measured_scps_traffic()
+    traffic = None if fip else measured_scps_traffic()   # the counter record is the serpin-sized chain's
     out["roofline"] = roofline_hbm(stack_bytes, [per[dom]] * 1, names[dom],
                                    traffic.get(dom) if traffic else None)
     out["roofline"]["launches_timed"] = timed
@@ -752,8 +756,9 @@ def bench_scps6000(args, torch, I, scps):
 
 
 def scps6000_cpu(w, p, stack, threads):
-    """The oracle on the same chain and stack size: one SCPS step of one
-    replica on one thread, and one step of `threads` replicas side by side."""
+    """The oracle on the same chain and stack size: SCPS steps of one replica
+    on one thread, and of `threads` replicas side by side, as many steps as
+    make each sample last about 10 s (one for the serpin-sized chain)."""
     import numpy as np
     import oracle as O
     sy = w.systems[0]
@@ -764,19 +769,25 @@ def scps6000_cpu(w, p, stack, threads):
     osys = O.System(sy.n, sy.contact_idx, sy.mass, sy.charge, p, native_xyz=sy.native, stack=stack)
     res = {}
     for m in (1, threads):
-        xs = np.concatenate([sy.start.ravel()] * m).astype(np.float64)
-        vs = np.zeros_like(xs)
-        cv0 = np.zeros((m, 8))
-        cv0[:, 1] = cv0[:, 5] = cv0[:, 6] = np.inf
-        t0 = time.perf_counter()
-        _, _, _, used = O.run_batch(p, [osys], np.zeros(m, dtype=np.int32), xs, vs, cv0, 1, 0, m)
-        res[m] = (m / (time.perf_counter() - t0), int(used), time.perf_counter() - t0)
-    v_all, used, dt = res[threads]
-    v_one, _, dt1 = res[1]
+        k = 1
+        while True:
+            xs = np.concatenate([sy.start.ravel()] * m).astype(np.float64)
+            vs = np.zeros_like(xs)
+            cv0 = np.zeros((m, 8))
+            cv0[:, 1] = cv0[:, 5] = cv0[:, 6] = np.inf
+            t0 = time.perf_counter()
+            _, _, _, used = O.run_batch(p, [osys], np.zeros(m, dtype=np.int32), xs, vs, cv0, k, 0, m)
+            dt = time.perf_counter() - t0
+            if dt >= 5.0 or k >= 4096:
+                break
+            k = min(4096, max(2 * k, int(k * 10.0 / max(dt, 1e-3)) + 1))
+        res[m] = (m * k / dt, int(used), dt, k)
+    v_all, used, dt, k_all = res[threads]
+    v_one, _, dt1, k_one = res[1]
     return {"value": v_all, "unit": "replica-steps/s", "cores": used, "kind": "oracle",
             "single_thread_value": v_one, "cpu_model": cpu_model(),
-            "sample": f"{threads} replicas x 1 SCPS step of the same chain and stack size, FP64, OpenMP over "
-                      f"replicas ({dt:.1f} s); single thread: 1 replica x 1 step ({dt1:.1f} s)"}
+            "sample": f"{threads} replicas x {k_all} SCPS step(s) of the same chain and stack size, FP64, OpenMP "
+                      f"over replicas ({dt:.1f} s); single thread: 1 replica x {k_one} step(s) ({dt1:.1f} s)"}
 
 
 # ---------------------------------------------------------------------------
@@ -923,7 +934,8 @@ def main():
 
     torch.cuda.set_device(0)
     fn = {"chain560": bench_chain560, "chain20": bench_chain20, "uneven512": bench_uneven512,
-          "autograd3000": bench_autograd3000, "scps6000": bench_scps6000, "cutoff6000": bench_cutoff6000, "funnel": bench_funnel}[args.workload]
+          "autograd3000": bench_autograd3000, "scps6000": bench_scps6000,
+          "scps560": lambda *a: bench_scps6000(*a, fip=True), "cutoff6000": bench_cutoff6000, "funnel": bench_funnel}[args.workload]
     out = fn(args, torch, I, scps)
     print(json.dumps(out), flush=True)
 
