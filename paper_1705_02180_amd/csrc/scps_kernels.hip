@@ -1422,7 +1422,10 @@ __global__ __launch_bounds__(256) void k_nl_build(const KParams P, const SysDesc
                                                   const int *__restrict__ rebuild, int *__restrict__ cnt,
                                                   int2 *__restrict__ nl, int *__restrict__ flags) {
     __shared__ float4 shpos[4][128];
-    __shared__ int shorg[4][64];
+    // block J's chain indices and list indices, stored twice like its positions:
+    // .x = chain index, .y = j (-1 past the end of the system) with bit 30 set
+    // inside the contact set
+    __shared__ int2 shorg[4][128];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int W = gridDim.x * 4, w = blockIdx.x * 4 + wave;
     const float rl2 = r_list * r_list;
@@ -1450,7 +1453,10 @@ __global__ __launch_bounds__(256) void k_nl_build(const KParams P, const SysDesc
                 const float4 pjl = xr2[J * 128 + lane];
                 shpos[wave][lane] = pjl;
                 shpos[wave][64 + lane] = pjl;
-                shorg[wave][lane] = S.perm[J * 64 + lane];
+                const int jw = J * 64 + lane;
+                const int2 orgj = make_int2(S.perm[jw], jw < S.n ? (jw | (jw < S.nc ? 1 << 30 : 0)) : -1);
+                shorg[wave][lane] = orgj;
+                shorg[wave][64 + lane] = orgj;
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -1458,49 +1464,83 @@ __global__ __launch_bounds__(256) void k_nl_build(const KParams P, const SysDesc
                 const float4 pi = xr2[I * 128 + lane];
                 const int oi = S.perm[i];
                 const bool diag = I == J, ival = i < S.n, icon = i < S.nc;
-                const int njv = S.n - J * 64, njc = S.nc - J * 64;
-                // tag of the pair met at sub-step k (0: no entry), without branches; every
-                // tile runs all 64 sub-steps, a diagonal tile counting only k = 1..32
-                // (lanes 0..31 at k = 32), so each unordered pair is met once
+                // the tag bits of the pair met at sub-step k (0: no entry), without
+                // branches; every tile runs all 64 sub-steps, a diagonal tile counting
+                // only k = 1..32 (lanes 0..31 at k = 32), so each unordered pair is met
+                // once.  Everything that depends on the partner comes from LDS, so
+                // nothing per sub-step is loop-invariant (hoisted values of all 64
+                // sub-steps would hold 64 registers).
                 auto tag_at = [&](int k) -> int {
-                    const int jl = (lane + k) & 63;
                     float dx, dy, dz;
                     const float r2 = pair_r2(pi, shpos[wave][lane + k], dx, dy, dz);
-                    const int sep = abs(oi - shorg[wave][jl]);
+                    const int2 oj = shorg[wave][lane + k];
+                    const int sep = abs(oi - oj.x);
                     const bool in_tile = !diag | ((k >= 1) & ((k < 32) | ((k == 32) & (lane < 32))));
-                    const bool act = ival & (jl < njv) & in_tile & (r2 <= rl2);
-                    const int con = (icon & (jl < njc) & (sep > P.min_sep)) ? 1 << 30 : 0;
+                    const bool act = ival & (oj.y >= 0) & in_tile & (r2 <= rl2);
+                    const int con = (icon & ((oj.y >> 30) & 1) & (sep > P.min_sep)) ? 1 << 30 : 0;
                     const int nbp = (sep > P.nb_excl) ? 1 << 29 : 0;
                     return act ? (con | nbp) : 0;
                 };
-                int n_i = 0, n_j = 0;
-#pragma unroll 8
-                for (int k = 0; k < 64; ++k) {
-                    const int hit = tag_at(k) != 0;
-                    n_i += hit;
-                    n_j = rot1i(n_j + hit);
-                }
-                // after 64 rotations lane l holds the j-side count of particle l of block J
-                const int base_i = n_i ? atomicAdd(&ci[i], n_i) : 0;
-                const int base_j = n_j ? atomicAdd(&ci[J * 64 + lane], n_j) : 0;
-                if (base_i + n_i > NL_CAP || base_j + n_j > NL_CAP) flags[r] = 2;
-                // second walk: the j-side write offset travels with its particle
-                int o_i = base_i, o_j = base_j;
+                // the lane's reference values of this tile stream through a ring of
+                // 32 registers: sub-steps 0..31 load before the first walk, so that
+                // their latency hides behind it, and the first half of the second
+                // walk reloads each slot it has used with the value 32 sub-steps
+                // ahead.  HR (a tile inside the contact set, which has a reference
+                // tile) is uniform, so the loads are unconditional within a form.
                 const float *rt =
                     (I < S.ncb && J < S.ncb) ? S.ref + (int64_t)tile_index(I, J, S.ncb) * 4096 : nullptr;
-#pragma unroll 4
-                for (int k = 0; k < 64; ++k) {
-                    const int tag = tag_at(k);
-                    if (tag) {
-                        const int jl = (lane + k) & 63, j = J * 64 + jl;
-                        const float Rv = (tag & (1 << 30)) ? ldg(rt, k * 64 + lane) : 0.f;
-                        if (o_i < NL_CAP) li[(int64_t)i * NL_CAP + o_i] = make_int2(j | tag, __float_as_int(Rv));
-                        if (o_j < NL_CAP) li[(int64_t)j * NL_CAP + o_j] = make_int2(i | tag, __float_as_int(Rv));
-                        ++o_i;
-                        ++o_j;
+                auto walks = [&](auto hr) {
+                    constexpr bool HR = decltype(hr)::value;
+                    float ring[32];
+#pragma unroll
+                    for (int k = 0; k < 32; ++k) ring[k] = HR ? ldg(rt, k * 64 + lane) : 0.f;
+                    // first walk: count the entries, and keep each sub-step's two tag
+                    // bits (nonbonded, contact) in tb for the second walk
+                    uint32_t tb[4] = {0u, 0u, 0u, 0u};
+                    int n_i = 0, n_j = 0;
+#pragma unroll
+                    for (int k = 0; k < 64; ++k) {
+                        const uint32_t b = (uint32_t)tag_at(k) >> 29;
+                        tb[k >> 4] |= b << (2 * (k & 15));
+                        const int hit = b != 0u;
+                        n_i += hit;
+                        n_j = rot1i(n_j + hit);
+                        if ((k & 3) == 3) __builtin_amdgcn_sched_barrier(0);
                     }
-                    o_j = rot1i(o_j);
-                }
+                    // after 64 rotations lane l holds the j-side count of particle l of block J
+                    const int base_i = n_i ? atomicAdd(&ci[i], n_i) : 0;
+                    const int base_j = n_j ? atomicAdd(&ci[J * 64 + lane], n_j) : 0;
+                    if (base_i + n_i > NL_CAP || base_j + n_j > NL_CAP) flags[r] = 2;
+                    // second walk, over the kept tags: the j-side write offset travels
+                    // with its particle
+                    int o_i = base_i, o_j = base_j;
+                    auto put = [&](const int k, const float Rk) {
+                        const uint32_t b = (tb[k >> 4] >> (2 * (k & 15))) & 3u;
+                        if (b) {
+                            const int j = shorg[wave][lane + k].y & 0x1FFFFFFF, tag = (int)(b << 29);
+                            const float Rv = (b & 2u) ? Rk : 0.f;
+                            if (o_i < NL_CAP) li[(int64_t)i * NL_CAP + o_i] = make_int2(j | tag, __float_as_int(Rv));
+                            if (o_j < NL_CAP) li[(int64_t)j * NL_CAP + o_j] = make_int2(i | tag, __float_as_int(Rv));
+                            ++o_i;
+                            ++o_j;
+                        }
+                        o_j = rot1i(o_j);
+                    };
+#pragma unroll
+                    for (int k = 0; k < 32; ++k) {
+                        const float Rk = ring[k];
+                        if constexpr (HR) ring[k] = ldg(rt, (32 + k) * 64 + lane);
+                        put(k, Rk);
+                        // issue the reloads as the slots free up, not all at once
+                        if ((k & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+                    }
+#pragma unroll
+                    for (int k = 32; k < 64; ++k) put(k, ring[k - 32]);
+                };
+                if (rt)
+                    walks(std::true_type{});
+                else
+                    walks(std::false_type{});
                 __builtin_amdgcn_wave_barrier();   // shpos / shorg are rewritten for the next tile
             }
         }
@@ -1515,6 +1555,7 @@ __global__ __launch_bounds__(256) void k_nl_build(const KParams P, const SysDesc
 // of C (C - 2R) / 2.
 constexpr int NL_LANES = 8;
 constexpr int NL_CHUNK = 256 / NL_LANES;
+constexpr int NL_BATCH = 4;
 template <int NBK>
 __global__ __launch_bounds__(256) void k_nl_force(const KParams P, const SysDesc *__restrict__ sysd,
                                                   const RepDesc *__restrict__ reps, const int *__restrict__ first,
@@ -1535,33 +1576,46 @@ __global__ __launch_bounds__(256) void k_nl_force(const KParams P, const SysDesc
     const int2 *li = nl + (rd.poff + i) * (int64_t)NL_CAP;
     float f[3] = {0.f, 0.f, 0.f}, g[3] = {0.f, 0.f, 0.f};
     float zt = 0.f;
-    for (int e = t; e < m; e += NL_LANES) {
-        const int2 en = li[e];
-        const int j = en.x & 0x1FFFFFFF;
-        const float4 pj = xr2[dup_index(j)];
-        float dx, dy, dz;
-        const float r2 = pair_r2(pi, pj, dx, dy, dz);
-        if (NBK != 0 && (en.x & (1 << 29)) && (!P.has_cut_nb || r2 <= P.r_cut_nb2)) {
-            const float s = nb_scalar<NBK>(P, r2, qp, pj.w);
-            f[0] = fmaf(s, dx, f[0]);
-            f[1] = fmaf(s, dy, f[1]);
-            f[2] = fmaf(s, dz, f[2]);
+    // NL_BATCH entries per lane at a time: their list loads, then their
+    // position gathers, are all issued before the first pair is computed, so
+    // each wave keeps NL_BATCH dependent load pairs in flight instead of one.
+    // Slots past the end read as (particle 0, no tag) and add nothing.
+    for (int e0 = t; e0 < m; e0 += NL_BATCH * NL_LANES) {
+        int2 en[NL_BATCH];
+        float4 pj[NL_BATCH];
+#pragma unroll
+        for (int u = 0; u < NL_BATCH; ++u) {
+            const int e = e0 + u * NL_LANES;
+            en[u] = e < m ? li[e] : make_int2(0, 0);
         }
-        if (en.x & (1 << 30)) {
-            const float R = __int_as_float(en.y);
-            const float q = r2 * P.inv_r0sq;
-            const float q2 = q * q;
-            const float t = q + q2;             // num = 1 + t, den = num + q^2 t
-            const float num = 1.f + t;
-            const float den = fmaf(q2, t, num);
-            const float inv_den = (!P.has_cut || r2 <= P.r_cut2) ? frcp(den) : 0.f;
-            const float C = num * inv_den;
-            zt = fmaf(C, C - 2.f * R, zt);
-            const float poly = fmaf(q, fmaf(q, fmaf(q, P.cp[0], P.cp[1]), P.cp[2]), P.cp[3]);
-            const float gg = ((C - R) * (q2 * inv_den)) * (poly * inv_den);
-            g[0] = fmaf(gg, dx, g[0]);
-            g[1] = fmaf(gg, dy, g[1]);
-            g[2] = fmaf(gg, dz, g[2]);
+#pragma unroll
+        for (int u = 0; u < NL_BATCH; ++u) pj[u] = xr2[dup_index(en[u].x & 0x1FFFFFFF)];
+#pragma unroll
+        for (int u = 0; u < NL_BATCH; ++u) {
+            float dx, dy, dz;
+            const float r2 = pair_r2(pi, pj[u], dx, dy, dz);
+            if (NBK != 0 && (en[u].x & (1 << 29)) && (!P.has_cut_nb || r2 <= P.r_cut_nb2)) {
+                const float s = nb_scalar<NBK>(P, r2, qp, pj[u].w);
+                f[0] = fmaf(s, dx, f[0]);
+                f[1] = fmaf(s, dy, f[1]);
+                f[2] = fmaf(s, dz, f[2]);
+            }
+            if (en[u].x & (1 << 30)) {
+                const float R = __int_as_float(en[u].y);
+                const float q = r2 * P.inv_r0sq;
+                const float q2 = q * q;
+                const float t = q + q2;             // num = 1 + t, den = num + q^2 t
+                const float num = 1.f + t;
+                const float den = fmaf(q2, t, num);
+                const float inv_den = (!P.has_cut || r2 <= P.r_cut2) ? frcp(den) : 0.f;
+                const float C = num * inv_den;
+                zt = fmaf(C, C - 2.f * R, zt);
+                const float poly = fmaf(q, fmaf(q, fmaf(q, P.cp[0], P.cp[1]), P.cp[2]), P.cp[3]);
+                const float gg = ((C - R) * (q2 * inv_den)) * (poly * inv_den);
+                g[0] = fmaf(gg, dx, g[0]);
+                g[1] = fmaf(gg, dy, g[1]);
+                g[2] = fmaf(gg, dz, g[2]);
+            }
         }
     }
 #pragma unroll
