@@ -229,6 +229,34 @@ scps_status scps_ratchet_energy(scps_ctx *ctx, const double *z, const double *z_
  * Asynchronous.  Errors: INVALID_ARG, HIP. */
 scps_status scps_scale_by_replica(scps_ctx *ctx, const float *in, const double *coef, float *out);
 
+/* Forward of the differentiable rMD bias in one call (eq (zrMD) and the
+ * ratchet energy of eq (FrMD)): z as scps_eval_z_and_grad computes it,
+ * E_b[r] = 1/2 k_R (z - z_m)^2 theta(z - z_m) with theta(0) = 1, and, when
+ * grad_z is not NULL, dz/dx.  The z sums, E_b and dz/dx leave the pair pass
+ * in one launch (scps_eval_z_and_grad + scps_ratchet_energy take two more).
+ *   x: device float32 (x layout); z_m, z, E_b: device float64 [R];
+ *   grad_z: device float32 (x layout) or NULL.
+ * Asynchronous.  Errors: INVALID_ARG (x, z_m, z or E_b NULL), STATE (a
+ * system without its native map), HIP. */
+scps_status scps_eval_zbias(scps_ctx *ctx, const float *x, const double *z_m, double *z,
+                            double *E_b, float *grad_z);
+
+/* Backward of the differentiable rMD bias in one launch: for every replica r,
+ *   grad_x = grad_z * (g_z[r] + g_E[r] k_R (z - z_m) theta(z - z_m)),
+ * the gradient of sum_r g_z[r] z_r + g_E[r] E_b,r with respect to x, from
+ * dz/dx kept by scps_eval_zbias (scps_ratchet_energy's coef and
+ * scps_scale_by_replica, fused).  g_z[r] is read at g_z[r * g_z_stride]
+ * (stride 0: one value for every replica, as the gradient of a sum arrives)
+ * and likewise g_E; either may be NULL (taken as 0).
+ *   z, z_m: device float64 [R]; grad_z, grad_x: device float32 (x layout;
+ *   grad_x may equal grad_z).
+ * Asynchronous.  Errors: INVALID_ARG (a NULL array other than g_z / g_E, a
+ * negative stride), HIP. */
+scps_status scps_zbias_backward(scps_ctx *ctx, const double *z, const double *z_m,
+                                const double *g_z, int64_t g_z_stride,
+                                const double *g_E, int64_t g_E_stride,
+                                const float *grad_z, float *grad_x);
+
 /* Path-ensemble mean contact map, eq (avCij): for every recorded frame k,
  * <C(t_k)>_p = (1/|S|) sum over successful paths p of C(X_p(t_k)), summed in
  * float64, and install the result as the system's SCPS frame stack

@@ -990,7 +990,8 @@ scps_status step_impl(scps_ctx *c, float *x, float *v, double *cv, int64_t n_ste
     return SCPS_OK;
 }
 
-scps_status eval_impl(scps_ctx *c, const float *x, double *z, float *grad, const double *coef) {
+scps_status eval_impl(scps_ctx *c, const float *x, double *z, float *grad, const double *coef,
+                      const double *z_m = nullptr, double *E_b = nullptr) {
     if (!x || !z) return fail(SCPS_ERR_INVALID_ARG, "x and z must not be NULL");
     for (int r = 0; r < c->R; ++r)
         if (!c->sys[c->rep_sys[r]].has_native)
@@ -999,8 +1000,7 @@ scps_status eval_impl(scps_ctx *c, const float *x, double *z, float *grad, const
     HIP_TRY(c, launch_pairs(grad ? 2 : 1, c->nbk, c->kp, c->d_sysd, c->d_reps, c->d_items_contact, c->n_items_contact,
                             c->d_xs, c->d_acc, c->d_zpart, nullptr, nullptr, c->stream));
     HIP_TRY(c, launch_eval_out(c->d_sysd, c->d_reps, c->R, c->n_pad_max, c->d_acc, c->d_first_con, c->d_zpart, z,
-                               grad, coef,
-                               c->stream));
+                               c->prm.k_R, z_m, E_b, grad, coef, c->stream));
     return SCPS_OK;
 }
 
@@ -1289,6 +1289,25 @@ scps_status scps_eval_z_and_grad(scps_ctx *ctx, const float *x, double *z, float
     scps_status st;
     if (!usable(ctx, &st)) return st;
     return eval_impl(ctx, x, z, grad, grad_coef);
+}
+
+scps_status scps_eval_zbias(scps_ctx *ctx, const float *x, const double *z_m, double *z, double *E_b, float *grad_z) {
+    scps_status st;
+    if (!usable(ctx, &st)) return st;
+    if (!z_m || !E_b) return fail(SCPS_ERR_INVALID_ARG, "z_m and E_b must not be NULL");
+    return eval_impl(ctx, x, z, grad_z, nullptr, z_m, E_b);
+}
+
+scps_status scps_zbias_backward(scps_ctx *ctx, const double *z, const double *z_m, const double *g_z,
+                                int64_t g_z_stride, const double *g_E, int64_t g_E_stride, const float *grad_z,
+                                float *grad_x) {
+    scps_status st;
+    if (!usable(ctx, &st)) return st;
+    if (!z || !z_m || !grad_z || !grad_x) return fail(SCPS_ERR_INVALID_ARG, "z, z_m, grad_z and grad_x must not be NULL");
+    if (g_z_stride < 0 || g_E_stride < 0) return fail(SCPS_ERR_INVALID_ARG, "gradient strides must be >= 0");
+    HIP_TRY(ctx, launch_zbias_backward(ctx->d_sysd, ctx->d_reps, ctx->R, ctx->n_pad_max, ctx->prm.k_R, z, z_m, g_z,
+                                       g_z_stride, g_E, g_E_stride, grad_z, grad_x, ctx->stream));
+    return SCPS_OK;
 }
 
 scps_status scps_ratchet_energy(scps_ctx *ctx, const double *z, const double *z_m, double *E_b, const double *gz,

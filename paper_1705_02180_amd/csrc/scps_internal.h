@@ -219,9 +219,15 @@ hipError_t launch_integrate(const KParams &P, const SysDesc *sysd, const RepDesc
 // *d = v (one thread), in stream order
 hipError_t launch_set_step(uint64_t *d, uint64_t v, hipStream_t st);
 
+// z[r] from the pass's partials, E_b[r] when zm is not NULL, and (grad not
+// NULL) grad_coef * grad z out of the accumulators, clearing them
 hipError_t launch_eval_out(const SysDesc *sysd, const RepDesc *reps, int R, int n_pad_max, double *acc,
-                           const int *first, const double *zpart, double *z_out, float *grad,
-                           const double *grad_coef, hipStream_t st);
+                           const int *first, const double *zpart, double *z_out, double k_R, const double *zm,
+                           double *Eb, float *grad, const double *grad_coef, hipStream_t st);
+// out = in * (gz[r sz] + gE[r sE] k_R (z - zm) theta) per replica
+hipError_t launch_zbias_backward(const SysDesc *sysd, const RepDesc *reps, int R, int n_pad_max, double k_R,
+                                 const double *z, const double *zm, const double *gz, int64_t sz, const double *gE,
+                                 int64_t sE, const float *in, float *out, hipStream_t st);
 hipError_t launch_ratchet_energy(int R, double k_R, const double *z, const double *zm, double *Eb,
                                  const double *gz, const double *gE, double *coef, hipStream_t st);
 

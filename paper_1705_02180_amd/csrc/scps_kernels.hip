@@ -1149,7 +1149,7 @@ hipError_t launch_scatter(const SysDesc *sysd, const RepDesc *reps, int R, int n
 // One wavefront per tile item; four per workgroup.  Force partial sums go to
 // the float64 accumulators in global memory with hardware float64 atomics;
 // the item's z partial to zpart[item] (summed per replica in a fixed order by
-// k_finalize_rmd / k_reduce_z, so no two tiles meet on one address).  In
+// k_finalize_rmd / k_eval_out, so no two tiles meet on one address).  In
 // PM_SCPS the contact reference of replica r is its effective reference
 // E + eoff_r (written by k_scps_eff) and csum[r] = sum_k c_k.
 template <int MODE, int NBK>
@@ -1685,12 +1685,6 @@ hipError_t launch_nl_force(int nbk, const KParams &P, const SysDesc *sysd, const
     return hipGetLastError();
 }
 
-__global__ void k_reduce_z(const int *__restrict__ first, const double *__restrict__ zpart, double *__restrict__ z) {
-    const int r = blockIdx.x;
-    const double v = replica_z(first, zpart, r, threadIdx.x);
-    if (threadIdx.x == 0) z[r] = v;
-}
-
 
 // SCPS tube variables per replica (one wavefront each), from the squared
 // distances d_k Z0 = sum_p (C_p - R_kp)^2 to every frame k = 0..M of the
@@ -1846,10 +1840,28 @@ hipError_t launch_set_step(uint64_t *d, uint64_t v, hipStream_t st) {
     return hipGetLastError();
 }
 
-// z and coef * grad z out of the accumulators (eval_z_and_grad); clears them.
+// Output of the z pass (eval_z_and_grad, eval_zbias), one launch: the first
+// wavefront of column 0 sums replica r's z partials into z[r] and, when zm is
+// given, writes the ratchet energy Eb[r] = 1/2 k_R (z - z_m)^2 theta(z - z_m)
+// (eq (FrMD)); when grad is given, every column writes coef * grad z out of the
+// accumulators and clears them.  The grid has one column without grad.
 __global__ void k_eval_out(const SysDesc *__restrict__ sysd, const RepDesc *__restrict__ reps,
+                           const int *__restrict__ first, const double *__restrict__ zpart, double *__restrict__ z_out,
+                           const double k_R, const double *__restrict__ zm, double *__restrict__ Eb,
                            double *__restrict__ acc, float *__restrict__ grad, const double *__restrict__ grad_coef) {
     const int r = blockIdx.y;
+    if (blockIdx.x == 0 && threadIdx.x < 64) {
+        const double z = replica_z(first, zpart, r, threadIdx.x);
+        if (threadIdx.x == 0) {
+            z_out[r] = z;
+            if (zm) {
+                const double d = z - zm[r];
+                const double th = d >= 0.0 ? 1.0 : 0.0;  // theta(0) = 1
+                Eb[r] = 0.5 * k_R * d * d * th;
+            }
+        }
+    }
+    if (!grad) return;
     const RepDesc rd = reps[r];
     const SysDesc S = sysd[rd.sys];
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1867,12 +1879,37 @@ __global__ void k_eval_out(const SysDesc *__restrict__ sysd, const RepDesc *__re
 }
 
 hipError_t launch_eval_out(const SysDesc *sysd, const RepDesc *reps, int R, int n_pad_max, double *acc,
-                           const int *first, const double *zpart, double *z_out, float *grad, const double *grad_coef,
-                           hipStream_t st) {
-    hipLaunchKernelGGL(k_reduce_z, dim3(R), dim3(64), 0, st, first, zpart, z_out);
-    if (grad)
-        hipLaunchKernelGGL(k_eval_out, dim3((n_pad_max + 255) / 256, R), dim3(256), 0, st, sysd, reps, acc, grad,
-                           grad_coef);
+                           const int *first, const double *zpart, double *z_out, double k_R, const double *zm,
+                           double *Eb, float *grad, const double *grad_coef, hipStream_t st) {
+    const int cols = grad ? (n_pad_max + 255) / 256 : 1;
+    hipLaunchKernelGGL(k_eval_out, dim3(cols, R), dim3(256), 0, st, sysd, reps, first, zpart, z_out, k_R, zm, Eb, acc,
+                       grad, grad_coef);
+    return hipGetLastError();
+}
+
+// grad_x = grad_z * (g_z + g_E k_R (z - z_m) theta(z - z_m)) over replica r's
+// coordinates (x layout), for every replica: the backward of z and E_b from
+// a kept dz/dx in one launch.  g_z and g_E are read with element strides
+// (0: one value for all replicas) and may be NULL (taken as 0).
+__global__ void k_zbias_backward(const SysDesc *__restrict__ sysd, const RepDesc *__restrict__ reps, const double k_R,
+                                 const double *__restrict__ z, const double *__restrict__ zm,
+                                 const double *__restrict__ gz, const int64_t sz, const double *__restrict__ gE,
+                                 const int64_t sE, const float *__restrict__ in, float *__restrict__ out) {
+    const int r = blockIdx.y;
+    const RepDesc rd = reps[r];
+    const int n3 = 3 * sysd[rd.sys].n;
+    const double d = z[r] - zm[r];
+    const double th = d >= 0.0 ? 1.0 : 0.0;  // theta(0) = 1
+    const double c = (gz ? gz[r * sz] : 0.0) + (gE ? gE[r * sE] : 0.0) * k_R * d * th;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n3; e += gridDim.x * blockDim.x)
+        out[3 * rd.off + e] = (float)(c * (double)in[3 * rd.off + e]);
+}
+
+hipError_t launch_zbias_backward(const SysDesc *sysd, const RepDesc *reps, int R, int n_pad_max, double k_R,
+                                 const double *z, const double *zm, const double *gz, int64_t sz, const double *gE,
+                                 int64_t sE, const float *in, float *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_zbias_backward, dim3((3 * n_pad_max + 255) / 256, R), dim3(256), 0, st, sysd, reps, k_R, z,
+                       zm, gz, sz, gE, sE, in, out);
     return hipGetLastError();
 }
 

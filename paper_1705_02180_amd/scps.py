@@ -103,6 +103,10 @@ _lib.scps_funnel_mean_path.restype = C.c_int
 _lib.scps_funnel_mean_path.argtypes = [_i32, _i32, _vp, _vp, _vp, _vp]
 _lib.scps_scale_by_replica.restype = C.c_int
 _lib.scps_scale_by_replica.argtypes = [_vp, _vp, _vp, _vp]
+_lib.scps_eval_zbias.restype = C.c_int
+_lib.scps_eval_zbias.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
+_lib.scps_zbias_backward.restype = C.c_int
+_lib.scps_zbias_backward.argtypes = [_vp, _vp, _vp, _vp, _i64, _vp, _i64, _vp, _vp]
 _lib.scps_destroy.restype = None
 _lib.scps_destroy.argtypes = [_vp]
 _lib.scps_last_error.restype = C.c_char_p
@@ -112,7 +116,8 @@ EXPORTS = ["scps_init_system", "scps_set_reference_map", "scps_step_replicas", "
            "scps_ratchet_energy", "scps_update_reference_from_paths", "scps_set_stream", "scps_sync",
            "scps_autotune", "scps_set_launch", "scps_get_launch", "scps_set_graph_steps", "scps_least_biased_path", "scps_eval_tube", "scps_eval_sigma", "scps_path_distance",
            "scps_path_distance_noalloc", "scps_time_passes", "scps_pass_times",
-           "scps_funnel_steps", "scps_funnel_mean_path", "scps_scale_by_replica", "scps_destroy",
+           "scps_funnel_steps", "scps_funnel_mean_path", "scps_scale_by_replica", "scps_eval_zbias",
+           "scps_zbias_backward", "scps_destroy",
            "scps_last_error"]
 
 
@@ -139,6 +144,23 @@ def _dev(t: Optional[torch.Tensor], dtype, numel: Optional[int] = None, name: st
     if numel is not None and t.numel() != numel:
         raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
     return C.c_void_p(t.data_ptr())
+
+
+def _dev_vec(t: Optional[torch.Tensor], dtype, n: int, name: str):
+    """(pointer, element stride) of a 1-D device tensor of n elements that may
+    be strided or broadcast (stride 0, as the gradient of a sum arrives)."""
+    if t is None:
+        return None, 0
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.dim() != 1 or t.shape[0] != n:
+        raise ValueError(f"{name} must have shape [{n}], got {list(t.shape)}")
+    stride = t.stride(0) if n > 1 else 0
+    if stride < 0:
+        raise ValueError(f"{name} must have a non-negative stride")
+    return C.c_void_p(t.data_ptr()), stride
 
 
 def make_params(d: dict, exec_mode: int = 0, replica_base: int = 0) -> Params:
@@ -281,6 +303,23 @@ class Context:
                                           _dev(coef, torch.float64, self.R, "coef"),
                                           _dev(out, torch.float32, n3, "out")))
 
+    def eval_zbias(self, x: torch.Tensor, z_m: torch.Tensor, z: torch.Tensor, E_b: torch.Tensor,
+                   grad_z: Optional[torch.Tensor] = None):
+        n3, R = 3 * self.sumN, self.R
+        _check(_lib.scps_eval_zbias(self._ctx(), _dev(x, torch.float32, n3, "x"), _dev(z_m, torch.float64, R, "z_m"),
+                                    _dev(z, torch.float64, R, "z"), _dev(E_b, torch.float64, R, "E_b"),
+                                    _dev(grad_z, torch.float32, n3, "grad_z")))
+
+    def zbias_backward(self, z: torch.Tensor, z_m: torch.Tensor, g_z: Optional[torch.Tensor],
+                       g_E: Optional[torch.Tensor], grad_z: torch.Tensor, grad_x: torch.Tensor):
+        n3, R = 3 * self.sumN, self.R
+        pz, sz = _dev_vec(g_z, torch.float64, R, "g_z")
+        pe, se = _dev_vec(g_E, torch.float64, R, "g_E")
+        _check(_lib.scps_zbias_backward(self._ctx(), _dev(z, torch.float64, R, "z"),
+                                        _dev(z_m, torch.float64, R, "z_m"), pz, int(sz), pe, int(se),
+                                        _dev(grad_z, torch.float32, n3, "grad_z"),
+                                        _dev(grad_x, torch.float32, n3, "grad_x")))
+
     def autotune(self, x: torch.Tensor, v: Optional[torch.Tensor], cvstate: torch.Tensor, n_steps: int):
         """Time the launch configurations on copies of the state and keep the
         fastest; returns (path, param): path 0 persistent, 1 per-step, 2
@@ -384,35 +423,41 @@ def update_reference_from_paths(ctx: Context, system, frames, n_paths, n_frames,
     return ctx.update_reference_from_paths(system, frames, n_paths, n_frames, success, want_maps)
 
 
+def eval_zbias(ctx: Context, x, z_m, z, E_b, grad_z=None):
+    return ctx.eval_zbias(x, z_m, z, E_b, grad_z)
+
+
+def zbias_backward(ctx: Context, z, z_m, g_z, g_E, grad_z, grad_x):
+    return ctx.zbias_backward(z, z_m, g_z, g_E, grad_z, grad_x)
+
+
 class ZBias(torch.autograd.Function):
     """z(X) and the rMD bias energy E_b = 1/2 k_R (z - z_m)^2 theta(z - z_m) as a
     differentiable function of the coordinates.  When x needs a gradient,
     forward runs the z + dz/dx pair pass once and keeps dz/dx (O(N) per
     replica; no map of the current contacts is stored); backward scales it by
     g_z + g_E k_R (z - z_m) theta per replica.  Otherwise forward evaluates z
-    alone."""
+    alone.  Forward and backward are one library call each (scps_eval_zbias,
+    scps_zbias_backward): three launches in all beside the pair pass."""
 
     @staticmethod
     def forward(ctx_, x: torch.Tensor, z_m: torch.Tensor, lib_ctx: Context):
         z = torch.empty(lib_ctx.R, dtype=torch.float64, device=x.device)
-        dz = torch.empty_like(x) if ctx_.needs_input_grad[0] else None
-        lib_ctx.eval_z_and_grad(x, z, dz)
         Eb = torch.empty_like(z)
-        lib_ctx.ratchet_energy(z, z_m, Eb)
+        dz = torch.empty_like(x) if ctx_.needs_input_grad[0] else None
+        lib_ctx.eval_zbias(x, z_m, z, Eb, dz)
         ctx_.save_for_backward(z, z_m, dz)
         ctx_.lib_ctx = lib_ctx
         return z, Eb
 
     @staticmethod
     def backward(ctx_, gz: torch.Tensor, gE: torch.Tensor):
+        # gz, gE arrive broadcast (stride 0) from a sum: the library reads them strided
         z, z_m, dz = ctx_.saved_tensors
-        lib = ctx_.lib_ctx
-        coef = torch.empty_like(z)
-        gz = None if gz is None else gz.contiguous().to(torch.float64)
-        gE = None if gE is None else gE.contiguous().to(torch.float64)
-        lib.ratchet_energy(z, z_m, None, gz, gE, coef)
+        gz = None if gz is None else gz.to(torch.float64)
+        gE = None if gE is None else gE.to(torch.float64)
         grad = torch.empty_like(dz)
-        lib.scale_by_replica(dz, coef, grad)
+        ctx_.lib_ctx.zbias_backward(z, z_m, gz, gE, dz, grad)
         return grad, None, None
 
 

@@ -74,6 +74,8 @@ def test_host_validation_rejects_bad_arguments(lib):
     assert lib.scps_set_launch(None, 2, 4) == -1
     assert lib.scps_get_launch(None, None) == -1
     assert lib.scps_set_graph_steps(None, 16) == -1
+    assert lib.scps_eval_zbias(None, None, None, None, None, None) == -1
+    assert lib.scps_zbias_backward(None, None, None, None, C.c_int64(0), None, C.c_int64(0), None, None) == -1
     lib.scps_last_error.restype = C.c_char_p
     assert b"NULL" in lib.scps_last_error()
 

@@ -671,6 +671,63 @@ def test_zbias_partial_gradients_and_no_grad_forward(S):
     ctx.close()
 
 
+def test_fused_zbias_calls_match_the_separate_calls(S):
+    """scps_eval_zbias against scps_eval_z_and_grad + scps_ratchet_energy (z
+    and E_b bit for bit, dz/dx up to the order of the float64 atomic sums)
+    and scps_zbias_backward against scps_ratchet_energy's coef +
+    scps_scale_by_replica (bit for bit) with contiguous, broadcast (stride 0)
+    and strided incoming gradients, one of them absent; a forward without
+    dz/dx gives the same z and E_b; argument errors come from the library."""
+    import ctypes as C
+    import torch
+    base = dict(I._base_params(), k_R=4e-3)
+    w = single_system_workload(330, np.arange(330), base, 5)
+    sy = w.systems[0]
+    ctx = context(S, w)
+    R = 5
+    X = states(sy, R, 23)
+    x = dev(X.ravel())
+    z0 = torch.empty(R, dtype=torch.float64, device="cuda")
+    ctx.eval_z_and_grad(x, z0)
+    zm = z0 * torch.tensor([0.8, 1.2, 1.0, 0.5, 1.01], dtype=torch.float64, device="cuda")
+    z_a, eb_a = torch.empty_like(z0), torch.empty_like(z0)
+    dz_a = torch.empty_like(x)
+    ctx.eval_z_and_grad(x, z_a, dz_a)
+    ctx.ratchet_energy(z_a, zm, eb_a)
+    z_b, eb_b = torch.empty_like(z0), torch.empty_like(z0)
+    dz_b = torch.empty_like(x)
+    ctx.eval_zbias(x, zm, z_b, eb_b, dz_b)
+    assert torch.equal(z_a, z_b) and torch.equal(eb_a, eb_b)
+    assert (host(eb_b) > 0).any() and (host(eb_b) == 0).any()        # replicas on both sides of z_m
+    np.testing.assert_allclose(host(dz_b), host(dz_a), rtol=1e-6, atol=1e-7 * np.abs(host(dz_a)).max())
+    z_c, eb_c = torch.empty_like(z0), torch.empty_like(z0)
+    ctx.eval_zbias(x, zm, z_c, eb_c, None)
+    np.testing.assert_allclose(host(z_c), host(z_b), rtol=1e-8)
+    np.testing.assert_allclose(host(eb_c), host(eb_b), rtol=1e-6, atol=1e-12)
+    rng = np.random.default_rng(24)
+    gz_full = dev(rng.normal(size=2 * R), "f64")
+    cases = [(dev(rng.normal(size=R), "f64"), dev(rng.normal(size=R), "f64")),
+             (torch.full((1,), 1.5, dtype=torch.float64, device="cuda").expand(R), None),
+             (None, torch.full((1,), -0.7, dtype=torch.float64, device="cuda").expand(R)),
+             (gz_full[::2], gz_full[1::2])]
+    for gz, gE in cases:
+        coef = torch.empty_like(z0)
+        ctx.ratchet_energy(z_b, zm, None, None if gz is None else gz.contiguous(),
+                           None if gE is None else gE.contiguous(), coef)
+        want = torch.empty_like(x)
+        ctx.scale_by_replica(dz_b, coef, want)
+        got = torch.empty_like(x)
+        ctx.zbias_backward(z_b, zm, gz, gE, dz_b, got)
+        assert torch.equal(got, want)
+    lib, h = S._lib, ctx._ctx()
+    p = lambda t: C.c_void_p(t.data_ptr())
+    assert lib.scps_zbias_backward(h, p(z_b), p(zm), p(z_b), C.c_int64(-1), None, C.c_int64(0), p(dz_b),
+                                   p(got)) == -1
+    assert lib.scps_zbias_backward(h, p(z_b), None, None, C.c_int64(0), None, C.c_int64(0), p(dz_b), p(got)) == -1
+    assert lib.scps_eval_zbias(h, p(x), None, p(z_c), p(eb_c), None) == -1
+    ctx.close()
+
+
 # ---------------------------------------------------------------------------
 # the benchmark configuration at full size, sampled replicas
 # ---------------------------------------------------------------------------
