@@ -1103,10 +1103,12 @@ hipError_t launch_scps_dist(const KParams &P, const SysDesc *sysd, const RepDesc
     const int nfb = (max_frames + 63) / 64;
     // a grid of the resident workgroups (256 CUs) striding over the work
     // units; too few items for that (small systems) split each tile's rows
-    // over up to 8 workgroups
+    // over up to 16 workgroups (4 rows each, half the wavefronts without a
+    // row: still faster than 8 at 32 x 560, while 16 sub-step ranges of the
+    // bias pass were slower than 8)
     auto split = [&](int resident) {
         int ns = 1;
-        while (ns < 8 && n_items * nfb * ns * 2 <= resident) ns *= 2;
+        while (ns < 16 && n_items * nfb * ns * 2 <= resident) ns *= 2;
         return ns;
     };
     if (nfb > 1) {
