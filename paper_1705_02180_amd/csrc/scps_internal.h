@@ -188,7 +188,7 @@ hipError_t launch_finalize_rmd(const KParams &P, int R, const int *first, const 
 // Neighbour lists of the cutoff variant (rMD with both cutoffs): NL_CAP
 // entries per particle, radius (larger cutoff) + NL_SKIN.
 constexpr int NL_CAP = 512;
-constexpr float NL_SKIN = 1.5f;
+constexpr float NL_SKIN = 2.0f;
 // Rebuild the lists of the replicas that need it (force: all of them).
 // first_blk [R+1]: blocks of 64 before each replica; bounds [R][nb_max],
 // xref [sum n_pad], bmax [sum nb], rebuild [R], cnt [sum n_pad],

@@ -1329,11 +1329,14 @@ hipError_t launch_finalize_rmd(const KParams &P, int R, const int *first, const 
 //   z = sum over all counted pairs of R^2 + sum over listed pairs of C (C - 2R)
 // and each unordered pair is listed twice (once per side).
 
-// Bounding sphere of block b of replica r (one wavefront): centroid of its
-// real particles and the largest distance from it.
-__global__ __launch_bounds__(64) void k_block_bounds(const SysDesc *__restrict__ sysd,
-                                                     const RepDesc *__restrict__ reps, int nb_max,
-                                                     const float4 *__restrict__ xs, float4 *__restrict__ bounds) {
+// Per block b of replica r (one wavefront): its bounding sphere (centroid of
+// its real particles and the largest distance from it) into bounds, and the
+// largest squared displacement of its particles since the last build into
+// bmax[first[r] + b].
+__global__ __launch_bounds__(64) void k_nl_blocks(const SysDesc *__restrict__ sysd, const RepDesc *__restrict__ reps,
+                                                  int nb_max, const int *__restrict__ first,
+                                                  const float4 *__restrict__ xs, const float4 *__restrict__ xref,
+                                                  float4 *__restrict__ bounds, float *__restrict__ bmax) {
     const int b = blockIdx.x, r = blockIdx.y, lane = threadIdx.x;
     const RepDesc rd = reps[r];
     const int n = sysd[rd.sys].n, nb = sysd[rd.sys].nb;
@@ -1341,6 +1344,13 @@ __global__ __launch_bounds__(64) void k_block_bounds(const SysDesc *__restrict__
     const int i = b * 64 + lane;
     const bool valid = i < n;
     const float4 p = xs[2 * rd.poff + b * 128 + lane];
+    float m2 = 0.f;
+    if (valid) {
+        const float4 q = xref[rd.poff + i];
+        const float dx = p.x - q.x, dy = p.y - q.y, dz = p.z - q.z;
+        m2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+        if (!(m2 <= 3.0e38f)) m2 = 3.0e38f;           // a non-finite position forces a rebuild
+    }
     const double cnt = wave_sum(valid ? 1.0 : 0.0);
     const double cx = wave_sum(valid ? (double)p.x : 0.0) / cnt;
     const double cy = wave_sum(valid ? (double)p.y : 0.0) / cnt;
@@ -1348,30 +1358,14 @@ __global__ __launch_bounds__(64) void k_block_bounds(const SysDesc *__restrict__
     const double dx = (double)p.x - cx, dy = (double)p.y - cy, dz = (double)p.z - cz;
     double d2 = valid ? dx * dx + dy * dy + dz * dz : 0.0;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) d2 = fmax(d2, __shfl_xor(d2, o, 64));
-    if (lane == 0) bounds[(int64_t)r * nb_max + b] = make_float4((float)cx, (float)cy, (float)cz, (float)sqrt(d2));
-}
-
-// Largest squared displacement of the particles of block b since the last
-// build (one wavefront per block); bmax[first[r] + b].
-__global__ __launch_bounds__(64) void k_nl_disp(const SysDesc *__restrict__ sysd, const RepDesc *__restrict__ reps,
-                                                const int *__restrict__ first, const float4 *__restrict__ xs,
-                                                const float4 *__restrict__ xref, float *__restrict__ bmax) {
-    const int b = blockIdx.x, r = blockIdx.y, lane = threadIdx.x;
-    const RepDesc rd = reps[r];
-    const int n = sysd[rd.sys].n, nb = sysd[rd.sys].nb;
-    if (b >= nb) return;
-    const int i = b * 64 + lane;
-    float d2 = 0.f;
-    if (i < n) {
-        const float4 p = xs[2 * rd.poff + b * 128 + lane], q = xref[rd.poff + i];
-        const float dx = p.x - q.x, dy = p.y - q.y, dz = p.z - q.z;
-        d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-        if (!(d2 <= 3.0e38f)) d2 = 3.0e38f;           // a non-finite position forces a rebuild
+    for (int o = 32; o > 0; o >>= 1) {
+        d2 = fmax(d2, __shfl_xor(d2, o, 64));
+        m2 = fmaxf(m2, __shfl_xor(m2, o, 64));
     }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) d2 = fmaxf(d2, __shfl_xor(d2, o, 64));
-    if (lane == 0) bmax[first[r] + b] = d2;
+    if (lane == 0) {
+        bounds[(int64_t)r * nb_max + b] = make_float4((float)cx, (float)cy, (float)cz, (float)sqrt(d2));
+        bmax[first[r] + b] = m2;
+    }
 }
 
 // Decide per replica whether to rebuild (force, or a displacement beyond
@@ -1657,8 +1651,7 @@ hipError_t launch_nl_update(const KParams &P, const SysDesc *sysd, const RepDesc
                             int *rebuild, int force, const TileItem *items_all, const int *first_all, float r_list,
                             int *cnt, int2 *nl, int *flags, hipStream_t st) {
     const dim3 blocks(nb_max, R);
-    hipLaunchKernelGGL(k_block_bounds, blocks, dim3(64), 0, st, sysd, reps, nb_max, xs, bounds);
-    hipLaunchKernelGGL(k_nl_disp, blocks, dim3(64), 0, st, sysd, reps, first_blk, xs, xref, bmax);
+    hipLaunchKernelGGL(k_nl_blocks, blocks, dim3(64), 0, st, sysd, reps, nb_max, first_blk, xs, xref, bounds, bmax);
     hipLaunchKernelGGL(k_nl_reset, blocks, dim3(64), 0, st, sysd, reps, first_blk, xs, xref, bmax, force, rebuild,
                        cnt);
     hipLaunchKernelGGL(k_nl_build, dim3(NL_BUILD_WG), dim3(256), 0, st, P, sysd, reps, R, items_all, first_all, xs,
