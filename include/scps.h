@@ -103,8 +103,8 @@ typedef struct {
                              (short chains one or several to a wavefront; see scps_set_launch);
                              SCPS_EXEC_PER_STEP: a few kernel launches per step (always used for SCPS and large chains);
                              with r_cut_contact and r_cut_nb both > 0 in rMD mode, this path evaluates the pairs of
-                             per-particle neighbour lists instead of every pair: radius (larger cutoff) + 1.5 A,
-                             rebuilt for a replica when one of its particles has moved more than 0.75 A since the
+                             per-particle neighbour lists instead of every pair: radius (larger cutoff) + 2 A,
+                             rebuilt for a replica when one of its particles has moved more than 1 A since the
                              last build (also by the caller between calls) or the reference map changed, at most
                              512 entries per particle
                              (scps_sync reports NONFINITE for a replica that would need more);
