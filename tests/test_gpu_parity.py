@@ -728,6 +728,46 @@ def test_fused_zbias_calls_match_the_separate_calls(S):
     ctx.close()
 
 
+def test_zbias_on_uneven_systems_matches_oracle(S):
+    """The autograd wrapper over replicas of two chains of different lengths
+    (one with every third particle in the contact set), interleaved: z, E_b
+    and the gradient of z + 2 E_b per replica against the oracle (the fused
+    forward and backward index each replica's own particles and order)."""
+    import torch
+    base = dict(I._base_params(), k_R=5e-3)
+    rng = np.random.default_rng(41)
+    systems = []
+    for n, kind, seed in ((150, "all", 42), (333, "every3", 43)):
+        systems.append(I.System(n=n, contact_idx=np.asarray(_cidx(n, kind), dtype=np.int32),
+                                mass=np.full(n, 12.011 * I.AMU, dtype=np.float32),
+                                charge=rng.normal(0, 0.3, n).astype(np.float32), native=I.compact_native(n, seed),
+                                start=I.persistent_start(n, seed + 1)))
+    rsys = np.array([1, 0, 1, 0, 1], dtype=np.int32)
+    R = len(rsys)
+    w = I.Workload("two_chains_zbias", dict(base), systems, rsys, 1)
+    ctx = context(S, w)
+    X = [_clean_starts(systems[s], 1, 50 + r)[0] for r, s in enumerate(rsys)]
+    osys = [O.System.from_inputs(sy, base) for sy in systems]
+    zr = [O.z_grad(X[r].astype(np.float64), osys[s].cidx, osys[s].native) for r, s in enumerate(rsys)]
+    zm = np.array([0.7, 1.3, 0.9, 1.1, 0.5]) * np.array([z[0] for z in zr])
+    x = dev(np.concatenate([xr.ravel() for xr in X])).requires_grad_(True)
+    z, Eb = S.zbias(x, dev(zm, "f64"), ctx)
+    (z.sum() + 2.0 * Eb.sum()).backward()
+    G, zg, Ebg = host(x.grad), host(z), host(Eb)
+    off = 0
+    for r, s in enumerate(rsys):
+        n = systems[s].n
+        d = zr[r][0] - zm[r]
+        th = 1.0 if d >= 0 else 0.0
+        assert abs(zg[r] - zr[r][0]) <= 1e-5 * zr[r][0]
+        assert abs(Ebg[r] - 0.5 * base["k_R"] * d * d * th) <= 1e-4 * max(0.5 * base["k_R"] * d * d, 1e-12)
+        want = (1.0 + 2.0 * base["k_R"] * d * th) * zr[r][1]
+        assert normwise(G[3 * off:3 * (off + n)].reshape(3, n), want) <= TOL, r
+        off += n
+    assert off * 3 == G.size
+    ctx.close()
+
+
 # ---------------------------------------------------------------------------
 # the benchmark configuration at full size, sampled replicas
 # ---------------------------------------------------------------------------
