@@ -891,12 +891,29 @@ __global__ __launch_bounds__(512) void k_rmd_packed(const KParams P, const SysDe
     // the sum over the lanes of this lane's segment: a binary tree in a fixed
     // order (lane a takes a + s for s = 1, 2, 4, ... while a is a multiple of
     // 2s), then the segment's first lane's total to every lane, so that all
-    // lanes of a replica hold the same value
+    // lanes of a replica hold the same value.  Each level's take flag (bit l
+    // of seg_take) and partner address are fixed for the call.
+    constexpr int SEG_LEVELS = 6;   // W <= 64
+    uint32_t seg_take = 0u;
+    int seg_from[SEG_LEVELS];
+#pragma unroll
+    for (int l = 0; l < SEG_LEVELS; ++l) {
+        const int s = 1 << l;
+        const bool take = s < W && ((a & (2 * s - 1)) == 0) && a + s < n;
+        seg_take |= take ? 1u << l : 0u;
+        seg_from[l] = (take ? lane + s : lane) << 2;
+    }
     auto seg_sum = [&](double val) {
-        for (int s = 1; s < W; s <<= 1) {
-            const bool take = ((a & (2 * s - 1)) == 0) && a + s < n;
-            const double o = bpermute_f64((take ? lane + s : lane) << 2, val);
-            val = take ? val + o : val;
+        // an opaque copy: tests of a loop-invariant value would be hoisted out
+        // of the step loop as lane masks held in (spilled) scalar registers
+        uint32_t tk = seg_take;
+        asm volatile("" : "+v"(tk));
+#pragma unroll
+        for (int l = 0; l < SEG_LEVELS; ++l) {
+            if ((1 << l) < W) {   // uniform
+                const double o = bpermute_f64(seg_from[l], val);
+                val = ((tk >> l) & 1u) ? val + o : val;
+            }
         }
         return bpermute_f64(sbase << 2, val);
     };
