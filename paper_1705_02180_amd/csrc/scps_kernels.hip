@@ -1580,9 +1580,9 @@ __global__ __launch_bounds__(256) void k_nl_build(const KParams P, const SysDesc
 // 256 / NL_LANES particles.  Only i's side of each listed pair is added (the
 // pair is listed for j as well).  zpart[first[r] + chunk] = the chunk's sum
 // of C (C - 2R) / 2.
-constexpr int NL_LANES = 8;
+constexpr int NL_LANES = 4;
 constexpr int NL_CHUNK = 256 / NL_LANES;
-constexpr int NL_BATCH = 4;
+constexpr int NL_BATCH = 8;
 template <int NBK>
 __global__ __launch_bounds__(256) void k_nl_force(const KParams P, const SysDesc *__restrict__ sysd,
                                                   const RepDesc *__restrict__ reps, const int *__restrict__ first,
