@@ -100,7 +100,7 @@ struct scps_ctx {
     TileItem *d_items_contact = nullptr;
     int n_items_contact = 0;
     float4 *d_xs = nullptr, *d_vs = nullptr;
-    double *d_acc = nullptr, *d_scale = nullptr, *d_negone = nullptr;
+    double *d_acc = nullptr, *d_negone = nullptr;
     double *d_zpart = nullptr;                       // z partial of every tile item
     int *d_first_all = nullptr, *d_first_con = nullptr;   // [R+1] item ranges per replica
     double *d_X = nullptr, *d_Q = nullptr, *d_csum = nullptr;   // SCPS: sum u R_k, sum u^2, sum c_k (u = C - R_j)
@@ -629,7 +629,6 @@ scps_status init_impl(const scps_params *params, const scps_topology *topo, int3
     HIP_TRY(c, dalloc(c, &c->d_vs, c->sumNpad));
     HIP_TRY(c, dalloc(c, &c->d_acc, 6 * c->sumNpad));
     HIP_TRY(c, hipMemset(c->d_acc, 0, 6 * c->sumNpad * sizeof(double)));
-    HIP_TRY(c, dalloc(c, &c->d_scale, R));
     HIP_TRY(c, dalloc(c, &c->d_negone, R));
     std::vector<double> neg(R, -1.0);
     HIP_TRY(c, hipMemcpy(c->d_negone, neg.data(), R * sizeof(double), hipMemcpyHostToDevice));
@@ -816,9 +815,9 @@ scps_status step_launches(scps_ctx *c, double *cv, uint64_t step, const uint64_t
     if (c->prm.bias_mode != SCPS_BIAS_SCPS) {
         HIP_TRY(c, launch_pairs(0, c->nbk, c->kp, c->d_sysd, c->d_reps, c->d_items_all, c->n_items_all, c->d_xs,
                                 c->d_acc, c->d_zpart, nullptr, nullptr, st));
-        HIP_TRY(c, launch_finalize_rmd(c->kp, c->R, c->d_first_all, c->d_zpart, nullptr, cv, c->d_scale, st));
         HIP_TRY(c, launch_integrate(c->kp, c->d_sysd, c->d_reps, c->R, c->n_pad_max, c->d_xs, c->d_vs, c->d_acc,
-                                    c->d_scale, cv, step, step_base, c->d_flags, st));
+                                    nullptr, cv, step, step_base, c->d_flags, st, c->d_first_all, c->d_zpart,
+                                    nullptr));
         return SCPS_OK;
     }
     // distances to every frame (matrix cores), tube variables and ratchets,
@@ -975,10 +974,9 @@ scps_status step_impl(scps_ctx *c, float *x, float *v, double *cv, int64_t n_ste
             c->nl_stale = false;
             HIP_TRY(c, launch_nl_force(c->nbk, c->kp, c->d_sysd, c->d_reps, c->R, c->n_pad_max, c->d_first_chunk,
                                        c->d_xs, c->d_nl_cnt, c->d_nl, c->d_acc, c->d_zpart_nl, c->stream));
-            HIP_TRY(c, launch_finalize_rmd(c->kp, c->R, c->d_first_chunk, c->d_zpart_nl, c->d_zbase, cv, c->d_scale,
-                                           c->stream));
             HIP_TRY(c, launch_integrate(c->kp, c->d_sysd, c->d_reps, c->R, c->n_pad_max, c->d_xs, c->d_vs, c->d_acc,
-                                        c->d_scale, cv, step0 + (uint64_t)m, nullptr, c->d_flags, c->stream));
+                                        nullptr, cv, step0 + (uint64_t)m, nullptr, c->d_flags, c->stream,
+                                        c->d_first_chunk, c->d_zpart_nl, c->d_zbase));
         } else {
             scps_status ss = step_launches(c, cv, step0 + (uint64_t)m, nullptr, true, c->stream);
             if (ss != SCPS_OK) return ss;

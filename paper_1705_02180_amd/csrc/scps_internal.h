@@ -181,10 +181,6 @@ hipError_t launch_stack_pairmajor(int nc, int ncb, int K, const float *stack, fl
 hipError_t launch_stack_gram(int nc, int ncb, int K, int min_sep, const int *perm, const float *stack, double *G,
                              hipStream_t st);
 
-// first[r] .. first[r+1]: replica r's items in the list whose z partials are in zpart
-// zbase: NULL, or a per-replica constant added to z (neighbour-list path).
-hipError_t launch_finalize_rmd(const KParams &P, int R, const int *first, const double *zpart,
-                               const double *zbase, double *cv, double *scale, hipStream_t st);
 // Neighbour lists of the cutoff variant (rMD with both cutoffs): NL_CAP
 // entries per particle, radius (larger cutoff) + NL_SKIN.
 constexpr int NL_CAP = 512;
@@ -212,10 +208,16 @@ hipError_t launch_tile_sumsq(int nc, int ncb, int min_sep, const int *perm, cons
 hipError_t launch_finalize_scps(const KParams &P, const SysDesc *sysd, const RepDesc *reps, int R,
                                 int kmax, int *jref, double *X, double *Q, double *cv, float *coef, double *csum,
                                 hipStream_t st);
+// The update of one step.  The contact-gradient accumulators are scaled by
+// scale[r], or, when zpart is not NULL, by the rMD ratchet of eq (FrMD)
+// computed in the same launch (cvstate's z, z_m and E_b written): z of
+// replica r = zbase[r] (when not NULL) + the sum of zpart[zfirst[r] ..
+// zfirst[r+1]).
 hipError_t launch_integrate(const KParams &P, const SysDesc *sysd, const RepDesc *reps, int R,
                             int n_pad_max, float4 *xs, float4 *vs, double *acc,
                             const double *scale, double *cv, uint64_t step, const uint64_t *step_base,
-                            int *flags, hipStream_t st);
+                            int *flags, hipStream_t st, const int *zfirst = nullptr,
+                            const double *zpart = nullptr, const double *zbase = nullptr);
 // *d = v (one thread), in stream order
 hipError_t launch_set_step(uint64_t *d, uint64_t v, hipStream_t st);
 

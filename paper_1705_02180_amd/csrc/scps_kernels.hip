@@ -1166,7 +1166,7 @@ hipError_t launch_scatter(const SysDesc *sysd, const RepDesc *reps, int R, int n
 // One wavefront per tile item; four per workgroup.  Force partial sums go to
 // the float64 accumulators in global memory with hardware float64 atomics;
 // the item's z partial to zpart[item] (summed per replica in a fixed order by
-// k_finalize_rmd / k_eval_out, so no two tiles meet on one address).  In
+// k_integrate / k_eval_out, so no two tiles meet on one address).  In
 // PM_SCPS the contact reference of replica r is its effective reference
 // E + eoff_r (written by k_scps_eff) and csum[r] = sum_k c_k.
 template <int MODE, int NBK>
@@ -1326,26 +1326,6 @@ __device__ __forceinline__ double replica_z(const int *__restrict__ first, const
     return wave_sum(zl);
 }
 
-// rMD ratchet per replica, eq (FrMD), from the replica's z.
-__global__ void k_finalize_rmd(const KParams P, const int *__restrict__ first, const double *__restrict__ zpart,
-                               const double *__restrict__ zbase, double *__restrict__ cv, double *__restrict__ scale) {
-    const int r = blockIdx.x;
-    const double z = (zbase ? zbase[r] : 0.0) + replica_z(first, zpart, r, threadIdx.x);
-    if (threadIdx.x != 0) return;
-    double *c = cv + (int64_t)r * CV_STRIDE;
-    const double zm = fmin(c[CV_ZM], z);
-    const double dz = z - zm;
-    c[CV_Z] = z;
-    c[CV_ZM] = zm;
-    c[CV_EB] = 0.5 * P.k_R * dz * dz;
-    scale[r] = -P.k_R * dz;
-}
-
-hipError_t launch_finalize_rmd(const KParams &P, int R, const int *first, const double *zpart,
-                               const double *zbase, double *cv, double *scale, hipStream_t st) {
-    hipLaunchKernelGGL(k_finalize_rmd, dim3(R), dim3(64), 0, st, P, first, zpart, zbase, cv, scale);
-    return hipGetLastError();
-}
 
 // ---------------------------------------------------------------------------
 // cutoff variant: neighbour lists (per-step rMD path)
@@ -1790,18 +1770,42 @@ __global__ __launch_bounds__(256) void k_integrate(const KParams P, const SysDes
                                                    float4 *__restrict__ vs, double *__restrict__ acc,
                                                    const double *__restrict__ scale, double *__restrict__ cv,
                                                    const uint64_t step_off, const uint64_t *__restrict__ step_base,
-                                                   int *__restrict__ flags) {
+                                                   int *__restrict__ flags, const int *__restrict__ zfirst,
+                                                   const double *__restrict__ zpart, const double *__restrict__ zbase) {
     __shared__ double tred[4];
+    __shared__ double sh_scale;
     const uint64_t step = step_off + (step_base ? *step_base : 0u);
     const int r = blockIdx.y;
     const RepDesc rd = reps[r];
     const SysDesc S = sysd[rd.sys];
+    if ((int)(blockIdx.x * blockDim.x) >= S.n) return;   // past a shorter chain's particles (uniform)
+    if (zpart) {
+        // the rMD ratchet, eq (FrMD), in every workgroup of the replica: z from
+        // its partials (the same fixed-order sum in each), z_m updated before
+        // the force is used; column 0 writes cvstate (a workgroup that reads
+        // the z_m column 0 has already written computes the same min again)
+        if (threadIdx.x < 64) {
+            const double z = (zbase ? zbase[r] : 0.0) + replica_z(zfirst, zpart, r, threadIdx.x);
+            if (threadIdx.x == 0) {
+                double *c = cv + (int64_t)r * CV_STRIDE;
+                const double zm = fmin(c[CV_ZM], z);
+                const double dz = z - zm;
+                if (blockIdx.x == 0) {
+                    c[CV_Z] = z;
+                    c[CV_ZM] = zm;
+                    c[CV_EB] = 0.5 * P.k_R * dz * dz;
+                }
+                sh_scale = -P.k_R * dz;
+            }
+        }
+        __syncthreads();
+    }
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     double tb = 0.0;
     if (a < S.n) {
         const int n_pad = S.n_pad;
         double *ar = acc + 6 * rd.poff;
-        const double sc = scale[r];
+        const double sc = zpart ? sh_scale : scale[r];
         const double inv_m = 1.0 / (double)S.mass[a];
         double F[3], fb2 = 0.0;
 #pragma unroll
@@ -1853,9 +1857,10 @@ __global__ __launch_bounds__(256) void k_integrate(const KParams P, const SysDes
 
 hipError_t launch_integrate(const KParams &P, const SysDesc *sysd, const RepDesc *reps, int R, int n_pad_max,
                             float4 *xs, float4 *vs, double *acc, const double *scale, double *cv, uint64_t step,
-                            const uint64_t *step_base, int *flags, hipStream_t st) {
+                            const uint64_t *step_base, int *flags, hipStream_t st, const int *zfirst,
+                            const double *zpart, const double *zbase) {
     hipLaunchKernelGGL(k_integrate, dim3((n_pad_max + 255) / 256, R), dim3(256), 0, st, P, sysd, reps, xs, vs, acc,
-                       scale, cv, step, step_base, flags);
+                       scale, cv, step, step_base, flags, zfirst, zpart, zbase);
     return hipGetLastError();
 }
 
