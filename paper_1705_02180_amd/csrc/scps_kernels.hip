@@ -1503,16 +1503,26 @@ __global__ __launch_bounds__(256) void k_nl_build(const KParams P, const SysDesc
                     for (int k = 0; k < 32; ++k) ring[k] = HR ? ldg(rt, k * 64 + lane) : 0.f;
                     // first walk: count the entries, and keep each sub-step's two tag
                     // bits (nonbonded, contact) in tb for the second walk
+                    // (16 sub-steps per word; after the four blocks tb[3 - q] holds
+                    // block q, the words having moved down one place per block)
                     uint32_t tb[4] = {0u, 0u, 0u, 0u};
                     int n_i = 0, n_j = 0;
+#pragma unroll 1
+                    for (int q = 0; q < 4; ++q) {
+                        uint32_t cur = 0u;
 #pragma unroll
-                    for (int k = 0; k < 64; ++k) {
-                        const uint32_t b = (uint32_t)tag_at(k) >> 29;
-                        tb[k >> 4] |= b << (2 * (k & 15));
-                        const int hit = b != 0u;
-                        n_i += hit;
-                        n_j = rot1i(n_j + hit);
-                        if ((k & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+                        for (int kk = 0; kk < 16; ++kk) {
+                            const uint32_t b = (uint32_t)tag_at(16 * q + kk) >> 29;
+                            cur |= b << (2 * kk);
+                            const int hit = b != 0u;
+                            n_i += hit;
+                            n_j = rot1i(n_j + hit);
+                            if ((kk & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+                        }
+                        tb[3] = tb[2];
+                        tb[2] = tb[1];
+                        tb[1] = tb[0];
+                        tb[0] = cur;
                     }
                     // after 64 rotations lane l holds the j-side count of particle l of block J
                     const int base_i = n_i ? atomicAdd(&ci[i], n_i) : 0;
@@ -1522,7 +1532,7 @@ __global__ __launch_bounds__(256) void k_nl_build(const KParams P, const SysDesc
                     // with its particle
                     int o_i = base_i, o_j = base_j;
                     auto put = [&](const int k, const float Rk) {
-                        const uint32_t b = (tb[k >> 4] >> (2 * (k & 15))) & 3u;
+                        const uint32_t b = (tb[3 - (k >> 4)] >> (2 * (k & 15))) & 3u;
                         if (b) {
                             const int j = shorg[wave][lane + k].y & 0x1FFFFFFF, tag = (int)(b << 29);
                             const float Rv = (b & 2u) ? Rk : 0.f;
