@@ -85,7 +85,8 @@ def parse():
     ap.add_argument("--replicas", type=int, default=0, help="0: the workload's own count")
     ap.add_argument("--graph-steps", type=int, default=None,
                     help="steps per replayed HIP graph on the per-step path (scps_set_graph_steps; "
-                         "uneven512 default: the block, 100; other workloads: the library's default, 0)")
+                         "uneven512 and scps560 default: the block, at most 256; other workloads: the "
+                         "library's default, 0)")
     ap.add_argument("--plain-replicas", type=int, default=8)
     ap.add_argument("--plain-steps", type=int, default=20)
     ap.add_argument("--cpu-steps", type=int, default=300)
@@ -672,10 +673,18 @@ def bench_scps6000(args, torch, I, scps, fip=False):
         step[0] += blk
 
     _, overlap = ctx.autotune(x, v, cvs, 10)                # on copies of the state, before timing
+    # the small chain's steps are short enough for launch costs to show: its
+    # steps replay captured graphs (whole blocks between recorded frames), and
+    # the passes are timed in a launch-by-launch segment after the timed
+    # region (pass timing keeps steps launch by launch)
+    gsteps = (min(blk, 256) if fip else 0) if args.graph_steps is None else args.graph_steps
+    ctx.set_graph_steps(0 if overlap else gsteps)
+    gsteps = 0 if overlap else gsteps
     for _ in range(args.warmup):
         block_call(0)
     ctx.sync()
-    ctx.time_passes(True)
+    if not gsteps:
+        ctx.time_passes(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for b in range(args.steps):
@@ -687,6 +696,11 @@ def bench_scps6000(args, torch, I, scps, fip=False):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     wall = t1 - t0
+    if gsteps:
+        ctx.time_passes(True)
+        for b in range(2):
+            block_call(b)
+        ctx.sync()
     pass_ms, timed = ctx.pass_times()
     ctx.time_passes(False)
     ctx.sync()
@@ -700,7 +714,8 @@ def bench_scps6000(args, torch, I, scps, fip=False):
         "iteration_steps": blk * args.steps,
         "launch": "per step: distance pass, ratchets, bias pass, update; nonbonded pass " +
                   ("beside the distance pass on a second stream" if overlap else "after the bias pass") +
-                  " (autotuned)"})
+                  " (autotuned)" + (f"; blocks of {gsteps} steps replayed from a captured HIP graph" if gsteps else ""),
+        "graph_steps": gsteps})
     out["contact_pair_evals_per_s"] = value * con
     out["eq_avCij_ms"] = 1e3 * (t1 - t_upd)
     out["parity"] = parity
@@ -716,6 +731,9 @@ def bench_scps6000(args, torch, I, scps, fip=False):
     out["roofline"] = roofline_hbm(stack_bytes, [per[dom]] * 1, names[dom],
                                    traffic.get(dom) if traffic else None)
     out["roofline"]["launches_timed"] = timed
+    if gsteps:
+        out["roofline"]["pass_timing"] = (f"HIP events around each pass over {timed} launch-by-launch steps "
+                                          f"after the timed region (the timed steps replay graphs)")
     other = "bias" if dom == "distance" else "distance"
     out["roofline_other_pass"] = roofline_hbm(stack_bytes, [per[other]], names[other],
                                               traffic.get(other) if traffic else None)
