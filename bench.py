@@ -678,8 +678,7 @@ def bench_scps6000(args, torch, I, scps, fip=False):
     # the passes are timed in a launch-by-launch segment after the timed
     # region (pass timing keeps steps launch by launch)
     gsteps = (min(blk, 256) if fip else 0) if args.graph_steps is None else args.graph_steps
-    ctx.set_graph_steps(0 if overlap else gsteps)
-    gsteps = 0 if overlap else gsteps
+    ctx.set_graph_steps(gsteps)
     for _ in range(args.warmup):
         block_call(0)
     ctx.sync()

@@ -395,8 +395,9 @@ scps_status scps_set_launch(scps_ctx *ctx, int32_t path, int32_t param);
  * cvstate buffer of the call (again when that buffer, the largest frame stack
  * or `steps` changes).  The noise is that of the same steps launched one by
  * one.  Steps run launch by launch where a block does not fit (before a
- * recorded frame or the end of a call) and with neighbour lists, the
- * overlapped SCPS schedule or pass timing.
+ * recorded frame or the end of a call) and with neighbour lists or pass
+ * timing.  The overlapped SCPS schedule is captured as two branches of the
+ * graph (the nonbonded pass on the context's second stream).
  *   steps: 0 (no graphs, the default) .. SCPS_MAX_GRAPH_STEPS.  Measured
  *   on MI355X with ROCm 7.2: an SCPS step of 32 replicas x 560 particles
  *   (tens of microseconds) takes 60 us replayed against 72 us launched one

@@ -75,6 +75,7 @@ struct scps_ctx {
     hipGraphExec_t gexec = nullptr;
     const double *g_cv = nullptr;     // what the graph was captured for
     int g_frames = 0, g_steps = 0;
+    bool g_overlap = false;
     uint64_t *d_step = nullptr;       // the replayed block's first step
     // scps_time_passes: HIP events around the SCPS step's two stack passes, in a ring
     // of PASS_RING slots (4 events each) whose oldest slot is read back before reuse
@@ -822,7 +823,9 @@ scps_status step_launches(scps_ctx *c, double *cv, uint64_t step, const uint64_t
     }
     // distances to every frame (matrix cores), tube variables and ratchets,
     // effective references (matrix cores), bias + physics
-    const bool overlap = eager && c->side && c->overlap_nb;
+    // (also while the step is captured into a graph: the fork and join become
+    // the graph's branch and merge, with no per-step event cost at replay)
+    const bool overlap = (eager || st == c->cap) && c->side && c->overlap_nb;
     if (overlap) {
         // nonbonded forces (acc components 0..2) need only the positions:
         // they overlap the bandwidth-bound distance pass
@@ -884,7 +887,9 @@ void drop_step_graph(scps_ctx *c) {
 // largest stack or the block length changes.
 scps_status ensure_step_graph(scps_ctx *c, double *cv) {
     const int kf = max_stack_frames(c);
-    if (c->gexec && c->g_cv == cv && c->g_frames == kf && c->g_steps == c->graph_steps) return SCPS_OK;
+    if (c->gexec && c->g_cv == cv && c->g_frames == kf && c->g_steps == c->graph_steps &&
+        c->g_overlap == c->overlap_nb)
+        return SCPS_OK;
     drop_step_graph(c);
     if (!c->cap) HIP_TRY(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
     if (!c->d_step) HIP_TRY(c, dalloc(c, &c->d_step, 1));
@@ -905,6 +910,7 @@ scps_status ensure_step_graph(scps_ctx *c, double *cv) {
     c->g_cv = cv;
     c->g_frames = kf;
     c->g_steps = c->graph_steps;
+    c->g_overlap = c->overlap_nb;
     return SCPS_OK;
 }
 
@@ -937,10 +943,11 @@ scps_status step_impl(scps_ctx *c, float *x, float *v, double *cv, int64_t n_ste
     HIP_TRY(c, launch_gather(c->d_sysd, c->d_reps, c->R, c->n_pad_max, x, v, c->d_xs, v ? c->d_vs : nullptr,
                              c->stream));
     // whole blocks of graph_steps steps replay one captured graph (not with
-    // neighbour lists, the overlapped schedule or pass timing); a block never
-    // crosses a recorded frame or the end of the call
+    // neighbour lists or pass timing; the overlapped SCPS schedule is captured
+    // as two branches); a block never crosses a recorded frame or the end of
+    // the call
     const int B = c->graph_steps;
-    const bool graphs = B > 0 && !(!scps && c->nl) && !(scps && c->side && c->overlap_nb) && !c->timing;
+    const bool graphs = B > 0 && !(!scps && c->nl) && !c->timing;
     for (int64_t m = 0;;) {
         if (record_every > 0 && m % record_every == 0)
             HIP_TRY(c, launch_scatter(c->d_sysd, c->d_reps, c->R, c->n_pad_max, c->d_xs, nullptr, nullptr, nullptr,

@@ -79,13 +79,16 @@ def test_replayed_noise_is_the_launched_noise(S):
     assert np.array_equal(out[0], out[1])
 
 
-def test_scps_blocks_match_launch_by_launch(S):
+@pytest.mark.parametrize("exec_mode", [0, 3], ids=["sequential", "overlapped"])
+def test_scps_blocks_match_launch_by_launch(S, exec_mode):
     """SCPS replicas under the tube ratchets (150 beads, every second in the
     contact set, 6 replicas, 9 frames): 48 steps recording a frame every 20
     (a replayed block and 4 launched steps before each recorded frame),
     other GPU work and a host synchronisation, 37 more steps (two blocks and
     a tail), then 16 steps on a copy of cvstate (a new capture).  Positions, velocities, recorded frames, s, w, their
-    minima and T agree with the launch-by-launch run."""
+    minima and T agree with the launch-by-launch run, with the nonbonded pass
+    after the bias pass and beside the distance pass on the context's second
+    stream (captured as two branches of the graph)."""
     import torch
     base = dict(I._base_params(), bias_mode=1, lam=13.5, k_s=50.0, k_w=5.0)
     n, R, K, n_paths = 150, 6, 9, 2
@@ -102,7 +105,7 @@ def test_scps_blocks_match_launch_by_launch(S):
     cv0[:, 5:7] = np.inf
     out = []
     for gs in (0, 16):
-        ctx = _context(S, w, base, 0, gs)
+        ctx = _context(S, w, base, exec_mode, gs)
         ctx.update_reference_from_paths(0, dev(fr.ravel()), n_paths, K, np.ones(n_paths, dtype=np.uint8))
         x, v, cv = dev(x0), dev(np.zeros_like(x0)), dev(cv0, "f64")
         frames = torch.zeros(3 * x0.size, dtype=torch.float32, device="cuda")
