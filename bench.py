@@ -85,8 +85,7 @@ def parse():
     ap.add_argument("--replicas", type=int, default=0, help="0: the workload's own count")
     ap.add_argument("--graph-steps", type=int, default=None,
                     help="steps per replayed HIP graph on the per-step path (scps_set_graph_steps; "
-                         "uneven512 and scps560 default: the block, at most 256; other workloads: the "
-                         "library's default, 0)")
+                         "uneven512 default: the block, 100; other workloads: the library's default, 0)")
     ap.add_argument("--plain-replicas", type=int, default=8)
     ap.add_argument("--plain-steps", type=int, default=20)
     ap.add_argument("--cpu-steps", type=int, default=300)
@@ -535,6 +534,7 @@ def bench_autograd3000(args, torch, I, scps):
 # 32 x 6000, 51 frames: one SCPS iteration (the headline workload)
 # ---------------------------------------------------------------------------
 SCPS_FRAMES = 51          # a frame every 200 steps over a 10^4-step iteration
+PASS_TIMING_PERIOD = 8    # scps_time_passes: events around the passes of every 8th step
 SCPS_ITER_STEPS = 10000
 
 
@@ -673,17 +673,17 @@ def bench_scps6000(args, torch, I, scps, fip=False):
         step[0] += blk
 
     _, overlap = ctx.autotune(x, v, cvs, 10)                # on copies of the state, before timing
-    # the small chain's steps are short enough for launch costs to show: its
-    # steps replay captured graphs (whole blocks between recorded frames), and
-    # the passes are timed in a launch-by-launch segment after the timed
-    # region (pass timing keeps steps launch by launch)
-    gsteps = (min(blk, 256) if fip else 0) if args.graph_steps is None else args.graph_steps
+    # the passes are timed on every PASS_TIMING_PERIOD-th step of the timed
+    # region (a timed step's kernels cannot overlap across its events); with
+    # --graph-steps the timed steps replay captured graphs instead and the
+    # passes are timed in a launch-by-launch segment after the timed region
+    gsteps = args.graph_steps or 0
     ctx.set_graph_steps(gsteps)
     for _ in range(args.warmup):
         block_call(0)
     ctx.sync()
     if not gsteps:
-        ctx.time_passes(True)
+        ctx.time_passes(PASS_TIMING_PERIOD)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for b in range(args.steps):
@@ -696,7 +696,7 @@ def bench_scps6000(args, torch, I, scps, fip=False):
     t1 = time.perf_counter()
     wall = t1 - t0
     if gsteps:
-        ctx.time_passes(True)
+        ctx.time_passes(PASS_TIMING_PERIOD)
         for b in range(2):
             block_call(b)
         ctx.sync()
@@ -730,9 +730,10 @@ def bench_scps6000(args, torch, I, scps, fip=False):
     out["roofline"] = roofline_hbm(stack_bytes, [per[dom]] * 1, names[dom],
                                    traffic.get(dom) if traffic else None)
     out["roofline"]["launches_timed"] = timed
-    if gsteps:
-        out["roofline"]["pass_timing"] = (f"HIP events around each pass over {timed} launch-by-launch steps "
-                                          f"after the timed region (the timed steps replay graphs)")
+    out["roofline"]["pass_timing"] = (
+        f"HIP events around each pass on every {PASS_TIMING_PERIOD}th step of the timed region" if not gsteps else
+        f"HIP events around each pass on every {PASS_TIMING_PERIOD}th of {2 * blk} launch-by-launch steps after "
+        f"the timed region (the timed steps replay graphs)")
     other = "bias" if dom == "distance" else "distance"
     out["roofline_other_pass"] = roofline_hbm(stack_bytes, [per[other]], names[other],
                                               traffic.get(other) if traffic else None)

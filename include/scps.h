@@ -321,13 +321,18 @@ scps_status scps_least_biased_path(scps_ctx *ctx, const double *cvstate, const u
 scps_status scps_set_stream(scps_ctx *ctx, void *hip_stream);
 
 /* Measurement of the SCPS step's two passes over the frame stack.  With
- * enable != 0, every later SCPS step records HIP events on the context's
- * stream right before and after its distance pass and its bias pass (in the
- * two-pass form: the effective references and the pair pass together); the
- * events are recycled in a ring of 256 steps whose oldest entry is read back,
- * waiting for it, before reuse, so timing adds no device work and no full
- * synchronisation.  Calling it resets the sums; enable = 0 stops recording.
- * Errors: STATE (not an SCPS context), HIP. */
+ * enable = k >= 1, every k-th later SCPS step (the first, then every k-th)
+ * records HIP events on the context's stream right before and after its
+ * distance pass and its bias pass (in the two-pass form: the effective
+ * references and the pair pass together); the events are recycled in a ring
+ * of 256 timed steps whose oldest entry is read back, waiting for it, before
+ * reuse, so timing adds no device work and no full synchronisation.  A timed
+ * step's kernels cannot overlap across the events, which shows on short
+ * steps: timing every step of 32 replicas x 560 particles (60 us per step)
+ * cost 16 % of the throughput, timing every 8th about 2 %.  Calling it
+ * resets the sums; enable = 0 stops recording.  Steps run launch by launch
+ * while timing is on (no graph replay).
+ * Errors: INVALID_ARG (enable < 0), STATE (not an SCPS context), HIP. */
 scps_status scps_time_passes(scps_ctx *ctx, int32_t enable);
 
 /* The summed durations in ms (host float64 [2]: distance pass, bias pass) and
@@ -400,9 +405,8 @@ scps_status scps_set_launch(scps_ctx *ctx, int32_t path, int32_t param);
  * graph (the nonbonded pass on the context's second stream).
  *   steps: 0 (no graphs, the default) .. SCPS_MAX_GRAPH_STEPS.  Measured
  *   on MI355X with ROCm 7.2: an SCPS step of 32 replicas x 560 particles
- *   (tens of microseconds) takes 60 us replayed against 72 us launched one
- *   by one; at 32 x 6000 (2.7 ms) the launch gaps are under 1 % and pass
- *   timing is wanted, and an rMD step of a few microseconds was slower
+ *   is about 1 % faster replayed, one of 32 x 6000 no faster (the launch
+ *   gaps are under 1 %), and an rMD step of a few microseconds was slower
  *   replayed, hence the default.
  * Synchronises the stream when the value changes.  Host only.
  * Errors: INVALID_ARG (NULL ctx, steps out of range), STATE (poisoned), HIP. */

@@ -81,6 +81,8 @@ struct scps_ctx {
     // of PASS_RING slots (4 events each) whose oldest slot is read back before reuse
     static constexpr int PASS_RING = 256;
     bool timing = false;
+    int timing_period = 1;           // time every timing_period-th SCPS step
+    int64_t timing_tick = 0;
     std::vector<hipEvent_t> pass_ev;  // [PASS_RING][4]: distance start, end, bias start, end
     int64_t pass_recorded = 0, pass_read = 0;
     double pass_ms[2] = {0.0, 0.0};
@@ -774,6 +776,7 @@ scps_status read_pass_slot(scps_ctx *c) {
 hipEvent_t *pass_slot(scps_ctx *c, scps_status *st) {
     *st = SCPS_OK;
     if (!c->timing) return nullptr;
+    if (c->timing_tick++ % c->timing_period != 0) return nullptr;
     if (c->pass_recorded - c->pass_read == scps_ctx::PASS_RING) {
         *st = read_pass_slot(c);
         if (*st != SCPS_OK) return nullptr;
@@ -1434,6 +1437,7 @@ scps_status scps_time_passes(scps_ctx *ctx, int32_t enable) {
     scps_status st;
     if (!usable(ctx, &st)) return st;
     if (ctx->prm.bias_mode != SCPS_BIAS_SCPS) return fail(SCPS_ERR_STATE, "pass timing needs an SCPS context");
+    if (enable < 0) return fail(SCPS_ERR_INVALID_ARG, "the timing period must be >= 0");
     if (ctx->pass_ev.empty()) {
         ctx->pass_ev.assign(4 * scps_ctx::PASS_RING, nullptr);
         for (auto &e : ctx->pass_ev) HIP_TRY(ctx, hipEventCreate(&e));
@@ -1443,6 +1447,8 @@ scps_status scps_time_passes(scps_ctx *ctx, int32_t enable) {
         if (st != SCPS_OK) return st;
     }
     ctx->timing = enable != 0;
+    ctx->timing_period = enable > 0 ? enable : 1;
+    ctx->timing_tick = 0;
     ctx->pass_ms[0] = ctx->pass_ms[1] = 0.0;
     ctx->pass_recorded = ctx->pass_read = 0;
     return SCPS_OK;

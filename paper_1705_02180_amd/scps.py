@@ -378,9 +378,11 @@ class Context:
         _check(_lib.scps_least_biased_path(self._ctx(), pc, ps, C.byref(idx), C.byref(t)))
         return int(idx.value), float(t.value)
 
-    def time_passes(self, enable: bool = True):
-        """Start (or stop) recording HIP events around the SCPS step's distance and bias passes."""
-        _check(_lib.scps_time_passes(self._ctx(), int(bool(enable))))
+    def time_passes(self, enable=True):
+        """Start (or stop: False / 0) recording HIP events around the SCPS
+        step's distance and bias passes; True or 1 times every step, an int
+        k >= 1 every k-th."""
+        _check(_lib.scps_time_passes(self._ctx(), int(enable)))
 
     def pass_times(self):
         """({"distance": ms, "bias": ms} summed, steps timed) since time_passes."""

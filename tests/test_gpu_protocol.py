@@ -406,7 +406,8 @@ def test_pass_timing_changes_no_result(S):
     steps give bit-identical positions and velocities with and without it (the
     collective variables to the last bits of their float64 atomic sums), and
     every step's two passes have a positive duration (more steps than the
-    event ring holds, so the ring is recycled)."""
+    event ring holds, so the ring is recycled); timing every 7th step times
+    15 of 100, and a negative period is an argument error."""
     import torch
     base = dict(I._base_params(), bias_mode=1, lam=13.5, k_s=50.0, k_w=5.0)
     n, R, K = 150, 5, 9
@@ -434,6 +435,13 @@ def test_pass_timing_changes_no_result(S):
             print(f"  300 steps: distance pass {ms['distance'] / steps:.4f} ms, bias pass {ms['bias'] / steps:.4f} ms",
                   flush=True)
             assert steps == 300 and ms["distance"] > 0 and ms["bias"] > 0
+            ctx.time_passes(7)                        # every 7th step: steps 0, 7, ..., 98 of 100
+            ctx.step_replicas(dev(x0), dev(np.zeros_like(x0)), dev(w.initial_cvstate(), "f64"), 100, step0=5)
+            ms7, steps7 = ctx.pass_times()
+            assert steps7 == 15 and ms7["distance"] > 0 and ms7["bias"] > 0
+            with pytest.raises(S.ScpsError) as e:
+                ctx.time_passes(-1)
+            assert e.value.status == -1
             ctx.time_passes(False)
         out.append((host(x), host(v), host(cv)))
         ctx.close()
