@@ -1798,11 +1798,14 @@ __global__ __launch_bounds__(256) void k_integrate(const KParams P, const SysDes
             const double z = (zbase ? zbase[r] : 0.0) + replica_z(zfirst, zpart, r, threadIdx.x);
             if (threadIdx.x == 0) {
                 double *c = cv + (int64_t)r * CV_STRIDE;
-                const double zm = fmin(c[CV_ZM], z);
+                // z_m is read here while column 0 may be writing it: both as
+                // relaxed atomics, so either value is read whole
+                const double zm =
+                    fmin(__hip_atomic_load(&c[CV_ZM], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), z);
                 const double dz = z - zm;
                 if (blockIdx.x == 0) {
                     c[CV_Z] = z;
-                    c[CV_ZM] = zm;
+                    __hip_atomic_store(&c[CV_ZM], zm, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     c[CV_EB] = 0.5 * P.k_R * dz * dz;
                 }
                 sh_scale = -P.k_R * dz;
